@@ -1,0 +1,417 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix (CPU only).
+
+None of these checks re-types the oracle's own formulas: each compares it with an
+independent fact (printed values, continuous Maxwellian moments, the Fourier form of
+the scheme, exact d'Alembert solutions, conservation laws, convergence order).
+"""
+import json
+import os
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+from oracle import closed_forms as cf
+from oracle import lattices as L
+from oracle import lbe
+
+from paper_1601_08103_amd import inputs
+
+RNG = np.random.default_rng(1234)
+
+
+def _classify(c):
+    nz = int(np.count_nonzero(c))
+    return {0: "rest", 1: "axis", 2: "edge", 3: "corner"}[nz]
+
+
+# --------------------------------------------------------------------------- printed values
+@pytest.mark.parametrize("name", ["D1Q3", "D2Q5", "D2Q5_DIA", "D3Q7", "D3Q9", "D3Q13", "D3Q19", "D3Q7_DIA"])
+def test_printed_tables(name, golden_dir):
+    gold = json.load(open(os.path.join(golden_dir, "paper_tables.json")))[name]
+    lat = L.get(name)
+    ex = lat.exact
+    assert ex["rho0"] == Fr(gold["rho0"]) and ex["theta0"] == Fr(gold["theta0"])
+    seen = set()
+    for i in range(lat.Q):
+        cls = _classify(lat.c[i])
+        # D2Q9-style diagonals are "edges" in 2D; none of the printed 2D sets has them
+        assert cls in gold["weights"], (name, cls)
+        assert ex["fstar"][i] == Fr(gold["weights"][cls]), (name, i)
+        if "beta" in gold:
+            assert ex["beta"][i] == Fr(gold["beta"][cls])
+        seen.add(cls)
+    assert seen == set(gold["weights"])
+    for key in ("a1", "a2", "b", "c1", "c2"):
+        if key in gold:
+            assert ex[key] == Fr(gold[key]), key
+    # number of velocities per class: 2D/3D axis = 2D, edge = 12, corner = 8
+    counts = {cls: sum(1 for i in range(lat.Q) if _classify(lat.c[i]) == cls) for cls in seen}
+    assert counts.get("axis", 2 * lat.D) == 2 * lat.D
+    if lat.D == 3:
+        assert counts.get("edge", 12) == 12 and counts.get("corner", 8) == 8
+
+
+# --------------------------------------------------------------------------- similarity conditions
+def _maxwell_moments(D, rho0, theta0):
+    """Moments of the continuous Maxwellian with density rho0 and temperature theta0 (Gaussian
+    moments: <v_a^2> = theta0, <v_a^4> = 3 theta0^2, <v_a^2 v_b^2> = theta0^2)."""
+    return {
+        "1": rho0,
+        "half_v2": Fr(D, 2) * rho0 * theta0,
+        "vxvx": rho0 * theta0,
+        "vxvy": Fr(0),
+        "half_v2_vxvx": Fr(D + 2, 2) * rho0 * theta0 ** 2,
+        "half_v2_vxvy": Fr(0),
+        "quarter_v4": Fr(D * (D + 2), 4) * rho0 * theta0 ** 2,
+    }
+
+
+def _discrete_moments(c, f):
+    out = {k: Fr(0) for k in ("1", "half_v2", "vxvx", "vxvy", "half_v2_vxvx", "half_v2_vxvy", "quarter_v4")}
+    for ci, fi in zip(c, f):
+        v2 = int((ci ** 2).sum())
+        vx, vy = int(ci[0]), int(ci[1])
+        out["1"] += fi
+        out["half_v2"] += Fr(v2, 2) * fi
+        out["vxvx"] += vx * vx * fi
+        out["vxvy"] += vx * vy * fi
+        out["half_v2_vxvx"] += Fr(v2, 2) * vx * vx * fi
+        out["half_v2_vxvy"] += Fr(v2, 2) * vx * vy * fi
+        out["quarter_v4"] += Fr(v2 * v2, 4) * fi
+    return out
+
+
+@pytest.mark.parametrize("name", L.MONOATOMIC)
+def test_similarity_conditions_exact(name):
+    lat = L.get(name)
+    ex = lat.exact
+    got = _discrete_moments(lat.c, ex["fstar"])
+    want = _maxwell_moments(lat.D, ex["rho0"], ex["theta0"])
+    if lat.D == 1:
+        for k in ("vxvy", "half_v2_vxvy"):
+            got.pop(k)
+            want.pop(k)
+    assert got == want
+    assert all(w > 0 for w in ex["fstar"])  # positivity (zero weights were dropped)
+
+
+@pytest.mark.parametrize("theta0,alpha", [(Fr(1, 5), Fr(1, 100)), (Fr(1, 3), Fr(1, 50)), (Fr(3, 10), Fr(1, 200))])
+def test_family27_similarity_for_any_parameters(theta0, alpha):
+    """The printed 3D family satisfies the similarity conditions for every (theta0, alpha)."""
+    rho0 = Fr(7, 5)
+    rest, axis, edge, corner = L.family27_weights(rho0, theta0, alpha)
+    c, f = [], []
+    for nnz, w in ((0, rest), (1, axis), (2, edge), (3, corner)):
+        for v in L._class_velocities(3, nnz) if nnz else [(0, 0, 0)]:
+            c.append(np.array(v))
+            f.append(w)
+    assert _discrete_moments(c, f) == _maxwell_moments(3, rho0, theta0)
+
+
+def test_d2q9_weights_reduce_to_d2q5():
+    """At theta0 = 1/4 the derived D2Q9 weights lose their diagonals and give D2Q5's weights."""
+    w0, w1, w2 = L.d2q9_weights(Fr(1, 4))
+    assert (w0, w1, w2) == (Fr(1, 2), Fr(1, 8), Fr(0))
+
+
+@pytest.mark.parametrize("name", list(L.ALL))
+def test_background_density(name):
+    lat = L.get(name)
+    assert sum(lat.exact["fstar"]) == lat.exact["rho0"]
+
+
+# --------------------------------------------------------------------------- equilibrium and moments
+@pytest.mark.parametrize("name", list(L.ALL))
+def test_equilibrium_reproduces_its_moments(name):
+    """Moments of g^eq(rho', u', theta') are (rho', u', theta') (the FDVM moment identities)."""
+    lat = L.get(name)
+    shape = (5,) * lat.D
+    rho, u, theta = inputs.random_fields(7, shape, lat.D)
+    m = lbe.moments(lat, lbe.equilibrium(lat, rho, u, theta))
+    scale = 1e-3
+    assert np.abs(m["rho"] - rho).max() < 1e-15 * 10 * scale * 100
+    assert np.abs(m["u"] - u).max() < 1e-13 * scale
+    assert np.abs(m["theta"] - theta).max() < 1e-13 * scale
+
+
+@pytest.mark.parametrize("name", list(L.ALL))
+def test_equilibrium_matrix_is_projection_of_rank_D_plus_2(name):
+    lat = L.get(name)
+    E = lbe.equilibrium_matrix(lat)
+    assert np.abs(E @ E - E).max() < 1e-14
+    assert np.linalg.matrix_rank(E) == lat.D + 2
+    # self-adjoint in <g,h> = sum g h / f*: W E symmetric
+    W = np.diag(1.0 / lat.fstar)
+    assert np.abs(W @ E - (W @ E).T).max() < 1e-12
+
+
+def test_isentropic_pressure_matches_lee_split():
+    lat = L.get("D3Q7")
+    p0 = RNG.standard_normal((4, 4, 4))
+    rho, u, theta = inputs.fields_from_pressure(p0, lat.rho0, lat.theta0, lat.gamma, "isentropic")
+    p, _, s = cf.split_state(lat, rho, u, theta)
+    assert np.abs(p - p0).max() < 1e-14 and np.abs(s).max() < 1e-15
+
+
+# --------------------------------------------------------------------------- update and stability structure
+@pytest.mark.parametrize("name", list(L.ALL))
+def test_update_matrix_at_half_is_reflection(name):
+    """H(1) = E is a projection, so H(1/2) = 2E - I has eigenvalues +1 and -1 only."""
+    lat = L.get(name)
+    H = lbe.update_matrix(lat, 0.5)
+    assert np.abs(lbe.update_matrix(lat, 1.0) - lbe.equilibrium_matrix(lat)).max() < 1e-15
+    ev = np.linalg.eigvals(H)
+    assert np.all(np.minimum(np.abs(ev - 1), np.abs(ev + 1)) < 1e-12)
+    assert np.sum(np.abs(ev - 1) < 1e-9) == lat.D + 2
+
+
+def test_d3q19_printed_stability_structure(golden_dir):
+    """D3Q19: with A0 = diag(3, 13 I6, 52 I12), A0 H(1/2) is symmetric and A0 is positive definite."""
+    gold = json.load(open(os.path.join(golden_dir, "paper_tables.json")))["D3Q19"]["A0"]
+    lat = L.get("D3Q19")
+    A0 = np.diag([float(Fr(gold[_classify(ci)])) for ci in lat.c])
+    M = A0 @ lbe.update_matrix(lat, 0.5)
+    assert np.abs(M - M.T).max() < 1e-12
+    # A0 is (up to one factor) the inverse weights: 0.975 / f*
+    assert np.allclose(np.diag(A0) * lat.fstar, 0.975)
+
+
+def test_d1q3_gamma_is_printed_diagonal():
+    lat = L.get("D1Q3")
+    for k in (0.3, -1.7, np.pi):
+        G = lbe.gamma_matrix(lat, [k])
+        # canonical order (0, -1, +1) is the paper's: diag(1, e^{ik}, e^{-ik})
+        assert np.allclose(G, np.diag([1.0, np.exp(1j * k), np.exp(-1j * k)]), atol=1e-15)
+
+
+UNITARY = ["D1Q3", "D2Q5", "D2Q5_DIA", "D3Q7", "D3Q9", "D3Q13", "D3Q7_DIA"]
+
+
+@pytest.mark.parametrize("name", list(L.ALL))
+def test_gamma_unitarity_claims(name):
+    """The paper states Gamma(k) unitary for these sets; every set is unitary in the 1/f* weighted norm."""
+    lat = L.get(name)
+    W = np.diag(1.0 / lat.fstar)
+    for _ in range(20):
+        k = RNG.uniform(-np.pi, np.pi, size=lat.D)
+        G = lbe.gamma_matrix(lat, k)
+        assert np.abs(G.conj().T @ W @ G - W).max() < 1e-11
+        unit = np.abs(G.conj().T @ G - np.eye(lat.Q)).max()
+        if name in UNITARY:
+            assert unit < 1e-12
+    if name not in UNITARY:
+        k = np.full(lat.D, 0.9)
+        G = lbe.gamma_matrix(lat, k)
+        assert np.abs(G.conj().T @ G - np.eye(lat.Q)).max() > 1e-3
+
+
+# --------------------------------------------------------------------------- the stepper
+def _grid_k(shape, D, rng):
+    ms = rng.integers(-3, 4, size=D)
+    while not np.any(ms):
+        ms = rng.integers(-3, 4, size=D)
+    dims = list(reversed(shape))
+    return [2 * np.pi * ms[a] / dims[a] for a in range(D)]
+
+
+@pytest.mark.parametrize("name", list(L.ALL))
+def test_stepper_matches_fourier_power(name):
+    """C stepper vs Re(Gamma(k)^n ghat exp(ikx)) for an arbitrary (non-equilibrium) Fourier mode."""
+    lat = L.get(name)
+    shape = {1: (24,), 2: (10, 12), 3: (6, 7, 8)}[lat.D]
+    rng = np.random.default_rng(hash(name) % 2 ** 32)
+    k = _grid_k(shape, lat.D, rng)
+    ghat = rng.standard_normal(lat.Q) + 1j * rng.standard_normal(lat.Q)
+    g0 = cf.plane_wave_discrete(lat, k, ghat, shape, 0)
+    for tau, n in ((0.5, 37), (0.8, 11)):
+        got = lbe.steps(lat, g0, n, tau=tau)
+        want = cf.plane_wave_discrete(lat, k, ghat, shape, n, tau=tau)
+        assert np.abs(got - want).max() < 1e-12 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("mode", ["isentropic", "paper"])
+def test_d1q3_is_exact_dalembert(mode):
+    """1D workload shape: N = 1024, sigma = 20, 1000 steps; D1Q3 solves the 1D LEE exactly."""
+    lat = L.get("D1Q3")
+    N = 1024
+    p0 = inputs.gaussian_pressure((N,), inputs.pulses_1d(N))
+    rho, u, theta = inputs.fields_from_pressure(p0, lat.rho0, lat.theta0, lat.gamma, mode)
+    g = lbe.run(lat, rho, u, theta, 1000)
+    m = lbe.moments(lat, g)
+    ex = cf.dalembert_1d_integer_shift(lat, rho, u, theta, 1000)
+    for key in ("rho", "p"):
+        assert lbe.rel_l2(m[key], ex[key]) < 1e-13, key
+    # theta' is identically zero in "paper" mode and a cancellation of O(rho') terms:
+    # compare on the scale of the initial density
+    for key in ("theta", "u"):
+        assert np.abs(m[key] - ex[key]).max() < 1e-12 * np.abs(rho).max(), key
+    if mode == "paper":
+        # density = 2/3 G + 1/6 (G(x - n) + G(x + n)) in units of the density pulse
+        G = rho
+        want = (2 / 3) * G + (1 / 6) * (np.roll(G, 1000) + np.roll(G, -1000))
+        assert lbe.rel_l2(m["rho"], want) < 1e-13
+
+
+@pytest.mark.parametrize("name", list(L.ALL))
+def test_global_conservation(name):
+    lat = L.get(name)
+    shape = {1: (31,), 2: (9, 11), 3: (5, 6, 7)}[lat.D]
+    rho, u, theta = inputs.random_fields(3, shape, lat.D)
+    g = lbe.equilibrium(lat, rho, u, theta) + 1e-4 * np.random.default_rng(5).standard_normal((lat.Q,) + shape)
+    c2 = (lat.c ** 2).sum(axis=1)
+    e = 0.5 * (c2 + lat.beta)
+
+    def inv(g):
+        return np.array([g.sum()] + [np.tensordot(lat.c[:, a], g, (0, 0)).sum() for a in range(lat.D)]
+                        + [np.tensordot(e, g, (0, 0)).sum()])
+
+    I0 = inv(g)
+    scale = np.abs(g).sum()
+    for _ in range(5):
+        g = lbe.steps(lat, g, 3, tau=0.7)
+        assert np.abs(inv(g) - I0).max() < 1e-14 * scale
+
+
+@pytest.mark.parametrize("name", list(L.ALL))
+def test_superposition(name):
+    lat = L.get(name)
+    shape = {1: (17,), 2: (8, 9), 3: (4, 5, 6)}[lat.D]
+    rng = np.random.default_rng(11)
+    g1 = rng.standard_normal((lat.Q,) + shape)
+    g2 = rng.standard_normal((lat.Q,) + shape)
+    a, b = 0.7, -1.9
+    lhs = lbe.steps(lat, a * g1 + b * g2, 13)
+    rhs = a * lbe.steps(lat, g1, 13) + b * lbe.steps(lat, g2, 13)
+    assert np.abs(lhs - rhs).max() < 1e-13 * np.abs(rhs).max()
+
+
+@pytest.mark.parametrize("name", list(L.ALL))
+def test_energy_conserved_at_half_and_decays_above(name):
+    lat = L.get(name)
+    shape = {1: (32,), 2: (12, 12), 3: (6, 6, 6)}[lat.D]
+    g0 = np.random.default_rng(2).standard_normal((lat.Q,) + shape)
+    E0 = lbe.weighted_energy(lat, g0)
+    g = lbe.steps(lat, g0, 200, tau=0.5)
+    assert abs(lbe.weighted_energy(lat, g) - E0) < 1e-12 * E0
+    if name in UNITARY:
+        assert abs(lbe.plain_energy(lat, g) - lbe.plain_energy(lat, g0)) < 1e-12 * lbe.plain_energy(lat, g0)
+    for tau in (0.6, 1.0):
+        prev = E0
+        g = g0
+        for _ in range(4):
+            g = lbe.steps(lat, g, 5, tau=tau)
+            E = lbe.weighted_energy(lat, g)
+            assert E < prev
+            prev = E
+
+
+def test_rest_population_invariant_for_decoupled_sets():
+    """For sets whose rest velocity decouples (E_00 = 1, E_0j = E_j0 = 0) g_0 never changes."""
+    for name in ("D1Q3", "D2Q5", "D2Q5_DIA", "D3Q7", "D3Q7_DIA", "D3Q9", "D3Q13"):
+        lat = L.get(name)
+        E = lbe.equilibrium_matrix(lat)
+        assert abs(E[0, 0] - 1) < 1e-14 and np.abs(E[0, 1:]).max() < 1e-14 and np.abs(E[1:, 0]).max() < 1e-14
+        shape = {1: (16,), 2: (6, 7), 3: (4, 5, 6)}[lat.D]
+        g0 = np.random.default_rng(9).standard_normal((lat.Q,) + shape)
+        g = lbe.steps(lat, g0, 9)
+        assert np.abs(g[0] - g0[0]).max() < 1e-13 * np.abs(g0).max()  # rounding only
+    for name in ("D2Q9", "D3Q19"):
+        E = lbe.equilibrium_matrix(L.get(name))
+        assert np.abs(E[1:, 0]).max() > 1e-3
+
+
+# --------------------------------------------------------------------------- convergence order
+def _plane_wave_error(lat, N, kdir):
+    shape = (N,) * lat.D
+    dims = list(reversed(shape))
+    k = [2 * np.pi * kdir[a] / dims[a] for a in range(lat.D)]
+    rho, u, theta = inputs.plane_wave_fields(shape, k, 1e-3, lat.rho0, lat.theta0, lat.gamma)
+    g = lbe.run(lat, rho, u, theta, N)
+    m = lbe.moments(lat, g)
+    ex = cf.plane_wave_continuum(lat, k, 1e-3, shape, float(N))
+    return lbe.l2_space(m["p"] - ex["p"], 1.0 / N, lat.D)
+
+
+@pytest.mark.parametrize("name,kdir", [("D2Q5", (1, 0)), ("D2Q5", (2, 1)), ("D2Q9", (1, 0)), ("D2Q9", (2, 1)),
+                                       ("D3Q7", (1, 0, 0)), ("D3Q7", (1, 1, 0)), ("D1Q3", (1,)),
+                                       ("D2Q5_DIA", (2, 1)), ("D3Q7_DIA", (1, 1, 0))])
+def test_second_order_plane_wave(name, kdir):
+    lat = L.get(name)
+    sizes = (16, 32, 64) if lat.D < 3 else (12, 24, 48)
+    errs = [_plane_wave_error(lat, N, kdir) for N in sizes]
+    if name == "D1Q3":
+        assert max(errs) < 1e-13  # exact: characteristic speed equals the lattice speed
+        return
+    slopes = [np.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert min(slopes) > 1.9, slopes
+
+
+@pytest.mark.slow
+def test_second_order_3d_radial_pulse():
+    """D3Q7 Gaussian pulse vs the spherical d'Alembert solution, sigma and time scaled with N."""
+    lat = L.get("D3Q7")
+    errs = []
+    for N in (16, 32, 64):
+        sigma = N / 8.0
+        shape = (N, N, N)
+        centre = (N / 2, N / 2, N / 2)
+        p0 = inputs.gaussian_pressure(shape, [inputs.Pulse(centre, 1e-3, sigma)])
+        rho, u, theta = inputs.fields_from_pressure(p0, lat.rho0, lat.theta0, lat.gamma)
+        n = N // 2
+        g = lbe.run(lat, rho, u, theta, n, nthreads=4)
+        m = lbe.moments(lat, g)
+        ex = cf.radial_3d_gaussian(lat, 1e-3, sigma, centre, shape, float(n))
+        errs.append(lbe.l2_space(m["p"] - ex["p"], 1.0 / N, 3))
+    slopes = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(slopes) > 1.85, (errs, slopes)
+
+
+# --------------------------------------------------------------------------- dimensional mapping (Table 1)
+def test_table1_end_time_offsets(golden_dir):
+    gold = json.load(open(os.path.join(golden_dir, "paper_tables.json")))["table1"]
+    lat = L.get("D3Q7_DIA")
+    T = cf.nondimensional_time(1.0, 1.0, lat.theta0)
+    assert abs(T - np.sqrt(21 / 5)) < 1e-15
+    for N, want in zip(gold["N"], gold["offset"]):
+        _, off = cf.end_time_offset(T, N)
+        assert float(f"{off:.2e}") == want, (N, off)
+
+
+# --------------------------------------------------------------------------- planted mistakes
+def _pins_detect(lat, coeffs):
+    """Run three independent pins on a stepper with planted coefficients; True if one fails."""
+    shape = {1: (16,), 2: (8, 8), 3: (6, 6, 6)}[lat.D]
+    rng = np.random.default_rng(0)
+    k = _grid_k(shape, lat.D, rng)
+    ghat = rng.standard_normal(lat.Q) + 1j * rng.standard_normal(lat.Q)
+    g0 = cf.plane_wave_discrete(lat, k, ghat, shape, 0)
+    got = lbe.steps(lat, g0, 7, coeffs=coeffs)
+    want = cf.plane_wave_discrete(lat, k, ghat, shape, 7)
+    fourier_bad = np.abs(got - want).max() > 1e-10 * np.abs(want).max()
+    energy_bad = abs(lbe.weighted_energy(lat, got) - lbe.weighted_energy(lat, g0)) > 1e-10 * lbe.weighted_energy(lat, g0)
+    mass_bad = abs(got.sum() - g0.sum()) > 1e-10 * np.abs(g0).sum()
+    return fourier_bad or energy_bad or mass_bad
+
+
+@pytest.mark.parametrize("mistake", ["b_sign", "drop_c2", "a2_off", "reverse_streaming", "theta0_wrong", "fstar_swap"])
+def test_planted_mistakes_are_caught(mistake):
+    lat = L.get("D3Q19" if mistake == "fstar_swap" else "D2Q9")
+    co = {}
+    if mistake == "b_sign":
+        co["b"] = -lat.b
+    elif mistake == "drop_c2":
+        co["c2"] = 0.0
+    elif mistake == "a2_off":
+        co["a2"] = lat.a2 * 1.01
+    elif mistake == "reverse_streaming":
+        co["c"] = -lat.c
+        co["b"] = -lat.b  # collision still consistent with the reversed velocities
+    elif mistake == "theta0_wrong":
+        co["theta0"] = lat.theta0 * 1.05
+    elif mistake == "fstar_swap":
+        f = lat.fstar.copy()
+        f[1], f[7] = f[7], f[1]
+        co["fstar"] = f
+    assert _pins_detect(lat, co)
+    assert not _pins_detect(lat, {})
