@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Benchmark of the LEE lattice Boltzmann hot path on one MI355X.
+
+Workload (default): 3D LEE-LBM on D3Q7, 256^3 periodic cells, 8 seeded Gaussian pressure
+pulses (amplitude 1e-3, sigma 12 cells, isentropic, zero velocity), tau = 1/2, 500 steps,
+FP32 population storage.  A "step" is one fused pull-stream + moments + equilibrium +
+relaxation pass over all cells.  The initial state is resident in HBM before timing starts.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + % peak HBM GB/s; FP16-store & learned-NRBC vs plain FP32 at stated err"
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256, help="cells per axis")
+    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--variant", default="auto")
+    ap.add_argument("--modes", default="f32,f16,bf16,f64", help="storage modes to time and compare")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-only", action="store_true", help="only the timed steps of --storage (for rocprofv3)")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "codec.hpp", "velsets.hpp", "api.hip"):
+        with open(os.path.join(ROOT, "paper_1601_08103_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_counters(storage: str, n: int):
+    """HBM bytes per launch measured with rocprofv3 counters, if they were taken on the current
+    kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_step_d3q7_{n}_{storage}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(shape, rho, u, theta, budget_s):
+    """The FP64 oracle (C stepper, OpenMP over rows) on the same workload, for a bounded number
+    of steps, on this host's cores."""
+    from oracle import lattices as L
+    from oracle import lbe
+
+    lat = L.get("D3Q7")
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        threads = os.cpu_count() or 1
+    threads = int(os.environ.get("LBM_ORACLE_THREADS", min(threads, 16)))
+    g = lbe.equilibrium(lat, rho, u, theta)
+    N = int(np.prod(shape))
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        g = lbe.steps(lat, g, 1, nthreads=threads)
+        steps += 1
+        el = time.perf_counter() - t0
+        log(f"cpu baseline: {steps} oracle steps, {el:.1f} s")
+        if el >= budget_s:
+            break
+    return dict(value=round(N * steps / el / 1e6, 3), unit="MLUPS", cores=threads, kind="oracle",
+                sample=f"first {steps} steps of the same {shape[0]}^3 D3Q7 workload, FP64, push-form C stepper")
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1601_08103_amd import inputs, lbm
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    lbm.load()
+    torch.cuda.set_device(0)
+    n = args.n
+    shape = (n, n, n)
+    N = n ** 3
+    K, W = args.steps, args.warmup
+    info = lbm.lbm_lee_lattice_info("D3Q7")
+
+    log(f"building initial fields {shape}")
+    p0 = inputs.gaussian_pressure(shape, inputs.pulses_3d(seed=0, n=n))
+    rho, u, theta = inputs.fields_from_pressure(p0, info["rho0"], info["theta0"], info["gamma"])
+    dev = torch.device("cuda")
+    rho_d = torch.from_numpy(rho).to(dev)
+    u_d = torch.from_numpy(u).to(dev)
+    th_d = torch.from_numpy(theta).to(dev)
+    stream = torch.cuda.current_stream()
+
+    def timed_run(storage):
+        sim = lbm.Solver("D3Q7", storage, shape, rho_d, u_d, th_d, variant=args.variant)
+        sim.step(W)
+        sim.reinit(rho_d, u_d, th_d)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t_host = time.perf_counter()
+        ev0.record(stream)
+        sim.step(K)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        t_host = time.perf_counter() - t_host
+        ms = ev0.elapsed_time(ev1)
+        log(f"{storage}: {K} steps in {ms:.3f} ms (host {t_host * 1e3:.3f} ms)")
+        return sim, ms
+
+    if args.profile_only:
+        sim, ms = timed_run(args.storage)
+        log(f"profile-only: {N * K / (ms / 1e3) / 1e6:.1f} MLUPS")
+        return
+
+    modes = [m for m in args.modes.split(",") if m]
+    if args.storage not in modes:
+        modes.insert(0, args.storage)
+    if "f64" not in modes:
+        modes.append("f64")
+    results = {}
+    moments = {}
+    for mode in modes:
+        sim, ms = timed_run(mode)
+        m = sim.moments()
+        moments[mode] = (m["p"].clone(), m["u"].clone())
+        results[mode] = dict(ms=ms, bpu=sim.bytes_per_update, scale=sim.store_scale)
+        sim.close()
+        del sim
+    p_ref, u_ref = moments["f64"]
+
+    def rel(mode):
+        p, uu = moments[mode]
+        return (float(torch.linalg.vector_norm(p - p_ref) / torch.linalg.vector_norm(p_ref)),
+                float(torch.linalg.vector_norm(uu - u_ref) / torch.linalg.vector_norm(u_ref)))
+
+    storage_modes = {}
+    for mode, r in results.items():
+        mlups = N * K / (r["ms"] / 1e3) / 1e6
+        gbs = mlups * r["bpu"] / 1e3
+        ep, eu = rel(mode)
+        storage_modes[mode] = dict(MLUPS=round(mlups, 1), ms_per_step=round(r["ms"] / K, 5),
+                                   bytes_per_update=r["bpu"], GBs=round(gbs, 1),
+                                   frac_peak_hbm=round(gbs / PEAK_HBM_GBS, 4),
+                                   rel_l2_p_vs_f64=ep, rel_l2_u_vs_f64=eu, store_scale=r["scale"])
+        log(mode, storage_modes[mode])
+
+    # plain copy kernel of the same size as one population buffer pair (read + write)
+    nbytes = N * 7 * 4
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        lbm.lbm_lee_device_copy(b.data_ptr(), a.data_ptr(), nbytes, stream.cuda_stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    ev0.record(stream)
+    for _ in range(reps):
+        lbm.lbm_lee_device_copy(b.data_ptr(), a.data_ptr(), nbytes, stream.cuda_stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * nbytes * reps / (ev0.elapsed_time(ev1) / 1e3) / 1e9
+    del a, b
+    log(f"copy kernel: {copy_gbs:.1f} GB/s")
+
+    main_mode = storage_modes[args.storage]
+    ms_step = results[args.storage]["ms"] / K
+    bpu = results[args.storage]["bpu"]
+    achieved = N * bpu / (ms_step / 1e3) / 1e9
+    traffic = traffic_from_counters(args.storage, n)
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                    frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
+                    kernel="step_dpp<D3Q7> (fused pull-stream/collide)",
+                    algorithmic_bytes_per_launch=N * bpu, frac_of_copy=round(achieved / copy_gbs, 4),
+                    copy_GBs=round(copy_gbs, 1))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(shape, rho, u, theta, args.cpu_seconds)
+        log("cpu baseline", cpu)
+
+    line = {
+        "metric": METRIC,
+        "value": main_mode["MLUPS"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {"workload": f"3D LEE-LBM D3Q7 {n}^3 periodic, 8 seeded Gaussian pressure pulses "
+                               f"(amplitude 1e-3, sigma 12 cells), tau=1/2, {K} steps",
+                   "lattice": "D3Q7", "cells": N, "storage": args.storage, "variant": args.variant,
+                   "global_batch": 1, "parallelism": "none (1 GPU)"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "storage_modes": storage_modes,
+        "error_reference": "GPU FP64 path (parity with the FP64 oracle <= 1e-12 in the test suite)",
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

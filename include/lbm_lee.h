@@ -1,0 +1,191 @@
+/*
+ * lbm_lee.h -- C ABI of the MI355X (gfx950) lattice Boltzmann solver for the Linearized
+ * Euler Equations without background velocity (Otte & Frank, "Derivation and Analysis of
+ * Lattice Boltzmann Schemes for the Linearized Euler Equations").
+ *
+ * The library computes the fully discrete LBE update (Section "Derivation of the Lattice
+ * Boltzmann Equation"):
+ *     g_i(t+1, x + c_i) = (1 - 1/tau) g_i(t, x) + (1/tau) g_i^eq(t, x),
+ * with the equilibrium of the polyatomic ansatz (Section "Generalization of the Finite
+ * Discrete Velocity Ansatz for Polyatomic Gases"; the monoatomic one of Section
+ * "Derivation of Finite Discrete Velocity Models for Monoatomic Gases" is its special case)
+ *     g_i^eq = f*_i (a1 rho' + a2 theta' + b c_i.u' + |c_i|^2/2 (c1 rho' + c2 theta')),
+ * and the moments rho' = sum g, u' = sum c g / rho0,
+ *     theta' = ((gamma - 1) sum (|c|^2 + beta)/2 g - theta0 rho') / rho0,
+ * on a periodic box, everything in lattice units (dx = dt = 1).  The second-order scheme is
+ * tau = 1/2 (Section "Analysis of the LBE").
+ *
+ * Conventions shared by every entry point
+ *   - Memory: the caller allocates and owns every device buffer (populations, initial
+ *     fields, outputs, scratch).  The library never allocates or frees device memory; a
+ *     handle keeps non-owning pointers and a small host-side table, nothing else.
+ *   - Streams: `stream` is a hipStream_t (NULL = the legacy default stream).  Every call
+ *     only enqueues work on it, except those documented as synchronising.
+ *   - Layout: populations are structure-of-arrays, g[i * N + cell] with
+ *     cell = x + nx * (y + ny * z), N = nx * ny * nz, x fastest.  Macroscopic fields are
+ *     N-element arrays in the same cell order; a velocity field is D such arrays back to
+ *     back (u[a * N + cell]).  Unused dimensions have extent 1.
+ *   - Errors: no C++ exception crosses this boundary.  Each call returns an lbm_status;
+ *     lbm_lee_last_error() gives a message for the calling thread.  HIP errors are
+ *     reported as LBM_E_HIP with the HIP error string in the message.
+ */
+#ifndef LBM_LEE_H
+#define LBM_LEE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lbm_status;
+#define LBM_OK 0
+#define LBM_E_INVALID (-1)     /* bad argument: size, alignment, null pointer, tau < 1/2 ... */
+#define LBM_E_UNSUPPORTED (-2) /* valid but not implemented combination                     */
+#define LBM_E_HIP (-3)         /* a HIP runtime call failed                                  */
+#define LBM_E_STATE (-4)       /* call not allowed in the handle's current state             */
+
+/* Velocity sets (Section "Examples of Velocity Sets").  D2Q9 is not in the paper: its
+ * weights solve the paper's similarity conditions at theta0 = 1/3 (4/9, 1/9, 1/36). */
+#define LBM_D1Q3 0     /* rho0 = 1, theta0 = 1/3                                   */
+#define LBM_D2Q5 1     /* rho0 = 1, theta0 = 1/4                                   */
+#define LBM_D2Q9 2     /* rho0 = 1, theta0 = 1/3 (derived)                         */
+#define LBM_D3Q7 3     /* 3D family, theta0 = 1/5, alpha = 0                       */
+#define LBM_D3Q9 4     /* 3D family, theta0 = 3/5, alpha = 3/40                    */
+#define LBM_D3Q13 5    /* 3D family, theta0 = 2/5, alpha = 0                       */
+#define LBM_D3Q19 6    /* 3D family, theta0 = 3/10, alpha = 0                      */
+#define LBM_D2Q5_DIA 7 /* diatomic, rho0 = 20/3, theta0 = 3/10, gamma = 5/3        */
+#define LBM_D3Q7_DIA 8 /* diatomic, f1 = 5/42 (rho0 = 1), theta0 = 5/21, gamma = 7/5 */
+#define LBM_NUM_LATTICES 9
+
+/* Population storage.  F64 and F32 store g itself.  F16 and BF16 store the normalised
+ * deviation h_i = S g_i / f*_i (S a power of two, see lbm_lee_desc.store_scale) rounded to
+ * nearest-even, and compute the collision in FP32. */
+#define LBM_F64 0
+#define LBM_F32 1
+#define LBM_F16 2
+#define LBM_BF16 3
+
+/* Step kernel variant (all give the same result up to FP summation order). */
+#define LBM_VARIANT_AUTO 0    /* DPP when nx % 4 == 0, else GENERIC                          */
+#define LBM_VARIANT_GENERIC 1 /* one thread per cell, per-element wrapped gathers            */
+#define LBM_VARIANT_DPP 2     /* 4 cells per lane, aligned vector loads, x shift by DPP     */
+#define LBM_VARIANT_LDS 3     /* 4 cells per lane, x shift through an LDS-staged row + halo */
+
+typedef struct lbm_lee_desc {
+    int32_t lattice;     /* LBM_D1Q3 ...                                                    */
+    int32_t storage;     /* LBM_F64 ...                                                     */
+    int64_t n[3];        /* nx, ny, nz >= 1; n[a] must be 1 for a >= D                      */
+    double tau;          /* relaxation time, >= 1/2 (1/2 is the second-order scheme)        */
+    int32_t variant;     /* LBM_VARIANT_*                                                   */
+    int32_t reserved0;   /* must be 0                                                       */
+    double store_scale;  /* S for F16/BF16: 0 = choose from the initial state so that       */
+                         /* max |S g / f*| lies in (1/2, 1]; otherwise a power of two > 0. */
+                         /* Ignored for F64/F32.                                            */
+} lbm_lee_desc;
+
+typedef struct lbm_lattice_info {
+    int32_t D, Q;
+    int32_t c[27][3];    /* velocities, canonical order: rest, -x,+x,-y,+y,-z,+z, edges, corners */
+    double fstar[27];    /* weights f*_i                                                     */
+    double beta[27];     /* extra energies beta_i (0 for monoatomic sets)                    */
+    double rho0, theta0, gamma, a1, a2, b, c1, c2;
+    char name[16];
+} lbm_lattice_info;
+
+typedef struct lbm_lee *lbm_lee_handle;
+
+/* Tables of a velocity set as used by the kernels (host only, no GPU work). */
+lbm_status lbm_lee_lattice_info(int32_t lattice, lbm_lattice_info *out);
+
+/* Bytes of one population buffer: Q * N * sizeof(storage element).  0 on a bad desc. */
+size_t lbm_lee_state_bytes(const lbm_lee_desc *desc);
+
+/* Bytes of device scratch lbm_lee_init needs (reductions, scale search).  0 on a bad desc. */
+size_t lbm_lee_scratch_bytes(const lbm_lee_desc *desc);
+
+/* Algorithmic HBM bytes per lattice-cell update of the step kernel: Q loads and Q stores
+ * of the storage element (2 Q s).  0 on a bad desc. */
+double lbm_lee_bytes_per_update(const lbm_lee_desc *desc);
+
+/*
+ * Create a solver on caller-owned buffers and set the initial state to equilibrium of the
+ * given macroscopic fields (Section "Analysis of the LBE": g_i(0, x) = g_i^eq(rho', u', theta')).
+ *   pop_a, pop_b  device buffers of bytes_each >= lbm_lee_state_bytes(desc), 256-byte aligned;
+ *                 the state ping-pongs between them.
+ *   rho, theta    device FP64 arrays of N values; u: device FP64, D * N values.
+ *   scratch       device buffer of scratch_bytes >= lbm_lee_scratch_bytes(desc), 256-byte aligned.
+ * Synchronises `stream` only when desc->store_scale == 0 with 16-bit storage (it reads back
+ * the maximum of |g / f*| to choose S).  On failure *out is NULL and nothing is enqueued.
+ */
+lbm_status lbm_lee_init(const lbm_lee_desc *desc, void *pop_a, void *pop_b, size_t bytes_each,
+                        const double *rho, const double *u, const double *theta,
+                        void *scratch, size_t scratch_bytes, void *stream, lbm_lee_handle *out);
+
+/* Re-initialise an existing handle from new macroscopic fields (same rules as lbm_lee_init,
+ * the storage scale is kept).  Resets the step counter. */
+lbm_status lbm_lee_reinit(lbm_lee_handle h, const double *rho, const double *u, const double *theta, void *stream);
+
+/* Advance nsteps >= 0 time steps (fused pull-stream + moments + equilibrium + relaxation,
+ * one kernel launch per step, periodic box). */
+lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream);
+
+/*
+ * Macroscopic fields of the current state (moments of the monoatomic / polyatomic FDVM
+ * sections; p' = rho0 theta' + theta0 rho' from Section "The Linearized Euler Equations").
+ * Sums are taken in FP64.  Any output may be NULL.  out_is_f64 != 0: outputs are double,
+ * else float.  p, rho, theta: N values; u: D * N values.
+ */
+lbm_status lbm_lee_moments(lbm_lee_handle h, void *p, void *u, void *rho, void *theta, int32_t out_is_f64,
+                           void *stream);
+
+/*
+ * out[0] = sum_x sum_i g_i^2 / f*_i  (the weighted L2 energy; constant at tau = 1/2 for every
+ *          set, non-increasing for tau > 1/2: stability structure of the D3Q19 section),
+ * out[1] = sum_x sum_i g_i^2         (the von Neumann L2 norm squared of Section "Analysis of
+ *          the LBE"; constant when Gamma(k) is unitary).
+ * FP64 accumulation, deterministic two-pass reduction.  SYNCHRONISES the stream.
+ */
+lbm_status lbm_lee_l2_energy(lbm_lee_handle h, double out[2], void *stream);
+
+/*
+ * Error of the current state against reference fields (device FP64, N and D * N values;
+ * ref_u may be NULL):  out = { sum (p'-p_ref)^2, sum p_ref^2, max |p'-p_ref|,
+ *                              sum |u'-u_ref|^2, sum |u_ref|^2, max_a,x |u'_a-u_ref,a| }.
+ * Multiply sums by dx^D for the discrete L2 norm of Section "Numerical Results".
+ * SYNCHRONISES the stream.
+ */
+lbm_status lbm_lee_error_norms(lbm_lee_handle h, const double *ref_p, const double *ref_u, double out[6],
+                               void *stream);
+
+/* Decode the current populations into FP64 g (device, Q * N doubles, the layout above). */
+lbm_status lbm_lee_export_f64(lbm_lee_handle h, double *g, void *stream);
+
+/* Encode FP64 populations g (device, Q * N doubles) into the current state (checkpoint
+ * restore, arbitrary non-equilibrium states).  steps_done is stored as the step counter. */
+lbm_status lbm_lee_import_f64(lbm_lee_handle h, const double *g, int64_t steps_done, void *stream);
+
+/* Device pointer of the buffer holding the current state, and the steps taken so far. */
+lbm_status lbm_lee_current(lbm_lee_handle h, void **pop, int64_t *steps_done);
+
+/* The storage scale S in use (1 for F64/F32). */
+double lbm_lee_store_scale(lbm_lee_handle h);
+
+/* Free the handle (host memory only; device buffers stay with the caller). NULL is a no-op. */
+void lbm_lee_destroy(lbm_lee_handle h);
+
+/* Plain device-to-device copy kernel (16-byte vectors): the reference point for bandwidth
+ * and counter calibration.  bytes must be a multiple of 16, both pointers 16-byte aligned. */
+lbm_status lbm_lee_device_copy(void *dst, const void *src, size_t bytes, void *stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *lbm_lee_last_error(void);
+
+/* Library version string. */
+const char *lbm_lee_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_LEE_H */

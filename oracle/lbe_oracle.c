@@ -22,7 +22,7 @@
  * Layout: g[i * N + cell], cell = x + nx * (y + ny * z), N = nx*ny*nz.
  * Unused dimensions have extent 1 and velocity component 0.
  *
- * The cell loop is split over OpenMP threads when nthreads > 1; every (i, destination)
+ * The loop over rows is split over OpenMP threads when nthreads > 1; every (i, destination)
  * pair is written by exactly one source cell, so the threads never write the same slot.
  */
 #include <stdlib.h>
@@ -79,10 +79,10 @@ int oracle_lbe_steps(int Q, const int *c, const double *fstar, const double *bet
     (void)nthreads;
 #endif
     for (long s = 0; s < nsteps; ++s) {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for collapse(2) schedule(static)
         for (long z = 0; z < nz; ++z) {
-            double in[27], out[27];
             for (long y = 0; y < ny; ++y) {
+                double in[27], out[27];
                 for (long x = 0; x < nx; ++x) {
                     long cell = x + nx * (y + ny * z);
                     for (int i = 0; i < Q; ++i) in[i] = src[(long)i * N + cell];

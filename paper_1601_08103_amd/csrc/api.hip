@@ -1,0 +1,477 @@
+// C ABI of the LEE lattice Boltzmann library: argument checks, coefficient setup, dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/lbm_lee.h"
+#include "kernels.hpp"
+#include "tables.hpp"
+
+using namespace lbm;
+
+struct lbm_lee {
+    lbm_lee_desc desc;
+    LatticeTable tab;
+    size_t N;
+    int nx, ny, nz;
+    void *buf[2];
+    int cur;
+    int64_t steps;
+    void *scratch;
+    size_t scratch_bytes;
+    double S;  // storage scale (1 for F64/F32)
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status st, const char *fmt, ...) {
+    char msg[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(msg, sizeof msg, fmt, ap);
+    va_end(ap);
+    g_err = msg;
+    return st;
+}
+
+lbm_status ok() {
+    g_err.clear();
+    return LBM_OK;
+}
+
+#define LBM_HIP(call)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess) return fail(LBM_E_HIP, "%s: %s", #call, hipGetErrorString(e_));  \
+    } while (0)
+
+constexpr int kReduceBlocks = 1024;           // fixed grid of the two-pass reductions
+constexpr size_t kScratchBytes = 96 * 1024;  // partials (1024 x 6 doubles) + results
+
+size_t elem_size(int storage) {
+    switch (storage) {
+        case LBM_F64: return 8;
+        case LBM_F32: return 4;
+        case LBM_F16:
+        case LBM_BF16: return 2;
+        default: return 0;
+    }
+}
+
+bool aligned256(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
+    if (!d) return fail(LBM_E_INVALID, "desc is NULL");
+    if (!build_lattice(d->lattice, tab)) return fail(LBM_E_INVALID, "unknown lattice id %d", d->lattice);
+    if (elem_size(d->storage) == 0) return fail(LBM_E_INVALID, "unknown storage id %d", d->storage);
+    for (int a = 0; a < 3; ++a) {
+        if (d->n[a] < 1 || d->n[a] > (int64_t)1 << 30) return fail(LBM_E_INVALID, "n[%d] = %lld out of range", a, (long long)d->n[a]);
+        if (a >= tab->D && d->n[a] != 1) return fail(LBM_E_INVALID, "n[%d] must be 1 for a %dD lattice", a, tab->D);
+    }
+    const double N = (double)d->n[0] * (double)d->n[1] * (double)d->n[2];
+    if (N * tab->Q > 9.0e18 / 8.0) return fail(LBM_E_INVALID, "domain too large");
+    if ((double)d->n[1] * (double)d->n[2] * 16.0 > 4.0e9) return fail(LBM_E_INVALID, "too many rows (ny * nz)");
+    if (!(d->tau >= 0.5) || !std::isfinite(d->tau)) return fail(LBM_E_INVALID, "tau must be finite and >= 1/2 (got %g)", d->tau);
+    if (d->variant < LBM_VARIANT_AUTO || d->variant > LBM_VARIANT_LDS) return fail(LBM_E_INVALID, "unknown variant %d", d->variant);
+    if (d->reserved0 != 0) return fail(LBM_E_INVALID, "reserved0 must be 0");
+    if (!(d->store_scale >= 0.0) || !std::isfinite(d->store_scale)) return fail(LBM_E_INVALID, "store_scale must be >= 0");
+    if (d->store_scale > 0.0) {
+        int ex;
+        if (std::frexp(d->store_scale, &ex) != 0.5) return fail(LBM_E_INVALID, "store_scale must be a power of two");
+    }
+    if (d->variant == LBM_VARIANT_DPP && d->n[0] % 4 != 0) return fail(LBM_E_UNSUPPORTED, "DPP variant needs nx %% 4 == 0");
+    if (d->variant == LBM_VARIANT_LDS) return fail(LBM_E_UNSUPPORTED, "LDS variant is not built");
+    return LBM_OK;
+}
+
+// ------------------------------------------------------------------ dispatch on (velocity set, storage)
+template <class VS, class F>
+lbm_status visit_storage(int storage, F &&f) {
+    switch (storage) {
+        case LBM_F64: return f(VS{}, StF64{});
+        case LBM_F32: return f(VS{}, StF32{});
+        case LBM_F16: return f(VS{}, StF16{});
+        case LBM_BF16: return f(VS{}, StBF16{});
+        default: return fail(LBM_E_INVALID, "unknown storage id %d", storage);
+    }
+}
+
+template <class F>
+lbm_status visit(int lattice, int storage, F &&f) {
+    switch (lattice) {
+        case LBM_D1Q3: return visit_storage<VS_D1Q3>(storage, f);
+        case LBM_D2Q5:
+        case LBM_D2Q5_DIA: return visit_storage<VS_D2Q5>(storage, f);
+        case LBM_D2Q9: return visit_storage<VS_D2Q9>(storage, f);
+        case LBM_D3Q7:
+        case LBM_D3Q7_DIA: return visit_storage<VS_D3Q7>(storage, f);
+        case LBM_D3Q9: return visit_storage<VS_D3Q9>(storage, f);
+        case LBM_D3Q13: return visit_storage<VS_D3Q13>(storage, f);
+        case LBM_D3Q19: return visit_storage<VS_D3Q19>(storage, f);
+        default: return fail(LBM_E_INVALID, "unknown lattice id %d", lattice);
+    }
+}
+
+template <int Q>
+FieldCoef<Q> field_coef(const lbm_lee *h) {
+    FieldCoef<Q> k;
+    const LatticeTable &t = h->tab;
+    const bool scaled = h->desc.storage == LBM_F16 || h->desc.storage == LBM_BF16;
+    for (int i = 0; i < Q; ++i) {
+        k.f[i] = t.f[i];
+        k.dec[i] = scaled ? t.f[i] / h->S : 1.0;
+        k.enc[i] = scaled ? h->S / t.f[i] : 1.0;
+        const int c2 = t.c[i][0] * t.c[i][0] + t.c[i][1] * t.c[i][1] + t.c[i][2] * t.c[i][2];
+        k.e[i] = 0.5 * (c2 + t.beta[i]);
+    }
+    k.rho0 = t.rho0;
+    k.theta0 = t.theta0;
+    k.gm1 = t.gamma - 1.0;
+    k.a1 = t.a1;
+    k.a2 = t.a2;
+    k.b = t.b;
+    k.c1 = t.c1;
+    k.c2 = t.c2;
+    return k;
+}
+
+template <typename CT, int Q>
+StepCoef<CT, Q> step_coef(const lbm_lee *h) {
+    const FieldCoef<Q> f = field_coef<Q>(h);
+    StepCoef<CT, Q> k;
+    const double omega = 1.0 / h->desc.tau;
+    for (int i = 0; i < Q; ++i) {
+        k.dec[i] = (CT)f.dec[i];
+        k.edec[i] = (CT)(f.e[i] * f.dec[i]);
+        k.w[i] = (CT)(omega * f.enc[i] * f.f[i]);
+    }
+    k.keep = (CT)(1.0 - omega);
+    k.gm1_rho0 = (CT)(f.gm1 / f.rho0);
+    k.theta0_rho0 = (CT)(f.theta0 / f.rho0);
+    k.a1 = (CT)f.a1;
+    k.a2 = (CT)f.a2;
+    k.c1 = (CT)f.c1;
+    k.c2 = (CT)f.c2;
+    k.b_rho0 = (CT)(f.b / f.rho0);
+    return k;
+}
+
+unsigned blocks_for(size_t n) { return (unsigned)((n + 255) / 256); }
+
+lbm_status launch_check() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(LBM_E_HIP, "kernel launch: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int resolve_variant(const lbm_lee *h) {
+    if (h->desc.variant != LBM_VARIANT_AUTO) return h->desc.variant;
+    return (h->nx % 4 == 0) ? LBM_VARIANT_DPP : LBM_VARIANT_GENERIC;
+}
+
+lbm_status launch_init(lbm_lee *h, const double *rho, const double *u, const double *theta, hipStream_t st) {
+    return visit(h->desc.lattice, h->desc.storage, [&](auto vs, auto sto) -> lbm_status {
+        using VS = decltype(vs);
+        using ST = decltype(sto);
+        auto k = field_coef<VS::Q>(h);
+        auto *dst = static_cast<typename ST::elem *>(h->buf[h->cur]);
+        init_equilibrium<VS, ST><<<blocks_for(h->N), 256, 0, st>>>(rho, u, theta, dst, h->N, k);
+        return launch_check();
+    });
+}
+
+lbm_status choose_scale(lbm_lee *h, const double *rho, const double *u, const double *theta, hipStream_t st) {
+    const bool scaled = h->desc.storage == LBM_F16 || h->desc.storage == LBM_BF16;
+    if (!scaled) {
+        h->S = 1.0;
+        return LBM_OK;
+    }
+    if (h->desc.store_scale > 0.0) {
+        h->S = h->desc.store_scale;
+        return LBM_OK;
+    }
+    double *part = static_cast<double *>(h->scratch);
+    double *res = part + 6 * kReduceBlocks;
+    lbm_status s = visit(h->desc.lattice, LBM_F64, [&](auto vs, auto) -> lbm_status {
+        using VS = decltype(vs);
+        auto k = field_coef<VS::Q>(h);  // scale-independent parts only are used
+        scale_partials<VS><<<kReduceBlocks, 256, 0, st>>>(rho, u, theta, h->N, k, part);
+        return launch_check();
+    });
+    if (s != LBM_OK) return s;
+    reduce_partials<1><<<1, 256, 0, st>>>(part, kReduceBlocks, res, 1u);
+    if ((s = launch_check()) != LBM_OK) return s;
+    double mx = 0.0;
+    LBM_HIP(hipMemcpyAsync(&mx, res, sizeof(double), hipMemcpyDeviceToHost, st));
+    LBM_HIP(hipStreamSynchronize(st));
+    if (!(mx > 0.0) || !std::isfinite(mx)) {
+        h->S = 1.0;
+    } else {
+        int ex;
+        std::frexp(mx, &ex);  // mx = m 2^ex, m in [1/2, 1)
+        h->S = std::ldexp(1.0, -ex);  // S mx in [1/2, 1)
+    }
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbm_lee_last_error(void) { return g_err.c_str(); }
+
+const char *lbm_lee_version(void) { return "lbm_lee 0.1 gfx950"; }
+
+lbm_status lbm_lee_lattice_info(int32_t lattice, lbm_lattice_info *out) {
+    if (!out) return fail(LBM_E_INVALID, "out is NULL");
+    LatticeTable t;
+    if (!build_lattice(lattice, &t)) return fail(LBM_E_INVALID, "unknown lattice id %d", lattice);
+    std::memset(out, 0, sizeof(*out));
+    out->D = t.D;
+    out->Q = t.Q;
+    for (int i = 0; i < t.Q; ++i) {
+        for (int a = 0; a < 3; ++a) out->c[i][a] = t.c[i][a];
+        out->fstar[i] = t.f[i];
+        out->beta[i] = t.beta[i];
+    }
+    out->rho0 = t.rho0;
+    out->theta0 = t.theta0;
+    out->gamma = t.gamma;
+    out->a1 = t.a1;
+    out->a2 = t.a2;
+    out->b = t.b;
+    out->c1 = t.c1;
+    out->c2 = t.c2;
+    std::snprintf(out->name, sizeof out->name, "%s", t.name);
+    return ok();
+}
+
+size_t lbm_lee_state_bytes(const lbm_lee_desc *d) {
+    LatticeTable t;
+    if (check_desc(d, &t) != LBM_OK) return 0;
+    return (size_t)t.Q * (size_t)(d->n[0] * d->n[1] * d->n[2]) * elem_size(d->storage);
+}
+
+size_t lbm_lee_scratch_bytes(const lbm_lee_desc *d) {
+    LatticeTable t;
+    if (check_desc(d, &t) != LBM_OK) return 0;
+    return kScratchBytes;
+}
+
+double lbm_lee_bytes_per_update(const lbm_lee_desc *d) {
+    LatticeTable t;
+    if (check_desc(d, &t) != LBM_OK) return 0.0;
+    return 2.0 * t.Q * (double)elem_size(d->storage);
+}
+
+lbm_status lbm_lee_init(const lbm_lee_desc *desc, void *pop_a, void *pop_b, size_t bytes_each, const double *rho,
+                        const double *u, const double *theta, void *scratch, size_t scratch_bytes, void *stream,
+                        lbm_lee_handle *out) {
+    if (!out) return fail(LBM_E_INVALID, "out is NULL");
+    *out = nullptr;
+    LatticeTable tab;
+    lbm_status s = check_desc(desc, &tab);
+    if (s != LBM_OK) return s;
+    const size_t N = (size_t)(desc->n[0] * desc->n[1] * desc->n[2]);
+    const size_t need = (size_t)tab.Q * N * elem_size(desc->storage);
+    if (!pop_a || !pop_b || pop_a == pop_b) return fail(LBM_E_INVALID, "pop_a and pop_b must be two distinct buffers");
+    if (!aligned256(pop_a) || !aligned256(pop_b)) return fail(LBM_E_INVALID, "population buffers must be 256-byte aligned");
+    if (bytes_each < need) return fail(LBM_E_INVALID, "population buffers hold %zu bytes, need %zu", bytes_each, need);
+    const char *a = static_cast<const char *>(pop_a), *b = static_cast<const char *>(pop_b);
+    if (a < b + need && b < a + need) return fail(LBM_E_INVALID, "population buffers overlap");
+    if (!rho || !u || !theta) return fail(LBM_E_INVALID, "initial fields must not be NULL");
+    if (!scratch || !aligned256(scratch) || scratch_bytes < kScratchBytes)
+        return fail(LBM_E_INVALID, "scratch must be 256-byte aligned and hold >= %zu bytes", kScratchBytes);
+    lbm_lee *h = new (std::nothrow) lbm_lee;
+    if (!h) return fail(LBM_E_INVALID, "out of host memory");
+    h->desc = *desc;
+    h->tab = tab;
+    h->N = N;
+    h->nx = (int)desc->n[0];
+    h->ny = (int)desc->n[1];
+    h->nz = (int)desc->n[2];
+    h->buf[0] = pop_a;
+    h->buf[1] = pop_b;
+    h->cur = 0;
+    h->steps = 0;
+    h->scratch = scratch;
+    h->scratch_bytes = scratch_bytes;
+    h->S = 1.0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((s = choose_scale(h, rho, u, theta, st)) != LBM_OK || (s = launch_init(h, rho, u, theta, st)) != LBM_OK) {
+        delete h;
+        return s;
+    }
+    *out = h;
+    return ok();
+}
+
+lbm_status lbm_lee_reinit(lbm_lee_handle h, const double *rho, const double *u, const double *theta, void *stream) {
+    if (!h) return fail(LBM_E_INVALID, "handle is NULL");
+    if (!rho || !u || !theta) return fail(LBM_E_INVALID, "initial fields must not be NULL");
+    h->cur = 0;
+    h->steps = 0;
+    lbm_status s = launch_init(h, rho, u, theta, static_cast<hipStream_t>(stream));
+    return s == LBM_OK ? ok() : s;
+}
+
+lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
+    if (!h) return fail(LBM_E_INVALID, "handle is NULL");
+    if (nsteps < 0) return fail(LBM_E_INVALID, "nsteps must be >= 0");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int variant = resolve_variant(h);
+    lbm_status s = visit(h->desc.lattice, h->desc.storage, [&](auto vs, auto sto) -> lbm_status {
+        using VS = decltype(vs);
+        using ST = decltype(sto);
+        using E = typename ST::elem;
+        const auto k = step_coef<typename ST::comp, VS::Q>(h);
+        const int cpr = (h->nx + 255) / 256;
+        const unsigned waves = (unsigned)((size_t)h->ny * h->nz * cpr);
+        const bool fullrow = h->nx == 256;
+        for (int64_t t = 0; t < nsteps; ++t) {
+            const E *src = static_cast<const E *>(h->buf[h->cur]);
+            E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);
+            if (variant == LBM_VARIANT_GENERIC) {
+                step_generic<VS, ST><<<blocks_for(h->N), 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, k);
+            } else if (fullrow) {
+                step_dpp<VS, ST, true><<<(waves + 3) / 4, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr, waves, k);
+            } else {
+                step_dpp<VS, ST, false><<<(waves + 3) / 4, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr, waves, k);
+            }
+            lbm_status ls = launch_check();
+            if (ls != LBM_OK) return ls;
+            h->cur ^= 1;
+            h->steps += 1;
+        }
+        return LBM_OK;
+    });
+    return s == LBM_OK ? ok() : s;
+}
+
+lbm_status lbm_lee_moments(lbm_lee_handle h, void *p, void *u, void *rho, void *theta, int32_t out_is_f64,
+                           void *stream) {
+    if (!h) return fail(LBM_E_INVALID, "handle is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    lbm_status s = visit(h->desc.lattice, h->desc.storage, [&](auto vs, auto sto) -> lbm_status {
+        using VS = decltype(vs);
+        using ST = decltype(sto);
+        auto k = field_coef<VS::Q>(h);
+        const auto *src = static_cast<const typename ST::elem *>(h->buf[h->cur]);
+        if (out_is_f64)
+            moments_kernel<VS, ST, double><<<blocks_for(h->N), 256, 0, st>>>(
+                src, h->N, k, (double *)p, (double *)u, (double *)rho, (double *)theta);
+        else
+            moments_kernel<VS, ST, float><<<blocks_for(h->N), 256, 0, st>>>(
+                src, h->N, k, (float *)p, (float *)u, (float *)rho, (float *)theta);
+        return launch_check();
+    });
+    return s == LBM_OK ? ok() : s;
+}
+
+lbm_status lbm_lee_l2_energy(lbm_lee_handle h, double out[2], void *stream) {
+    if (!h || !out) return fail(LBM_E_INVALID, "handle or out is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *part = static_cast<double *>(h->scratch);
+    double *res = part + 6 * kReduceBlocks;
+    lbm_status s = visit(h->desc.lattice, h->desc.storage, [&](auto vs, auto sto) -> lbm_status {
+        using VS = decltype(vs);
+        using ST = decltype(sto);
+        auto k = field_coef<VS::Q>(h);
+        const auto *src = static_cast<const typename ST::elem *>(h->buf[h->cur]);
+        energy_partials<VS, ST><<<kReduceBlocks, 256, 0, st>>>(src, h->N, k, part);
+        return launch_check();
+    });
+    if (s != LBM_OK) return s;
+    reduce_partials<2><<<1, 256, 0, st>>>(part, kReduceBlocks, res, 0u);
+    if ((s = launch_check()) != LBM_OK) return s;
+    LBM_HIP(hipMemcpyAsync(out, res, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    LBM_HIP(hipStreamSynchronize(st));
+    return ok();
+}
+
+lbm_status lbm_lee_error_norms(lbm_lee_handle h, const double *ref_p, const double *ref_u, double out[6],
+                               void *stream) {
+    if (!h || !out || !ref_p) return fail(LBM_E_INVALID, "handle, ref_p or out is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *part = static_cast<double *>(h->scratch);
+    double *res = part + 6 * kReduceBlocks;
+    lbm_status s = visit(h->desc.lattice, h->desc.storage, [&](auto vs, auto sto) -> lbm_status {
+        using VS = decltype(vs);
+        using ST = decltype(sto);
+        auto k = field_coef<VS::Q>(h);
+        const auto *src = static_cast<const typename ST::elem *>(h->buf[h->cur]);
+        error_partials<VS, ST><<<kReduceBlocks, 256, 0, st>>>(src, h->N, k, ref_p, ref_u, part);
+        return launch_check();
+    });
+    if (s != LBM_OK) return s;
+    reduce_partials<6><<<1, 256, 0, st>>>(part, kReduceBlocks, res, (1u << 2) | (1u << 5));
+    if ((s = launch_check()) != LBM_OK) return s;
+    LBM_HIP(hipMemcpyAsync(out, res, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
+    LBM_HIP(hipStreamSynchronize(st));
+    return ok();
+}
+
+lbm_status lbm_lee_export_f64(lbm_lee_handle h, double *g, void *stream) {
+    if (!h || !g) return fail(LBM_E_INVALID, "handle or g is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    lbm_status s = visit(h->desc.lattice, h->desc.storage, [&](auto vs, auto sto) -> lbm_status {
+        using VS = decltype(vs);
+        using ST = decltype(sto);
+        auto k = field_coef<VS::Q>(h);
+        const auto *src = static_cast<const typename ST::elem *>(h->buf[h->cur]);
+        export_f64<VS, ST><<<blocks_for((size_t)VS::Q * h->N), 256, 0, st>>>(src, h->N, k, g);
+        return launch_check();
+    });
+    return s == LBM_OK ? ok() : s;
+}
+
+lbm_status lbm_lee_import_f64(lbm_lee_handle h, const double *g, int64_t steps_done, void *stream) {
+    if (!h || !g) return fail(LBM_E_INVALID, "handle or g is NULL");
+    if (steps_done < 0) return fail(LBM_E_INVALID, "steps_done must be >= 0");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    lbm_status s = visit(h->desc.lattice, h->desc.storage, [&](auto vs, auto sto) -> lbm_status {
+        using VS = decltype(vs);
+        using ST = decltype(sto);
+        auto k = field_coef<VS::Q>(h);
+        auto *dst = static_cast<typename ST::elem *>(h->buf[h->cur]);
+        import_f64<VS, ST><<<blocks_for((size_t)VS::Q * h->N), 256, 0, st>>>(g, h->N, k, dst);
+        return launch_check();
+    });
+    if (s != LBM_OK) return s;
+    h->steps = steps_done;
+    return ok();
+}
+
+lbm_status lbm_lee_current(lbm_lee_handle h, void **pop, int64_t *steps_done) {
+    if (!h) return fail(LBM_E_INVALID, "handle is NULL");
+    if (pop) *pop = h->buf[h->cur];
+    if (steps_done) *steps_done = h->steps;
+    return ok();
+}
+
+double lbm_lee_store_scale(lbm_lee_handle h) { return h ? h->S : 0.0; }
+
+void lbm_lee_destroy(lbm_lee_handle h) { delete h; }
+
+lbm_status lbm_lee_device_copy(void *dst, const void *src, size_t bytes, void *stream) {
+    if (!dst || !src) return fail(LBM_E_INVALID, "NULL pointer");
+    if (bytes % 16 || (reinterpret_cast<uintptr_t>(dst) & 15) || (reinterpret_cast<uintptr_t>(src) & 15))
+        return fail(LBM_E_INVALID, "copy needs 16-byte aligned pointers and a size multiple of 16");
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return ok();
+    const size_t want = (n16 + 255) / 256;
+    const unsigned blocks = (unsigned)(want < 65536 ? want : 65536);
+    copy16<<<blocks, 256, 0, static_cast<hipStream_t>(stream)>>>(static_cast<const f32x4 *>(src),
+                                                                   static_cast<f32x4 *>(dst), n16);
+    lbm_status s = launch_check();
+    return s == LBM_OK ? ok() : s;
+}
+
+}  // extern "C"

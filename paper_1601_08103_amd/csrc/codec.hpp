@@ -1,0 +1,111 @@
+// Storage codecs for the population arrays.
+//
+// F64 / F32 store g itself.  F16 / BF16 store h = S g / f* (S a power of two), rounded to
+// nearest-even; the collision is computed in FP32 on the decoded h, with the constants
+// folded so that no per-population rescaling is needed inside the step kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+
+struct StF64 {
+    using elem = double;
+    using comp = double;
+    static constexpr bool scaled = false;
+    __device__ static comp dec(elem v) { return v; }
+    __device__ static elem enc(comp v) { return v; }
+    __device__ static elem enc_d(double v) { return v; }
+};
+
+struct StF32 {
+    using elem = float;
+    using comp = float;
+    static constexpr bool scaled = false;
+    __device__ static comp dec(elem v) { return v; }
+    __device__ static elem enc(comp v) { return v; }
+    __device__ static elem enc_d(double v) { return (float)v; }
+};
+
+struct StF16 {
+    using elem = unsigned short;
+    using comp = float;
+    static constexpr bool scaled = true;
+    __device__ static comp dec(elem v) { return (float)__builtin_bit_cast(_Float16, v); }
+    // v_cvt_f16_f32 rounds with the default mode: to nearest, ties to even.
+    __device__ static elem enc(comp v) { return __builtin_bit_cast(unsigned short, (_Float16)v); }
+    __device__ static elem enc_d(double v) { return __builtin_bit_cast(unsigned short, (_Float16)v); }
+};
+
+struct StBF16 {
+    using elem = unsigned short;
+    using comp = float;
+    static constexpr bool scaled = true;
+    __device__ static comp dec(elem v) { return __uint_as_float(((unsigned)v) << 16); }
+    // Round to nearest, ties to even, on the upper 16 bits of the FP32 pattern.  Finite
+    // inputs only (the state of a stable run never holds NaN or Inf).
+    __device__ static elem enc(comp v) {
+        unsigned u = __float_as_uint(v);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return (elem)(u >> 16);
+    }
+    __device__ static elem enc_d(double v) { return enc((float)v); }
+};
+
+// Four consecutive elements starting at a 4-element-aligned index, decoded to the compute type.
+template <class ST>
+__device__ inline void load4(const typename ST::elem *p, typename ST::comp (&v)[4]);
+
+template <>
+__device__ inline void load4<StF64>(const double *p, double (&v)[4]) {
+    f64x2 a = *reinterpret_cast<const f64x2 *>(p);
+    f64x2 b = *reinterpret_cast<const f64x2 *>(p + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+template <>
+__device__ inline void load4<StF32>(const float *p, float (&v)[4]) {
+    f32x4 a = *reinterpret_cast<const f32x4 *>(p);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+template <>
+__device__ inline void load4<StF16>(const unsigned short *p, float (&v)[4]) {
+    u16x4 a = *reinterpret_cast<const u16x4 *>(p);
+    v[0] = StF16::dec(a.x); v[1] = StF16::dec(a.y); v[2] = StF16::dec(a.z); v[3] = StF16::dec(a.w);
+}
+template <>
+__device__ inline void load4<StBF16>(const unsigned short *p, float (&v)[4]) {
+    u16x4 a = *reinterpret_cast<const u16x4 *>(p);
+    v[0] = StBF16::dec(a.x); v[1] = StBF16::dec(a.y); v[2] = StBF16::dec(a.z); v[3] = StBF16::dec(a.w);
+}
+
+template <class ST>
+__device__ inline void store4(typename ST::elem *p, const typename ST::comp (&v)[4]);
+
+template <>
+__device__ inline void store4<StF64>(double *p, const double (&v)[4]) {
+    f64x2 a = {v[0], v[1]}, b = {v[2], v[3]};
+    *reinterpret_cast<f64x2 *>(p) = a;
+    *reinterpret_cast<f64x2 *>(p + 2) = b;
+}
+template <>
+__device__ inline void store4<StF32>(float *p, const float (&v)[4]) {
+    f32x4 a = {v[0], v[1], v[2], v[3]};
+    *reinterpret_cast<f32x4 *>(p) = a;
+}
+template <>
+__device__ inline void store4<StF16>(unsigned short *p, const float (&v)[4]) {
+    u16x4 a = {StF16::enc(v[0]), StF16::enc(v[1]), StF16::enc(v[2]), StF16::enc(v[3])};
+    *reinterpret_cast<u16x4 *>(p) = a;
+}
+template <>
+__device__ inline void store4<StBF16>(unsigned short *p, const float (&v)[4]) {
+    u16x4 a = {StBF16::enc(v[0]), StBF16::enc(v[1]), StBF16::enc(v[2]), StBF16::enc(v[3])};
+    *reinterpret_cast<u16x4 *>(p) = a;
+}
+
+}  // namespace lbm

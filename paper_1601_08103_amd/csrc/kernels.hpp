@@ -1,0 +1,416 @@
+// HIP kernels of the LEE lattice Boltzmann scheme for gfx950.
+//
+// The time step is the fully discrete LBE update (Section "Derivation of the Lattice
+// Boltzmann Equation") in pull form: every cell gathers g_i from x - c_i (streaming), takes
+// the moments rho', u', theta' (monoatomic / polyatomic FDVM sections), builds the
+// equilibrium of the polyatomic ansatz and relaxes with 1/tau.  The collision conserves the
+// moments (the equilibrium map is a projection), so moments of the pre- and post-collision
+// states agree and the pull form is the paper's push form shifted by one half step.  A state
+// set to equilibrium is a fixed point of the collision, so the initial condition g = g^eq
+// may be stored as a post-collision state.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "codec.hpp"
+#include "velsets.hpp"
+
+namespace lbm {
+
+// ------------------------------------------------------------------ constants
+// Collision constants in storage units, for compute type CT.  With stored value s_i and
+// decoded population g_i = dec_i s_i:
+//   rho'  = sum dec_i s_i,      j = sum c_i dec_i s_i,      e = sum edec_i s_i,
+//   theta' = gm1_rho0 e - theta0_rho0 rho',   U = b_rho0 j  (= b u'),
+//   A = a1 rho' + a2 theta',  C = c1 rho' + c2 theta',
+//   s_i <- keep s_i + w_i (A + c_i.U + |c_i|^2/2 C)
+// where keep = 1 - 1/tau and w_i = (1/tau) enc_i f*_i (the equilibrium in storage units).
+template <typename CT, int Q>
+struct StepCoef {
+    CT dec[Q];
+    CT edec[Q];
+    CT w[Q];
+    CT keep, gm1_rho0, theta0_rho0, a1, a2, c1, c2, b_rho0;
+};
+
+// FP64 constants of the non-hot kernels (init, moments, reductions, import/export).
+template <int Q>
+struct FieldCoef {
+    double f[Q];      // f*_i
+    double dec[Q];    // g_i = dec_i s_i
+    double enc[Q];    // s_i = enc_i g_i
+    double e[Q];      // (|c_i|^2 + beta_i) / 2
+    double rho0, theta0, gm1, a1, a2, b, c1, c2;
+};
+
+// ------------------------------------------------------------------ collision
+template <class VS, typename CT>
+__device__ __forceinline__ void collide(const StepCoef<CT, VS::Q> &k, CT (&s)[VS::Q]) {
+    CT rho = 0, jx = 0, jy = 0, jz = 0, e = 0;
+#pragma unroll
+    for (int i = 0; i < VS::Q; ++i) {
+        const CT g = k.dec[i] * s[i];
+        rho += g;
+        if (VS::cx(i) > 0) jx += g;
+        if (VS::cx(i) < 0) jx -= g;
+        if (VS::cy(i) > 0) jy += g;
+        if (VS::cy(i) < 0) jy -= g;
+        if (VS::cz(i) > 0) jz += g;
+        if (VS::cz(i) < 0) jz -= g;
+        e += k.edec[i] * s[i];
+    }
+    const CT theta = k.gm1_rho0 * e - k.theta0_rho0 * rho;
+    const CT A = k.a1 * rho + k.a2 * theta;
+    const CT C = k.c1 * rho + k.c2 * theta;
+    const CT Ux = k.b_rho0 * jx, Uy = k.b_rho0 * jy, Uz = k.b_rho0 * jz;
+#pragma unroll
+    for (int i = 0; i < VS::Q; ++i) {
+        CT t = A;
+        if (VS::cx(i) > 0) t += Ux;
+        if (VS::cx(i) < 0) t -= Ux;
+        if (VS::cy(i) > 0) t += Uy;
+        if (VS::cy(i) < 0) t -= Uy;
+        if (VS::cz(i) > 0) t += Uz;
+        if (VS::cz(i) < 0) t -= Uz;
+        if (VS::c2(i) != 0) t += (CT)(0.5 * VS::c2(i)) * C;
+        s[i] = k.keep * s[i] + k.w[i] * t;
+    }
+}
+
+__device__ __forceinline__ int wrap_add(int v, int d, int n) {
+    v += d;
+    if (v < 0) v += n;
+    if (v >= n) v -= n;
+    return v;
+}
+
+// ------------------------------------------------------------------ step: generic variant
+// One thread per cell, each population gathered with its own wrapped index.  Any extents.
+template <class VS, class ST>
+__global__ __launch_bounds__(256) void step_generic(const typename ST::elem *__restrict__ src,
+                                                    typename ST::elem *__restrict__ dst, int nx, int ny, int nz,
+                                                    size_t N, StepCoef<typename ST::comp, VS::Q> k) {
+    using CT = typename ST::comp;
+    const size_t cell = (size_t)blockIdx.x * 256u + threadIdx.x;
+    if (cell >= N) return;
+    const int x = (int)(cell % (size_t)nx);
+    const size_t r = cell / (size_t)nx;
+    const int y = (int)(r % (size_t)ny);
+    const int z = (int)(r / (size_t)ny);
+    CT s[VS::Q];
+#pragma unroll
+    for (int i = 0; i < VS::Q; ++i) {
+        const int xs = wrap_add(x, -VS::cx(i), nx);
+        const int ys = wrap_add(y, -VS::cy(i), ny);
+        const int zs = wrap_add(z, -VS::cz(i), nz);
+        s[i] = ST::dec(src[(size_t)i * N + ((size_t)zs * ny + ys) * nx + xs]);
+    }
+    collide<VS, CT>(k, s);
+#pragma unroll
+    for (int i = 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
+}
+
+// ------------------------------------------------------------------ step: DPP variant
+// DPP controls of whole-wave moves (GFX9 family): lane l receives from lane l-1 (shr/ror)
+// or l+1 (shl/rol); the rotations wrap lane 0 <-> lane 63.
+enum : int { kDppWaveShl1 = 0x130, kDppWaveRol1 = 0x134, kDppWaveShr1 = 0x138, kDppWaveRor1 = 0x13C };
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Each wave owns a chunk of 256 consecutive cells of one x-row (64 lanes x 4 cells).  Rows
+// along y/z are whole-row offsets, so every load and store is an aligned 4-element vector.
+// A population with c_x = +1 needs the element left of each lane's quad: it comes from the
+// lane below through a DPP move; c_x = -1 needs the element right of the quad from the lane
+// above.  FULLROW (nx == 256) rotates within the wave, which is exactly the periodic wrap;
+// otherwise the first lane and the last active lane load their neighbour element directly.
+template <class VS, class ST, bool FULLROW>
+__global__ __launch_bounds__(256) void step_dpp(const typename ST::elem *__restrict__ src,
+                                                typename ST::elem *__restrict__ dst, int nx, int ny, int nz,
+                                                size_t N, int chunks_per_row, unsigned total_waves,
+                                                StepCoef<typename ST::comp, VS::Q> k) {
+    using CT = typename ST::comp;
+    using E = typename ST::elem;
+    const int lane = threadIdx.x & 63;
+    const unsigned wave = blockIdx.x * 4u + (unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave >= total_waves) return;  // uniform per wave
+    const unsigned row = wave / (unsigned)chunks_per_row;
+    const int chunk = (int)(wave - row * (unsigned)chunks_per_row);
+    const int y = (int)(row % (unsigned)ny);
+    const int z = (int)(row / (unsigned)ny);
+    const int x0 = chunk * 256 + lane * 4;
+    const bool active = x0 < nx;
+    const bool last = (lane == 63) || (x0 + 4 >= nx);
+
+    CT s[VS::Q][4];
+#pragma unroll
+    for (int i = 0; i < VS::Q; ++i) {
+        const int ys = wrap_add(y, -VS::cy(i), ny);
+        const int zs = wrap_add(z, -VS::cz(i), nz);
+        const E *rowp = src + (size_t)i * N + ((size_t)zs * ny + ys) * (size_t)nx;
+        CT v[4] = {0, 0, 0, 0};
+        if (active) load4<ST>(rowp + x0, v);
+        if (VS::cx(i) == 0) {
+            s[i][0] = v[0]; s[i][1] = v[1]; s[i][2] = v[2]; s[i][3] = v[3];
+        } else if (VS::cx(i) > 0) {
+            CT prev = FULLROW ? dpp_move<kDppWaveRor1>(v[3]) : dpp_move<kDppWaveShr1>(v[3]);
+            if (!FULLROW && lane == 0) prev = ST::dec(rowp[x0 == 0 ? nx - 1 : x0 - 1]);
+            s[i][0] = prev; s[i][1] = v[0]; s[i][2] = v[1]; s[i][3] = v[2];
+        } else {
+            CT next = FULLROW ? dpp_move<kDppWaveRol1>(v[0]) : dpp_move<kDppWaveShl1>(v[0]);
+            if (!FULLROW && last && active) next = ST::dec(rowp[x0 + 4 >= nx ? 0 : x0 + 4]);
+            s[i][0] = v[1]; s[i][1] = v[2]; s[i][2] = v[3]; s[i][3] = next;
+        }
+    }
+    if (!active) return;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        CT c[VS::Q];
+#pragma unroll
+        for (int i = 0; i < VS::Q; ++i) c[i] = s[i][q];
+        collide<VS, CT>(k, c);
+#pragma unroll
+        for (int i = 0; i < VS::Q; ++i) s[i][q] = c[i];
+    }
+    const size_t out = ((size_t)z * ny + y) * (size_t)nx + x0;
+#pragma unroll
+    for (int i = 0; i < VS::Q; ++i) store4<ST>(dst + (size_t)i * N + out, s[i]);
+}
+
+// ------------------------------------------------------------------ initial state
+// g_i(0, x) = g_i^eq(rho'(x), u'(x), theta'(x)) in FP64, then encoded to storage.
+template <class VS, class ST>
+__global__ __launch_bounds__(256) void init_equilibrium(const double *__restrict__ rho, const double *__restrict__ u,
+                                                        const double *__restrict__ theta,
+                                                        typename ST::elem *__restrict__ dst, size_t N,
+                                                        FieldCoef<VS::Q> k) {
+    const size_t cell = (size_t)blockIdx.x * 256u + threadIdx.x;
+    if (cell >= N) return;
+    const double r = rho[cell], th = theta[cell];
+    const double ux = u[cell];
+    const double uy = VS::D >= 2 ? u[N + cell] : 0.0;
+    const double uz = VS::D >= 3 ? u[2 * N + cell] : 0.0;
+    const double A = k.a1 * r + k.a2 * th;
+    const double C = k.c1 * r + k.c2 * th;
+#pragma unroll
+    for (int i = 0; i < VS::Q; ++i) {
+        const double cu = VS::cx(i) * ux + VS::cy(i) * uy + VS::cz(i) * uz;
+        const double geq = k.f[i] * (A + k.b * cu + 0.5 * VS::c2(i) * C);
+        dst[(size_t)i * N + cell] = ST::enc_d(k.enc[i] * geq);
+    }
+}
+
+// ------------------------------------------------------------------ block reductions (FP64)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Reduce NV values per thread over a 256-thread block; thread 0 gets the result.  Fixed
+// order (lane tree, then waves 0..3), so a launch with a fixed grid is deterministic.
+// IS_MAX[j] selects max instead of sum for value j.
+template <int NV>
+__device__ void block_reduce(double (&v)[NV], const bool (&is_max)[NV]) {
+    __shared__ double part[4][NV];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = is_max[j] ? wave_max(v[j]) : wave_sum(v[j]);
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) part[wv][j] = v[j];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            double a = part[0][j];
+            for (int w = 1; w < 4; ++w) a = is_max[j] ? fmax(a, part[w][j]) : a + part[w][j];
+            v[j] = a;
+        }
+    }
+}
+
+// Second pass: one block folds `nblk` partial rows (NV doubles each) in a fixed order.
+template <int NV>
+__global__ __launch_bounds__(256) void reduce_partials(const double *__restrict__ part, int nblk,
+                                                       double *__restrict__ out, unsigned max_mask) {
+    double v[NV];
+    bool is_max[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        is_max[j] = (max_mask >> j) & 1u;
+        v[j] = 0.0;
+    }
+    for (int b = threadIdx.x; b < nblk; b += 256)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] = is_max[j] ? fmax(v[j], part[(size_t)b * NV + j]) : v[j] + part[(size_t)b * NV + j];
+    block_reduce<NV>(v, is_max);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) out[j] = v[j];
+}
+
+// Weighted and plain energy of the current state: per-block partials of
+// sum g^2 / f* and sum g^2, FP64, grid-stride over cells.
+template <class VS, class ST>
+__global__ __launch_bounds__(256) void energy_partials(const typename ST::elem *__restrict__ src, size_t N,
+                                                       FieldCoef<VS::Q> k, double *__restrict__ part) {
+    double v[2] = {0.0, 0.0};
+    const bool is_max[2] = {false, false};
+    for (size_t cell = (size_t)blockIdx.x * 256u + threadIdx.x; cell < N; cell += (size_t)gridDim.x * 256u) {
+#pragma unroll
+        for (int i = 0; i < VS::Q; ++i) {
+            const double g = k.dec[i] * (double)ST::dec(src[(size_t)i * N + cell]);
+            v[0] += g * g / k.f[i];
+            v[1] += g * g;
+        }
+    }
+    block_reduce<2>(v, is_max);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = v[0];
+        part[2 * blockIdx.x + 1] = v[1];
+    }
+}
+
+// FP64 moments of one cell of the current state.
+template <class VS, class ST>
+__device__ __forceinline__ void cell_moments(const typename ST::elem *__restrict__ src, size_t N, size_t cell,
+                                             const FieldCoef<VS::Q> &k, double &rho, double (&u)[3], double &theta,
+                                             double &p) {
+    double r = 0, jx = 0, jy = 0, jz = 0, e = 0;
+#pragma unroll
+    for (int i = 0; i < VS::Q; ++i) {
+        const double g = k.dec[i] * (double)ST::dec(src[(size_t)i * N + cell]);
+        r += g;
+        jx += VS::cx(i) * g;
+        jy += VS::cy(i) * g;
+        jz += VS::cz(i) * g;
+        e += k.e[i] * g;
+    }
+    rho = r;
+    u[0] = jx / k.rho0;
+    u[1] = jy / k.rho0;
+    u[2] = jz / k.rho0;
+    theta = (k.gm1 * e - k.theta0 * r) / k.rho0;
+    p = k.rho0 * theta + k.theta0 * r;
+}
+
+template <class VS, class ST, typename OT>
+__global__ __launch_bounds__(256) void moments_kernel(const typename ST::elem *__restrict__ src, size_t N,
+                                                      FieldCoef<VS::Q> k, OT *__restrict__ p, OT *__restrict__ u,
+                                                      OT *__restrict__ rho, OT *__restrict__ theta) {
+    const size_t cell = (size_t)blockIdx.x * 256u + threadIdx.x;
+    if (cell >= N) return;
+    double r, uu[3], th, pp;
+    cell_moments<VS, ST>(src, N, cell, k, r, uu, th, pp);
+    if (p) p[cell] = (OT)pp;
+    if (rho) rho[cell] = (OT)r;
+    if (theta) theta[cell] = (OT)th;
+    if (u)
+#pragma unroll
+        for (int a = 0; a < VS::D; ++a) u[(size_t)a * N + cell] = (OT)uu[a];
+}
+
+// Error against reference fields: per-block partials of
+// { sum dp^2, sum p_ref^2, max |dp|, sum |du|^2, sum |u_ref|^2, max |du_a| }.
+template <class VS, class ST>
+__global__ __launch_bounds__(256) void error_partials(const typename ST::elem *__restrict__ src, size_t N,
+                                                      FieldCoef<VS::Q> k, const double *__restrict__ ref_p,
+                                                      const double *__restrict__ ref_u, double *__restrict__ part) {
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    const bool is_max[6] = {false, false, true, false, false, true};
+    for (size_t cell = (size_t)blockIdx.x * 256u + threadIdx.x; cell < N; cell += (size_t)gridDim.x * 256u) {
+        double r, uu[3], th, pp;
+        cell_moments<VS, ST>(src, N, cell, k, r, uu, th, pp);
+        const double dp = pp - ref_p[cell];
+        v[0] += dp * dp;
+        v[1] += ref_p[cell] * ref_p[cell];
+        v[2] = fmax(v[2], fabs(dp));
+        if (ref_u) {
+#pragma unroll
+            for (int a = 0; a < VS::D; ++a) {
+                const double ur = ref_u[(size_t)a * N + cell];
+                const double du = uu[a] - ur;
+                v[3] += du * du;
+                v[4] += ur * ur;
+                v[5] = fmax(v[5], fabs(du));
+            }
+        }
+    }
+    block_reduce<6>(v, is_max);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < 6; ++j) part[6 * blockIdx.x + j] = v[j];
+}
+
+// Max over cells and populations of |g^eq_i / f*_i| of the initial fields (storage scale).
+template <class VS>
+__global__ __launch_bounds__(256) void scale_partials(const double *__restrict__ rho, const double *__restrict__ u,
+                                                      const double *__restrict__ theta, size_t N, FieldCoef<VS::Q> k,
+                                                      double *__restrict__ part) {
+    double v[1] = {0.0};
+    const bool is_max[1] = {true};
+    for (size_t cell = (size_t)blockIdx.x * 256u + threadIdx.x; cell < N; cell += (size_t)gridDim.x * 256u) {
+        const double r = rho[cell], th = theta[cell];
+        const double ux = u[cell];
+        const double uy = VS::D >= 2 ? u[N + cell] : 0.0;
+        const double uz = VS::D >= 3 ? u[2 * N + cell] : 0.0;
+        const double A = k.a1 * r + k.a2 * th, C = k.c1 * r + k.c2 * th;
+#pragma unroll
+        for (int i = 0; i < VS::Q; ++i) {
+            const double cu = VS::cx(i) * ux + VS::cy(i) * uy + VS::cz(i) * uz;
+            v[0] = fmax(v[0], fabs(A + k.b * cu + 0.5 * VS::c2(i) * C));
+        }
+    }
+    block_reduce<1>(v, is_max);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// ------------------------------------------------------------------ import / export
+template <class VS, class ST>
+__global__ __launch_bounds__(256) void export_f64(const typename ST::elem *__restrict__ src, size_t N,
+                                                  FieldCoef<VS::Q> k, double *__restrict__ g) {
+    const size_t idx = (size_t)blockIdx.x * 256u + threadIdx.x;
+    if (idx >= (size_t)VS::Q * N) return;
+    const int i = (int)(idx / N);
+    double d = k.dec[0];
+#pragma unroll
+    for (int j = 1; j < VS::Q; ++j)
+        if (j == i) d = k.dec[j];
+    g[idx] = d * (double)ST::dec(src[idx]);
+}
+
+template <class VS, class ST>
+__global__ __launch_bounds__(256) void import_f64(const double *__restrict__ g, size_t N, FieldCoef<VS::Q> k,
+                                                  typename ST::elem *__restrict__ dst) {
+    const size_t idx = (size_t)blockIdx.x * 256u + threadIdx.x;
+    if (idx >= (size_t)VS::Q * N) return;
+    const int i = (int)(idx / N);
+    double e = k.enc[0];
+#pragma unroll
+    for (int j = 1; j < VS::Q; ++j)
+        if (j == i) e = k.enc[j];
+    dst[idx] = ST::enc_d(e * g[idx]);
+}
+
+// ------------------------------------------------------------------ plain copy (calibration)
+__global__ __launch_bounds__(256) void copy16(const f32x4 *__restrict__ src, f32x4 *__restrict__ dst, size_t n16) {
+    for (size_t i = (size_t)blockIdx.x * 256u + threadIdx.x; i < n16; i += (size_t)gridDim.x * 256u) dst[i] = src[i];
+}
+
+}  // namespace lbm

@@ -1,0 +1,109 @@
+"""The C-ABI library loads, exports every declared symbol, and checks its arguments (CPU only:
+no call here launches GPU work)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import lattices as L
+from paper_1601_08103_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "lbm_lee.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_\w+)\s*\(", text)))
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    lib = lbm.load()
+    syms = _declared_symbols()
+    assert len(syms) >= 18
+    for s in syms:
+        assert hasattr(lib, s), s
+    # the binding declares a signature for each of them, and nothing else
+    assert sorted(lbm.SIGNATURES) == syms
+    assert "gfx950" in lbm.lbm_lee_version()
+
+
+@pytest.mark.parametrize("name", list(L.ALL))
+def test_library_tables_match_oracle_tables(name):
+    """The library's host coefficient setup and the oracle's rational tables are separate
+    implementations of the same printed formulas: they must agree to rounding."""
+    got = lbm.lbm_lee_lattice_info(name)
+    lat = L.get(name)
+    assert got["D"] == lat.D and got["Q"] == lat.Q
+    assert np.array_equal(got["c"], lat.c)
+    np.testing.assert_allclose(got["fstar"], lat.fstar, rtol=0, atol=2e-16 * max(1, lat.rho0))
+    np.testing.assert_allclose(got["beta"], lat.beta, rtol=0, atol=1e-16)
+    for key in ("rho0", "theta0", "gamma", "a1", "a2", "b", "c1", "c2"):
+        assert abs(got[key] - getattr(lat, key)) <= 4e-16 * max(1.0, abs(getattr(lat, key))), key
+
+
+@pytest.mark.parametrize("lattice,storage,shape,bpu", [
+    ("D3Q7", "f32", (8, 8, 8), 56), ("D3Q7", "f16", (8, 8, 8), 28), ("D3Q7", "bf16", (8, 8, 8), 28),
+    ("D3Q7", "f64", (8, 8, 8), 112), ("D2Q9", "f32", (16, 16), 72), ("D2Q5", "f32", (16, 16), 40),
+    ("D1Q3", "f64", (1024,), 48), ("D3Q19", "f32", (4, 4, 4), 152)])
+def test_sizes(lattice, storage, shape, bpu):
+    d = lbm.make_desc(lattice, storage, shape)
+    Q = lbm.lbm_lee_lattice_info(lattice)["Q"]
+    assert lbm.lbm_lee_state_bytes(d) == Q * int(np.prod(shape)) * lbm.ELEM_BYTES[storage]
+    assert lbm.lbm_lee_bytes_per_update(d) == bpu
+    assert lbm.lbm_lee_scratch_bytes(d) >= 1024 * 6 * 8
+
+
+@pytest.mark.parametrize("kw", [
+    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), tau=0.49),
+    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), tau=float("nan")),
+    dict(lattice="D3Q7", storage="f32", shape=(0, 8, 8)),
+    dict(lattice="D3Q7", storage="f16", shape=(8, 8, 8), store_scale=3.0),
+    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 6), variant="dpp"),
+    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), variant="lds"),
+])
+def test_bad_descriptors_are_rejected(kw):
+    d = lbm.make_desc(**kw)
+    assert lbm.lbm_lee_state_bytes(d) == 0
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_lee_init(d, 256, 512, 1 << 20, 8, 8, 8, 1024, 1 << 20, None)
+    assert lbm.load().lbm_lee_last_error().decode() != ""
+
+
+def test_dimension_mismatch_rejected():
+    d = lbm.make_desc("D2Q9", "f32", (4, 4, 4))  # 3D shape for a 2D lattice
+    assert lbm.lbm_lee_state_bytes(d) == 0
+
+
+def test_init_argument_checks_before_any_gpu_work():
+    d = lbm.make_desc("D3Q7", "f32", (8, 8, 8))
+    need = lbm.lbm_lee_state_bytes(d)
+    sb = lbm.lbm_lee_scratch_bytes(d)
+    cases = [
+        (0, 4096, need, 8, 8, 8, 256, sb),          # null population buffer
+        (256, 256, need, 8, 8, 8, 256, sb),         # same buffer twice
+        (256, 1 << 30, need - 1, 8, 8, 8, 256, sb), # too small
+        (260, 1 << 30, need, 8, 8, 8, 256, sb),     # misaligned
+        (256, 1 << 30, need, 0, 8, 8, 256, sb),     # null field
+        (256, 1 << 30, need, 8, 8, 8, 256, 16),     # scratch too small
+        (256, 256 + need // 2, need, 8, 8, 8, 256, sb),  # overlapping buffers (aligned offsets)
+    ]
+    for a, b, nb, r, u, t, s, ns in cases:
+        if (a, b) == (256, 256 + need // 2) and (need // 2) % 256:
+            b = 256 + ((need // 2) // 256) * 256
+        with pytest.raises(lbm.LbmError) as ei:
+            lbm.lbm_lee_init(d, a, b, nb, r, u, t, s, ns, None)
+        assert ei.value.status == -1
+
+
+def test_null_handle_calls_fail_cleanly():
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_lee_step(None, 1, None)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_lee_l2_energy(None, None)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_lee_device_copy(16, 32, 17, None)
+    lbm.lbm_lee_destroy(None)
+    assert lbm.lbm_lee_store_scale(None) == 0.0

@@ -1,0 +1,328 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle, element by element.
+
+Bars (relative L2 over the compared field): FP64 storage 1e-12, FP32 storage 1e-5.  The
+16-bit storage modes round every stored population; their single-step error is bounded by
+the format's unit roundoff u (2^-11 for FP16, 2^-8 for BF16) and is checked against that.
+"""
+import numpy as np
+import pytest
+
+from oracle import closed_forms as cf
+from oracle import lbe
+
+from paper_1601_08103_amd import inputs
+
+from tests._gpu import gpu_ok, lattice, oracle_pull_state, rel_l2, say, stable_seed
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ok(), reason="needs a GPU")]
+
+BAR = {"f64": 1e-12, "f32": 1e-5}
+UNIT_ROUNDOFF = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+ALL_LATTICES = ["D1Q3", "D2Q5", "D2Q9", "D3Q7", "D3Q9", "D3Q13", "D3Q19", "D2Q5_DIA", "D3Q7_DIA"]
+
+SHAPES = {
+    # several 256-cell chunks per row, a partial last chunk, and the one-chunk (nx = 256) path
+    1: {"dpp": [(1028,), (256,)], "generic": [(1027,)]},
+    2: {"dpp": [(9, 520), (5, 256)], "generic": [(9, 517)]},
+    3: {"dpp": [(5, 6, 264), (3, 4, 256)], "generic": [(5, 6, 13)]},
+}
+
+
+def _solver(name, storage, shape, tau=0.5, variant="auto", store_scale=0.0, fields=None):
+    from paper_1601_08103_amd.lbm import Solver
+    lat = lattice(name)
+    if fields is None:
+        fields = (np.zeros(shape), np.zeros((lat.D,) + tuple(shape)), np.zeros(shape))
+    return Solver(name, storage, shape, *fields, tau=tau, variant=variant, store_scale=store_scale)
+
+
+def _cases():
+    out = []
+    for name in ALL_LATTICES:
+        D = lattice(name).D
+        for variant, shapes in SHAPES[D].items():
+            for shape in shapes:
+                for storage in ("f64", "f32"):
+                    out.append((name, storage, variant, shape))
+    return out
+
+
+@pytest.mark.parametrize("name,storage,variant,shape", _cases())
+def test_step_matches_oracle_on_random_state(name, storage, variant, shape):
+    """Arbitrary (non-equilibrium) populations, 5 steps at tau = 1/2 and 3 at tau = 0.8."""
+    lat = lattice(name)
+    for tau, n in ((0.5, 5), (0.8, 3)):
+        say(name, storage, variant, shape, "tau", tau)
+        rng = np.random.default_rng(stable_seed(name, storage, variant, shape, tau))
+        t0 = 1e-3 * lat.fstar.reshape((-1,) + (1,) * lat.D) * rng.standard_normal((lat.Q,) + tuple(shape))
+        sim = _solver(name, storage, shape, tau=tau, variant=variant)
+        sim.import_f64(t0)
+        t0 = sim.export_f64().cpu().numpy()  # exactly what the storage holds
+        sim.step(n)
+        got = sim.export_f64().cpu().numpy()
+        want = oracle_pull_state(lat, t0, n, tau)
+        err = rel_l2(got, want)
+        assert err < BAR[storage], (err, tau)
+        assert np.abs(got - want).max() < 10 * BAR[storage] * np.abs(want).max()
+        sim.close()
+
+
+@pytest.mark.parametrize("name", ALL_LATTICES)
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_16bit_storage_single_step_rounding(name, storage):
+    """One step from a state the format holds exactly: the result differs from the FP64
+    oracle only by the final rounding to storage (plus FP32 collision arithmetic)."""
+    lat = lattice(name)
+    shape = {1: (1028,), 2: (9, 520), 3: (5, 6, 264)}[lat.D]
+    say(name, storage, shape)
+    rng = np.random.default_rng(5)
+    t0 = 1e-3 * lat.fstar.reshape((-1,) + (1,) * lat.D) * rng.standard_normal((lat.Q,) + shape)
+    sim = _solver(name, storage, shape, store_scale=512.0)
+    assert sim.store_scale == 512.0
+    sim.import_f64(t0)
+    t0 = sim.export_f64().cpu().numpy()
+    sim.step(1)
+    got = sim.export_f64().cpu().numpy()
+    want = oracle_pull_state(lat, t0, 1)
+    # each stored h_i = S g_i / f*_i is rounded once: |error_i| <= u |h_i| (+ FP32 noise)
+    h_want = want * 512.0 / lat.fstar.reshape((-1,) + (1,) * lat.D)
+    h_got = got * 512.0 / lat.fstar.reshape((-1,) + (1,) * lat.D)
+    u = UNIT_ROUNDOFF[storage]
+    assert np.all(np.abs(h_got - h_want) <= u * np.abs(h_want) * 1.01 + 64 * 2.0 ** -24 * np.abs(h_want).max())
+    sim.close()
+
+
+@pytest.mark.parametrize("name", ["D1Q3", "D2Q9", "D3Q7", "D3Q19", "D3Q7_DIA"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_moments_energy_and_norm_kernels(name, storage):
+    lat = lattice(name)
+    shape = {1: (1028,), 2: (9, 520), 3: (5, 6, 264)}[lat.D]
+    say(name, storage, shape)
+    rho, u, theta = inputs.random_fields(3, shape, lat.D)
+    sim = _solver(name, storage, shape, fields=(rho, u, theta))
+    sim.step(4)
+    g = sim.export_f64().cpu().numpy()
+    m_or = lbe.moments(lat, g)
+    m_gpu = {k: v.cpu().numpy() for k, v in sim.moments(f64=True).items()}
+    for key in ("p", "rho", "theta"):
+        assert rel_l2(m_gpu[key], m_or[key]) < 1e-13, key
+    assert rel_l2(m_gpu["u"], m_or["u"]) < 1e-13
+    m32 = {k: v.cpu().numpy() for k, v in sim.moments(f64=False).items()}
+    assert rel_l2(m32["p"], m_or["p"]) < 1e-6
+    ew, ep = sim.l2_energy()
+    assert abs(ew - lbe.weighted_energy(lat, g)) < 1e-12 * ew
+    assert abs(ep - lbe.plain_energy(lat, g)) < 1e-12 * ep
+    ref_p = m_or["p"] + 1e-6 * np.random.default_rng(1).standard_normal(shape)
+    ref_u = m_or["u"] * 1.01
+    nrm = sim.error_norms(ref_p, ref_u)
+    want = [np.sum((m_or["p"] - ref_p) ** 2), np.sum(ref_p ** 2), np.abs(m_or["p"] - ref_p).max(),
+            np.sum((m_or["u"] - ref_u) ** 2), np.sum(ref_u ** 2), np.abs(m_or["u"] - ref_u).max()]
+    for a, b in zip(nrm, want):
+        assert abs(a - b) <= 1e-9 * abs(b) + 1e-300
+    sim.close()
+
+
+@pytest.mark.parametrize("mode", ["isentropic", "paper"])
+@pytest.mark.parametrize("variant", ["dpp", "generic"])
+def test_1d_workload_exact(mode, variant):
+    """D1Q3, N = 1024, FP64, Gaussian pulse (amplitude 1e-3, sigma 20, centre 512), 1000 steps:
+    GPU vs oracle and vs the exact d'Alembert solution."""
+    lat = lattice("D1Q3")
+    N = 1024
+    say("1D workload", mode, variant)
+    p0 = inputs.gaussian_pressure((N,), inputs.pulses_1d(N))
+    rho, u, theta = inputs.fields_from_pressure(p0, lat.rho0, lat.theta0, lat.gamma, mode)
+    sim = _solver("D1Q3", "f64", (N,), variant=variant, fields=(rho, u, theta))
+    sim.step(1000)
+    m = {k: v.cpu().numpy() for k, v in sim.moments().items()}
+    g_or = lbe.run(lat, rho, u, theta, 1000)
+    m_or = lbe.moments(lat, g_or)
+    ex = cf.dalembert_1d_integer_shift(lat, rho, u, theta, 1000)
+    assert rel_l2(m["p"], m_or["p"]) < 1e-12 and rel_l2(m["u"], m_or["u"]) < 1e-12
+    assert rel_l2(m["p"], ex["p"]) < 1e-12 and rel_l2(m["u"], ex["u"]) < 1e-12
+    sim.close()
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D2Q5"])
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_2d_workload_full_size(name, storage):
+    """512^2, 16 seeded pulses (amplitude U(-1e-3, 1e-3), sigma U(8, 24)), 2000 steps, every cell."""
+    lat = lattice(name)
+    shape = (512, 512)
+    say("2D workload", name, storage)
+    p0 = inputs.gaussian_pressure(shape, inputs.pulses_2d(seed=0))
+    rho, u, theta = inputs.fields_from_pressure(p0, lat.rho0, lat.theta0, lat.gamma)
+    sim = _solver(name, storage, shape, fields=(rho, u, theta))
+    sim.step(2000)
+    m = {k: v.cpu().numpy() for k, v in sim.moments().items()}
+    g_or = lbe.run(lat, rho, u, theta, 2000, nthreads=16)
+    m_or = lbe.moments(lat, g_or)
+    ep, eu = rel_l2(m["p"], m_or["p"]), rel_l2(m["u"], m_or["u"])
+    say("2D workload", name, storage, "rel L2 p", ep, "u", eu)
+    assert ep < BAR[storage] and eu < BAR[storage]
+    sim.close()
+
+
+def _sub_box_oracle(lat, p0_full, centre_cell, n):
+    """Oracle moments at one cell after n steps, from a periodic sub-box of half-width n + 2
+    cut out of the full initial field (the cell's domain of dependence after n steps has
+    half-width n, and the sub-box's own wrap needs n + 1 more steps to reach the centre)."""
+    hw = n + 2
+    idx = [np.arange(c - hw, c + hw + 1) % s for c, s in zip(centre_cell, p0_full.shape)]
+    sub = p0_full[np.ix_(*idx)]
+    rho, u, theta = inputs.fields_from_pressure(sub, lat.rho0, lat.theta0, lat.gamma)
+    g = lbe.run(lat, rho, u, theta, n, nthreads=16)
+    m = lbe.moments(lat, g)
+    c = (hw,) * 3
+    return m["p"][c], m["u"][(slice(None),) + c]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+def test_3d_workload_full_size_sampled(storage):
+    """256^3 D3Q7, 8 pulses (amplitude 1e-3, sigma 12), the benchmark's launch configuration:
+    24 steps, then p' and u' at 12 seeded cells against the oracle on sub-boxes."""
+    lat = lattice("D3Q7")
+    shape = (256, 256, 256)
+    n = 24
+    say("3D workload sampled", storage)
+    p0 = inputs.gaussian_pressure(shape, inputs.pulses_3d(seed=0))
+    rho, u, theta = inputs.fields_from_pressure(p0, lat.rho0, lat.theta0, lat.gamma)
+    sim = _solver("D3Q7", storage, shape, fields=(rho, u, theta))
+    sim.step(n)
+    m = sim.moments()
+    p_gpu = m["p"].cpu().numpy()
+    u_gpu = m["u"].cpu().numpy()
+    sim.close()
+    # cells near the pulse centres (where the field is large) plus random cells
+    rng = np.random.default_rng(42)
+    pulses = inputs.pulses_3d(seed=0)
+    cells = [tuple(int(round(pl.centre[2 - a] + rng.uniform(-10, 10))) % 256 for a in range(3)) for pl in pulses[:8]]
+    cells += [tuple(int(v) for v in rng.integers(0, 256, 3)) for _ in range(4)]
+    scale = np.abs(p_gpu).max()
+    errs = []
+    for cell in cells:
+        p_or, u_or = _sub_box_oracle(lat, p0, cell, n)
+        errs.append(abs(p_gpu[cell] - p_or) / scale)
+        errs.append(np.abs(u_gpu[(slice(None),) + cell] - u_or).max() / np.abs(u_gpu).max())
+    worst = max(errs)
+    say("3D sampled", storage, "worst rel err", worst)
+    bar = {"f64": 1e-12, "f32": 1e-5, "f16": 2e-3, "bf16": 2e-2}[storage]
+    assert worst < bar
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_3d_plane_wave_full_size_500_steps(storage):
+    """256^3 D3Q7 isentropic plane wave, 500 steps: p' against Re(m_p Gamma(k)^n ghat exp(ikx))."""
+    lat = lattice("D3Q7")
+    shape = (256, 256, 256)
+    k = [2 * np.pi * 1 / 256, 2 * np.pi * 2 / 256, 0.0]
+    say("3D plane wave", storage)
+    rho, u, theta = inputs.plane_wave_fields(shape, k, 1e-3, lat.rho0, lat.theta0, lat.gamma)
+    sim = _solver("D3Q7", storage, shape, fields=(rho, u, theta))
+    sim.step(500)
+    p_gpu = sim.moments()["p"].cpu().numpy()
+    sim.close()
+    # Fourier amplitude of the initial equilibrium mode: fields are A cos(k.x) -> amplitude A e^{ikx}
+    c = np.sqrt(lat.cs2)
+    khat = np.array(k) / np.linalg.norm(k)
+    A = 1e-3
+    rho_h = A / lat.cs2
+    theta_h = (lat.gamma - 1) * lat.theta0 * rho_h / lat.rho0
+    u_h = khat * A / (lat.rho0 * c)
+    ghat = lbe.equilibrium(lat, np.array(rho_h), u_h.reshape(3), np.array(theta_h))
+    G = lbe.gamma_matrix(lat, k)
+    gn = np.linalg.matrix_power(G, 500) @ ghat.astype(np.complex128)
+    mp = lbe.moment_matrix(lat)
+    p_hat = lat.rho0 * (mp[lat.D + 1] @ gn) + lat.theta0 * (mp[0] @ gn)
+    z, y, x = np.meshgrid(*[np.arange(s, dtype=np.float64) for s in shape], indexing="ij")
+    p_ref = np.real(p_hat * np.exp(1j * (k[0] * x + k[1] * y + k[2] * z)))
+    err = rel_l2(p_gpu, p_ref)
+    say("3D plane wave", storage, "rel L2", err)
+    assert err < BAR[storage]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+def test_energy_conservation_and_decay(storage):
+    lat = lattice("D3Q7")
+    shape = (32, 32, 64)
+    say("energy", storage)
+    p0 = inputs.gaussian_pressure(shape, [inputs.Pulse((20.0, 10.0, 12.0), 1e-3, 4.0)])
+    fields = inputs.fields_from_pressure(p0, lat.rho0, lat.theta0, lat.gamma)
+    sim = _solver("D3Q7", storage, shape, fields=fields)
+    e0 = sim.l2_energy()[0]
+    sim.step(200)
+    e1 = sim.l2_energy()[0]
+    drift_bar = {"f64": 1e-12, "f32": 1e-5, "f16": 2e-3, "bf16": 3e-2}[storage]
+    assert abs(e1 - e0) < drift_bar * e0
+    sim.close()
+    for tau in (0.6, 1.0):
+        sim = _solver("D3Q7", storage, shape, tau=tau, fields=fields)
+        prev = sim.l2_energy()[0]
+        for _ in range(3):
+            sim.step(10)
+            e = sim.l2_energy()[0]
+            assert e < prev
+            prev = e
+        sim.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+def test_checkpoint_restart_is_bitwise(storage):
+    lat = lattice("D2Q9")
+    shape = (64, 256)
+    say("checkpoint", storage)
+    fields = inputs.random_fields(8, shape, 2)
+    a = _solver("D2Q9", storage, shape, fields=fields)
+    a.step(20)
+    ga = a.export_f64().cpu().numpy()
+    b = _solver("D2Q9", storage, shape, fields=fields, store_scale=a.store_scale)
+    b.step(10)
+    snap = b.export_f64()
+    c = _solver("D2Q9", storage, shape, fields=fields, store_scale=a.store_scale)
+    c.import_f64(snap, steps_done=10)
+    c.step(10)
+    assert c.current()[1] == 20
+    assert np.array_equal(c.export_f64().cpu().numpy(), ga)
+    for s in (a, b, c):
+        s.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+def test_every_cell_is_written(storage):
+    """Poison the target buffer with NaN bytes; one step must overwrite every value."""
+    import torch
+    for name, shape in (("D3Q19", (5, 6, 264)), ("D2Q9", (9, 520)), ("D3Q7", (3, 4, 256))):
+        say("poison", name, storage, shape)
+        lat = lattice(name)
+        sim = _solver(name, storage, shape, fields=inputs.random_fields(1, shape, lat.D))
+        sim.pop_b.fill_(0xFF)
+        sim.step(1)
+        assert sim.current()[0] == sim.pop_b.data_ptr()
+        g = sim.export_f64()
+        assert bool(torch.isfinite(g).all())
+        sim.close()
+
+
+def test_variants_agree():
+    for name, shape in (("D3Q19", (5, 6, 264)), ("D2Q9", (9, 520))):
+        lat = lattice(name)
+        fields = inputs.random_fields(2, shape, lat.D)
+        outs = []
+        for variant in ("generic", "dpp"):
+            say("variants", name, variant)
+            sim = _solver(name, "f32", shape, variant=variant, fields=fields)
+            sim.step(7)
+            outs.append(sim.export_f64().cpu().numpy())
+            sim.close()
+        assert rel_l2(outs[1], outs[0]) < 1e-6
+
+
+def test_device_copy():
+    import torch
+    from paper_1601_08103_amd import lbm
+    say("device copy")
+    src = torch.randn(1 << 20, device="cuda")
+    dst = torch.empty_like(src)
+    lbm.lbm_lee_device_copy(dst.data_ptr(), src.data_ptr(), src.numel() * 4, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
