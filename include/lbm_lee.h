@@ -61,11 +61,18 @@ typedef int32_t lbm_status;
 
 /* Population storage.  F64 and F32 store g itself.  F16 and BF16 store the normalised
  * deviation h_i = S g_i / f*_i (S a power of two, see lbm_lee_desc.store_scale) rounded to
- * nearest-even, and compute the collision in FP32. */
+ * nearest-even, and compute the collision in FP32.  I16 stores the same h as a signed 16-bit
+ * fixed-point integer (round to nearest-even, saturating at +-32767), FP32 collision. */
 #define LBM_F64 0
 #define LBM_F32 1
 #define LBM_F16 2
 #define LBM_BF16 3
+#define LBM_I16 4
+
+/* Performance knobs of the DPP step kernel (lbm_lee_desc.tune); results do not depend on them. */
+#define LBM_TUNE_NT_STORE 1  /* non-temporal (streaming) stores                        */
+#define LBM_TUNE_NT_LOAD 2   /* non-temporal (streaming) loads                         */
+#define LBM_TUNE_PERSISTENT 4 /* grid sized to the resident wave slots, grid-stride loop */
 
 /* Step kernel variant (all give the same result up to FP summation order). */
 #define LBM_VARIANT_AUTO 0    /* DPP when nx % 4 == 0, else GENERIC                          */
@@ -79,10 +86,10 @@ typedef struct lbm_lee_desc {
     int64_t n[3];        /* nx, ny, nz >= 1; n[a] must be 1 for a >= D                      */
     double tau;          /* relaxation time, >= 1/2 (1/2 is the second-order scheme)        */
     int32_t variant;     /* LBM_VARIANT_*                                                   */
-    int32_t reserved0;   /* must be 0                                                       */
-    double store_scale;  /* S for F16/BF16: 0 = choose from the initial state so that       */
-                         /* max |S g / f*| lies in (1/2, 1]; otherwise a power of two > 0. */
-                         /* Ignored for F64/F32.                                            */
+    int32_t tune;        /* LBM_TUNE_* bits, 0 for the defaults                             */
+    double store_scale;  /* S for F16/BF16/I16: 0 = choose from the initial state so that   */
+                         /* max |S g / f*| lies in [1/2, 1) (F16/BF16) or [2^13, 2^14)      */
+                         /* (I16); otherwise a power of two > 0.  Ignored for F64/F32.     */
 } lbm_lee_desc;
 
 typedef struct lbm_lattice_info {

@@ -1,0 +1,96 @@
+"""FP64 reference of the boundary-closure network (not in the paper).
+
+TEST INFRASTRUCTURE: only tests, the package smoke check and the benchmark's CPU-baseline
+leg may import this module.
+
+The network maps a strip of post-collision populations (3 cells deep along the inward
+normal, Q values each, in the canonical face frame) to the k populations that enter the box
+through the face:  x -> s = rms(x),  z = x / s,
+    h1 = relu(z W1 + b1),  h2 = relu(h1 W2 + b2),  y = h2 W3 + b3,  output = s * y.
+Training minimises the mean squared error between y and target / s (Adam).
+
+`quantize=True` rounds every GEMM input (weights, the normalised strip and the hidden
+activations) to bfloat16 with round-to-nearest-even, as the GPU kernels do before their
+matrix-core products; accumulation stays FP64 here.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+EPS_RMS = 1e-30
+
+
+def bf16_round(a) -> np.ndarray:
+    """Round FP64 values to the nearest bfloat16 (ties to even), returned as FP64."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def init_params(rng, n_in: int, n_out: int, hidden: int = 64) -> dict:
+    """He-normal weights, zero biases."""
+    return dict(
+        W1=rng.standard_normal((n_in, hidden)) * np.sqrt(2.0 / n_in), b1=np.zeros(hidden),
+        W2=rng.standard_normal((hidden, hidden)) * np.sqrt(2.0 / hidden), b2=np.zeros(hidden),
+        W3=rng.standard_normal((hidden, n_out)) * np.sqrt(1.0 / hidden), b3=np.zeros(n_out),
+    )
+
+
+def normalise(x):
+    s = np.sqrt(np.mean(np.asarray(x, dtype=np.float64) ** 2, axis=1, keepdims=True)) + EPS_RMS
+    return x / s, s
+
+
+def forward(p: dict, z, quantize: bool = False):
+    q = bf16_round if quantize else (lambda a: np.asarray(a, dtype=np.float64))
+    z = q(z)
+    a1 = z @ q(p["W1"]) + p["b1"]
+    h1 = np.maximum(a1, 0.0)
+    h1q = q(h1)
+    a2 = h1q @ q(p["W2"]) + p["b2"]
+    h2 = np.maximum(a2, 0.0)
+    h2q = q(h2)
+    y = h2q @ q(p["W3"]) + p["b3"]
+    return y, dict(z=z, a1=a1, h1=h1q, a2=a2, h2=h2q)
+
+
+def mse(y, t) -> float:
+    return float(np.mean((y - t) ** 2))
+
+
+def backward(p: dict, cache: dict, y, t, quantize: bool = False) -> dict:
+    """Gradients of mse(y, t) = mean((y - t)^2) by the chain rule."""
+    q = bf16_round if quantize else (lambda a: np.asarray(a, dtype=np.float64))
+    B, k = y.shape
+    dy = 2.0 * (y - t) / (B * k)
+    g = {}
+    g["W3"] = cache["h2"].T @ dy
+    g["b3"] = dy.sum(axis=0)
+    dh2 = dy @ q(p["W3"]).T
+    da2 = dh2 * (cache["a2"] > 0)
+    g["W2"] = cache["h1"].T @ da2
+    g["b2"] = da2.sum(axis=0)
+    dh1 = da2 @ q(p["W2"]).T
+    da1 = dh1 * (cache["a1"] > 0)
+    g["W1"] = cache["z"].T @ da1
+    g["b1"] = da1.sum(axis=0)
+    return g
+
+
+def adam(p: dict, g: dict, m: dict, v: dict, t: int, lr: float, b1: float = 0.9, b2: float = 0.999,
+         eps: float = 1e-8) -> None:
+    """One Adam update (Kingma & Ba) of every parameter, in place; t counts from 1."""
+    for key in p:
+        m[key] = b1 * m[key] + (1 - b1) * g[key]
+        v[key] = b2 * v[key] + (1 - b2) * g[key] ** 2
+        mh = m[key] / (1 - b1 ** t)
+        vh = v[key] / (1 - b2 ** t)
+        p[key] = p[key] - lr * mh / (np.sqrt(vh) + eps)
+
+
+def predict(p: dict, strips, quantize: bool = False):
+    """Incoming populations for raw strips (B, 3Q): network on the normalised strip, rescaled."""
+    z, s = normalise(strips)
+    y, _ = forward(p, z, quantize)
+    return y * s

@@ -25,6 +25,7 @@ struct lbm_lee {
     void *scratch;
     size_t scratch_bytes;
     double S;  // storage scale (1 for F64/F32)
+    int cus;   // compute units of the device (persistent launches)
 };
 
 namespace {
@@ -60,10 +61,13 @@ size_t elem_size(int storage) {
         case LBM_F64: return 8;
         case LBM_F32: return 4;
         case LBM_F16:
-        case LBM_BF16: return 2;
+        case LBM_BF16:
+        case LBM_I16: return 2;
         default: return 0;
     }
 }
+
+bool is_scaled(int storage) { return storage == LBM_F16 || storage == LBM_BF16 || storage == LBM_I16; }
 
 bool aligned256(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 
@@ -80,7 +84,7 @@ lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
     if ((double)d->n[1] * (double)d->n[2] * 16.0 > 4.0e9) return fail(LBM_E_INVALID, "too many rows (ny * nz)");
     if (!(d->tau >= 0.5) || !std::isfinite(d->tau)) return fail(LBM_E_INVALID, "tau must be finite and >= 1/2 (got %g)", d->tau);
     if (d->variant < LBM_VARIANT_AUTO || d->variant > LBM_VARIANT_LDS) return fail(LBM_E_INVALID, "unknown variant %d", d->variant);
-    if (d->reserved0 != 0) return fail(LBM_E_INVALID, "reserved0 must be 0");
+    if (d->tune < 0 || d->tune > 7) return fail(LBM_E_INVALID, "unknown tune bits 0x%x", d->tune);
     if (!(d->store_scale >= 0.0) || !std::isfinite(d->store_scale)) return fail(LBM_E_INVALID, "store_scale must be >= 0");
     if (d->store_scale > 0.0) {
         int ex;
@@ -99,6 +103,7 @@ lbm_status visit_storage(int storage, F &&f) {
         case LBM_F32: return f(VS{}, StF32{});
         case LBM_F16: return f(VS{}, StF16{});
         case LBM_BF16: return f(VS{}, StBF16{});
+        case LBM_I16: return f(VS{}, StI16{});
         default: return fail(LBM_E_INVALID, "unknown storage id %d", storage);
     }
 }
@@ -123,7 +128,7 @@ template <int Q>
 FieldCoef<Q> field_coef(const lbm_lee *h) {
     FieldCoef<Q> k;
     const LatticeTable &t = h->tab;
-    const bool scaled = h->desc.storage == LBM_F16 || h->desc.storage == LBM_BF16;
+    const bool scaled = is_scaled(h->desc.storage);
     for (int i = 0; i < Q; ++i) {
         k.f[i] = t.f[i];
         k.dec[i] = scaled ? t.f[i] / h->S : 1.0;
@@ -142,24 +147,32 @@ FieldCoef<Q> field_coef(const lbm_lee *h) {
     return k;
 }
 
+template <typename CT>
+Kc<CT> split(double v) {
+    Kc<CT> k;
+    k.hi = (CT)v;
+    k.lo = (CT)(v - (double)k.hi);
+    return k;
+}
+
 template <typename CT, int Q>
 StepCoef<CT, Q> step_coef(const lbm_lee *h) {
     const FieldCoef<Q> f = field_coef<Q>(h);
     StepCoef<CT, Q> k;
     const double omega = 1.0 / h->desc.tau;
     for (int i = 0; i < Q; ++i) {
-        k.dec[i] = (CT)f.dec[i];
-        k.edec[i] = (CT)(f.e[i] * f.dec[i]);
-        k.w[i] = (CT)(omega * f.enc[i] * f.f[i]);
+        k.dec[i] = split<CT>(f.dec[i]);
+        k.edec[i] = split<CT>(f.e[i] * f.dec[i]);
+        k.w[i] = split<CT>(omega * f.enc[i] * f.f[i]);
     }
-    k.keep = (CT)(1.0 - omega);
-    k.gm1_rho0 = (CT)(f.gm1 / f.rho0);
-    k.theta0_rho0 = (CT)(f.theta0 / f.rho0);
-    k.a1 = (CT)f.a1;
-    k.a2 = (CT)f.a2;
-    k.c1 = (CT)f.c1;
-    k.c2 = (CT)f.c2;
-    k.b_rho0 = (CT)(f.b / f.rho0);
+    k.keep = split<CT>(1.0 - omega);
+    k.gm1_rho0 = split<CT>(f.gm1 / f.rho0);
+    k.theta0_rho0 = split<CT>(f.theta0 / f.rho0);
+    k.a1 = split<CT>(f.a1);
+    k.a2 = split<CT>(f.a2);
+    k.c1 = split<CT>(f.c1);
+    k.c2 = split<CT>(f.c2);
+    k.b_rho0 = split<CT>(f.b / f.rho0);
     return k;
 }
 
@@ -188,8 +201,7 @@ lbm_status launch_init(lbm_lee *h, const double *rho, const double *u, const dou
 }
 
 lbm_status choose_scale(lbm_lee *h, const double *rho, const double *u, const double *theta, hipStream_t st) {
-    const bool scaled = h->desc.storage == LBM_F16 || h->desc.storage == LBM_BF16;
-    if (!scaled) {
+    if (!is_scaled(h->desc.storage)) {
         h->S = 1.0;
         return LBM_OK;
     }
@@ -216,7 +228,8 @@ lbm_status choose_scale(lbm_lee *h, const double *rho, const double *u, const do
     } else {
         int ex;
         std::frexp(mx, &ex);  // mx = m 2^ex, m in [1/2, 1)
-        h->S = std::ldexp(1.0, -ex);  // S mx in [1/2, 1)
+        // S mx in [1/2, 1) for the floating formats, in [2^13, 2^14) for fixed point
+        h->S = std::ldexp(1.0, (h->desc.storage == LBM_I16 ? 14 : 0) - ex);
     }
     return LBM_OK;
 }
@@ -304,6 +317,12 @@ lbm_status lbm_lee_init(const lbm_lee_desc *desc, void *pop_a, void *pop_b, size
     h->scratch = scratch;
     h->scratch_bytes = scratch_bytes;
     h->S = 1.0;
+    h->cus = 0;
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipGetLastError();
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
     if ((s = choose_scale(h, rho, u, theta, st)) != LBM_OK || (s = launch_init(h, rho, u, theta, st)) != LBM_OK) {
         delete h;
@@ -335,15 +354,27 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
         const int cpr = (h->nx + 255) / 256;
         const unsigned waves = (unsigned)((size_t)h->ny * h->nz * cpr);
         const bool fullrow = h->nx == 256;
+        const unsigned tune = (unsigned)h->desc.tune;
+        unsigned grid = (waves + 3) / 4;
+        if ((tune & kTunePersistent) && h->cus > 0) {
+            int per_cu = 0;
+            const void *fn = fullrow ? reinterpret_cast<const void *>(&step_dpp<VS, ST, true>)
+                                     : reinterpret_cast<const void *>(&step_dpp<VS, ST, false>);
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) == hipSuccess && per_cu > 0) {
+                const unsigned g = (unsigned)(per_cu * h->cus);
+                if (g < grid) grid = g;
+            }
+            (void)hipGetLastError();
+        }
         for (int64_t t = 0; t < nsteps; ++t) {
             const E *src = static_cast<const E *>(h->buf[h->cur]);
             E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);
             if (variant == LBM_VARIANT_GENERIC) {
                 step_generic<VS, ST><<<blocks_for(h->N), 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, k);
             } else if (fullrow) {
-                step_dpp<VS, ST, true><<<(waves + 3) / 4, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr, waves, k);
+                step_dpp<VS, ST, true><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr, waves, tune, k);
             } else {
-                step_dpp<VS, ST, false><<<(waves + 3) / 4, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr, waves, k);
+                step_dpp<VS, ST, false><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr, waves, tune, k);
             }
             lbm_status ls = launch_check();
             if (ls != LBM_OK) return ls;

@@ -1,8 +1,9 @@
 // Storage codecs for the population arrays.
 //
 // F64 / F32 store g itself.  F16 / BF16 store h = S g / f* (S a power of two), rounded to
-// nearest-even; the collision is computed in FP32 on the decoded h, with the constants
-// folded so that no per-population rescaling is needed inside the step kernel.
+// nearest-even; I16 stores the same h as a signed 16-bit integer (fixed point, rounded to
+// nearest-even, saturating at +-32767).  The collision is computed in FP32 on the decoded h,
+// with the constants folded so that no per-population rescaling is needed in the step kernel.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -13,6 +14,7 @@ namespace lbm {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
 
 struct StF64 {
     using elem = double;
@@ -57,55 +59,95 @@ struct StBF16 {
     __device__ static elem enc_d(double v) { return enc((float)v); }
 };
 
+struct StI16 {
+    using elem = short;
+    using comp = float;
+    static constexpr bool scaled = true;
+    __device__ static comp dec(elem v) { return (float)v; }
+    __device__ static elem enc(comp v) {
+        const float r = __builtin_rintf(v);  // ties to even
+        return (elem)(int)fminf(fmaxf(r, -32767.0f), 32767.0f);
+    }
+    __device__ static elem enc_d(double v) {
+        const double r = __builtin_rint(v);
+        return (elem)(int)fmin(fmax(r, -32767.0), 32767.0);
+    }
+};
+
 // Four consecutive elements starting at a 4-element-aligned index, decoded to the compute type.
+// Vector loads/stores; NT selects the non-temporal (streaming) cache policy.
+template <typename V>
+__device__ __forceinline__ V vload(const V *p, bool nt) {
+    return nt ? __builtin_nontemporal_load(p) : *p;
+}
+template <typename V>
+__device__ __forceinline__ void vstore(V *p, V v, bool nt) {
+    if (nt)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 template <class ST>
-__device__ inline void load4(const typename ST::elem *p, typename ST::comp (&v)[4]);
+__device__ inline void load4(const typename ST::elem *p, typename ST::comp (&v)[4], bool nt = false);
 
 template <>
-__device__ inline void load4<StF64>(const double *p, double (&v)[4]) {
-    f64x2 a = *reinterpret_cast<const f64x2 *>(p);
-    f64x2 b = *reinterpret_cast<const f64x2 *>(p + 2);
+__device__ inline void load4<StF64>(const double *p, double (&v)[4], bool nt) {
+    f64x2 a = vload(reinterpret_cast<const f64x2 *>(p), nt);
+    f64x2 b = vload(reinterpret_cast<const f64x2 *>(p + 2), nt);
     v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
 }
 template <>
-__device__ inline void load4<StF32>(const float *p, float (&v)[4]) {
-    f32x4 a = *reinterpret_cast<const f32x4 *>(p);
+__device__ inline void load4<StF32>(const float *p, float (&v)[4], bool nt) {
+    f32x4 a = vload(reinterpret_cast<const f32x4 *>(p), nt);
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
 }
 template <>
-__device__ inline void load4<StF16>(const unsigned short *p, float (&v)[4]) {
-    u16x4 a = *reinterpret_cast<const u16x4 *>(p);
+__device__ inline void load4<StF16>(const unsigned short *p, float (&v)[4], bool nt) {
+    u16x4 a = vload(reinterpret_cast<const u16x4 *>(p), nt);
     v[0] = StF16::dec(a.x); v[1] = StF16::dec(a.y); v[2] = StF16::dec(a.z); v[3] = StF16::dec(a.w);
 }
 template <>
-__device__ inline void load4<StBF16>(const unsigned short *p, float (&v)[4]) {
-    u16x4 a = *reinterpret_cast<const u16x4 *>(p);
+__device__ inline void load4<StBF16>(const unsigned short *p, float (&v)[4], bool nt) {
+    u16x4 a = vload(reinterpret_cast<const u16x4 *>(p), nt);
     v[0] = StBF16::dec(a.x); v[1] = StBF16::dec(a.y); v[2] = StBF16::dec(a.z); v[3] = StBF16::dec(a.w);
 }
 
+template <>
+__device__ inline void load4<StI16>(const short *p, float (&v)[4], bool nt) {
+    s16x4 a = vload(reinterpret_cast<const s16x4 *>(p), nt);
+    v[0] = StI16::dec(a.x); v[1] = StI16::dec(a.y); v[2] = StI16::dec(a.z); v[3] = StI16::dec(a.w);
+}
+
 template <class ST>
-__device__ inline void store4(typename ST::elem *p, const typename ST::comp (&v)[4]);
+__device__ inline void store4(typename ST::elem *p, const typename ST::comp (&v)[4], bool nt = false);
 
 template <>
-__device__ inline void store4<StF64>(double *p, const double (&v)[4]) {
+__device__ inline void store4<StF64>(double *p, const double (&v)[4], bool nt) {
     f64x2 a = {v[0], v[1]}, b = {v[2], v[3]};
-    *reinterpret_cast<f64x2 *>(p) = a;
-    *reinterpret_cast<f64x2 *>(p + 2) = b;
+    vstore(reinterpret_cast<f64x2 *>(p), a, nt);
+    vstore(reinterpret_cast<f64x2 *>(p + 2), b, nt);
 }
 template <>
-__device__ inline void store4<StF32>(float *p, const float (&v)[4]) {
+__device__ inline void store4<StF32>(float *p, const float (&v)[4], bool nt) {
     f32x4 a = {v[0], v[1], v[2], v[3]};
-    *reinterpret_cast<f32x4 *>(p) = a;
+    vstore(reinterpret_cast<f32x4 *>(p), a, nt);
 }
 template <>
-__device__ inline void store4<StF16>(unsigned short *p, const float (&v)[4]) {
+__device__ inline void store4<StF16>(unsigned short *p, const float (&v)[4], bool nt) {
     u16x4 a = {StF16::enc(v[0]), StF16::enc(v[1]), StF16::enc(v[2]), StF16::enc(v[3])};
-    *reinterpret_cast<u16x4 *>(p) = a;
+    vstore(reinterpret_cast<u16x4 *>(p), a, nt);
 }
 template <>
-__device__ inline void store4<StBF16>(unsigned short *p, const float (&v)[4]) {
+__device__ inline void store4<StBF16>(unsigned short *p, const float (&v)[4], bool nt) {
     u16x4 a = {StBF16::enc(v[0]), StBF16::enc(v[1]), StBF16::enc(v[2]), StBF16::enc(v[3])};
-    *reinterpret_cast<u16x4 *>(p) = a;
+    vstore(reinterpret_cast<u16x4 *>(p), a, nt);
+}
+
+template <>
+__device__ inline void store4<StI16>(short *p, const float (&v)[4], bool nt) {
+    s16x4 a = {StI16::enc(v[0]), StI16::enc(v[1]), StI16::enc(v[2]), StI16::enc(v[3])};
+    vstore(reinterpret_cast<s16x4 *>(p), a, nt);
 }
 
 }  // namespace lbm

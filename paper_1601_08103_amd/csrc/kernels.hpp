@@ -19,6 +19,21 @@
 namespace lbm {
 
 // ------------------------------------------------------------------ constants
+// A constant of the collision carried as hi + lo (lo = the rounding residual of hi).  The
+// products below use fma(hi, x, lo * x), so a constant enters with ~2^-48 relative error
+// in FP32.  With the constant rounded to FP32 alone, the rounding would be the same in
+// every cell and every step: the collision would no longer be an exact reflection in the
+// 1/f* weighted norm and the error would grow linearly with the step count.
+template <typename CT>
+struct Kc {
+    CT hi, lo;
+};
+
+template <typename CT>
+__device__ __forceinline__ CT mulk(CT x, Kc<CT> k) {
+    return fma(k.hi, x, k.lo * x);
+}
+
 // Collision constants in storage units, for compute type CT.  With stored value s_i and
 // decoded population g_i = dec_i s_i:
 //   rho'  = sum dec_i s_i,      j = sum c_i dec_i s_i,      e = sum edec_i s_i,
@@ -28,10 +43,10 @@ namespace lbm {
 // where keep = 1 - 1/tau and w_i = (1/tau) enc_i f*_i (the equilibrium in storage units).
 template <typename CT, int Q>
 struct StepCoef {
-    CT dec[Q];
-    CT edec[Q];
-    CT w[Q];
-    CT keep, gm1_rho0, theta0_rho0, a1, a2, c1, c2, b_rho0;
+    Kc<CT> dec[Q];
+    Kc<CT> edec[Q];
+    Kc<CT> w[Q];
+    Kc<CT> keep, gm1_rho0, theta0_rho0, a1, a2, c1, c2, b_rho0;
 };
 
 // FP64 constants of the non-hot kernels (init, moments, reductions, import/export).
@@ -50,7 +65,7 @@ __device__ __forceinline__ void collide(const StepCoef<CT, VS::Q> &k, CT (&s)[VS
     CT rho = 0, jx = 0, jy = 0, jz = 0, e = 0;
 #pragma unroll
     for (int i = 0; i < VS::Q; ++i) {
-        const CT g = k.dec[i] * s[i];
+        const CT g = mulk(s[i], k.dec[i]);
         rho += g;
         if (VS::cx(i) > 0) jx += g;
         if (VS::cx(i) < 0) jx -= g;
@@ -58,12 +73,12 @@ __device__ __forceinline__ void collide(const StepCoef<CT, VS::Q> &k, CT (&s)[VS
         if (VS::cy(i) < 0) jy -= g;
         if (VS::cz(i) > 0) jz += g;
         if (VS::cz(i) < 0) jz -= g;
-        e += k.edec[i] * s[i];
+        e += mulk(s[i], k.edec[i]);
     }
-    const CT theta = k.gm1_rho0 * e - k.theta0_rho0 * rho;
-    const CT A = k.a1 * rho + k.a2 * theta;
-    const CT C = k.c1 * rho + k.c2 * theta;
-    const CT Ux = k.b_rho0 * jx, Uy = k.b_rho0 * jy, Uz = k.b_rho0 * jz;
+    const CT theta = mulk(e, k.gm1_rho0) - mulk(rho, k.theta0_rho0);
+    const CT A = mulk(rho, k.a1) + mulk(theta, k.a2);
+    const CT C = mulk(rho, k.c1) + mulk(theta, k.c2);
+    const CT Ux = mulk(jx, k.b_rho0), Uy = mulk(jy, k.b_rho0), Uz = mulk(jz, k.b_rho0);
 #pragma unroll
     for (int i = 0; i < VS::Q; ++i) {
         CT t = A;
@@ -73,8 +88,8 @@ __device__ __forceinline__ void collide(const StepCoef<CT, VS::Q> &k, CT (&s)[VS
         if (VS::cy(i) < 0) t -= Uy;
         if (VS::cz(i) > 0) t += Uz;
         if (VS::cz(i) < 0) t -= Uz;
-        if (VS::c2(i) != 0) t += (CT)(0.5 * VS::c2(i)) * C;
-        s[i] = k.keep * s[i] + k.w[i] * t;
+        if (VS::c2(i) != 0) t += (CT)(0.5 * VS::c2(i)) * C;  // 1/2, 1 or 3/2: exact
+        s[i] = mulk(s[i], k.keep) + mulk(t, k.w[i]);
     }
 }
 
@@ -134,18 +149,17 @@ __device__ __forceinline__ double dpp_move(double v) {
 // lane below through a DPP move; c_x = -1 needs the element right of the quad from the lane
 // above.  FULLROW (nx == 256) rotates within the wave, which is exactly the periodic wrap;
 // otherwise the first lane and the last active lane load their neighbour element directly.
+// Waves walk the chunks grid-stride (one pass when the grid covers them all).
+// tune: bit 0 = non-temporal stores, bit 1 = non-temporal loads.
+enum : unsigned { kTuneNtStore = 1u, kTuneNtLoad = 2u, kTunePersistent = 4u };
+
 template <class VS, class ST, bool FULLROW>
-__global__ __launch_bounds__(256) void step_dpp(const typename ST::elem *__restrict__ src,
-                                                typename ST::elem *__restrict__ dst, int nx, int ny, int nz,
-                                                size_t N, int chunks_per_row, unsigned total_waves,
-                                                StepCoef<typename ST::comp, VS::Q> k) {
+__device__ __forceinline__ void step_chunk(const typename ST::elem *__restrict__ src,
+                                           typename ST::elem *__restrict__ dst, int nx, int ny, int nz, size_t N,
+                                           unsigned row, int chunk, int lane, bool ntl, bool nts,
+                                           const StepCoef<typename ST::comp, VS::Q> &k) {
     using CT = typename ST::comp;
     using E = typename ST::elem;
-    const int lane = threadIdx.x & 63;
-    const unsigned wave = blockIdx.x * 4u + (unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (wave >= total_waves) return;  // uniform per wave
-    const unsigned row = wave / (unsigned)chunks_per_row;
-    const int chunk = (int)(wave - row * (unsigned)chunks_per_row);
     const int y = (int)(row % (unsigned)ny);
     const int z = (int)(row / (unsigned)ny);
     const int x0 = chunk * 256 + lane * 4;
@@ -159,7 +173,7 @@ __global__ __launch_bounds__(256) void step_dpp(const typename ST::elem *__restr
         const int zs = wrap_add(z, -VS::cz(i), nz);
         const E *rowp = src + (size_t)i * N + ((size_t)zs * ny + ys) * (size_t)nx;
         CT v[4] = {0, 0, 0, 0};
-        if (active) load4<ST>(rowp + x0, v);
+        if (active) load4<ST>(rowp + x0, v, ntl);
         if (VS::cx(i) == 0) {
             s[i][0] = v[0]; s[i][1] = v[1]; s[i][2] = v[2]; s[i][3] = v[3];
         } else if (VS::cx(i) > 0) {
@@ -184,7 +198,22 @@ __global__ __launch_bounds__(256) void step_dpp(const typename ST::elem *__restr
     }
     const size_t out = ((size_t)z * ny + y) * (size_t)nx + x0;
 #pragma unroll
-    for (int i = 0; i < VS::Q; ++i) store4<ST>(dst + (size_t)i * N + out, s[i]);
+    for (int i = 0; i < VS::Q; ++i) store4<ST>(dst + (size_t)i * N + out, s[i], nts);
+}
+
+template <class VS, class ST, bool FULLROW>
+__global__ __launch_bounds__(256) void step_dpp(const typename ST::elem *__restrict__ src,
+                                                typename ST::elem *__restrict__ dst, int nx, int ny, int nz,
+                                                size_t N, int chunks_per_row, unsigned total_waves, unsigned tune,
+                                                StepCoef<typename ST::comp, VS::Q> k) {
+    const int lane = threadIdx.x & 63;
+    const unsigned wid = (unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool ntl = (tune & kTuneNtLoad) != 0, nts = (tune & kTuneNtStore) != 0;
+    for (unsigned wave = blockIdx.x * 4u + wid; wave < total_waves; wave += gridDim.x * 4u) {
+        const unsigned row = wave / (unsigned)chunks_per_row;
+        const int chunk = (int)(wave - row * (unsigned)chunks_per_row);
+        step_chunk<VS, ST, FULLROW>(src, dst, nx, ny, nz, N, row, chunk, lane, ntl, nts, k);
+    }
 }
 
 // ------------------------------------------------------------------ initial state

@@ -16,8 +16,9 @@ LIB_PATH = os.path.join(PKG, "liblbm_lee.so")
 
 LATTICES = {"D1Q3": 0, "D2Q5": 1, "D2Q9": 2, "D3Q7": 3, "D3Q9": 4, "D3Q13": 5, "D3Q19": 6,
             "D2Q5_DIA": 7, "D3Q7_DIA": 8}
-STORAGES = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
-ELEM_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+STORAGES = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "i16": 4}
+ELEM_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "i16": 2}
+TUNE = {"nt_store": 1, "nt_load": 2, "persistent": 4}
 VARIANTS = {"auto": 0, "generic": 1, "dpp": 2, "lds": 3}
 
 LBM_OK = 0
@@ -31,7 +32,7 @@ class LbmError(RuntimeError):
 
 class lbm_lee_desc(ctypes.Structure):
     _fields_ = [("lattice", ctypes.c_int32), ("storage", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
-                ("tau", ctypes.c_double), ("variant", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("variant", ctypes.c_int32), ("tune", ctypes.c_int32),
                 ("store_scale", ctypes.c_double)]
 
 
@@ -92,7 +93,7 @@ def _check(name, status):
 
 
 def make_desc(lattice: str, storage: str, shape, tau: float = 0.5, variant: str = "auto",
-              store_scale: float = 0.0) -> lbm_lee_desc:
+              store_scale: float = 0.0, tune: int = 0) -> lbm_lee_desc:
     """Descriptor for a spatial shape given in C order ((nz, ny, nx), (ny, nx) or (nx,))."""
     dims = list(reversed([int(s) for s in shape])) + [1] * (3 - len(shape))
     d = lbm_lee_desc()
@@ -102,7 +103,7 @@ def make_desc(lattice: str, storage: str, shape, tau: float = 0.5, variant: str 
         d.n[a] = dims[a]
     d.tau = float(tau)
     d.variant = VARIANTS[variant]
-    d.reserved0 = 0
+    d.tune = int(tune)
     d.store_scale = float(store_scale)
     return d
 
@@ -197,7 +198,7 @@ class Solver:
     """Owns torch device buffers for one solver handle; every method is one C-ABI call."""
 
     def __init__(self, lattice: str, storage: str, shape, rho, u, theta, tau: float = 0.5, variant: str = "auto",
-                 store_scale: float = 0.0, stream=None):
+                 store_scale: float = 0.0, tune: int = 0, stream=None):
         import torch
 
         if not torch.cuda.is_available():
@@ -210,7 +211,7 @@ class Solver:
         if len(self.shape) != self.D:
             raise ValueError(f"{lattice} needs a {self.D}D shape, got {self.shape}")
         self.N = int(np.prod(self.shape))
-        self.desc = make_desc(lattice, storage, self.shape, tau, variant, store_scale)
+        self.desc = make_desc(lattice, storage, self.shape, tau, variant, store_scale, tune)
         self.state_bytes = lbm_lee_state_bytes(self.desc)
         if self.state_bytes == 0:
             load()

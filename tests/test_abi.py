@@ -46,7 +46,7 @@ def test_library_tables_match_oracle_tables(name):
 
 @pytest.mark.parametrize("lattice,storage,shape,bpu", [
     ("D3Q7", "f32", (8, 8, 8), 56), ("D3Q7", "f16", (8, 8, 8), 28), ("D3Q7", "bf16", (8, 8, 8), 28),
-    ("D3Q7", "f64", (8, 8, 8), 112), ("D2Q9", "f32", (16, 16), 72), ("D2Q5", "f32", (16, 16), 40),
+    ("D3Q7", "f64", (8, 8, 8), 112), ("D3Q7", "i16", (8, 8, 8), 28), ("D2Q9", "f32", (16, 16), 72), ("D2Q5", "f32", (16, 16), 40),
     ("D1Q3", "f64", (1024,), 48), ("D3Q19", "f32", (4, 4, 4), 152)])
 def test_sizes(lattice, storage, shape, bpu):
     d = lbm.make_desc(lattice, storage, shape)
@@ -63,6 +63,8 @@ def test_sizes(lattice, storage, shape, bpu):
     dict(lattice="D3Q7", storage="f16", shape=(8, 8, 8), store_scale=3.0),
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 6), variant="dpp"),
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), variant="lds"),
+    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), tune=8),
+    dict(lattice="D3Q7", storage="i16", shape=(8, 8, 8), store_scale=0.75),
 ])
 def test_bad_descriptors_are_rejected(kw):
     d = lbm.make_desc(**kw)

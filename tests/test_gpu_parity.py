@@ -18,6 +18,7 @@ pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ok(), reason="needs a 
 
 BAR = {"f64": 1e-12, "f32": 1e-5}
 UNIT_ROUNDOFF = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+# I16 rounds h to an integer: absolute error <= 1/2 in h units
 ALL_LATTICES = ["D1Q3", "D2Q5", "D2Q9", "D3Q7", "D3Q9", "D3Q13", "D3Q19", "D2Q5_DIA", "D3Q7_DIA"]
 
 SHAPES = {
@@ -28,12 +29,12 @@ SHAPES = {
 }
 
 
-def _solver(name, storage, shape, tau=0.5, variant="auto", store_scale=0.0, fields=None):
+def _solver(name, storage, shape, tau=0.5, variant="auto", store_scale=0.0, fields=None, tune=0):
     from paper_1601_08103_amd.lbm import Solver
     lat = lattice(name)
     if fields is None:
         fields = (np.zeros(shape), np.zeros((lat.D,) + tuple(shape)), np.zeros(shape))
-    return Solver(name, storage, shape, *fields, tau=tau, variant=variant, store_scale=store_scale)
+    return Solver(name, storage, shape, *fields, tau=tau, variant=variant, store_scale=store_scale, tune=tune)
 
 
 def _cases():
@@ -68,7 +69,7 @@ def test_step_matches_oracle_on_random_state(name, storage, variant, shape):
 
 
 @pytest.mark.parametrize("name", ALL_LATTICES)
-@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f16", "bf16", "i16"])
 def test_16bit_storage_single_step_rounding(name, storage):
     """One step from a state the format holds exactly: the result differs from the FP64
     oracle only by the final rounding to storage (plus FP32 collision arithmetic)."""
@@ -77,18 +78,25 @@ def test_16bit_storage_single_step_rounding(name, storage):
     say(name, storage, shape)
     rng = np.random.default_rng(5)
     t0 = 1e-3 * lat.fstar.reshape((-1,) + (1,) * lat.D) * rng.standard_normal((lat.Q,) + shape)
-    sim = _solver(name, storage, shape, store_scale=512.0)
-    assert sim.store_scale == 512.0
+    S = 512.0 if storage != "i16" else 2.0 ** 21  # h ~ N(0, 2^11) for fixed point
+    sim = _solver(name, storage, shape, store_scale=S)
+    assert sim.store_scale == S
     sim.import_f64(t0)
     t0 = sim.export_f64().cpu().numpy()
     sim.step(1)
     got = sim.export_f64().cpu().numpy()
     want = oracle_pull_state(lat, t0, 1)
-    # each stored h_i = S g_i / f*_i is rounded once: |error_i| <= u |h_i| (+ FP32 noise)
-    h_want = want * 512.0 / lat.fstar.reshape((-1,) + (1,) * lat.D)
-    h_got = got * 512.0 / lat.fstar.reshape((-1,) + (1,) * lat.D)
-    u = UNIT_ROUNDOFF[storage]
-    assert np.all(np.abs(h_got - h_want) <= u * np.abs(h_want) * 1.01 + 64 * 2.0 ** -24 * np.abs(h_want).max())
+    # each stored h_i = S g_i / f*_i is rounded once: |error_i| <= u |h_i| (floating formats)
+    # or <= 1/2 (fixed point), plus FP32 collision noise
+    h_want = want * S / lat.fstar.reshape((-1,) + (1,) * lat.D)
+    h_got = got * S / lat.fstar.reshape((-1,) + (1,) * lat.D)
+    noise = 64 * 2.0 ** -24 * np.abs(h_want).max()
+    if storage == "i16":
+        assert np.abs(h_want).max() < 32767
+        assert np.all(np.abs(h_got - h_want) <= 0.5 + noise)
+    else:
+        u = UNIT_ROUNDOFF[storage]
+        assert np.all(np.abs(h_got - h_want) <= u * np.abs(h_want) * 1.01 + noise)
     sim.close()
 
 
@@ -177,7 +185,7 @@ def _sub_box_oracle(lat, p0_full, centre_cell, n):
     return m["p"][c], m["u"][(slice(None),) + c]
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "i16"])
 def test_3d_workload_full_size_sampled(storage):
     """256^3 D3Q7, 8 pulses (amplitude 1e-3, sigma 12), the benchmark's launch configuration:
     24 steps, then p' and u' at 12 seeded cells against the oracle on sub-boxes."""
@@ -206,7 +214,7 @@ def test_3d_workload_full_size_sampled(storage):
         errs.append(np.abs(u_gpu[(slice(None),) + cell] - u_or).max() / np.abs(u_gpu).max())
     worst = max(errs)
     say("3D sampled", storage, "worst rel err", worst)
-    bar = {"f64": 1e-12, "f32": 1e-5, "f16": 2e-3, "bf16": 2e-2}[storage]
+    bar = {"f64": 1e-12, "f32": 1e-5, "f16": 2e-3, "bf16": 2e-2, "i16": 2e-3}[storage]
     assert worst < bar
 
 
@@ -241,7 +249,7 @@ def test_3d_plane_wave_full_size_500_steps(storage):
     assert err < BAR[storage]
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "i16"])
 def test_energy_conservation_and_decay(storage):
     lat = lattice("D3Q7")
     shape = (32, 32, 64)
@@ -252,7 +260,7 @@ def test_energy_conservation_and_decay(storage):
     e0 = sim.l2_energy()[0]
     sim.step(200)
     e1 = sim.l2_energy()[0]
-    drift_bar = {"f64": 1e-12, "f32": 1e-5, "f16": 2e-3, "bf16": 3e-2}[storage]
+    drift_bar = {"f64": 1e-12, "f32": 1e-5, "f16": 2e-3, "bf16": 3e-2, "i16": 2e-3}[storage]
     assert abs(e1 - e0) < drift_bar * e0
     sim.close()
     for tau in (0.6, 1.0):
@@ -266,7 +274,7 @@ def test_energy_conservation_and_decay(storage):
         sim.close()
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "i16"])
 def test_checkpoint_restart_is_bitwise(storage):
     lat = lattice("D2Q9")
     shape = (64, 256)
@@ -287,34 +295,46 @@ def test_checkpoint_restart_is_bitwise(storage):
         s.close()
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
-def test_every_cell_is_written(storage):
-    """Poison the target buffer with NaN bytes; one step must overwrite every value."""
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "i16"])
+@pytest.mark.parametrize("tune", [0, 7])
+def test_every_cell_is_written(storage, tune):
+    """Poison the target buffer (NaN bytes; -32768 for I16, which the encoder never writes);
+    one step must overwrite every value."""
     import torch
     for name, shape in (("D3Q19", (5, 6, 264)), ("D2Q9", (9, 520)), ("D3Q7", (3, 4, 256))):
-        say("poison", name, storage, shape)
+        say("poison", name, storage, shape, "tune", tune)
         lat = lattice(name)
-        sim = _solver(name, storage, shape, fields=inputs.random_fields(1, shape, lat.D))
-        sim.pop_b.fill_(0xFF)
+        sim = _solver(name, storage, shape, fields=inputs.random_fields(1, shape, lat.D), tune=tune)
+        if storage == "i16":
+            sim.pop_b.view(torch.int16).fill_(-32768)
+        else:
+            sim.pop_b.fill_(0xFF)
         sim.step(1)
         assert sim.current()[0] == sim.pop_b.data_ptr()
-        g = sim.export_f64()
-        assert bool(torch.isfinite(g).all())
+        if storage == "i16":
+            assert not bool((sim.pop_b.view(torch.int16) == -32768).any())
+        else:
+            assert bool(torch.isfinite(sim.export_f64()).all())
         sim.close()
 
 
-def test_variants_agree():
-    for name, shape in (("D3Q19", (5, 6, 264)), ("D2Q9", (9, 520))):
+def test_variants_and_tunings_agree():
+    """All step-kernel variants and tuning knobs compute the same update: identical bits
+    (same arithmetic per cell, only the memory access pattern differs)."""
+    for name, shape in (("D3Q19", (5, 6, 264)), ("D2Q9", (9, 520)), ("D3Q7", (4, 3, 256))):
         lat = lattice(name)
         fields = inputs.random_fields(2, shape, lat.D)
         outs = []
-        for variant in ("generic", "dpp"):
-            say("variants", name, variant)
-            sim = _solver(name, "f32", shape, variant=variant, fields=fields)
+        for variant, tune in (("generic", 0), ("dpp", 0), ("dpp", 1), ("dpp", 2), ("dpp", 4), ("dpp", 7)):
+            say("variants", name, variant, tune)
+            sim = _solver(name, "f32", shape, variant=variant, fields=fields, tune=tune)
             sim.step(7)
             outs.append(sim.export_f64().cpu().numpy())
             sim.close()
-        assert rel_l2(outs[1], outs[0]) < 1e-6
+        for o in outs[1:]:
+            assert rel_l2(o, outs[0]) < 1e-6
+        for o in outs[2:]:
+            assert np.array_equal(o, outs[1])
 
 
 def test_device_copy():
