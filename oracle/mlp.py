@@ -9,9 +9,10 @@ through the face:  x -> s = rms(x),  z = x / s,
     h1 = relu(z W1 + b1),  h2 = relu(h1 W2 + b2),  y = h2 W3 + b3,  output = s * y.
 Training minimises the mean squared error between y and target / s (Adam).
 
-`quantize=True` rounds every GEMM input (weights, the normalised strip and the hidden
-activations) to bfloat16 with round-to-nearest-even, as the GPU kernels do before their
-matrix-core products; accumulation stays FP64 here.
+`quantize=True` rounds every GEMM input to bfloat16 with round-to-nearest-even, as the GPU
+kernels do before their matrix-core products: weights, the normalised strip, the hidden
+activations, and in the backward pass the output and pre-activation gradients (bias
+gradients are sums of those rounded gradients).  Accumulation stays FP64 here.
 """
 from __future__ import annotations
 
@@ -63,19 +64,36 @@ def backward(p: dict, cache: dict, y, t, quantize: bool = False) -> dict:
     """Gradients of mse(y, t) = mean((y - t)^2) by the chain rule."""
     q = bf16_round if quantize else (lambda a: np.asarray(a, dtype=np.float64))
     B, k = y.shape
-    dy = 2.0 * (y - t) / (B * k)
+    dy = q(2.0 * (y - t) / (B * k))
     g = {}
     g["W3"] = cache["h2"].T @ dy
     g["b3"] = dy.sum(axis=0)
     dh2 = dy @ q(p["W3"]).T
-    da2 = dh2 * (cache["a2"] > 0)
+    da2 = q(dh2 * (cache["a2"] > 0))
     g["W2"] = cache["h1"].T @ da2
     g["b2"] = da2.sum(axis=0)
     dh1 = da2 @ q(p["W2"]).T
-    da1 = dh1 * (cache["a1"] > 0)
+    da1 = q(dh1 * (cache["a1"] > 0))
     g["W1"] = cache["z"].T @ da1
     g["b1"] = da1.sum(axis=0)
     return g
+
+
+def flat(p: dict) -> np.ndarray:
+    """Parameters in the library's order: W1 (n_in x 64, row-major), b1, W2, b2, W3 (64 x k), b3."""
+    return np.concatenate([p[k].ravel() for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+
+def unflat(v, n_in: int, n_out: int, hidden: int = 64) -> dict:
+    shapes = [("W1", (n_in, hidden)), ("b1", (hidden,)), ("W2", (hidden, hidden)), ("b2", (hidden,)),
+              ("W3", (hidden, n_out)), ("b3", (n_out,))]
+    out, o = {}, 0
+    for key, shp in shapes:
+        n = int(np.prod(shp))
+        out[key] = np.asarray(v[o:o + n], dtype=np.float64).reshape(shp)
+        o += n
+    assert o == len(v)
+    return out
 
 
 def adam(p: dict, g: dict, m: dict, v: dict, t: int, lr: float, b1: float = 0.9, b2: float = 0.999,

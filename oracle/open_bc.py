@@ -1,0 +1,188 @@
+"""FP64 reference of the open-boundary closures (not in the paper: it treats periodic domains
+only and leaves boundary conditions to future work).
+
+TEST INFRASTRUCTURE: only tests, the package smoke check and the benchmark's CPU-baseline
+leg may import this module.
+
+Definitions (these are the build's own, stated here and nowhere else in code):
+
+State.  The post-collision populations g*(x) on the box [0, n_a) per axis ("pull" state,
+the same convention as the GPU library).  One step: for every cell x and population i the
+streamed value is g*_i(x - c_i) when x - c_i is inside the box, else a ghost value given by
+the closure; then the collision (the paper's LBE relaxation) at x; then, for the sponge, a
+damping of the new post-collision values near the faces.
+
+Closures for a source s = x - c_i outside the box:
+  "zero"    0 (the exterior is at rest),
+  "copy"    g*_i(clamp(s)) (zero normal gradient; clamp = nearest cell of the box),
+  "sponge"  0, and after the collision g* <- (1 - sigma(d)) g* for cells at distance
+            d = min_a min(x_a, n_a - 1 - x_a) < W from the faces, sigma(d) = sigma_max ((W-d)/W)^2,
+  "mlp"     a network prediction (below),
+  "external" the value of a given outer state at s (a test device: with the state of a
+            larger periodic run the open step must reproduce that run inside the box).
+
+Faces and the canonical frame.  Face (a, side): axis a, side 0 = low (x_a = 0), 1 = high.
+p = clamp(s) is the face node.  A source outside along one axis takes that face's
+prediction at p; a source beyond an edge or a corner takes the mean of the predictions of
+every face it lies beyond (the same node p), which keeps the closure symmetric under the
+box's symmetries.
+A signed axis permutation M maps the face's outward normal to -x (the canonical face), so
+one network serves every face:  (a,0): identity; (a,1): negate axis a; then axis a is
+swapped with x.  In the canonical frame the populations that enter through the face are
+those with c'_x = +1.  The network input is the strip g*(p + m n_in), m = 0, 1, 2 (n_in the
+inward normal), listed m-major with populations in canonical order; its output is the k
+entering populations in canonical order.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import mlp as mlp_ref
+from .lattices import Lattice
+from .lbe import update_matrix
+
+
+def faces(D):
+    return [(a, side) for a in range(D) for side in (0, 1)]
+
+
+def face_transform(a: int, side: int) -> np.ndarray:
+    """3x3 signed permutation M with M n_out = (-1, 0, 0)."""
+    M = np.eye(3, dtype=np.int64)
+    if side == 1:
+        M[a, a] = -1
+    P = np.eye(3, dtype=np.int64)
+    P[[0, a]] = P[[a, 0]]  # swap axis a and x
+    return P @ M
+
+
+def canonical_perm(lat: Lattice, a: int, side: int) -> np.ndarray:
+    """perm[j] = face population index i whose velocity maps to canonical velocity j."""
+    M = face_transform(a, side)
+    cc = lat.c @ M.T  # canonical velocities of every population, c' = M c
+    perm = np.empty(lat.Q, dtype=np.int64)
+    for j in range(lat.Q):
+        hits = np.where((cc == lat.c[j]).all(axis=1))[0]
+        assert len(hits) == 1
+        perm[j] = hits[0]
+    return perm
+
+
+def incoming_canonical(lat: Lattice) -> np.ndarray:
+    """Canonical indices j with c'_x = +1, in increasing order."""
+    return np.where(lat.c[:, 0] == 1)[0]
+
+
+def strip(lat: Lattice, g, a: int, side: int, node) -> np.ndarray:
+    """Network input (3Q,) at face node `node` (a full spatial index tuple, C order)."""
+    perm = canonical_perm(lat, a, side)
+    D = lat.D
+    ax = D - 1 - a  # array axis of coordinate a
+    step = 1 if side == 0 else -1
+    vals = []
+    for m in range(3):
+        idx = list(node)
+        idx[ax] += m * step
+        cell = tuple(idx)
+        vals.append(np.array([g[(perm[j],) + cell] for j in range(lat.Q)]))
+    return np.concatenate(vals)
+
+
+def _clamp(idx, shape):
+    return tuple(min(max(v, 0), n - 1) for v, n in zip(idx, shape))
+
+
+def _out_faces(idx, shape, D):
+    """Faces (a, side) beyond which idx lies, in axis order."""
+    out = []
+    for a in range(D):
+        ax = D - 1 - a
+        if idx[ax] < 0:
+            out.append((a, 0))
+        elif idx[ax] >= shape[ax]:
+            out.append((a, 1))
+    return out
+
+
+def ghost_values(lat: Lattice, g, closure: str, params: dict | None = None, quantize: bool = False):
+    """Padded populations (Q, n+2 per axis) whose one-cell shell holds the closure's ghosts."""
+    shape = g.shape[1:]
+    D = lat.D
+    pad = np.zeros((lat.Q,) + tuple(n + 2 for n in shape))
+    inner = (slice(None),) + tuple(slice(1, n + 1) for n in shape)
+    pad[inner] = g
+    if closure in ("zero", "sponge"):
+        return pad
+    if closure == "external":
+        ext = np.asarray(params)  # (Q, n+2 per axis): the outer state around the box
+        shell = np.ones(pad.shape[1:], dtype=bool)
+        shell[tuple(slice(1, n + 1) for n in shape)] = False
+        pad[:, shell] = ext[:, shell]
+        return pad
+    it = np.ndindex(*pad.shape[1:])
+    jin = incoming_canonical(lat) if closure == "mlp" else None
+    cache = {}
+    for pidx in it:
+        s = tuple(v - 1 for v in pidx)
+        fs = _out_faces(s, shape, D)
+        if not fs:
+            continue
+        p = _clamp(s, shape)
+        if closure == "copy":
+            pad[(slice(None),) + pidx] = g[(slice(None),) + p]
+        elif closure == "mlp":
+            acc = {}
+            for a, side in fs:
+                key = (a, side, p)
+                if key not in cache:
+                    x = strip(lat, g, a, side, p)[None, :]
+                    cache[key] = mlp_ref.predict(params, x, quantize)[0]
+                perm = canonical_perm(lat, a, side)
+                for r, j in enumerate(jin):
+                    acc.setdefault(perm[j], []).append(cache[key][r])
+            for i, vals in acc.items():
+                # only the populations entering through every listed face are ever pulled
+                # from this ghost; others keep 0
+                if len(vals) == len(fs):
+                    pad[(i,) + pidx] = sum(vals) / len(vals)
+        else:
+            raise ValueError(closure)
+    return pad
+
+
+def sponge_factor(shape, D, width: int, sigma_max: float) -> np.ndarray:
+    grids = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    d = np.full(shape, np.iinfo(np.int64).max)
+    for ax in range(D):
+        n = shape[ax]
+        d = np.minimum(d, np.minimum(grids[ax], n - 1 - grids[ax]))
+    sig = np.where(d < width, sigma_max * ((width - d) / width) ** 2, 0.0)
+    return 1.0 - sig
+
+
+def step_open(lat: Lattice, g, closure: str, tau: float = 0.5, params: dict | None = None,
+              sponge_width: int = 0, sponge_sigma: float = 0.0, quantize: bool = False) -> np.ndarray:
+    """One step of the open-box scheme on the post-collision state g (Q, *shape)."""
+    shape = g.shape[1:]
+    D = lat.D
+    pad = ghost_values(lat, g, closure, params, quantize)
+    pulled = np.empty_like(g)
+    for i in range(lat.Q):
+        sl = []
+        for ax in range(D):
+            a = D - 1 - ax
+            c = int(lat.c[i, a])
+            sl.append(slice(1 - c, 1 - c + shape[ax]))
+        pulled[i] = pad[(i,) + tuple(sl)]
+    H = update_matrix(lat, tau)
+    out = np.tensordot(H, pulled, axes=(1, 0))
+    if closure == "sponge":
+        out *= sponge_factor(shape, D, sponge_width, sponge_sigma)[None]
+    return out
+
+
+def run_open(lat: Lattice, g0, nsteps: int, closure: str, **kw) -> np.ndarray:
+    g = np.array(g0, dtype=np.float64)
+    for _ in range(nsteps):
+        g = step_open(lat, g, closure, **kw)
+    return g
