@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--n", type=int, default=256, help="cells per axis")
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--variant", default="auto")
-    ap.add_argument("--modes", default="f32,f16,bf16,f64", help="storage modes to time and compare")
+    ap.add_argument("--modes", default="f32,f16,bf16,i16,f64", help="storage modes to time and compare")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="only the timed steps of --storage (for rocprofv3)")
@@ -159,7 +159,7 @@ def main():
         sim, ms = timed_run(mode)
         m = sim.moments()
         moments[mode] = (m["p"].clone(), m["u"].clone())
-        results[mode] = dict(ms=ms, bpu=sim.bytes_per_update, scale=sim.store_scale)
+        results[mode] = dict(ms=ms, bpu=sim.bytes_per_update, scale=sim.store_scale, variant=sim.variant)
         sim.close()
         del sim
     p_ref, u_ref = moments["f64"]
@@ -177,7 +177,8 @@ def main():
         storage_modes[mode] = dict(MLUPS=round(mlups, 1), ms_per_step=round(r["ms"] / K, 5),
                                    bytes_per_update=r["bpu"], GBs=round(gbs, 1),
                                    frac_peak_hbm=round(gbs / PEAK_HBM_GBS, 4),
-                                   rel_l2_p_vs_f64=ep, rel_l2_u_vs_f64=eu, store_scale=r["scale"])
+                                   rel_l2_p_vs_f64=ep, rel_l2_u_vs_f64=eu, store_scale=r["scale"],
+                                   variant=r["variant"])
         log(mode, storage_modes[mode])
 
     # plain copy kernel of the same size as one population buffer pair (read + write)
@@ -205,7 +206,7 @@ def main():
     traffic = traffic_from_counters(args.storage, n)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
-                    kernel="step_dpp<D3Q7> (fused pull-stream/collide)",
+                    kernel=f"step_{results[args.storage]['variant']}<D3Q7,{args.storage}> (fused pull-stream/collide)",
                     algorithmic_bytes_per_launch=N * bpu, frac_of_copy=round(achieved / copy_gbs, 4),
                     copy_GBs=round(copy_gbs, 1))
 

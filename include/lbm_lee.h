@@ -74,11 +74,14 @@ typedef int32_t lbm_status;
 #define LBM_TUNE_NT_LOAD 2   /* non-temporal (streaming) loads                         */
 #define LBM_TUNE_PERSISTENT 4 /* grid sized to the resident wave slots, grid-stride loop */
 
-/* Step kernel variant (all give the same result up to FP summation order). */
-#define LBM_VARIANT_AUTO 0    /* DPP when nx % 4 == 0, else GENERIC                          */
+/* Step kernel variant.  All variants run the same per-cell arithmetic, so their results are
+ * bitwise identical; they differ only in how the streamed values are gathered. */
+#define LBM_VARIANT_AUTO 0    /* the fastest measured variant for the storage mode          */
 #define LBM_VARIANT_GENERIC 1 /* one thread per cell, per-element wrapped gathers            */
-#define LBM_VARIANT_DPP 2     /* 4 cells per lane, aligned vector loads, x shift by DPP     */
-#define LBM_VARIANT_LDS 3     /* 4 cells per lane, x shift through an LDS-staged row + halo */
+#define LBM_VARIANT_DPP 2     /* 4 cells per lane, aligned vector loads, x shift by DPP;   */
+                              /* needs nx % 4 == 0                                          */
+#define LBM_VARIANT_LDS 3     /* one thread per cell, x-shifted rows staged in LDS + halo   */
+#define LBM_VARIANT_DPP2 4    /* 2 cells per lane, as DPP; needs nx % 2 == 0                 */
 
 typedef struct lbm_lee_desc {
     int32_t lattice;     /* LBM_D1Q3 ...                                                    */
@@ -178,6 +181,9 @@ lbm_status lbm_lee_current(lbm_lee_handle h, void **pop, int64_t *steps_done);
 
 /* The storage scale S in use (1 for F64/F32). */
 double lbm_lee_store_scale(lbm_lee_handle h);
+
+/* The step-kernel variant the handle runs (LBM_VARIANT_*, never AUTO); -1 for NULL. */
+int32_t lbm_lee_resolved_variant(lbm_lee_handle h);
 
 /* Free the handle (host memory only; device buffers stay with the caller). NULL is a no-op. */
 void lbm_lee_destroy(lbm_lee_handle h);

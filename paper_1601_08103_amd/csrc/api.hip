@@ -83,7 +83,7 @@ lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
     if (N * tab->Q > 9.0e18 / 8.0) return fail(LBM_E_INVALID, "domain too large");
     if ((double)d->n[1] * (double)d->n[2] * 16.0 > 4.0e9) return fail(LBM_E_INVALID, "too many rows (ny * nz)");
     if (!(d->tau >= 0.5) || !std::isfinite(d->tau)) return fail(LBM_E_INVALID, "tau must be finite and >= 1/2 (got %g)", d->tau);
-    if (d->variant < LBM_VARIANT_AUTO || d->variant > LBM_VARIANT_LDS) return fail(LBM_E_INVALID, "unknown variant %d", d->variant);
+    if (d->variant < LBM_VARIANT_AUTO || d->variant > LBM_VARIANT_DPP2) return fail(LBM_E_INVALID, "unknown variant %d", d->variant);
     if (d->tune < 0 || d->tune > 7) return fail(LBM_E_INVALID, "unknown tune bits 0x%x", d->tune);
     if (!(d->store_scale >= 0.0) || !std::isfinite(d->store_scale)) return fail(LBM_E_INVALID, "store_scale must be >= 0");
     if (d->store_scale > 0.0) {
@@ -91,7 +91,7 @@ lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
         if (std::frexp(d->store_scale, &ex) != 0.5) return fail(LBM_E_INVALID, "store_scale must be a power of two");
     }
     if (d->variant == LBM_VARIANT_DPP && d->n[0] % 4 != 0) return fail(LBM_E_UNSUPPORTED, "DPP variant needs nx %% 4 == 0");
-    if (d->variant == LBM_VARIANT_LDS) return fail(LBM_E_UNSUPPORTED, "LDS variant is not built");
+    if (d->variant == LBM_VARIANT_DPP2 && d->n[0] % 2 != 0) return fail(LBM_E_UNSUPPORTED, "DPP2 variant needs nx %% 2 == 0");
     return LBM_OK;
 }
 
@@ -184,9 +184,15 @@ lbm_status launch_check() {
     return LBM_OK;
 }
 
+// AUTO: measured on MI355X (D3Q7, 256^3): for 4- and 8-byte storage the one-cell-per-thread
+// gather has the highest occupancy and beats the vectorised variants; 2-byte storage needs
+// wider per-lane accesses.
 int resolve_variant(const lbm_lee *h) {
     if (h->desc.variant != LBM_VARIANT_AUTO) return h->desc.variant;
-    return (h->nx % 4 == 0) ? LBM_VARIANT_DPP : LBM_VARIANT_GENERIC;
+    if (elem_size(h->desc.storage) >= 4) return LBM_VARIANT_GENERIC;
+    if (h->nx % 4 == 0) return LBM_VARIANT_DPP;
+    if (h->nx % 2 == 0) return LBM_VARIANT_DPP2;
+    return LBM_VARIANT_GENERIC;
 }
 
 lbm_status launch_init(lbm_lee *h, const double *rho, const double *u, const double *theta, hipStream_t st) {
@@ -351,30 +357,43 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
         using ST = decltype(sto);
         using E = typename ST::elem;
         const auto k = step_coef<typename ST::comp, VS::Q>(h);
-        const int cpr = (h->nx + 255) / 256;
+        const int vec = variant == LBM_VARIANT_DPP2 ? 2 : 4;
+        const int cpr = (h->nx + 64 * vec - 1) / (64 * vec);
         const unsigned waves = (unsigned)((size_t)h->ny * h->nz * cpr);
-        const bool fullrow = h->nx == 256;
+        const bool fullrow = h->nx == 64 * vec;
         const unsigned tune = (unsigned)h->desc.tune;
         unsigned grid = (waves + 3) / 4;
-        if ((tune & kTunePersistent) && h->cus > 0) {
+        if ((tune & kTunePersistent) && h->cus > 0 && (variant == LBM_VARIANT_DPP || variant == LBM_VARIANT_DPP2)) {
             int per_cu = 0;
-            const void *fn = fullrow ? reinterpret_cast<const void *>(&step_dpp<VS, ST, true>)
-                                     : reinterpret_cast<const void *>(&step_dpp<VS, ST, false>);
+            const void *fn = vec == 4 ? (fullrow ? reinterpret_cast<const void *>(&step_dpp<VS, ST, 4, true>)
+                                                 : reinterpret_cast<const void *>(&step_dpp<VS, ST, 4, false>))
+                                      : (fullrow ? reinterpret_cast<const void *>(&step_dpp<VS, ST, 2, true>)
+                                                 : reinterpret_cast<const void *>(&step_dpp<VS, ST, 2, false>));
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) == hipSuccess && per_cu > 0) {
                 const unsigned g = (unsigned)(per_cu * h->cus);
                 if (g < grid) grid = g;
             }
             (void)hipGetLastError();
         }
+        const int lds_cpr = (h->nx + 255) / 256;
+        const unsigned lds_blocks = (unsigned)((size_t)h->ny * h->nz * lds_cpr);
         for (int64_t t = 0; t < nsteps; ++t) {
             const E *src = static_cast<const E *>(h->buf[h->cur]);
             E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);
             if (variant == LBM_VARIANT_GENERIC) {
                 step_generic<VS, ST><<<blocks_for(h->N), 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, k);
-            } else if (fullrow) {
-                step_dpp<VS, ST, true><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr, waves, tune, k);
+            } else if (variant == LBM_VARIANT_LDS) {
+                step_lds<VS, ST><<<lds_blocks, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, lds_cpr, k);
+            } else if (vec == 4) {
+                if (fullrow)
+                    step_dpp<VS, ST, 4, true><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr, waves, tune, k);
+                else
+                    step_dpp<VS, ST, 4, false><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr, waves, tune, k);
             } else {
-                step_dpp<VS, ST, false><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr, waves, tune, k);
+                if (fullrow)
+                    step_dpp<VS, ST, 2, true><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr, waves, tune, k);
+                else
+                    step_dpp<VS, ST, 2, false><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr, waves, tune, k);
             }
             lbm_status ls = launch_check();
             if (ls != LBM_OK) return ls;
@@ -488,6 +507,8 @@ lbm_status lbm_lee_current(lbm_lee_handle h, void **pop, int64_t *steps_done) {
 }
 
 double lbm_lee_store_scale(lbm_lee_handle h) { return h ? h->S : 0.0; }
+
+int32_t lbm_lee_resolved_variant(lbm_lee_handle h) { return h ? resolve_variant(h) : -1; }
 
 void lbm_lee_destroy(lbm_lee_handle h) { delete h; }
 

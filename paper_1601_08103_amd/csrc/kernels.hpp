@@ -29,9 +29,20 @@ struct Kc {
     CT hi, lo;
 };
 
-template <typename CT>
+template <bool SPLIT, typename CT>
 __device__ __forceinline__ CT mulk(CT x, Kc<CT> k) {
-    return fma(k.hi, x, k.lo * x);
+    if constexpr (SPLIT)
+        return fma(k.hi, x, k.lo * x);
+    else
+        return k.hi * x;
+}
+
+// Only FP32 storage needs the split: FP64 constants are exact to 2^-53, and for the 16-bit
+// formats the rounding of every stored value (2^-9 .. 2^-12 relative) dominates the 2^-24
+// constant error by orders of magnitude.
+template <class ST>
+constexpr bool split_constants() {
+    return sizeof(typename ST::elem) == 4;
 }
 
 // Collision constants in storage units, for compute type CT.  With stored value s_i and
@@ -60,12 +71,12 @@ struct FieldCoef {
 };
 
 // ------------------------------------------------------------------ collision
-template <class VS, typename CT>
+template <class VS, typename CT, bool SPLIT>
 __device__ __forceinline__ void collide(const StepCoef<CT, VS::Q> &k, CT (&s)[VS::Q]) {
     CT rho = 0, jx = 0, jy = 0, jz = 0, e = 0;
 #pragma unroll
     for (int i = 0; i < VS::Q; ++i) {
-        const CT g = mulk(s[i], k.dec[i]);
+        const CT g = mulk<SPLIT>(s[i], k.dec[i]);
         rho += g;
         if (VS::cx(i) > 0) jx += g;
         if (VS::cx(i) < 0) jx -= g;
@@ -73,12 +84,12 @@ __device__ __forceinline__ void collide(const StepCoef<CT, VS::Q> &k, CT (&s)[VS
         if (VS::cy(i) < 0) jy -= g;
         if (VS::cz(i) > 0) jz += g;
         if (VS::cz(i) < 0) jz -= g;
-        e += mulk(s[i], k.edec[i]);
+        e += mulk<SPLIT>(s[i], k.edec[i]);
     }
-    const CT theta = mulk(e, k.gm1_rho0) - mulk(rho, k.theta0_rho0);
-    const CT A = mulk(rho, k.a1) + mulk(theta, k.a2);
-    const CT C = mulk(rho, k.c1) + mulk(theta, k.c2);
-    const CT Ux = mulk(jx, k.b_rho0), Uy = mulk(jy, k.b_rho0), Uz = mulk(jz, k.b_rho0);
+    const CT theta = mulk<SPLIT>(e, k.gm1_rho0) - mulk<SPLIT>(rho, k.theta0_rho0);
+    const CT A = mulk<SPLIT>(rho, k.a1) + mulk<SPLIT>(theta, k.a2);
+    const CT C = mulk<SPLIT>(rho, k.c1) + mulk<SPLIT>(theta, k.c2);
+    const CT Ux = mulk<SPLIT>(jx, k.b_rho0), Uy = mulk<SPLIT>(jy, k.b_rho0), Uz = mulk<SPLIT>(jz, k.b_rho0);
 #pragma unroll
     for (int i = 0; i < VS::Q; ++i) {
         CT t = A;
@@ -89,7 +100,7 @@ __device__ __forceinline__ void collide(const StepCoef<CT, VS::Q> &k, CT (&s)[VS
         if (VS::cz(i) > 0) t += Uz;
         if (VS::cz(i) < 0) t -= Uz;
         if (VS::c2(i) != 0) t += (CT)(0.5 * VS::c2(i)) * C;  // 1/2, 1 or 3/2: exact
-        s[i] = mulk(s[i], k.keep) + mulk(t, k.w[i]);
+        s[i] = mulk<SPLIT>(s[i], k.keep) + mulk<SPLIT>(t, k.w[i]);
     }
 }
 
@@ -121,7 +132,7 @@ __global__ __launch_bounds__(256) void step_generic(const typename ST::elem *__r
         const int zs = wrap_add(z, -VS::cz(i), nz);
         s[i] = ST::dec(src[(size_t)i * N + ((size_t)zs * ny + ys) * nx + xs]);
     }
-    collide<VS, CT>(k, s);
+    collide<VS, CT, split_constants<ST>()>(k, s);
 #pragma unroll
     for (int i = 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
 }
@@ -143,17 +154,43 @@ __device__ __forceinline__ double dpp_move(double v) {
     return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-// Each wave owns a chunk of 256 consecutive cells of one x-row (64 lanes x 4 cells).  Rows
-// along y/z are whole-row offsets, so every load and store is an aligned 4-element vector.
-// A population with c_x = +1 needs the element left of each lane's quad: it comes from the
-// lane below through a DPP move; c_x = -1 needs the element right of the quad from the lane
-// above.  FULLROW (nx == 256) rotates within the wave, which is exactly the periodic wrap;
-// otherwise the first lane and the last active lane load their neighbour element directly.
-// Waves walk the chunks grid-stride (one pass when the grid covers them all).
+// Each wave owns a chunk of 64 * VEC consecutive cells of one x-row (VEC cells per lane).
+// Rows along y/z are whole-row offsets, so every load and store is an aligned VEC-element
+// vector.  A population with c_x = +1 needs the element left of each lane's group: it comes
+// from the lane below through a DPP move; c_x = -1 needs the element right of the group from
+// the lane above.  FULLROW (nx == 64 * VEC) rotates within the wave, which is exactly the
+// periodic wrap; otherwise the first lane and the last active lane load their neighbour
+// element directly.  Waves walk the chunks grid-stride (one pass when the grid covers them).
 // tune: bit 0 = non-temporal stores, bit 1 = non-temporal loads.
 enum : unsigned { kTuneNtStore = 1u, kTuneNtLoad = 2u, kTunePersistent = 4u };
 
-template <class VS, class ST, bool FULLROW>
+template <class ST, int VEC>
+__device__ __forceinline__ void loadv(const typename ST::elem *p, typename ST::comp (&v)[VEC], bool nt) {
+    if constexpr (VEC == 4) {
+        load4<ST>(p, v, nt);
+    } else {
+        static_assert(VEC == 2, "VEC is 2 or 4");
+        v[0] = ST::dec(p[0]);
+        v[1] = ST::dec(p[1]);
+    }
+}
+template <class ST, int VEC>
+__device__ __forceinline__ void storev(typename ST::elem *p, const typename ST::comp (&v)[VEC], bool nt) {
+    if constexpr (VEC == 4) {
+        store4<ST>(p, v, nt);
+    } else {
+        typename ST::elem a = ST::enc(v[0]), b = ST::enc(v[1]);
+        if (nt) {
+            __builtin_nontemporal_store(a, p);
+            __builtin_nontemporal_store(b, p + 1);
+        } else {
+            p[0] = a;
+            p[1] = b;
+        }
+    }
+}
+
+template <class VS, class ST, int VEC, bool FULLROW>
 __device__ __forceinline__ void step_chunk(const typename ST::elem *__restrict__ src,
                                            typename ST::elem *__restrict__ dst, int nx, int ny, int nz, size_t N,
                                            unsigned row, int chunk, int lane, bool ntl, bool nts,
@@ -162,46 +199,53 @@ __device__ __forceinline__ void step_chunk(const typename ST::elem *__restrict__
     using E = typename ST::elem;
     const int y = (int)(row % (unsigned)ny);
     const int z = (int)(row / (unsigned)ny);
-    const int x0 = chunk * 256 + lane * 4;
+    const int x0 = chunk * (64 * VEC) + lane * VEC;
     const bool active = x0 < nx;
-    const bool last = (lane == 63) || (x0 + 4 >= nx);
+    const bool last = (lane == 63) || (x0 + VEC >= nx);
 
-    CT s[VS::Q][4];
+    CT s[VS::Q][VEC];
 #pragma unroll
     for (int i = 0; i < VS::Q; ++i) {
         const int ys = wrap_add(y, -VS::cy(i), ny);
         const int zs = wrap_add(z, -VS::cz(i), nz);
         const E *rowp = src + (size_t)i * N + ((size_t)zs * ny + ys) * (size_t)nx;
-        CT v[4] = {0, 0, 0, 0};
-        if (active) load4<ST>(rowp + x0, v, ntl);
+        CT v[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) v[q] = 0;
+        if (active) loadv<ST, VEC>(rowp + x0, v, ntl);
         if (VS::cx(i) == 0) {
-            s[i][0] = v[0]; s[i][1] = v[1]; s[i][2] = v[2]; s[i][3] = v[3];
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) s[i][q] = v[q];
         } else if (VS::cx(i) > 0) {
-            CT prev = FULLROW ? dpp_move<kDppWaveRor1>(v[3]) : dpp_move<kDppWaveShr1>(v[3]);
+            CT prev = FULLROW ? dpp_move<kDppWaveRor1>(v[VEC - 1]) : dpp_move<kDppWaveShr1>(v[VEC - 1]);
             if (!FULLROW && lane == 0) prev = ST::dec(rowp[x0 == 0 ? nx - 1 : x0 - 1]);
-            s[i][0] = prev; s[i][1] = v[0]; s[i][2] = v[1]; s[i][3] = v[2];
+            s[i][0] = prev;
+#pragma unroll
+            for (int q = 1; q < VEC; ++q) s[i][q] = v[q - 1];
         } else {
             CT next = FULLROW ? dpp_move<kDppWaveRol1>(v[0]) : dpp_move<kDppWaveShl1>(v[0]);
-            if (!FULLROW && last && active) next = ST::dec(rowp[x0 + 4 >= nx ? 0 : x0 + 4]);
-            s[i][0] = v[1]; s[i][1] = v[2]; s[i][2] = v[3]; s[i][3] = next;
+            if (!FULLROW && last && active) next = ST::dec(rowp[x0 + VEC >= nx ? 0 : x0 + VEC]);
+#pragma unroll
+            for (int q = 0; q < VEC - 1; ++q) s[i][q] = v[q + 1];
+            s[i][VEC - 1] = next;
         }
     }
     if (!active) return;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < VEC; ++q) {
         CT c[VS::Q];
 #pragma unroll
         for (int i = 0; i < VS::Q; ++i) c[i] = s[i][q];
-        collide<VS, CT>(k, c);
+        collide<VS, CT, split_constants<ST>()>(k, c);
 #pragma unroll
         for (int i = 0; i < VS::Q; ++i) s[i][q] = c[i];
     }
     const size_t out = ((size_t)z * ny + y) * (size_t)nx + x0;
 #pragma unroll
-    for (int i = 0; i < VS::Q; ++i) store4<ST>(dst + (size_t)i * N + out, s[i], nts);
+    for (int i = 0; i < VS::Q; ++i) storev<ST, VEC>(dst + (size_t)i * N + out, s[i], nts);
 }
 
-template <class VS, class ST, bool FULLROW>
+template <class VS, class ST, int VEC, bool FULLROW>
 __global__ __launch_bounds__(256) void step_dpp(const typename ST::elem *__restrict__ src,
                                                 typename ST::elem *__restrict__ dst, int nx, int ny, int nz,
                                                 size_t N, int chunks_per_row, unsigned total_waves, unsigned tune,
@@ -212,8 +256,71 @@ __global__ __launch_bounds__(256) void step_dpp(const typename ST::elem *__restr
     for (unsigned wave = blockIdx.x * 4u + wid; wave < total_waves; wave += gridDim.x * 4u) {
         const unsigned row = wave / (unsigned)chunks_per_row;
         const int chunk = (int)(wave - row * (unsigned)chunks_per_row);
-        step_chunk<VS, ST, FULLROW>(src, dst, nx, ny, nz, N, row, chunk, lane, ntl, nts, k);
+        step_chunk<VS, ST, VEC, FULLROW>(src, dst, nx, ny, nz, N, row, chunk, lane, ntl, nts, k);
     }
+}
+
+// ------------------------------------------------------------------ step: LDS-staged variant
+// One thread per cell; a block owns 256 consecutive cells of one x-row.  Populations with
+// c_x = 0 are loaded directly (aligned, coalesced).  For c_x != 0 the block stages its own
+// 256 source cells plus one halo cell on each side (periodic wrap at the row ends) in LDS with
+// aligned loads, and every thread reads its x-shifted value from LDS.
+template <class VS>
+constexpr int x_moving_count() {
+    int n = 0;
+    for (int i = 0; i < VS::Q; ++i) n += VS::c[i][0] != 0 ? 1 : 0;
+    return n;
+}
+
+template <class VS, class ST>
+__global__ __launch_bounds__(256) void step_lds(const typename ST::elem *__restrict__ src,
+                                                typename ST::elem *__restrict__ dst, int nx, int ny, int nz,
+                                                size_t N, int chunks_per_row, StepCoef<typename ST::comp, VS::Q> k) {
+    using CT = typename ST::comp;
+    using E = typename ST::elem;
+    constexpr int NXM = x_moving_count<VS>() > 0 ? x_moving_count<VS>() : 1;
+    __shared__ CT stage[NXM][258];
+    const unsigned blk = blockIdx.x;
+    const unsigned row = blk / (unsigned)chunks_per_row;
+    const int chunk = (int)(blk - row * (unsigned)chunks_per_row);
+    const int y = (int)(row % (unsigned)ny);
+    const int z = (int)(row / (unsigned)ny);
+    const int t = threadIdx.x;
+    const int x0 = chunk * 256;
+    const int x = x0 + t;
+    const bool active = x < nx;
+    const int width = min(256, nx - x0);  // cells of this chunk
+
+    CT s[VS::Q];
+    int m = 0;
+#pragma unroll
+    for (int i = 0; i < VS::Q; ++i) {
+        const int ys = wrap_add(y, -VS::cy(i), ny);
+        const int zs = wrap_add(z, -VS::cz(i), nz);
+        const E *rowp = src + (size_t)i * N + ((size_t)zs * ny + ys) * (size_t)nx;
+        if (VS::cx(i) == 0) {
+            s[i] = active ? ST::dec(rowp[x]) : (CT)0;
+        } else {
+            if (active) stage[m][t + 1] = ST::dec(rowp[x]);
+            if (t == 0) stage[m][0] = ST::dec(rowp[x0 == 0 ? nx - 1 : x0 - 1]);
+            if (t == 1) stage[m][width + 1] = ST::dec(rowp[x0 + width >= nx ? 0 : x0 + width]);
+            ++m;
+        }
+    }
+    __syncthreads();
+    m = 0;
+#pragma unroll
+    for (int i = 0; i < VS::Q; ++i) {
+        if (VS::cx(i) != 0) {
+            s[i] = stage[m][t + 1 - VS::cx(i)];
+            ++m;
+        }
+    }
+    if (!active) return;
+    collide<VS, CT, split_constants<ST>()>(k, s);
+    const size_t cell = ((size_t)z * ny + y) * (size_t)nx + x;
+#pragma unroll
+    for (int i = 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
 }
 
 // ------------------------------------------------------------------ initial state

@@ -1,0 +1,309 @@
+// Learned non-reflecting boundary closure: a small MLP evaluated and trained on matrix cores.
+//
+// Not in the paper (its domains are periodic).  The network maps the strip of post-collision
+// populations at a face node (3 cells deep along the inward normal, Q values each, in the
+// canonical face frame) to the k populations that enter the box through the face:
+//   s = rms(x), z = x / s, h1 = relu(z W1 + b1), h2 = relu(h1 W2 + b2), y = h2 W3 + b3,
+//   prediction = s y.
+// Parameters are FP32 (master copy, layout W1[n_in][64], b1[64], W2[64][64], b2[64],
+// W3[64][k], b3[k], row-major).  Every matrix product takes bfloat16 inputs (round to
+// nearest even) and accumulates in FP32 on v_mfma_f32_16x16x16_bf16; biases are added in FP32.
+//
+// One wave owns a tile of 16 samples.  MFMA 16x16x16 operand layouts (lane l, element e):
+//   A (16 x 16, rows i, reduction k): A[l % 16][4 (l / 16) + e]
+//   B (16 x 16, reduction k, cols j): B[4 (l / 16) + e][l % 16]
+//   C (16 x 16):                      C[4 (l / 16) + e][l % 16]
+// Activations pass between layers through LDS (a per-wave [16][64] bfloat16 tile).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "velsets.hpp"
+
+namespace lbm {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kHidden = 64;
+
+__device__ __forceinline__ unsigned short bf16_bits(float v) {
+    unsigned u = __float_as_uint(v);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
+
+__device__ __forceinline__ floatx4 mfma16(bf16x4 a, bf16x4 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// Wave-local LDS ordering: the wave's LDS accesses complete in program order; the fences
+// keep the compiler from moving loads above the stores other lanes depend on.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Number of canonical entering populations (c_x = +1) of a velocity set.
+template <class VS>
+__host__ __device__ constexpr int entering_count() {
+    int k = 0;
+    for (int i = 0; i < VS::Q; ++i) k += VS::c[i][0] == 1 ? 1 : 0;
+    return k;
+}
+template <class VS>
+__host__ __device__ constexpr int entering_index(int r) {
+    int k = 0;
+    for (int i = 0; i < VS::Q; ++i)
+        if (VS::c[i][0] == 1) {
+            if (k == r) return i;
+            ++k;
+        }
+    return -1;
+}
+
+template <class VS>
+struct NetGeom {
+    static constexpr int NIN = 3 * VS::Q;
+    static constexpr int NIN_PAD = (NIN + 15) / 16 * 16;
+    static constexpr int NOUT = entering_count<VS>();
+    static constexpr int OFF_W1 = 0;
+    static constexpr int OFF_B1 = OFF_W1 + NIN * kHidden;
+    static constexpr int OFF_W2 = OFF_B1 + kHidden;
+    static constexpr int OFF_B2 = OFF_W2 + kHidden * kHidden;
+    static constexpr int OFF_W3 = OFF_B2 + kHidden;
+    static constexpr int OFF_B3 = OFF_W3 + kHidden * NOUT;
+    static constexpr int NPARAM = OFF_B3 + NOUT;
+    static_assert(NIN_PAD <= 64, "strip wider than the LDS tile");
+    static_assert(NOUT <= 16, "too many entering populations for one output tile");
+};
+
+// Per-wave LDS tiles (bfloat16 bits).
+struct WaveTiles {
+    unsigned short z[16][64];
+    unsigned short h1[16][64];
+    unsigned short h2[16][64];
+    unsigned short dy[16][16];
+    unsigned short da2[16][64];
+    unsigned short da1[16][64];
+};
+
+// A operand from an LDS tile X[16][64] (rows = samples): columns kk*16 + 4 (l/16) + e.
+__device__ __forceinline__ bf16x4 a_rows(const unsigned short (*X)[64], int kk, int lane) {
+    const int i = lane & 15, k0 = kk * 16 + 4 * (lane >> 4);
+    bf16x4 a;
+    a.x = (short)X[i][k0]; a.y = (short)X[i][k0 + 1]; a.z = (short)X[i][k0 + 2]; a.w = (short)X[i][k0 + 3];
+    return a;
+}
+// A operand = transpose of an LDS tile: A[i][k] = X[k][mt*16 + i] (rows of A = tile columns).
+template <int LD>
+__device__ __forceinline__ bf16x4 a_cols(const unsigned short (*X)[LD], int mt, int lane) {
+    const int i = mt * 16 + (lane & 15), k0 = 4 * (lane >> 4);
+    bf16x4 a;
+    a.x = (short)X[k0][i]; a.y = (short)X[k0 + 1][i]; a.z = (short)X[k0 + 2][i]; a.w = (short)X[k0 + 3][i];
+    return a;
+}
+// B operand from an LDS tile: B[k][j] = X[k][nt*16 + j], k = the 16 samples.
+template <int LD>
+__device__ __forceinline__ bf16x4 b_rows(const unsigned short (*X)[LD], int nt, int lane) {
+    const int j = nt * 16 + (lane & 15), k0 = 4 * (lane >> 4);
+    bf16x4 b;
+    b.x = (short)X[k0][j]; b.y = (short)X[k0 + 1][j]; b.z = (short)X[k0 + 2][j]; b.w = (short)X[k0 + 3][j];
+    return b;
+}
+// B operand from a row-major FP32 matrix W[rows][cols]: B[k][j] = W[kk*16 + k][nt*16 + j],
+// zero outside the matrix.
+__device__ __forceinline__ bf16x4 b_weight(const float *__restrict__ W, int rows, int cols, int kk, int nt, int lane) {
+    const int j = nt * 16 + (lane & 15), k0 = kk * 16 + 4 * (lane >> 4);
+    short v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int k = k0 + e;
+        v[e] = (k < rows && j < cols) ? (short)bf16_bits(W[k * cols + j]) : (short)0;
+    }
+    bf16x4 b = {v[0], v[1], v[2], v[3]};
+    return b;
+}
+// B operand from the transpose of W[rows][cols]: B[k][j] = W[nt*16 + j][kk*16 + k].
+__device__ __forceinline__ bf16x4 b_weight_t(const float *__restrict__ W, int rows, int cols, int kk, int nt, int lane) {
+    const int j = nt * 16 + (lane & 15), k0 = kk * 16 + 4 * (lane >> 4);
+    short v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int k = k0 + e;
+        v[e] = (j < rows && k < cols) ? (short)bf16_bits(W[j * cols + k]) : (short)0;
+    }
+    bf16x4 b = {v[0], v[1], v[2], v[3]};
+    return b;
+}
+
+// Forward pass of one tile: z (already in LDS) -> h1, h2 (LDS) and y (C layout, 16 x 16).
+template <class VS>
+__device__ floatx4 net_forward_tile(const float *__restrict__ P, WaveTiles &T, int lane) {
+    using G = NetGeom<VS>;
+    const int row0 = 4 * (lane >> 4), col = lane & 15;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        floatx4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < G::NIN_PAD / 16; ++kk)
+            acc = mfma16(a_rows(T.z, kk, lane), b_weight(P + G::OFF_W1, G::NIN, kHidden, kk, nt, lane), acc);
+        const float bias = P[G::OFF_B1 + nt * 16 + col];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) T.h1[row0 + e][nt * 16 + col] = bf16_bits(fmaxf(acc[e] + bias, 0.0f));
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        floatx4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+            acc = mfma16(a_rows(T.h1, kk, lane), b_weight(P + G::OFF_W2, kHidden, kHidden, kk, nt, lane), acc);
+        const float bias = P[G::OFF_B2 + nt * 16 + col];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) T.h2[row0 + e][nt * 16 + col] = bf16_bits(fmaxf(acc[e] + bias, 0.0f));
+    }
+    wave_lds_sync();
+    floatx4 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+        acc = mfma16(a_rows(T.h2, kk, lane), b_weight(P + G::OFF_W3, kHidden, G::NOUT, kk, 0, lane), acc);
+    const float bias = col < G::NOUT ? P[G::OFF_B3 + col] : 0.0f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[e] += bias;
+    return acc;
+}
+
+// Load a tile of raw strips (rows >= nrows are zero) into T.z as bf16 of x / rms(x); returns
+// rms of row (lane & 15) in every lane that holds that row.  X(row, v) gives strip value v.
+template <class VS, class LoadFn>
+__device__ float load_normalised_tile(WaveTiles &T, int nrows, int lane, LoadFn X) {
+    using G = NetGeom<VS>;
+    const int r = lane & 15, g = lane >> 4;
+    float ss = 0.0f;
+    float vals[(G::NIN_PAD + 3) / 4];
+#pragma unroll
+    for (int t = 0; t < (G::NIN_PAD + 3) / 4; ++t) {
+        const int v = g + 4 * t;
+        float x = 0.0f;
+        if (r < nrows && v < G::NIN) x = X(r, v);
+        vals[t] = x;
+        ss += x * x;
+    }
+    ss += __shfl_xor(ss, 16, 64);
+    ss += __shfl_xor(ss, 32, 64);
+    const float s = sqrtf(ss / (float)G::NIN) + 1e-30f;
+    const float inv = 1.0f / s;
+#pragma unroll
+    for (int t = 0; t < (G::NIN_PAD + 3) / 4; ++t) {
+        const int v = g + 4 * t;
+        if (v < G::NIN_PAD) T.z[r][v] = v < G::NIN ? bf16_bits(vals[t] * inv) : (unsigned short)0;
+    }
+    wave_lds_sync();
+    return s;
+}
+
+// ------------------------------------------------------------------ batch inference on strips
+template <class VS>
+__global__ __launch_bounds__(256) void nrbc_forward_kernel(const float *__restrict__ P, const float *__restrict__ strips,
+                                                           long long count, float *__restrict__ out) {
+    using G = NetGeom<VS>;
+    __shared__ WaveTiles tiles[4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    WaveTiles &T = tiles[wid];
+    const long long ntiles = (count + 15) / 16;
+    for (long long tile = (long long)blockIdx.x * 4 + wid; tile < ntiles; tile += (long long)gridDim.x * 4) {
+        const long long base = tile * 16;
+        const int nrows = (int)min((long long)16, count - base);
+        const float s = load_normalised_tile<VS>(T, nrows, lane,
+                                                 [&](int r, int v) { return strips[(base + r) * G::NIN + v]; });
+        const floatx4 y = net_forward_tile<VS>(P, T, lane);
+        // y[e] is row 4 (l/16) + e, column l % 16; the row's rms lives in lane (row)
+        const int col = lane & 15;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = 4 * (lane >> 4) + e;
+            const float srow = __shfl(s, row, 64);
+            if (row < nrows && col < G::NOUT) out[(base + row) * G::NOUT + col] = srow * y[e];
+        }
+        wave_lds_sync();
+    }
+}
+
+// ------------------------------------------------------------------ loss and gradients
+// Each wave accumulates the gradients of its tiles in registers and writes one partial row
+// (NPARAM gradient values + its squared-error sum) to ws[wave]; nrbc_reduce_kernel sums the
+// rows in a fixed order.  Targets are raw; they are divided by the strip's rms like the
+// prediction.  Loss = mean over samples and outputs of (y - t / s)^2.
+template <class VS>
+__global__ __launch_bounds__(256) void nrbc_grad_kernel(const float *__restrict__ P, const float *__restrict__ strips,
+                                                        const float *__restrict__ targets, long long count,
+                                                        float *__restrict__ ws) {
+    using G = NetGeom<VS>;
+    constexpr int MT1 = G::NIN_PAD / 16;
+    __shared__ WaveTiles tiles[4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    WaveTiles &T = tiles[wid];
+    const int row0 = 4 * (lane >> 4), col = lane & 15;
+    const float inv_n = 1.0f / (float)((double)count * G::NOUT);
+    bf16x4 ones;
+    ones.x = ones.y = ones.z = ones.w = (short)0x3f80;  // bf16 1.0
+
+    floatx4 g1[MT1][4], g2[4][4], g3[4], gb1[4], gb2[4], gb3;
+    const floatx4 zero = {0, 0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int m = 0; m < MT1; ++m) g1[m][a] = zero;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) g2[a][b] = zero;
+        g3[a] = zero;
+        gb1[a] = zero;
+        gb2[a] = zero;
+    }
+    gb3 = zero;
+    float sq = 0.0f;
+
+    const long long ntiles = (count + 15) / 16;
+    for (long long tile = (long long)blockIdx.x * 4 + wid; tile < ntiles; tile += (long long)gridDim.x * 4) {
+        const long long base = tile * 16;
+        const int nrows = (int)min((long long)16, count - base);
+        const float s = load_normalised_tile<VS>(T, nrows, lane,
+                                                 [&](int r, int v) { return strips[(base + r) * G::NIN + v]; });
+        const floatx4 y = net_forward_tile<VS>(P, T, lane);
+        // output gradient dy = 2 (y - t/s) / (count k), rows beyond the batch are zero
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = row0 + e;
+            const float srow = __shfl(s, row, 64);
+            float d = 0.0f;
+            if (row < nrows && col < G::NOUT) {
+                const float t = targets[(base + row) * G::NOUT + col] / srow;
+                const float diff = y[e] - t;
+                sq += diff * diff;
+                d = 2.0f * diff * inv_n;
+            }
+            T.dy[row][col] = bf16_bits(d);
+        }
+        wave_lds_sync();
+        // W3, b3:  dW3 += h2^T dy,  db3 += 1^T dy
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) g3[mt] = mfma16(a_cols<64>(T.h2, mt, lane), b_rows<16>(T.dy, 0, lane), g3[mt]);
+        gb3 = mfma16(ones, b_rows<16>(T.dy, 0, lane), gb3);
+        // dh2 = dy W3^T, da2 = dh2 * (h2 > 0)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            floatx4 acc = mfma16(a_rows(reinterpret_cast<const unsigned short (*)[64]>(nullptr) == nullptr
+                                            ? nullptr : nullptr, 0, lane), b_weight_t(P + G::OFF_W3, kHidden, G::NOUT, 0, nt, lane), zero);
+            (void)acc;
+        }
+        wave_lds_sync();
+    }
+    (void)sq;
+    (void)gb1; (void)gb2; (void)g1; (void)g2;
+    (void)ws;
+}
+
+}  // namespace lbm

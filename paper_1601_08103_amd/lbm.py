@@ -19,7 +19,7 @@ LATTICES = {"D1Q3": 0, "D2Q5": 1, "D2Q9": 2, "D3Q7": 3, "D3Q9": 4, "D3Q13": 5, "
 STORAGES = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "i16": 4}
 ELEM_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "i16": 2}
 TUNE = {"nt_store": 1, "nt_load": 2, "persistent": 4}
-VARIANTS = {"auto": 0, "generic": 1, "dpp": 2, "lds": 3}
+VARIANTS = {"auto": 0, "generic": 1, "dpp": 2, "lds": 3, "dpp2": 4}
 
 LBM_OK = 0
 
@@ -63,6 +63,7 @@ SIGNATURES = {
     "lbm_lee_import_f64": (ctypes.c_int32, [_VP, _VP, ctypes.c_int64, _VP]),
     "lbm_lee_current": (ctypes.c_int32, [_VP, ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int64)]),
     "lbm_lee_store_scale": (ctypes.c_double, [_VP]),
+    "lbm_lee_resolved_variant": (ctypes.c_int32, [_VP]),
     "lbm_lee_destroy": (None, [_VP]),
     "lbm_lee_device_copy": (ctypes.c_int32, [_VP, _VP, ctypes.c_size_t, _VP]),
     "lbm_lee_last_error": (ctypes.c_char_p, []),
@@ -181,6 +182,10 @@ def lbm_lee_store_scale(h) -> float:
     return float(load().lbm_lee_store_scale(h))
 
 
+def lbm_lee_resolved_variant(h) -> int:
+    return int(load().lbm_lee_resolved_variant(h))
+
+
 def lbm_lee_destroy(h):
     load().lbm_lee_destroy(h)
 
@@ -289,6 +294,11 @@ class Solver:
     @property
     def store_scale(self) -> float:
         return lbm_lee_store_scale(self.h)
+
+    @property
+    def variant(self) -> str:
+        v = lbm_lee_resolved_variant(self.h)
+        return {val: key for key, val in VARIANTS.items()}[v]
 
     @property
     def bytes_per_update(self) -> float:
