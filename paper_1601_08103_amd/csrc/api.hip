@@ -326,7 +326,9 @@ lbm_status lbm_lee_init(const lbm_lee_desc *desc, void *pop_a, void *pop_b, size
     h->cus = 0;
     {
         int dev = 0;
-        if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            h->cus = 0;  // persistent launches then fall back to the full grid
         (void)hipGetLastError();
     }
     hipStream_t st = static_cast<hipStream_t>(stream);

@@ -234,9 +234,15 @@ __global__ __launch_bounds__(256) void nrbc_forward_kernel(const float *__restri
 
 // ------------------------------------------------------------------ loss and gradients
 // Each wave accumulates the gradients of its tiles in registers and writes one partial row
-// (NPARAM gradient values + its squared-error sum) to ws[wave]; nrbc_reduce_kernel sums the
+// (NPARAM gradient values, then its squared-error sum) to ws[wave]; nrbc_reduce_kernel sums the
 // rows in a fixed order.  Targets are raw; they are divided by the strip's rms like the
 // prediction.  Loss = mean over samples and outputs of (y - t / s)^2.
+//   dy  = 2 (y - t/s) / (count k)                       (bf16)
+//   dW3 = h2^T dy,  db3 = 1^T dy,   dh2 = dy W3^T,  da2 = dh2 [h2 > 0]   (bf16)
+//   dW2 = h1^T da2, db2 = 1^T da2,  dh1 = da2 W2^T, da1 = dh1 [h1 > 0]   (bf16)
+//   dW1 = z^T da1,  db1 = 1^T da1
+// Column sums use a product with an all-ones bf16 operand, so they are summed in FP32 exactly
+// like the weight gradients.
 template <class VS>
 __global__ __launch_bounds__(256) void nrbc_grad_kernel(const float *__restrict__ P, const float *__restrict__ strips,
                                                         const float *__restrict__ targets, long long count,
@@ -247,12 +253,12 @@ __global__ __launch_bounds__(256) void nrbc_grad_kernel(const float *__restrict_
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     WaveTiles &T = tiles[wid];
     const int row0 = 4 * (lane >> 4), col = lane & 15;
-    const float inv_n = 1.0f / (float)((double)count * G::NOUT);
+    const float inv_n = (float)(1.0 / ((double)count * G::NOUT));
     bf16x4 ones;
     ones.x = ones.y = ones.z = ones.w = (short)0x3f80;  // bf16 1.0
+    const floatx4 zero = {0, 0, 0, 0};
 
     floatx4 g1[MT1][4], g2[4][4], g3[4], gb1[4], gb2[4], gb3;
-    const floatx4 zero = {0, 0, 0, 0};
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
@@ -273,7 +279,6 @@ __global__ __launch_bounds__(256) void nrbc_grad_kernel(const float *__restrict_
         const float s = load_normalised_tile<VS>(T, nrows, lane,
                                                  [&](int r, int v) { return strips[(base + r) * G::NIN + v]; });
         const floatx4 y = net_forward_tile<VS>(P, T, lane);
-        // output gradient dy = 2 (y - t/s) / (count k), rows beyond the batch are zero
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int row = row0 + e;
@@ -288,22 +293,115 @@ __global__ __launch_bounds__(256) void nrbc_grad_kernel(const float *__restrict_
             T.dy[row][col] = bf16_bits(d);
         }
         wave_lds_sync();
-        // W3, b3:  dW3 += h2^T dy,  db3 += 1^T dy
+        // layer 3
+        const bf16x4 bdy = b_rows<16>(T.dy, 0, lane);
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) g3[mt] = mfma16(a_cols<64>(T.h2, mt, lane), b_rows<16>(T.dy, 0, lane), g3[mt]);
-        gb3 = mfma16(ones, b_rows<16>(T.dy, 0, lane), gb3);
-        // dh2 = dy W3^T, da2 = dh2 * (h2 > 0)
+        for (int mt = 0; mt < 4; ++mt) g3[mt] = mfma16(a_cols<64>(T.h2, mt, lane), bdy, g3[mt]);
+        gb3 = mfma16(ones, bdy, gb3);
+        {
+            bf16x4 ady;  // A = dy (rows = samples, k = outputs 0..15)
+            const int i = lane & 15, k0 = 4 * (lane >> 4);
+            ady.x = (short)T.dy[i][k0]; ady.y = (short)T.dy[i][k0 + 1];
+            ady.z = (short)T.dy[i][k0 + 2]; ady.w = (short)T.dy[i][k0 + 3];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const floatx4 dh = mfma16(ady, b_weight_t(P + G::OFF_W3, kHidden, G::NOUT, 0, nt, lane), zero);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = row0 + e, c = nt * 16 + col;
+                    T.da2[row][c] = bf16_bits(T.h2[row][c] != 0 ? dh[e] : 0.0f);
+                }
+            }
+        }
+        wave_lds_sync();
+        // layer 2
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-            floatx4 acc = mfma16(a_rows(reinterpret_cast<const unsigned short (*)[64]>(nullptr) == nullptr
-                                            ? nullptr : nullptr, 0, lane), b_weight_t(P + G::OFF_W3, kHidden, G::NOUT, 0, nt, lane), zero);
-            (void)acc;
+            const bf16x4 bda = b_rows<64>(T.da2, nt, lane);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) g2[mt][nt] = mfma16(a_cols<64>(T.h1, mt, lane), bda, g2[mt][nt]);
+            gb2[nt] = mfma16(ones, bda, gb2[nt]);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            floatx4 dh = zero;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                dh = mfma16(a_rows(T.da2, kk, lane), b_weight_t(P + G::OFF_W2, kHidden, kHidden, kk, nt, lane), dh);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = row0 + e, c = nt * 16 + col;
+                T.da1[row][c] = bf16_bits(T.h1[row][c] != 0 ? dh[e] : 0.0f);
+            }
+        }
+        wave_lds_sync();
+        // layer 1
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const bf16x4 bda = b_rows<64>(T.da1, nt, lane);
+#pragma unroll
+            for (int mt = 0; mt < MT1; ++mt) g1[mt][nt] = mfma16(a_cols<64>(T.z, mt, lane), bda, g1[mt][nt]);
+            gb1[nt] = mfma16(ones, bda, gb1[nt]);
         }
         wave_lds_sync();
     }
-    (void)sq;
-    (void)gb1; (void)gb2; (void)g1; (void)g2;
-    (void)ws;
+    // partial row of this wave: C layout element (row = 4 (l/16) + e, col = l % 16)
+    float *out = ws + (size_t)(blockIdx.x * 4 + wid) * (G::NPARAM + 1);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int r = row0 + e;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int c = nt * 16 + col;
+#pragma unroll
+            for (int mt = 0; mt < MT1; ++mt) {
+                const int in = mt * 16 + r;
+                if (in < G::NIN) out[G::OFF_W1 + in * kHidden + c] = g1[mt][nt][e];
+            }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) out[G::OFF_W2 + (mt * 16 + r) * kHidden + c] = g2[mt][nt][e];
+            if (r == 0) {
+                out[G::OFF_B1 + c] = gb1[nt][e];
+                out[G::OFF_B2 + c] = gb2[nt][e];
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            if (col < G::NOUT) out[G::OFF_W3 + (mt * 16 + r) * G::NOUT + col] = g3[mt][e];
+        if (r == 0 && col < G::NOUT) out[G::OFF_B3 + col] = gb3[e];
+    }
+    // squared-error sum of the wave (lanes hold disjoint elements)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off, 64);
+    if (lane == 0) out[G::NPARAM] = sq;
+}
+
+// grad[p] = sum over waves of ws[w][p] (fixed order); loss = sum of the squared errors / (count k).
+__global__ __launch_bounds__(256) void nrbc_reduce_kernel(const float *__restrict__ ws, int nwaves, int nparam,
+                                                          long long count, int nout, float *__restrict__ grad,
+                                                          float *__restrict__ loss) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p > nparam) return;
+    double acc = 0.0;
+    for (int w = 0; w < nwaves; ++w) acc += (double)ws[(size_t)w * (nparam + 1) + p];
+    if (p < nparam)
+        grad[p] = (float)acc;
+    else if (loss)
+        *loss = (float)(acc / ((double)count * nout));
+}
+
+// Adam (Kingma & Ba) on FP32 master parameters; t counts from 1.
+__global__ __launch_bounds__(256) void nrbc_adam_kernel(long long n, float *__restrict__ P, const float *__restrict__ g,
+                                                        float *__restrict__ m, float *__restrict__ v, float lr,
+                                                        float b1, float b2, float eps, float c1, float c2) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
 }  // namespace lbm
