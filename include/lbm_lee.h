@@ -74,6 +74,21 @@ typedef int32_t lbm_status;
 #define LBM_TUNE_NT_LOAD 2   /* non-temporal (streaming) loads                         */
 #define LBM_TUNE_PERSISTENT 4 /* grid sized to the resident wave slots, grid-stride loop */
 
+/* Boundary of the box.  The paper's scheme is periodic; the open closures are not in the
+ * paper (it leaves boundary conditions to future work) and are defined here.  For a cell x
+ * whose population i streams from s = x - c_i outside the box:
+ *   ZERO    the streamed value is 0 (the exterior is at rest);
+ *   COPY    the value at clamp(s), the nearest cell of the box (zero normal gradient);
+ *   SPONGE  as ZERO, and after the collision the state is damped by
+ *           1 - sponge_sigma ((W - d) / W)^2 at distance d < W = sponge_width from the faces;
+ *   MLP     a learned prediction (lbm_lee_set_closure) for the face node clamp(s); for a source
+ *           beyond an edge or corner, the mean of the predictions of every face it lies beyond. */
+#define LBM_BC_PERIODIC 0
+#define LBM_BC_ZERO 1
+#define LBM_BC_COPY 2
+#define LBM_BC_SPONGE 3
+#define LBM_BC_MLP 4
+
 /* Step kernel variant.  All variants run the same per-cell arithmetic, so their results are
  * bitwise identical; they differ only in how the streamed values are gathered. */
 #define LBM_VARIANT_AUTO 0    /* the fastest measured variant for the storage mode          */
@@ -93,6 +108,9 @@ typedef struct lbm_lee_desc {
     double store_scale;  /* S for F16/BF16/I16: 0 = choose from the initial state so that   */
                          /* max |S g / f*| lies in [1/2, 1) (F16/BF16) or [2^13, 2^14)      */
                          /* (I16); otherwise a power of two > 0.  Ignored for F64/F32.     */
+    int32_t bc;          /* LBM_BC_*; open boxes need n[a] >= 3 on every axis a < D         */
+    int32_t sponge_width;/* LBM_BC_SPONGE: layer width W >= 1 in cells                      */
+    double sponge_sigma; /* LBM_BC_SPONGE: sigma_max in [0, 1]                              */
 } lbm_lee_desc;
 
 typedef struct lbm_lattice_info {
@@ -187,6 +205,74 @@ int32_t lbm_lee_resolved_variant(lbm_lee_handle h);
 
 /* Free the handle (host memory only; device buffers stay with the caller). NULL is a no-op. */
 void lbm_lee_destroy(lbm_lee_handle h);
+
+/* Bytes of the caller-owned ghost buffer an LBM_BC_MLP handle needs: one FP32 value per
+ * entering population per face node.  0 for other boundaries or a bad desc. */
+size_t lbm_lee_ghost_bytes(const lbm_lee_desc *desc);
+
+/* Attach the closure network (device FP32 parameters, layout of lbm_nrbc_dims) and the ghost
+ * buffer to an LBM_BC_MLP handle.  The library keeps the pointers; the caller keeps both
+ * buffers alive and may update the parameters between steps.  Steps fail with LBM_E_STATE
+ * until this has been called. */
+lbm_status lbm_lee_set_closure(lbm_lee_handle h, const float *params, void *ghost, size_t ghost_bytes);
+
+/*
+ * Learned non-reflecting closure network (not in the paper).  Input: the strip of
+ * post-collision populations at a face node, 3 cells deep along the inward normal, in the
+ * canonical face frame (outward normal -x), m-major: x[m * Q + j]; output: the populations
+ * entering through the face (canonical c_x = +1, in canonical order).  Network:
+ *   s = rms(x), z = x / s, h1 = relu(z W1 + b1), h2 = relu(h1 W2 + b2), y = h2 W3 + b3, out = s y.
+ * FP32 parameters, row-major, concatenated: W1[n_in][64], b1[64], W2[64][64], b2[64],
+ * W3[64][n_out], b3[n_out].  Every product runs on matrix cores with bfloat16 inputs (round to
+ * nearest even) and FP32 accumulation.
+ */
+/* dims = { n_in = 3 Q, n_out, hidden = 64, n_params }. */
+lbm_status lbm_nrbc_dims(int32_t lattice, int32_t dims[4]);
+
+/* Number of face nodes of a box (the id range of lbm_nrbc_gather): faces in the order
+ * (x low, x high, y low, y high, z low, z high), nodes over the two in-face axes (ascending,
+ * the lower axis fastest).  -1 on a bad desc. */
+int64_t lbm_nrbc_face_nodes(const lbm_lee_desc *box);
+
+/* Inference on `count` strips (device FP32 [count][n_in]) -> out (device FP32 [count][n_out]). */
+lbm_status lbm_nrbc_forward(int32_t lattice, const float *params, const float *strips, int64_t count, float *out,
+                            void *stream);
+
+/* Workspace bytes of lbm_nrbc_loss_grad for a batch of `count` samples. */
+size_t lbm_nrbc_workspace_bytes(int32_t lattice, int64_t count);
+
+/*
+ * Mean squared error of the network on a batch, in normalised units:
+ *   loss = mean over samples and outputs of (y - target / s)^2,
+ * and its gradient with respect to every parameter (device FP32, n_params values).
+ * `loss` (device, one float) may be NULL.  Deterministic (fixed reduction order).
+ */
+lbm_status lbm_nrbc_loss_grad(int32_t lattice, const float *params, const float *strips, const float *targets,
+                              int64_t count, float *grad, float *loss, void *workspace, size_t workspace_bytes,
+                              void *stream);
+
+/* One Adam step (Kingma & Ba) on n FP32 parameters: m, v are the moment buffers, t >= 1. */
+lbm_status lbm_nrbc_adam(int64_t n, float *params, const float *grad, float *m, float *v, int64_t t, float lr,
+                         float beta1, float beta2, float eps, void *stream);
+
+/*
+ * Training pairs from a larger (e.g. periodic, three times wider) run `outer` whose cell
+ * origin + x corresponds to cell x of the box `inner` (origin >= 1 and origin + n + 1 <= outer n
+ * on every axis): for each face node id of the inner box (device int64 ids), the strip at the
+ * node (strips [count][n_in]) and the true entering populations, i.e. the outer state at the
+ * node's outside neighbour (targets [count][n_out]), physical FP32 values.
+ */
+lbm_status lbm_nrbc_gather(lbm_lee_handle outer, const int64_t origin[3], const lbm_lee_desc *inner,
+                           const int64_t *node_ids, int64_t count, float *strips, float *targets, void *stream);
+
+/*
+ * Compare a field a of a box (n_a[3] cells, device FP64) with the field b of a larger box
+ * (n_b[3]) at cell offset origin: out = { sum (a - b)^2, sum b^2, max |a - b| }.
+ * scratch as for lbm_lee_init.  SYNCHRONISES the stream.
+ */
+lbm_status lbm_lee_compare_fields(const double *a, const int64_t n_a[3], const double *b, const int64_t n_b[3],
+                                  const int64_t origin[3], double out[3], void *scratch, size_t scratch_bytes,
+                                  void *stream);
 
 /* Plain device-to-device copy kernel (16-byte vectors): the reference point for bandwidth
  * and counter calibration.  bytes must be a multiple of 16, both pointers 16-byte aligned. */

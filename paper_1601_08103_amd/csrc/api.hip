@@ -1,6 +1,7 @@
 // C ABI of the LEE lattice Boltzmann library: argument checks, coefficient setup, dispatch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -10,6 +11,8 @@
 
 #include "../../include/lbm_lee.h"
 #include "kernels.hpp"
+#include "nrbc.hpp"
+#include "open_bc.hpp"
 #include "tables.hpp"
 
 using namespace lbm;
@@ -26,6 +29,8 @@ struct lbm_lee {
     size_t scratch_bytes;
     double S;  // storage scale (1 for F64/F32)
     int cus;   // compute units of the device (persistent launches)
+    const float *net;  // LBM_BC_MLP: closure parameters (caller-owned)
+    float *ghost;      // LBM_BC_MLP: ghost buffer (caller-owned)
 };
 
 namespace {
@@ -89,6 +94,14 @@ lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
     if (d->store_scale > 0.0) {
         int ex;
         if (std::frexp(d->store_scale, &ex) != 0.5) return fail(LBM_E_INVALID, "store_scale must be a power of two");
+    }
+    if (d->bc < LBM_BC_PERIODIC || d->bc > LBM_BC_MLP) return fail(LBM_E_INVALID, "unknown boundary %d", d->bc);
+    if (d->bc != LBM_BC_PERIODIC)
+        for (int a = 0; a < tab->D; ++a)
+            if (d->n[a] < 3) return fail(LBM_E_INVALID, "open boundaries need n[%d] >= 3", a);
+    if (d->bc == LBM_BC_SPONGE) {
+        if (d->sponge_width < 1) return fail(LBM_E_INVALID, "sponge_width must be >= 1");
+        if (!(d->sponge_sigma >= 0.0 && d->sponge_sigma <= 1.0)) return fail(LBM_E_INVALID, "sponge_sigma must lie in [0, 1]");
     }
     if (d->variant == LBM_VARIANT_DPP && d->n[0] % 4 != 0) return fail(LBM_E_UNSUPPORTED, "DPP variant needs nx %% 4 == 0");
     if (d->variant == LBM_VARIANT_DPP2 && d->n[0] % 2 != 0) return fail(LBM_E_UNSUPPORTED, "DPP2 variant needs nx %% 2 == 0");
@@ -174,6 +187,61 @@ StepCoef<CT, Q> step_coef(const lbm_lee *h) {
     k.c2 = split<CT>(f.c2);
     k.b_rho0 = split<CT>(f.b / f.rho0);
     return k;
+}
+
+// Face frames: negate axis a for the high side, then swap axis a with x, so the outward normal
+// becomes -x.  perm[f][j]: population whose transformed velocity is canonical velocity j.
+template <class VS>
+FaceTab<VS::Q> face_table(const LatticeTable &t, const int64_t n[3]) {
+    FaceTab<VS::Q> ft;
+    std::memset(&ft, 0, sizeof ft);
+    ft.D = t.D;
+    ft.nfaces = 2 * t.D;
+    for (int a = 0; a < 3; ++a) ft.n[a] = (int)n[a];
+    long long off = 0;
+    for (int f = 0; f < ft.nfaces; ++f) {
+        const int a = f >> 1, side = f & 1;
+        ft.node_off[f] = off;
+        long long cnt = 1;
+        for (int b = 0; b < t.D; ++b)
+            if (b != a) cnt *= n[b];
+        off += cnt;
+        for (int i = 0; i < VS::Q; ++i) ft.rank[f][i] = -1;
+        for (int i = 0; i < VS::Q; ++i) {
+            int c[3] = {t.c[i][0], t.c[i][1], t.c[i][2]};
+            if (side) c[a] = -c[a];
+            const int tmp = c[0];
+            c[0] = c[a];
+            c[a] = tmp;
+            for (int j = 0; j < VS::Q; ++j)
+                if (t.c[j][0] == c[0] && t.c[j][1] == c[1] && t.c[j][2] == c[2]) ft.perm[f][j] = (signed char)i;
+        }
+        for (int r = 0; r < NetGeom<VS>::NOUT; ++r) ft.rank[f][ft.perm[f][entering_index<VS>(r)]] = (signed char)r;
+    }
+    for (int f = ft.nfaces; f < 7; ++f) ft.node_off[f] = off;
+    return ft;
+}
+
+int64_t face_node_count(const LatticeTable &t, const int64_t n[3]) {
+    int64_t total = 0;
+    for (int a = 0; a < t.D; ++a) {
+        int64_t cnt = 1;
+        for (int b = 0; b < t.D; ++b)
+            if (b != a) cnt *= n[b];
+        total += 2 * cnt;
+    }
+    return total;
+}
+
+int net_outputs(const LatticeTable &t) {
+    int k = 0;
+    for (int i = 0; i < t.Q; ++i) k += t.c[i][0] == 1 ? 1 : 0;
+    return k;
+}
+
+int64_t net_params(const LatticeTable &t) {
+    const int64_t nin = 3 * t.Q, nout = net_outputs(t);
+    return nin * kHidden + kHidden + kHidden * kHidden + kHidden + kHidden * nout + nout;
 }
 
 unsigned blocks_for(size_t n) { return (unsigned)((n + 255) / 256); }
@@ -324,6 +392,8 @@ lbm_status lbm_lee_init(const lbm_lee_desc *desc, void *pop_a, void *pop_b, size
     h->scratch_bytes = scratch_bytes;
     h->S = 1.0;
     h->cus = 0;
+    h->net = nullptr;
+    h->ghost = nullptr;
     {
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -354,6 +424,9 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
     if (nsteps < 0) return fail(LBM_E_INVALID, "nsteps must be >= 0");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int variant = resolve_variant(h);
+    const int bc = h->desc.bc;
+    if (bc == LBM_BC_MLP && (!h->net || !h->ghost))
+        return fail(LBM_E_STATE, "an LBM_BC_MLP handle needs lbm_lee_set_closure before stepping");
     lbm_status s = visit(h->desc.lattice, h->desc.storage, [&](auto vs, auto sto) -> lbm_status {
         using VS = decltype(vs);
         using ST = decltype(sto);
@@ -379,9 +452,28 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
         }
         const int lds_cpr = (h->nx + 255) / 256;
         const unsigned lds_blocks = (unsigned)((size_t)h->ny * h->nz * lds_cpr);
+        FaceTab<VS::Q> ft;
+        FieldCoef<VS::Q> fk;
+        unsigned shell_x = 1, ghost_blocks = 1;
+        if (bc != LBM_BC_PERIODIC) {
+            ft = face_table<VS>(h->tab, h->desc.n);
+            fk = field_coef<VS::Q>(h);
+            long long mx = 1;
+            for (int a = 0; a < VS::D; ++a) {
+                long long cnt = 1;
+                for (int b = 0; b < VS::D; ++b)
+                    if (b != a) cnt *= h->desc.n[b];
+                if (cnt > mx) mx = cnt;
+            }
+            shell_x = (unsigned)((mx + 255) / 256);
+            const long long tiles = (ft.node_off[ft.nfaces] + 15) / 16;
+            ghost_blocks = (unsigned)std::min<long long>((tiles + 3) / 4, 4096);
+        }
         for (int64_t t = 0; t < nsteps; ++t) {
             const E *src = static_cast<const E *>(h->buf[h->cur]);
             E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);
+            if (bc == LBM_BC_MLP)
+                ghost_mlp_kernel<VS, ST><<<ghost_blocks, 256, 0, st>>>(src, h->N, h->net, h->ghost, ft, fk);
             if (variant == LBM_VARIANT_GENERIC) {
                 step_generic<VS, ST><<<blocks_for(h->N), 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, k);
             } else if (variant == LBM_VARIANT_LDS) {
@@ -396,6 +488,13 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
                     step_dpp<VS, ST, 2, true><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr, waves, tune, k);
                 else
                     step_dpp<VS, ST, 2, false><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr, waves, tune, k);
+            }
+            if (bc != LBM_BC_PERIODIC) {
+                shell_kernel<VS, ST><<<dim3(shell_x, 2 * VS::D), 256, 0, st>>>(src, dst, h->N, bc, h->ghost, ft, k, fk);
+                if (bc == LBM_BC_SPONGE)
+                    sponge_kernel<VS, ST><<<blocks_for(h->N), 256, 0, st>>>(dst, h->N, h->nx, h->ny, h->nz,
+                                                                          h->desc.sponge_width,
+                                                                          h->desc.sponge_sigma);
             }
             lbm_status ls = launch_check();
             if (ls != LBM_OK) return ls;
@@ -513,6 +612,149 @@ double lbm_lee_store_scale(lbm_lee_handle h) { return h ? h->S : 0.0; }
 int32_t lbm_lee_resolved_variant(lbm_lee_handle h) { return h ? resolve_variant(h) : -1; }
 
 void lbm_lee_destroy(lbm_lee_handle h) { delete h; }
+
+size_t lbm_lee_ghost_bytes(const lbm_lee_desc *d) {
+    LatticeTable t;
+    if (check_desc(d, &t) != LBM_OK || d->bc != LBM_BC_MLP) return 0;
+    return (size_t)face_node_count(t, d->n) * (size_t)net_outputs(t) * sizeof(float);
+}
+
+lbm_status lbm_lee_set_closure(lbm_lee_handle h, const float *params, void *ghost, size_t ghost_bytes) {
+    if (!h) return fail(LBM_E_INVALID, "handle is NULL");
+    if (h->desc.bc != LBM_BC_MLP) return fail(LBM_E_STATE, "the handle's boundary is not LBM_BC_MLP");
+    if (!params || !ghost) return fail(LBM_E_INVALID, "params and ghost must not be NULL");
+    if (ghost_bytes < lbm_lee_ghost_bytes(&h->desc)) return fail(LBM_E_INVALID, "ghost buffer too small");
+    if (reinterpret_cast<uintptr_t>(params) & 3 || reinterpret_cast<uintptr_t>(ghost) & 3)
+        return fail(LBM_E_INVALID, "params and ghost must be 4-byte aligned");
+    h->net = params;
+    h->ghost = static_cast<float *>(ghost);
+    return ok();
+}
+
+lbm_status lbm_nrbc_dims(int32_t lattice, int32_t dims[4]) {
+    LatticeTable t;
+    if (!dims) return fail(LBM_E_INVALID, "dims is NULL");
+    if (!build_lattice(lattice, &t)) return fail(LBM_E_INVALID, "unknown lattice id %d", lattice);
+    dims[0] = 3 * t.Q;
+    dims[1] = net_outputs(t);
+    dims[2] = kHidden;
+    dims[3] = (int32_t)net_params(t);
+    return ok();
+}
+
+int64_t lbm_nrbc_face_nodes(const lbm_lee_desc *d) {
+    LatticeTable t;
+    if (check_desc(d, &t) != LBM_OK) return -1;
+    return face_node_count(t, d->n);
+}
+
+namespace {
+constexpr int kNetGrid = 256;  // blocks of the gradient kernel: 1024 partial rows
+}
+
+size_t lbm_nrbc_workspace_bytes(int32_t lattice, int64_t count) {
+    LatticeTable t;
+    if (!build_lattice(lattice, &t) || count < 0) return 0;
+    (void)count;
+    return (size_t)kNetGrid * 4 * (size_t)(net_params(t) + 1) * sizeof(float);
+}
+
+lbm_status lbm_nrbc_forward(int32_t lattice, const float *params, const float *strips, int64_t count, float *out,
+                            void *stream) {
+    if (!params || !strips || !out || count < 0) return fail(LBM_E_INVALID, "bad arguments");
+    if (count == 0) return ok();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const long long tiles = (count + 15) / 16;
+    const unsigned grid = (unsigned)std::min<long long>((tiles + 3) / 4, 4096);
+    lbm_status s = visit(lattice, LBM_F32, [&](auto vs, auto) -> lbm_status {
+        using VS = decltype(vs);
+        nrbc_forward_kernel<VS><<<grid, 256, 0, st>>>(params, strips, count, out);
+        return launch_check();
+    });
+    return s == LBM_OK ? ok() : s;
+}
+
+lbm_status lbm_nrbc_loss_grad(int32_t lattice, const float *params, const float *strips, const float *targets,
+                              int64_t count, float *grad, float *loss, void *workspace, size_t workspace_bytes,
+                              void *stream) {
+    if (!params || !strips || !targets || !grad || !workspace || count <= 0)
+        return fail(LBM_E_INVALID, "bad arguments");
+    if (workspace_bytes < lbm_nrbc_workspace_bytes(lattice, count)) return fail(LBM_E_INVALID, "workspace too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    lbm_status s = visit(lattice, LBM_F32, [&](auto vs, auto) -> lbm_status {
+        using VS = decltype(vs);
+        using G = NetGeom<VS>;
+        float *ws = static_cast<float *>(workspace);
+        nrbc_grad_kernel<VS><<<kNetGrid, 256, 0, st>>>(params, strips, targets, count, ws);
+        lbm_status ls = launch_check();
+        if (ls != LBM_OK) return ls;
+        nrbc_reduce_kernel<<<(G::NPARAM + 1 + 255) / 256, 256, 0, st>>>(ws, kNetGrid * 4, G::NPARAM, count, G::NOUT,
+                                                                       grad, loss);
+        return launch_check();
+    });
+    return s == LBM_OK ? ok() : s;
+}
+
+lbm_status lbm_nrbc_adam(int64_t n, float *params, const float *grad, float *m, float *v, int64_t t, float lr,
+                         float beta1, float beta2, float eps, void *stream) {
+    if (!params || !grad || !m || !v || n <= 0 || t < 1) return fail(LBM_E_INVALID, "bad arguments");
+    const float c1 = (float)(1.0 - std::pow((double)beta1, (double)t));
+    const float c2 = (float)(1.0 - std::pow((double)beta2, (double)t));
+    nrbc_adam_kernel<<<(unsigned)((n + 255) / 256), 256, 0, static_cast<hipStream_t>(stream)>>>(
+        n, params, grad, m, v, lr, beta1, beta2, eps, c1, c2);
+    lbm_status s = launch_check();
+    return s == LBM_OK ? ok() : s;
+}
+
+lbm_status lbm_nrbc_gather(lbm_lee_handle outer, const int64_t origin[3], const lbm_lee_desc *inner,
+                           const int64_t *node_ids, int64_t count, float *strips, float *targets, void *stream) {
+    if (!outer || !origin || !inner || !node_ids || !strips || !targets || count < 0)
+        return fail(LBM_E_INVALID, "bad arguments");
+    LatticeTable t;
+    lbm_status s = check_desc(inner, &t);
+    if (s != LBM_OK) return s;
+    if (inner->lattice != outer->desc.lattice) return fail(LBM_E_INVALID, "inner and outer lattices differ");
+    for (int a = 0; a < t.D; ++a)
+        if (origin[a] < 1 || origin[a] + inner->n[a] + 1 > outer->desc.n[a] || inner->n[a] < 3)
+            return fail(LBM_E_INVALID, "inner box (axis %d) must sit inside the outer box with one cell to spare", a);
+    if (count == 0) return ok();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    s = visit(outer->desc.lattice, outer->desc.storage, [&](auto vs, auto sto) -> lbm_status {
+        using VS = decltype(vs);
+        using ST = decltype(sto);
+        const auto ft = face_table<VS>(t, inner->n);
+        const auto fk = field_coef<VS::Q>(outer);
+        const auto *src = static_cast<const typename ST::elem *>(outer->buf[outer->cur]);
+        gather_pairs_kernel<VS, ST><<<blocks_for((size_t)count), 256, 0, st>>>(
+            src, outer->N, outer->nx, outer->ny, (int)origin[0], (int)(t.D > 1 ? origin[1] : 0),
+            (int)(t.D > 2 ? origin[2] : 0), reinterpret_cast<const long long *>(node_ids), count, strips, targets, ft,
+            fk);
+        return launch_check();
+    });
+    return s == LBM_OK ? ok() : s;
+}
+
+lbm_status lbm_lee_compare_fields(const double *a, const int64_t n_a[3], const double *b, const int64_t n_b[3],
+                                  const int64_t origin[3], double out[3], void *scratch, size_t scratch_bytes,
+                                  void *stream) {
+    if (!a || !n_a || !b || !n_b || !origin || !out || !scratch) return fail(LBM_E_INVALID, "bad arguments");
+    if (scratch_bytes < kScratchBytes || !aligned256(scratch)) return fail(LBM_E_INVALID, "scratch too small or misaligned");
+    for (int d = 0; d < 3; ++d)
+        if (n_a[d] < 1 || origin[d] < 0 || origin[d] + n_a[d] > n_b[d] || n_a[d] > (1 << 30) || n_b[d] > (1 << 30))
+            return fail(LBM_E_INVALID, "box a must lie inside box b (axis %d)", d);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *part = static_cast<double *>(scratch);
+    double *res = part + 6 * kReduceBlocks;
+    compare_partials<<<kReduceBlocks, 256, 0, st>>>(a, (int)n_a[0], (int)n_a[1], (int)n_a[2], b, (int)n_b[0],
+                                                    (int)n_b[1], (int)origin[0], (int)origin[1], (int)origin[2], part);
+    lbm_status s = launch_check();
+    if (s != LBM_OK) return s;
+    reduce_partials<3><<<1, 256, 0, st>>>(part, kReduceBlocks, res, 1u << 2);
+    if ((s = launch_check()) != LBM_OK) return s;
+    LBM_HIP(hipMemcpyAsync(out, res, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    LBM_HIP(hipStreamSynchronize(st));
+    return ok();
+}
 
 lbm_status lbm_lee_device_copy(void *dst, const void *src, size_t bytes, void *stream) {
     if (!dst || !src) return fail(LBM_E_INVALID, "NULL pointer");

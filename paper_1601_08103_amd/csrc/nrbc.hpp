@@ -309,7 +309,7 @@ __global__ __launch_bounds__(256) void nrbc_grad_kernel(const float *__restrict_
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int row = row0 + e, c = nt * 16 + col;
-                    T.da2[row][c] = bf16_bits(T.h2[row][c] != 0 ? dh[e] : 0.0f);
+                    T.da2[row][c] = bf16_bits(bf16_val(T.h2[row][c]) > 0.0f ? dh[e] : 0.0f);
                 }
             }
         }
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void nrbc_grad_kernel(const float *__restrict_
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int row = row0 + e, c = nt * 16 + col;
-                T.da1[row][c] = bf16_bits(T.h1[row][c] != 0 ? dh[e] : 0.0f);
+                T.da1[row][c] = bf16_bits(bf16_val(T.h1[row][c]) > 0.0f ? dh[e] : 0.0f);
             }
         }
         wave_lds_sync();

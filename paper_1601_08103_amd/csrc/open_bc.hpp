@@ -1,0 +1,268 @@
+// Open (non-periodic) boundaries of the box.  Not in the paper, which treats periodic
+// domains only and names boundary conditions as future work.
+//
+// One step on an open box: the bulk step kernel runs on every cell as if periodic, then the
+// shell kernel recomputes every boundary cell (a cell whose pull crosses a face), taking the
+// streamed value of a population whose source s = x - c_i lies outside from the closure:
+//   ZERO / SPONGE : 0 (exterior at rest);
+//   COPY          : the value at clamp(s) (zero normal gradient);
+//   MLP           : the learned prediction for the face node clamp(s) (mean over every face
+//                   the source lies beyond, for edge and corner sources).
+// SPONGE then damps the new post-collision state by 1 - sigma_max ((W - d) / W)^2 at distance
+// d < W from the nearest face.
+//
+// Face f = 2a + side (axis a, side 0 = low, 1 = high).  A signed axis permutation maps the
+// face's outward normal to -x; perm[f][j] is the population whose velocity maps to canonical
+// velocity j, and the populations entering through the face are the canonical ones with
+// c_x = +1 (rank r in canonical order).  Nodes of face f are its cells, numbered over the two
+// in-face axes (ascending, the lower one fastest); global node ids run face after face.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "codec.hpp"
+#include "kernels.hpp"
+#include "nrbc.hpp"
+#include "velsets.hpp"
+
+namespace lbm {
+
+enum : int { kBcPeriodic = 0, kBcZero = 1, kBcCopy = 2, kBcSponge = 3, kBcMlp = 4 };
+
+template <int Q>
+struct FaceTab {
+    int nfaces;
+    signed char perm[6][Q];  // canonical j -> face population
+    signed char rank[6][Q];  // face population -> entering rank, -1 if not entering
+    long long node_off[7];   // first global node of each face; node_off[nfaces] = total
+    int n[3];
+    int D;
+};
+
+// In-face axes of axis a (ascending); -1 when absent.
+__host__ __device__ inline void infaces(int a, int D, int &t1, int &t2) {
+    t1 = t2 = -1;
+    for (int b = 0; b < D; ++b)
+        if (b != a) {
+            if (t1 < 0)
+                t1 = b;
+            else
+                t2 = b;
+        }
+}
+
+template <int Q>
+__device__ inline long long node_index(const FaceTab<Q> &ft, int f, const int (&p)[3]) {
+    int t1, t2;
+    infaces(f >> 1, ft.D, t1, t2);
+    long long nd = 0;
+    if (t1 >= 0) nd = p[t1];
+    if (t2 >= 0) nd += (long long)ft.n[t1] * p[t2];
+    return ft.node_off[f] + nd;
+}
+
+template <int Q>
+__device__ inline int node_cell(const FaceTab<Q> &ft, long long g, int (&p)[3]) {
+    int f = 0;
+    while (f + 1 < ft.nfaces && g >= ft.node_off[f + 1]) ++f;
+    long long nd = g - ft.node_off[f];
+    const int a = f >> 1;
+    int t1, t2;
+    infaces(a, ft.D, t1, t2);
+    p[0] = p[1] = p[2] = 0;
+    if (t1 >= 0) {
+        p[t1] = (int)(nd % ft.n[t1]);
+        nd /= ft.n[t1];
+    }
+    if (t2 >= 0) p[t2] = (int)nd;
+    p[a] = (f & 1) ? ft.n[a] - 1 : 0;
+    return f;
+}
+
+// ------------------------------------------------------------------ shell recompute
+template <class VS, class ST>
+__global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__restrict__ src,
+                                                    typename ST::elem *__restrict__ dst, size_t N, int closure,
+                                                    const float *__restrict__ ghost, FaceTab<VS::Q> ft,
+                                                    StepCoef<typename ST::comp, VS::Q> k, FieldCoef<VS::Q> fk) {
+    using CT = typename ST::comp;
+    const int f = blockIdx.y;
+    const int a = f >> 1, side = f & 1;
+    int t1, t2;
+    infaces(a, VS::D, t1, t2);
+    // cells of this face not already owned by a face of a lower axis
+    const int lo1 = (t1 >= 0 && t1 < a) ? 1 : 0, lo2 = (t2 >= 0 && t2 < a) ? 1 : 0;
+    const int n1 = t1 >= 0 ? ft.n[t1] - 2 * lo1 : 1, n2 = t2 >= 0 ? ft.n[t2] - 2 * lo2 : 1;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long long)n1 * n2) return;
+    int x[3] = {0, 0, 0};
+    if (t1 >= 0) x[t1] = (int)(t % n1) + lo1;
+    if (t2 >= 0) x[t2] = (int)(t / n1) + lo2;
+    x[a] = side ? ft.n[a] - 1 : 0;
+    const size_t cell = ((size_t)x[2] * ft.n[1] + x[1]) * ft.n[0] + x[0];
+    constexpr int K = NetGeom<VS>::NOUT;
+
+    CT s[VS::Q];
+#pragma unroll
+    for (int i = 0; i < VS::Q; ++i) {
+        const int c[3] = {VS::cx(i), VS::cy(i), VS::cz(i)};
+        int sp[3], cl[3];
+        bool inside = true;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            sp[b] = x[b] - c[b];
+            cl[b] = min(max(sp[b], 0), ft.n[b] - 1);
+            inside = inside && sp[b] == cl[b];
+        }
+        const size_t scell = ((size_t)cl[2] * ft.n[1] + cl[1]) * ft.n[0] + cl[0];
+        CT v = 0;
+        if (inside || closure == kBcCopy) {
+            v = ST::dec(src[(size_t)i * N + scell]);
+        } else if (closure == kBcMlp) {
+            float acc = 0.0f;
+            int cnt = 0;
+#pragma unroll
+            for (int b = 0; b < VS::D; ++b) {
+                if (sp[b] != cl[b]) {
+                    const int fb = 2 * b + (sp[b] > cl[b] ? 1 : 0);
+                    const int r = ft.rank[fb][i];
+                    acc += ghost[node_index(ft, fb, cl) * K + (r < 0 ? 0 : r)];
+                    ++cnt;
+                }
+            }
+            v = (CT)(fk.enc[i] * (double)(acc / (float)cnt));
+        }
+        s[i] = v;
+    }
+    collide<VS, CT, split_constants<ST>()>(k, s);
+#pragma unroll
+    for (int i = 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
+}
+
+// ------------------------------------------------------------------ sponge damping
+template <class VS, class ST>
+__global__ __launch_bounds__(256) void sponge_kernel(typename ST::elem *__restrict__ g, size_t N, int nx, int ny,
+                                                     int nz, int width, double sigma_max) {
+    using CT = typename ST::comp;
+    const size_t cell = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (cell >= N) return;
+    const int x = (int)(cell % nx);
+    const size_t r = cell / nx;
+    const int y = (int)(r % ny), z = (int)(r / ny);
+    int d = min(x, nx - 1 - x);
+    if (VS::D >= 2) d = min(d, min(y, ny - 1 - y));
+    if (VS::D >= 3) d = min(d, min(z, nz - 1 - z));
+    if (d >= width) return;
+    const CT w = (CT)(width - d) / (CT)width;
+    const CT fac = (CT)1 - (CT)sigma_max * w * w;
+#pragma unroll
+    for (int i = 0; i < VS::Q; ++i) {
+        typename ST::elem *p = g + (size_t)i * N + cell;
+        *p = ST::enc(ST::dec(*p) * fac);
+    }
+}
+
+// ------------------------------------------------------------------ network ghosts
+// Every face node: strip (3 cells x Q populations, canonical order, physical units) ->
+// network -> the K entering populations (physical units) into ghost[node * K + r].
+template <class VS, class ST>
+__global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem *__restrict__ src, size_t N,
+                                                        const float *__restrict__ P, float *__restrict__ ghost,
+                                                        FaceTab<VS::Q> ft, FieldCoef<VS::Q> fk) {
+    using G = NetGeom<VS>;
+    __shared__ WaveTiles tiles[4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    WaveTiles &T = tiles[wid];
+    const long long count = ft.node_off[ft.nfaces];
+    const long long ntiles = (count + 15) / 16;
+    for (long long tile = (long long)blockIdx.x * 4 + wid; tile < ntiles; tile += (long long)gridDim.x * 4) {
+        const long long base = tile * 16;
+        const int nrows = (int)min((long long)16, count - base);
+        // the node of this lane's row
+        int p[3];
+        const int r = lane & 15;
+        const int f = node_cell(ft, base + (r < nrows ? r : 0), p);
+        const int a = f >> 1, step = (f & 1) ? -1 : 1;
+        const float s = load_normalised_tile<VS>(T, nrows, lane, [&](int, int v) {
+            const int m = v / VS::Q, j = v - m * VS::Q;
+            int q[3] = {p[0], p[1], p[2]};
+            q[a] += m * step;
+            const size_t cell = ((size_t)q[2] * ft.n[1] + q[1]) * ft.n[0] + q[0];
+            const int i = ft.perm[f][j];
+            return (float)(fk.dec[i] * (double)ST::dec(src[(size_t)i * N + cell]));
+        });
+        const floatx4 y = net_forward_tile<VS>(P, T, lane);
+        const int col = lane & 15;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = 4 * (lane >> 4) + e;
+            const float srow = __shfl(s, row, 64);
+            if (row < nrows && col < G::NOUT) ghost[(base + row) * G::NOUT + col] = srow * y[e];
+        }
+        wave_lds_sync();
+    }
+}
+
+// ------------------------------------------------------------------ training pairs
+// For inner-box face nodes (ids in the inner box's numbering), read the state of a larger
+// run whose cell origin + x is inner cell x: the strip at the node (inputs) and the
+// entering populations at the node's outside neighbour (targets), physical units.
+template <class VS, class ST>
+__global__ __launch_bounds__(256) void gather_pairs_kernel(const typename ST::elem *__restrict__ src, size_t N,
+                                                           int onx, int ony, int ox, int oy, int oz,
+                                                           const long long *__restrict__ ids, long long count,
+                                                           float *__restrict__ strips, float *__restrict__ targets,
+                                                           FaceTab<VS::Q> ft, FieldCoef<VS::Q> fk) {
+    using G = NetGeom<VS>;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= count) return;
+    int p[3];
+    const int f = node_cell(ft, ids[t], p);
+    const int a = f >> 1, step = (f & 1) ? -1 : 1;
+    const int o[3] = {ox, oy, oz};
+    auto outer_cell = [&](const int (&q)[3]) {
+        return ((size_t)(q[2] + o[2]) * ony + (q[1] + o[1])) * onx + (q[0] + o[0]);
+    };
+    for (int m = 0; m < 3; ++m) {
+        int q[3] = {p[0], p[1], p[2]};
+        q[a] += m * step;
+        const size_t cell = outer_cell(q);
+        for (int j = 0; j < VS::Q; ++j) {
+            const int i = ft.perm[f][j];
+            strips[t * G::NIN + m * VS::Q + j] = (float)(fk.dec[i] * (double)ST::dec(src[(size_t)i * N + cell]));
+        }
+    }
+    int q[3] = {p[0], p[1], p[2]};
+    q[a] -= step;  // the outside neighbour
+    const size_t gcell = outer_cell(q);
+    for (int r = 0; r < G::NOUT; ++r) {
+        const int i = ft.perm[f][entering_index<VS>(r)];
+        targets[t * G::NOUT + r] = (float)(fk.dec[i] * (double)ST::dec(src[(size_t)i * N + gcell]));
+    }
+}
+
+// ------------------------------------------------------------------ field comparison
+// Partials of { sum (a - b)^2, sum b^2, max |a - b| } of a box field a against field b of a
+// larger box at offset origin.
+__global__ __launch_bounds__(256) void compare_partials(const double *__restrict__ A, int nx, int ny, int nz,
+                                                        const double *__restrict__ B, int bnx, int bny, int ox, int oy,
+                                                        int oz, double *__restrict__ part) {
+    double v[3] = {0, 0, 0};
+    const bool is_max[3] = {false, false, true};
+    const size_t N = (size_t)nx * ny * nz;
+    for (size_t cell = (size_t)blockIdx.x * 256 + threadIdx.x; cell < N; cell += (size_t)gridDim.x * 256) {
+        const int x = (int)(cell % nx);
+        const size_t r = cell / nx;
+        const int y = (int)(r % ny), z = (int)(r / ny);
+        const double b = B[((size_t)(z + oz) * bny + (y + oy)) * bnx + (x + ox)];
+        const double d = A[cell] - b;
+        v[0] += d * d;
+        v[1] += b * b;
+        v[2] = fmax(v[2], fabs(d));
+    }
+    block_reduce<3>(v, is_max);
+    if (threadIdx.x == 0)
+        for (int j = 0; j < 3; ++j) part[3 * blockIdx.x + j] = v[j];
+}
+
+}  // namespace lbm

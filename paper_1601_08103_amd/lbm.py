@@ -20,6 +20,7 @@ STORAGES = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "i16": 4}
 ELEM_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "i16": 2}
 TUNE = {"nt_store": 1, "nt_load": 2, "persistent": 4}
 VARIANTS = {"auto": 0, "generic": 1, "dpp": 2, "lds": 3, "dpp2": 4}
+BCS = {"periodic": 0, "zero": 1, "copy": 2, "sponge": 3, "mlp": 4}
 
 LBM_OK = 0
 
@@ -33,7 +34,8 @@ class LbmError(RuntimeError):
 class lbm_lee_desc(ctypes.Structure):
     _fields_ = [("lattice", ctypes.c_int32), ("storage", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
                 ("tau", ctypes.c_double), ("variant", ctypes.c_int32), ("tune", ctypes.c_int32),
-                ("store_scale", ctypes.c_double)]
+                ("store_scale", ctypes.c_double), ("bc", ctypes.c_int32), ("sponge_width", ctypes.c_int32),
+                ("sponge_sigma", ctypes.c_double)]
 
 
 class lbm_lattice_info(ctypes.Structure):
@@ -66,6 +68,21 @@ SIGNATURES = {
     "lbm_lee_resolved_variant": (ctypes.c_int32, [_VP]),
     "lbm_lee_destroy": (None, [_VP]),
     "lbm_lee_device_copy": (ctypes.c_int32, [_VP, _VP, ctypes.c_size_t, _VP]),
+    "lbm_lee_ghost_bytes": (ctypes.c_size_t, [_DESC_P]),
+    "lbm_lee_set_closure": (ctypes.c_int32, [_VP, _VP, _VP, ctypes.c_size_t]),
+    "lbm_nrbc_dims": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "lbm_nrbc_face_nodes": (ctypes.c_int64, [_DESC_P]),
+    "lbm_nrbc_forward": (ctypes.c_int32, [ctypes.c_int32, _VP, _VP, ctypes.c_int64, _VP, _VP]),
+    "lbm_nrbc_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int64]),
+    "lbm_nrbc_loss_grad": (ctypes.c_int32, [ctypes.c_int32, _VP, _VP, _VP, ctypes.c_int64, _VP, _VP, _VP,
+                                            ctypes.c_size_t, _VP]),
+    "lbm_nrbc_adam": (ctypes.c_int32, [ctypes.c_int64, _VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_float,
+                                       ctypes.c_float, ctypes.c_float, ctypes.c_float, _VP]),
+    "lbm_nrbc_gather": (ctypes.c_int32, [_VP, ctypes.POINTER(ctypes.c_int64), _DESC_P, _VP, ctypes.c_int64, _VP, _VP,
+                                         _VP]),
+    "lbm_lee_compare_fields": (ctypes.c_int32, [_VP, ctypes.POINTER(ctypes.c_int64), _VP,
+                                                ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                                ctypes.POINTER(ctypes.c_double), _VP, ctypes.c_size_t, _VP]),
     "lbm_lee_last_error": (ctypes.c_char_p, []),
     "lbm_lee_version": (ctypes.c_char_p, []),
 }
@@ -94,7 +111,8 @@ def _check(name, status):
 
 
 def make_desc(lattice: str, storage: str, shape, tau: float = 0.5, variant: str = "auto",
-              store_scale: float = 0.0, tune: int = 0) -> lbm_lee_desc:
+              store_scale: float = 0.0, tune: int = 0, bc: str = "periodic", sponge_width: int = 0,
+              sponge_sigma: float = 0.0) -> lbm_lee_desc:
     """Descriptor for a spatial shape given in C order ((nz, ny, nx), (ny, nx) or (nx,))."""
     dims = list(reversed([int(s) for s in shape])) + [1] * (3 - len(shape))
     d = lbm_lee_desc()
@@ -106,6 +124,9 @@ def make_desc(lattice: str, storage: str, shape, tau: float = 0.5, variant: str 
     d.variant = VARIANTS[variant]
     d.tune = int(tune)
     d.store_scale = float(store_scale)
+    d.bc = BCS[bc]
+    d.sponge_width = int(sponge_width)
+    d.sponge_sigma = float(sponge_sigma)
     return d
 
 
@@ -194,6 +215,58 @@ def lbm_lee_device_copy(dst, src, nbytes, stream):
     _check("lbm_lee_device_copy", load().lbm_lee_device_copy(dst, src, int(nbytes), stream))
 
 
+def lbm_lee_ghost_bytes(desc) -> int:
+    return int(load().lbm_lee_ghost_bytes(ctypes.byref(desc)))
+
+
+def lbm_lee_set_closure(h, params, ghost, ghost_bytes):
+    _check("lbm_lee_set_closure", load().lbm_lee_set_closure(h, params, ghost, ghost_bytes))
+
+
+def lbm_nrbc_dims(lattice: str) -> dict:
+    d = (ctypes.c_int32 * 4)()
+    _check("lbm_nrbc_dims", load().lbm_nrbc_dims(LATTICES[lattice], d))
+    return dict(n_in=d[0], n_out=d[1], hidden=d[2], n_params=d[3])
+
+
+def lbm_nrbc_face_nodes(desc) -> int:
+    return int(load().lbm_nrbc_face_nodes(ctypes.byref(desc)))
+
+
+def lbm_nrbc_forward(lattice, params, strips, count, out, stream):
+    _check("lbm_nrbc_forward", load().lbm_nrbc_forward(LATTICES[lattice], params, strips, int(count), out, stream))
+
+
+def lbm_nrbc_workspace_bytes(lattice, count) -> int:
+    return int(load().lbm_nrbc_workspace_bytes(LATTICES[lattice], int(count)))
+
+
+def lbm_nrbc_loss_grad(lattice, params, strips, targets, count, grad, loss, workspace, workspace_bytes, stream):
+    _check("lbm_nrbc_loss_grad", load().lbm_nrbc_loss_grad(LATTICES[lattice], params, strips, targets, int(count),
+                                                           grad, loss, workspace, int(workspace_bytes), stream))
+
+
+def lbm_nrbc_adam(n, params, grad, m, v, t, lr, beta1, beta2, eps, stream):
+    _check("lbm_nrbc_adam", load().lbm_nrbc_adam(int(n), params, grad, m, v, int(t), float(lr), float(beta1),
+                                                 float(beta2), float(eps), stream))
+
+
+def _i64x3(v):
+    return (ctypes.c_int64 * 3)(*[int(x) for x in v])
+
+
+def lbm_nrbc_gather(outer, origin, inner_desc, node_ids, count, strips, targets, stream):
+    _check("lbm_nrbc_gather", load().lbm_nrbc_gather(outer, _i64x3(origin), ctypes.byref(inner_desc), node_ids,
+                                                     int(count), strips, targets, stream))
+
+
+def lbm_lee_compare_fields(a, n_a, b, n_b, origin, scratch, scratch_bytes, stream):
+    out = (ctypes.c_double * 3)()
+    _check("lbm_lee_compare_fields", load().lbm_lee_compare_fields(a, _i64x3(n_a), b, _i64x3(n_b), _i64x3(origin),
+                                                                   out, scratch, int(scratch_bytes), stream))
+    return [float(v) for v in out]
+
+
 def lbm_lee_version() -> str:
     return load().lbm_lee_version().decode()
 
@@ -203,7 +276,8 @@ class Solver:
     """Owns torch device buffers for one solver handle; every method is one C-ABI call."""
 
     def __init__(self, lattice: str, storage: str, shape, rho, u, theta, tau: float = 0.5, variant: str = "auto",
-                 store_scale: float = 0.0, tune: int = 0, stream=None):
+                 store_scale: float = 0.0, tune: int = 0, bc: str = "periodic", sponge_width: int = 0,
+                 sponge_sigma: float = 0.0, stream=None):
         import torch
 
         if not torch.cuda.is_available():
@@ -216,7 +290,8 @@ class Solver:
         if len(self.shape) != self.D:
             raise ValueError(f"{lattice} needs a {self.D}D shape, got {self.shape}")
         self.N = int(np.prod(self.shape))
-        self.desc = make_desc(lattice, storage, self.shape, tau, variant, store_scale, tune)
+        self.desc = make_desc(lattice, storage, self.shape, tau, variant, store_scale, tune, bc, sponge_width,
+                              sponge_sigma)
         self.state_bytes = lbm_lee_state_bytes(self.desc)
         if self.state_bytes == 0:
             load()
@@ -290,6 +365,18 @@ class Solver:
 
     def current(self):
         return lbm_lee_current(self.h)
+
+    def set_closure(self, params):
+        """Attach closure-network parameters (FP32, device or host array) for LBM_BC_MLP."""
+        t = self.torch
+        self._net = t.as_tensor(params, dtype=t.float32).to("cuda").contiguous()
+        nb = lbm_lee_ghost_bytes(self.desc)
+        self._ghost = t.zeros(max(nb // 4, 1), dtype=t.float32, device="cuda")
+        lbm_lee_set_closure(self.h, self._net.data_ptr(), self._ghost.data_ptr(), nb)
+
+    @property
+    def ghost(self):
+        return self._ghost
 
     @property
     def store_scale(self) -> float:

@@ -109,3 +109,59 @@ def test_null_handle_calls_fail_cleanly():
         lbm.lbm_lee_device_copy(16, 32, 17, None)
     lbm.lbm_lee_destroy(None)
     assert lbm.lbm_lee_store_scale(None) == 0.0
+
+
+@pytest.mark.parametrize("name", list(L.ALL))
+def test_network_dims_match_the_oracle_definition(name):
+    from oracle import mlp, open_bc
+    lat = L.get(name)
+    d = lbm.lbm_nrbc_dims(name)
+    k = len(open_bc.incoming_canonical(lat))
+    assert d["n_in"] == 3 * lat.Q and d["n_out"] == k and d["hidden"] == 64
+    assert d["n_params"] == mlp.flat(mlp.init_params(np.random.default_rng(0), 3 * lat.Q, k)).size
+
+
+@pytest.mark.parametrize("name,shape", [("D2Q9", (7, 11)), ("D3Q7", (4, 5, 6)), ("D1Q3", (9,)), ("D3Q19", (3, 3, 3))])
+def test_face_node_count_and_ghost_bytes(name, shape):
+    D = len(shape)
+    dims = list(reversed(shape))
+    want = sum(2 * int(np.prod([dims[b] for b in range(D) if b != a])) for a in range(D))
+    d = lbm.make_desc(name, "f32", shape, bc="mlp")
+    assert lbm.lbm_nrbc_face_nodes(d) == want
+    assert lbm.lbm_lee_ghost_bytes(d) == want * lbm.lbm_nrbc_dims(name)["n_out"] * 4
+    assert lbm.lbm_lee_ghost_bytes(lbm.make_desc(name, "f32", shape, bc="zero")) == 0
+
+
+@pytest.mark.parametrize("kw", [
+    dict(lattice="D2Q9", storage="f32", shape=(8, 8), bc="periodic"),
+])
+def test_good_boundary_descriptors(kw):
+    for bc, extra in (("zero", {}), ("copy", {}), ("sponge", dict(sponge_width=3, sponge_sigma=0.5)), ("mlp", {})):
+        k = dict(kw, bc=bc, **extra)
+        assert lbm.lbm_lee_state_bytes(lbm.make_desc(**k)) > 0
+
+
+@pytest.mark.parametrize("kw", [
+    dict(lattice="D2Q9", storage="f32", shape=(8, 2), bc="zero"),
+    dict(lattice="D2Q9", storage="f32", shape=(8, 8), bc="sponge", sponge_width=0, sponge_sigma=0.5),
+    dict(lattice="D2Q9", storage="f32", shape=(8, 8), bc="sponge", sponge_width=3, sponge_sigma=1.5),
+])
+def test_bad_boundary_descriptors(kw):
+    assert lbm.lbm_lee_state_bytes(lbm.make_desc(**kw)) == 0
+    d = lbm.make_desc("D2Q9", "f32", (8, 8))
+    d.bc = 7
+    assert lbm.lbm_lee_state_bytes(d) == 0
+
+
+def test_network_entry_points_reject_bad_arguments():
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_nrbc_forward("D2Q9", None, 64, 10, 128, None)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_nrbc_loss_grad("D2Q9", 256, 256, 256, 10, 256, None, 256, 16, None)  # workspace too small
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_nrbc_adam(10, 256, 256, 256, 256, 0, 1e-3, 0.9, 0.999, 1e-8, None)  # t < 1
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_lee_set_closure(None, 256, 256, 1024)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_lee_compare_fields(256, (4, 4, 1), 512, (3, 4, 1), (0, 0, 0), 1024, 1 << 20, None)
+    assert lbm.lbm_nrbc_workspace_bytes("D2Q9", 1000) >= 1024 * (lbm.lbm_nrbc_dims("D2Q9")["n_params"] + 1) * 4

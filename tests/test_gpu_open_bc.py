@@ -1,0 +1,262 @@
+"""GPU parity of the open-boundary closures and the closure network against the FP64 oracle.
+
+The network kernels round every matrix-product input to bfloat16; they are compared with the
+oracle run with the same rounding points (quantize=True), where only FP32-vs-FP64 accumulation
+and rare bfloat16 rounding ties differ, and with the exact FP64 network at a looser bar.
+"""
+import numpy as np
+import pytest
+
+from oracle import lattices as L
+from oracle import lbe
+from oracle import mlp
+from oracle import open_bc as ob
+
+from paper_1601_08103_amd import inputs
+
+from tests._gpu import gpu_ok, rel_l2, say, stable_seed
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ok(), reason="needs a GPU")]
+
+SHAPES = {1: (23,), 2: (14, 17), 3: (6, 7, 9)}
+BAR = {"f64": 1e-12, "f32": 1e-5}
+
+
+def _solver(name, storage, shape, bc, **kw):
+    from paper_1601_08103_amd.lbm import Solver
+    lat = L.get(name)
+    z = (np.zeros(shape), np.zeros((lat.D,) + tuple(shape)), np.zeros(shape))
+    return Solver(name, storage, shape, *z, bc=bc, **kw)
+
+
+def _random_state(lat, shape, seed):
+    rng = np.random.default_rng(seed)
+    return 1e-3 * lat.fstar.reshape((-1,) + (1,) * lat.D) * rng.standard_normal((lat.Q,) + tuple(shape))
+
+
+@pytest.mark.parametrize("name", ["D1Q3", "D2Q5", "D2Q9", "D3Q7", "D3Q19", "D2Q5_DIA", "D3Q7_DIA", "D3Q13"])
+@pytest.mark.parametrize("bc", ["zero", "copy", "sponge"])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_open_step_matches_oracle(name, bc, storage):
+    lat = L.get(name)
+    shape = SHAPES[lat.D]
+    kw = dict(sponge_width=3, sponge_sigma=0.4) if bc == "sponge" else {}
+    say("open", name, bc, storage)
+    sim = _solver(name, storage, shape, bc, **kw)
+    sim.import_f64(_random_state(lat, shape, stable_seed(name, bc, storage)))
+    g = sim.export_f64().cpu().numpy()
+    sim.step(4)
+    got = sim.export_f64().cpu().numpy()
+    want = ob.run_open(lat, g, 4, bc, **kw)
+    assert rel_l2(got, want) < BAR[storage]
+    sim.close()
+
+
+def _small_params(lat, seed):
+    k = len(ob.incoming_canonical(lat))
+    p = mlp.init_params(np.random.default_rng(seed), 3 * lat.Q, k)
+    rng = np.random.default_rng(seed + 1)
+    for key in ("b1", "b2", "b3"):
+        p[key] = 0.05 * rng.standard_normal(p[key].shape)
+    return p
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D2Q5", "D3Q7", "D3Q19", "D1Q3"])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_network_closure_step_matches_oracle(name, storage):
+    lat = L.get(name)
+    shape = SHAPES[lat.D]
+    say("mlp closure", name, storage)
+    params = _small_params(lat, 3)
+    sim = _solver(name, storage, shape, "mlp")
+    sim.set_closure(mlp.flat(params).astype(np.float32))
+    sim.import_f64(_random_state(lat, shape, 17))
+    g = sim.export_f64().cpu().numpy()
+    sim.step(3)
+    got = sim.export_f64().cpu().numpy()
+    p32 = mlp.unflat(mlp.flat(params).astype(np.float32).astype(np.float64), 3 * lat.Q, len(ob.incoming_canonical(lat)))
+    want = ob.run_open(lat, g, 3, "mlp", params=p32, quantize=True)
+    err = rel_l2(got, want)
+    say("mlp closure", name, storage, "rel L2", err)
+    assert err < 2e-3
+    sim.close()
+
+
+def test_copy_network_reproduces_copy_closure_on_gpu():
+    lat = L.get("D2Q9")
+    shape = (20, 24)
+    jin = ob.incoming_canonical(lat)
+    Q, k = lat.Q, len(jin)
+    p = {"W1": np.zeros((3 * Q, 64)), "b1": np.zeros(64), "W2": np.zeros((64, 64)), "b2": np.zeros(64),
+         "W3": np.zeros((64, k)), "b3": np.zeros(k)}
+    for r, j in enumerate(jin):
+        p["W1"][j, 2 * r], p["W1"][j, 2 * r + 1] = 1.0, -1.0
+        p["W2"][2 * r, 2 * r], p["W2"][2 * r + 1, 2 * r + 1] = 1.0, 1.0
+        p["W3"][2 * r, r], p["W3"][2 * r + 1, r] = 1.0, -1.0
+    state = _random_state(lat, shape, 5)
+    outs = []
+    for bc in ("copy", "mlp"):
+        sim = _solver("D2Q9", "f64", shape, bc)
+        if bc == "mlp":
+            sim.set_closure(mlp.flat(p).astype(np.float32))
+        sim.import_f64(state)
+        sim.step(2)
+        outs.append(sim.export_f64().cpu().numpy())
+        sim.close()
+    # the network sees x / rms(x) rounded to bfloat16: 2^-9 relative on each copied value
+    assert rel_l2(outs[1], outs[0]) < 2e-3
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D2Q5", "D3Q7", "D3Q19", "D3Q13"])
+def test_network_forward_matches_oracle(name):
+    import torch
+    from paper_1601_08103_amd import lbm
+    lat = L.get(name)
+    k = len(ob.incoming_canonical(lat))
+    params = _small_params(lat, 11)
+    p32 = mlp.flat(params).astype(np.float32)
+    pq = mlp.unflat(p32.astype(np.float64), 3 * lat.Q, k)
+    rng = np.random.default_rng(12)
+    B = 1000  # 62.5 tiles: a ragged last tile
+    x = (rng.standard_normal((B, 3 * lat.Q)) * rng.uniform(1e-5, 1e-2, size=(B, 1))).astype(np.float32)
+    say("nrbc forward", name)
+    xd = torch.from_numpy(x).cuda()
+    pd = torch.from_numpy(p32).cuda()
+    out = torch.empty((B, k), dtype=torch.float32, device="cuda")
+    lbm.lbm_nrbc_forward(name, pd.data_ptr(), xd.data_ptr(), B, out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    got = out.cpu().numpy().astype(np.float64)
+    want_q = mlp.predict(pq, x.astype(np.float64), quantize=True)
+    want = mlp.predict(pq, x.astype(np.float64))
+    assert rel_l2(got, want_q) < 1e-3
+    assert rel_l2(got, want) < 2e-2
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q7", "D3Q19", "D2Q5"])
+def test_network_gradients_match_oracle(name):
+    import torch
+    from paper_1601_08103_amd import lbm
+    lat = L.get(name)
+    k = len(ob.incoming_canonical(lat))
+    nin = 3 * lat.Q
+    params = _small_params(lat, 21)
+    p32 = mlp.flat(params).astype(np.float32)
+    pq = mlp.unflat(p32.astype(np.float64), nin, k)
+    rng = np.random.default_rng(22)
+    B = 777
+    x = (rng.standard_normal((B, nin)) * 1e-3).astype(np.float32)
+    t = (rng.standard_normal((B, k)) * 1e-3).astype(np.float32)
+    say("nrbc grad", name)
+    s = torch.cuda.current_stream().cuda_stream
+    xd, td, pd = (torch.from_numpy(a).cuda() for a in (x, t, p32))
+    grad = torch.empty_like(pd)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    wsb = lbm.lbm_nrbc_workspace_bytes(name, B)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    lbm.lbm_nrbc_loss_grad(name, pd.data_ptr(), xd.data_ptr(), td.data_ptr(), B, grad.data_ptr(), loss.data_ptr(),
+                           ws.data_ptr(), wsb, s)
+    g_gpu = mlp.unflat(grad.cpu().numpy().astype(np.float64), nin, k)
+    z, sc = mlp.normalise(x.astype(np.float64))
+    tn = t.astype(np.float64) / sc
+    yq, cq = mlp.forward(pq, z, quantize=True)
+    gq = mlp.backward(pq, cq, yq, tn, quantize=True)
+    y, c = mlp.forward(pq, z)
+    g = mlp.backward(pq, c, y, tn)
+    assert abs(float(loss.item()) - mlp.mse(yq, tn)) < 1e-4 * mlp.mse(yq, tn)
+    for key in g:
+        eq = rel_l2(g_gpu[key], gq[key])
+        e = rel_l2(g_gpu[key], g[key])
+        say("nrbc grad", name, key, "vs quantized", eq, "vs exact", e)
+        assert eq < 1e-2, key
+        assert e < 5e-2, key
+    # determinism: the same call gives the same bits
+    grad2 = torch.empty_like(pd)
+    lbm.lbm_nrbc_loss_grad(name, pd.data_ptr(), xd.data_ptr(), td.data_ptr(), B, grad2.data_ptr(), None,
+                           ws.data_ptr(), wsb, s)
+    assert torch.equal(grad, grad2)
+
+
+def test_adam_matches_oracle():
+    import torch
+    from paper_1601_08103_amd import lbm
+    rng = np.random.default_rng(3)
+    n = 5000
+    p = rng.standard_normal(n).astype(np.float32)
+    po = {"w": p.astype(np.float64)}
+    m = {"w": np.zeros(n)}
+    v = {"w": np.zeros(n)}
+    pd = torch.from_numpy(p.copy()).cuda()
+    md = torch.zeros(n, device="cuda")
+    vd = torch.zeros(n, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    for t in range(1, 6):
+        g = rng.standard_normal(n).astype(np.float32)
+        gd = torch.from_numpy(g).cuda()
+        lbm.lbm_nrbc_adam(n, pd.data_ptr(), gd.data_ptr(), md.data_ptr(), vd.data_ptr(), t, 1e-3, 0.9, 0.999, 1e-8, s)
+        mlp.adam(po, {"w": g.astype(np.float64)}, m, v, t, lr=1e-3)
+    assert np.abs(pd.cpu().numpy() - po["w"]).max() < 1e-6
+
+
+@pytest.mark.parametrize("name,inner,outer,origin", [("D2Q9", (10, 12), (30, 36), (12, 10)),
+                                                     ("D3Q7", (5, 6, 7), (9, 10, 11), (2, 2, 2)),
+                                                     ("D3Q19", (4, 4, 5), (8, 8, 9), (2, 2, 2))])
+def test_gather_pairs_match_the_outer_state(name, inner, outer, origin):
+    """origin is (x, y, z) order; shapes are C order."""
+    import torch
+    from paper_1601_08103_amd import lbm
+    lat = L.get(name)
+    say("gather", name)
+    big = _solver(name, "f32", outer, "periodic")
+    big.import_f64(_random_state(lat, outer, 9))
+    G = big.export_f64().cpu().numpy()
+    dinner = lbm.make_desc(name, "f32", inner, bc="mlp")
+    nn = lbm.lbm_nrbc_face_nodes(dinner)
+    k = lbm.lbm_nrbc_dims(name)["n_out"]
+    ids = torch.arange(nn, dtype=torch.int64, device="cuda")
+    strips = torch.empty((nn, 3 * lat.Q), dtype=torch.float32, device="cuda")
+    targ = torch.empty((nn, k), dtype=torch.float32, device="cuda")
+    lbm.lbm_nrbc_gather(big.h, list(origin) + [0] * (3 - len(origin)), dinner, ids.data_ptr(), nn, strips.data_ptr(),
+                        targ.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    S = strips.cpu().numpy().astype(np.float64)
+    T = targ.cpu().numpy().astype(np.float64)
+    # oracle: the outer state around the inner box, and its strips / outside neighbours
+    D = lat.D
+    win = (slice(None),) + tuple(slice(origin[D - 1 - ax] - 1, origin[D - 1 - ax] + inner[ax] + 1) for ax in range(D))
+    pad = G[win]
+    gin = pad[(slice(None),) + tuple(slice(1, n + 1) for n in inner)]
+    jin = ob.incoming_canonical(lat)
+    node = 0
+    for a in range(D):
+        for side in (0, 1):
+            other = [b for b in range(D) if b != a]
+            extents = [inner[D - 1 - b] for b in other]
+            for idx in np.ndindex(*reversed(extents)):
+                coords = [0, 0, 0]
+                for b, v in zip(other, reversed(idx)):
+                    coords[b] = v
+                coords[a] = 0 if side == 0 else inner[D - 1 - a] - 1
+                cell = tuple(coords[D - 1 - ax] for ax in range(D))
+                assert np.array_equal(S[node], ob.strip(lat, gin, a, side, cell))
+                perm = ob.canonical_perm(lat, a, side)
+                gc = list(coords)
+                gc[a] += -1 if side == 0 else 1
+                gcell = tuple(gc[D - 1 - ax] + 1 for ax in range(D))
+                assert np.array_equal(T[node], [pad[(perm[j],) + gcell] for j in jin])
+                node += 1
+    assert node == nn
+    big.close()
+
+
+def test_compare_fields():
+    import torch
+    from paper_1601_08103_amd import lbm
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((5, 6, 7))
+    B = rng.standard_normal((9, 10, 11))
+    o = (2, 3, 1)  # (x, y, z)
+    ad, bd = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    scratch = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    got = lbm.lbm_lee_compare_fields(ad.data_ptr(), (7, 6, 5), bd.data_ptr(), (11, 10, 9), o, scratch.data_ptr(),
+                                     1 << 20, torch.cuda.current_stream().cuda_stream)
+    Bw = B[o[2]:o[2] + 5, o[1]:o[1] + 6, o[0]:o[0] + 7]
+    want = [np.sum((A - Bw) ** 2), np.sum(Bw ** 2), np.abs(A - Bw).max()]
+    assert np.allclose(got, want, rtol=1e-12)
