@@ -39,10 +39,13 @@ def parse():
     ap.add_argument("--n", type=int, default=256, help="cells per axis")
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--variant", default="auto")
-    ap.add_argument("--modes", default="f32,f16,bf16,i16,f64", help="storage modes to time and compare")
+    ap.add_argument("--modes", default="f32,f16,bf16,i16,e3m12,f64", help="storage modes to time and compare")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="only the timed steps of --storage (for rocprofv3)")
+    ap.add_argument("--with-copy", action="store_true",
+                    help="with --profile-only: also run the plain copy kernel on one state buffer's bytes "
+                         "(the reference point for counter calibration)")
     return ap.parse_args()
 
 
@@ -145,7 +148,15 @@ def main():
 
     if args.profile_only:
         sim, ms = timed_run(args.storage)
-        log(f"profile-only: {N * K / (ms / 1e3) / 1e6:.1f} MLUPS")
+        log(f"profile-only: {N * K / (ms / 1e3) / 1e6:.1f} MLUPS, {sim.bytes_per_update} B/LU")
+        if args.with_copy:
+            nbytes = N * 7 * 4
+            a = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+            b = torch.empty_like(a)
+            for _ in range(10):
+                lbm.lbm_lee_device_copy(b.data_ptr(), a.data_ptr(), nbytes, stream.cuda_stream)
+            torch.cuda.synchronize()
+            log(f"copy kernel: 10 launches of {nbytes} bytes read + {nbytes} bytes written")
         return
 
     modes = [m for m in args.modes.split(",") if m]

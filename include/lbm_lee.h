@@ -68,6 +68,10 @@ typedef int32_t lbm_status;
 #define LBM_F16 2
 #define LBM_BF16 3
 #define LBM_I16 4
+#define LBM_E3M12 5 /* h as a 16-bit float with 3 exponent and 12 mantissa bits (see below)  */
+/* E3M12 (not an IEEE format): sign, 3-bit exponent e, 12-bit mantissa m; value
+ * (1 + m/4096) 2^(e-7) for e >= 1 and m 2^-18 for e = 0; round to nearest even; saturating at
+ * 2 - 2^-12.  Same 2 bytes as FP16, 4x finer spacing over the 8 binades below 2. */
 
 /* Performance knobs of the DPP step kernel (lbm_lee_desc.tune); results do not depend on them. */
 #define LBM_TUNE_NT_STORE 1  /* non-temporal (streaming) stores                        */
@@ -105,8 +109,8 @@ typedef struct lbm_lee_desc {
     double tau;          /* relaxation time, >= 1/2 (1/2 is the second-order scheme)        */
     int32_t variant;     /* LBM_VARIANT_*                                                   */
     int32_t tune;        /* LBM_TUNE_* bits, 0 for the defaults                             */
-    double store_scale;  /* S for F16/BF16/I16: 0 = choose from the initial state so that   */
-                         /* max |S g / f*| lies in [1/2, 1) (F16/BF16) or [2^13, 2^14)      */
+    double store_scale;  /* S for 16-bit storage: 0 = choose from the initial state so that  */
+                         /* max |S g / f*| lies in [1/2, 1) (F16/BF16/E3M12) or [2^13, 2^14)*/
                          /* (I16); otherwise a power of two > 0.  Ignored for F64/F32.     */
     int32_t bc;          /* LBM_BC_*; open boxes need n[a] >= 3 on every axis a < D         */
     int32_t sponge_width;/* LBM_BC_SPONGE: layer width W >= 1 in cells                      */

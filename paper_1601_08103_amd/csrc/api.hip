@@ -67,12 +67,15 @@ size_t elem_size(int storage) {
         case LBM_F32: return 4;
         case LBM_F16:
         case LBM_BF16:
-        case LBM_I16: return 2;
+        case LBM_I16:
+        case LBM_E3M12: return 2;
         default: return 0;
     }
 }
 
-bool is_scaled(int storage) { return storage == LBM_F16 || storage == LBM_BF16 || storage == LBM_I16; }
+bool is_scaled(int storage) {
+    return storage == LBM_F16 || storage == LBM_BF16 || storage == LBM_I16 || storage == LBM_E3M12;
+}
 
 bool aligned256(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 
@@ -117,6 +120,7 @@ lbm_status visit_storage(int storage, F &&f) {
         case LBM_F16: return f(VS{}, StF16{});
         case LBM_BF16: return f(VS{}, StBF16{});
         case LBM_I16: return f(VS{}, StI16{});
+        case LBM_E3M12: return f(VS{}, StE3M12{});
         default: return fail(LBM_E_INVALID, "unknown storage id %d", storage);
     }
 }

@@ -74,6 +74,38 @@ struct StI16 {
     }
 };
 
+// E3M12: 1 sign bit, 3 exponent bits, 12 mantissa bits.  value = (-1)^s (1 + m/4096) 2^(e-7)
+// for e >= 1 (binades [2^-6, 2)), (-1)^s m 2^-18 for e = 0 (subnormals, same spacing as the
+// lowest binade).  Encoding rounds to nearest even and saturates at 2 - 2^-12 (the largest
+// finite value); S is chosen so the initial |h| stays below 1, leaving one binade of headroom.
+struct StE3M12 {
+    using elem = unsigned short;
+    using comp = float;
+    static constexpr bool scaled = true;
+    __device__ static comp dec(elem v) {
+        const unsigned t = ((unsigned)v & 0x7fffu) << 11;  // e, m into the FP32 exponent/mantissa
+        const bool sub = ((unsigned)v & 0x7000u) == 0;
+        // normal: exponent field e + 120; subnormal: (1 + m/4096) 2^-6 - 2^-6 = m 2^-18 (exact)
+        float f = __uint_as_float(t + (sub ? (121u << 23) : (120u << 23)));
+        if (sub) f -= 0.015625f;
+        return ((unsigned)v & 0x8000u) ? -f : f;
+    }
+    __device__ static elem enc(comp v) {
+        const unsigned bits = __float_as_uint(v);
+        const unsigned sign = (bits >> 16) & 0x8000u;
+        const unsigned b = bits & 0x7fffffffu;
+        unsigned code;
+        if (b >= (121u << 23)) {  // |v| >= 2^-6: round the 23-bit mantissa to 12 bits, ties to even
+            const unsigned r = (b + 0x3ffu + ((b >> 11) & 1u)) >> 11;
+            code = min(r - (120u << 12), 0x7fffu);
+        } else {  // subnormal range: an integer multiple of 2^-18 (4096 is 2^-6, the first normal)
+            code = (unsigned)__builtin_rintf(__uint_as_float(b) * 262144.0f);
+        }
+        return (elem)(code | sign);
+    }
+    __device__ static elem enc_d(double v) { return enc((float)v); }
+};
+
 // Four consecutive elements starting at a 4-element-aligned index, decoded to the compute type.
 // Vector loads/stores; NT selects the non-temporal (streaming) cache policy.
 template <typename V>
@@ -114,6 +146,12 @@ __device__ inline void load4<StBF16>(const unsigned short *p, float (&v)[4], boo
 }
 
 template <>
+__device__ inline void load4<StE3M12>(const unsigned short *p, float (&v)[4], bool nt) {
+    u16x4 a = vload(reinterpret_cast<const u16x4 *>(p), nt);
+    v[0] = StE3M12::dec(a.x); v[1] = StE3M12::dec(a.y); v[2] = StE3M12::dec(a.z); v[3] = StE3M12::dec(a.w);
+}
+
+template <>
 __device__ inline void load4<StI16>(const short *p, float (&v)[4], bool nt) {
     s16x4 a = vload(reinterpret_cast<const s16x4 *>(p), nt);
     v[0] = StI16::dec(a.x); v[1] = StI16::dec(a.y); v[2] = StI16::dec(a.z); v[3] = StI16::dec(a.w);
@@ -141,6 +179,12 @@ __device__ inline void store4<StF16>(unsigned short *p, const float (&v)[4], boo
 template <>
 __device__ inline void store4<StBF16>(unsigned short *p, const float (&v)[4], bool nt) {
     u16x4 a = {StBF16::enc(v[0]), StBF16::enc(v[1]), StBF16::enc(v[2]), StBF16::enc(v[3])};
+    vstore(reinterpret_cast<u16x4 *>(p), a, nt);
+}
+
+template <>
+__device__ inline void store4<StE3M12>(unsigned short *p, const float (&v)[4], bool nt) {
+    u16x4 a = {StE3M12::enc(v[0]), StE3M12::enc(v[1]), StE3M12::enc(v[2]), StE3M12::enc(v[3])};
     vstore(reinterpret_cast<u16x4 *>(p), a, nt);
 }
 

@@ -17,7 +17,7 @@ from tests._gpu import gpu_ok, lattice, oracle_pull_state, rel_l2, say, stable_s
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ok(), reason="needs a GPU")]
 
 BAR = {"f64": 1e-12, "f32": 1e-5}
-UNIT_ROUNDOFF = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+UNIT_ROUNDOFF = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "f16": 2.0 ** -11, "bf16": 2.0 ** -8, "e3m12": 2.0 ** -13}
 # I16 rounds h to an integer: absolute error <= 1/2 in h units
 ALL_LATTICES = ["D1Q3", "D2Q5", "D2Q9", "D3Q7", "D3Q9", "D3Q13", "D3Q19", "D2Q5_DIA", "D3Q7_DIA"]
 
@@ -69,7 +69,7 @@ def test_step_matches_oracle_on_random_state(name, storage, variant, shape):
 
 
 @pytest.mark.parametrize("name", ALL_LATTICES)
-@pytest.mark.parametrize("storage", ["f16", "bf16", "i16"])
+@pytest.mark.parametrize("storage", ["f16", "bf16", "i16", "e3m12"])
 def test_16bit_storage_single_step_rounding(name, storage):
     """One step from a state the format holds exactly: the result differs from the FP64
     oracle only by the final rounding to storage (plus FP32 collision arithmetic)."""
@@ -78,7 +78,8 @@ def test_16bit_storage_single_step_rounding(name, storage):
     say(name, storage, shape)
     rng = np.random.default_rng(5)
     t0 = 1e-3 * lat.fstar.reshape((-1,) + (1,) * lat.D) * rng.standard_normal((lat.Q,) + shape)
-    S = 512.0 if storage != "i16" else 2.0 ** 21  # h ~ N(0, 2^11) for fixed point
+    # h ~ N(0, 1/2) for the floating formats (E3M12 saturates at 2), N(0, 2^11) for fixed point
+    S = {"i16": 2.0 ** 21, "e3m12": 256.0}.get(storage, 512.0)
     sim = _solver(name, storage, shape, store_scale=S)
     assert sim.store_scale == S
     sim.import_f64(t0)
@@ -96,7 +97,37 @@ def test_16bit_storage_single_step_rounding(name, storage):
         assert np.all(np.abs(h_got - h_want) <= 0.5 + noise)
     else:
         u = UNIT_ROUNDOFF[storage]
-        assert np.all(np.abs(h_got - h_want) <= u * np.abs(h_want) * 1.01 + noise)
+        sub = 2.0 ** -19 if storage == "e3m12" else 0.0  # half the subnormal spacing
+        assert np.abs(h_want).max() < 2.0 or storage != "e3m12"
+        assert np.all(np.abs(h_got - h_want) <= u * np.abs(h_want) * 1.01 + noise + sub)
+    sim.close()
+
+
+def _e3m12_round(x):
+    """Nearest-even rounding to the E3M12 grid (spacing 2^(e-12) in binade [2^e, 2^(e+1)),
+    e = -6..0; 2^-18 below 2^-6), saturating at 2 - 2^-12."""
+    x = np.asarray(x, dtype=np.float64)
+    a = np.abs(x)
+    e = np.floor(np.log2(np.maximum(a, 2.0 ** -6)))
+    q = 2.0 ** (e - 12)
+    r = np.round(a / q) * q  # numpy rounds half to even
+    return np.sign(x) * np.minimum(r, 2.0 - 2.0 ** -12)
+
+
+def test_e3m12_codec_matches_its_definition():
+    """Import exact FP32 values through the E3M12 encoder and read them back."""
+    lat = lattice("D1Q3")
+    rng = np.random.default_rng(3)
+    n = 3 * 4096
+    h = np.concatenate([rng.uniform(-2.5, 2.5, n // 3), rng.standard_normal(n // 3) * 2.0 ** -7,
+                        (rng.integers(-4096, 4097, n // 3) + rng.choice([0.0, 0.5], n // 3)) * 2.0 ** -18])
+    h = h.astype(np.float32).astype(np.float64)
+    sim = _solver("D1Q3", "e3m12", (n // 3,), store_scale=1.0)
+    g = h.reshape(3, n // 3) * lat.fstar[:, None]  # h = S g / f* with S = 1
+    sim.import_f64(g)
+    got = sim.export_f64().cpu().numpy() / lat.fstar[:, None]
+    want = _e3m12_round(h).reshape(3, n // 3)
+    assert np.array_equal(got, want)
     sim.close()
 
 
@@ -185,7 +216,7 @@ def _sub_box_oracle(lat, p0_full, centre_cell, n):
     return m["p"][c], m["u"][(slice(None),) + c]
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "i16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "i16", "e3m12"])
 def test_3d_workload_full_size_sampled(storage):
     """256^3 D3Q7, 8 pulses (amplitude 1e-3, sigma 12), the benchmark's launch configuration:
     24 steps, then p' and u' at 12 seeded cells against the oracle on sub-boxes."""
@@ -214,7 +245,7 @@ def test_3d_workload_full_size_sampled(storage):
         errs.append(np.abs(u_gpu[(slice(None),) + cell] - u_or).max() / np.abs(u_gpu).max())
     worst = max(errs)
     say("3D sampled", storage, "worst rel err", worst)
-    bar = {"f64": 1e-12, "f32": 1e-5, "f16": 2e-3, "bf16": 2e-2, "i16": 2e-3}[storage]
+    bar = {"f64": 1e-12, "f32": 1e-5, "f16": 2e-3, "bf16": 2e-2, "i16": 2e-3, "e3m12": 1e-3}[storage]
     assert worst < bar
 
 
@@ -249,7 +280,7 @@ def test_3d_plane_wave_full_size_500_steps(storage):
     assert err < BAR[storage]
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "i16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "i16", "e3m12"])
 def test_energy_conservation_and_decay(storage):
     lat = lattice("D3Q7")
     shape = (32, 32, 64)
@@ -260,7 +291,7 @@ def test_energy_conservation_and_decay(storage):
     e0 = sim.l2_energy()[0]
     sim.step(200)
     e1 = sim.l2_energy()[0]
-    drift_bar = {"f64": 1e-12, "f32": 1e-5, "f16": 2e-3, "bf16": 3e-2, "i16": 2e-3}[storage]
+    drift_bar = {"f64": 1e-12, "f32": 1e-5, "f16": 2e-3, "bf16": 3e-2, "i16": 2e-3, "e3m12": 1e-3}[storage]
     assert abs(e1 - e0) < drift_bar * e0
     sim.close()
     for tau in (0.6, 1.0):
@@ -274,7 +305,7 @@ def test_energy_conservation_and_decay(storage):
         sim.close()
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "i16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "i16", "e3m12"])
 def test_checkpoint_restart_is_bitwise(storage):
     lat = lattice("D2Q9")
     shape = (64, 256)
@@ -295,7 +326,7 @@ def test_checkpoint_restart_is_bitwise(storage):
         s.close()
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "i16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "i16", "e3m12"])
 @pytest.mark.parametrize("tune", [0, 7])
 def test_every_cell_is_written(storage, tune):
     """Poison the target buffer (NaN bytes; -32768 for I16, which the encoder never writes);
