@@ -77,6 +77,8 @@ typedef int32_t lbm_status;
 #define LBM_TUNE_NT_STORE 1  /* non-temporal (streaming) stores                        */
 #define LBM_TUNE_NT_LOAD 2   /* non-temporal (streaming) loads                         */
 #define LBM_TUNE_PERSISTENT 4 /* grid sized to the resident wave slots, grid-stride loop */
+#define LBM_TUNE_FULL_REST 8  /* also load, collide and store the rest population where it is */
+                              /* provably invariant (see lbm_lee_bytes_per_update)            */
 
 /* Boundary of the box.  The paper's scheme is periodic; the open closures are not in the
  * paper (it leaves boundary conditions to future work) and are defined here.  For a cell x
@@ -137,8 +139,12 @@ size_t lbm_lee_state_bytes(const lbm_lee_desc *desc);
 /* Bytes of device scratch lbm_lee_init needs (reductions, scale search).  0 on a bad desc. */
 size_t lbm_lee_scratch_bytes(const lbm_lee_desc *desc);
 
-/* Algorithmic HBM bytes per lattice-cell update of the step kernel: Q loads and Q stores
- * of the storage element (2 Q s).  0 on a bad desc. */
+/* Algorithmic HBM bytes per lattice-cell update of the step kernel: Q loads and Q stores of
+ * the storage element (2 Q s), or 2 (Q - 1) s when the rest population is left out of the step.
+ * It is left out when the equilibrium map leaves it invariant (E_00 = 1, E_0j = E_j0 = 0:
+ * D1Q3, D2Q5, D3Q7, D3Q9, D3Q13 and the diatomic D2Q5/D3Q7 sets), the boundary is not
+ * LBM_BC_SPONGE and LBM_TUNE_FULL_REST is not set; both buffers then hold the same (constant)
+ * rest population.  0 on a bad desc. */
 double lbm_lee_bytes_per_update(const lbm_lee_desc *desc);
 
 /*

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -31,6 +32,7 @@ struct lbm_lee {
     int cus;   // compute units of the device (persistent launches)
     const float *net;  // LBM_BC_MLP: closure parameters (caller-owned)
     float *ghost;      // LBM_BC_MLP: ghost buffer (caller-owned)
+    bool skip0;        // rest population left out of the step (invariant under it)
 };
 
 namespace {
@@ -92,7 +94,7 @@ lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
     if ((double)d->n[1] * (double)d->n[2] * 16.0 > 4.0e9) return fail(LBM_E_INVALID, "too many rows (ny * nz)");
     if (!(d->tau >= 0.5) || !std::isfinite(d->tau)) return fail(LBM_E_INVALID, "tau must be finite and >= 1/2 (got %g)", d->tau);
     if (d->variant < LBM_VARIANT_AUTO || d->variant > LBM_VARIANT_DPP2) return fail(LBM_E_INVALID, "unknown variant %d", d->variant);
-    if (d->tune < 0 || d->tune > 7) return fail(LBM_E_INVALID, "unknown tune bits 0x%x", d->tune);
+    if (d->tune < 0 || d->tune > 15) return fail(LBM_E_INVALID, "unknown tune bits 0x%x", d->tune);
     if (!(d->store_scale >= 0.0) || !std::isfinite(d->store_scale)) return fail(LBM_E_INVALID, "store_scale must be >= 0");
     if (d->store_scale > 0.0) {
         int ex;
@@ -226,6 +228,29 @@ FaceTab<VS::Q> face_table(const LatticeTable &t, const int64_t n[3]) {
     return ft;
 }
 
+// The rest population (index 0, velocity 0) is invariant under the update for every tau when
+// the equilibrium map E = d g^eq / d g has E_00 = 1 and E_0j = E_j0 = 0: then
+// g_0* = (1 - 1/tau) g_0 + (1/tau) g_0 = g_0 and no moving population depends on g_0.  The
+// sponge damps every population, so it keeps the rest population in the update.
+bool rest_decoupled(const LatticeTable &t) {
+    if (t.c[0][0] || t.c[0][1] || t.c[0][2]) return false;
+    auto E = [&](int i, int j) {
+        const int c2i = t.c[i][0] * t.c[i][0] + t.c[i][1] * t.c[i][1] + t.c[i][2] * t.c[i][2];
+        const int c2j = t.c[j][0] * t.c[j][0] + t.c[j][1] * t.c[j][1] + t.c[j][2] * t.c[j][2];
+        const int cc = t.c[i][0] * t.c[j][0] + t.c[i][1] * t.c[j][1] + t.c[i][2] * t.c[j][2];
+        const double wth = ((t.gamma - 1.0) * 0.5 * (c2j + t.beta[j]) - t.theta0) / t.rho0;
+        return t.f[i] * ((t.a1 + 0.5 * c2i * t.c1) + t.b * cc / t.rho0 + wth * (t.a2 + 0.5 * c2i * t.c2));
+    };
+    if (std::fabs(E(0, 0) - 1.0) > 1e-12) return false;
+    for (int j = 1; j < t.Q; ++j)
+        if (std::fabs(E(0, j)) > 1e-12 || std::fabs(E(j, 0)) > 1e-12) return false;
+    return true;
+}
+
+bool skip_rest(const LatticeTable &t, const lbm_lee_desc *d) {
+    return rest_decoupled(t) && d->bc != LBM_BC_SPONGE && !(d->tune & LBM_TUNE_FULL_REST);
+}
+
 int64_t face_node_count(const LatticeTable &t, const int64_t n[3]) {
     int64_t total = 0;
     for (int a = 0; a < t.D; ++a) {
@@ -273,7 +298,8 @@ lbm_status launch_init(lbm_lee *h, const double *rho, const double *u, const dou
         using ST = decltype(sto);
         auto k = field_coef<VS::Q>(h);
         auto *dst = static_cast<typename ST::elem *>(h->buf[h->cur]);
-        init_equilibrium<VS, ST><<<blocks_for(h->N), 256, 0, st>>>(rho, u, theta, dst, h->N, k);
+        auto *other = h->skip0 ? static_cast<typename ST::elem *>(h->buf[h->cur ^ 1]) : nullptr;
+        init_equilibrium<VS, ST><<<blocks_for(h->N), 256, 0, st>>>(rho, u, theta, dst, other, h->N, k);
         return launch_check();
     });
 }
@@ -359,7 +385,8 @@ size_t lbm_lee_scratch_bytes(const lbm_lee_desc *d) {
 double lbm_lee_bytes_per_update(const lbm_lee_desc *d) {
     LatticeTable t;
     if (check_desc(d, &t) != LBM_OK) return 0.0;
-    return 2.0 * t.Q * (double)elem_size(d->storage);
+    const int moved = skip_rest(t, d) ? t.Q - 1 : t.Q;
+    return 2.0 * moved * (double)elem_size(d->storage);
 }
 
 lbm_status lbm_lee_init(const lbm_lee_desc *desc, void *pop_a, void *pop_b, size_t bytes_each, const double *rho,
@@ -398,6 +425,7 @@ lbm_status lbm_lee_init(const lbm_lee_desc *desc, void *pop_a, void *pop_b, size
     h->cus = 0;
     h->net = nullptr;
     h->ghost = nullptr;
+    h->skip0 = skip_rest(tab, desc);
     {
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -444,10 +472,10 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
         unsigned grid = (waves + 3) / 4;
         if ((tune & kTunePersistent) && h->cus > 0 && (variant == LBM_VARIANT_DPP || variant == LBM_VARIANT_DPP2)) {
             int per_cu = 0;
-            const void *fn = vec == 4 ? (fullrow ? reinterpret_cast<const void *>(&step_dpp<VS, ST, 4, true>)
-                                                 : reinterpret_cast<const void *>(&step_dpp<VS, ST, 4, false>))
-                                      : (fullrow ? reinterpret_cast<const void *>(&step_dpp<VS, ST, 2, true>)
-                                                 : reinterpret_cast<const void *>(&step_dpp<VS, ST, 2, false>));
+            const void *fn = vec == 4 ? (fullrow ? reinterpret_cast<const void *>(&step_dpp<VS, ST, 4, true, false>)
+                                                 : reinterpret_cast<const void *>(&step_dpp<VS, ST, 4, false, false>))
+                                      : (fullrow ? reinterpret_cast<const void *>(&step_dpp<VS, ST, 2, true, false>)
+                                                 : reinterpret_cast<const void *>(&step_dpp<VS, ST, 2, false, false>));
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) == hipSuccess && per_cu > 0) {
                 const unsigned g = (unsigned)(per_cu * h->cus);
                 if (g < grid) grid = g;
@@ -473,39 +501,51 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
             const long long tiles = (ft.node_off[ft.nfaces] + 15) / 16;
             ghost_blocks = (unsigned)std::min<long long>((tiles + 3) / 4, 4096);
         }
-        for (int64_t t = 0; t < nsteps; ++t) {
-            const E *src = static_cast<const E *>(h->buf[h->cur]);
-            E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);
-            if (bc == LBM_BC_MLP)
-                ghost_mlp_kernel<VS, ST><<<ghost_blocks, 256, 0, st>>>(src, h->N, h->net, h->ghost, ft, fk);
-            if (variant == LBM_VARIANT_GENERIC) {
-                step_generic<VS, ST><<<blocks_for(h->N), 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, k);
-            } else if (variant == LBM_VARIANT_LDS) {
-                step_lds<VS, ST><<<lds_blocks, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, lds_cpr, k);
-            } else if (vec == 4) {
-                if (fullrow)
-                    step_dpp<VS, ST, 4, true><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr, waves, tune, k);
-                else
-                    step_dpp<VS, ST, 4, false><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr, waves, tune, k);
-            } else {
-                if (fullrow)
-                    step_dpp<VS, ST, 2, true><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr, waves, tune, k);
-                else
-                    step_dpp<VS, ST, 2, false><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr, waves, tune, k);
+        auto run = [&](auto skip) -> lbm_status {
+            constexpr bool SK = decltype(skip)::value;
+            for (int64_t t = 0; t < nsteps; ++t) {
+                const E *src = static_cast<const E *>(h->buf[h->cur]);
+                E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);
+                if (bc == LBM_BC_MLP)
+                    ghost_mlp_kernel<VS, ST><<<ghost_blocks, 256, 0, st>>>(src, h->N, h->net, h->ghost, ft, fk);
+                if (variant == LBM_VARIANT_GENERIC) {
+                    step_generic<VS, ST, SK><<<blocks_for(h->N), 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, k);
+                } else if (variant == LBM_VARIANT_LDS) {
+                    step_lds<VS, ST, SK><<<lds_blocks, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, lds_cpr, k);
+                } else if (vec == 4) {
+                    if (fullrow)
+                        step_dpp<VS, ST, 4, true, SK><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
+                                                                           waves, tune, k);
+                    else
+                        step_dpp<VS, ST, 4, false, SK><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
+                                                                            waves, tune, k);
+                } else {
+                    if (fullrow)
+                        step_dpp<VS, ST, 2, true, SK><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
+                                                                           waves, tune, k);
+                    else
+                        step_dpp<VS, ST, 2, false, SK><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
+                                                                            waves, tune, k);
+                }
+                if (bc != LBM_BC_PERIODIC) {
+                    shell_kernel<VS, ST, SK><<<dim3(shell_x, 2 * VS::D), 256, 0, st>>>(src, dst, h->N, bc, h->ghost,
+                                                                                      ft, k, fk);
+                    if (bc == LBM_BC_SPONGE)
+                        sponge_kernel<VS, ST><<<blocks_for(h->N), 256, 0, st>>>(dst, h->N, h->nx, h->ny, h->nz,
+                                                                              h->desc.sponge_width,
+                                                                              h->desc.sponge_sigma);
+                }
+                lbm_status ls = launch_check();
+                if (ls != LBM_OK) return ls;
+                h->cur ^= 1;
+                h->steps += 1;
             }
-            if (bc != LBM_BC_PERIODIC) {
-                shell_kernel<VS, ST><<<dim3(shell_x, 2 * VS::D), 256, 0, st>>>(src, dst, h->N, bc, h->ghost, ft, k, fk);
-                if (bc == LBM_BC_SPONGE)
-                    sponge_kernel<VS, ST><<<blocks_for(h->N), 256, 0, st>>>(dst, h->N, h->nx, h->ny, h->nz,
-                                                                          h->desc.sponge_width,
-                                                                          h->desc.sponge_sigma);
-            }
-            lbm_status ls = launch_check();
-            if (ls != LBM_OK) return ls;
-            h->cur ^= 1;
-            h->steps += 1;
+            return LBM_OK;
+        };
+        if constexpr (VS::rest_may_decouple) {
+            if (h->skip0) return run(std::true_type{});
         }
-        return LBM_OK;
+        return run(std::false_type{});
     });
     return s == LBM_OK ? ok() : s;
 }
@@ -596,7 +636,8 @@ lbm_status lbm_lee_import_f64(lbm_lee_handle h, const double *g, int64_t steps_d
         using ST = decltype(sto);
         auto k = field_coef<VS::Q>(h);
         auto *dst = static_cast<typename ST::elem *>(h->buf[h->cur]);
-        import_f64<VS, ST><<<blocks_for((size_t)VS::Q * h->N), 256, 0, st>>>(g, h->N, k, dst);
+        auto *other = h->skip0 ? static_cast<typename ST::elem *>(h->buf[h->cur ^ 1]) : nullptr;
+        import_f64<VS, ST><<<blocks_for((size_t)VS::Q * h->N), 256, 0, st>>>(g, h->N, k, dst, other);
         return launch_check();
     });
     if (s != LBM_OK) return s;

@@ -82,13 +82,14 @@ struct StE3M12 {
     using elem = unsigned short;
     using comp = float;
     static constexpr bool scaled = true;
+    // e and m go to the FP32 exponent / mantissa fields (exponent field e, mantissa m << 11);
+    // scaling by 2^120 then gives 2^(e-7) (1 + m/4096) for e >= 1, and for e = 0 the FP32
+    // denormal m 2^-138 becomes m 2^-18.  Exact; needs FP32 denormals enabled (the kernels'
+    // default float mode).
     __device__ static comp dec(elem v) {
-        const unsigned t = ((unsigned)v & 0x7fffu) << 11;  // e, m into the FP32 exponent/mantissa
-        const bool sub = ((unsigned)v & 0x7000u) == 0;
-        // normal: exponent field e + 120; subnormal: (1 + m/4096) 2^-6 - 2^-6 = m 2^-18 (exact)
-        float f = __uint_as_float(t + (sub ? (121u << 23) : (120u << 23)));
-        if (sub) f -= 0.015625f;
-        return ((unsigned)v & 0x8000u) ? -f : f;
+        const unsigned x = ((unsigned)v) << 16;
+        const unsigned bits = ((x >> 5) & 0x03fff800u) | (x & 0x80000000u);
+        return __uint_as_float(bits) * 0x1p120f;
     }
     __device__ static elem enc(comp v) {
         const unsigned bits = __float_as_uint(v);

@@ -71,11 +71,14 @@ struct FieldCoef {
 };
 
 // ------------------------------------------------------------------ collision
-template <class VS, typename CT, bool SPLIT>
+// SKIP0: the rest population (index 0) is left out: the host enables this only when the
+// equilibrium map leaves it invariant (E_00 = 1, E_0j = E_j0 = 0), in which case the moving
+// populations' equilibria do not depend on it either.
+template <class VS, typename CT, bool SPLIT, bool SKIP0 = false>
 __device__ __forceinline__ void collide(const StepCoef<CT, VS::Q> &k, CT (&s)[VS::Q]) {
     CT rho = 0, jx = 0, jy = 0, jz = 0, e = 0;
 #pragma unroll
-    for (int i = 0; i < VS::Q; ++i) {
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) {
         const CT g = mulk<SPLIT>(s[i], k.dec[i]);
         rho += g;
         if (VS::cx(i) > 0) jx += g;
@@ -91,7 +94,7 @@ __device__ __forceinline__ void collide(const StepCoef<CT, VS::Q> &k, CT (&s)[VS
     const CT C = mulk<SPLIT>(rho, k.c1) + mulk<SPLIT>(theta, k.c2);
     const CT Ux = mulk<SPLIT>(jx, k.b_rho0), Uy = mulk<SPLIT>(jy, k.b_rho0), Uz = mulk<SPLIT>(jz, k.b_rho0);
 #pragma unroll
-    for (int i = 0; i < VS::Q; ++i) {
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) {
         CT t = A;
         if (VS::cx(i) > 0) t += Ux;
         if (VS::cx(i) < 0) t -= Ux;
@@ -113,7 +116,7 @@ __device__ __forceinline__ int wrap_add(int v, int d, int n) {
 
 // ------------------------------------------------------------------ step: generic variant
 // One thread per cell, each population gathered with its own wrapped index.  Any extents.
-template <class VS, class ST>
+template <class VS, class ST, bool SKIP0>
 __global__ __launch_bounds__(256) void step_generic(const typename ST::elem *__restrict__ src,
                                                     typename ST::elem *__restrict__ dst, int nx, int ny, int nz,
                                                     size_t N, StepCoef<typename ST::comp, VS::Q> k) {
@@ -125,16 +128,17 @@ __global__ __launch_bounds__(256) void step_generic(const typename ST::elem *__r
     const int y = (int)(r % (size_t)ny);
     const int z = (int)(r / (size_t)ny);
     CT s[VS::Q];
+    s[0] = 0;
 #pragma unroll
-    for (int i = 0; i < VS::Q; ++i) {
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) {
         const int xs = wrap_add(x, -VS::cx(i), nx);
         const int ys = wrap_add(y, -VS::cy(i), ny);
         const int zs = wrap_add(z, -VS::cz(i), nz);
         s[i] = ST::dec(src[(size_t)i * N + ((size_t)zs * ny + ys) * nx + xs]);
     }
-    collide<VS, CT, split_constants<ST>()>(k, s);
+    collide<VS, CT, split_constants<ST>(), SKIP0>(k, s);
 #pragma unroll
-    for (int i = 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
 }
 
 // ------------------------------------------------------------------ step: DPP variant
@@ -190,7 +194,7 @@ __device__ __forceinline__ void storev(typename ST::elem *p, const typename ST::
     }
 }
 
-template <class VS, class ST, int VEC, bool FULLROW>
+template <class VS, class ST, int VEC, bool FULLROW, bool SKIP0>
 __device__ __forceinline__ void step_chunk(const typename ST::elem *__restrict__ src,
                                            typename ST::elem *__restrict__ dst, int nx, int ny, int nz, size_t N,
                                            unsigned row, int chunk, int lane, bool ntl, bool nts,
@@ -205,7 +209,9 @@ __device__ __forceinline__ void step_chunk(const typename ST::elem *__restrict__
 
     CT s[VS::Q][VEC];
 #pragma unroll
-    for (int i = 0; i < VS::Q; ++i) {
+    for (int q = 0; q < VEC; ++q) s[0][q] = 0;
+#pragma unroll
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) {
         const int ys = wrap_add(y, -VS::cy(i), ny);
         const int zs = wrap_add(z, -VS::cz(i), nz);
         const E *rowp = src + (size_t)i * N + ((size_t)zs * ny + ys) * (size_t)nx;
@@ -236,16 +242,16 @@ __device__ __forceinline__ void step_chunk(const typename ST::elem *__restrict__
         CT c[VS::Q];
 #pragma unroll
         for (int i = 0; i < VS::Q; ++i) c[i] = s[i][q];
-        collide<VS, CT, split_constants<ST>()>(k, c);
+        collide<VS, CT, split_constants<ST>(), SKIP0>(k, c);
 #pragma unroll
         for (int i = 0; i < VS::Q; ++i) s[i][q] = c[i];
     }
     const size_t out = ((size_t)z * ny + y) * (size_t)nx + x0;
 #pragma unroll
-    for (int i = 0; i < VS::Q; ++i) storev<ST, VEC>(dst + (size_t)i * N + out, s[i], nts);
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) storev<ST, VEC>(dst + (size_t)i * N + out, s[i], nts);
 }
 
-template <class VS, class ST, int VEC, bool FULLROW>
+template <class VS, class ST, int VEC, bool FULLROW, bool SKIP0>
 __global__ __launch_bounds__(256) void step_dpp(const typename ST::elem *__restrict__ src,
                                                 typename ST::elem *__restrict__ dst, int nx, int ny, int nz,
                                                 size_t N, int chunks_per_row, unsigned total_waves, unsigned tune,
@@ -256,7 +262,7 @@ __global__ __launch_bounds__(256) void step_dpp(const typename ST::elem *__restr
     for (unsigned wave = blockIdx.x * 4u + wid; wave < total_waves; wave += gridDim.x * 4u) {
         const unsigned row = wave / (unsigned)chunks_per_row;
         const int chunk = (int)(wave - row * (unsigned)chunks_per_row);
-        step_chunk<VS, ST, VEC, FULLROW>(src, dst, nx, ny, nz, N, row, chunk, lane, ntl, nts, k);
+        step_chunk<VS, ST, VEC, FULLROW, SKIP0>(src, dst, nx, ny, nz, N, row, chunk, lane, ntl, nts, k);
     }
 }
 
@@ -272,7 +278,7 @@ constexpr int x_moving_count() {
     return n;
 }
 
-template <class VS, class ST>
+template <class VS, class ST, bool SKIP0>
 __global__ __launch_bounds__(256) void step_lds(const typename ST::elem *__restrict__ src,
                                                 typename ST::elem *__restrict__ dst, int nx, int ny, int nz,
                                                 size_t N, int chunks_per_row, StepCoef<typename ST::comp, VS::Q> k) {
@@ -292,9 +298,10 @@ __global__ __launch_bounds__(256) void step_lds(const typename ST::elem *__restr
     const int width = min(256, nx - x0);  // cells of this chunk
 
     CT s[VS::Q];
+    s[0] = 0;
     int m = 0;
 #pragma unroll
-    for (int i = 0; i < VS::Q; ++i) {
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) {
         const int ys = wrap_add(y, -VS::cy(i), ny);
         const int zs = wrap_add(z, -VS::cz(i), nz);
         const E *rowp = src + (size_t)i * N + ((size_t)zs * ny + ys) * (size_t)nx;
@@ -317,10 +324,10 @@ __global__ __launch_bounds__(256) void step_lds(const typename ST::elem *__restr
         }
     }
     if (!active) return;
-    collide<VS, CT, split_constants<ST>()>(k, s);
+    collide<VS, CT, split_constants<ST>(), SKIP0>(k, s);
     const size_t cell = ((size_t)z * ny + y) * (size_t)nx + x;
 #pragma unroll
-    for (int i = 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
 }
 
 // ------------------------------------------------------------------ initial state
@@ -328,7 +335,8 @@ __global__ __launch_bounds__(256) void step_lds(const typename ST::elem *__restr
 template <class VS, class ST>
 __global__ __launch_bounds__(256) void init_equilibrium(const double *__restrict__ rho, const double *__restrict__ u,
                                                         const double *__restrict__ theta,
-                                                        typename ST::elem *__restrict__ dst, size_t N,
+                                                        typename ST::elem *__restrict__ dst,
+                                                        typename ST::elem *__restrict__ rest_copy, size_t N,
                                                         FieldCoef<VS::Q> k) {
     const size_t cell = (size_t)blockIdx.x * 256u + threadIdx.x;
     if (cell >= N) return;
@@ -342,7 +350,9 @@ __global__ __launch_bounds__(256) void init_equilibrium(const double *__restrict
     for (int i = 0; i < VS::Q; ++i) {
         const double cu = VS::cx(i) * ux + VS::cy(i) * uy + VS::cz(i) * uz;
         const double geq = k.f[i] * (A + k.b * cu + 0.5 * VS::c2(i) * C);
-        dst[(size_t)i * N + cell] = ST::enc_d(k.enc[i] * geq);
+        const typename ST::elem v = ST::enc_d(k.enc[i] * geq);
+        dst[(size_t)i * N + cell] = v;
+        if (i == 0 && rest_copy) rest_copy[cell] = v;  // the other buffer's rest plane
     }
 }
 
@@ -533,7 +543,8 @@ __global__ __launch_bounds__(256) void export_f64(const typename ST::elem *__res
 
 template <class VS, class ST>
 __global__ __launch_bounds__(256) void import_f64(const double *__restrict__ g, size_t N, FieldCoef<VS::Q> k,
-                                                  typename ST::elem *__restrict__ dst) {
+                                                  typename ST::elem *__restrict__ dst,
+                                                  typename ST::elem *__restrict__ rest_copy) {
     const size_t idx = (size_t)blockIdx.x * 256u + threadIdx.x;
     if (idx >= (size_t)VS::Q * N) return;
     const int i = (int)(idx / N);
@@ -541,7 +552,9 @@ __global__ __launch_bounds__(256) void import_f64(const double *__restrict__ g, 
 #pragma unroll
     for (int j = 1; j < VS::Q; ++j)
         if (j == i) e = k.enc[j];
-    dst[idx] = ST::enc_d(e * g[idx]);
+    const typename ST::elem v = ST::enc_d(e * g[idx]);
+    dst[idx] = v;
+    if (i == 0 && rest_copy) rest_copy[idx] = v;
 }
 
 // ------------------------------------------------------------------ plain copy (calibration)

@@ -80,7 +80,7 @@ __device__ inline int node_cell(const FaceTab<Q> &ft, long long g, int (&p)[3]) 
 }
 
 // ------------------------------------------------------------------ shell recompute
-template <class VS, class ST>
+template <class VS, class ST, bool SKIP0>
 __global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__restrict__ src,
                                                     typename ST::elem *__restrict__ dst, size_t N, int closure,
                                                     const float *__restrict__ ghost, FaceTab<VS::Q> ft,
@@ -103,8 +103,9 @@ __global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__r
     constexpr int K = NetGeom<VS>::NOUT;
 
     CT s[VS::Q];
+    s[0] = 0;
 #pragma unroll
-    for (int i = 0; i < VS::Q; ++i) {
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) {
         const int c[3] = {VS::cx(i), VS::cy(i), VS::cz(i)};
         int sp[3], cl[3];
         bool inside = true;
@@ -134,9 +135,9 @@ __global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__r
         }
         s[i] = v;
     }
-    collide<VS, CT, split_constants<ST>()>(k, s);
+    collide<VS, CT, split_constants<ST>(), SKIP0>(k, s);
 #pragma unroll
-    for (int i = 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
 }
 
 // ------------------------------------------------------------------ sponge damping

@@ -17,8 +17,12 @@ struct VelSetBase {
     static constexpr int Q = Q_;
 };
 
-#define LBM_VELSET(NAME, D_, Q_, ...)                                                   \
+// REST0: the set has a rest velocity at index 0 that the collision may leave untouched (this
+// is decided per coefficient table on the host; sets whose rest population is always coupled
+// are compiled without the rest-skipping kernels).
+#define LBM_VELSET(NAME, D_, Q_, REST0, ...)                                            \
     struct NAME : VelSetBase<D_, Q_> {                                                  \
+        static constexpr bool rest_may_decouple = REST0;                                \
         static constexpr signed char c[Q_][3] = {__VA_ARGS__};                          \
         static constexpr int cx(int i) { return c[i][0]; }                              \
         static constexpr int cy(int i) { return c[i][1]; }                              \
@@ -26,24 +30,24 @@ struct VelSetBase {
         static constexpr int c2(int i) { return cx(i) * cx(i) + cy(i) * cy(i) + cz(i) * cz(i); } \
     };
 
-LBM_VELSET(VS_D1Q3, 1, 3, {0, 0, 0}, {-1, 0, 0}, {1, 0, 0})
+LBM_VELSET(VS_D1Q3, 1, 3, true, {0, 0, 0}, {-1, 0, 0}, {1, 0, 0})
 
-LBM_VELSET(VS_D2Q5, 2, 5, {0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0})
+LBM_VELSET(VS_D2Q5, 2, 5, true, {0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0})
 
-LBM_VELSET(VS_D2Q9, 2, 9, {0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0},
+LBM_VELSET(VS_D2Q9, 2, 9, false, {0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0},
            {-1, -1, 0}, {-1, 1, 0}, {1, -1, 0}, {1, 1, 0})
 
-LBM_VELSET(VS_D3Q7, 3, 7, {0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1})
+LBM_VELSET(VS_D3Q7, 3, 7, true, {0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1})
 
-LBM_VELSET(VS_D3Q9, 3, 9, {0, 0, 0}, {-1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}, {-1, 1, 1},
+LBM_VELSET(VS_D3Q9, 3, 9, true, {0, 0, 0}, {-1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}, {-1, 1, 1},
            {1, -1, -1}, {1, -1, 1}, {1, 1, -1}, {1, 1, 1})
 
-LBM_VELSET(VS_D3Q13, 3, 13, {0, 0, 0},
+LBM_VELSET(VS_D3Q13, 3, 13, true, {0, 0, 0},
            {-1, -1, 0}, {-1, 1, 0}, {1, -1, 0}, {1, 1, 0},
            {-1, 0, -1}, {-1, 0, 1}, {1, 0, -1}, {1, 0, 1},
            {0, -1, -1}, {0, -1, 1}, {0, 1, -1}, {0, 1, 1})
 
-LBM_VELSET(VS_D3Q19, 3, 19, {0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1},
+LBM_VELSET(VS_D3Q19, 3, 19, false, {0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1},
            {-1, -1, 0}, {-1, 1, 0}, {1, -1, 0}, {1, 1, 0},
            {-1, 0, -1}, {-1, 0, 1}, {1, 0, -1}, {1, 0, 1},
            {0, -1, -1}, {0, -1, 1}, {0, 1, -1}, {0, 1, 1})

@@ -45,14 +45,26 @@ def test_library_tables_match_oracle_tables(name):
 
 
 @pytest.mark.parametrize("lattice,storage,shape,bpu", [
-    ("D3Q7", "f32", (8, 8, 8), 56), ("D3Q7", "f16", (8, 8, 8), 28), ("D3Q7", "bf16", (8, 8, 8), 28),
-    ("D3Q7", "f64", (8, 8, 8), 112), ("D3Q7", "i16", (8, 8, 8), 28), ("D2Q9", "f32", (16, 16), 72), ("D2Q5", "f32", (16, 16), 40),
-    ("D1Q3", "f64", (1024,), 48), ("D3Q19", "f32", (4, 4, 4), 152)])
+    ("D3Q7", "f32", (8, 8, 8), 48), ("D3Q7", "f16", (8, 8, 8), 24), ("D3Q7", "bf16", (8, 8, 8), 24),
+    ("D3Q7", "f64", (8, 8, 8), 96), ("D3Q7", "i16", (8, 8, 8), 24), ("D3Q7", "e3m12", (8, 8, 8), 24),
+    ("D2Q9", "f32", (16, 16), 72), ("D2Q5", "f32", (16, 16), 32), ("D1Q3", "f64", (1024,), 32),
+    ("D3Q19", "f32", (4, 4, 4), 152), ("D3Q7_DIA", "f32", (8, 8, 8), 48), ("D3Q13", "f32", (4, 4, 4), 96)])
 def test_sizes(lattice, storage, shape, bpu):
+    """2 Q s bytes per update, or 2 (Q - 1) s where the rest population is invariant (exactly the
+    sets for which the oracle's equilibrium matrix has E_00 = 1, E_0j = E_j0 = 0)."""
+    from oracle import lbe
     d = lbm.make_desc(lattice, storage, shape)
     Q = lbm.lbm_lee_lattice_info(lattice)["Q"]
-    assert lbm.lbm_lee_state_bytes(d) == Q * int(np.prod(shape)) * lbm.ELEM_BYTES[storage]
+    s = lbm.ELEM_BYTES[storage]
+    assert lbm.lbm_lee_state_bytes(d) == Q * int(np.prod(shape)) * s
     assert lbm.lbm_lee_bytes_per_update(d) == bpu
+    E = lbe.equilibrium_matrix(L.get(lattice))
+    decoupled = abs(E[0, 0] - 1) < 1e-12 and np.abs(E[0, 1:]).max() < 1e-12 and np.abs(E[1:, 0]).max() < 1e-12
+    assert bpu == 2 * (Q - 1 if decoupled else Q) * s
+    full = lbm.make_desc(lattice, storage, shape, tune=8)
+    assert lbm.lbm_lee_bytes_per_update(full) == 2 * Q * s
+    sponge = lbm.make_desc(lattice, storage, shape, bc="sponge", sponge_width=1, sponge_sigma=0.1)
+    assert lbm.lbm_lee_bytes_per_update(sponge) == 2 * Q * s
     assert lbm.lbm_lee_scratch_bytes(d) >= 1024 * 6 * 8
 
 
@@ -63,7 +75,7 @@ def test_sizes(lattice, storage, shape, bpu):
     dict(lattice="D3Q7", storage="f16", shape=(8, 8, 8), store_scale=3.0),
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 6), variant="dpp"),
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 7), variant="dpp2"),
-    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), tune=8),
+    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), tune=16),
     dict(lattice="D3Q7", storage="i16", shape=(8, 8, 8), store_scale=0.75),
 ])
 def test_bad_descriptors_are_rejected(kw):

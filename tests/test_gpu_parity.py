@@ -115,18 +115,21 @@ def _e3m12_round(x):
 
 
 def test_e3m12_codec_matches_its_definition():
-    """Import exact FP32 values through the E3M12 encoder and read them back."""
-    lat = lattice("D1Q3")
+    """Import exact FP32 values through the E3M12 encoder and read them back.  D2Q5 has
+    weights 1/2 and 1/8, so the test's own scaling by f* is exact."""
+    lat = lattice("D2Q5")
     rng = np.random.default_rng(3)
-    n = 3 * 4096
-    h = np.concatenate([rng.uniform(-2.5, 2.5, n // 3), rng.standard_normal(n // 3) * 2.0 ** -7,
-                        (rng.integers(-4096, 4097, n // 3) + rng.choice([0.0, 0.5], n // 3)) * 2.0 ** -18])
-    h = h.astype(np.float32).astype(np.float64)
-    sim = _solver("D1Q3", "e3m12", (n // 3,), store_scale=1.0)
-    g = h.reshape(3, n // 3) * lat.fstar[:, None]  # h = S g / f* with S = 1
-    sim.import_f64(g)
-    got = sim.export_f64().cpu().numpy() / lat.fstar[:, None]
-    want = _e3m12_round(h).reshape(3, n // 3)
+    shape = (4, 1024)
+    n = lat.Q * 4096
+    k = n // 3
+    h = np.concatenate([rng.uniform(-2.5, 2.5, k), rng.standard_normal(k) * 2.0 ** -7,
+                        (rng.integers(-4096, 4097, n - 2 * k) + rng.choice([0.0, 0.5], n - 2 * k)) * 2.0 ** -18])
+    h = rng.permutation(h).astype(np.float32).astype(np.float64)
+    sim = _solver("D2Q5", "e3m12", shape, store_scale=1.0)
+    fs = lat.fstar.reshape(-1, 1, 1)
+    sim.import_f64(h.reshape((lat.Q,) + shape) * fs)  # h = S g / f* with S = 1
+    got = sim.export_f64().cpu().numpy() / fs
+    want = _e3m12_round(h).reshape((lat.Q,) + shape)
     assert np.array_equal(got, want)
     sim.close()
 
@@ -365,6 +368,28 @@ def test_variants_and_tunings_agree():
             sim.close()
         for o in outs[1:]:
             assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("name", ["D3Q7", "D2Q5", "D1Q3", "D3Q7_DIA", "D3Q13"])
+def test_rest_population_skip(name):
+    """Where the rest population is invariant the step leaves it out: both buffers keep the
+    same rest plane, and the result equals the full update (LBM_TUNE_FULL_REST) to rounding."""
+    import torch
+    lat = lattice(name)
+    shape = {1: (1028,), 2: (9, 520), 3: (5, 6, 264)}[lat.D]
+    fields = inputs.random_fields(4, shape, lat.D)
+    outs = []
+    for tune in (0, 8):
+        say("rest skip", name, tune)
+        sim = _solver(name, "f64", shape, fields=fields, tune=tune)
+        assert sim.bytes_per_update == 2 * (lat.Q - (1 if tune == 0 else 0)) * 8
+        sim.step(9)
+        outs.append(sim.export_f64().cpu().numpy())
+        if tune == 0:
+            n = int(np.prod(shape)) * 8
+            assert torch.equal(sim.pop_a[:n], sim.pop_b[:n])
+        sim.close()
+    assert rel_l2(outs[0], outs[1]) < 1e-13
 
 
 def test_device_copy():
