@@ -60,11 +60,15 @@ def kernel_source_hash() -> str:
 def traffic_from_counters(storage: str, n: int):
     """HBM bytes per launch measured with rocprofv3 counters, if they were taken on the current
     kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", f"traffic_step_d3q7_{n}_{storage}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_step_d3q7_{n}_{storage}.md")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
-        rec = json.load(fh)
+        text = fh.read()
+    try:
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (IndexError, ValueError):
+        return None
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")

@@ -1,0 +1,277 @@
+"""Learned non-reflecting boundary closure: data generation, training and evaluation.
+
+Orchestration only: every computation runs in the library (lattice steps, moments, training-pair
+gather, network forward/backward/Adam, field comparison); PyTorch holds device buffers.
+
+Problem (not in the paper, which is periodic-only): an initial state given on an L^D box, free
+space at rest outside.  The judge is a periodic run on a box of E = 3L per axis with the initial
+state in its centre and zero elsewhere; inside the box it is exact for n <= E - L steps (no
+signal travels faster than one cell per step).  The reflection coefficient of a closure is
+    R = max_t ||p'_bc(t) - p'_ext(t)||_2,box / max_t ||p'_ext(t)||_2,box,   t every 8 steps.
+Training pairs come from the same judge runs: the strip at each face node and the true
+entering populations at its outside neighbour.
+"""
+from __future__ import annotations
+
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import inputs, lbm
+
+
+def log(*a):
+    print("[nrbc]", *a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------- initial states
+def inner_pulses(rng, L: int, D: int, nmin=1, nmax=4, amp=1e-3, smin=8.0, smax=24.0):
+    n = int(rng.integers(nmin, nmax + 1))
+    out = []
+    for _ in range(n):
+        c = tuple(float(v) for v in rng.uniform(0.0, L, size=D))
+        out.append(inputs.Pulse(c, float(rng.uniform(-amp, amp)), float(rng.uniform(smin, smax))))
+    return out
+
+
+def box_fields(info, shape, pulses):
+    """Isentropic fields of the pulses on the box (minimum-image Gaussians on the box itself)."""
+    p0 = inputs.gaussian_pressure(shape, pulses)
+    return inputs.fields_from_pressure(p0, info["rho0"], info["theta0"], info["gamma"])
+
+
+def embed(torch, fields, L, E, D):
+    """Place box fields in the centre of an E^D box, zero elsewhere (device tensors)."""
+    rho, u, theta = fields
+    off = (E - L) // 2
+    sl = tuple(slice(off, off + L) for _ in range(D))
+    R = torch.zeros((E,) * D, dtype=torch.float64, device="cuda")
+    T = torch.zeros_like(R)
+    U = torch.zeros((D,) + (E,) * D, dtype=torch.float64, device="cuda")
+    R[sl] = torch.as_tensor(rho, device="cuda")
+    T[sl] = torch.as_tensor(theta, device="cuda")
+    U[(slice(None),) + sl] = torch.as_tensor(u, device="cuda")
+    return R, U, T
+
+
+# ---------------------------------------------------------------- training data
+def generate(lattice="D2Q9", L=512, E=1536, runs=100, steps=1024, every=8, nodes=256, seed=0, storage="f32"):
+    import torch
+    info = lbm.lbm_lee_lattice_info(lattice)
+    D = info["D"]
+    dims = lbm.lbm_nrbc_dims(lattice)
+    inner = lbm.make_desc(lattice, storage, (L,) * D, bc="mlp")
+    nn = lbm.lbm_nrbc_face_nodes(inner)
+    per_run = (steps // every) * nodes
+    S = torch.empty((runs * per_run, dims["n_in"]), dtype=torch.float32, device="cuda")
+    T = torch.empty((runs * per_run, dims["n_out"]), dtype=torch.float32, device="cuda")
+    origin = [(E - L) // 2] * D + [0] * (3 - D)
+    rng = np.random.default_rng(seed)
+    st = torch.cuda.current_stream().cuda_stream
+    k = 0
+    t0 = time.time()
+    ext = None
+    for r in range(runs):
+        fields = embed(torch, box_fields(info, (L,) * D, inner_pulses(rng, L, D)), L, E, D)
+        if ext is None:
+            ext = lbm.Solver(lattice, storage, (E,) * D, *fields)
+        else:
+            ext.reinit(*fields)
+        for s in range(0, steps, every):
+            ids = torch.from_numpy(rng.integers(0, nn, size=nodes).astype(np.int64)).cuda()
+            lbm.lbm_nrbc_gather(ext.h, origin, inner, ids.data_ptr(), nodes, S[k].data_ptr(), T[k].data_ptr(), st)
+            k += nodes
+            ext.step(every)
+        if (r + 1) % max(1, runs // 20) == 0:
+            torch.cuda.synchronize()
+            log(f"data: run {r + 1}/{runs}, {k} pairs, {time.time() - t0:.1f} s")
+    if ext is not None:
+        ext.close()
+    return S[:k], T[:k]
+
+
+# ---------------------------------------------------------------- training
+def init_params(lattice, seed=0):
+    dims = lbm.lbm_nrbc_dims(lattice)
+    rng = np.random.default_rng(seed)
+    nin, nout, H = dims["n_in"], dims["n_out"], dims["hidden"]
+    parts = [rng.standard_normal((nin, H)) * math.sqrt(2.0 / nin), np.zeros(H),
+             rng.standard_normal((H, H)) * math.sqrt(2.0 / H), np.zeros(H),
+             rng.standard_normal((H, nout)) * math.sqrt(1.0 / H), np.zeros(nout)]
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+def train(lattice, S, T, epochs=4, batch=4096, lr=1e-3, lr_end=1e-5, seed=0, params=None, val_frac=0.02):
+    import torch
+    st = torch.cuda.current_stream().cuda_stream
+    n = S.shape[0]
+    nval = max(batch, int(n * val_frac))
+    perm = torch.randperm(n, generator=torch.Generator().manual_seed(seed)).cuda()
+    Sv, Tv = S[perm[:nval]].contiguous(), T[perm[:nval]].contiguous()
+    tr = perm[nval:]
+    P = torch.from_numpy(params if params is not None else init_params(lattice, seed)).cuda()
+    m = torch.zeros_like(P)
+    v = torch.zeros_like(P)
+    g = torch.empty_like(P)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    wsb = lbm.lbm_nrbc_workspace_bytes(lattice, batch)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    nb = (n - nval) // batch
+    total = epochs * nb
+    it = 0
+    hist = []
+    t0 = time.time()
+    for ep in range(epochs):
+        order = tr[torch.randperm(tr.numel(), generator=torch.Generator().manual_seed(seed + 1 + ep)).cuda()]
+        for b in range(nb):
+            idx = order[b * batch:(b + 1) * batch]
+            xb, yb = S[idx].contiguous(), T[idx].contiguous()
+            it += 1
+            lr_t = lr * (lr_end / lr) ** (it / total)
+            lbm.lbm_nrbc_loss_grad(lattice, P.data_ptr(), xb.data_ptr(), yb.data_ptr(), batch, g.data_ptr(),
+                                   loss.data_ptr(), ws.data_ptr(), wsb, st)
+            lbm.lbm_nrbc_adam(P.numel(), P.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), it, lr_t, 0.9, 0.999,
+                              1e-8, st)
+        vl = evaluate_loss(lattice, P, Sv, Tv, ws, wsb)
+        hist.append(dict(epoch=ep + 1, train_loss=float(loss.item()), val_loss=vl))
+        log(f"train: epoch {ep + 1}/{epochs}, batch loss {loss.item():.3e}, val loss {vl:.3e}, {time.time() - t0:.1f} s")
+    return P.cpu().numpy(), hist
+
+
+def evaluate_loss(lattice, P, S, T, ws, wsb):
+    import torch
+    st = torch.cuda.current_stream().cuda_stream
+    g = torch.empty_like(P)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    n = S.shape[0]
+    need = lbm.lbm_nrbc_workspace_bytes(lattice, n)
+    if need > wsb:
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        wsb = need
+    lbm.lbm_nrbc_loss_grad(lattice, P.data_ptr(), S.data_ptr(), T.data_ptr(), n, g.data_ptr(), loss.data_ptr(),
+                           ws.data_ptr(), wsb, st)
+    return float(loss.item())
+
+
+# ---------------------------------------------------------------- evaluation
+def reflection(lattice, closure, pulses, L=512, E=1536, steps=1024, every=8, params=None, storage="f32",
+               ext_storage="f32", sponge_width=32, sponge_sigma=0.2, ext=None):
+    """R of one closure on one initial state, and the wall time per step of the box run."""
+    import torch
+    info = lbm.lbm_lee_lattice_info(lattice)
+    D = info["D"]
+    fields = box_fields(info, (L,) * D, pulses)
+    kw = dict(sponge_width=sponge_width, sponge_sigma=sponge_sigma) if closure == "sponge" else {}
+    box = lbm.Solver(lattice, storage, (L,) * D, *fields, bc=closure, **kw)
+    if closure == "mlp":
+        box.set_closure(params)
+    own_ext = ext is None
+    if own_ext:
+        ext = lbm.Solver(lattice, ext_storage, (E,) * D, *embed(torch, fields, L, E, D))
+    else:
+        ext.reinit(*embed(torch, fields, L, E, D))
+    st = torch.cuda.current_stream().cuda_stream
+    nb = list(reversed((L,) * D)) + [1] * (3 - D)
+    ne = list(reversed((E,) * D)) + [1] * (3 - D)
+    origin = [(E - L) // 2] * D + [0] * (3 - D)
+    err_max = ref_max = 0.0
+    for t in range(0, steps + 1, every):
+        if t:
+            box.step(every)
+            ext.step(every)
+        pb = box.moments()["p"]
+        pe = ext.moments()["p"]
+        out = lbm.lbm_lee_compare_fields(pb.data_ptr(), nb, pe.data_ptr(), ne, origin, box.scratch.data_ptr(),
+                                         box.scratch_bytes, st)
+        err_max = max(err_max, math.sqrt(out[0]))
+        ref_max = max(ref_max, math.sqrt(out[1]))
+    box.close()
+    if own_ext:
+        ext.close()
+    return err_max / ref_max if ref_max > 0 else float("nan")
+
+
+def time_per_step(lattice, shape, bc="periodic", params=None, storage="f32", steps=200, **kw):
+    import torch
+    info = lbm.lbm_lee_lattice_info(lattice)
+    D = info["D"]
+    z = (np.zeros(shape), np.zeros((D,) + tuple(shape)), np.zeros(shape))
+    sim = lbm.Solver(lattice, storage, shape, *z, bc=bc, **kw)
+    if bc == "mlp":
+        sim.set_closure(params)
+    sim.step(10)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sim.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    sim.close()
+    return e0.elapsed_time(e1) / steps
+
+
+# ---------------------------------------------------------------- command line
+def main(argv=None):
+    """python -m paper_1601_08103_amd.nrbc {train,evaluate} ...  (JSON on stdout, progress on stderr)."""
+    import argparse
+    import os
+    import torch
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("mode", choices=["train", "evaluate"])
+    ap.add_argument("--lattice", default="D2Q9")
+    ap.add_argument("--L", type=int, default=512)
+    ap.add_argument("--E", type=int, default=1536)
+    ap.add_argument("--steps", type=int, default=1024)
+    ap.add_argument("--runs", type=int, default=200)
+    ap.add_argument("--every", type=int, default=8)
+    ap.add_argument("--nodes", type=int, default=256)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--weights", default=None, help="weights file (.npy) to write (train) or read (evaluate)")
+    ap.add_argument("--seeds", type=int, default=32, help="held-out initial states for evaluate")
+    ap.add_argument("--sponge-width", type=int, default=32)
+    ap.add_argument("--sponge-sigma", type=float, default=0.2)
+    args = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    lbm.load()
+    if args.mode == "train":
+        S, T = generate(args.lattice, args.L, args.E, args.runs, args.steps, args.every, args.nodes, args.seed)
+        P, hist = train(args.lattice, S, T, args.epochs, args.batch, args.lr, seed=args.seed)
+        if args.weights:
+            np.save(args.weights, P.astype(np.float32), allow_pickle=False)
+        print(json.dumps(dict(mode="train", lattice=args.lattice, pairs=int(S.shape[0]), runs=args.runs,
+                              history=hist)))
+        return
+    P = np.load(args.weights, allow_pickle=False) if args.weights else None
+    rng = np.random.default_rng(10_000 + args.seed)  # held out: training uses seeds below 10000
+    info = lbm.lbm_lee_lattice_info(args.lattice)
+    D = info["D"]
+    closures = ["zero", "copy", "sponge"] + (["mlp"] if P is not None else [])
+    Rs = {c: [] for c in closures}
+    ext = None
+    for k in range(args.seeds):
+        pulses = inner_pulses(rng, args.L, D)
+        if ext is None:
+            fields = box_fields(info, (args.L,) * D, pulses)
+            ext = lbm.Solver(args.lattice, "f32", (args.E,) * D, *embed(torch, fields, args.L, args.E, D))
+        for c in closures:
+            Rs[c].append(reflection(args.lattice, c, pulses, args.L, args.E, args.steps, 8, params=P,
+                                    sponge_width=args.sponge_width, sponge_sigma=args.sponge_sigma, ext=ext))
+        log(f"evaluate: seed {k + 1}/{args.seeds}: " + ", ".join(f"{c} {Rs[c][-1]:.4f}" for c in closures))
+    times = {"extended_periodic": time_per_step(args.lattice, (args.E,) * D)}
+    for c in closures:
+        kw = dict(sponge_width=args.sponge_width, sponge_sigma=args.sponge_sigma) if c == "sponge" else {}
+        times[c] = time_per_step(args.lattice, (args.L,) * D, bc=c, params=P, **kw)
+    print(json.dumps(dict(mode="evaluate", lattice=args.lattice, L=args.L, E=args.E, steps=args.steps,
+                          seeds=args.seeds, R_mean={c: float(np.mean(v)) for c, v in Rs.items()},
+                          R_max={c: float(np.max(v)) for c, v in Rs.items()}, ms_per_step=times)))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,47 @@
+"""GPU end-to-end check of the learned-closure pipeline at a small size: judge runs produce
+training pairs, the library's kernels train the network, and the reflection coefficient of
+every closure is measured against the larger periodic run."""
+import numpy as np
+import pytest
+
+from tests._gpu import gpu_ok, say
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ok(), reason="needs a GPU")]
+
+
+def test_pipeline_small():
+    import torch
+    from paper_1601_08103_amd import lbm, nrbc
+    say("nrbc pipeline small")
+    S, T = nrbc.generate("D2Q9", L=32, E=96, runs=3, steps=64, every=8, nodes=64, seed=1)
+    assert S.shape == (3 * 8 * 64, 27) and T.shape == (3 * 8 * 64, 3)
+    assert bool(torch.isfinite(S).all()) and bool(torch.isfinite(T).all())
+    P, hist = nrbc.train("D2Q9", S, T, epochs=3, batch=256, lr=3e-3, seed=0)
+    assert P.shape == (lbm.lbm_nrbc_dims("D2Q9")["n_params"],) and np.isfinite(P).all()
+    assert hist[-1]["val_loss"] < hist[0]["val_loss"] * 1.5
+    rng = np.random.default_rng(5)
+    pulses = nrbc.inner_pulses(rng, 32, 2, smin=3.0, smax=5.0)
+    R = {c: nrbc.reflection("D2Q9", c, pulses, L=32, E=96, steps=64, params=P, sponge_width=6, sponge_sigma=0.3)
+         for c in ("zero", "copy", "sponge", "mlp")}
+    say("nrbc pipeline small", R)
+    for c, r in R.items():
+        assert 0.0 < r < 2.0, (c, r)
+
+
+def test_exact_ghosts_give_zero_reflection():
+    """Control: the judge compared with itself (a box run whose ghosts would be exact) -- here the
+    box is the judge's own central region, so R must be 0 before signals wrap around."""
+    import torch
+    from paper_1601_08103_amd import lbm, nrbc
+    info = lbm.lbm_lee_lattice_info("D2Q9")
+    rng = np.random.default_rng(2)
+    pulses = nrbc.inner_pulses(rng, 32, 2, smin=3.0, smax=5.0)
+    fields = nrbc.box_fields(info, (32, 32), pulses)
+    a = lbm.Solver("D2Q9", "f32", (96, 96), *nrbc.embed(torch, fields, 32, 96, 2))
+    b = lbm.Solver("D2Q9", "f32", (96, 96), *nrbc.embed(torch, fields, 32, 96, 2))
+    a.step(40)
+    b.step(40)
+    pa, pb = a.moments()["p"], b.moments()["p"]
+    out = lbm.lbm_lee_compare_fields(pa.data_ptr(), (96, 96, 1), pb.data_ptr(), (96, 96, 1), (0, 0, 0),
+                                     a.scratch.data_ptr(), a.scratch_bytes, torch.cuda.current_stream().cuda_stream)
+    assert out[0] == 0.0 and out[1] > 0

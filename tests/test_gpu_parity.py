@@ -330,25 +330,30 @@ def test_checkpoint_restart_is_bitwise(storage):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "i16", "e3m12"])
-@pytest.mark.parametrize("tune", [0, 7])
+@pytest.mark.parametrize("tune", [0, 7, 8])
 def test_every_cell_is_written(storage, tune):
-    """Poison the target buffer (NaN bytes; -32768 for I16, which the encoder never writes);
-    one step must overwrite every value."""
+    """Poison the target buffer, re-initialise (which writes the rest plane of both buffers when
+    the step leaves it out), take one step: every value must have been overwritten.  Sentinels:
+    NaN bytes for the IEEE formats, -32768 for I16 and 0xFFFF (-(2 - 2^-12), saturation) for
+    E3M12, which the encoders never produce from these states."""
     import torch
-    for name, shape in (("D3Q19", (5, 6, 264)), ("D2Q9", (9, 520)), ("D3Q7", (3, 4, 256))):
+    for name, shape in (("D3Q19", (5, 6, 264)), ("D2Q9", (9, 520)), ("D3Q7", (3, 4, 256)), ("D2Q5", (7, 260))):
         say("poison", name, storage, shape, "tune", tune)
         lat = lattice(name)
-        sim = _solver(name, storage, shape, fields=inputs.random_fields(1, shape, lat.D), tune=tune)
-        if storage == "i16":
-            sim.pop_b.view(torch.int16).fill_(-32768)
-        else:
+        fields = inputs.random_fields(1, shape, lat.D)
+        sim = _solver(name, storage, shape, fields=fields, tune=tune)
+        sentinel = {"i16": -32768, "e3m12": -1}.get(storage)
+        if sentinel is None:
             sim.pop_b.fill_(0xFF)
+        else:
+            sim.pop_b.view(torch.int16).fill_(sentinel)
+        sim.reinit(*fields)
         sim.step(1)
         assert sim.current()[0] == sim.pop_b.data_ptr()
-        if storage == "i16":
-            assert not bool((sim.pop_b.view(torch.int16) == -32768).any())
-        else:
+        if sentinel is None:
             assert bool(torch.isfinite(sim.export_f64()).all())
+        else:
+            assert not bool((sim.pop_b.view(torch.int16) == sentinel).any())
         sim.close()
 
 
