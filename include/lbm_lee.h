@@ -165,6 +165,13 @@ lbm_status lbm_lee_init(const lbm_lee_desc *desc, void *pop_a, void *pop_b, size
  * the storage scale is kept).  Resets the step counter. */
 lbm_status lbm_lee_reinit(lbm_lee_handle h, const double *rho, const double *u, const double *theta, void *stream);
 
+/* Re-initialise to the equilibrium of fields given on a sub-box only (n_sub cells at cell
+ * offset origin; rho, theta: n_sub cells, u: D * n_sub, same layout rules), with the fields zero
+ * (the state at rest) on every other cell.  Lets a large box (e.g. the wider periodic run that
+ * judges an open box) start from a small initial state without full-size field arrays. */
+lbm_status lbm_lee_reinit_region(lbm_lee_handle h, const int64_t origin[3], const int64_t n_sub[3], const double *rho,
+                                 const double *u, const double *theta, void *stream);
+
 /* Advance nsteps >= 0 time steps (fused pull-stream + moments + equilibrium + relaxation,
  * one kernel launch per step, periodic box). */
 lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream);
@@ -177,6 +184,11 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream);
  */
 lbm_status lbm_lee_moments(lbm_lee_handle h, void *p, void *u, void *rho, void *theta, int32_t out_is_f64,
                            void *stream);
+
+/* lbm_lee_moments restricted to a sub-box (n_sub cells at cell offset origin); the outputs are
+ * sub-box arrays (n_sub cells, u: D of them). */
+lbm_status lbm_lee_moments_region(lbm_lee_handle h, const int64_t origin[3], const int64_t n_sub[3], void *p, void *u,
+                                  void *rho, void *theta, int32_t out_is_f64, void *stream);
 
 /*
  * out[0] = sum_x sum_i g_i^2 / f*_i  (the weighted L2 energy; constant at tau = 1/2 for every
@@ -231,7 +243,8 @@ lbm_status lbm_lee_set_closure(lbm_lee_handle h, const float *params, void *ghos
  * post-collision populations at a face node, 3 cells deep along the inward normal, in the
  * canonical face frame (outward normal -x), m-major: x[m * Q + j]; output: the populations
  * entering through the face (canonical c_x = +1, in canonical order).  Network:
- *   s = rms(x), z = x / s, h1 = relu(z W1 + b1), h2 = relu(h1 W2 + b2), y = h2 W3 + b3, out = s y.
+ *   s = rms(x), z = x / s, h1 = relu(z W1 + b1), h2 = relu(h1 W2 + b2), y = h2 W3 + b3, out = s y,
+ * with rms computed as m sqrt(mean((x/m)^2)), m = max |x|; an all-zero strip predicts 0.
  * FP32 parameters, row-major, concatenated: W1[n_in][64], b1[64], W2[64][64], b2[64],
  * W3[64][n_out], b3[n_out].  Every product runs on matrix cores with bfloat16 inputs (round to
  * nearest even) and FP32 accumulation.
@@ -253,7 +266,7 @@ size_t lbm_nrbc_workspace_bytes(int32_t lattice, int64_t count);
 
 /*
  * Mean squared error of the network on a batch, in normalised units:
- *   loss = mean over samples and outputs of (y - target / s)^2,
+ *   loss = mean over samples with s > 0 and over outputs of (y - target / s)^2,
  * and its gradient with respect to every parameter (device FP32, n_params values).
  * `loss` (device, one float) may be NULL.  Deterministic (fixed reduction order).
  */

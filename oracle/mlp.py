@@ -7,7 +7,10 @@ The network maps a strip of post-collision populations (3 cells deep along the i
 normal, Q values each, in the canonical face frame) to the k populations that enter the box
 through the face:  x -> s = rms(x),  z = x / s,
     h1 = relu(z W1 + b1),  h2 = relu(h1 W2 + b2),  y = h2 W3 + b3,  output = s * y.
-Training minimises the mean squared error between y and target / s (Adam).
+The rms is taken as m sqrt(mean((x/m)^2)) with m = max |x| (no underflow for tiny strips);
+an all-zero strip has s = 0, z = 0 and predicts 0 (the scheme is linear).
+Training minimises the mean squared error between y and target / s over samples with s > 0
+(Adam).
 
 `quantize=True` rounds every GEMM input to bfloat16 with round-to-nearest-even, as the GPU
 kernels do before their matrix-core products: weights, the normalised strip, the hidden
@@ -17,8 +20,6 @@ gradients are sums of those rounded gradients).  Accumulation stays FP64 here.
 from __future__ import annotations
 
 import numpy as np
-
-EPS_RMS = 1e-30
 
 
 def bf16_round(a) -> np.ndarray:
@@ -39,8 +40,13 @@ def init_params(rng, n_in: int, n_out: int, hidden: int = 64) -> dict:
 
 
 def normalise(x):
-    s = np.sqrt(np.mean(np.asarray(x, dtype=np.float64) ** 2, axis=1, keepdims=True)) + EPS_RMS
-    return x / s, s
+    """(z, s): s = rms of each row (computed scaled by the row's max |x|), z = x / s (0 if s = 0)."""
+    x = np.asarray(x, dtype=np.float64)
+    m = np.abs(x).max(axis=1, keepdims=True)
+    safe = np.where(m > 0, m, 1.0)
+    s = np.where(m > 0, m * np.sqrt(np.mean((x / safe) ** 2, axis=1, keepdims=True)), 0.0)
+    z = np.where(s > 0, x / np.where(s > 0, s, 1.0), 0.0)
+    return z, s
 
 
 def forward(p: dict, z, quantize: bool = False):
@@ -56,15 +62,21 @@ def forward(p: dict, z, quantize: bool = False):
     return y, dict(z=z, a1=a1, h1=h1q, a2=a2, h2=h2q)
 
 
-def mse(y, t) -> float:
-    return float(np.mean((y - t) ** 2))
+def mse(y, t, valid=None) -> float:
+    """Mean of (y - t)^2 over the valid rows (all rows if valid is None) and all outputs."""
+    if valid is None:
+        return float(np.mean((y - t) ** 2))
+    v = np.asarray(valid, dtype=bool).reshape(-1)
+    return float(np.sum((y[v] - t[v]) ** 2) / (v.sum() * y.shape[1])) if v.any() else 0.0
 
 
-def backward(p: dict, cache: dict, y, t, quantize: bool = False) -> dict:
-    """Gradients of mse(y, t) = mean((y - t)^2) by the chain rule."""
+def backward(p: dict, cache: dict, y, t, quantize: bool = False, valid=None) -> dict:
+    """Gradients of mse(y, t, valid) by the chain rule."""
     q = bf16_round if quantize else (lambda a: np.asarray(a, dtype=np.float64))
     B, k = y.shape
-    dy = q(2.0 * (y - t) / (B * k))
+    v = np.ones(B, dtype=bool) if valid is None else np.asarray(valid, dtype=bool).reshape(-1)
+    nv = max(int(v.sum()), 1)
+    dy = q(2.0 * (y - t) / (nv * k) * v[:, None])
     g = {}
     g["W3"] = cache["h2"].T @ dy
     g["b3"] = dy.sum(axis=0)

@@ -451,6 +451,66 @@ lbm_status lbm_lee_reinit(lbm_lee_handle h, const double *rho, const double *u, 
     return s == LBM_OK ? ok() : s;
 }
 
+namespace {
+lbm_status check_region(const lbm_lee *h, const int64_t origin[3], const int64_t n_sub[3]) {
+    if (!origin || !n_sub) return fail(LBM_E_INVALID, "origin and n_sub must not be NULL");
+    for (int a = 0; a < 3; ++a)
+        if (n_sub[a] < 1 || origin[a] < 0 || origin[a] + n_sub[a] > h->desc.n[a])
+            return fail(LBM_E_INVALID, "sub-box (axis %d) must lie inside the box", a);
+    return LBM_OK;
+}
+}  // namespace
+
+lbm_status lbm_lee_reinit_region(lbm_lee_handle h, const int64_t origin[3], const int64_t n_sub[3], const double *rho,
+                                 const double *u, const double *theta, void *stream) {
+    if (!h) return fail(LBM_E_INVALID, "handle is NULL");
+    if (!rho || !u || !theta) return fail(LBM_E_INVALID, "fields must not be NULL");
+    lbm_status s = check_region(h, origin, n_sub);
+    if (s != LBM_OK) return s;
+    h->cur = 0;
+    h->steps = 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    s = visit(h->desc.lattice, h->desc.storage, [&](auto vs, auto sto) -> lbm_status {
+        using VS = decltype(vs);
+        using ST = decltype(sto);
+        auto k = field_coef<VS::Q>(h);
+        auto *dst = static_cast<typename ST::elem *>(h->buf[h->cur]);
+        auto *other = h->skip0 ? static_cast<typename ST::elem *>(h->buf[h->cur ^ 1]) : nullptr;
+        init_region<VS, ST><<<blocks_for(h->N), 256, 0, st>>>(rho, u, theta, dst, other, h->nx, h->ny, h->N,
+                                                              (int)origin[0], (int)origin[1], (int)origin[2],
+                                                              (int)n_sub[0], (int)n_sub[1], (int)n_sub[2], k);
+        return launch_check();
+    });
+    return s == LBM_OK ? ok() : s;
+}
+
+lbm_status lbm_lee_moments_region(lbm_lee_handle h, const int64_t origin[3], const int64_t n_sub[3], void *p, void *u,
+                                  void *rho, void *theta, int32_t out_is_f64, void *stream) {
+    if (!h) return fail(LBM_E_INVALID, "handle is NULL");
+    lbm_status s = check_region(h, origin, n_sub);
+    if (s != LBM_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t Ns = (size_t)(n_sub[0] * n_sub[1] * n_sub[2]);
+    s = visit(h->desc.lattice, h->desc.storage, [&](auto vs, auto sto) -> lbm_status {
+        using VS = decltype(vs);
+        using ST = decltype(sto);
+        auto k = field_coef<VS::Q>(h);
+        const auto *src = static_cast<const typename ST::elem *>(h->buf[h->cur]);
+        const int o0 = (int)origin[0], o1 = (int)origin[1], o2 = (int)origin[2];
+        const int s0 = (int)n_sub[0], s1 = (int)n_sub[1], s2 = (int)n_sub[2];
+        if (out_is_f64)
+            moments_region_kernel<VS, ST, double><<<blocks_for(Ns), 256, 0, st>>>(
+                src, h->N, h->nx, h->ny, o0, o1, o2, s0, s1, s2, k, (double *)p, (double *)u, (double *)rho,
+                (double *)theta);
+        else
+            moments_region_kernel<VS, ST, float><<<blocks_for(Ns), 256, 0, st>>>(
+                src, h->N, h->nx, h->ny, o0, o1, o2, s0, s1, s2, k, (float *)p, (float *)u, (float *)rho,
+                (float *)theta);
+        return launch_check();
+    });
+    return s == LBM_OK ? ok() : s;
+}
+
 lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
     if (!h) return fail(LBM_E_INVALID, "handle is NULL");
     if (nsteps < 0) return fail(LBM_E_INVALID, "nsteps must be >= 0");
@@ -701,7 +761,7 @@ size_t lbm_nrbc_workspace_bytes(int32_t lattice, int64_t count) {
     LatticeTable t;
     if (!build_lattice(lattice, &t) || count < 0) return 0;
     (void)count;
-    return (size_t)kNetGrid * 4 * (size_t)(net_params(t) + 1) * sizeof(float);
+    return (size_t)kNetGrid * 4 * (size_t)(net_params(t) + 1) * sizeof(float) + 256;
 }
 
 lbm_status lbm_nrbc_forward(int32_t lattice, const float *params, const float *strips, int64_t count, float *out,
@@ -729,11 +789,15 @@ lbm_status lbm_nrbc_loss_grad(int32_t lattice, const float *params, const float 
     lbm_status s = visit(lattice, LBM_F32, [&](auto vs, auto) -> lbm_status {
         using VS = decltype(vs);
         using G = NetGeom<VS>;
-        float *ws = static_cast<float *>(workspace);
-        nrbc_grad_kernel<VS><<<kNetGrid, 256, 0, st>>>(params, strips, targets, count, ws);
+        // layout: [counter (256 bytes)][kNetGrid * 4 partial rows]
+        auto *nvalid = static_cast<unsigned long long *>(workspace);
+        float *ws = reinterpret_cast<float *>(static_cast<char *>(workspace) + 256);
+        nrbc_zero_counter<<<1, 1, 0, st>>>(nvalid);
+        nrbc_count_valid<VS><<<blocks_for((size_t)count), 256, 0, st>>>(strips, count, nvalid);
+        nrbc_grad_kernel<VS><<<kNetGrid, 256, 0, st>>>(params, strips, targets, count, nvalid, ws);
         lbm_status ls = launch_check();
         if (ls != LBM_OK) return ls;
-        nrbc_reduce_kernel<<<(G::NPARAM + 1 + 255) / 256, 256, 0, st>>>(ws, kNetGrid * 4, G::NPARAM, count, G::NOUT,
+        nrbc_reduce_kernel<<<(G::NPARAM + 1 + 255) / 256, 256, 0, st>>>(ws, kNetGrid * 4, G::NPARAM, nvalid, G::NOUT,
                                                                        grad, loss);
         return launch_check();
     });

@@ -356,6 +356,41 @@ __global__ __launch_bounds__(256) void init_equilibrium(const double *__restrict
     }
 }
 
+// Equilibrium of fields given on a sub-box (n_sub cells at origin o), zero elsewhere.
+template <class VS, class ST>
+__global__ __launch_bounds__(256) void init_region(const double *__restrict__ rho, const double *__restrict__ u,
+                                                   const double *__restrict__ theta,
+                                                   typename ST::elem *__restrict__ dst,
+                                                   typename ST::elem *__restrict__ rest_copy, int nx, int ny, size_t N,
+                                                   int ox, int oy, int oz, int sx, int sy, int sz,
+                                                   FieldCoef<VS::Q> k) {
+    const size_t cell = (size_t)blockIdx.x * 256u + threadIdx.x;
+    if (cell >= N) return;
+    const int x = (int)(cell % nx) - ox;
+    const size_t r = cell / nx;
+    const int y = (int)(r % ny) - oy, z = (int)(r / ny) - oz;
+    double rr = 0, th = 0, ux = 0, uy = 0, uz = 0;
+    if (x >= 0 && x < sx && y >= 0 && y < sy && z >= 0 && z < sz) {
+        const size_t Ns = (size_t)sx * sy * sz;
+        const size_t sc = ((size_t)z * sy + y) * sx + x;
+        rr = rho[sc];
+        th = theta[sc];
+        ux = u[sc];
+        if (VS::D >= 2) uy = u[Ns + sc];
+        if (VS::D >= 3) uz = u[2 * Ns + sc];
+    }
+    const double A = k.a1 * rr + k.a2 * th;
+    const double C = k.c1 * rr + k.c2 * th;
+#pragma unroll
+    for (int i = 0; i < VS::Q; ++i) {
+        const double cu = VS::cx(i) * ux + VS::cy(i) * uy + VS::cz(i) * uz;
+        const double geq = k.f[i] * (A + k.b * cu + 0.5 * VS::c2(i) * C);
+        const typename ST::elem v = ST::enc_d(k.enc[i] * geq);
+        dst[(size_t)i * N + cell] = v;
+        if (i == 0 && rest_copy) rest_copy[cell] = v;
+    }
+}
+
 // ------------------------------------------------------------------ block reductions (FP64)
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -470,6 +505,30 @@ __global__ __launch_bounds__(256) void moments_kernel(const typename ST::elem *_
     if (u)
 #pragma unroll
         for (int a = 0; a < VS::D; ++a) u[(size_t)a * N + cell] = (OT)uu[a];
+}
+
+// Moments of the cells of a sub-box (n_sub cells at origin o); outputs are sub-box arrays.
+template <class VS, class ST, typename OT>
+__global__ __launch_bounds__(256) void moments_region_kernel(const typename ST::elem *__restrict__ src, size_t N,
+                                                             int nx, int ny, int ox, int oy, int oz, int sx, int sy,
+                                                             int sz, FieldCoef<VS::Q> k, OT *__restrict__ p,
+                                                             OT *__restrict__ u, OT *__restrict__ rho,
+                                                             OT *__restrict__ theta) {
+    const size_t Ns = (size_t)sx * sy * sz;
+    const size_t sc = (size_t)blockIdx.x * 256u + threadIdx.x;
+    if (sc >= Ns) return;
+    const int x = (int)(sc % sx);
+    const size_t r = sc / sx;
+    const int y = (int)(r % sy), z = (int)(r / sy);
+    const size_t cell = ((size_t)(z + oz) * ny + (y + oy)) * nx + (x + ox);
+    double rr, uu[3], th, pp;
+    cell_moments<VS, ST>(src, N, cell, k, rr, uu, th, pp);
+    if (p) p[sc] = (OT)pp;
+    if (rho) rho[sc] = (OT)rr;
+    if (theta) theta[sc] = (OT)th;
+    if (u)
+#pragma unroll
+        for (int a = 0; a < VS::D; ++a) u[(size_t)a * Ns + sc] = (OT)uu[a];
 }
 
 // Error against reference fields: per-block partials of

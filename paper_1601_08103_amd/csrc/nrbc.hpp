@@ -4,7 +4,8 @@
 // populations at a face node (3 cells deep along the inward normal, Q values each, in the
 // canonical face frame) to the k populations that enter the box through the face:
 //   s = rms(x), z = x / s, h1 = relu(z W1 + b1), h2 = relu(h1 W2 + b2), y = h2 W3 + b3,
-//   prediction = s y.
+//   prediction = s y;  s is computed as m sqrt(mean((x/m)^2)), m = max |x|, so tiny strips do
+//   not underflow; an all-zero strip has s = 0, z = 0 and predicts 0.
 // Parameters are FP32 (master copy, layout W1[n_in][64], b1[64], W2[64][64], b2[64],
 // W3[64][k], b3[k], row-major).  Every matrix product takes bfloat16 inputs (round to
 // nearest even) and accumulates in FP32 on v_mfma_f32_16x16x16_bf16; biases are added in FP32.
@@ -182,24 +183,32 @@ template <class VS, class LoadFn>
 __device__ float load_normalised_tile(WaveTiles &T, int nrows, int lane, LoadFn X) {
     using G = NetGeom<VS>;
     const int r = lane & 15, g = lane >> 4;
-    float ss = 0.0f;
     float vals[(G::NIN_PAD + 3) / 4];
+    float m = 0.0f;
 #pragma unroll
     for (int t = 0; t < (G::NIN_PAD + 3) / 4; ++t) {
         const int v = g + 4 * t;
         float x = 0.0f;
         if (r < nrows && v < G::NIN) x = X(r, v);
         vals[t] = x;
-        ss += x * x;
+        m = fmaxf(m, fabsf(x));
+    }
+    m = fmaxf(m, __shfl_xor(m, 16, 64));
+    m = fmaxf(m, __shfl_xor(m, 32, 64));
+    // divisions (not reciprocals): m and s may be FP32 denormals, whose reciprocal overflows
+    float ss = 0.0f;
+#pragma unroll
+    for (int t = 0; t < (G::NIN_PAD + 3) / 4; ++t) {
+        const float q = m > 0.0f ? vals[t] / m : 0.0f;
+        ss += q * q;
     }
     ss += __shfl_xor(ss, 16, 64);
     ss += __shfl_xor(ss, 32, 64);
-    const float s = sqrtf(ss / (float)G::NIN) + 1e-30f;
-    const float inv = 1.0f / s;
+    const float s = m * sqrtf(ss / (float)G::NIN);
 #pragma unroll
     for (int t = 0; t < (G::NIN_PAD + 3) / 4; ++t) {
         const int v = g + 4 * t;
-        if (v < G::NIN_PAD) T.z[r][v] = v < G::NIN ? bf16_bits(vals[t] * inv) : (unsigned short)0;
+        if (v < G::NIN_PAD) T.z[r][v] = (v < G::NIN && s > 0.0f) ? bf16_bits(vals[t] / s) : (unsigned short)0;
     }
     wave_lds_sync();
     return s;
@@ -246,6 +255,7 @@ __global__ __launch_bounds__(256) void nrbc_forward_kernel(const float *__restri
 template <class VS>
 __global__ __launch_bounds__(256) void nrbc_grad_kernel(const float *__restrict__ P, const float *__restrict__ strips,
                                                         const float *__restrict__ targets, long long count,
+                                                        const unsigned long long *__restrict__ nvalid,
                                                         float *__restrict__ ws) {
     using G = NetGeom<VS>;
     constexpr int MT1 = G::NIN_PAD / 16;
@@ -253,7 +263,7 @@ __global__ __launch_bounds__(256) void nrbc_grad_kernel(const float *__restrict_
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     WaveTiles &T = tiles[wid];
     const int row0 = 4 * (lane >> 4), col = lane & 15;
-    const float inv_n = (float)(1.0 / ((double)count * G::NOUT));
+    const float inv_n = (float)(1.0 / ((double)(*nvalid ? *nvalid : 1ull) * G::NOUT));
     bf16x4 ones;
     ones.x = ones.y = ones.z = ones.w = (short)0x3f80;  // bf16 1.0
     const floatx4 zero = {0, 0, 0, 0};
@@ -284,7 +294,7 @@ __global__ __launch_bounds__(256) void nrbc_grad_kernel(const float *__restrict_
             const int row = row0 + e;
             const float srow = __shfl(s, row, 64);
             float d = 0.0f;
-            if (row < nrows && col < G::NOUT) {
+            if (row < nrows && col < G::NOUT && srow > 0.0f) {
                 const float t = targets[(base + row) * G::NOUT + col] / srow;
                 const float diff = y[e] - t;
                 sq += diff * diff;
@@ -376,10 +386,25 @@ __global__ __launch_bounds__(256) void nrbc_grad_kernel(const float *__restrict_
     if (lane == 0) out[G::NPARAM] = sq;
 }
 
+__global__ void nrbc_zero_counter(unsigned long long *c) { *c = 0ull; }
+
+// Number of strips with at least one non-zero value (the samples the loss averages over).
+template <class VS>
+__global__ __launch_bounds__(256) void nrbc_count_valid(const float *__restrict__ strips, long long count,
+                                                        unsigned long long *__restrict__ out) {
+    using G = NetGeom<VS>;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    bool nz = false;
+    if (t < count)
+        for (int v = 0; v < G::NIN; ++v) nz = nz || strips[t * G::NIN + v] != 0.0f;
+    const unsigned long long b = __ballot(nz);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(out, (unsigned long long)__popcll(b));
+}
+
 // grad[p] = sum over waves of ws[w][p] (fixed order); loss = sum of the squared errors / (count k).
 __global__ __launch_bounds__(256) void nrbc_reduce_kernel(const float *__restrict__ ws, int nwaves, int nparam,
-                                                          long long count, int nout, float *__restrict__ grad,
-                                                          float *__restrict__ loss) {
+                                                          const unsigned long long *__restrict__ nvalid, int nout,
+                                                          float *__restrict__ grad, float *__restrict__ loss) {
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p > nparam) return;
     double acc = 0.0;
@@ -387,7 +412,7 @@ __global__ __launch_bounds__(256) void nrbc_reduce_kernel(const float *__restric
     if (p < nparam)
         grad[p] = (float)acc;
     else if (loss)
-        *loss = (float)(acc / ((double)count * nout));
+        *loss = *nvalid ? (float)(acc / ((double)*nvalid * nout)) : 0.0f;
 }
 
 // Adam (Kingma & Ba) on FP32 master parameters; t counts from 1.

@@ -58,6 +58,10 @@ SIGNATURES = {
                                       ctypes.POINTER(_VP)]),
     "lbm_lee_reinit": (ctypes.c_int32, [_VP, _VP, _VP, _VP, _VP]),
     "lbm_lee_step": (ctypes.c_int32, [_VP, ctypes.c_int64, _VP]),
+    "lbm_lee_reinit_region": (ctypes.c_int32, [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                               _VP, _VP, _VP, _VP]),
+    "lbm_lee_moments_region": (ctypes.c_int32, [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                                _VP, _VP, _VP, _VP, ctypes.c_int32, _VP]),
     "lbm_lee_moments": (ctypes.c_int32, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int32, _VP]),
     "lbm_lee_l2_energy": (ctypes.c_int32, [_VP, ctypes.POINTER(ctypes.c_double), _VP]),
     "lbm_lee_error_norms": (ctypes.c_int32, [_VP, _VP, _VP, ctypes.POINTER(ctypes.c_double), _VP]),
@@ -162,6 +166,16 @@ def lbm_lee_init(desc, pop_a, pop_b, bytes_each, rho, u, theta, scratch, scratch
 
 def lbm_lee_reinit(h, rho, u, theta, stream):
     _check("lbm_lee_reinit", load().lbm_lee_reinit(h, rho, u, theta, stream))
+
+
+def lbm_lee_reinit_region(h, origin, n_sub, rho, u, theta, stream):
+    _check("lbm_lee_reinit_region", load().lbm_lee_reinit_region(h, _i64x3(origin), _i64x3(n_sub), rho, u, theta,
+                                                                 stream))
+
+
+def lbm_lee_moments_region(h, origin, n_sub, p, u, rho, theta, out_is_f64, stream):
+    _check("lbm_lee_moments_region", load().lbm_lee_moments_region(h, _i64x3(origin), _i64x3(n_sub), p, u, rho, theta,
+                                                                   int(out_is_f64), stream))
 
 
 def lbm_lee_step(h, nsteps, stream):
@@ -328,6 +342,38 @@ class Solver:
 
     def step(self, n: int = 1):
         lbm_lee_step(self.h, n, self.s)
+
+    def reinit_region(self, origin_xyz, sub_shape, rho, u, theta):
+        """Equilibrium of fields given on a sub-box (C-order shape sub_shape at cell offset
+        origin_xyz = (x, y, z)), the state at rest elsewhere."""
+        t = self.torch
+        sub = tuple(int(v) for v in sub_shape)
+        n = int(np.prod(sub))
+        def dev(a, m):
+            a = t.as_tensor(a, dtype=t.float64).to("cuda").contiguous()
+            if a.numel() != m:
+                raise ValueError("field size does not match the sub-box")
+            return a
+        self._keep = (dev(rho, n), dev(u, self.D * n), dev(theta, n))
+        dims = list(reversed(sub)) + [1] * (3 - len(sub))
+        org = list(origin_xyz) + [0] * (3 - len(origin_xyz))
+        lbm_lee_reinit_region(self.h, org, dims, self._keep[0].data_ptr(), self._keep[1].data_ptr(),
+                              self._keep[2].data_ptr(), self.s)
+
+    def moments_region(self, origin_xyz, sub_shape, f64: bool = True) -> dict:
+        t = self.torch
+        sub = tuple(int(v) for v in sub_shape)
+        n = int(np.prod(sub))
+        dt = t.float64 if f64 else t.float32
+        out = {k: t.empty(n, dtype=dt, device="cuda") for k in ("p", "rho", "theta")}
+        out["u"] = t.empty(self.D * n, dtype=dt, device="cuda")
+        dims = list(reversed(sub)) + [1] * (3 - len(sub))
+        org = list(origin_xyz) + [0] * (3 - len(origin_xyz))
+        lbm_lee_moments_region(self.h, org, dims, out["p"].data_ptr(), out["u"].data_ptr(), out["rho"].data_ptr(),
+                               out["theta"].data_ptr(), int(f64), self.s)
+        res = {k: v.view(sub) for k, v in out.items() if k != "u"}
+        res["u"] = out["u"].view((self.D,) + sub)
+        return res
 
     def moments(self, f64: bool = True) -> dict:
         t = self.torch
