@@ -88,7 +88,12 @@ typedef int32_t lbm_status;
  *   SPONGE  as ZERO, and after the collision the state is damped by
  *           1 - sponge_sigma ((W - d) / W)^2 at distance d < W = sponge_width from the faces;
  *   MLP     a learned prediction (lbm_lee_set_closure) for the face node clamp(s); for a source
- *           beyond an edge or corner, the mean of the predictions of every face it lies beyond. */
+ *           beyond an edge or corner, the mean of the predictions of every face it lies beyond.
+ *           Each face prediction at node p is limited in weighted energy (sum g^2 / f*) to
+ *           E_out / (2^n - 1), E_out the energy of p's populations leaving through that face and
+ *           n the number of faces p lies on (scaled down, direction kept), so the energy that
+ *           enters at p never exceeds the energy that leaves it: at tau = 1/2 the open box's
+ *           weighted energy cannot grow, whatever the network predicts. */
 #define LBM_BC_PERIODIC 0
 #define LBM_BC_ZERO 1
 #define LBM_BC_COPY 2
@@ -168,7 +173,11 @@ lbm_status lbm_lee_reinit(lbm_lee_handle h, const double *rho, const double *u, 
 /* Re-initialise to the equilibrium of fields given on a sub-box only (n_sub cells at cell
  * offset origin; rho, theta: n_sub cells, u: D * n_sub, same layout rules), with the fields zero
  * (the state at rest) on every other cell.  Lets a large box (e.g. the wider periodic run that
- * judges an open box) start from a small initial state without full-size field arrays. */
+ * judges an open box) start from a small initial state without full-size field arrays.
+ * Like lbm_lee_reinit it keeps the handle's storage scale: for the 16-bit formats create the
+ * handle with desc.store_scale set when its first fields are at rest (the automatic choice
+ * then has no amplitude to go by and takes 1).  Errors: LBM_E_INVALID for a NULL pointer or a
+ * sub-box not inside the box. */
 lbm_status lbm_lee_reinit_region(lbm_lee_handle h, const int64_t origin[3], const int64_t n_sub[3], const double *rho,
                                  const double *u, const double *theta, void *stream);
 

@@ -26,6 +26,16 @@ p = clamp(s) is the face node.  A source outside along one axis takes that face'
 prediction at p; a source beyond an edge or a corner takes the mean of the predictions of
 every face it lies beyond (the same node p), which keeps the closure symmetric under the
 box's symmetries.
+The network's prediction at p for a face is then limited in energy (weighted norm
+sum g^2 / f*, conserved by the collision at tau = 1/2 and by streaming): with E_in the energy
+of the k predicted values and E_out that of the populations leaving p through the face
+(canonical c'_x = -1), the prediction is scaled by sqrt(B / E_in) when E_in > B, where
+B = E_out / (2^n - 1) and n is the number of faces p lies on.  Every ghost value pulled into
+the box is attributed to its node p; a face prediction at p feeds the ghost cells beyond
+every subset of p's faces that contains the face, at most (2^n - 1) / n times its energy in
+total (mean over faces, Jensen), while the populations leaving p carry at least the mean of
+the n face energies E_out.  So the energy entering at p never exceeds the energy leaving p,
+and the open box's energy cannot grow, whatever the network predicts.
 A signed axis permutation M maps the face's outward normal to -x (the canonical face), so
 one network serves every face:  (a,0): identity; (a,1): negate axis a; then axis a is
 swapped with x.  In the canonical frame the populations that enter through the face are
@@ -104,8 +114,33 @@ def _out_faces(idx, shape, D):
     return out
 
 
-def ghost_values(lat: Lattice, g, closure: str, params: dict | None = None, quantize: bool = False):
-    """Padded populations (Q, n+2 per axis) whose one-cell shell holds the closure's ghosts."""
+def node_face_count(p, shape, D) -> int:
+    """Number of faces the box cell p (C-order index) lies on."""
+    n = 0
+    for a in range(D):
+        ax = D - 1 - a
+        n += int(p[ax] == 0) + int(p[ax] == shape[ax] - 1)
+    return n
+
+
+def energy_limit(lat: Lattice, x, y, nfaces: int) -> np.ndarray:
+    """Scale the prediction y (k entering values, canonical order) so that its weighted energy
+    is at most E_out / (2^nfaces - 1), E_out from the populations of the strip's first cell
+    that leave through the face (canonical c'_x = -1)."""
+    jin = incoming_canonical(lat)
+    jout = np.where(lat.c[:, 0] == -1)[0]
+    e_in = float(np.sum(np.asarray(y) ** 2 / lat.fstar[jin]))
+    e_out = float(np.sum(np.asarray(x)[jout] ** 2 / lat.fstar[jout]))
+    budget = e_out / (2 ** nfaces - 1)
+    if e_in > budget:
+        return np.asarray(y) * np.sqrt(budget / e_in)
+    return np.asarray(y)
+
+
+def ghost_values(lat: Lattice, g, closure: str, params: dict | None = None, quantize: bool = False,
+                 limit: bool = True):
+    """Padded populations (Q, n+2 per axis) whose one-cell shell holds the closure's ghosts.
+    limit=False drops the energy limit of the network closure (a test device)."""
     shape = g.shape[1:]
     D = lat.D
     pad = np.zeros((lat.Q,) + tuple(n + 2 for n in shape))
@@ -135,8 +170,9 @@ def ghost_values(lat: Lattice, g, closure: str, params: dict | None = None, quan
             for a, side in fs:
                 key = (a, side, p)
                 if key not in cache:
-                    x = strip(lat, g, a, side, p)[None, :]
-                    cache[key] = mlp_ref.predict(params, x, quantize)[0]
+                    x = strip(lat, g, a, side, p)
+                    y = mlp_ref.predict(params, x[None, :], quantize)[0]
+                    cache[key] = energy_limit(lat, x, y, node_face_count(p, shape, D)) if limit else y
                 perm = canonical_perm(lat, a, side)
                 for r, j in enumerate(jin):
                     acc.setdefault(perm[j], []).append(cache[key][r])
@@ -161,11 +197,12 @@ def sponge_factor(shape, D, width: int, sigma_max: float) -> np.ndarray:
 
 
 def step_open(lat: Lattice, g, closure: str, tau: float = 0.5, params: dict | None = None,
-              sponge_width: int = 0, sponge_sigma: float = 0.0, quantize: bool = False) -> np.ndarray:
+              sponge_width: int = 0, sponge_sigma: float = 0.0, quantize: bool = False,
+              limit: bool = True) -> np.ndarray:
     """One step of the open-box scheme on the post-collision state g (Q, *shape)."""
     shape = g.shape[1:]
     D = lat.D
-    pad = ghost_values(lat, g, closure, params, quantize)
+    pad = ghost_values(lat, g, closure, params, quantize, limit)
     pulled = np.empty_like(g)
     for i in range(lat.Q):
         sl = []

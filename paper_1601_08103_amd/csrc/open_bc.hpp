@@ -165,13 +165,20 @@ __global__ __launch_bounds__(256) void sponge_kernel(typename ST::elem *__restri
 
 // ------------------------------------------------------------------ network ghosts
 // Every face node: strip (3 cells x Q populations, canonical order, physical units) ->
-// network -> the K entering populations (physical units) into ghost[node * K + r].
+// network -> the K entering populations (physical units) into ghost[node * K + r], limited in
+// energy: with E_in = sum_r y_r^2 / f*, E_out = sum over the node's populations leaving through
+// the face (canonical c_x = -1) of g^2 / f*, and n the number of faces the node lies on, y is
+// scaled by sqrt(B / E_in) when E_in > B = E_out / (2^n - 1).  Each ghost value pulled into the
+// box belongs to one node, and a face prediction feeds at most (2^n - 1) / n of its energy into
+// the box (means over faces), so the energy entering at a node never exceeds the energy leaving
+// it: the open box cannot gain energy at tau = 1/2 whatever the network predicts.
 template <class VS, class ST>
 __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem *__restrict__ src, size_t N,
                                                         const float *__restrict__ P, float *__restrict__ ghost,
                                                         FaceTab<VS::Q> ft, FieldCoef<VS::Q> fk) {
     using G = NetGeom<VS>;
     __shared__ WaveTiles tiles[4];
+    __shared__ float pred[4][16][G::NOUT];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     WaveTiles &T = tiles[wid];
     const long long count = ft.node_off[ft.nfaces];
@@ -198,7 +205,30 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
         for (int e = 0; e < 4; ++e) {
             const int row = 4 * (lane >> 4) + e;
             const float srow = __shfl(s, row, 64);
-            if (row < nrows && col < G::NOUT) ghost[(base + row) * G::NOUT + col] = srow * y[e];
+            if (row < nrows && col < G::NOUT) pred[wid][row][col] = srow * y[e];
+        }
+        wave_lds_sync();
+        if (lane < nrows) {  // lane == r: this lane's node is row `lane`
+            const size_t cell = ((size_t)p[2] * ft.n[1] + p[1]) * ft.n[0] + p[0];
+            double e_in = 0.0, e_out = 0.0;
+#pragma unroll
+            for (int k = 0; k < G::NOUT; ++k) {
+                const double v = pred[wid][lane][k];
+                e_in += v * v / fk.f[ft.perm[f][entering_index<VS>(k)]];
+            }
+#pragma unroll
+            for (int j = 0; j < VS::Q; ++j) {
+                if (VS::cx(j) != -1) continue;
+                const int i = ft.perm[f][j];
+                const double g = fk.dec[i] * (double)ST::dec(src[(size_t)i * N + cell]);
+                e_out += g * g / fk.f[i];
+            }
+            int nf = 0;
+            for (int b = 0; b < VS::D; ++b) nf += (p[b] == 0) + (p[b] == ft.n[b] - 1);
+            const double budget = e_out / (double)((1 << nf) - 1);
+            const float sc = e_in > budget ? (float)sqrt(budget / e_in) : 1.0f;
+#pragma unroll
+            for (int k = 0; k < G::NOUT; ++k) ghost[(base + lane) * G::NOUT + k] = sc * pred[wid][lane][k];
         }
         wave_lds_sync();
     }

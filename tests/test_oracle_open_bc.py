@@ -97,9 +97,56 @@ def test_network_closure_plumbing_against_copy(name):
     lat = L.get(name)
     shape = {2: (7, 9), 3: (4, 5, 6)}[lat.D]
     g = np.random.default_rng(2).standard_normal((lat.Q,) + shape)
-    a = ob.step_open(lat, g, "mlp", params=_copy_network(lat))
+    a = ob.step_open(lat, g, "mlp", params=_copy_network(lat), limit=False)
     b = ob.step_open(lat, g, "copy")
     assert np.abs(a - b).max() < 1e-14 * np.abs(b).max()
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D2Q5", "D3Q7", "D3Q19", "D1Q3"])
+def test_network_closure_never_adds_energy(name):
+    """With the energy limit, a network closure cannot raise the weighted energy of the open box
+    at tau = 1/2, whatever it predicts: random networks with large biases, random states, every
+    step.  Without the limit the same networks do raise it (so the property is not vacuous)."""
+    lat = L.get(name)
+    shape = {1: (9,), 2: (7, 9), 3: (4, 5, 6)}[lat.D]
+    k = len(ob.incoming_canonical(lat))
+    grew_without = False
+    for seed in range(3):
+        rng = np.random.default_rng(100 + seed)
+        p = mlp.init_params(rng, 3 * lat.Q, k)
+        p["b1"] = rng.standard_normal(64)
+        p["b3"] = 3.0 * rng.standard_normal(k)
+        g = rng.standard_normal((lat.Q,) + shape) * lat.fstar.reshape((-1,) + (1,) * lat.D)
+        e0 = lbe.weighted_energy(lat, g)
+        h = g
+        for _ in range(6):
+            h2 = ob.step_open(lat, h, "mlp", params=p)
+            assert lbe.weighted_energy(lat, h2) <= lbe.weighted_energy(lat, h) * (1 + 1e-12)
+            h = h2
+        grew_without |= lbe.weighted_energy(lat, ob.step_open(lat, g, "mlp", params=p, limit=False)) > e0
+    assert grew_without
+
+
+def test_energy_limit_budget_by_face_count():
+    """The limit scales a prediction to E_out / (2^n - 1) only when it exceeds that budget."""
+    lat = L.get("D2Q9")
+    jin = ob.incoming_canonical(lat)
+    jout = np.where(lat.c[:, 0] == -1)[0]
+    x = np.zeros(3 * lat.Q)
+    x[jout] = [1.0, 2.0, -1.0]
+    e_out = float(np.sum(x[jout] ** 2 / lat.fstar[jout]))
+    y = np.array([3.0, -1.0, 0.5])
+    e_in = float(np.sum(y ** 2 / lat.fstar[jin]))
+    for n in (1, 2, 3):
+        got = ob.energy_limit(lat, x, y, n)
+        budget = e_out / (2 ** n - 1)
+        if e_in > budget:
+            assert abs(float(np.sum(got ** 2 / lat.fstar[jin])) - budget) < 1e-12 * budget
+            assert np.allclose(got / y, got[0] / y[0])
+        else:
+            assert np.array_equal(got, y)
+    small = y * 1e-3
+    assert np.array_equal(ob.energy_limit(lat, x, small, 1), small)
 
 
 def test_face_frames_are_lattice_symmetries():
