@@ -157,7 +157,9 @@ double lbm_lee_bytes_per_update(const lbm_lee_desc *desc);
  * given macroscopic fields (Section "Analysis of the LBE": g_i(0, x) = g_i^eq(rho', u', theta')).
  *   pop_a, pop_b  device buffers of bytes_each >= lbm_lee_state_bytes(desc), 256-byte aligned;
  *                 the state ping-pongs between them.
- *   rho, theta    device FP64 arrays of N values; u: device FP64, D * N values.
+ *   rho, theta    device FP64 arrays of N values; u: device FP64, D * N values.  All three
+ *                 NULL: the state at rest (zero fields; the 16-bit storage scale is then
+ *                 desc->store_scale, or 1 when that is 0).
  *   scratch       device buffer of scratch_bytes >= lbm_lee_scratch_bytes(desc), 256-byte aligned.
  * Synchronises `stream` only when desc->store_scale == 0 with 16-bit storage (it reads back
  * the maximum of |g / f*| to choose S).  On failure *out is NULL and nothing is enqueued.
@@ -293,6 +295,11 @@ lbm_status lbm_nrbc_adam(int64_t n, float *params, const float *grad, float *m, 
  * on every axis): for each face node id of the inner box (device int64 ids), the strip at the
  * node (strips [count][n_in]) and the true entering populations, i.e. the outer state at the
  * node's outside neighbour (targets [count][n_out]), physical FP32 values.
+ * targets may be NULL: strips only, and then origin >= 0, origin + n <= outer n suffice, so
+ * `outer` may be the open box itself (origin 0, inner = its own desc): the strips its closure
+ * sees, for training on the states the closed loop actually visits.  Ids outside
+ * [0, lbm_nrbc_face_nodes(inner)) give zero rows.  Errors: LBM_E_INVALID for NULL arguments,
+ * count < 0, differing lattices or a misplaced inner box.
  */
 lbm_status lbm_nrbc_gather(lbm_lee_handle outer, const int64_t origin[3], const lbm_lee_desc *inner,
                            const int64_t *node_ids, int64_t count, float *strips, float *targets, void *stream);

@@ -304,6 +304,23 @@ lbm_status launch_init(lbm_lee *h, const double *rho, const double *u, const dou
     });
 }
 
+// Equilibrium of fields given on a sub-box (n_sub cells at origin), the state at rest elsewhere;
+// n_sub = {0, 0, 0} sets the whole box at rest (the field pointers are then not read).
+lbm_status launch_init_region(lbm_lee *h, const int64_t origin[3], const int64_t n_sub[3], const double *rho,
+                              const double *u, const double *theta, hipStream_t st) {
+    return visit(h->desc.lattice, h->desc.storage, [&](auto vs, auto sto) -> lbm_status {
+        using VS = decltype(vs);
+        using ST = decltype(sto);
+        auto k = field_coef<VS::Q>(h);
+        auto *dst = static_cast<typename ST::elem *>(h->buf[h->cur]);
+        auto *other = h->skip0 ? static_cast<typename ST::elem *>(h->buf[h->cur ^ 1]) : nullptr;
+        init_region<VS, ST><<<blocks_for(h->N), 256, 0, st>>>(rho, u, theta, dst, other, h->nx, h->ny, h->N,
+                                                              (int)origin[0], (int)origin[1], (int)origin[2],
+                                                              (int)n_sub[0], (int)n_sub[1], (int)n_sub[2], k);
+        return launch_check();
+    });
+}
+
 lbm_status choose_scale(lbm_lee *h, const double *rho, const double *u, const double *theta, hipStream_t st) {
     if (!is_scaled(h->desc.storage)) {
         h->S = 1.0;
@@ -404,7 +421,9 @@ lbm_status lbm_lee_init(const lbm_lee_desc *desc, void *pop_a, void *pop_b, size
     if (bytes_each < need) return fail(LBM_E_INVALID, "population buffers hold %zu bytes, need %zu", bytes_each, need);
     const char *a = static_cast<const char *>(pop_a), *b = static_cast<const char *>(pop_b);
     if (a < b + need && b < a + need) return fail(LBM_E_INVALID, "population buffers overlap");
-    if (!rho || !u || !theta) return fail(LBM_E_INVALID, "initial fields must not be NULL");
+    const bool at_rest = !rho && !u && !theta;
+    if (!at_rest && (!rho || !u || !theta))
+        return fail(LBM_E_INVALID, "initial fields must be all given or all NULL (the state at rest)");
     if (!scratch || !aligned256(scratch) || scratch_bytes < kScratchBytes)
         return fail(LBM_E_INVALID, "scratch must be 256-byte aligned and hold >= %zu bytes", kScratchBytes);
     lbm_lee *h = new (std::nothrow) lbm_lee;
@@ -434,7 +453,14 @@ lbm_status lbm_lee_init(const lbm_lee_desc *desc, void *pop_a, void *pop_b, size
         (void)hipGetLastError();
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if ((s = choose_scale(h, rho, u, theta, st)) != LBM_OK || (s = launch_init(h, rho, u, theta, st)) != LBM_OK) {
+    if (at_rest) {
+        const int64_t zero[3] = {0, 0, 0};
+        h->S = (is_scaled(desc->storage) && desc->store_scale > 0.0) ? desc->store_scale : 1.0;
+        s = launch_init_region(h, zero, zero, nullptr, nullptr, nullptr, st);
+    } else if ((s = choose_scale(h, rho, u, theta, st)) == LBM_OK) {
+        s = launch_init(h, rho, u, theta, st);
+    }
+    if (s != LBM_OK) {
         delete h;
         return s;
     }
@@ -469,18 +495,7 @@ lbm_status lbm_lee_reinit_region(lbm_lee_handle h, const int64_t origin[3], cons
     if (s != LBM_OK) return s;
     h->cur = 0;
     h->steps = 0;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    s = visit(h->desc.lattice, h->desc.storage, [&](auto vs, auto sto) -> lbm_status {
-        using VS = decltype(vs);
-        using ST = decltype(sto);
-        auto k = field_coef<VS::Q>(h);
-        auto *dst = static_cast<typename ST::elem *>(h->buf[h->cur]);
-        auto *other = h->skip0 ? static_cast<typename ST::elem *>(h->buf[h->cur ^ 1]) : nullptr;
-        init_region<VS, ST><<<blocks_for(h->N), 256, 0, st>>>(rho, u, theta, dst, other, h->nx, h->ny, h->N,
-                                                              (int)origin[0], (int)origin[1], (int)origin[2],
-                                                              (int)n_sub[0], (int)n_sub[1], (int)n_sub[2], k);
-        return launch_check();
-    });
+    s = launch_init_region(h, origin, n_sub, rho, u, theta, static_cast<hipStream_t>(stream));
     return s == LBM_OK ? ok() : s;
 }
 
@@ -817,15 +832,16 @@ lbm_status lbm_nrbc_adam(int64_t n, float *params, const float *grad, float *m, 
 
 lbm_status lbm_nrbc_gather(lbm_lee_handle outer, const int64_t origin[3], const lbm_lee_desc *inner,
                            const int64_t *node_ids, int64_t count, float *strips, float *targets, void *stream) {
-    if (!outer || !origin || !inner || !node_ids || !strips || !targets || count < 0)
-        return fail(LBM_E_INVALID, "bad arguments");
+    if (!outer || !origin || !inner || !node_ids || !strips || count < 0) return fail(LBM_E_INVALID, "bad arguments");
     LatticeTable t;
     lbm_status s = check_desc(inner, &t);
     if (s != LBM_OK) return s;
     if (inner->lattice != outer->desc.lattice) return fail(LBM_E_INVALID, "inner and outer lattices differ");
+    const int spare = targets ? 1 : 0;  // targets read one cell beyond the inner box
     for (int a = 0; a < t.D; ++a)
-        if (origin[a] < 1 || origin[a] + inner->n[a] + 1 > outer->desc.n[a] || inner->n[a] < 3)
-            return fail(LBM_E_INVALID, "inner box (axis %d) must sit inside the outer box with one cell to spare", a);
+        if (origin[a] < spare || origin[a] + inner->n[a] + spare > outer->desc.n[a] || inner->n[a] < 3)
+            return fail(LBM_E_INVALID, "inner box (axis %d) must sit inside the outer box%s", a,
+                        targets ? " with one cell to spare" : "");
     if (count == 0) return ok();
     hipStream_t st = static_cast<hipStream_t>(stream);
     s = visit(outer->desc.lattice, outer->desc.storage, [&](auto vs, auto sto) -> lbm_status {

@@ -237,7 +237,8 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
 // ------------------------------------------------------------------ training pairs
 // For inner-box face nodes (ids in the inner box's numbering), read the state of a larger
 // run whose cell origin + x is inner cell x: the strip at the node (inputs) and the
-// entering populations at the node's outside neighbour (targets), physical units.
+// entering populations at the node's outside neighbour (targets, skipped when NULL),
+// physical units.  Ids outside the face-node range give zeros.
 template <class VS, class ST>
 __global__ __launch_bounds__(256) void gather_pairs_kernel(const typename ST::elem *__restrict__ src, size_t N,
                                                            int onx, int ony, int ox, int oy, int oz,
@@ -247,8 +248,15 @@ __global__ __launch_bounds__(256) void gather_pairs_kernel(const typename ST::el
     using G = NetGeom<VS>;
     const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
     if (t >= count) return;
+    const long long id = ids[t];
+    if (id < 0 || id >= ft.node_off[ft.nfaces]) {  // not a face node: zeros
+        for (int v = 0; v < G::NIN; ++v) strips[t * G::NIN + v] = 0.0f;
+        if (targets)
+            for (int r = 0; r < G::NOUT; ++r) targets[t * G::NOUT + r] = 0.0f;
+        return;
+    }
     int p[3];
-    const int f = node_cell(ft, ids[t], p);
+    const int f = node_cell(ft, id, p);
     const int a = f >> 1, step = (f & 1) ? -1 : 1;
     const int o[3] = {ox, oy, oz};
     auto outer_cell = [&](const int (&q)[3]) {
@@ -263,6 +271,7 @@ __global__ __launch_bounds__(256) void gather_pairs_kernel(const typename ST::el
             strips[t * G::NIN + m * VS::Q + j] = (float)(fk.dec[i] * (double)ST::dec(src[(size_t)i * N + cell]));
         }
     }
+    if (!targets) return;
     int q[3] = {p[0], p[1], p[2]};
     q[a] -= step;  // the outside neighbour
     const size_t gcell = outer_cell(q);

@@ -316,11 +316,13 @@ class Solver:
         self.pop_b = torch.empty(self.state_bytes, dtype=torch.uint8, device=dev)
         self.scratch = torch.empty(self.scratch_bytes, dtype=torch.uint8, device=dev)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        rho_t, u_t, th_t = self._fields(rho, u, theta)
-        self.h = lbm_lee_init(self.desc, self.pop_a.data_ptr(), self.pop_b.data_ptr(), self.state_bytes,
-                              rho_t.data_ptr(), u_t.data_ptr(), th_t.data_ptr(), self.scratch.data_ptr(),
-                              self.scratch_bytes, self.stream.cuda_stream)
-        self._keep = (rho_t, u_t, th_t)  # the init kernel may still be reading them
+        if rho is None and u is None and theta is None:  # the state at rest
+            ptrs, self._keep = (None, None, None), ()
+        else:
+            self._keep = self._fields(rho, u, theta)  # the init kernel may still be reading them
+            ptrs = tuple(a.data_ptr() for a in self._keep)
+        self.h = lbm_lee_init(self.desc, self.pop_a.data_ptr(), self.pop_b.data_ptr(), self.state_bytes, *ptrs,
+                              self.scratch.data_ptr(), self.scratch_bytes, self.stream.cuda_stream)
 
     def _fields(self, rho, u, theta):
         t = self.torch

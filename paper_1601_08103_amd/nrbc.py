@@ -60,10 +60,6 @@ def embed(torch, fields, L, E, D):
 
 
 # ---------------------------------------------------------------- training data
-def _zeros(D, shape):
-    return (np.zeros(shape), np.zeros((D,) + tuple(shape)), np.zeros(shape))
-
-
 def generate(lattice="D2Q9", L=512, E=1536, runs=100, steps=1024, every=8, nodes=256, seed=0, storage="f32"):
     import torch
     info = lbm.lbm_lee_lattice_info(lattice)
@@ -79,7 +75,7 @@ def generate(lattice="D2Q9", L=512, E=1536, runs=100, steps=1024, every=8, nodes
     st = torch.cuda.current_stream().cuda_stream
     k = 0
     t0 = time.time()
-    ext = lbm.Solver(lattice, storage, (E,) * D, *_zeros(D, (E,) * D))
+    ext = lbm.Solver(lattice, storage, (E,) * D, None, None, None)
     org = [(E - L) // 2] * D
     for r in range(runs):
         ext.reinit_region(org, (L,) * D, *box_fields(info, (L,) * D, inner_pulses(rng, L, D)))
@@ -92,6 +88,50 @@ def generate(lattice="D2Q9", L=512, E=1536, runs=100, steps=1024, every=8, nodes
             torch.cuda.synchronize()
             log(f"data: run {r + 1}/{runs}, {k} pairs, {time.time() - t0:.1f} s")
     ext.close()
+    return S[:k], T[:k]
+
+
+def generate_closed_loop(lattice, params, L=512, E=1536, runs=100, steps=1024, every=8, nodes=256, seed=0,
+                         storage="f32"):
+    """Pairs from the states the closed loop visits: the open box runs with the network closure
+    `params` beside the judge; inputs are the box's own strips at face nodes, targets the judge's
+    entering populations at the same nodes (what the exact exterior would have supplied)."""
+    import torch
+    info = lbm.lbm_lee_lattice_info(lattice)
+    D = info["D"]
+    dims = lbm.lbm_nrbc_dims(lattice)
+    inner = lbm.make_desc(lattice, storage, (L,) * D, bc="mlp")
+    nn = lbm.lbm_nrbc_face_nodes(inner)
+    per_run = (steps // every) * nodes
+    S = torch.empty((runs * per_run, dims["n_in"]), dtype=torch.float32, device="cuda")
+    T = torch.empty((runs * per_run, dims["n_out"]), dtype=torch.float32, device="cuda")
+    junk = torch.empty((nodes, dims["n_in"]), dtype=torch.float32, device="cuda")
+    org = [(E - L) // 2] * D
+    origin = org + [0] * (3 - D)
+    rng = np.random.default_rng(seed)
+    st = torch.cuda.current_stream().cuda_stream
+    P = torch.as_tensor(np.asarray(params, dtype=np.float32)).cuda()
+    ext = lbm.Solver(lattice, storage, (E,) * D, None, None, None)
+    box = lbm.Solver(lattice, storage, (L,) * D, None, None, None, bc="mlp")
+    box.set_closure(P)
+    k = 0
+    t0 = time.time()
+    for r in range(runs):
+        fields = box_fields(info, (L,) * D, inner_pulses(rng, L, D))
+        ext.reinit_region(org, (L,) * D, *fields)
+        box.reinit_region([0] * D, (L,) * D, *fields)
+        for s in range(0, steps, every):
+            ids = torch.from_numpy(rng.integers(0, nn, size=nodes).astype(np.int64)).cuda()
+            lbm.lbm_nrbc_gather(box.h, [0, 0, 0], box.desc, ids.data_ptr(), nodes, S[k].data_ptr(), None, st)
+            lbm.lbm_nrbc_gather(ext.h, origin, inner, ids.data_ptr(), nodes, junk.data_ptr(), T[k].data_ptr(), st)
+            k += nodes
+            ext.step(every)
+            box.step(every)
+        if (r + 1) % max(1, runs // 10) == 0:
+            torch.cuda.synchronize()
+            log(f"closed-loop data: run {r + 1}/{runs}, {k} pairs, {time.time() - t0:.1f} s")
+    ext.close()
+    box.close()
     return S[:k], T[:k]
 
 
@@ -169,13 +209,13 @@ def reflection(lattice, closure, pulses, L=512, E=1536, steps=1024, every=8, par
     W = sponge_width if closure == "sponge" else 0
     kw = dict(sponge_width=sponge_width, sponge_sigma=sponge_sigma) if closure == "sponge" else {}
     nb = L + 2 * W
-    box = lbm.Solver(lattice, storage, (nb,) * D, *_zeros(D, (nb,) * D), bc=closure, **kw)
+    box = lbm.Solver(lattice, storage, (nb,) * D, None, None, None, bc=closure, **kw)
     box.reinit_region([W] * D, (L,) * D, *fields)
     if closure == "mlp":
         box.set_closure(params)
     own_ext = ext is None
     if own_ext:
-        ext = lbm.Solver(lattice, ext_storage, (E,) * D, *_zeros(D, (E,) * D))
+        ext = lbm.Solver(lattice, ext_storage, (E,) * D, None, None, None)
     oe = [(E - L) // 2] * D
     ext.reinit_region(oe, (L,) * D, *fields)
     st = torch.cuda.current_stream().cuda_stream
@@ -204,8 +244,7 @@ def time_per_step(lattice, shape, bc="periodic", params=None, storage="f32", ste
     import torch
     info = lbm.lbm_lee_lattice_info(lattice)
     D = info["D"]
-    z = (np.zeros(shape), np.zeros((D,) + tuple(shape)), np.zeros(shape))
-    sim = lbm.Solver(lattice, storage, shape, *z, bc=bc, **kw)
+    sim = lbm.Solver(lattice, storage, shape, None, None, None, bc=bc, **kw)
     if bc == "mlp":
         sim.set_closure(params)
     sim.step(10)
@@ -243,12 +282,23 @@ def main(argv=None):
     ap.add_argument("--seeds", type=int, default=32, help="held-out initial states for evaluate")
     ap.add_argument("--sponge-width", type=int, default=32)
     ap.add_argument("--sponge-sigma", type=float, default=0.2)
+    ap.add_argument("--dagger", type=int, default=0, help="rounds of closed-loop data + further training")
+    ap.add_argument("--dagger-runs", type=int, default=100)
+    ap.add_argument("--dagger-epochs", type=int, default=2)
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
     lbm.load()
     if args.mode == "train":
         S, T = generate(args.lattice, args.L, args.E, args.runs, args.steps, args.every, args.nodes, args.seed)
         P, hist = train(args.lattice, S, T, args.epochs, args.batch, args.lr, seed=args.seed)
+        for d in range(args.dagger):
+            Sc, Tc = generate_closed_loop(args.lattice, P, args.L, args.E, args.dagger_runs, args.steps, args.every,
+                                          args.nodes, seed=args.seed + 1000 * (d + 1))
+            S, T = torch.cat([S, Sc]), torch.cat([T, Tc])
+            del Sc, Tc
+            P, h2 = train(args.lattice, S, T, args.dagger_epochs, args.batch, args.lr * 0.3, seed=args.seed + d + 1,
+                          params=P)
+            hist += [dict(h, dagger=d + 1) for h in h2]
         if args.weights:
             np.save(args.weights, P.astype(np.float32), allow_pickle=False)
         print(json.dumps(dict(mode="train", lattice=args.lattice, pairs=int(S.shape[0]), runs=args.runs,
@@ -260,7 +310,7 @@ def main(argv=None):
     D = info["D"]
     closures = ["zero", "copy", "sponge"] + (["mlp"] if P is not None else [])
     Rs = {c: [] for c in closures}
-    ext = lbm.Solver(args.lattice, "f32", (args.E,) * D, *_zeros(D, (args.E,) * D))
+    ext = lbm.Solver(args.lattice, "f32", (args.E,) * D, None, None, None)
     for k in range(args.seeds):
         pulses = inner_pulses(rng, args.L, D)
         for c in closures:

@@ -430,8 +430,7 @@ def test_region_init_and_moments(name, storage, shape, origin, sub):
     U[(slice(None),) + sl] = u
     a = lbm.Solver(name, storage, shape, R, U, T)
     # a handle created from a state at rest cannot pick the 16-bit scale from its fields: pass a's
-    b = lbm.Solver(name, storage, shape, np.zeros(shape), np.zeros((D,) + shape), np.zeros(shape),
-                   store_scale=a.store_scale())
+    b = lbm.Solver(name, storage, shape, None, None, None, store_scale=a.store_scale)
     b.reinit_region(origin, sub, rho, u, th)
     for s in (0, 3):
         a.step(s)
@@ -445,3 +444,21 @@ def test_region_init_and_moments(name, storage, shape, origin, sub):
     assert float(ma["p"].abs().max()) > 0
     a.close()
     b.close()
+
+
+def test_init_at_rest():
+    """NULL fields give the state at rest (every population zero), which stays at rest; the
+    16-bit scale is the one passed in the descriptor.  Some but not all NULL is an error."""
+    import torch
+    from paper_1601_08103_amd import lbm
+    say("init at rest")
+    sim = lbm.Solver("D3Q7", "f16", (8, 12, 16), None, None, None, store_scale=64.0)
+    assert sim.store_scale == 64.0
+    assert not bool(sim.export_f64().any())
+    sim.step(3)
+    assert not bool(sim.export_f64().any())
+    rho = torch.zeros(sim.N, dtype=torch.float64, device="cuda")
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_lee_init(sim.desc, sim.pop_a.data_ptr(), sim.pop_b.data_ptr(), sim.state_bytes, rho.data_ptr(), None,
+                         None, sim.scratch.data_ptr(), sim.scratch_bytes, sim.s)
+    sim.close()
