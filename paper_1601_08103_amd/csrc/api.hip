@@ -81,9 +81,30 @@ bool is_scaled(int storage) {
 
 bool aligned256(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 
+// The step kernels take their constants per shell (same |c|^2): every population of a shell
+// must have the same weight f* and energy offset beta.  True for every built-in table (their
+// weights are isotropic); checked here so a table that breaks it is refused, not mis-stepped.
+bool shell_uniform(const LatticeTable &t) {
+    double f[kShells], beta[kShells];
+    bool seen[kShells] = {false, false, false, false};
+    for (int i = 0; i < t.Q; ++i) {
+        const int sh = t.c[i][0] * t.c[i][0] + t.c[i][1] * t.c[i][1] + t.c[i][2] * t.c[i][2];
+        if (sh >= kShells) return false;
+        if (!seen[sh]) {
+            seen[sh] = true;
+            f[sh] = t.f[i];
+            beta[sh] = t.beta[i];
+        } else if (f[sh] != t.f[i] || beta[sh] != t.beta[i]) {
+            return false;
+        }
+    }
+    return true;
+}
+
 lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
     if (!d) return fail(LBM_E_INVALID, "desc is NULL");
     if (!build_lattice(d->lattice, tab)) return fail(LBM_E_INVALID, "unknown lattice id %d", d->lattice);
+    if (!shell_uniform(*tab)) return fail(LBM_E_UNSUPPORTED, "lattice %d: weights differ within a shell", d->lattice);
     if (elem_size(d->storage) == 0) return fail(LBM_E_INVALID, "unknown storage id %d", d->storage);
     for (int a = 0; a < 3; ++a) {
         if (d->n[a] < 1 || d->n[a] > (int64_t)1 << 30) return fail(LBM_E_INVALID, "n[%d] = %lld out of range", a, (long long)d->n[a]);
@@ -174,15 +195,21 @@ Kc<CT> split(double v) {
     return k;
 }
 
+// Per-shell collision constants (the shell of population i is |c_i|^2); shell_uniform() has
+// checked that every population of a shell has the same f*_i and beta_i.
 template <typename CT, int Q>
 StepCoef<CT, Q> step_coef(const lbm_lee *h) {
     const FieldCoef<Q> f = field_coef<Q>(h);
     StepCoef<CT, Q> k;
+    std::memset(&k, 0, sizeof k);
     const double omega = 1.0 / h->desc.tau;
+    const LatticeTable &t = h->tab;
     for (int i = 0; i < Q; ++i) {
-        k.dec[i] = split<CT>(f.dec[i]);
-        k.edec[i] = split<CT>(f.e[i] * f.dec[i]);
-        k.w[i] = split<CT>(omega * f.enc[i] * f.f[i]);
+        const int sh = t.c[i][0] * t.c[i][0] + t.c[i][1] * t.c[i][1] + t.c[i][2] * t.c[i][2];
+        k.dec[sh] = split<CT>(f.dec[i]);
+        k.edec[sh] = split<CT>(f.e[i] * f.dec[i]);
+        k.bu[sh] = split<CT>(f.b * f.dec[i] / f.rho0);
+        k.w[sh] = split<CT>(omega * f.enc[i] * f.f[i]);
     }
     k.keep = split<CT>(1.0 - omega);
     k.gm1_rho0 = split<CT>(f.gm1 / f.rho0);
@@ -191,7 +218,6 @@ StepCoef<CT, Q> step_coef(const lbm_lee *h) {
     k.a2 = split<CT>(f.a2);
     k.c1 = split<CT>(f.c1);
     k.c2 = split<CT>(f.c2);
-    k.b_rho0 = split<CT>(f.b / f.rho0);
     return k;
 }
 
@@ -576,34 +602,35 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
             const long long tiles = (ft.node_off[ft.nfaces] + 15) / 16;
             ghost_blocks = (unsigned)std::min<long long>((tiles + 3) / 4, 4096);
         }
-        auto run = [&](auto skip) -> lbm_status {
+        auto run = [&](auto skip, auto half) -> lbm_status {
             constexpr bool SK = decltype(skip)::value;
+            constexpr bool HF = decltype(half)::value;
             for (int64_t t = 0; t < nsteps; ++t) {
                 const E *src = static_cast<const E *>(h->buf[h->cur]);
                 E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);
                 if (bc == LBM_BC_MLP)
                     ghost_mlp_kernel<VS, ST><<<ghost_blocks, 256, 0, st>>>(src, h->N, h->net, h->ghost, ft, fk);
                 if (variant == LBM_VARIANT_GENERIC) {
-                    step_generic<VS, ST, SK><<<blocks_for(h->N), 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, k);
+                    step_generic<VS, ST, SK, HF><<<blocks_for(h->N), 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, k);
                 } else if (variant == LBM_VARIANT_LDS) {
-                    step_lds<VS, ST, SK><<<lds_blocks, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, lds_cpr, k);
+                    step_lds<VS, ST, SK, HF><<<lds_blocks, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, lds_cpr, k);
                 } else if (vec == 4) {
                     if (fullrow)
-                        step_dpp<VS, ST, 4, true, SK><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
+                        step_dpp<VS, ST, 4, true, SK, HF><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
                                                                            waves, tune, k);
                     else
-                        step_dpp<VS, ST, 4, false, SK><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
+                        step_dpp<VS, ST, 4, false, SK, HF><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
                                                                             waves, tune, k);
                 } else {
                     if (fullrow)
-                        step_dpp<VS, ST, 2, true, SK><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
+                        step_dpp<VS, ST, 2, true, SK, HF><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
                                                                            waves, tune, k);
                     else
-                        step_dpp<VS, ST, 2, false, SK><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
+                        step_dpp<VS, ST, 2, false, SK, HF><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
                                                                             waves, tune, k);
                 }
                 if (bc != LBM_BC_PERIODIC) {
-                    shell_kernel<VS, ST, SK><<<dim3(shell_x, 2 * VS::D), 256, 0, st>>>(src, dst, h->N, bc, h->ghost,
+                    shell_kernel<VS, ST, SK, HF><<<dim3(shell_x, 2 * VS::D), 256, 0, st>>>(src, dst, h->N, bc, h->ghost,
                                                                                       ft, k, fk);
                     if (bc == LBM_BC_SPONGE)
                         sponge_kernel<VS, ST><<<blocks_for(h->N), 256, 0, st>>>(dst, h->N, h->nx, h->ny, h->nz,
@@ -617,10 +644,20 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
             }
             return LBM_OK;
         };
-        if constexpr (VS::rest_may_decouple) {
-            if (h->skip0) return run(std::true_type{});
+        // tau = 1/2 takes the one-fma relaxation; compiled for the 2-byte formats only, whose
+        // steps are bound by ALU work (the 4- and 8-byte steps are bound by memory traffic).
+        if constexpr (sizeof(E) == 2) {
+            if (h->desc.tau == 0.5) {
+                if constexpr (VS::rest_may_decouple) {
+                    if (h->skip0) return run(std::true_type{}, std::true_type{});
+                }
+                return run(std::false_type{}, std::true_type{});
+            }
         }
-        return run(std::false_type{});
+        if constexpr (VS::rest_may_decouple) {
+            if (h->skip0) return run(std::true_type{}, std::false_type{});
+        }
+        return run(std::false_type{}, std::false_type{});
     });
     return s == LBM_OK ? ok() : s;
 }

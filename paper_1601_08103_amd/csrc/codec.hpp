@@ -93,16 +93,14 @@ struct StE3M12 {
     }
     __device__ static elem enc(comp v) {
         const unsigned bits = __float_as_uint(v);
-        const unsigned sign = (bits >> 16) & 0x8000u;
         const unsigned b = bits & 0x7fffffffu;
-        unsigned code;
-        if (b >= (121u << 23)) {  // |v| >= 2^-6: round the 23-bit mantissa to 12 bits, ties to even
-            const unsigned r = (b + 0x3ffu + ((b >> 11) & 1u)) >> 11;
-            code = min(r - (120u << 12), 0x7fffu);
-        } else {  // subnormal range: an integer multiple of 2^-18 (4096 is 2^-6, the first normal)
-            code = (unsigned)__builtin_rintf(__uint_as_float(b) * 262144.0f);
-        }
-        return (elem)(code | sign);
+        // |v| >= 2^-6: round the 23-bit mantissa to 12 bits, ties to even, exponent rebased by
+        // 120 (done before the shift), saturating at the largest code
+        const unsigned rn = min((b - (120u << 23) + 0x3ffu + ((b >> 11) & 1u)) >> 11, 0x7fffu);
+        // subnormal range, a multiple of 2^-18: FP32 numbers in [32, 64) are spaced 2^-18 apart,
+        // so |v| + 32 rounds |v| to it (ties to even) and its low bits are the code
+        const unsigned rs = __float_as_uint(__builtin_fabsf(v) + 32.0f) - 0x42000000u;
+        return (elem)((b >= (121u << 23) ? rn : rs) | ((bits >> 16) & 0x8000u));
     }
     __device__ static elem enc_d(double v) { return enc((float)v); }
 };
@@ -193,6 +191,23 @@ template <>
 __device__ inline void store4<StI16>(short *p, const float (&v)[4], bool nt) {
     s16x4 a = {StI16::enc(v[0]), StI16::enc(v[1]), StI16::enc(v[2]), StI16::enc(v[3])};
     vstore(reinterpret_cast<s16x4 *>(p), a, nt);
+}
+
+// Two consecutive elements starting at an even index: one 16-, 8- or 4-byte access.
+template <class ST>
+__device__ inline void load2(const typename ST::elem *p, typename ST::comp (&v)[2], bool nt = false) {
+    using E = typename ST::elem;
+    typedef E e2 __attribute__((ext_vector_type(2)));
+    const e2 a = vload(reinterpret_cast<const e2 *>(p), nt);
+    v[0] = ST::dec(a.x);
+    v[1] = ST::dec(a.y);
+}
+template <class ST>
+__device__ inline void store2(typename ST::elem *p, const typename ST::comp (&v)[2], bool nt = false) {
+    using E = typename ST::elem;
+    typedef E e2 __attribute__((ext_vector_type(2)));
+    const e2 a = {ST::enc(v[0]), ST::enc(v[1])};
+    vstore(reinterpret_cast<e2 *>(p), a, nt);
 }
 
 }  // namespace lbm

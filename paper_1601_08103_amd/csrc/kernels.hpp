@@ -45,19 +45,25 @@ constexpr bool split_constants() {
     return sizeof(typename ST::elem) == 4;
 }
 
-// Collision constants in storage units, for compute type CT.  With stored value s_i and
-// decoded population g_i = dec_i s_i:
-//   rho'  = sum dec_i s_i,      j = sum c_i dec_i s_i,      e = sum edec_i s_i,
-//   theta' = gm1_rho0 e - theta0_rho0 rho',   U = b_rho0 j  (= b u'),
+// Collision constants in storage units, for compute type CT, per shell: the populations with
+// the same |c_i|^2 (0 rest, 1 axes, 2 edges, 3 corners) share f*_i, beta_i and hence every
+// constant below (the host checks this for each table).  With stored value s_i and decoded
+// population g_i = dec_i s_i:
+//   rho'  = sum_shell dec (sum s_i),      e = sum_shell edec (sum s_i),
+//   U     = b u' = sum_shell bu (sum c_i s_i),        bu = b dec / rho0,
+//   theta' = gm1_rho0 e - theta0_rho0 rho',
 //   A = a1 rho' + a2 theta',  C = c1 rho' + c2 theta',
-//   s_i <- keep s_i + w_i (A + c_i.U + |c_i|^2/2 C)
-// where keep = 1 - 1/tau and w_i = (1/tau) enc_i f*_i (the equilibrium in storage units).
+//   s_i <- keep s_i + w (A + |c_i|^2/2 C + c_i.U)
+// where keep = 1 - 1/tau and w = (1/tau) enc_i f*_i (the equilibrium in storage units).
+constexpr int kShells = 4;
+
 template <typename CT, int Q>
 struct StepCoef {
-    Kc<CT> dec[Q];
-    Kc<CT> edec[Q];
-    Kc<CT> w[Q];
-    Kc<CT> keep, gm1_rho0, theta0_rho0, a1, a2, c1, c2, b_rho0;
+    Kc<CT> dec[kShells];
+    Kc<CT> edec[kShells];
+    Kc<CT> bu[kShells];
+    Kc<CT> w[kShells];
+    Kc<CT> keep, gm1_rho0, theta0_rho0, a1, a2, c1, c2;
 };
 
 // FP64 constants of the non-hot kernels (init, moments, reductions, import/export).
@@ -70,40 +76,97 @@ struct FieldCoef {
     double rho0, theta0, gm1, a1, a2, b, c1, c2;
 };
 
+// Is population i the first (from i0 on) of its shell, or with axis >= 0, the first of its
+// shell with a nonzero velocity component along that axis?
+template <class VS, int i0>
+constexpr bool first_of(int i, int axis) {
+    for (int j = i0; j < i; ++j)
+        if (VS::c2(j) == VS::c2(i) && (axis < 0 || VS::c[j][axis] != 0)) return false;
+    return true;
+}
+
+template <class VS, bool SKIP0>
+constexpr bool has_shell(int sh) {
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i)
+        if (VS::c2(i) == sh) return true;
+    return false;
+}
+
+// fma with a split constant: k t + c with ~2^-48 relative error in the constant.
+template <bool SPLIT, typename CT>
+__device__ __forceinline__ CT fmak(Kc<CT> k, CT t, CT c) {
+    if constexpr (SPLIT)
+        return fma(k.hi, t, fma(k.lo, t, c));
+    else
+        return fma(k.hi, t, c);
+}
+
 // ------------------------------------------------------------------ collision
 // SKIP0: the rest population (index 0) is left out: the host enables this only when the
 // equilibrium map leaves it invariant (E_00 = 1, E_0j = E_j0 = 0), in which case the moving
 // populations' equilibria do not depend on it either.
-template <class VS, typename CT, bool SPLIT, bool SKIP0 = false>
+// HALF: tau = 1/2 (keep = -1), the paper's second-order choice: s_i <- w t_i - s_i, one fma.
+template <class VS, typename CT, bool SPLIT, bool SKIP0 = false, bool HALF = false>
 __device__ __forceinline__ void collide(const StepCoef<CT, VS::Q> &k, CT (&s)[VS::Q]) {
-    CT rho = 0, jx = 0, jy = 0, jz = 0, e = 0;
+    constexpr int i0 = SKIP0 ? 1 : 0;
+    // Sums start from the first term (not from 0 + term, which IEEE arithmetic cannot drop).
+    CT sum[kShells] = {}, jx[kShells] = {}, jy[kShells] = {}, jz[kShells] = {};
 #pragma unroll
-    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) {
-        const CT g = mulk<SPLIT>(s[i], k.dec[i]);
-        rho += g;
-        if (VS::cx(i) > 0) jx += g;
-        if (VS::cx(i) < 0) jx -= g;
-        if (VS::cy(i) > 0) jy += g;
-        if (VS::cy(i) < 0) jy -= g;
-        if (VS::cz(i) > 0) jz += g;
-        if (VS::cz(i) < 0) jz -= g;
-        e += mulk<SPLIT>(s[i], k.edec[i]);
+    for (int i = i0; i < VS::Q; ++i) {
+        const int sh = VS::c2(i);
+        const CT v = s[i];
+        if (first_of<VS, i0>(i, -1)) sum[sh] = v; else sum[sh] += v;
+        if (VS::cx(i) != 0) {
+            const CT sv = VS::cx(i) > 0 ? v : -v;
+            if (first_of<VS, i0>(i, 0)) jx[sh] = sv; else jx[sh] += sv;
+        }
+        if (VS::cy(i) != 0) {
+            const CT sv = VS::cy(i) > 0 ? v : -v;
+            if (first_of<VS, i0>(i, 1)) jy[sh] = sv; else jy[sh] += sv;
+        }
+        if (VS::cz(i) != 0) {
+            const CT sv = VS::cz(i) > 0 ? v : -v;
+            if (first_of<VS, i0>(i, 2)) jz[sh] = sv; else jz[sh] += sv;
+        }
+    }
+    CT rho = 0, e = 0, Ux = 0, Uy = 0, Uz = 0;
+    bool first = true, firstu = true;
+#pragma unroll
+    for (int sh = 0; sh < kShells; ++sh) {
+        if (!has_shell<VS, SKIP0>(sh)) continue;
+        const CT r = mulk<SPLIT>(sum[sh], k.dec[sh]), ee = mulk<SPLIT>(sum[sh], k.edec[sh]);
+        rho = first ? r : rho + r;
+        e = first ? ee : e + ee;
+        first = false;
+        if (sh == 0) continue;  // the rest velocity carries no momentum
+        const CT ux = mulk<SPLIT>(jx[sh], k.bu[sh]);
+        const CT uy = VS::D >= 2 ? mulk<SPLIT>(jy[sh], k.bu[sh]) : (CT)0;
+        const CT uz = VS::D >= 3 ? mulk<SPLIT>(jz[sh], k.bu[sh]) : (CT)0;
+        Ux = firstu ? ux : Ux + ux;
+        Uy = firstu ? uy : Uy + uy;
+        Uz = firstu ? uz : Uz + uz;
+        firstu = false;
     }
     const CT theta = mulk<SPLIT>(e, k.gm1_rho0) - mulk<SPLIT>(rho, k.theta0_rho0);
     const CT A = mulk<SPLIT>(rho, k.a1) + mulk<SPLIT>(theta, k.a2);
     const CT C = mulk<SPLIT>(rho, k.c1) + mulk<SPLIT>(theta, k.c2);
-    const CT Ux = mulk<SPLIT>(jx, k.b_rho0), Uy = mulk<SPLIT>(jy, k.b_rho0), Uz = mulk<SPLIT>(jz, k.b_rho0);
+    CT As[kShells];
 #pragma unroll
-    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) {
-        CT t = A;
+    for (int sh = 0; sh < kShells; ++sh) As[sh] = sh == 0 ? A : A + (CT)(0.5 * sh) * C;  // 1/2, 1, 3/2: exact
+#pragma unroll
+    for (int i = i0; i < VS::Q; ++i) {
+        const int sh = VS::c2(i);
+        CT t = As[sh];
         if (VS::cx(i) > 0) t += Ux;
         if (VS::cx(i) < 0) t -= Ux;
         if (VS::cy(i) > 0) t += Uy;
         if (VS::cy(i) < 0) t -= Uy;
         if (VS::cz(i) > 0) t += Uz;
         if (VS::cz(i) < 0) t -= Uz;
-        if (VS::c2(i) != 0) t += (CT)(0.5 * VS::c2(i)) * C;  // 1/2, 1 or 3/2: exact
-        s[i] = mulk<SPLIT>(s[i], k.keep) + mulk<SPLIT>(t, k.w[i]);
+        if constexpr (HALF)
+            s[i] = fmak<SPLIT>(k.w[sh], t, -s[i]);
+        else
+            s[i] = mulk<SPLIT>(s[i], k.keep) + mulk<SPLIT>(t, k.w[sh]);
     }
 }
 
@@ -116,7 +179,7 @@ __device__ __forceinline__ int wrap_add(int v, int d, int n) {
 
 // ------------------------------------------------------------------ step: generic variant
 // One thread per cell, each population gathered with its own wrapped index.  Any extents.
-template <class VS, class ST, bool SKIP0>
+template <class VS, class ST, bool SKIP0, bool HALF = false>
 __global__ __launch_bounds__(256) void step_generic(const typename ST::elem *__restrict__ src,
                                                     typename ST::elem *__restrict__ dst, int nx, int ny, int nz,
                                                     size_t N, StepCoef<typename ST::comp, VS::Q> k) {
@@ -136,7 +199,7 @@ __global__ __launch_bounds__(256) void step_generic(const typename ST::elem *__r
         const int zs = wrap_add(z, -VS::cz(i), nz);
         s[i] = ST::dec(src[(size_t)i * N + ((size_t)zs * ny + ys) * nx + xs]);
     }
-    collide<VS, CT, split_constants<ST>(), SKIP0>(k, s);
+    collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, s);
 #pragma unroll
     for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
 }
@@ -174,8 +237,7 @@ __device__ __forceinline__ void loadv(const typename ST::elem *p, typename ST::c
         load4<ST>(p, v, nt);
     } else {
         static_assert(VEC == 2, "VEC is 2 or 4");
-        v[0] = ST::dec(p[0]);
-        v[1] = ST::dec(p[1]);
+        load2<ST>(p, v, nt);
     }
 }
 template <class ST, int VEC>
@@ -183,18 +245,11 @@ __device__ __forceinline__ void storev(typename ST::elem *p, const typename ST::
     if constexpr (VEC == 4) {
         store4<ST>(p, v, nt);
     } else {
-        typename ST::elem a = ST::enc(v[0]), b = ST::enc(v[1]);
-        if (nt) {
-            __builtin_nontemporal_store(a, p);
-            __builtin_nontemporal_store(b, p + 1);
-        } else {
-            p[0] = a;
-            p[1] = b;
-        }
+        store2<ST>(p, v, nt);
     }
 }
 
-template <class VS, class ST, int VEC, bool FULLROW, bool SKIP0>
+template <class VS, class ST, int VEC, bool FULLROW, bool SKIP0, bool HALF>
 __device__ __forceinline__ void step_chunk(const typename ST::elem *__restrict__ src,
                                            typename ST::elem *__restrict__ dst, int nx, int ny, int nz, size_t N,
                                            unsigned row, int chunk, int lane, bool ntl, bool nts,
@@ -242,7 +297,7 @@ __device__ __forceinline__ void step_chunk(const typename ST::elem *__restrict__
         CT c[VS::Q];
 #pragma unroll
         for (int i = 0; i < VS::Q; ++i) c[i] = s[i][q];
-        collide<VS, CT, split_constants<ST>(), SKIP0>(k, c);
+        collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, c);
 #pragma unroll
         for (int i = 0; i < VS::Q; ++i) s[i][q] = c[i];
     }
@@ -251,7 +306,7 @@ __device__ __forceinline__ void step_chunk(const typename ST::elem *__restrict__
     for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) storev<ST, VEC>(dst + (size_t)i * N + out, s[i], nts);
 }
 
-template <class VS, class ST, int VEC, bool FULLROW, bool SKIP0>
+template <class VS, class ST, int VEC, bool FULLROW, bool SKIP0, bool HALF = false>
 __global__ __launch_bounds__(256) void step_dpp(const typename ST::elem *__restrict__ src,
                                                 typename ST::elem *__restrict__ dst, int nx, int ny, int nz,
                                                 size_t N, int chunks_per_row, unsigned total_waves, unsigned tune,
@@ -262,7 +317,7 @@ __global__ __launch_bounds__(256) void step_dpp(const typename ST::elem *__restr
     for (unsigned wave = blockIdx.x * 4u + wid; wave < total_waves; wave += gridDim.x * 4u) {
         const unsigned row = wave / (unsigned)chunks_per_row;
         const int chunk = (int)(wave - row * (unsigned)chunks_per_row);
-        step_chunk<VS, ST, VEC, FULLROW, SKIP0>(src, dst, nx, ny, nz, N, row, chunk, lane, ntl, nts, k);
+        step_chunk<VS, ST, VEC, FULLROW, SKIP0, HALF>(src, dst, nx, ny, nz, N, row, chunk, lane, ntl, nts, k);
     }
 }
 
@@ -278,7 +333,7 @@ constexpr int x_moving_count() {
     return n;
 }
 
-template <class VS, class ST, bool SKIP0>
+template <class VS, class ST, bool SKIP0, bool HALF = false>
 __global__ __launch_bounds__(256) void step_lds(const typename ST::elem *__restrict__ src,
                                                 typename ST::elem *__restrict__ dst, int nx, int ny, int nz,
                                                 size_t N, int chunks_per_row, StepCoef<typename ST::comp, VS::Q> k) {
@@ -324,7 +379,7 @@ __global__ __launch_bounds__(256) void step_lds(const typename ST::elem *__restr
         }
     }
     if (!active) return;
-    collide<VS, CT, split_constants<ST>(), SKIP0>(k, s);
+    collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, s);
     const size_t cell = ((size_t)z * ny + y) * (size_t)nx + x;
 #pragma unroll
     for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);

@@ -91,6 +91,13 @@ struct WaveTiles {
     unsigned short da1[16][64];
 };
 
+// Per-wave LDS tiles of the forward pass alone (inference).
+struct FwdTiles {
+    unsigned short z[16][64];
+    unsigned short h1[16][64];
+    unsigned short h2[16][64];
+};
+
 // A operand from an LDS tile X[16][64] (rows = samples): columns kk*16 + 4 (l/16) + e.
 __device__ __forceinline__ bf16x4 a_rows(const unsigned short (*X)[64], int kk, int lane) {
     const int i = lane & 15, k0 = kk * 16 + 4 * (lane >> 4);
@@ -177,10 +184,81 @@ __device__ floatx4 net_forward_tile(const float *__restrict__ P, WaveTiles &T, i
     return acc;
 }
 
+// The forward pass's weights as bfloat16 B-operand fragments (one 8-byte LDS read per lane and
+// product) and its FP32 biases, staged once per block.
+template <class VS>
+struct NetFrags {
+    bf16x4 w1[NetGeom<VS>::NIN_PAD / 16][4][64];
+    bf16x4 w2[4][4][64];
+    bf16x4 w3[4][64];
+    float b1[kHidden], b2[kHidden], b3[16];
+};
+
+// Every thread of the block must call this (it ends with a block barrier).
+template <class VS>
+__device__ void stage_forward_weights(const float *__restrict__ P, NetFrags<VS> &F) {
+    using G = NetGeom<VS>;
+    constexpr int n1 = G::NIN_PAD / 16 * 4 * 64, n2 = 4 * 4 * 64, n3 = 4 * 64;
+    for (int t = threadIdx.x; t < n1 + n2 + n3; t += blockDim.x) {
+        if (t < n1) {
+            F.w1[t >> 8][(t >> 6) & 3][t & 63] = b_weight(P + G::OFF_W1, G::NIN, kHidden, t >> 8, (t >> 6) & 3, t & 63);
+        } else if (t < n1 + n2) {
+            const int u = t - n1;
+            F.w2[u >> 8][(u >> 6) & 3][u & 63] = b_weight(P + G::OFF_W2, kHidden, kHidden, u >> 8, (u >> 6) & 3, u & 63);
+        } else {
+            const int u = t - n1 - n2;
+            F.w3[u >> 6][u & 63] = b_weight(P + G::OFF_W3, kHidden, G::NOUT, u >> 6, 0, u & 63);
+        }
+    }
+    for (int t = threadIdx.x; t < 2 * kHidden + 16; t += blockDim.x) {
+        if (t < kHidden)
+            F.b1[t] = P[G::OFF_B1 + t];
+        else if (t < 2 * kHidden)
+            F.b2[t - kHidden] = P[G::OFF_B2 + t - kHidden];
+        else
+            F.b3[t - 2 * kHidden] = t - 2 * kHidden < G::NOUT ? P[G::OFF_B3 + t - 2 * kHidden] : 0.0f;
+    }
+    __syncthreads();
+}
+
+// net_forward_tile with the staged weights: the same products and roundings.
+template <class VS, class TT>
+__device__ floatx4 net_forward_tile_staged(const NetFrags<VS> &F, TT &T, int lane) {
+    using G = NetGeom<VS>;
+    const int row0 = 4 * (lane >> 4), col = lane & 15;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        floatx4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < G::NIN_PAD / 16; ++kk) acc = mfma16(a_rows(T.z, kk, lane), F.w1[kk][nt][lane], acc);
+        const float bias = F.b1[nt * 16 + col];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) T.h1[row0 + e][nt * 16 + col] = bf16_bits(fmaxf(acc[e] + bias, 0.0f));
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        floatx4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) acc = mfma16(a_rows(T.h1, kk, lane), F.w2[kk][nt][lane], acc);
+        const float bias = F.b2[nt * 16 + col];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) T.h2[row0 + e][nt * 16 + col] = bf16_bits(fmaxf(acc[e] + bias, 0.0f));
+    }
+    wave_lds_sync();
+    floatx4 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) acc = mfma16(a_rows(T.h2, kk, lane), F.w3[kk][lane], acc);
+    const float bias = F.b3[col];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[e] += bias;
+    return acc;
+}
+
 // Load a tile of raw strips (rows >= nrows are zero) into T.z as bf16 of x / rms(x); returns
 // rms of row (lane & 15) in every lane that holds that row.  X(row, v) gives strip value v.
-template <class VS, class LoadFn>
-__device__ float load_normalised_tile(WaveTiles &T, int nrows, int lane, LoadFn X) {
+template <class VS, class TT, class LoadFn>
+__device__ float load_normalised_tile(TT &T, int nrows, int lane, LoadFn X) {
     using G = NetGeom<VS>;
     const int r = lane & 15, g = lane >> 4;
     float vals[(G::NIN_PAD + 3) / 4];
@@ -219,16 +297,18 @@ template <class VS>
 __global__ __launch_bounds__(256) void nrbc_forward_kernel(const float *__restrict__ P, const float *__restrict__ strips,
                                                            long long count, float *__restrict__ out) {
     using G = NetGeom<VS>;
-    __shared__ WaveTiles tiles[4];
+    __shared__ FwdTiles tiles[4];
+    __shared__ NetFrags<VS> F;
+    stage_forward_weights<VS>(P, F);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    WaveTiles &T = tiles[wid];
+    FwdTiles &T = tiles[wid];
     const long long ntiles = (count + 15) / 16;
     for (long long tile = (long long)blockIdx.x * 4 + wid; tile < ntiles; tile += (long long)gridDim.x * 4) {
         const long long base = tile * 16;
         const int nrows = (int)min((long long)16, count - base);
         const float s = load_normalised_tile<VS>(T, nrows, lane,
                                                  [&](int r, int v) { return strips[(base + r) * G::NIN + v]; });
-        const floatx4 y = net_forward_tile<VS>(P, T, lane);
+        const floatx4 y = net_forward_tile_staged<VS>(F, T, lane);
         // y[e] is row 4 (l/16) + e, column l % 16; the row's rms lives in lane (row)
         const int col = lane & 15;
 #pragma unroll

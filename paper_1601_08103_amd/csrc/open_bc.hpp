@@ -80,7 +80,7 @@ __device__ inline int node_cell(const FaceTab<Q> &ft, long long g, int (&p)[3]) 
 }
 
 // ------------------------------------------------------------------ shell recompute
-template <class VS, class ST, bool SKIP0>
+template <class VS, class ST, bool SKIP0, bool HALF = false>
 __global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__restrict__ src,
                                                     typename ST::elem *__restrict__ dst, size_t N, int closure,
                                                     const float *__restrict__ ghost, FaceTab<VS::Q> ft,
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__r
         }
         s[i] = v;
     }
-    collide<VS, CT, split_constants<ST>(), SKIP0>(k, s);
+    collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, s);
 #pragma unroll
     for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
 }
@@ -177,10 +177,12 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
                                                         const float *__restrict__ P, float *__restrict__ ghost,
                                                         FaceTab<VS::Q> ft, FieldCoef<VS::Q> fk) {
     using G = NetGeom<VS>;
-    __shared__ WaveTiles tiles[4];
+    __shared__ FwdTiles tiles[4];
     __shared__ float pred[4][16][G::NOUT];
+    __shared__ NetFrags<VS> F;
+    stage_forward_weights<VS>(P, F);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    WaveTiles &T = tiles[wid];
+    FwdTiles &T = tiles[wid];
     const long long count = ft.node_off[ft.nfaces];
     const long long ntiles = (count + 15) / 16;
     for (long long tile = (long long)blockIdx.x * 4 + wid; tile < ntiles; tile += (long long)gridDim.x * 4) {
@@ -199,7 +201,7 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
             const int i = ft.perm[f][j];
             return (float)(fk.dec[i] * (double)ST::dec(src[(size_t)i * N + cell]));
         });
-        const floatx4 y = net_forward_tile<VS>(P, T, lane);
+        const floatx4 y = net_forward_tile_staged<VS>(F, T, lane);
         const int col = lane & 15;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
