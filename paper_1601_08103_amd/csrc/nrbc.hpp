@@ -194,29 +194,54 @@ struct NetFrags {
     float b1[kHidden], b2[kHidden], b3[16];
 };
 
-// Every thread of the block must call this (it ends with a block barrier).
+// Every thread of a 256-thread block must call this (it ends with a block barrier).  All global
+// loads are issued before the first conversion, so the staging costs about one memory latency.
 template <class VS>
 __device__ void stage_forward_weights(const float *__restrict__ P, NetFrags<VS> &F) {
     using G = NetGeom<VS>;
     constexpr int n1 = G::NIN_PAD / 16 * 4 * 64, n2 = 4 * 4 * 64, n3 = 4 * 64;
-    for (int t = threadIdx.x; t < n1 + n2 + n3; t += blockDim.x) {
+    constexpr int total = n1 + n2 + n3, per = (total + 255) / 256;
+    float v[per][4];
+#pragma unroll
+    for (int u = 0; u < per; ++u) {
+        const int t = (int)threadIdx.x + 256 * u;
+        // fragment t: matrix, k-block kk, n-tile nt, lane l -> B[k][j] = W[kk*16 + k][nt*16 + j]
+        const float *W = P + G::OFF_W1;
+        int rows = G::NIN, cols = kHidden, q = t;
+        if (t >= n1 + n2) {
+            W = P + G::OFF_W3, rows = kHidden, cols = G::NOUT, q = t - n1 - n2;
+        } else if (t >= n1) {
+            W = P + G::OFF_W2, rows = kHidden, cols = kHidden, q = t - n1;
+        }
+        const int l = q & 63, nt = t >= n1 + n2 ? 0 : (q >> 6) & 3, kk = t >= n1 + n2 ? q >> 6 : q >> 8;
+        const int j = nt * 16 + (l & 15), k0 = kk * 16 + 4 * (l >> 4);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            v[u][e] = (t < total && k0 + e < rows && j < cols) ? W[(k0 + e) * cols + j] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < per; ++u) {
+        const int t = (int)threadIdx.x + 256 * u;
+        if (t >= total) continue;
+        const bf16x4 b = {(short)bf16_bits(v[u][0]), (short)bf16_bits(v[u][1]), (short)bf16_bits(v[u][2]),
+                          (short)bf16_bits(v[u][3])};
         if (t < n1) {
-            F.w1[t >> 8][(t >> 6) & 3][t & 63] = b_weight(P + G::OFF_W1, G::NIN, kHidden, t >> 8, (t >> 6) & 3, t & 63);
+            F.w1[t >> 8][(t >> 6) & 3][t & 63] = b;
         } else if (t < n1 + n2) {
-            const int u = t - n1;
-            F.w2[u >> 8][(u >> 6) & 3][u & 63] = b_weight(P + G::OFF_W2, kHidden, kHidden, u >> 8, (u >> 6) & 3, u & 63);
+            const int q = t - n1;
+            F.w2[q >> 8][(q >> 6) & 3][q & 63] = b;
         } else {
-            const int u = t - n1 - n2;
-            F.w3[u >> 6][u & 63] = b_weight(P + G::OFF_W3, kHidden, G::NOUT, u >> 6, 0, u & 63);
+            const int q = t - n1 - n2;
+            F.w3[q >> 6][q & 63] = b;
         }
     }
-    for (int t = threadIdx.x; t < 2 * kHidden + 16; t += blockDim.x) {
-        if (t < kHidden)
-            F.b1[t] = P[G::OFF_B1 + t];
-        else if (t < 2 * kHidden)
-            F.b2[t - kHidden] = P[G::OFF_B2 + t - kHidden];
-        else
-            F.b3[t - 2 * kHidden] = t - 2 * kHidden < G::NOUT ? P[G::OFF_B3 + t - 2 * kHidden] : 0.0f;
+    const int t = threadIdx.x;
+    if (t < kHidden) {
+        F.b1[t] = P[G::OFF_B1 + t];
+    } else if (t < 2 * kHidden) {
+        F.b2[t - kHidden] = P[G::OFF_B2 + t - kHidden];
+    } else if (t < 2 * kHidden + 16) {
+        F.b3[t - 2 * kHidden] = t - 2 * kHidden < G::NOUT ? P[G::OFF_B3 + t - 2 * kHidden] : 0.0f;
     }
     __syncthreads();
 }
@@ -257,8 +282,10 @@ __device__ floatx4 net_forward_tile_staged(const NetFrags<VS> &F, TT &T, int lan
 
 // Load a tile of raw strips (rows >= nrows are zero) into T.z as bf16 of x / rms(x); returns
 // rms of row (lane & 15) in every lane that holds that row.  X(row, v) gives strip value v.
-template <class VS, class TT, class LoadFn>
-__device__ float load_normalised_tile(TT &T, int nrows, int lane, LoadFn X) {
+// With EW (v -> weight, 0 for most inputs), also returns in *m_out the row's max |x| and in
+// *e_out sum_v EW(v) (x_v / max|x|)^2 (an energy in units of the row's max, no underflow).
+template <class VS, class TT, class LoadFn, class EWFn>
+__device__ float load_normalised_tile(TT &T, int nrows, int lane, LoadFn X, EWFn EW, float *m_out, float *e_out) {
     using G = NetGeom<VS>;
     const int r = lane & 15, g = lane >> 4;
     float vals[(G::NIN_PAD + 3) / 4];
@@ -274,14 +301,18 @@ __device__ float load_normalised_tile(TT &T, int nrows, int lane, LoadFn X) {
     m = fmaxf(m, __shfl_xor(m, 16, 64));
     m = fmaxf(m, __shfl_xor(m, 32, 64));
     // divisions (not reciprocals): m and s may be FP32 denormals, whose reciprocal overflows
-    float ss = 0.0f;
+    float ss = 0.0f, ee = 0.0f;
 #pragma unroll
     for (int t = 0; t < (G::NIN_PAD + 3) / 4; ++t) {
         const float q = m > 0.0f ? vals[t] / m : 0.0f;
         ss += q * q;
+        const int v = g + 4 * t;
+        if (v < G::NIN) ee += EW(v) * q * q;
     }
     ss += __shfl_xor(ss, 16, 64);
     ss += __shfl_xor(ss, 32, 64);
+    ee += __shfl_xor(ee, 16, 64);
+    ee += __shfl_xor(ee, 32, 64);
     const float s = m * sqrtf(ss / (float)G::NIN);
 #pragma unroll
     for (int t = 0; t < (G::NIN_PAD + 3) / 4; ++t) {
@@ -289,7 +320,13 @@ __device__ float load_normalised_tile(TT &T, int nrows, int lane, LoadFn X) {
         if (v < G::NIN_PAD) T.z[r][v] = (v < G::NIN && s > 0.0f) ? bf16_bits(vals[t] / s) : (unsigned short)0;
     }
     wave_lds_sync();
+    if (m_out) *m_out = m;
+    if (e_out) *e_out = ee;
     return s;
+}
+template <class VS, class TT, class LoadFn>
+__device__ float load_normalised_tile(TT &T, int nrows, int lane, LoadFn X) {
+    return load_normalised_tile<VS>(T, nrows, lane, X, [](int) { return 0.0f; }, nullptr, nullptr);
 }
 
 // ------------------------------------------------------------------ batch inference on strips

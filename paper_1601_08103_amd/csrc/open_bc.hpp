@@ -193,14 +193,21 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
         const int r = lane & 15;
         const int f = node_cell(ft, base + (r < nrows ? r : 0), p);
         const int a = f >> 1, step = (f & 1) ? -1 : 1;
-        const float s = load_normalised_tile<VS>(T, nrows, lane, [&](int, int v) {
-            const int m = v / VS::Q, j = v - m * VS::Q;
-            int q[3] = {p[0], p[1], p[2]};
-            q[a] += m * step;
-            const size_t cell = ((size_t)q[2] * ft.n[1] + q[1]) * ft.n[0] + q[0];
-            const int i = ft.perm[f][j];
-            return (float)(fk.dec[i] * (double)ST::dec(src[(size_t)i * N + cell]));
-        });
+        // energy weights 1/f* of the node's populations leaving through the face (first cell of
+        // the strip, canonical c_x = -1)
+        float mx = 0.0f, e_out = 0.0f;
+        const float s = load_normalised_tile<VS>(
+            T, nrows, lane,
+            [&](int, int v) {
+                const int m = v / VS::Q, j = v - m * VS::Q;
+                int q[3] = {p[0], p[1], p[2]};
+                q[a] += m * step;
+                const size_t cell = ((size_t)q[2] * ft.n[1] + q[1]) * ft.n[0] + q[0];
+                const int i = ft.perm[f][j];
+                return (float)(fk.dec[i] * (double)ST::dec(src[(size_t)i * N + cell]));
+            },
+            [&](int v) { return v < VS::Q && VS::cx(v) == -1 ? (float)(1.0 / fk.f[ft.perm[f][v]]) : 0.0f; }, &mx,
+            &e_out);
         const floatx4 y = net_forward_tile_staged<VS>(F, T, lane);
         const int col = lane & 15;
 #pragma unroll
@@ -210,25 +217,17 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
             if (row < nrows && col < G::NOUT) pred[wid][row][col] = srow * y[e];
         }
         wave_lds_sync();
-        if (lane < nrows) {  // lane == r: this lane's node is row `lane`
-            const size_t cell = ((size_t)p[2] * ft.n[1] + p[1]) * ft.n[0] + p[0];
-            double e_in = 0.0, e_out = 0.0;
+        if (lane < nrows) {  // lane == r: this lane's node is row `lane`; energies in units of mx^2
+            float e_in = 0.0f;
 #pragma unroll
             for (int k = 0; k < G::NOUT; ++k) {
-                const double v = pred[wid][lane][k];
-                e_in += v * v / fk.f[ft.perm[f][entering_index<VS>(k)]];
-            }
-#pragma unroll
-            for (int j = 0; j < VS::Q; ++j) {
-                if (VS::cx(j) != -1) continue;
-                const int i = ft.perm[f][j];
-                const double g = fk.dec[i] * (double)ST::dec(src[(size_t)i * N + cell]);
-                e_out += g * g / fk.f[i];
+                const float v = pred[wid][lane][k] / mx;
+                e_in += v * v * (float)(1.0 / fk.f[ft.perm[f][entering_index<VS>(k)]]);
             }
             int nf = 0;
             for (int b = 0; b < VS::D; ++b) nf += (p[b] == 0) + (p[b] == ft.n[b] - 1);
-            const double budget = e_out / (double)((1 << nf) - 1);
-            const float sc = e_in > budget ? (float)sqrt(budget / e_in) : 1.0f;
+            const float budget = e_out / (float)((1 << nf) - 1);
+            const float sc = e_in > budget ? sqrtf(budget / e_in) : 1.0f;
 #pragma unroll
             for (int k = 0; k < G::NOUT; ++k) ghost[(base + lane) * G::NOUT + k] = sc * pred[wid][lane][k];
         }

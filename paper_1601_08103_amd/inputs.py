@@ -84,6 +84,56 @@ def plane_wave_fields(shape, k, A: float, rho0: float, theta0: float, gamma: flo
     return rho, u, theta
 
 
+@dataclass(frozen=True)
+class Packet:
+    centre: tuple     # (x, y, z) in cells
+    k: tuple          # wave vector (kx, ky, kz), radians per cell; travels along k
+    amplitude: float
+    width: float      # Gaussian envelope standard deviation in cells
+
+
+def packet_fields(shape, packets, rho0: float, theta0: float, gamma: float):
+    """Isentropic wave packets p' = A cos(k.(x - x0)) exp(-|x - x0|^2 / (2 w^2)) travelling along
+    k (u' = khat p' / (rho0 c), c^2 = gamma theta0).  Plain (not periodic) distances: the packets
+    must lie well inside the box."""
+    shape = tuple(int(s) for s in shape)
+    D = len(shape)
+    grids = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape], indexing="ij")
+    coords = [grids[D - 1 - a] for a in range(D)]
+    c = np.sqrt(gamma * theta0)
+    p = np.zeros(shape)
+    u = np.zeros((D,) + shape)
+    for pk in packets:
+        d = [coords[a] - pk.centre[a] for a in range(D)]
+        r2 = sum(x * x for x in d)
+        kx = sum(pk.k[a] * d[a] for a in range(D))
+        pp = pk.amplitude * np.cos(kx) * np.exp(-r2 / (2.0 * pk.width * pk.width))
+        kn = float(np.linalg.norm(pk.k[:D]))
+        p += pp
+        for a in range(D):
+            u[a] += (pk.k[a] / kn) * pp / (rho0 * c)
+    rho, _, theta = fields_from_pressure(p, rho0, theta0, gamma, "isentropic")
+    return rho, u, theta
+
+
+def random_packets(rng, L: int, D: int, count: int = 1, lam=(16.0, 64.0), amp: float = 1e-3, width_factor=2.0,
+                   margin_factor: float = 2.5):
+    """`count` packets in an L^D box: wavelength U(lam), width = width_factor * wavelength, centre
+    drawn so the envelope (margin_factor widths) stays inside where the box allows it (else the box
+    centre), travelling along a uniformly random direction (so it meets the faces at random angles)."""
+    out = []
+    for _ in range(count):
+        lamb = float(rng.uniform(*lam))
+        w = width_factor * lamb
+        lo, hi = margin_factor * w, L - margin_factor * w
+        centre = tuple(float(rng.uniform(lo, hi)) if hi > lo else L / 2.0 for _ in range(D))
+        v = rng.standard_normal(D)
+        v /= np.linalg.norm(v)
+        k = tuple(float(x) * 2.0 * np.pi / lamb for x in v) + (0.0,) * (3 - D)
+        out.append(Packet(centre, k, float(rng.choice([-1.0, 1.0])) * amp, w))
+    return out
+
+
 # ---------------------------------------------------------------- the workloads
 def pulses_1d(n: int = 1024):
     """One pulse, amplitude 1e-3, sigma 20 cells, centred at cell n/2."""

@@ -39,6 +39,20 @@ def inner_pulses(rng, L: int, D: int, nmin=1, nmax=4, amp=1e-3, smin=8.0, smax=2
     return out
 
 
+def initial_fields(kind, rng, info, L: int, D: int):
+    """Fields of one seeded initial state on the L^D box: "pulses" (1-4 Gaussian pressure pulses,
+    sigma U(8, 24)), "packets" (one wave packet, wavelength U(16, 64), width one wavelength, random
+    direction), or "mixed" (either, with probability 1/2)."""
+    if kind == "mixed":
+        kind = "pulses" if rng.uniform() < 0.5 else "packets"
+    if kind == "pulses":
+        return box_fields(info, (L,) * D, inner_pulses(rng, L, D))
+    if kind == "packets":
+        pk = inputs.random_packets(rng, L, D, 1, width_factor=1.0)
+        return inputs.packet_fields((L,) * D, pk, info["rho0"], info["theta0"], info["gamma"])
+    raise ValueError(kind)
+
+
 def box_fields(info, shape, pulses):
     """Isentropic fields of the pulses on the box (minimum-image Gaussians on the box itself)."""
     p0 = inputs.gaussian_pressure(shape, pulses)
@@ -60,7 +74,8 @@ def embed(torch, fields, L, E, D):
 
 
 # ---------------------------------------------------------------- training data
-def generate(lattice="D2Q9", L=512, E=1536, runs=100, steps=1024, every=8, nodes=256, seed=0, storage="f32"):
+def generate(lattice="D2Q9", L=512, E=1536, runs=100, steps=1024, every=8, nodes=256, seed=0, storage="f32",
+             init="pulses"):
     import torch
     info = lbm.lbm_lee_lattice_info(lattice)
     D = info["D"]
@@ -78,7 +93,7 @@ def generate(lattice="D2Q9", L=512, E=1536, runs=100, steps=1024, every=8, nodes
     ext = lbm.Solver(lattice, storage, (E,) * D, None, None, None)
     org = [(E - L) // 2] * D
     for r in range(runs):
-        ext.reinit_region(org, (L,) * D, *box_fields(info, (L,) * D, inner_pulses(rng, L, D)))
+        ext.reinit_region(org, (L,) * D, *initial_fields(init, rng, info, L, D))
         for s in range(0, steps, every):
             ids = torch.from_numpy(rng.integers(0, nn, size=nodes).astype(np.int64)).cuda()
             lbm.lbm_nrbc_gather(ext.h, origin, inner, ids.data_ptr(), nodes, S[k].data_ptr(), T[k].data_ptr(), st)
@@ -92,7 +107,7 @@ def generate(lattice="D2Q9", L=512, E=1536, runs=100, steps=1024, every=8, nodes
 
 
 def generate_closed_loop(lattice, params, L=512, E=1536, runs=100, steps=1024, every=8, nodes=256, seed=0,
-                         storage="f32"):
+                         storage="f32", init="pulses"):
     """Pairs from the states the closed loop visits: the open box runs with the network closure
     `params` beside the judge; inputs are the box's own strips at face nodes, targets the judge's
     entering populations at the same nodes (what the exact exterior would have supplied)."""
@@ -117,7 +132,7 @@ def generate_closed_loop(lattice, params, L=512, E=1536, runs=100, steps=1024, e
     k = 0
     t0 = time.time()
     for r in range(runs):
-        fields = box_fields(info, (L,) * D, inner_pulses(rng, L, D))
+        fields = initial_fields(init, rng, info, L, D)
         ext.reinit_region(org, (L,) * D, *fields)
         box.reinit_region([0] * D, (L,) * D, *fields)
         for s in range(0, steps, every):
@@ -199,54 +214,72 @@ def evaluate_loss(lattice, P, S, T, ws, wsb):
 
 
 # ---------------------------------------------------------------- evaluation
-def reflection(lattice, closure, pulses, L=512, E=1536, steps=1024, every=8, params=None, storage="f32",
-               ext_storage="f32", sponge_width=32, sponge_sigma=0.2, ext=None):
-    """R of one closure on one initial state (see the module docstring)."""
+def _compare(a, b, n3, scratch, scratch_bytes, st):
+    return lbm.lbm_lee_compare_fields(a.data_ptr(), n3, b.data_ptr(), n3, [0, 0, 0], scratch, scratch_bytes, st)
+
+
+def reflection(lattice, closure, fields, L=512, E=1536, steps=1024, every=8, params=None, storage="f32",
+               ext_storage="f32", sponge_width=32, sponge_sigma=0.2, ext=None, slices=False):
+    """R of one closure on one initial state (see the module docstring).  slices: compare on the
+    box's mid-planes (one per axis) instead of the whole box."""
     import torch
     info = lbm.lbm_lee_lattice_info(lattice)
     D = info["D"]
-    fields = box_fields(info, (L,) * D, pulses)
     W = sponge_width if closure == "sponge" else 0
     kw = dict(sponge_width=sponge_width, sponge_sigma=sponge_sigma) if closure == "sponge" else {}
     nb = L + 2 * W
-    box = lbm.Solver(lattice, storage, (nb,) * D, None, None, None, bc=closure, **kw)
-    box.reinit_region([W] * D, (L,) * D, *fields)
+    if W == 0:  # the library picks the 16-bit storage scale from the fields
+        box = lbm.Solver(lattice, storage, (L,) * D, *fields, bc=closure, **kw)
+    else:  # the sponge layer lies outside the fields: take the scale the box alone would get
+        probe = lbm.Solver(lattice, storage, (L,) * D, *fields)
+        scale = probe.store_scale if lbm.ELEM_BYTES[storage] == 2 else 0.0
+        probe.close()
+        box = lbm.Solver(lattice, storage, (nb,) * D, None, None, None, bc=closure, store_scale=scale, **kw)
+        box.reinit_region([W] * D, (L,) * D, *fields)
     if closure == "mlp":
         box.set_closure(params)
     own_ext = ext is None
     if own_ext:
         ext = lbm.Solver(lattice, ext_storage, (E,) * D, None, None, None)
-    oe = [(E - L) // 2] * D
-    ext.reinit_region(oe, (L,) * D, *fields)
+    oe = (E - L) // 2
+    ext.reinit_region([oe] * D, (L,) * D, *fields)
     st = torch.cuda.current_stream().cuda_stream
-    n3 = list(reversed((L,) * D)) + [1] * (3 - D)
+    # regions compared: (origin in box coordinates, extent), x-first
+    if slices and D > 1:
+        regions = []
+        for a in range(D):
+            o = [0] * D
+            n = [L] * D
+            o[a], n[a] = L // 2, 1
+            regions.append((o, n))
+    else:
+        regions = [([0] * D, [L] * D)]
     err_max = ref_max = 0.0
     for t in range(0, steps + 1, every):
         if t:
             box.step(every)
             ext.step(every)
-        pb = box.moments_region([W] * D, (L,) * D)["p"]
-        pe = ext.moments_region(oe, (L,) * D)["p"]
-        out = lbm.lbm_lee_compare_fields(pb.data_ptr(), n3, pe.data_ptr(), n3, [0, 0, 0], box.scratch.data_ptr(),
-                                         box.scratch_bytes, st)
-        if not all(math.isfinite(v) for v in out):
+        e2 = r2 = 0.0
+        for o, n in regions:
+            shape = tuple(reversed(n))
+            pb = box.moments_region([v + W for v in o], shape)["p"]
+            pe = ext.moments_region([v + oe for v in o], shape)["p"]
+            out = _compare(pb, pe, list(n) + [1] * (3 - D), box.scratch.data_ptr(), box.scratch_bytes, st)
+            e2 += out[0]
+            r2 += out[1]
+        if not (math.isfinite(e2) and math.isfinite(r2)):
             err_max = float("inf")
             break
-        err_max = max(err_max, math.sqrt(out[0]))
-        ref_max = max(ref_max, math.sqrt(out[1]))
+        err_max = max(err_max, math.sqrt(e2))
+        ref_max = max(ref_max, math.sqrt(r2))
     box.close()
     if own_ext:
         ext.close()
     return err_max / ref_max if ref_max > 0 else float("nan")
 
 
-def time_per_step(lattice, shape, bc="periodic", params=None, storage="f32", steps=200, **kw):
+def time_solver(sim, steps=200):
     import torch
-    info = lbm.lbm_lee_lattice_info(lattice)
-    D = info["D"]
-    sim = lbm.Solver(lattice, storage, shape, None, None, None, bc=bc, **kw)
-    if bc == "mlp":
-        sim.set_closure(params)
     sim.step(10)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -254,15 +287,22 @@ def time_per_step(lattice, shape, bc="periodic", params=None, storage="f32", ste
     sim.step(steps)
     e1.record()
     torch.cuda.synchronize()
-    sim.close()
     return e0.elapsed_time(e1) / steps
+
+
+def time_per_step(lattice, shape, bc="periodic", params=None, storage="f32", steps=200, **kw):
+    sim = lbm.Solver(lattice, storage, shape, None, None, None, bc=bc, **kw)
+    if bc == "mlp":
+        sim.set_closure(params)
+    ms = time_solver(sim, steps)
+    sim.close()
+    return ms
 
 
 # ---------------------------------------------------------------- command line
 def main(argv=None):
     """python -m paper_1601_08103_amd.nrbc {train,evaluate} ...  (JSON on stdout, progress on stderr)."""
     import argparse
-    import os
     import torch
 
     ap = argparse.ArgumentParser()
@@ -272,12 +312,17 @@ def main(argv=None):
     ap.add_argument("--E", type=int, default=1536)
     ap.add_argument("--steps", type=int, default=1024)
     ap.add_argument("--runs", type=int, default=200)
-    ap.add_argument("--every", type=int, default=8)
+    ap.add_argument("--every", type=int, default=8, help="steps between samples (training) / comparisons")
     ap.add_argument("--nodes", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--init", default="pulses", choices=["pulses", "packets", "mixed"])
+    ap.add_argument("--storage", default="f32", help="storage of the open box (evaluate)")
+    ap.add_argument("--ext-storage", default="f32", help="storage of the judge run")
+    ap.add_argument("--slices", action="store_true", help="compare on the mid-planes only (evaluate)")
+    ap.add_argument("--closures", default="zero,copy,sponge,mlp")
     ap.add_argument("--weights", default=None, help="weights file (.npy) to write (train) or read (evaluate)")
     ap.add_argument("--seeds", type=int, default=32, help="held-out initial states for evaluate")
     ap.add_argument("--sponge-width", type=int, default=32)
@@ -288,12 +333,15 @@ def main(argv=None):
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
     lbm.load()
+    info = lbm.lbm_lee_lattice_info(args.lattice)
+    D = info["D"]
     if args.mode == "train":
-        S, T = generate(args.lattice, args.L, args.E, args.runs, args.steps, args.every, args.nodes, args.seed)
+        S, T = generate(args.lattice, args.L, args.E, args.runs, args.steps, args.every, args.nodes, args.seed,
+                        init=args.init)
         P, hist = train(args.lattice, S, T, args.epochs, args.batch, args.lr, seed=args.seed)
         for d in range(args.dagger):
             Sc, Tc = generate_closed_loop(args.lattice, P, args.L, args.E, args.dagger_runs, args.steps, args.every,
-                                          args.nodes, seed=args.seed + 1000 * (d + 1))
+                                          args.nodes, seed=args.seed + 1000 * (d + 1), init=args.init)
             S, T = torch.cat([S, Sc]), torch.cat([T, Tc])
             del Sc, Tc
             P, h2 = train(args.lattice, S, T, args.dagger_epochs, args.batch, args.lr * 0.3, seed=args.seed + d + 1,
@@ -301,29 +349,32 @@ def main(argv=None):
             hist += [dict(h, dagger=d + 1) for h in h2]
         if args.weights:
             np.save(args.weights, P.astype(np.float32), allow_pickle=False)
-        print(json.dumps(dict(mode="train", lattice=args.lattice, pairs=int(S.shape[0]), runs=args.runs,
-                              history=hist)))
+        print(json.dumps(dict(mode="train", lattice=args.lattice, init=args.init, pairs=int(S.shape[0]),
+                              runs=args.runs, dagger=args.dagger, history=hist)))
         return
     P = np.load(args.weights, allow_pickle=False) if args.weights else None
     rng = np.random.default_rng(10_000 + args.seed)  # held out: training uses seeds below 10000
-    info = lbm.lbm_lee_lattice_info(args.lattice)
-    D = info["D"]
-    closures = ["zero", "copy", "sponge"] + (["mlp"] if P is not None else [])
+    closures = [c for c in args.closures.split(",") if c and (c != "mlp" or P is not None)]
     Rs = {c: [] for c in closures}
-    ext = lbm.Solver(args.lattice, "f32", (args.E,) * D, None, None, None)
+    ext = lbm.Solver(args.lattice, args.ext_storage, (args.E,) * D, None, None, None)
     for k in range(args.seeds):
-        pulses = inner_pulses(rng, args.L, D)
+        fields = initial_fields(args.init, rng, info, args.L, D)
         for c in closures:
-            Rs[c].append(reflection(args.lattice, c, pulses, args.L, args.E, args.steps, 8, params=P,
-                                    sponge_width=args.sponge_width, sponge_sigma=args.sponge_sigma, ext=ext))
+            Rs[c].append(reflection(args.lattice, c, fields, args.L, args.E, args.steps, args.every, params=P,
+                                    storage=args.storage, ext_storage=args.ext_storage,
+                                    sponge_width=args.sponge_width, sponge_sigma=args.sponge_sigma, ext=ext,
+                                    slices=args.slices))
         log(f"evaluate: seed {k + 1}/{args.seeds}: " + ", ".join(f"{c} {Rs[c][-1]:.4f}" for c in closures))
-    times = {"extended_periodic": time_per_step(args.lattice, (args.E,) * D)}
+    times = {"extended_periodic": time_solver(ext, 50 if D == 3 else 200)}
+    ext.close()
+    del ext
     for c in closures:
         kw = dict(sponge_width=args.sponge_width, sponge_sigma=args.sponge_sigma) if c == "sponge" else {}
         nb = args.L + (2 * args.sponge_width if c == "sponge" else 0)
-        times[c] = time_per_step(args.lattice, (nb,) * D, bc=c, params=P, **kw)
-    print(json.dumps(dict(mode="evaluate", lattice=args.lattice, L=args.L, E=args.E, steps=args.steps,
-                          seeds=args.seeds, R_mean={c: float(np.mean(v)) for c, v in Rs.items()},
+        times[c] = time_per_step(args.lattice, (nb,) * D, bc=c, params=P, storage=args.storage, **kw)
+    print(json.dumps(dict(mode="evaluate", lattice=args.lattice, init=args.init, L=args.L, E=args.E,
+                          steps=args.steps, storage=args.storage, ext_storage=args.ext_storage, seeds=args.seeds,
+                          slices=args.slices, R_mean={c: float(np.mean(v)) for c, v in Rs.items()},
                           R_max={c: float(np.max(v)) for c, v in Rs.items()}, ms_per_step=times)))
 
 
