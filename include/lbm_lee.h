@@ -246,7 +246,10 @@ size_t lbm_lee_ghost_bytes(const lbm_lee_desc *desc);
 /* Attach the closure network (device FP32 parameters, layout of lbm_nrbc_dims) and the ghost
  * buffer to an LBM_BC_MLP handle.  The library keeps the pointers; the caller keeps both
  * buffers alive and may update the parameters between steps.  Steps fail with LBM_E_STATE
- * until this has been called. */
+ * until this has been called.  The first call creates, on the current device (which must be
+ * the handle's), a helper stream and two events: each step forks the network onto that stream
+ * so it runs beside the bulk step kernel, and joins it back before the boundary recompute;
+ * lbm_lee_destroy releases them.  Errors: LBM_E_HIP if they cannot be created. */
 lbm_status lbm_lee_set_closure(lbm_lee_handle h, const float *params, void *ghost, size_t ghost_bytes);
 
 /*

@@ -33,6 +33,16 @@ struct lbm_lee {
     const float *net;  // LBM_BC_MLP: closure parameters (caller-owned)
     float *ghost;      // LBM_BC_MLP: ghost buffer (caller-owned)
     bool skip0;        // rest population left out of the step (invariant under it)
+    // LBM_BC_MLP: the network runs on a helper stream of the handle's device, concurrently with
+    // the bulk step (both only read the pre-step state); events fork it from and join it to
+    // the caller's stream.  Created by lbm_lee_set_closure, released by lbm_lee_destroy.
+    hipStream_t aux = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    ~lbm_lee() {
+        if (join) (void)hipEventDestroy(join);
+        if (fork) (void)hipEventDestroy(fork);
+        if (aux) (void)hipStreamDestroy(aux);
+    }
 };
 
 namespace {
@@ -587,7 +597,7 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
         const unsigned lds_blocks = (unsigned)((size_t)h->ny * h->nz * lds_cpr);
         FaceTab<VS::Q> ft;
         FieldCoef<VS::Q> fk;
-        unsigned shell_x = 1, ghost_blocks = 1;
+        unsigned shell_x = 1, ghost_blocks = 1, sponge_x = 1;
         if (bc != LBM_BC_PERIODIC) {
             ft = face_table<VS>(h->tab, h->desc.n);
             fk = field_coef<VS::Q>(h);
@@ -599,6 +609,16 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
                 if (cnt > mx) mx = cnt;
             }
             shell_x = (unsigned)((mx + 255) / 256);
+            if (bc == LBM_BC_SPONGE) {  // the largest slab: depth W times a full face
+                long long big = 1;
+                for (int a = 0; a < VS::D; ++a) {
+                    long long cnt = std::min<long long>(h->desc.sponge_width, h->desc.n[a]);
+                    for (int b = 0; b < VS::D; ++b)
+                        if (b != a) cnt *= h->desc.n[b];
+                    big = std::max(big, cnt);
+                }
+                sponge_x = (unsigned)((big + 255) / 256);
+            }
             const long long tiles = (ft.node_off[ft.nfaces] + 15) / 16;
             ghost_blocks = (unsigned)std::min<long long>((tiles + 3) / 4, 4096);
         }
@@ -608,8 +628,12 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
             for (int64_t t = 0; t < nsteps; ++t) {
                 const E *src = static_cast<const E *>(h->buf[h->cur]);
                 E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);
-                if (bc == LBM_BC_MLP)
-                    ghost_mlp_kernel<VS, ST><<<ghost_blocks, 256, 0, st>>>(src, h->N, h->net, h->ghost, ft, fk);
+                if (bc == LBM_BC_MLP) {  // fork: the network on the helper stream
+                    LBM_HIP(hipEventRecord(h->fork, st));
+                    LBM_HIP(hipStreamWaitEvent(h->aux, h->fork, 0));
+                    ghost_mlp_kernel<VS, ST><<<ghost_blocks, 256, 0, h->aux>>>(src, h->N, h->net, h->ghost, ft, fk);
+                    LBM_HIP(hipEventRecord(h->join, h->aux));
+                }
                 if (variant == LBM_VARIANT_GENERIC) {
                     step_generic<VS, ST, SK, HF><<<blocks_for(h->N), 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, k);
                 } else if (variant == LBM_VARIANT_LDS) {
@@ -629,13 +653,13 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
                         step_dpp<VS, ST, 2, false, SK, HF><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
                                                                             waves, tune, k);
                 }
+                if (bc == LBM_BC_MLP) LBM_HIP(hipStreamWaitEvent(st, h->join, 0));  // join
                 if (bc != LBM_BC_PERIODIC) {
                     shell_kernel<VS, ST, SK, HF><<<dim3(shell_x, 2 * VS::D), 256, 0, st>>>(src, dst, h->N, bc, h->ghost,
                                                                                       ft, k, fk);
                     if (bc == LBM_BC_SPONGE)
-                        sponge_kernel<VS, ST><<<blocks_for(h->N), 256, 0, st>>>(dst, h->N, h->nx, h->ny, h->nz,
-                                                                              h->desc.sponge_width,
-                                                                              h->desc.sponge_sigma);
+                        sponge_kernel<VS, ST><<<dim3(sponge_x, 2 * VS::D), 256, 0, st>>>(
+                            dst, h->N, h->nx, h->ny, h->nz, h->desc.sponge_width, h->desc.sponge_sigma);
                 }
                 lbm_status ls = launch_check();
                 if (ls != LBM_OK) return ls;
@@ -783,6 +807,21 @@ lbm_status lbm_lee_set_closure(lbm_lee_handle h, const float *params, void *ghos
     if (ghost_bytes < lbm_lee_ghost_bytes(&h->desc)) return fail(LBM_E_INVALID, "ghost buffer too small");
     if (reinterpret_cast<uintptr_t>(params) & 3 || reinterpret_cast<uintptr_t>(ghost) & 3)
         return fail(LBM_E_INVALID, "params and ghost must be 4-byte aligned");
+    if (!h->aux) {
+        hipStream_t a = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&e0, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&e1, hipEventDisableTiming) != hipSuccess) {
+            if (e0) (void)hipEventDestroy(e0);
+            if (a) (void)hipStreamDestroy(a);
+            (void)hipGetLastError();
+            return fail(LBM_E_HIP, "cannot create the closure's helper stream and events");
+        }
+        h->aux = a;
+        h->fork = e0;
+        h->join = e1;
+    }
     h->net = params;
     h->ghost = static_cast<float *>(ghost);
     return ok();

@@ -71,8 +71,14 @@ __device__ inline int node_cell(const FaceTab<Q> &ft, long long g, int (&p)[3]) 
     infaces(a, ft.D, t1, t2);
     p[0] = p[1] = p[2] = 0;
     if (t1 >= 0) {
-        p[t1] = (int)(nd % ft.n[t1]);
-        nd /= ft.n[t1];
+        if (nd <= 0x7fffffffLL) {  // 32-bit division when it fits (64-bit division is emulated)
+            const unsigned u = (unsigned)nd, m = (unsigned)ft.n[t1];
+            p[t1] = (int)(u % m);
+            nd = u / m;
+        } else {
+            p[t1] = (int)(nd % ft.n[t1]);
+            nd /= ft.n[t1];
+        }
     }
     if (t2 >= 0) p[t2] = (int)nd;
     p[a] = (f & 1) ? ft.n[a] - 1 : 0;
@@ -96,8 +102,13 @@ __global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__r
     const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
     if (t >= (long long)n1 * n2) return;
     int x[3] = {0, 0, 0};
-    if (t1 >= 0) x[t1] = (int)(t % n1) + lo1;
-    if (t2 >= 0) x[t2] = (int)(t / n1) + lo2;
+    if (t <= 0x7fffffffLL) {  // 32-bit division when it fits
+        if (t1 >= 0) x[t1] = (int)((unsigned)t % (unsigned)n1) + lo1;
+        if (t2 >= 0) x[t2] = (int)((unsigned)t / (unsigned)n1) + lo2;
+    } else {
+        if (t1 >= 0) x[t1] = (int)(t % n1) + lo1;
+        if (t2 >= 0) x[t2] = (int)(t / n1) + lo2;
+    }
     x[a] = side ? ft.n[a] - 1 : 0;
     const size_t cell = ((size_t)x[2] * ft.n[1] + x[1]) * ft.n[0] + x[0];
     constexpr int K = NetGeom<VS>::NOUT;
@@ -131,7 +142,7 @@ __global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__r
                     ++cnt;
                 }
             }
-            v = (CT)(fk.enc[i] * (double)(acc / (float)cnt));
+            v = (CT)(acc / (float)cnt) * (CT)fk.enc[i];
         }
         s[i] = v;
     }
@@ -141,19 +152,45 @@ __global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__r
 }
 
 // ------------------------------------------------------------------ sponge damping
+// Grid (x blocks, 2D slabs): slab f = 2a + side holds the cells within W of face f that are not
+// in a slab of a lower axis, so every layer cell is visited exactly once and the interior not at all.
 template <class VS, class ST>
 __global__ __launch_bounds__(256) void sponge_kernel(typename ST::elem *__restrict__ g, size_t N, int nx, int ny,
                                                      int nz, int width, double sigma_max) {
     using CT = typename ST::comp;
-    const size_t cell = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (cell >= N) return;
-    const int x = (int)(cell % nx);
-    const size_t r = cell / nx;
-    const int y = (int)(r % ny), z = (int)(r / ny);
+    const int n[3] = {nx, ny, nz};
+    const int f = blockIdx.y, a = f >> 1, side = f & 1;
+    const int wa = min(width, n[a]);  // slab depth
+    int ext[3], lo[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        if (b == a) {
+            ext[b] = wa;
+            lo[b] = side ? n[b] - wa : 0;
+        } else if (b < a && b < VS::D) {  // the slabs of axis b own its first and last W cells
+            const int wb = min(width, n[b]);
+            ext[b] = max(n[b] - 2 * wb, 0);
+            lo[b] = wb;
+        } else {
+            ext[b] = n[b];
+            lo[b] = 0;
+        }
+    }
+    if (side == 1 && 2 * wa > n[a]) {  // thin box: the low slab already covers the overlap
+        ext[a] = n[a] - wa;
+        lo[a] = wa;
+    }
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long long)ext[0] * ext[1] * ext[2]) return;
+    const long long r = t / ext[0];
+    const int x = (int)(t - r * ext[0]) + lo[0];
+    const int y = (int)(r % ext[1]) + lo[1];
+    const int z = (int)(r / ext[1]) + lo[2];
     int d = min(x, nx - 1 - x);
     if (VS::D >= 2) d = min(d, min(y, ny - 1 - y));
     if (VS::D >= 3) d = min(d, min(z, nz - 1 - z));
     if (d >= width) return;
+    const size_t cell = ((size_t)z * ny + y) * nx + x;
     const CT w = (CT)(width - d) / (CT)width;
     const CT fac = (CT)1 - (CT)sigma_max * w * w;
 #pragma unroll
