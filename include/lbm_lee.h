@@ -79,6 +79,10 @@ typedef int32_t lbm_status;
 #define LBM_TUNE_PERSISTENT 4 /* grid sized to the resident wave slots, grid-stride loop */
 #define LBM_TUNE_FULL_REST 8  /* also load, collide and store the rest population where it is */
                               /* provably invariant (see lbm_lee_bytes_per_update)            */
+#define LBM_TUNE_CLOSURE_STREAM 16 /* LBM_BC_MLP: run the network on the handle's helper stream,  */
+                                   /* forked from and joined to the caller's stream each step, so */
+                                   /* it overlaps the bulk step (pays off in captured graphs;     */
+                                   /* eager launches add two event calls per step)                */
 
 /* Boundary of the box.  The paper's scheme is periodic; the open closures are not in the
  * paper (it leaves boundary conditions to future work) and are defined here.  For a cell x
@@ -247,9 +251,10 @@ size_t lbm_lee_ghost_bytes(const lbm_lee_desc *desc);
  * buffer to an LBM_BC_MLP handle.  The library keeps the pointers; the caller keeps both
  * buffers alive and may update the parameters between steps.  Steps fail with LBM_E_STATE
  * until this has been called.  The first call creates, on the current device (which must be
- * the handle's), a helper stream and two events: each step forks the network onto that stream
- * so it runs beside the bulk step kernel, and joins it back before the boundary recompute;
- * lbm_lee_destroy releases them.  Errors: LBM_E_HIP if they cannot be created. */
+ * the handle's), a helper stream and two events; with LBM_TUNE_CLOSURE_STREAM each step forks
+ * the network onto that stream so it runs beside the bulk step kernel, and joins it back before
+ * the boundary recompute.  lbm_lee_destroy releases them.  Errors: LBM_E_HIP if they cannot be
+ * created. */
 lbm_status lbm_lee_set_closure(lbm_lee_handle h, const float *params, void *ghost, size_t ghost_bytes);
 
 /*

@@ -125,7 +125,7 @@ lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
     if ((double)d->n[1] * (double)d->n[2] * 16.0 > 4.0e9) return fail(LBM_E_INVALID, "too many rows (ny * nz)");
     if (!(d->tau >= 0.5) || !std::isfinite(d->tau)) return fail(LBM_E_INVALID, "tau must be finite and >= 1/2 (got %g)", d->tau);
     if (d->variant < LBM_VARIANT_AUTO || d->variant > LBM_VARIANT_DPP2) return fail(LBM_E_INVALID, "unknown variant %d", d->variant);
-    if (d->tune < 0 || d->tune > 15) return fail(LBM_E_INVALID, "unknown tune bits 0x%x", d->tune);
+    if (d->tune < 0 || d->tune > 31) return fail(LBM_E_INVALID, "unknown tune bits 0x%x", d->tune);
     if (!(d->store_scale >= 0.0) || !std::isfinite(d->store_scale)) return fail(LBM_E_INVALID, "store_scale must be >= 0");
     if (d->store_scale > 0.0) {
         int ex;
@@ -207,8 +207,10 @@ Kc<CT> split(double v) {
 
 // Per-shell collision constants (the shell of population i is |c_i|^2); shell_uniform() has
 // checked that every population of a shell has the same f*_i and beta_i.
+// raw_unit: the step works on stored values times raw_unit (the storage type's raw domain, 1
+// for the plain formats): the moment constants take 1/raw_unit, the equilibrium weight raw_unit.
 template <typename CT, int Q>
-StepCoef<CT, Q> step_coef(const lbm_lee *h) {
+StepCoef<CT, Q> step_coef(const lbm_lee *h, double raw_unit = 1.0) {
     const FieldCoef<Q> f = field_coef<Q>(h);
     StepCoef<CT, Q> k;
     std::memset(&k, 0, sizeof k);
@@ -216,10 +218,10 @@ StepCoef<CT, Q> step_coef(const lbm_lee *h) {
     const LatticeTable &t = h->tab;
     for (int i = 0; i < Q; ++i) {
         const int sh = t.c[i][0] * t.c[i][0] + t.c[i][1] * t.c[i][1] + t.c[i][2] * t.c[i][2];
-        k.dec[sh] = split<CT>(f.dec[i]);
-        k.edec[sh] = split<CT>(f.e[i] * f.dec[i]);
-        k.bu[sh] = split<CT>(f.b * f.dec[i] / f.rho0);
-        k.w[sh] = split<CT>(omega * f.enc[i] * f.f[i]);
+        k.dec[sh] = split<CT>(f.dec[i] / raw_unit);
+        k.edec[sh] = split<CT>(f.e[i] * f.dec[i] / raw_unit);
+        k.bu[sh] = split<CT>(f.b * f.dec[i] / f.rho0 / raw_unit);
+        k.w[sh] = split<CT>(omega * f.enc[i] * f.f[i] * raw_unit);
     }
     k.keep = split<CT>(1.0 - omega);
     k.gm1_rho0 = split<CT>(f.gm1 / f.rho0);
@@ -574,12 +576,15 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
         using VS = decltype(vs);
         using ST = decltype(sto);
         using E = typename ST::elem;
-        const auto k = step_coef<typename ST::comp, VS::Q>(h);
+        // bulk kernels in the storage type's raw domain; the shell recompute in the real one
+        const auto k = step_coef<typename ST::comp, VS::Q>(h, ST::raw_unit);
+        const auto ks = step_coef<typename ST::comp, VS::Q>(h);
         const int vec = variant == LBM_VARIANT_DPP2 ? 2 : 4;
         const int cpr = (h->nx + 64 * vec - 1) / (64 * vec);
         const unsigned waves = (unsigned)((size_t)h->ny * h->nz * cpr);
         const bool fullrow = h->nx == 64 * vec;
         const unsigned tune = (unsigned)h->desc.tune;
+        const bool fork = (tune & 16u) != 0;  // LBM_TUNE_CLOSURE_STREAM
         unsigned grid = (waves + 3) / 4;
         if ((tune & kTunePersistent) && h->cus > 0 && (variant == LBM_VARIANT_DPP || variant == LBM_VARIANT_DPP2)) {
             int per_cu = 0;
@@ -628,11 +633,13 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
             for (int64_t t = 0; t < nsteps; ++t) {
                 const E *src = static_cast<const E *>(h->buf[h->cur]);
                 E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);
-                if (bc == LBM_BC_MLP) {  // fork: the network on the helper stream
+                if (bc == LBM_BC_MLP && fork) {  // fork: the network on the helper stream
                     LBM_HIP(hipEventRecord(h->fork, st));
                     LBM_HIP(hipStreamWaitEvent(h->aux, h->fork, 0));
                     ghost_mlp_kernel<VS, ST><<<ghost_blocks, 256, 0, h->aux>>>(src, h->N, h->net, h->ghost, ft, fk);
                     LBM_HIP(hipEventRecord(h->join, h->aux));
+                } else if (bc == LBM_BC_MLP) {
+                    ghost_mlp_kernel<VS, ST><<<ghost_blocks, 256, 0, st>>>(src, h->N, h->net, h->ghost, ft, fk);
                 }
                 if (variant == LBM_VARIANT_GENERIC) {
                     step_generic<VS, ST, SK, HF><<<blocks_for(h->N), 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, k);
@@ -653,10 +660,10 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
                         step_dpp<VS, ST, 2, false, SK, HF><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
                                                                             waves, tune, k);
                 }
-                if (bc == LBM_BC_MLP) LBM_HIP(hipStreamWaitEvent(st, h->join, 0));  // join
+                if (bc == LBM_BC_MLP && fork) LBM_HIP(hipStreamWaitEvent(st, h->join, 0));  // join
                 if (bc != LBM_BC_PERIODIC) {
                     shell_kernel<VS, ST, SK, HF><<<dim3(shell_x, 2 * VS::D), 256, 0, st>>>(src, dst, h->N, bc, h->ghost,
-                                                                                      ft, k, fk);
+                                                                                      ft, ks, fk);
                     if (bc == LBM_BC_SPONGE)
                         sponge_kernel<VS, ST><<<dim3(sponge_x, 2 * VS::D), 256, 0, st>>>(
                             dst, h->N, h->nx, h->ny, h->nz, h->desc.sponge_width, h->desc.sponge_sigma);

@@ -12,14 +12,16 @@
 namespace lbm {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
-typedef short s16x4 __attribute__((ext_vector_type(4)));
 
 struct StF64 {
     using elem = double;
     using comp = double;
     static constexpr bool scaled = false;
+    // raw domain of the step kernels (see StE3M12); identical to the real domain here
+    static constexpr bool has_raw = false;
+    static constexpr double raw_unit = 1.0;
+    __device__ static comp dec_raw(elem v) { return dec(v); }
+    __device__ static elem enc_raw(comp v) { return enc(v); }
     __device__ static comp dec(elem v) { return v; }
     __device__ static elem enc(comp v) { return v; }
     __device__ static elem enc_d(double v) { return v; }
@@ -29,6 +31,11 @@ struct StF32 {
     using elem = float;
     using comp = float;
     static constexpr bool scaled = false;
+    // raw domain of the step kernels (see StE3M12); identical to the real domain here
+    static constexpr bool has_raw = false;
+    static constexpr double raw_unit = 1.0;
+    __device__ static comp dec_raw(elem v) { return dec(v); }
+    __device__ static elem enc_raw(comp v) { return enc(v); }
     __device__ static comp dec(elem v) { return v; }
     __device__ static elem enc(comp v) { return v; }
     __device__ static elem enc_d(double v) { return (float)v; }
@@ -38,6 +45,11 @@ struct StF16 {
     using elem = unsigned short;
     using comp = float;
     static constexpr bool scaled = true;
+    // raw domain of the step kernels (see StE3M12); identical to the real domain here
+    static constexpr bool has_raw = false;
+    static constexpr double raw_unit = 1.0;
+    __device__ static comp dec_raw(elem v) { return dec(v); }
+    __device__ static elem enc_raw(comp v) { return enc(v); }
     __device__ static comp dec(elem v) { return (float)__builtin_bit_cast(_Float16, v); }
     // v_cvt_f16_f32 rounds with the default mode: to nearest, ties to even.
     __device__ static elem enc(comp v) { return __builtin_bit_cast(unsigned short, (_Float16)v); }
@@ -48,6 +60,11 @@ struct StBF16 {
     using elem = unsigned short;
     using comp = float;
     static constexpr bool scaled = true;
+    // raw domain of the step kernels (see StE3M12); identical to the real domain here
+    static constexpr bool has_raw = false;
+    static constexpr double raw_unit = 1.0;
+    __device__ static comp dec_raw(elem v) { return dec(v); }
+    __device__ static elem enc_raw(comp v) { return enc(v); }
     __device__ static comp dec(elem v) { return __uint_as_float(((unsigned)v) << 16); }
     // Round to nearest, ties to even, on the upper 16 bits of the FP32 pattern.  Finite
     // inputs only (the state of a stable run never holds NaN or Inf).
@@ -63,6 +80,11 @@ struct StI16 {
     using elem = short;
     using comp = float;
     static constexpr bool scaled = true;
+    // raw domain of the step kernels (see StE3M12); identical to the real domain here
+    static constexpr bool has_raw = false;
+    static constexpr double raw_unit = 1.0;
+    __device__ static comp dec_raw(elem v) { return dec(v); }
+    __device__ static elem enc_raw(comp v) { return enc(v); }
     __device__ static comp dec(elem v) { return (float)v; }
     __device__ static elem enc(comp v) {
         const float r = __builtin_rintf(v);  // ties to even
@@ -102,6 +124,25 @@ struct StE3M12 {
         const unsigned rs = __float_as_uint(__builtin_fabsf(v) + 32.0f) - 0x42000000u;
         return (elem)((b >= (121u << 23) ? rn : rs) | ((bits >> 16) & 0x8000u));
     }
+    // Raw domain: the FP32 number whose exponent and mantissa fields are the code's, i.e. the
+    // value times 2^-120 (an FP32 denormal below 2^-6).  The bulk step works on raw values with
+    // 2^120 folded into its constants: decoding is a shift and a mask, and encoding is one
+    // integer rounding of the FP32 pattern for every magnitude (the denormal patterns continue
+    // the normal ones with the same spacing).  A raw result below 2^-126 has been rounded to
+    // FP32's denormal spacing (2^-29 in value units) before that, a 2^-30 effect on a 2^-19
+    // rounding step.
+    static constexpr bool has_raw = true;
+    static constexpr double raw_unit = 0x1p-120;  // raw value = value * raw_unit
+    __device__ static comp dec_raw(elem v) {
+        const unsigned x = ((unsigned)v) << 16;
+        return __uint_as_float(((x >> 5) & 0x03fff800u) | (x & 0x80000000u));
+    }
+    __device__ static elem enc_raw(comp v) {
+        const unsigned bits = __float_as_uint(v);
+        const unsigned b = bits & 0x7fffffffu;
+        const unsigned code = min((b + 0x3ffu + ((b >> 11) & 1u)) >> 11, 0x7fffu);
+        return (elem)(code | ((bits >> 16) & 0x8000u));
+    }
     __device__ static elem enc_d(double v) { return enc((float)v); }
 };
 
@@ -119,94 +160,55 @@ __device__ __forceinline__ void vstore(V *p, V v, bool nt) {
         *p = v;
 }
 
-template <class ST>
-__device__ inline void load4(const typename ST::elem *p, typename ST::comp (&v)[4], bool nt = false);
-
-template <>
-__device__ inline void load4<StF64>(const double *p, double (&v)[4], bool nt) {
-    f64x2 a = vload(reinterpret_cast<const f64x2 *>(p), nt);
-    f64x2 b = vload(reinterpret_cast<const f64x2 *>(p + 2), nt);
-    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+// Element decode/encode in the real or (RAW) raw domain.
+template <class ST, bool RAW>
+__device__ __forceinline__ typename ST::comp dec_io(typename ST::elem v) {
+    if constexpr (RAW)
+        return ST::dec_raw(v);
+    else
+        return ST::dec(v);
 }
-template <>
-__device__ inline void load4<StF32>(const float *p, float (&v)[4], bool nt) {
-    f32x4 a = vload(reinterpret_cast<const f32x4 *>(p), nt);
-    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-}
-template <>
-__device__ inline void load4<StF16>(const unsigned short *p, float (&v)[4], bool nt) {
-    u16x4 a = vload(reinterpret_cast<const u16x4 *>(p), nt);
-    v[0] = StF16::dec(a.x); v[1] = StF16::dec(a.y); v[2] = StF16::dec(a.z); v[3] = StF16::dec(a.w);
-}
-template <>
-__device__ inline void load4<StBF16>(const unsigned short *p, float (&v)[4], bool nt) {
-    u16x4 a = vload(reinterpret_cast<const u16x4 *>(p), nt);
-    v[0] = StBF16::dec(a.x); v[1] = StBF16::dec(a.y); v[2] = StBF16::dec(a.z); v[3] = StBF16::dec(a.w);
+template <class ST, bool RAW>
+__device__ __forceinline__ typename ST::elem enc_io(typename ST::comp v) {
+    if constexpr (RAW)
+        return ST::enc_raw(v);
+    else
+        return ST::enc(v);
 }
 
-template <>
-__device__ inline void load4<StE3M12>(const unsigned short *p, float (&v)[4], bool nt) {
-    u16x4 a = vload(reinterpret_cast<const u16x4 *>(p), nt);
-    v[0] = StE3M12::dec(a.x); v[1] = StE3M12::dec(a.y); v[2] = StE3M12::dec(a.z); v[3] = StE3M12::dec(a.w);
+template <class ST, bool RAW = false>
+__device__ inline void load4(const typename ST::elem *p, typename ST::comp (&v)[4], bool nt = false) {
+    using E = typename ST::elem;
+    typedef E e4 __attribute__((ext_vector_type(4)));
+    const e4 a = vload(reinterpret_cast<const e4 *>(p), nt);
+    v[0] = dec_io<ST, RAW>(a.x);
+    v[1] = dec_io<ST, RAW>(a.y);
+    v[2] = dec_io<ST, RAW>(a.z);
+    v[3] = dec_io<ST, RAW>(a.w);
 }
 
-template <>
-__device__ inline void load4<StI16>(const short *p, float (&v)[4], bool nt) {
-    s16x4 a = vload(reinterpret_cast<const s16x4 *>(p), nt);
-    v[0] = StI16::dec(a.x); v[1] = StI16::dec(a.y); v[2] = StI16::dec(a.z); v[3] = StI16::dec(a.w);
-}
-
-template <class ST>
-__device__ inline void store4(typename ST::elem *p, const typename ST::comp (&v)[4], bool nt = false);
-
-template <>
-__device__ inline void store4<StF64>(double *p, const double (&v)[4], bool nt) {
-    f64x2 a = {v[0], v[1]}, b = {v[2], v[3]};
-    vstore(reinterpret_cast<f64x2 *>(p), a, nt);
-    vstore(reinterpret_cast<f64x2 *>(p + 2), b, nt);
-}
-template <>
-__device__ inline void store4<StF32>(float *p, const float (&v)[4], bool nt) {
-    f32x4 a = {v[0], v[1], v[2], v[3]};
-    vstore(reinterpret_cast<f32x4 *>(p), a, nt);
-}
-template <>
-__device__ inline void store4<StF16>(unsigned short *p, const float (&v)[4], bool nt) {
-    u16x4 a = {StF16::enc(v[0]), StF16::enc(v[1]), StF16::enc(v[2]), StF16::enc(v[3])};
-    vstore(reinterpret_cast<u16x4 *>(p), a, nt);
-}
-template <>
-__device__ inline void store4<StBF16>(unsigned short *p, const float (&v)[4], bool nt) {
-    u16x4 a = {StBF16::enc(v[0]), StBF16::enc(v[1]), StBF16::enc(v[2]), StBF16::enc(v[3])};
-    vstore(reinterpret_cast<u16x4 *>(p), a, nt);
-}
-
-template <>
-__device__ inline void store4<StE3M12>(unsigned short *p, const float (&v)[4], bool nt) {
-    u16x4 a = {StE3M12::enc(v[0]), StE3M12::enc(v[1]), StE3M12::enc(v[2]), StE3M12::enc(v[3])};
-    vstore(reinterpret_cast<u16x4 *>(p), a, nt);
-}
-
-template <>
-__device__ inline void store4<StI16>(short *p, const float (&v)[4], bool nt) {
-    s16x4 a = {StI16::enc(v[0]), StI16::enc(v[1]), StI16::enc(v[2]), StI16::enc(v[3])};
-    vstore(reinterpret_cast<s16x4 *>(p), a, nt);
+template <class ST, bool RAW = false>
+__device__ inline void store4(typename ST::elem *p, const typename ST::comp (&v)[4], bool nt = false) {
+    using E = typename ST::elem;
+    typedef E e4 __attribute__((ext_vector_type(4)));
+    const e4 a = {enc_io<ST, RAW>(v[0]), enc_io<ST, RAW>(v[1]), enc_io<ST, RAW>(v[2]), enc_io<ST, RAW>(v[3])};
+    vstore(reinterpret_cast<e4 *>(p), a, nt);
 }
 
 // Two consecutive elements starting at an even index: one 16-, 8- or 4-byte access.
-template <class ST>
+template <class ST, bool RAW = false>
 __device__ inline void load2(const typename ST::elem *p, typename ST::comp (&v)[2], bool nt = false) {
     using E = typename ST::elem;
     typedef E e2 __attribute__((ext_vector_type(2)));
     const e2 a = vload(reinterpret_cast<const e2 *>(p), nt);
-    v[0] = ST::dec(a.x);
-    v[1] = ST::dec(a.y);
+    v[0] = dec_io<ST, RAW>(a.x);
+    v[1] = dec_io<ST, RAW>(a.y);
 }
-template <class ST>
+template <class ST, bool RAW = false>
 __device__ inline void store2(typename ST::elem *p, const typename ST::comp (&v)[2], bool nt = false) {
     using E = typename ST::elem;
     typedef E e2 __attribute__((ext_vector_type(2)));
-    const e2 a = {ST::enc(v[0]), ST::enc(v[1])};
+    const e2 a = {enc_io<ST, RAW>(v[0]), enc_io<ST, RAW>(v[1])};
     vstore(reinterpret_cast<e2 *>(p), a, nt);
 }
 

@@ -45,7 +45,8 @@ constexpr bool split_constants() {
     return sizeof(typename ST::elem) == 4;
 }
 
-// Collision constants in storage units, for compute type CT, per shell: the populations with
+// Collision constants in storage units (the raw domain of the storage type in the bulk step
+// kernels, ST::dec_raw / enc_raw), for compute type CT, per shell: the populations with
 // the same |c_i|^2 (0 rest, 1 axes, 2 edges, 3 corners) share f*_i, beta_i and hence every
 // constant below (the host checks this for each table).  With stored value s_i and decoded
 // population g_i = dec_i s_i:
@@ -197,11 +198,11 @@ __global__ __launch_bounds__(256) void step_generic(const typename ST::elem *__r
         const int xs = wrap_add(x, -VS::cx(i), nx);
         const int ys = wrap_add(y, -VS::cy(i), ny);
         const int zs = wrap_add(z, -VS::cz(i), nz);
-        s[i] = ST::dec(src[(size_t)i * N + ((size_t)zs * ny + ys) * nx + xs]);
+        s[i] = dec_io<ST, ST::has_raw>(src[(size_t)i * N + ((size_t)zs * ny + ys) * nx + xs]);
     }
     collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, s);
 #pragma unroll
-    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = enc_io<ST, ST::has_raw>(s[i]);
 }
 
 // ------------------------------------------------------------------ step: DPP variant
@@ -234,18 +235,18 @@ enum : unsigned { kTuneNtStore = 1u, kTuneNtLoad = 2u, kTunePersistent = 4u };
 template <class ST, int VEC>
 __device__ __forceinline__ void loadv(const typename ST::elem *p, typename ST::comp (&v)[VEC], bool nt) {
     if constexpr (VEC == 4) {
-        load4<ST>(p, v, nt);
+        load4<ST, ST::has_raw>(p, v, nt);
     } else {
         static_assert(VEC == 2, "VEC is 2 or 4");
-        load2<ST>(p, v, nt);
+        load2<ST, ST::has_raw>(p, v, nt);
     }
 }
 template <class ST, int VEC>
 __device__ __forceinline__ void storev(typename ST::elem *p, const typename ST::comp (&v)[VEC], bool nt) {
     if constexpr (VEC == 4) {
-        store4<ST>(p, v, nt);
+        store4<ST, ST::has_raw>(p, v, nt);
     } else {
-        store2<ST>(p, v, nt);
+        store2<ST, ST::has_raw>(p, v, nt);
     }
 }
 
@@ -279,13 +280,13 @@ __device__ __forceinline__ void step_chunk(const typename ST::elem *__restrict__
             for (int q = 0; q < VEC; ++q) s[i][q] = v[q];
         } else if (VS::cx(i) > 0) {
             CT prev = FULLROW ? dpp_move<kDppWaveRor1>(v[VEC - 1]) : dpp_move<kDppWaveShr1>(v[VEC - 1]);
-            if (!FULLROW && lane == 0) prev = ST::dec(rowp[x0 == 0 ? nx - 1 : x0 - 1]);
+            if (!FULLROW && lane == 0) prev = dec_io<ST, ST::has_raw>(rowp[x0 == 0 ? nx - 1 : x0 - 1]);
             s[i][0] = prev;
 #pragma unroll
             for (int q = 1; q < VEC; ++q) s[i][q] = v[q - 1];
         } else {
             CT next = FULLROW ? dpp_move<kDppWaveRol1>(v[0]) : dpp_move<kDppWaveShl1>(v[0]);
-            if (!FULLROW && last && active) next = ST::dec(rowp[x0 + VEC >= nx ? 0 : x0 + VEC]);
+            if (!FULLROW && last && active) next = dec_io<ST, ST::has_raw>(rowp[x0 + VEC >= nx ? 0 : x0 + VEC]);
 #pragma unroll
             for (int q = 0; q < VEC - 1; ++q) s[i][q] = v[q + 1];
             s[i][VEC - 1] = next;
@@ -361,11 +362,11 @@ __global__ __launch_bounds__(256) void step_lds(const typename ST::elem *__restr
         const int zs = wrap_add(z, -VS::cz(i), nz);
         const E *rowp = src + (size_t)i * N + ((size_t)zs * ny + ys) * (size_t)nx;
         if (VS::cx(i) == 0) {
-            s[i] = active ? ST::dec(rowp[x]) : (CT)0;
+            s[i] = active ? dec_io<ST, ST::has_raw>(rowp[x]) : (CT)0;
         } else {
-            if (active) stage[m][t + 1] = ST::dec(rowp[x]);
-            if (t == 0) stage[m][0] = ST::dec(rowp[x0 == 0 ? nx - 1 : x0 - 1]);
-            if (t == 1) stage[m][width + 1] = ST::dec(rowp[x0 + width >= nx ? 0 : x0 + width]);
+            if (active) stage[m][t + 1] = dec_io<ST, ST::has_raw>(rowp[x]);
+            if (t == 0) stage[m][0] = dec_io<ST, ST::has_raw>(rowp[x0 == 0 ? nx - 1 : x0 - 1]);
+            if (t == 1) stage[m][width + 1] = dec_io<ST, ST::has_raw>(rowp[x0 + width >= nx ? 0 : x0 + width]);
             ++m;
         }
     }
@@ -382,7 +383,7 @@ __global__ __launch_bounds__(256) void step_lds(const typename ST::elem *__restr
     collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, s);
     const size_t cell = ((size_t)z * ny + y) * (size_t)nx + x;
 #pragma unroll
-    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = enc_io<ST, ST::has_raw>(s[i]);
 }
 
 // ------------------------------------------------------------------ initial state

@@ -217,7 +217,17 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
     __shared__ FwdTiles tiles[4];
     __shared__ float pred[4][16][G::NOUT];
     __shared__ NetFrags<VS> F;
-    stage_forward_weights<VS>(P, F);
+    // per face f and canonical population j: the face population, its decode factor and 1/f*
+    __shared__ int perm_s[6][VS::Q];
+    __shared__ float dec_s[6][VS::Q], invf_s[6][VS::Q];
+    for (int t = threadIdx.x; t < 6 * VS::Q; t += 256) {
+        const int f = t / VS::Q, j = t - f * VS::Q;
+        const int i = f < ft.nfaces ? ft.perm[f][j] : 0;
+        perm_s[f][j] = i;
+        dec_s[f][j] = (float)fk.dec[i];
+        invf_s[f][j] = (float)(1.0 / fk.f[i]);
+    }
+    stage_forward_weights<VS>(P, F);  // ends with a block barrier
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     FwdTiles &T = tiles[wid];
     const long long count = ft.node_off[ft.nfaces];
@@ -230,6 +240,8 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
         const int r = lane & 15;
         const int f = node_cell(ft, base + (r < nrows ? r : 0), p);
         const int a = f >> 1, step = (f & 1) ? -1 : 1;
+        const size_t cell0 = ((size_t)p[2] * ft.n[1] + p[1]) * ft.n[0] + p[0];
+        const long long stride_a = a == 0 ? 1 : (a == 1 ? (long long)ft.n[0] : (long long)ft.n[0] * ft.n[1]);
         // energy weights 1/f* of the node's populations leaving through the face (first cell of
         // the strip, canonical c_x = -1)
         float mx = 0.0f, e_out = 0.0f;
@@ -237,14 +249,10 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
             T, nrows, lane,
             [&](int, int v) {
                 const int m = v / VS::Q, j = v - m * VS::Q;
-                int q[3] = {p[0], p[1], p[2]};
-                q[a] += m * step;
-                const size_t cell = ((size_t)q[2] * ft.n[1] + q[1]) * ft.n[0] + q[0];
-                const int i = ft.perm[f][j];
-                return (float)(fk.dec[i] * (double)ST::dec(src[(size_t)i * N + cell]));
+                const size_t cell = (size_t)((long long)cell0 + (long long)(m * step) * stride_a);
+                return dec_s[f][j] * ST::dec(src[(size_t)perm_s[f][j] * N + cell]);
             },
-            [&](int v) { return v < VS::Q && VS::cx(v) == -1 ? (float)(1.0 / fk.f[ft.perm[f][v]]) : 0.0f; }, &mx,
-            &e_out);
+            [&](int v) { return v < VS::Q && VS::cx(v) == -1 ? invf_s[f][v] : 0.0f; }, &mx, &e_out);
         const floatx4 y = net_forward_tile_staged<VS>(F, T, lane);
         const int col = lane & 15;
 #pragma unroll
@@ -259,7 +267,7 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
 #pragma unroll
             for (int k = 0; k < G::NOUT; ++k) {
                 const float v = pred[wid][lane][k] / mx;
-                e_in += v * v * (float)(1.0 / fk.f[ft.perm[f][entering_index<VS>(k)]]);
+                e_in += v * v * invf_s[f][entering_index<VS>(k)];
             }
             int nf = 0;
             for (int b = 0; b < VS::D; ++b) nf += (p[b] == 0) + (p[b] == ft.n[b] - 1);

@@ -278,23 +278,38 @@ def reflection(lattice, closure, fields, L=512, E=1536, steps=1024, every=8, par
     return err_max / ref_max if ref_max > 0 else float("nan")
 
 
-def time_solver(sim, steps=200):
+def time_solver(sim, steps=200, graph=False):
+    """ms per step.  graph=True replays a captured two-step graph (no host launch cost per
+    kernel); the replays advance the buffers but not the handle's step counter."""
     import torch
     sim.step(10)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    if not graph:
+        e0.record()
+        sim.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        lbm.lbm_lee_step(sim.h, 2, torch.cuda.current_stream().cuda_stream)
+    g.replay()
+    torch.cuda.synchronize()
+    reps = max(1, steps // 2)
     e0.record()
-    sim.step(steps)
+    for _ in range(reps):
+        g.replay()
     e1.record()
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps
+    return e0.elapsed_time(e1) / (2 * reps)
 
 
-def time_per_step(lattice, shape, bc="periodic", params=None, storage="f32", steps=200, **kw):
-    sim = lbm.Solver(lattice, storage, shape, None, None, None, bc=bc, **kw)
+def time_per_step(lattice, shape, bc="periodic", params=None, storage="f32", steps=200, graph=False, tune=0, **kw):
+    sim = lbm.Solver(lattice, storage, shape, None, None, None, bc=bc, tune=tune, **kw)
     if bc == "mlp":
         sim.set_closure(params)
-    ms = time_solver(sim, steps)
+    ms = time_solver(sim, steps, graph)
     sim.close()
     return ms
 
@@ -365,17 +380,26 @@ def main(argv=None):
                                     sponge_width=args.sponge_width, sponge_sigma=args.sponge_sigma, ext=ext,
                                     slices=args.slices))
         log(f"evaluate: seed {k + 1}/{args.seeds}: " + ", ".join(f"{c} {Rs[c][-1]:.4f}" for c in closures))
-    times = {"extended_periodic": time_solver(ext, 50 if D == 3 else 200)}
+    nrep = 50 if D == 3 else 200
+    times = {"extended_periodic": time_solver(ext, nrep)}
+    times_graph = {"extended_periodic": time_solver(ext, nrep, graph=True)}
     ext.close()
     del ext
     for c in closures:
         kw = dict(sponge_width=args.sponge_width, sponge_sigma=args.sponge_sigma) if c == "sponge" else {}
         nb = args.L + (2 * args.sponge_width if c == "sponge" else 0)
         times[c] = time_per_step(args.lattice, (nb,) * D, bc=c, params=P, storage=args.storage, **kw)
+        times_graph[c] = time_per_step(args.lattice, (nb,) * D, bc=c, params=P, storage=args.storage, graph=True,
+                                       **kw)
+        if c == "mlp":
+            times_graph["mlp_closure_stream"] = time_per_step(args.lattice, (nb,) * D, bc=c, params=P,
+                                                              storage=args.storage, graph=True,
+                                                              tune=lbm.TUNE["closure_stream"])
     print(json.dumps(dict(mode="evaluate", lattice=args.lattice, init=args.init, L=args.L, E=args.E,
                           steps=args.steps, storage=args.storage, ext_storage=args.ext_storage, seeds=args.seeds,
                           slices=args.slices, R_mean={c: float(np.mean(v)) for c, v in Rs.items()},
-                          R_max={c: float(np.max(v)) for c, v in Rs.items()}, ms_per_step=times)))
+                          R_max={c: float(np.max(v)) for c, v in Rs.items()}, ms_per_step=times,
+                          ms_per_step_graph=times_graph)))
 
 
 if __name__ == "__main__":
