@@ -50,8 +50,9 @@ def parse():
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sources of the step kernels (the device code the counters measured)."""
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "codec.hpp", "velsets.hpp", "api.hip"):
+    for f in ("kernels.hpp", "codec.hpp", "velsets.hpp"):
         with open(os.path.join(ROOT, "paper_1601_08103_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -243,8 +243,9 @@ int32_t lbm_lee_resolved_variant(lbm_lee_handle h);
 /* Free the handle (host memory only; device buffers stay with the caller). NULL is a no-op. */
 void lbm_lee_destroy(lbm_lee_handle h);
 
-/* Bytes of the caller-owned ghost buffer an LBM_BC_MLP handle needs: one FP32 value per
- * entering population per face node.  0 for other boundaries or a bad desc. */
+/* Bytes of the caller-owned ghost buffer an LBM_BC_MLP handle needs: per face node one FP32
+ * value per entering population, then two history strips (3 Q FP32 values each, written and
+ * read on alternate steps).  0 for other boundaries or a bad desc. */
 size_t lbm_lee_ghost_bytes(const lbm_lee_desc *desc);
 
 /* Attach the closure network (device FP32 parameters, layout of lbm_nrbc_dims) and the ghost
@@ -258,17 +259,21 @@ size_t lbm_lee_ghost_bytes(const lbm_lee_desc *desc);
 lbm_status lbm_lee_set_closure(lbm_lee_handle h, const float *params, void *ghost, size_t ghost_bytes);
 
 /*
- * Learned non-reflecting closure network (not in the paper).  Input: the strip of
+ * Learned non-reflecting closure network (not in the paper).  Input: the strips of
  * post-collision populations at a face node, 3 cells deep along the inward normal, in the
- * canonical face frame (outward normal -x), m-major: x[m * Q + j]; output: the populations
- * entering through the face (canonical c_x = +1, in canonical order).  Network:
+ * canonical face frame (outward normal -x), of the current step and of the step before:
+ * x[h * 3Q + m * Q + j], h = 0 now, h = 1 one step earlier (n_in = 6 Q); output: the populations
+ * entering through the face (canonical c_x = +1, in canonical order).  In a step of an
+ * LBM_BC_MLP box the earlier strip comes from the history the previous step stored in the ghost
+ * buffer; on the first step after the state was set (init, reinit, import) or the closure
+ * attached, the current strip stands in for it.  Network:
  *   s = rms(x), z = x / s, h1 = relu(z W1 + b1), h2 = relu(h1 W2 + b2), y = h2 W3 + b3, out = s y,
  * with rms computed as m sqrt(mean((x/m)^2)), m = max |x|; an all-zero strip predicts 0.
  * FP32 parameters, row-major, concatenated: W1[n_in][64], b1[64], W2[64][64], b2[64],
  * W3[64][n_out], b3[n_out].  Every product runs on matrix cores with bfloat16 inputs (round to
  * nearest even) and FP32 accumulation.
  */
-/* dims = { n_in = 3 Q, n_out, hidden = 64, n_params }. */
+/* dims = { n_in = 6 Q, n_out, hidden = 64, n_params }. */
 lbm_status lbm_nrbc_dims(int32_t lattice, int32_t dims[4]);
 
 /* Number of face nodes of a box (the id range of lbm_nrbc_gather): faces in the order
@@ -300,17 +305,21 @@ lbm_status lbm_nrbc_adam(int64_t n, float *params, const float *grad, float *m, 
 /*
  * Training pairs from a larger (e.g. periodic, three times wider) run `outer` whose cell
  * origin + x corresponds to cell x of the box `inner` (origin >= 1 and origin + n + 1 <= outer n
- * on every axis): for each face node id of the inner box (device int64 ids), the strip at the
- * node (strips [count][n_in]) and the true entering populations, i.e. the outer state at the
- * node's outside neighbour (targets [count][n_out]), physical FP32 values.
+ * on every axis): for each face node id of the inner box (device int64 ids), the strip of the
+ * current state at the node (one time level, 3 Q values, written at strips + t * strip_stride
+ * floats, strip_stride >= 3 Q) and the true entering populations, i.e. the outer state at the
+ * node's outside neighbour (targets [count][n_out]), physical FP32 values.  A network input row
+ * [strip(t), strip(t-1)] (n_in = 6 Q) takes two calls with strip_stride = n_in: one on the
+ * state before the step (strips + 3 Q, targets NULL), one after it (strips, with targets).
  * targets may be NULL: strips only, and then origin >= 0, origin + n <= outer n suffice, so
  * `outer` may be the open box itself (origin 0, inner = its own desc): the strips its closure
  * sees, for training on the states the closed loop actually visits.  Ids outside
  * [0, lbm_nrbc_face_nodes(inner)) give zero rows.  Errors: LBM_E_INVALID for NULL arguments,
- * count < 0, differing lattices or a misplaced inner box.
+ * count < 0, strip_stride < 3 Q, differing lattices or a misplaced inner box.
  */
 lbm_status lbm_nrbc_gather(lbm_lee_handle outer, const int64_t origin[3], const lbm_lee_desc *inner,
-                           const int64_t *node_ids, int64_t count, float *strips, float *targets, void *stream);
+                           const int64_t *node_ids, int64_t count, float *strips, int64_t strip_stride, float *targets,
+                           void *stream);
 
 /*
  * Compare a field a of a box (n_a[3] cells, device FP64) with the field b of a larger box

@@ -39,9 +39,10 @@ and the open box's energy cannot grow, whatever the network predicts.
 A signed axis permutation M maps the face's outward normal to -x (the canonical face), so
 one network serves every face:  (a,0): identity; (a,1): negate axis a; then axis a is
 swapped with x.  In the canonical frame the populations that enter through the face are
-those with c'_x = +1.  The network input is the strip g*(p + m n_in), m = 0, 1, 2 (n_in the
-inward normal), listed m-major with populations in canonical order; its output is the k
-entering populations in canonical order.
+those with c'_x = +1.  A strip is g*(p + m n_in), m = 0, 1, 2 (n_in the inward normal), listed
+m-major with populations in canonical order; the network input is the strip of the current state
+followed by the strip of the state one step earlier (the current one again on the first step);
+its output is the k entering populations in canonical order.
 """
 from __future__ import annotations
 
@@ -138,9 +139,11 @@ def energy_limit(lat: Lattice, x, y, nfaces: int) -> np.ndarray:
 
 
 def ghost_values(lat: Lattice, g, closure: str, params: dict | None = None, quantize: bool = False,
-                 limit: bool = True):
+                 limit: bool = True, g_prev=None):
     """Padded populations (Q, n+2 per axis) whose one-cell shell holds the closure's ghosts.
-    limit=False drops the energy limit of the network closure (a test device)."""
+    The network sees [strip of g, strip of g_prev] (g_prev: the state one step earlier; None on
+    the first step, when the current strip stands in for it).  limit=False drops the energy limit
+    of the network closure (a test device)."""
     shape = g.shape[1:]
     D = lat.D
     pad = np.zeros((lat.Q,) + tuple(n + 2 for n in shape))
@@ -171,7 +174,8 @@ def ghost_values(lat: Lattice, g, closure: str, params: dict | None = None, quan
                 key = (a, side, p)
                 if key not in cache:
                     x = strip(lat, g, a, side, p)
-                    y = mlp_ref.predict(params, x[None, :], quantize)[0]
+                    xp = strip(lat, g_prev, a, side, p) if g_prev is not None else x
+                    y = mlp_ref.predict(params, np.concatenate([x, xp])[None, :], quantize)[0]
                     cache[key] = energy_limit(lat, x, y, node_face_count(p, shape, D)) if limit else y
                 perm = canonical_perm(lat, a, side)
                 for r, j in enumerate(jin):
@@ -198,11 +202,12 @@ def sponge_factor(shape, D, width: int, sigma_max: float) -> np.ndarray:
 
 def step_open(lat: Lattice, g, closure: str, tau: float = 0.5, params: dict | None = None,
               sponge_width: int = 0, sponge_sigma: float = 0.0, quantize: bool = False,
-              limit: bool = True) -> np.ndarray:
-    """One step of the open-box scheme on the post-collision state g (Q, *shape)."""
+              limit: bool = True, g_prev=None) -> np.ndarray:
+    """One step of the open-box scheme on the post-collision state g (Q, *shape); g_prev is the
+    state one step earlier (the network closure's second time level)."""
     shape = g.shape[1:]
     D = lat.D
-    pad = ghost_values(lat, g, closure, params, quantize, limit)
+    pad = ghost_values(lat, g, closure, params, quantize, limit, g_prev)
     pulled = np.empty_like(g)
     for i in range(lat.Q):
         sl = []
@@ -220,6 +225,7 @@ def step_open(lat: Lattice, g, closure: str, tau: float = 0.5, params: dict | No
 
 def run_open(lat: Lattice, g0, nsteps: int, closure: str, **kw) -> np.ndarray:
     g = np.array(g0, dtype=np.float64)
+    prev = None
     for _ in range(nsteps):
-        g = step_open(lat, g, closure, **kw)
+        g, prev = step_open(lat, g, closure, g_prev=prev, **kw), g
     return g

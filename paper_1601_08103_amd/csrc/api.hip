@@ -38,6 +38,9 @@ struct lbm_lee {
     // the caller's stream.  Created by lbm_lee_set_closure, released by lbm_lee_destroy.
     hipStream_t aux = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    // LBM_BC_MLP: the history buffer holds the strips of the state before the current one;
+    // false after the state was set (init, reinit, import) or the closure attached
+    bool hist_valid = false;
     ~lbm_lee() {
         if (join) (void)hipEventDestroy(join);
         if (fork) (void)hipEventDestroy(fork);
@@ -306,8 +309,10 @@ int net_outputs(const LatticeTable &t) {
     return k;
 }
 
+int64_t net_inputs(const LatticeTable &t) { return (int64_t)kHistory * 3 * t.Q; }
+
 int64_t net_params(const LatticeTable &t) {
-    const int64_t nin = 3 * t.Q, nout = net_outputs(t);
+    const int64_t nin = net_inputs(t), nout = net_outputs(t);
     return nin * kHidden + kHidden + kHidden * kHidden + kHidden + kHidden * nout + nout;
 }
 
@@ -511,6 +516,7 @@ lbm_status lbm_lee_reinit(lbm_lee_handle h, const double *rho, const double *u, 
     if (!rho || !u || !theta) return fail(LBM_E_INVALID, "initial fields must not be NULL");
     h->cur = 0;
     h->steps = 0;
+    h->hist_valid = false;
     lbm_status s = launch_init(h, rho, u, theta, static_cast<hipStream_t>(stream));
     return s == LBM_OK ? ok() : s;
 }
@@ -533,6 +539,7 @@ lbm_status lbm_lee_reinit_region(lbm_lee_handle h, const int64_t origin[3], cons
     if (s != LBM_OK) return s;
     h->cur = 0;
     h->steps = 0;
+    h->hist_valid = false;
     s = launch_init_region(h, origin, n_sub, rho, u, theta, static_cast<hipStream_t>(stream));
     return s == LBM_OK ? ok() : s;
 }
@@ -603,6 +610,8 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
         FaceTab<VS::Q> ft;
         FieldCoef<VS::Q> fk;
         unsigned shell_x = 1, ghost_blocks = 1, sponge_x = 1;
+        long long nodes = 0;
+        const long long nstrip = 3 * VS::Q;
         if (bc != LBM_BC_PERIODIC) {
             ft = face_table<VS>(h->tab, h->desc.n);
             fk = field_coef<VS::Q>(h);
@@ -624,7 +633,8 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
                 }
                 sponge_x = (unsigned)((big + 255) / 256);
             }
-            const long long tiles = (ft.node_off[ft.nfaces] + 15) / 16;
+            nodes = ft.node_off[ft.nfaces];
+            const long long tiles = (nodes + 15) / 16;
             ghost_blocks = (unsigned)std::min<long long>((tiles + 3) / 4, 4096);
         }
         auto run = [&](auto skip, auto half) -> lbm_status {
@@ -633,13 +643,19 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
             for (int64_t t = 0; t < nsteps; ++t) {
                 const E *src = static_cast<const E *>(h->buf[h->cur]);
                 E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);
-                if (bc == LBM_BC_MLP && fork) {  // fork: the network on the helper stream
-                    LBM_HIP(hipEventRecord(h->fork, st));
-                    LBM_HIP(hipStreamWaitEvent(h->aux, h->fork, 0));
-                    ghost_mlp_kernel<VS, ST><<<ghost_blocks, 256, 0, h->aux>>>(src, h->N, h->net, h->ghost, ft, fk);
-                    LBM_HIP(hipEventRecord(h->join, h->aux));
-                } else if (bc == LBM_BC_MLP) {
-                    ghost_mlp_kernel<VS, ST><<<ghost_blocks, 256, 0, st>>>(src, h->N, h->net, h->ghost, ft, fk);
+                if (bc == LBM_BC_MLP) {
+                    // history pair after the ghost values, selected by the state buffer's parity
+                    float *hist = h->ghost + nodes * (long long)net_outputs(h->tab);
+                    const float *hin = h->hist_valid ? hist + (long long)h->cur * nodes * nstrip : nullptr;
+                    float *hout = hist + (long long)(h->cur ^ 1) * nodes * nstrip;
+                    if (fork) {  // fork: the network on the helper stream
+                        LBM_HIP(hipEventRecord(h->fork, st));
+                        LBM_HIP(hipStreamWaitEvent(h->aux, h->fork, 0));
+                    }
+                    ghost_mlp_kernel<VS, ST><<<ghost_blocks, 256, 0, fork ? h->aux : st>>>(src, h->N, h->net, h->ghost,
+                                                                                           hin, hout, ft, fk);
+                    if (fork) LBM_HIP(hipEventRecord(h->join, h->aux));
+                    h->hist_valid = true;
                 }
                 if (variant == LBM_VARIANT_GENERIC) {
                     step_generic<VS, ST, SK, HF><<<blocks_for(h->N), 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, k);
@@ -785,6 +801,7 @@ lbm_status lbm_lee_import_f64(lbm_lee_handle h, const double *g, int64_t steps_d
     });
     if (s != LBM_OK) return s;
     h->steps = steps_done;
+    h->hist_valid = false;
     return ok();
 }
 
@@ -804,7 +821,8 @@ void lbm_lee_destroy(lbm_lee_handle h) { delete h; }
 size_t lbm_lee_ghost_bytes(const lbm_lee_desc *d) {
     LatticeTable t;
     if (check_desc(d, &t) != LBM_OK || d->bc != LBM_BC_MLP) return 0;
-    return (size_t)face_node_count(t, d->n) * (size_t)net_outputs(t) * sizeof(float);
+    // ghost values, then two history buffers of one strip per node (read one, write the other)
+    return (size_t)face_node_count(t, d->n) * (size_t)(net_outputs(t) + 2 * 3 * t.Q) * sizeof(float);
 }
 
 lbm_status lbm_lee_set_closure(lbm_lee_handle h, const float *params, void *ghost, size_t ghost_bytes) {
@@ -831,6 +849,7 @@ lbm_status lbm_lee_set_closure(lbm_lee_handle h, const float *params, void *ghos
     }
     h->net = params;
     h->ghost = static_cast<float *>(ghost);
+    h->hist_valid = false;
     return ok();
 }
 
@@ -838,7 +857,7 @@ lbm_status lbm_nrbc_dims(int32_t lattice, int32_t dims[4]) {
     LatticeTable t;
     if (!dims) return fail(LBM_E_INVALID, "dims is NULL");
     if (!build_lattice(lattice, &t)) return fail(LBM_E_INVALID, "unknown lattice id %d", lattice);
-    dims[0] = 3 * t.Q;
+    dims[0] = (int32_t)net_inputs(t);
     dims[1] = net_outputs(t);
     dims[2] = kHidden;
     dims[3] = (int32_t)net_params(t);
@@ -914,11 +933,13 @@ lbm_status lbm_nrbc_adam(int64_t n, float *params, const float *grad, float *m, 
 }
 
 lbm_status lbm_nrbc_gather(lbm_lee_handle outer, const int64_t origin[3], const lbm_lee_desc *inner,
-                           const int64_t *node_ids, int64_t count, float *strips, float *targets, void *stream) {
+                           const int64_t *node_ids, int64_t count, float *strips, int64_t strip_stride, float *targets,
+                           void *stream) {
     if (!outer || !origin || !inner || !node_ids || !strips || count < 0) return fail(LBM_E_INVALID, "bad arguments");
     LatticeTable t;
     lbm_status s = check_desc(inner, &t);
     if (s != LBM_OK) return s;
+    if (strip_stride < 3 * t.Q) return fail(LBM_E_INVALID, "strip_stride must be >= 3 Q = %d", 3 * t.Q);
     if (inner->lattice != outer->desc.lattice) return fail(LBM_E_INVALID, "inner and outer lattices differ");
     const int spare = targets ? 1 : 0;  // targets read one cell beyond the inner box
     for (int a = 0; a < t.D; ++a)
@@ -935,8 +956,8 @@ lbm_status lbm_nrbc_gather(lbm_lee_handle outer, const int64_t origin[3], const 
         const auto *src = static_cast<const typename ST::elem *>(outer->buf[outer->cur]);
         gather_pairs_kernel<VS, ST><<<blocks_for((size_t)count), 256, 0, st>>>(
             src, outer->N, outer->nx, outer->ny, (int)origin[0], (int)(t.D > 1 ? origin[1] : 0),
-            (int)(t.D > 2 ? origin[2] : 0), reinterpret_cast<const long long *>(node_ids), count, strips, targets, ft,
-            fk);
+            (int)(t.D > 2 ? origin[2] : 0), reinterpret_cast<const long long *>(node_ids), count, strips,
+            (long long)strip_stride, targets, ft, fk);
         return launch_check();
     });
     return s == LBM_OK ? ok() : s;

@@ -65,10 +65,15 @@ __host__ __device__ constexpr int entering_index(int r) {
     return -1;
 }
 
+// Time levels of the strip in the network input: the current step's and the previous step's.
+constexpr int kHistory = 2;
+
 template <class VS>
 struct NetGeom {
-    static constexpr int NIN = 3 * VS::Q;
+    static constexpr int NSTRIP = 3 * VS::Q;         // one time level: 3 cells x Q populations
+    static constexpr int NIN = kHistory * NSTRIP;    // input: [strip(t), strip(t-1)]
     static constexpr int NIN_PAD = (NIN + 15) / 16 * 16;
+    static constexpr int ZW = NIN_PAD > kHidden ? NIN_PAD : kHidden;  // width of the input tile
     static constexpr int NOUT = entering_count<VS>();
     static constexpr int OFF_W1 = 0;
     static constexpr int OFF_B1 = OFF_W1 + NIN * kHidden;
@@ -77,13 +82,14 @@ struct NetGeom {
     static constexpr int OFF_W3 = OFF_B2 + kHidden;
     static constexpr int OFF_B3 = OFF_W3 + kHidden * NOUT;
     static constexpr int NPARAM = OFF_B3 + NOUT;
-    static_assert(NIN_PAD <= 64, "strip wider than the LDS tile");
+    static_assert(NIN_PAD <= 128, "strip wider than the input tile");
     static_assert(NOUT <= 16, "too many entering populations for one output tile");
 };
 
-// Per-wave LDS tiles (bfloat16 bits).
+// Per-wave LDS tiles (bfloat16 bits); ZW = width of the input tile.
+template <int ZW>
 struct WaveTiles {
-    unsigned short z[16][64];
+    unsigned short z[16][ZW];
     unsigned short h1[16][64];
     unsigned short h2[16][64];
     unsigned short dy[16][16];
@@ -92,14 +98,16 @@ struct WaveTiles {
 };
 
 // Per-wave LDS tiles of the forward pass alone (inference).
+template <int ZW>
 struct FwdTiles {
-    unsigned short z[16][64];
+    unsigned short z[16][ZW];
     unsigned short h1[16][64];
     unsigned short h2[16][64];
 };
 
-// A operand from an LDS tile X[16][64] (rows = samples): columns kk*16 + 4 (l/16) + e.
-__device__ __forceinline__ bf16x4 a_rows(const unsigned short (*X)[64], int kk, int lane) {
+// A operand from an LDS tile X[16][LD] (rows = samples): columns kk*16 + 4 (l/16) + e.
+template <int LD>
+__device__ __forceinline__ bf16x4 a_rows(const unsigned short (*X)[LD], int kk, int lane) {
     const int i = lane & 15, k0 = kk * 16 + 4 * (lane >> 4);
     bf16x4 a;
     a.x = (short)X[i][k0]; a.y = (short)X[i][k0 + 1]; a.z = (short)X[i][k0 + 2]; a.w = (short)X[i][k0 + 3];
@@ -148,8 +156,8 @@ __device__ __forceinline__ bf16x4 b_weight_t(const float *__restrict__ W, int ro
 }
 
 // Forward pass of one tile: z (already in LDS) -> h1, h2 (LDS) and y (C layout, 16 x 16).
-template <class VS>
-__device__ floatx4 net_forward_tile(const float *__restrict__ P, WaveTiles &T, int lane) {
+template <class VS, class TT>
+__device__ floatx4 net_forward_tile(const float *__restrict__ P, TT &T, int lane) {
     using G = NetGeom<VS>;
     const int row0 = 4 * (lane >> 4), col = lane & 15;
 #pragma unroll
@@ -334,11 +342,11 @@ template <class VS>
 __global__ __launch_bounds__(256) void nrbc_forward_kernel(const float *__restrict__ P, const float *__restrict__ strips,
                                                            long long count, float *__restrict__ out) {
     using G = NetGeom<VS>;
-    __shared__ FwdTiles tiles[4];
+    __shared__ FwdTiles<G::ZW> tiles[4];
     __shared__ NetFrags<VS> F;
     stage_forward_weights<VS>(P, F);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    FwdTiles &T = tiles[wid];
+    FwdTiles<G::ZW> &T = tiles[wid];
     const long long ntiles = (count + 15) / 16;
     for (long long tile = (long long)blockIdx.x * 4 + wid; tile < ntiles; tile += (long long)gridDim.x * 4) {
         const long long base = tile * 16;
@@ -376,9 +384,9 @@ __global__ __launch_bounds__(256) void nrbc_grad_kernel(const float *__restrict_
                                                         float *__restrict__ ws) {
     using G = NetGeom<VS>;
     constexpr int MT1 = G::NIN_PAD / 16;
-    __shared__ WaveTiles tiles[4];
+    __shared__ WaveTiles<G::ZW> tiles[4];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    WaveTiles &T = tiles[wid];
+    WaveTiles<G::ZW> &T = tiles[wid];
     const int row0 = 4 * (lane >> 4), col = lane & 15;
     const float inv_n = (float)(1.0 / ((double)(*nvalid ? *nvalid : 1ull) * G::NOUT));
     bf16x4 ones;
@@ -467,7 +475,7 @@ __global__ __launch_bounds__(256) void nrbc_grad_kernel(const float *__restrict_
         for (int nt = 0; nt < 4; ++nt) {
             const bf16x4 bda = b_rows<64>(T.da1, nt, lane);
 #pragma unroll
-            for (int mt = 0; mt < MT1; ++mt) g1[mt][nt] = mfma16(a_cols<64>(T.z, mt, lane), bda, g1[mt][nt]);
+            for (int mt = 0; mt < MT1; ++mt) g1[mt][nt] = mfma16(a_cols<G::ZW>(T.z, mt, lane), bda, g1[mt][nt]);
             gb1[nt] = mfma16(ones, bda, gb1[nt]);
         }
         wave_lds_sync();

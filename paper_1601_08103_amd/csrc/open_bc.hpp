@@ -201,8 +201,8 @@ __global__ __launch_bounds__(256) void sponge_kernel(typename ST::elem *__restri
 }
 
 // ------------------------------------------------------------------ network ghosts
-// Every face node: strip (3 cells x Q populations, canonical order, physical units) ->
-// network -> the K entering populations (physical units) into ghost[node * K + r], limited in
+// Every face node: [strip(t), strip(t-1)] (each 3 cells x Q populations, canonical order, physical
+// units) -> network -> the K entering populations (physical units) into ghost[node * K + r], limited in
 // energy: with E_in = sum_r y_r^2 / f*, E_out = sum over the node's populations leaving through
 // the face (canonical c_x = -1) of g^2 / f*, and n the number of faces the node lies on, y is
 // scaled by sqrt(B / E_in) when E_in > B = E_out / (2^n - 1).  Each ghost value pulled into the
@@ -212,9 +212,11 @@ __global__ __launch_bounds__(256) void sponge_kernel(typename ST::elem *__restri
 template <class VS, class ST>
 __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem *__restrict__ src, size_t N,
                                                         const float *__restrict__ P, float *__restrict__ ghost,
+                                                        const float *__restrict__ hist_in, float *__restrict__ hist_out,
                                                         FaceTab<VS::Q> ft, FieldCoef<VS::Q> fk) {
     using G = NetGeom<VS>;
-    __shared__ FwdTiles tiles[4];
+    constexpr int NS = G::NSTRIP;
+    __shared__ FwdTiles<G::ZW> tiles[4];
     __shared__ float pred[4][16][G::NOUT];
     __shared__ NetFrags<VS> F;
     // per face f and canonical population j: the face population, its decode factor and 1/f*
@@ -229,7 +231,7 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
     }
     stage_forward_weights<VS>(P, F);  // ends with a block barrier
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    FwdTiles &T = tiles[wid];
+    FwdTiles<G::ZW> &T = tiles[wid];
     const long long count = ft.node_off[ft.nfaces];
     const long long ntiles = (count + 15) / 16;
     for (long long tile = (long long)blockIdx.x * 4 + wid; tile < ntiles; tile += (long long)gridDim.x * 4) {
@@ -238,21 +240,26 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
         // the node of this lane's row
         int p[3];
         const int r = lane & 15;
-        const int f = node_cell(ft, base + (r < nrows ? r : 0), p);
+        const long long node = base + (r < nrows ? r : 0);
+        const int f = node_cell(ft, node, p);
         const int a = f >> 1, step = (f & 1) ? -1 : 1;
         const size_t cell0 = ((size_t)p[2] * ft.n[1] + p[1]) * ft.n[0] + p[0];
         const long long stride_a = a == 0 ? 1 : (a == 1 ? (long long)ft.n[0] : (long long)ft.n[0] * ft.n[1]);
-        // energy weights 1/f* of the node's populations leaving through the face (first cell of
-        // the strip, canonical c_x = -1)
+        auto strip_now = [&](int v) {  // value v of this node's current strip
+            const int m = v / VS::Q, j = v - m * VS::Q;
+            const size_t cell = (size_t)((long long)cell0 + (long long)(m * step) * stride_a);
+            return dec_s[f][j] * (float)ST::dec(src[(size_t)perm_s[f][j] * N + cell]);
+        };
+        // input [strip(t), strip(t-1)]; the previous strip comes from the history buffer (the
+        // current one again on the first step after the state was set)
         float mx = 0.0f, e_out = 0.0f;
         const float s = load_normalised_tile<VS>(
             T, nrows, lane,
-            [&](int, int v) {
-                const int m = v / VS::Q, j = v - m * VS::Q;
-                const size_t cell = (size_t)((long long)cell0 + (long long)(m * step) * stride_a);
-                return dec_s[f][j] * ST::dec(src[(size_t)perm_s[f][j] * N + cell]);
-            },
+            [&](int, int v) { return v < NS ? strip_now(v) : (hist_in ? hist_in[node * NS + (v - NS)] : strip_now(v - NS)); },
             [&](int v) { return v < VS::Q && VS::cx(v) == -1 ? invf_s[f][v] : 0.0f; }, &mx, &e_out);
+        // this step's strip becomes the next step's history (the other buffer of the pair)
+        if (r < nrows)
+            for (int v = lane >> 4; v < NS; v += 4) hist_out[node * NS + v] = strip_now(v);
         const floatx4 y = net_forward_tile_staged<VS>(F, T, lane);
         const int col = lane & 15;
 #pragma unroll
@@ -282,21 +289,23 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
 
 // ------------------------------------------------------------------ training pairs
 // For inner-box face nodes (ids in the inner box's numbering), read the state of a larger
-// run whose cell origin + x is inner cell x: the strip at the node (inputs) and the
-// entering populations at the node's outside neighbour (targets, skipped when NULL),
-// physical units.  Ids outside the face-node range give zeros.
+// run whose cell origin + x is inner cell x: the strip at the node (one time level, NSTRIP
+// values at strips + t * stride) and the entering populations at the node's outside neighbour
+// (targets, skipped when NULL), physical units.  Ids outside the face-node range give zeros.
 template <class VS, class ST>
 __global__ __launch_bounds__(256) void gather_pairs_kernel(const typename ST::elem *__restrict__ src, size_t N,
                                                            int onx, int ony, int ox, int oy, int oz,
                                                            const long long *__restrict__ ids, long long count,
-                                                           float *__restrict__ strips, float *__restrict__ targets,
-                                                           FaceTab<VS::Q> ft, FieldCoef<VS::Q> fk) {
+                                                           float *__restrict__ strips, long long stride,
+                                                           float *__restrict__ targets, FaceTab<VS::Q> ft,
+                                                           FieldCoef<VS::Q> fk) {
     using G = NetGeom<VS>;
     const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
     if (t >= count) return;
+    float *row = strips + t * stride;
     const long long id = ids[t];
     if (id < 0 || id >= ft.node_off[ft.nfaces]) {  // not a face node: zeros
-        for (int v = 0; v < G::NIN; ++v) strips[t * G::NIN + v] = 0.0f;
+        for (int v = 0; v < G::NSTRIP; ++v) row[v] = 0.0f;
         if (targets)
             for (int r = 0; r < G::NOUT; ++r) targets[t * G::NOUT + r] = 0.0f;
         return;
@@ -314,7 +323,7 @@ __global__ __launch_bounds__(256) void gather_pairs_kernel(const typename ST::el
         const size_t cell = outer_cell(q);
         for (int j = 0; j < VS::Q; ++j) {
             const int i = ft.perm[f][j];
-            strips[t * G::NIN + m * VS::Q + j] = (float)(fk.dec[i] * (double)ST::dec(src[(size_t)i * N + cell]));
+            row[m * VS::Q + j] = (float)fk.dec[i] * (float)ST::dec(src[(size_t)i * N + cell]);
         }
     }
     if (!targets) return;

@@ -82,8 +82,8 @@ SIGNATURES = {
                                             ctypes.c_size_t, _VP]),
     "lbm_nrbc_adam": (ctypes.c_int32, [ctypes.c_int64, _VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_float,
                                        ctypes.c_float, ctypes.c_float, ctypes.c_float, _VP]),
-    "lbm_nrbc_gather": (ctypes.c_int32, [_VP, ctypes.POINTER(ctypes.c_int64), _DESC_P, _VP, ctypes.c_int64, _VP, _VP,
-                                         _VP]),
+    "lbm_nrbc_gather": (ctypes.c_int32, [_VP, ctypes.POINTER(ctypes.c_int64), _DESC_P, _VP, ctypes.c_int64, _VP,
+                                         ctypes.c_int64, _VP, _VP]),
     "lbm_lee_compare_fields": (ctypes.c_int32, [_VP, ctypes.POINTER(ctypes.c_int64), _VP,
                                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                                 ctypes.POINTER(ctypes.c_double), _VP, ctypes.c_size_t, _VP]),
@@ -269,9 +269,9 @@ def _i64x3(v):
     return (ctypes.c_int64 * 3)(*[int(x) for x in v])
 
 
-def lbm_nrbc_gather(outer, origin, inner_desc, node_ids, count, strips, targets, stream):
+def lbm_nrbc_gather(outer, origin, inner_desc, node_ids, count, strips, strip_stride, targets, stream):
     _check("lbm_nrbc_gather", load().lbm_nrbc_gather(outer, _i64x3(origin), ctypes.byref(inner_desc), node_ids,
-                                                     int(count), strips, targets, stream))
+                                                     int(count), strips, int(strip_stride), targets, stream))
 
 
 def lbm_lee_compare_fields(a, n_a, b, n_b, origin, scratch, scratch_bytes, stream):

@@ -10,8 +10,8 @@ signal travels faster than one cell per step).  The reflection coefficient of a 
     R = max_t ||p'_bc(t) - p'_ext(t)||_2,box / max_t ||p'_ext(t)||_2,box,   t every 8 steps.
 The sponge baseline runs on a box widened by its layer (L + 2W per axis, the layer outside the
 compared L^D region), so its damping is not counted as error inside the box.
-Training pairs come from the same judge runs: the strip at each face node and the true
-entering populations at its outside neighbour.
+Training pairs come from the same judge runs: the strips at each face node now and one step
+earlier, and the true entering populations at its outside neighbour.
 """
 from __future__ import annotations
 
@@ -83,7 +83,8 @@ def generate(lattice="D2Q9", L=512, E=1536, runs=100, steps=1024, every=8, nodes
     inner = lbm.make_desc(lattice, storage, (L,) * D, bc="mlp")
     nn = lbm.lbm_nrbc_face_nodes(inner)
     per_run = (steps // every) * nodes
-    S = torch.empty((runs * per_run, dims["n_in"]), dtype=torch.float32, device="cuda")
+    nin, ns = dims["n_in"], 3 * info["Q"]
+    S = torch.empty((runs * per_run, nin), dtype=torch.float32, device="cuda")
     T = torch.empty((runs * per_run, dims["n_out"]), dtype=torch.float32, device="cuda")
     origin = [(E - L) // 2] * D + [0] * (3 - D)
     rng = np.random.default_rng(seed)
@@ -96,9 +97,13 @@ def generate(lattice="D2Q9", L=512, E=1536, runs=100, steps=1024, every=8, nodes
         ext.reinit_region(org, (L,) * D, *initial_fields(init, rng, info, L, D))
         for s in range(0, steps, every):
             ids = torch.from_numpy(rng.integers(0, nn, size=nodes).astype(np.int64)).cuda()
-            lbm.lbm_nrbc_gather(ext.h, origin, inner, ids.data_ptr(), nodes, S[k].data_ptr(), T[k].data_ptr(), st)
+            # input row [strip(t), strip(t-1)]: the earlier strip first, then one step, then the
+            # current strip with its targets
+            lbm.lbm_nrbc_gather(ext.h, origin, inner, ids.data_ptr(), nodes, S[k].data_ptr() + 4 * ns, nin, None, st)
+            ext.step(1)
+            lbm.lbm_nrbc_gather(ext.h, origin, inner, ids.data_ptr(), nodes, S[k].data_ptr(), nin, T[k].data_ptr(), st)
             k += nodes
-            ext.step(every)
+            ext.step(every - 1)
         if (r + 1) % max(1, runs // 20) == 0:
             torch.cuda.synchronize()
             log(f"data: run {r + 1}/{runs}, {k} pairs, {time.time() - t0:.1f} s")
@@ -118,7 +123,8 @@ def generate_closed_loop(lattice, params, L=512, E=1536, runs=100, steps=1024, e
     inner = lbm.make_desc(lattice, storage, (L,) * D, bc="mlp")
     nn = lbm.lbm_nrbc_face_nodes(inner)
     per_run = (steps // every) * nodes
-    S = torch.empty((runs * per_run, dims["n_in"]), dtype=torch.float32, device="cuda")
+    nin, ns = dims["n_in"], 3 * info["Q"]
+    S = torch.empty((runs * per_run, nin), dtype=torch.float32, device="cuda")
     T = torch.empty((runs * per_run, dims["n_out"]), dtype=torch.float32, device="cuda")
     junk = torch.empty((nodes, dims["n_in"]), dtype=torch.float32, device="cuda")
     org = [(E - L) // 2] * D
@@ -137,11 +143,15 @@ def generate_closed_loop(lattice, params, L=512, E=1536, runs=100, steps=1024, e
         box.reinit_region([0] * D, (L,) * D, *fields)
         for s in range(0, steps, every):
             ids = torch.from_numpy(rng.integers(0, nn, size=nodes).astype(np.int64)).cuda()
-            lbm.lbm_nrbc_gather(box.h, [0, 0, 0], box.desc, ids.data_ptr(), nodes, S[k].data_ptr(), None, st)
-            lbm.lbm_nrbc_gather(ext.h, origin, inner, ids.data_ptr(), nodes, junk.data_ptr(), T[k].data_ptr(), st)
+            lbm.lbm_nrbc_gather(box.h, [0, 0, 0], box.desc, ids.data_ptr(), nodes, S[k].data_ptr() + 4 * ns, nin, None,
+                                st)
+            ext.step(1)
+            box.step(1)
+            lbm.lbm_nrbc_gather(box.h, [0, 0, 0], box.desc, ids.data_ptr(), nodes, S[k].data_ptr(), nin, None, st)
+            lbm.lbm_nrbc_gather(ext.h, origin, inner, ids.data_ptr(), nodes, junk.data_ptr(), nin, T[k].data_ptr(), st)
             k += nodes
-            ext.step(every)
-            box.step(every)
+            ext.step(every - 1)
+            box.step(every - 1)
         if (r + 1) % max(1, runs // 10) == 0:
             torch.cuda.synchronize()
             log(f"closed-loop data: run {r + 1}/{runs}, {k} pairs, {time.time() - t0:.1f} s")

@@ -129,8 +129,8 @@ def test_network_dims_match_the_oracle_definition(name):
     lat = L.get(name)
     d = lbm.lbm_nrbc_dims(name)
     k = len(open_bc.incoming_canonical(lat))
-    assert d["n_in"] == 3 * lat.Q and d["n_out"] == k and d["hidden"] == 64
-    assert d["n_params"] == mlp.flat(mlp.init_params(np.random.default_rng(0), 3 * lat.Q, k)).size
+    assert d["n_in"] == 6 * lat.Q and d["n_out"] == k and d["hidden"] == 64  # two time levels of 3Q
+    assert d["n_params"] == mlp.flat(mlp.init_params(np.random.default_rng(0), 6 * lat.Q, k)).size
 
 
 @pytest.mark.parametrize("name,shape", [("D2Q9", (7, 11)), ("D3Q7", (4, 5, 6)), ("D1Q3", (9,)), ("D3Q19", (3, 3, 3))])
@@ -140,7 +140,9 @@ def test_face_node_count_and_ghost_bytes(name, shape):
     want = sum(2 * int(np.prod([dims[b] for b in range(D) if b != a])) for a in range(D))
     d = lbm.make_desc(name, "f32", shape, bc="mlp")
     assert lbm.lbm_nrbc_face_nodes(d) == want
-    assert lbm.lbm_lee_ghost_bytes(d) == want * lbm.lbm_nrbc_dims(name)["n_out"] * 4
+    Q = lbm.lbm_lee_lattice_info(name)["Q"]
+    # ghost values, then two one-step history strips (3Q values each) per face node
+    assert lbm.lbm_lee_ghost_bytes(d) == want * (lbm.lbm_nrbc_dims(name)["n_out"] + 2 * 3 * Q) * 4
     assert lbm.lbm_lee_ghost_bytes(lbm.make_desc(name, "f32", shape, bc="zero")) == 0
 
 

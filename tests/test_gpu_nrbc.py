@@ -14,7 +14,7 @@ def test_pipeline_small():
     from paper_1601_08103_amd import lbm, nrbc
     say("nrbc pipeline small")
     S, T = nrbc.generate("D2Q9", L=32, E=96, runs=3, steps=64, every=8, nodes=64, seed=1)
-    assert S.shape == (3 * 8 * 64, 27) and T.shape == (3 * 8 * 64, 3)
+    assert S.shape == (3 * 8 * 64, 54) and T.shape == (3 * 8 * 64, 3)
     assert bool(torch.isfinite(S).all()) and bool(torch.isfinite(T).all())
     P, hist = nrbc.train("D2Q9", S, T, epochs=3, batch=256, lr=3e-3, seed=0)
     assert P.shape == (lbm.lbm_nrbc_dims("D2Q9")["n_params"],) and np.isfinite(P).all()
@@ -56,7 +56,7 @@ def test_pipeline_3d_packets_small():
     from paper_1601_08103_amd import lbm, nrbc
     say("nrbc pipeline 3d small")
     S, T = nrbc.generate("D3Q7", L=24, E=72, runs=2, steps=48, every=8, nodes=128, seed=3, init="mixed")
-    assert S.shape == (2 * 6 * 128, 21) and T.shape == (2 * 6 * 128, 1)
+    assert S.shape == (2 * 6 * 128, 42) and T.shape == (2 * 6 * 128, 1)
     assert bool(torch.isfinite(S).all()) and bool(torch.isfinite(T).all())
     P, hist = nrbc.train("D3Q7", S, T, epochs=2, batch=256, lr=3e-3, seed=0)
     assert np.isfinite(P).all()

@@ -54,7 +54,7 @@ def test_open_step_matches_oracle(name, bc, storage):
 
 def _small_params(lat, seed):
     k = len(ob.incoming_canonical(lat))
-    p = mlp.init_params(np.random.default_rng(seed), 3 * lat.Q, k)
+    p = mlp.init_params(np.random.default_rng(seed), 6 * lat.Q, k)
     rng = np.random.default_rng(seed + 1)
     for key in ("b1", "b2", "b3"):
         p[key] = 0.05 * rng.standard_normal(p[key].shape)
@@ -74,7 +74,7 @@ def test_network_closure_step_matches_oracle(name, storage):
     g = sim.export_f64().cpu().numpy()
     sim.step(3)
     got = sim.export_f64().cpu().numpy()
-    p32 = mlp.unflat(mlp.flat(params).astype(np.float32).astype(np.float64), 3 * lat.Q, len(ob.incoming_canonical(lat)))
+    p32 = mlp.unflat(mlp.flat(params).astype(np.float32).astype(np.float64), 6 * lat.Q, len(ob.incoming_canonical(lat)))
     want = ob.run_open(lat, g, 3, "mlp", params=p32, quantize=True)
     err = rel_l2(got, want)
     say("mlp closure", name, storage, "rel L2", err)
@@ -90,7 +90,7 @@ def test_network_closure_never_adds_energy_on_gpu():
     shape = (20, 24)
     k = len(ob.incoming_canonical(lat))
     rng = np.random.default_rng(8)
-    p = mlp.init_params(rng, 3 * lat.Q, k)
+    p = mlp.init_params(rng, 6 * lat.Q, k)
     p["b1"] = rng.standard_normal(64)
     p["b3"] = 3.0 * rng.standard_normal(k)
     sim = _solver("D2Q9", "f64", shape, "mlp")
@@ -114,10 +114,10 @@ def test_network_forward_matches_oracle(name):
     k = len(ob.incoming_canonical(lat))
     params = _small_params(lat, 11)
     p32 = mlp.flat(params).astype(np.float32)
-    pq = mlp.unflat(p32.astype(np.float64), 3 * lat.Q, k)
+    pq = mlp.unflat(p32.astype(np.float64), 6 * lat.Q, k)
     rng = np.random.default_rng(12)
     B = 1000  # 62.5 tiles: a ragged last tile
-    x = (rng.standard_normal((B, 3 * lat.Q)) * rng.uniform(1e-5, 1e-2, size=(B, 1))).astype(np.float32)
+    x = (rng.standard_normal((B, 6 * lat.Q)) * rng.uniform(1e-5, 1e-2, size=(B, 1))).astype(np.float32)
     say("nrbc forward", name)
     xd = torch.from_numpy(x).cuda()
     pd = torch.from_numpy(p32).cuda()
@@ -136,7 +136,7 @@ def test_network_gradients_match_oracle(name):
     from paper_1601_08103_amd import lbm
     lat = L.get(name)
     k = len(ob.incoming_canonical(lat))
-    nin = 3 * lat.Q
+    nin = 6 * lat.Q
     params = _small_params(lat, 21)
     p32 = mlp.flat(params).astype(np.float32)
     pq = mlp.unflat(p32.astype(np.float64), nin, k)
@@ -213,8 +213,13 @@ def test_gather_pairs_match_the_outer_state(name, inner, outer, origin):
     ids = torch.arange(nn, dtype=torch.int64, device="cuda")
     strips = torch.empty((nn, 3 * lat.Q), dtype=torch.float32, device="cuda")
     targ = torch.empty((nn, k), dtype=torch.float32, device="cuda")
-    lbm.lbm_nrbc_gather(big.h, list(origin) + [0] * (3 - len(origin)), dinner, ids.data_ptr(), nn, strips.data_ptr(),
-                        targ.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    st = torch.cuda.current_stream().cuda_stream
+    org3 = list(origin) + [0] * (3 - len(origin))
+    lbm.lbm_nrbc_gather(big.h, org3, dinner, ids.data_ptr(), nn, strips.data_ptr(), 3 * lat.Q, targ.data_ptr(), st)
+    # the second time level of a network input row: stride 6Q, offset 3Q, strips only
+    rows = torch.zeros((nn, 6 * lat.Q), dtype=torch.float32, device="cuda")
+    lbm.lbm_nrbc_gather(big.h, org3, dinner, ids.data_ptr(), nn, rows.data_ptr() + 4 * 3 * lat.Q, 6 * lat.Q, None, st)
+    assert torch.equal(rows[:, 3 * lat.Q:], strips) and not bool(rows[:, :3 * lat.Q].any())
     S = strips.cpu().numpy().astype(np.float64)
     T = targ.cpu().numpy().astype(np.float64)
     # oracle: the outer state around the inner box, and its strips / outside neighbours
@@ -283,6 +288,8 @@ def test_captured_graph_replays_match_eager_steps(case):
         sim.import_f64(state)
         sims.append(sim)
     graphed, eager = sims
+    for sim in sims:  # the network's history is in place after one step
+        sim.step(1)
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         lbm.lbm_lee_step(graphed.h, 2, torch.cuda.current_stream().cuda_stream)

@@ -78,7 +78,7 @@ def _copy_network(lat):
     Q = lat.Q
     jin = ob.incoming_canonical(lat)
     k = len(jin)
-    p = {"W1": np.zeros((3 * Q, 64)), "b1": np.zeros(64), "W2": np.zeros((64, 64)), "b2": np.zeros(64),
+    p = {"W1": np.zeros((6 * Q, 64)), "b1": np.zeros(64), "W2": np.zeros((64, 64)), "b2": np.zeros(64),
          "W3": np.zeros((64, k)), "b3": np.zeros(k)}
     for r, j in enumerate(jin):
         p["W1"][j, 2 * r] = 1.0
@@ -102,6 +102,34 @@ def test_network_closure_plumbing_against_copy(name):
     assert np.abs(a - b).max() < 1e-14 * np.abs(b).max()
 
 
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q7"])
+def test_network_closure_history_plumbing(name):
+    """A network that copies the boundary value of the previous step's strip: its first step
+    equals the copy closure (the current strip stands in for the missing history), its second
+    step takes the ghosts of the copy closure applied to the state one step earlier."""
+    lat = L.get(name)
+    Q = lat.Q
+    shape = {2: (7, 9), 3: (4, 5, 6)}[lat.D]
+    jin = ob.incoming_canonical(lat)
+    k = len(jin)
+    p = {"W1": np.zeros((6 * Q, 64)), "b1": np.zeros(64), "W2": np.zeros((64, 64)), "b2": np.zeros(64),
+         "W3": np.zeros((64, k)), "b3": np.zeros(k)}
+    for r, j in enumerate(jin):  # rows 3Q + j: the earlier strip's first cell
+        p["W1"][3 * Q + j, 2 * r] = 1.0
+        p["W1"][3 * Q + j, 2 * r + 1] = -1.0
+        p["W2"][2 * r, 2 * r] = 1.0
+        p["W2"][2 * r + 1, 2 * r + 1] = 1.0
+        p["W3"][2 * r, r] = 1.0
+        p["W3"][2 * r + 1, r] = -1.0
+    g0 = np.random.default_rng(3).standard_normal((Q,) + shape)
+    g1 = ob.step_open(lat, g0, "mlp", params=p, limit=False)
+    assert np.abs(g1 - ob.step_open(lat, g0, "copy")).max() < 1e-14 * np.abs(g1).max()
+    g2 = ob.run_open(lat, g0, 2, "mlp", params=p, limit=False)
+    want = ob.step_open(lat, g1, "external", params=ob.ghost_values(lat, g0, "copy"))
+    assert np.abs(g2 - want).max() < 1e-14 * np.abs(want).max()
+    assert np.abs(g2 - ob.step_open(lat, g1, "copy")).max() > 1e-3 * np.abs(want).max()  # history matters
+
+
 @pytest.mark.parametrize("name", ["D2Q9", "D2Q5", "D3Q7", "D3Q19", "D1Q3"])
 def test_network_closure_never_adds_energy(name):
     """With the energy limit, a network closure cannot raise the weighted energy of the open box
@@ -113,7 +141,7 @@ def test_network_closure_never_adds_energy(name):
     grew_without = False
     for seed in range(3):
         rng = np.random.default_rng(100 + seed)
-        p = mlp.init_params(rng, 3 * lat.Q, k)
+        p = mlp.init_params(rng, 6 * lat.Q, k)
         p["b1"] = rng.standard_normal(64)
         p["b3"] = 3.0 * rng.standard_normal(k)
         g = rng.standard_normal((lat.Q,) + shape) * lat.fstar.reshape((-1,) + (1,) * lat.D)
@@ -173,9 +201,9 @@ def _flip_equivariant_network(lat, rng):
     jin = ob.incoming_canonical(lat)
     k = len(jin)
     refl = np.array([np.where((lat.c == lat.c[j] * np.array([1, -1, 1])).all(axis=1))[0][0] for j in range(Q)])
-    pi = np.concatenate([m * Q + refl for m in range(3)])  # (pi x)[n] = x[pi[n]]
+    pi = np.concatenate([m * Q + refl for m in range(6)])  # (pi x)[n] = x[pi[n]], both time levels
     rho = np.array([list(jin).index(refl[j]) for j in jin])
-    g = mlp.init_params(rng, 3 * Q, k, hidden=32)
+    g = mlp.init_params(rng, 6 * Q, k, hidden=32)
     g["b1"] = 0.1 * rng.standard_normal(32)
     g["b2"] = 0.1 * rng.standard_normal(32)
     g["b3"] = 0.1 * rng.standard_normal(k)
@@ -192,7 +220,7 @@ def test_flip_equivariant_network_construction():
     lat = L.get("D2Q9")
     rng = np.random.default_rng(5)
     p, pi, rho = _flip_equivariant_network(lat, rng)
-    x = rng.standard_normal((10, 27))
+    x = rng.standard_normal((10, 54))
     assert np.allclose(mlp.predict(p, x[:, pi]), mlp.predict(p, x)[:, rho], atol=1e-14)
 
 
@@ -210,7 +238,7 @@ def test_network_closure_respects_square_symmetry():
     scale = np.abs(p).max()
     for img in (p.T, p[::-1, :], p[:, ::-1], p[::-1, ::-1], p.T[::-1, :]):
         assert np.abs(p - img).max() < 1e-12 * scale
-    generic = mlp.init_params(np.random.default_rng(6), 27, 3)
+    generic = mlp.init_params(np.random.default_rng(6), 54, 3)
     p = lbe.moments(lat, ob.run_open(lat, g, 8, "mlp", params=generic))["p"]
     assert np.abs(p - p.T).max() < 1e-12 * np.abs(p).max()
 
