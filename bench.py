@@ -5,6 +5,10 @@ Workload (default): 3D LEE-LBM on D3Q7, 256^3 periodic cells, 8 seeded Gaussian 
 pulses (amplitude 1e-3, sigma 12 cells, isentropic, zero velocity), tau = 1/2, 500 steps,
 FP32 population storage.  A "step" is one fused pull-stream + moments + equilibrium +
 relaxation pass over all cells.  The initial state is resident in HBM before timing starts.
+Besides the FP32 headline the line reports every storage mode with its error against the FP64
+path, the roofline of the step kernel, the FP64 CPU oracle as a baseline, and the learned
+non-reflecting closure on its 2D open-box workload (reflection coefficient and step time
+against the zero and sponge closures and the wider periodic run).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -42,6 +46,7 @@ def parse():
     ap.add_argument("--modes", default="f32,f16,bf16,i16,e3m12,f64", help="storage modes to time and compare")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-nrbc", action="store_true", help="skip the learned-closure leg")
     ap.add_argument("--profile-only", action="store_true", help="only the timed steps of --storage (for rocprofv3)")
     ap.add_argument("--with-copy", action="store_true",
                     help="with --profile-only: also run the plain copy kernel on one state buffer's bytes "
@@ -73,6 +78,44 @@ def traffic_from_counters(storage: str, n: int):
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def nrbc_leg():
+    """The learned non-reflecting closure on its 2D workload (D2Q9 512^2 open box, 1536^2 periodic
+    judge, 1024 steps) with the shipped weights (trained by the library's own kernels): reflection
+    coefficient of the zero, sponge and network closures on two held-out initial states, and the
+    time per step of each box next to the judge's."""
+
+    from paper_1601_08103_amd import lbm, nrbc
+
+    path = os.path.join(ROOT, "paper_1601_08103_amd", "weights", "nrbc_D2Q9.npy")
+    if not os.path.exists(path):
+        return None
+    P = np.load(path, allow_pickle=False)
+    L, E, steps, seeds = 512, 1536, 1024, 2
+    sponge = dict(sponge_width=96, sponge_sigma=0.03)
+    info = lbm.lbm_lee_lattice_info("D2Q9")
+    rng = np.random.default_rng(10_000)  # held-out states: training draws seeds below 10000
+    ext = lbm.Solver("D2Q9", "f32", (E, E), None, None, None)
+    closures = ("zero", "sponge", "mlp")
+    R = {c: [] for c in closures}
+    for _ in range(seeds):
+        fields = nrbc.initial_fields("pulses", rng, info, L, 2)
+        for c in closures:
+            R[c].append(nrbc.reflection("D2Q9", c, fields, L, E, steps, 8, params=P, ext=ext, **sponge))
+    times = {"extended_periodic": round(nrbc.time_solver(ext, 200), 5)}
+    ext.close()
+    for c in closures:
+        nb = L + 2 * sponge["sponge_width"] if c == "sponge" else L
+        kw = sponge if c == "sponge" else {}
+        times[c] = round(nrbc.time_per_step("D2Q9", (nb, nb), bc=c, params=P, **kw), 5)
+    out = dict(workload=f"2D open box D2Q9 {L}^2 FP32, judge {E}^2 periodic, {steps} steps, {seeds} held-out "
+                        "pulse states", weights="paper_1601_08103_amd/weights/nrbc_D2Q9.npy",
+               sponge=dict(width=sponge["sponge_width"], sigma=sponge["sponge_sigma"]),
+               R_mean={c: round(float(np.mean(v)), 5) for c, v in R.items()},
+               R_max={c: round(float(np.max(v)), 5) for c, v in R.items()}, ms_per_step=times)
+    log("nrbc", out)
+    return out
 
 
 def cpu_baseline(shape, rho, u, theta, budget_s):
@@ -226,6 +269,8 @@ def main():
                     algorithmic_bytes_per_launch=N * bpu, frac_of_copy=round(achieved / copy_gbs, 4),
                     copy_GBs=round(copy_gbs, 1))
 
+    nrbc_result = None if args.no_nrbc else nrbc_leg()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(shape, rho, u, theta, args.cpu_seconds)
@@ -252,6 +297,7 @@ def main():
         "cpu_baseline": cpu,
         "storage_modes": storage_modes,
         "error_reference": "GPU FP64 path (parity with the FP64 oracle <= 1e-12 in the test suite)",
+        "learned_closure": nrbc_result,
     }
     print(json.dumps(line), flush=True)
 

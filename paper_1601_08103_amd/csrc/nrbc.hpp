@@ -202,55 +202,58 @@ struct NetFrags {
     float b1[kHidden], b2[kHidden], b3[16];
 };
 
-// Every thread of a 256-thread block must call this (it ends with a block barrier).  All global
-// loads are issued before the first conversion, so the staging costs about one memory latency.
+// Every thread of a 256-thread block must call this (it ends with a block barrier).  Fragment
+// (kk, nt, l) of a matrix is handled by thread 64 nt + l for every kk, so each thread's work is
+// fixed at compile time: all its global loads are issued before the first conversion, and the
+// staging costs about one memory latency.
 template <class VS>
 __device__ void stage_forward_weights(const float *__restrict__ P, NetFrags<VS> &F) {
     using G = NetGeom<VS>;
-    constexpr int n1 = G::NIN_PAD / 16 * 4 * 64, n2 = 4 * 4 * 64, n3 = 4 * 64;
-    constexpr int total = n1 + n2 + n3, per = (total + 255) / 256;
-    float v[per][4];
+    constexpr int K1 = G::NIN_PAD / 16;
+    const int tid = threadIdx.x, l = tid & 63, nt = (tid >> 6) & 3;
+    const int j = nt * 16 + (l & 15), r0 = 4 * (l >> 4);
+    float v1[K1][4], v2[4][4], v3[4][4];
 #pragma unroll
-    for (int u = 0; u < per; ++u) {
-        const int t = (int)threadIdx.x + 256 * u;
-        // fragment t: matrix, k-block kk, n-tile nt, lane l -> B[k][j] = W[kk*16 + k][nt*16 + j]
-        const float *W = P + G::OFF_W1;
-        int rows = G::NIN, cols = kHidden, q = t;
-        if (t >= n1 + n2) {
-            W = P + G::OFF_W3, rows = kHidden, cols = G::NOUT, q = t - n1 - n2;
-        } else if (t >= n1) {
-            W = P + G::OFF_W2, rows = kHidden, cols = kHidden, q = t - n1;
+    for (int kk = 0; kk < K1; ++kk)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = kk * 16 + r0 + e;
+            v1[kk][e] = k < G::NIN ? P[G::OFF_W1 + k * kHidden + j] : 0.0f;
         }
-        const int l = q & 63, nt = t >= n1 + n2 ? 0 : (q >> 6) & 3, kk = t >= n1 + n2 ? q >> 6 : q >> 8;
-        const int j = nt * 16 + (l & 15), k0 = kk * 16 + 4 * (l >> 4);
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-            v[u][e] = (t < total && k0 + e < rows && j < cols) ? W[(k0 + e) * cols + j] : 0.0f;
-    }
+    for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-    for (int u = 0; u < per; ++u) {
-        const int t = (int)threadIdx.x + 256 * u;
-        if (t >= total) continue;
-        const bf16x4 b = {(short)bf16_bits(v[u][0]), (short)bf16_bits(v[u][1]), (short)bf16_bits(v[u][2]),
-                          (short)bf16_bits(v[u][3])};
-        if (t < n1) {
-            F.w1[t >> 8][(t >> 6) & 3][t & 63] = b;
-        } else if (t < n1 + n2) {
-            const int q = t - n1;
-            F.w2[q >> 8][(q >> 6) & 3][q & 63] = b;
-        } else {
-            const int q = t - n1 - n2;
-            F.w3[q >> 6][q & 63] = b;
-        }
+        for (int e = 0; e < 4; ++e) v2[kk][e] = P[G::OFF_W2 + (kk * 16 + r0 + e) * kHidden + j];
+    // W3 has one column tile: thread 64 nt + l takes k-block kk = nt
+    const int j3 = l & 15;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int k = nt * 16 + r0 + e;
+        v3[0][e] = j3 < G::NOUT ? P[G::OFF_W3 + k * G::NOUT + j3] : 0.0f;
     }
-    const int t = threadIdx.x;
-    if (t < kHidden) {
-        F.b1[t] = P[G::OFF_B1 + t];
-    } else if (t < 2 * kHidden) {
-        F.b2[t - kHidden] = P[G::OFF_B2 + t - kHidden];
-    } else if (t < 2 * kHidden + 16) {
-        F.b3[t - 2 * kHidden] = t - 2 * kHidden < G::NOUT ? P[G::OFF_B3 + t - 2 * kHidden] : 0.0f;
-    }
+    float bias = 0.0f;
+    if (tid < kHidden)
+        bias = P[G::OFF_B1 + tid];
+    else if (tid < 2 * kHidden)
+        bias = P[G::OFF_B2 + tid - kHidden];
+    else if (tid < 2 * kHidden + 16)
+        bias = tid - 2 * kHidden < G::NOUT ? P[G::OFF_B3 + tid - 2 * kHidden] : 0.0f;
+    auto pack = [](const float (&v)[4]) {
+        const bf16x4 b = {(short)bf16_bits(v[0]), (short)bf16_bits(v[1]), (short)bf16_bits(v[2]),
+                          (short)bf16_bits(v[3])};
+        return b;
+    };
+#pragma unroll
+    for (int kk = 0; kk < K1; ++kk) F.w1[kk][nt][l] = pack(v1[kk]);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) F.w2[kk][nt][l] = pack(v2[kk]);
+    F.w3[nt][l] = pack(v3[0]);
+    if (tid < kHidden)
+        F.b1[tid] = bias;
+    else if (tid < 2 * kHidden)
+        F.b2[tid - kHidden] = bias;
+    else if (tid < 2 * kHidden + 16)
+        F.b3[tid - 2 * kHidden] = bias;
     __syncthreads();
 }
 
