@@ -592,19 +592,17 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
         const bool fullrow = h->nx == 64 * vec;
         const unsigned tune = (unsigned)h->desc.tune;
         const bool fork = (tune & 16u) != 0;  // LBM_TUNE_CLOSURE_STREAM
-        unsigned grid = (waves + 3) / 4;
-        if ((tune & kTunePersistent) && h->cus > 0 && (variant == LBM_VARIANT_DPP || variant == LBM_VARIANT_DPP2)) {
+        const unsigned full_grid = (waves + 3) / 4;
+        // persistent DPP launches: the grid is the resident block slots of the exact kernel launched
+        auto dpp_grid = [&](const void *fn) -> unsigned {
+            if (!(tune & kTunePersistent) || h->cus <= 0) return full_grid;
             int per_cu = 0;
-            const void *fn = vec == 4 ? (fullrow ? reinterpret_cast<const void *>(&step_dpp<VS, ST, 4, true, false>)
-                                                 : reinterpret_cast<const void *>(&step_dpp<VS, ST, 4, false, false>))
-                                      : (fullrow ? reinterpret_cast<const void *>(&step_dpp<VS, ST, 2, true, false>)
-                                                 : reinterpret_cast<const void *>(&step_dpp<VS, ST, 2, false, false>));
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) == hipSuccess && per_cu > 0) {
-                const unsigned g = (unsigned)(per_cu * h->cus);
-                if (g < grid) grid = g;
-            }
+            unsigned g = full_grid;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) == hipSuccess && per_cu > 0)
+                g = std::min(g, (unsigned)(per_cu * h->cus));
             (void)hipGetLastError();
-        }
+            return g;
+        };
         const int lds_cpr = (h->nx + 255) / 256;
         const unsigned lds_blocks = (unsigned)((size_t)h->ny * h->nz * lds_cpr);
         FaceTab<VS::Q> ft;
@@ -640,6 +638,11 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
         auto run = [&](auto skip, auto half) -> lbm_status {
             constexpr bool SK = decltype(skip)::value;
             constexpr bool HF = decltype(half)::value;
+            const bool dpp = variant == LBM_VARIANT_DPP || variant == LBM_VARIANT_DPP2;
+            const unsigned g_dpp4t = dpp && vec == 4 && fullrow ? dpp_grid((const void *)&step_dpp<VS, ST, 4, true, SK, HF>) : 1;
+            const unsigned g_dpp4f = dpp && vec == 4 && !fullrow ? dpp_grid((const void *)&step_dpp<VS, ST, 4, false, SK, HF>) : 1;
+            const unsigned g_dpp2t = dpp && vec == 2 && fullrow ? dpp_grid((const void *)&step_dpp<VS, ST, 2, true, SK, HF>) : 1;
+            const unsigned g_dpp2f = dpp && vec == 2 && !fullrow ? dpp_grid((const void *)&step_dpp<VS, ST, 2, false, SK, HF>) : 1;
             for (int64_t t = 0; t < nsteps; ++t) {
                 const E *src = static_cast<const E *>(h->buf[h->cur]);
                 E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);
@@ -663,18 +666,18 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
                     step_lds<VS, ST, SK, HF><<<lds_blocks, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, lds_cpr, k);
                 } else if (vec == 4) {
                     if (fullrow)
-                        step_dpp<VS, ST, 4, true, SK, HF><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
-                                                                           waves, tune, k);
+                        step_dpp<VS, ST, 4, true, SK, HF><<<g_dpp4t, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N,
+                                                                              cpr, waves, tune, k);
                     else
-                        step_dpp<VS, ST, 4, false, SK, HF><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
-                                                                            waves, tune, k);
+                        step_dpp<VS, ST, 4, false, SK, HF><<<g_dpp4f, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N,
+                                                                               cpr, waves, tune, k);
                 } else {
                     if (fullrow)
-                        step_dpp<VS, ST, 2, true, SK, HF><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
-                                                                           waves, tune, k);
+                        step_dpp<VS, ST, 2, true, SK, HF><<<g_dpp2t, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N,
+                                                                              cpr, waves, tune, k);
                     else
-                        step_dpp<VS, ST, 2, false, SK, HF><<<grid, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
-                                                                            waves, tune, k);
+                        step_dpp<VS, ST, 2, false, SK, HF><<<g_dpp2f, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N,
+                                                                               cpr, waves, tune, k);
                 }
                 if (bc == LBM_BC_MLP && fork) LBM_HIP(hipStreamWaitEvent(st, h->join, 0));  // join
                 if (bc != LBM_BC_PERIODIC) {

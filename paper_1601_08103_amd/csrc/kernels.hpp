@@ -250,13 +250,41 @@ __device__ __forceinline__ void storev(typename ST::elem *p, const typename ST::
     }
 }
 
+// The populations of one chunk as loaded (still encoded): one aligned VEC-element vector each.
+template <class VS, class ST, int VEC>
+struct ChunkRaw {
+    typedef typename ST::elem ev __attribute__((ext_vector_type(VEC)));
+    ev v[VS::Q];
+};
+
+template <class VS, class ST, int VEC, bool SKIP0>
+__device__ __forceinline__ void load_chunk(const typename ST::elem *__restrict__ src, int nx, int ny, int nz, size_t N,
+                                           unsigned row, int chunk, int lane, bool ntl, ChunkRaw<VS, ST, VEC> &r) {
+    using V = typename ChunkRaw<VS, ST, VEC>::ev;
+    const int y = (int)(row % (unsigned)ny);
+    const int z = (int)(row / (unsigned)ny);
+    const int x0 = chunk * (64 * VEC) + lane * VEC;
+#pragma unroll
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) {
+        const int ys = wrap_add(y, -VS::cy(i), ny);
+        const int zs = wrap_add(z, -VS::cz(i), nz);
+        const typename ST::elem *rowp = src + (size_t)i * N + ((size_t)zs * ny + ys) * (size_t)nx;
+        V v = {};
+        if (x0 < nx) v = vload(reinterpret_cast<const V *>(rowp + x0), ntl);
+        r.v[i] = v;
+    }
+}
+
+// Decode a loaded chunk, move the x-neighbours across lanes, collide and store.
 template <class VS, class ST, int VEC, bool FULLROW, bool SKIP0, bool HALF>
-__device__ __forceinline__ void step_chunk(const typename ST::elem *__restrict__ src,
-                                           typename ST::elem *__restrict__ dst, int nx, int ny, int nz, size_t N,
-                                           unsigned row, int chunk, int lane, bool ntl, bool nts,
-                                           const StepCoef<typename ST::comp, VS::Q> &k) {
+__device__ __forceinline__ void finish_chunk(const typename ST::elem *__restrict__ src,
+                                             typename ST::elem *__restrict__ dst, int nx, int ny, int nz, size_t N,
+                                             unsigned row, int chunk, int lane, bool nts,
+                                             const StepCoef<typename ST::comp, VS::Q> &k,
+                                             const ChunkRaw<VS, ST, VEC> &r) {
     using CT = typename ST::comp;
     using E = typename ST::elem;
+    constexpr bool RAW = ST::has_raw;
     const int y = (int)(row % (unsigned)ny);
     const int z = (int)(row / (unsigned)ny);
     const int x0 = chunk * (64 * VEC) + lane * VEC;
@@ -268,28 +296,29 @@ __device__ __forceinline__ void step_chunk(const typename ST::elem *__restrict__
     for (int q = 0; q < VEC; ++q) s[0][q] = 0;
 #pragma unroll
     for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) {
-        const int ys = wrap_add(y, -VS::cy(i), ny);
-        const int zs = wrap_add(z, -VS::cz(i), nz);
-        const E *rowp = src + (size_t)i * N + ((size_t)zs * ny + ys) * (size_t)nx;
         CT v[VEC];
 #pragma unroll
-        for (int q = 0; q < VEC; ++q) v[q] = 0;
-        if (active) loadv<ST, VEC>(rowp + x0, v, ntl);
+        for (int q = 0; q < VEC; ++q) v[q] = dec_io<ST, RAW>(r.v[i][q]);
         if (VS::cx(i) == 0) {
 #pragma unroll
             for (int q = 0; q < VEC; ++q) s[i][q] = v[q];
-        } else if (VS::cx(i) > 0) {
-            CT prev = FULLROW ? dpp_move<kDppWaveRor1>(v[VEC - 1]) : dpp_move<kDppWaveShr1>(v[VEC - 1]);
-            if (!FULLROW && lane == 0) prev = dec_io<ST, ST::has_raw>(rowp[x0 == 0 ? nx - 1 : x0 - 1]);
-            s[i][0] = prev;
-#pragma unroll
-            for (int q = 1; q < VEC; ++q) s[i][q] = v[q - 1];
         } else {
-            CT next = FULLROW ? dpp_move<kDppWaveRol1>(v[0]) : dpp_move<kDppWaveShl1>(v[0]);
-            if (!FULLROW && last && active) next = dec_io<ST, ST::has_raw>(rowp[x0 + VEC >= nx ? 0 : x0 + VEC]);
+            const int ys = wrap_add(y, -VS::cy(i), ny);
+            const int zs = wrap_add(z, -VS::cz(i), nz);
+            const E *rowp = src + (size_t)i * N + ((size_t)zs * ny + ys) * (size_t)nx;
+            if (VS::cx(i) > 0) {
+                CT prev = FULLROW ? dpp_move<kDppWaveRor1>(v[VEC - 1]) : dpp_move<kDppWaveShr1>(v[VEC - 1]);
+                if (!FULLROW && lane == 0) prev = dec_io<ST, RAW>(rowp[x0 == 0 ? nx - 1 : x0 - 1]);
+                s[i][0] = prev;
 #pragma unroll
-            for (int q = 0; q < VEC - 1; ++q) s[i][q] = v[q + 1];
-            s[i][VEC - 1] = next;
+                for (int q = 1; q < VEC; ++q) s[i][q] = v[q - 1];
+            } else {
+                CT next = FULLROW ? dpp_move<kDppWaveRol1>(v[0]) : dpp_move<kDppWaveShl1>(v[0]);
+                if (!FULLROW && last && active) next = dec_io<ST, RAW>(rowp[x0 + VEC >= nx ? 0 : x0 + VEC]);
+#pragma unroll
+                for (int q = 0; q < VEC - 1; ++q) s[i][q] = v[q + 1];
+                s[i][VEC - 1] = next;
+            }
         }
     }
     if (!active) return;
@@ -307,6 +336,10 @@ __device__ __forceinline__ void step_chunk(const typename ST::elem *__restrict__
     for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) storev<ST, VEC>(dst + (size_t)i * N + out, s[i], nts);
 }
 
+// Each wave owns chunks wave, wave + G, wave + 2G, ... (G = waves in the grid).  Without the
+// persistent tuning the grid covers every chunk once.  With it the grid is sized to the resident
+// wave slots and every wave loads its next chunk before it finishes the current one, so its
+// loads stay in flight across the collision and the waves end together.
 template <class VS, class ST, int VEC, bool FULLROW, bool SKIP0, bool HALF = false>
 __global__ __launch_bounds__(256) void step_dpp(const typename ST::elem *__restrict__ src,
                                                 typename ST::elem *__restrict__ dst, int nx, int ny, int nz,
@@ -315,10 +348,23 @@ __global__ __launch_bounds__(256) void step_dpp(const typename ST::elem *__restr
     const int lane = threadIdx.x & 63;
     const unsigned wid = (unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool ntl = (tune & kTuneNtLoad) != 0, nts = (tune & kTuneNtStore) != 0;
-    for (unsigned wave = blockIdx.x * 4u + wid; wave < total_waves; wave += gridDim.x * 4u) {
-        const unsigned row = wave / (unsigned)chunks_per_row;
-        const int chunk = (int)(wave - row * (unsigned)chunks_per_row);
-        step_chunk<VS, ST, VEC, FULLROW, SKIP0, HALF>(src, dst, nx, ny, nz, N, row, chunk, lane, ntl, nts, k);
+    const unsigned G = gridDim.x * 4u;
+    unsigned wave = blockIdx.x * 4u + wid;
+    if (wave >= total_waves) return;
+    ChunkRaw<VS, ST, VEC> cur, nxt;
+    load_chunk<VS, ST, VEC, SKIP0>(src, nx, ny, nz, N, wave / (unsigned)chunks_per_row,
+                                   (int)(wave % (unsigned)chunks_per_row), lane, ntl, cur);
+    for (;;) {
+        const unsigned wn = wave + G;
+        const bool more = wn < total_waves;  // uniform across the wave
+        if (more)
+            load_chunk<VS, ST, VEC, SKIP0>(src, nx, ny, nz, N, wn / (unsigned)chunks_per_row,
+                                           (int)(wn % (unsigned)chunks_per_row), lane, ntl, nxt);
+        finish_chunk<VS, ST, VEC, FULLROW, SKIP0, HALF>(src, dst, nx, ny, nz, N, wave / (unsigned)chunks_per_row,
+                                                        (int)(wave % (unsigned)chunks_per_row), lane, nts, k, cur);
+        if (!more) break;
+        cur = nxt;
+        wave = wn;
     }
 }
 

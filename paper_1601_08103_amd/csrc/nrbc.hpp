@@ -295,8 +295,12 @@ __device__ floatx4 net_forward_tile_staged(const NetFrags<VS> &F, TT &T, int lan
 // rms of row (lane & 15) in every lane that holds that row.  X(row, v) gives strip value v.
 // With EW (v -> weight, 0 for most inputs), also returns in *m_out the row's max |x| and in
 // *e_out sum_v EW(v) (x_v / max|x|)^2 (an energy in units of the row's max, no underflow).
-template <class VS, class TT, class LoadFn, class EWFn>
-__device__ float load_normalised_tile(TT &T, int nrows, int lane, LoadFn X, EWFn EW, float *m_out, float *e_out) {
+// ON(row, v, x) sees every loaded value (row < nrows, v < n_in).
+// A row whose max is below 2^-100 is scaled by 2^64 first (exact), so the reciprocals of its
+// max and rms cannot overflow; the returned max and rms are scaled back.
+template <class VS, class TT, class LoadFn, class EWFn, class OnFn>
+__device__ float load_normalised_tile(TT &T, int nrows, int lane, LoadFn X, EWFn EW, float *m_out, float *e_out,
+                                      OnFn ON) {
     using G = NetGeom<VS>;
     const int r = lane & 15, g = lane >> 4;
     float vals[(G::NIN_PAD + 3) / 4];
@@ -305,17 +309,23 @@ __device__ float load_normalised_tile(TT &T, int nrows, int lane, LoadFn X, EWFn
     for (int t = 0; t < (G::NIN_PAD + 3) / 4; ++t) {
         const int v = g + 4 * t;
         float x = 0.0f;
-        if (r < nrows && v < G::NIN) x = X(r, v);
+        if (r < nrows && v < G::NIN) {
+            x = X(r, v);
+            ON(r, v, x);
+        }
         vals[t] = x;
         m = fmaxf(m, fabsf(x));
     }
     m = fmaxf(m, __shfl_xor(m, 16, 64));
     m = fmaxf(m, __shfl_xor(m, 32, 64));
-    // divisions (not reciprocals): m and s may be FP32 denormals, whose reciprocal overflows
+    const float pre = m < 0x1p-100f ? 0x1p64f : 1.0f;
+    m *= pre;
+    const float im = m > 0.0f ? 1.0f / m : 0.0f;
     float ss = 0.0f, ee = 0.0f;
 #pragma unroll
     for (int t = 0; t < (G::NIN_PAD + 3) / 4; ++t) {
-        const float q = m > 0.0f ? vals[t] / m : 0.0f;
+        vals[t] *= pre;
+        const float q = vals[t] * im;
         ss += q * q;
         const int v = g + 4 * t;
         if (v < G::NIN) ee += EW(v) * q * q;
@@ -325,15 +335,20 @@ __device__ float load_normalised_tile(TT &T, int nrows, int lane, LoadFn X, EWFn
     ee += __shfl_xor(ee, 16, 64);
     ee += __shfl_xor(ee, 32, 64);
     const float s = m * sqrtf(ss / (float)G::NIN);
+    const float is = s > 0.0f ? 1.0f / s : 0.0f;
 #pragma unroll
     for (int t = 0; t < (G::NIN_PAD + 3) / 4; ++t) {
         const int v = g + 4 * t;
-        if (v < G::NIN_PAD) T.z[r][v] = (v < G::NIN && s > 0.0f) ? bf16_bits(vals[t] / s) : (unsigned short)0;
+        if (v < G::NIN_PAD) T.z[r][v] = v < G::NIN ? bf16_bits(vals[t] * is) : (unsigned short)0;
     }
     wave_lds_sync();
-    if (m_out) *m_out = m;
+    if (m_out) *m_out = m / pre;
     if (e_out) *e_out = ee;
-    return s;
+    return s / pre;
+}
+template <class VS, class TT, class LoadFn, class EWFn>
+__device__ float load_normalised_tile(TT &T, int nrows, int lane, LoadFn X, EWFn EW, float *m_out, float *e_out) {
+    return load_normalised_tile<VS>(T, nrows, lane, X, EW, m_out, e_out, [](int, int, float) {});
 }
 template <class VS, class TT, class LoadFn>
 __device__ float load_normalised_tile(TT &T, int nrows, int lane, LoadFn X) {

@@ -252,14 +252,15 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
         };
         // input [strip(t), strip(t-1)]; the previous strip comes from the history buffer (the
         // current one again on the first step after the state was set)
+        // this step's strip becomes the next step's history (the other buffer of the pair)
         float mx = 0.0f, e_out = 0.0f;
         const float s = load_normalised_tile<VS>(
             T, nrows, lane,
             [&](int, int v) { return v < NS ? strip_now(v) : (hist_in ? hist_in[node * NS + (v - NS)] : strip_now(v - NS)); },
-            [&](int v) { return v < VS::Q && VS::cx(v) == -1 ? invf_s[f][v] : 0.0f; }, &mx, &e_out);
-        // this step's strip becomes the next step's history (the other buffer of the pair)
-        if (r < nrows)
-            for (int v = lane >> 4; v < NS; v += 4) hist_out[node * NS + v] = strip_now(v);
+            [&](int v) { return v < VS::Q && VS::cx(v) == -1 ? invf_s[f][v] : 0.0f; }, &mx, &e_out,
+            [&](int, int v, float x) {
+                if (v < NS) hist_out[node * NS + v] = x;
+            });
         const floatx4 y = net_forward_tile_staged<VS>(F, T, lane);
         const int col = lane & 15;
 #pragma unroll

@@ -360,14 +360,16 @@ def test_every_cell_is_written(storage, tune):
 def test_variants_and_tunings_agree():
     """All step-kernel variants and tuning knobs compute the same update: identical bits
     (same arithmetic per cell, only the memory access pattern differs)."""
-    for name, shape in (("D3Q19", (5, 6, 264)), ("D2Q9", (9, 520)), ("D3Q7", (4, 3, 256))):
+    for name, shape, storage in (("D3Q19", (5, 6, 264), "f32"), ("D2Q9", (9, 520), "f32"),
+                                 ("D3Q7", (4, 3, 256), "f32"), ("D3Q7", (6, 40, 256), "e3m12"),
+                                 ("D2Q5", (33, 264), "f16"), ("D3Q7", (5, 7, 128), "f64")):
         lat = lattice(name)
         fields = inputs.random_fields(2, shape, lat.D)
         outs = []
         for variant, tune in (("generic", 0), ("dpp", 0), ("dpp", 1), ("dpp", 2), ("dpp", 4), ("dpp", 7),
                               ("lds", 0), ("dpp2", 0), ("dpp2", 7)):
-            say("variants", name, variant, tune)
-            sim = _solver(name, "f32", shape, variant=variant, fields=fields, tune=tune)
+            say("variants", name, storage, variant, tune)
+            sim = _solver(name, storage, shape, variant=variant, fields=fields, tune=tune)
             sim.step(7)
             outs.append(sim.export_f64().cpu().numpy())
             sim.close()
