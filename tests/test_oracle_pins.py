@@ -206,6 +206,35 @@ def test_gamma_unitarity_claims(name):
         assert np.abs(G.conj().T @ G - np.eye(lat.Q)).max() > 1e-3
 
 
+@pytest.mark.parametrize("name", list(L.ALL))
+def test_spectral_scan_stability_range(name):
+    """Von Neumann scan of Gamma(k) over a regular grid of k in [-pi, pi]^D (Section "Analysis of
+    the LBE", the L2-stability theorem): for tau >= 1/2 the spectral radius and the 1/f*-weighted
+    norm of Gamma(k) stay <= 1 at every k (the weighted norm is the stability certificate for the
+    sets whose Gamma is not unitary); for tau < 1/2 the radius exceeds 1 (at k = 0 already, where
+    Gamma = H(tau) has the eigenvalue 1 - 1/tau), except for D1Q3, whose equilibrium map is the
+    identity (rank Q), so that H(tau) = I for every tau."""
+    lat = L.get(name)
+    m = {1: 201, 2: 41, 3: 13}[lat.D]
+    axis = np.linspace(-np.pi, np.pi, m)
+    ks = np.stack(np.meshgrid(*([axis] * lat.D), indexing="ij"), -1).reshape(-1, lat.D)
+    w = np.sqrt(1.0 / lat.fstar)
+    for tau in (0.5, 0.7, 1.5):
+        H = lbe.update_matrix(lat, tau)
+        phases = np.exp(-1j * (ks @ lat.c[:, :lat.D].T))  # (nk, Q)
+        G = phases[:, :, None] * H[None, :, :]
+        rho = np.abs(np.linalg.eigvals(G)).max()
+        Gw = w[None, :, None] * G / w[None, None, :]  # W^(1/2) G W^(-1/2): its 2-norm is the W-norm
+        wnorm = np.linalg.norm(Gw, ord=2, axis=(1, 2)).max()
+        assert rho <= 1 + 1e-12, (tau, rho)
+        assert wnorm <= 1 + 1e-12, (tau, wnorm)
+    H45 = lbe.update_matrix(lat, 0.45)
+    if np.allclose(lbe.equilibrium_matrix(lat), np.eye(lat.Q), atol=1e-12):
+        assert np.allclose(H45, np.eye(lat.Q), atol=1e-12)
+    else:
+        assert np.abs(np.linalg.eigvals(H45)).max() > 1.2
+
+
 # --------------------------------------------------------------------------- the stepper
 def _grid_k(shape, D, rng):
     ms = rng.integers(-3, 4, size=D)
