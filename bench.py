@@ -96,7 +96,7 @@ def nrbc_leg():
     sponge = dict(sponge_width=96, sponge_sigma=0.03)
     info = lbm.lbm_lee_lattice_info("D2Q9")
     rng = np.random.default_rng(10_000)  # held-out states: training draws seeds below 10000
-    ext = lbm.Solver("D2Q9", "f32", (E, E), None, None, None)
+    ext = nrbc.judge_solver("D2Q9", "f32", E, 2)
     closures = ("zero", "sponge", "mlp")
     R = {c: [] for c in closures}
     for _ in range(seeds):

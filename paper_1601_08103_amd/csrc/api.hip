@@ -33,6 +33,8 @@ struct lbm_lee {
     const float *net;  // LBM_BC_MLP: closure parameters (caller-owned)
     float *ghost;      // LBM_BC_MLP: ghost buffer (caller-owned)
     bool skip0;        // rest population left out of the step (invariant under it)
+    bool inplace = false;  // LBM_TUNE_IN_PLACE: one buffer, layouts S and P alternate
+    int phase = 0;         // in place: 0 = layout S (swapped), 1 = layout P (pushed)
     // LBM_BC_MLP: the network runs on a helper stream of the handle's device, concurrently with
     // the bulk step (both only read the pre-step state); events fork it from and join it to
     // the caller's stream.  Created by lbm_lee_set_closure, released by lbm_lee_destroy.
@@ -128,7 +130,12 @@ lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
     if ((double)d->n[1] * (double)d->n[2] * 16.0 > 4.0e9) return fail(LBM_E_INVALID, "too many rows (ny * nz)");
     if (!(d->tau >= 0.5) || !std::isfinite(d->tau)) return fail(LBM_E_INVALID, "tau must be finite and >= 1/2 (got %g)", d->tau);
     if (d->variant < LBM_VARIANT_AUTO || d->variant > LBM_VARIANT_DPP2) return fail(LBM_E_INVALID, "unknown variant %d", d->variant);
-    if (d->tune < 0 || d->tune > 31) return fail(LBM_E_INVALID, "unknown tune bits 0x%x", d->tune);
+    if (d->tune < 0 || d->tune > 63) return fail(LBM_E_INVALID, "unknown tune bits 0x%x", d->tune);
+    if (d->tune & kTuneInPlace) {
+        if (d->bc != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "in-place streaming needs the periodic box");
+        if (d->variant != LBM_VARIANT_AUTO && d->variant != LBM_VARIANT_GENERIC)
+            return fail(LBM_E_UNSUPPORTED, "in-place streaming runs its own kernels: variant must be AUTO or GENERIC");
+    }
     if (!(d->store_scale >= 0.0) || !std::isfinite(d->store_scale)) return fail(LBM_E_INVALID, "store_scale must be >= 0");
     if (d->store_scale > 0.0) {
         int ex;
@@ -328,6 +335,7 @@ lbm_status launch_check() {
 // gather has the highest occupancy and beats the vectorised variants; 2-byte storage needs
 // wider per-lane accesses.
 int resolve_variant(const lbm_lee *h) {
+    if (h->inplace) return LBM_VARIANT_GENERIC;  // the in-place kernels are one thread per cell
     if (h->desc.variant != LBM_VARIANT_AUTO) return h->desc.variant;
     if (elem_size(h->desc.storage) >= 4) return LBM_VARIANT_GENERIC;
     if (h->nx % 4 == 0) return LBM_VARIANT_DPP;
@@ -335,14 +343,27 @@ int resolve_variant(const lbm_lee *h) {
     return LBM_VARIANT_GENERIC;
 }
 
+// Layout of the state buffer as it is now, and the one a fresh state is written in.
+Layout layout_now(const lbm_lee *h) {
+    Layout l{kLayoutPlain, h->nx, h->ny, h->nz};
+    if (h->inplace) l.mode = h->phase == 0 ? kLayoutSwapped : kLayoutPushed;
+    return l;
+}
+Layout layout_fresh(const lbm_lee *h) {
+    Layout l{h->inplace ? kLayoutSwapped : kLayoutPlain, h->nx, h->ny, h->nz};
+    return l;
+}
+// The other ping-pong buffer's rest plane (kept equal to this one's when the step skips it).
+void *rest_copy_buffer(const lbm_lee *h) { return (h->skip0 && !h->inplace) ? h->buf[h->cur ^ 1] : nullptr; }
+
 lbm_status launch_init(lbm_lee *h, const double *rho, const double *u, const double *theta, hipStream_t st) {
     return visit(h->desc.lattice, h->desc.storage, [&](auto vs, auto sto) -> lbm_status {
         using VS = decltype(vs);
         using ST = decltype(sto);
         auto k = field_coef<VS::Q>(h);
         auto *dst = static_cast<typename ST::elem *>(h->buf[h->cur]);
-        auto *other = h->skip0 ? static_cast<typename ST::elem *>(h->buf[h->cur ^ 1]) : nullptr;
-        init_equilibrium<VS, ST><<<blocks_for(h->N), 256, 0, st>>>(rho, u, theta, dst, other, h->N, k);
+        auto *other = static_cast<typename ST::elem *>(rest_copy_buffer(h));
+        init_equilibrium<VS, ST><<<blocks_for(h->N), 256, 0, st>>>(rho, u, theta, dst, other, h->N, k, layout_fresh(h));
         return launch_check();
     });
 }
@@ -356,10 +377,11 @@ lbm_status launch_init_region(lbm_lee *h, const int64_t origin[3], const int64_t
         using ST = decltype(sto);
         auto k = field_coef<VS::Q>(h);
         auto *dst = static_cast<typename ST::elem *>(h->buf[h->cur]);
-        auto *other = h->skip0 ? static_cast<typename ST::elem *>(h->buf[h->cur ^ 1]) : nullptr;
+        auto *other = static_cast<typename ST::elem *>(rest_copy_buffer(h));
         init_region<VS, ST><<<blocks_for(h->N), 256, 0, st>>>(rho, u, theta, dst, other, h->nx, h->ny, h->N,
                                                               (int)origin[0], (int)origin[1], (int)origin[2],
-                                                              (int)n_sub[0], (int)n_sub[1], (int)n_sub[2], k);
+                                                              (int)n_sub[0], (int)n_sub[1], (int)n_sub[2], k,
+                                                              layout_fresh(h));
         return launch_check();
     });
 }
@@ -459,11 +481,19 @@ lbm_status lbm_lee_init(const lbm_lee_desc *desc, void *pop_a, void *pop_b, size
     if (s != LBM_OK) return s;
     const size_t N = (size_t)(desc->n[0] * desc->n[1] * desc->n[2]);
     const size_t need = (size_t)tab.Q * N * elem_size(desc->storage);
-    if (!pop_a || !pop_b || pop_a == pop_b) return fail(LBM_E_INVALID, "pop_a and pop_b must be two distinct buffers");
-    if (!aligned256(pop_a) || !aligned256(pop_b)) return fail(LBM_E_INVALID, "population buffers must be 256-byte aligned");
-    if (bytes_each < need) return fail(LBM_E_INVALID, "population buffers hold %zu bytes, need %zu", bytes_each, need);
-    const char *a = static_cast<const char *>(pop_a), *b = static_cast<const char *>(pop_b);
-    if (a < b + need && b < a + need) return fail(LBM_E_INVALID, "population buffers overlap");
+    const bool inplace = (desc->tune & kTuneInPlace) != 0;
+    if (inplace) {
+        if (!pop_a) return fail(LBM_E_INVALID, "pop_a must not be NULL");
+        if (!aligned256(pop_a)) return fail(LBM_E_INVALID, "the population buffer must be 256-byte aligned");
+        if (bytes_each < need) return fail(LBM_E_INVALID, "the population buffer holds %zu bytes, need %zu", bytes_each, need);
+        pop_b = nullptr;  // one buffer
+    } else {
+        if (!pop_a || !pop_b || pop_a == pop_b) return fail(LBM_E_INVALID, "pop_a and pop_b must be two distinct buffers");
+        if (!aligned256(pop_a) || !aligned256(pop_b)) return fail(LBM_E_INVALID, "population buffers must be 256-byte aligned");
+        if (bytes_each < need) return fail(LBM_E_INVALID, "population buffers hold %zu bytes, need %zu", bytes_each, need);
+        const char *a = static_cast<const char *>(pop_a), *b = static_cast<const char *>(pop_b);
+        if (a < b + need && b < a + need) return fail(LBM_E_INVALID, "population buffers overlap");
+    }
     const bool at_rest = !rho && !u && !theta;
     if (!at_rest && (!rho || !u || !theta))
         return fail(LBM_E_INVALID, "initial fields must be all given or all NULL (the state at rest)");
@@ -488,6 +518,8 @@ lbm_status lbm_lee_init(const lbm_lee_desc *desc, void *pop_a, void *pop_b, size
     h->net = nullptr;
     h->ghost = nullptr;
     h->skip0 = skip_rest(tab, desc);
+    h->inplace = inplace;
+    h->phase = 0;
     {
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -517,6 +549,7 @@ lbm_status lbm_lee_reinit(lbm_lee_handle h, const double *rho, const double *u, 
     h->cur = 0;
     h->steps = 0;
     h->hist_valid = false;
+    h->phase = 0;
     lbm_status s = launch_init(h, rho, u, theta, static_cast<hipStream_t>(stream));
     return s == LBM_OK ? ok() : s;
 }
@@ -540,6 +573,7 @@ lbm_status lbm_lee_reinit_region(lbm_lee_handle h, const int64_t origin[3], cons
     h->cur = 0;
     h->steps = 0;
     h->hist_valid = false;
+    h->phase = 0;
     s = launch_init_region(h, origin, n_sub, rho, u, theta, static_cast<hipStream_t>(stream));
     return s == LBM_OK ? ok() : s;
 }
@@ -561,11 +595,11 @@ lbm_status lbm_lee_moments_region(lbm_lee_handle h, const int64_t origin[3], con
         if (out_is_f64)
             moments_region_kernel<VS, ST, double><<<blocks_for(Ns), 256, 0, st>>>(
                 src, h->N, h->nx, h->ny, o0, o1, o2, s0, s1, s2, k, (double *)p, (double *)u, (double *)rho,
-                (double *)theta);
+                (double *)theta, layout_now(h));
         else
             moments_region_kernel<VS, ST, float><<<blocks_for(Ns), 256, 0, st>>>(
                 src, h->N, h->nx, h->ny, o0, o1, o2, s0, s1, s2, k, (float *)p, (float *)u, (float *)rho,
-                (float *)theta);
+                (float *)theta, layout_now(h));
         return launch_check();
     });
     return s == LBM_OK ? ok() : s;
@@ -643,6 +677,22 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
             const unsigned g_dpp4f = dpp && vec == 4 && !fullrow ? dpp_grid((const void *)&step_dpp<VS, ST, 4, false, SK, HF>) : 1;
             const unsigned g_dpp2t = dpp && vec == 2 && fullrow ? dpp_grid((const void *)&step_dpp<VS, ST, 2, true, SK, HF>) : 1;
             const unsigned g_dpp2f = dpp && vec == 2 && !fullrow ? dpp_grid((const void *)&step_dpp<VS, ST, 2, false, SK, HF>) : 1;
+            if (h->inplace) {  // periodic box, one buffer: layouts S and P alternate
+                E *A = static_cast<E *>(h->buf[0]);
+                for (int64_t t = 0; t < nsteps; ++t) {
+                    if (h->phase == 0)
+                        step_inplace<VS, ST, SK, HF, true><<<blocks_for(h->N), 256, 0, st>>>(A, h->nx, h->ny, h->nz,
+                                                                                          h->N, k);
+                    else
+                        step_inplace<VS, ST, SK, HF, false><<<blocks_for(h->N), 256, 0, st>>>(A, h->nx, h->ny, h->nz,
+                                                                                           h->N, k);
+                    lbm_status ls = launch_check();
+                    if (ls != LBM_OK) return ls;
+                    h->phase ^= 1;
+                    h->steps += 1;
+                }
+                return LBM_OK;
+            }
             for (int64_t t = 0; t < nsteps; ++t) {
                 const E *src = static_cast<const E *>(h->buf[h->cur]);
                 E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);
@@ -723,10 +773,10 @@ lbm_status lbm_lee_moments(lbm_lee_handle h, void *p, void *u, void *rho, void *
         const auto *src = static_cast<const typename ST::elem *>(h->buf[h->cur]);
         if (out_is_f64)
             moments_kernel<VS, ST, double><<<blocks_for(h->N), 256, 0, st>>>(
-                src, h->N, k, (double *)p, (double *)u, (double *)rho, (double *)theta);
+                src, h->N, k, (double *)p, (double *)u, (double *)rho, (double *)theta, layout_now(h));
         else
             moments_kernel<VS, ST, float><<<blocks_for(h->N), 256, 0, st>>>(
-                src, h->N, k, (float *)p, (float *)u, (float *)rho, (float *)theta);
+                src, h->N, k, (float *)p, (float *)u, (float *)rho, (float *)theta, layout_now(h));
         return launch_check();
     });
     return s == LBM_OK ? ok() : s;
@@ -764,7 +814,7 @@ lbm_status lbm_lee_error_norms(lbm_lee_handle h, const double *ref_p, const doub
         using ST = decltype(sto);
         auto k = field_coef<VS::Q>(h);
         const auto *src = static_cast<const typename ST::elem *>(h->buf[h->cur]);
-        error_partials<VS, ST><<<kReduceBlocks, 256, 0, st>>>(src, h->N, k, ref_p, ref_u, part);
+        error_partials<VS, ST><<<kReduceBlocks, 256, 0, st>>>(src, h->N, k, ref_p, ref_u, part, layout_now(h));
         return launch_check();
     });
     if (s != LBM_OK) return s;
@@ -783,7 +833,7 @@ lbm_status lbm_lee_export_f64(lbm_lee_handle h, double *g, void *stream) {
         using ST = decltype(sto);
         auto k = field_coef<VS::Q>(h);
         const auto *src = static_cast<const typename ST::elem *>(h->buf[h->cur]);
-        export_f64<VS, ST><<<blocks_for((size_t)VS::Q * h->N), 256, 0, st>>>(src, h->N, k, g);
+        export_f64<VS, ST><<<blocks_for((size_t)VS::Q * h->N), 256, 0, st>>>(src, h->N, k, g, layout_now(h));
         return launch_check();
     });
     return s == LBM_OK ? ok() : s;
@@ -798,13 +848,14 @@ lbm_status lbm_lee_import_f64(lbm_lee_handle h, const double *g, int64_t steps_d
         using ST = decltype(sto);
         auto k = field_coef<VS::Q>(h);
         auto *dst = static_cast<typename ST::elem *>(h->buf[h->cur]);
-        auto *other = h->skip0 ? static_cast<typename ST::elem *>(h->buf[h->cur ^ 1]) : nullptr;
-        import_f64<VS, ST><<<blocks_for((size_t)VS::Q * h->N), 256, 0, st>>>(g, h->N, k, dst, other);
+        auto *other = static_cast<typename ST::elem *>(rest_copy_buffer(h));
+        import_f64<VS, ST><<<blocks_for((size_t)VS::Q * h->N), 256, 0, st>>>(g, h->N, k, dst, other, layout_fresh(h));
         return launch_check();
     });
     if (s != LBM_OK) return s;
     h->steps = steps_done;
     h->hist_valid = false;
+    h->phase = 0;
     return ok();
 }
 

@@ -51,8 +51,15 @@ struct StF16 {
     __device__ static comp dec_raw(elem v) { return dec(v); }
     __device__ static elem enc_raw(comp v) { return enc(v); }
     __device__ static comp dec(elem v) { return (float)__builtin_bit_cast(_Float16, v); }
-    // v_cvt_f16_f32 rounds with the default mode: to nearest, ties to even.
-    __device__ static elem enc(comp v) { return __builtin_bit_cast(unsigned short, (_Float16)v); }
+    // v_cvt_f16_f32 rounds with the default mode: to nearest, ties to even.  The input is
+    // first fixed as an FP32 value: without the empty asm the compiler fuses the conversion
+    // into the fma that produced v (v_fma_mixlo_f16, one rounding straight to FP16) for some
+    // stores and not for others, depending on how a kernel packs them, and two kernels with
+    // the same arithmetic would differ in the last FP16 bit.
+    __device__ static elem enc(comp v) {
+        __asm__("" : "+v"(v));
+        return __builtin_bit_cast(unsigned short, (_Float16)v);
+    }
     __device__ static elem enc_d(double v) { return __builtin_bit_cast(unsigned short, (_Float16)v); }
 };
 

@@ -31,6 +31,7 @@ struct Kc {
 
 template <bool SPLIT, typename CT>
 __device__ __forceinline__ CT mulk(CT x, Kc<CT> k) {
+#pragma clang fp contract(off)
     if constexpr (SPLIT)
         return fma(k.hi, x, k.lo * x);
     else
@@ -96,10 +97,22 @@ constexpr bool has_shell(int sh) {
 // fma with a split constant: k t + c with ~2^-48 relative error in the constant.
 template <bool SPLIT, typename CT>
 __device__ __forceinline__ CT fmak(Kc<CT> k, CT t, CT c) {
+#pragma clang fp contract(off)
     if constexpr (SPLIT)
         return fma(k.hi, t, fma(k.lo, t, c));
     else
         return fma(k.hi, t, c);
+}
+
+// acc + k x: one fma with a plain constant; with a split one the product is formed first
+// (as mulk) and then added, so that the sum sees the same product in both cases.
+template <bool SPLIT, typename CT>
+__device__ __forceinline__ CT addk(CT acc, CT x, Kc<CT> k) {
+#pragma clang fp contract(off)
+    if constexpr (SPLIT)
+        return acc + mulk<SPLIT>(x, k);
+    else
+        return fma(k.hi, x, acc);
 }
 
 // ------------------------------------------------------------------ collision
@@ -109,6 +122,10 @@ __device__ __forceinline__ CT fmak(Kc<CT> k, CT t, CT c) {
 // HALF: tau = 1/2 (keep = -1), the paper's second-order choice: s_i <- w t_i - s_i, one fma.
 template <class VS, typename CT, bool SPLIT, bool SKIP0 = false, bool HALF = false>
 __device__ __forceinline__ void collide(const StepCoef<CT, VS::Q> &k, CT (&s)[VS::Q]) {
+    // No implicit contraction: every fused multiply-add below is written out, so the result
+    // does not depend on how the compiler schedules the surrounding kernel (all step variants,
+    // the in-place step and the boundary recompute give the same bits for the same inputs).
+#pragma clang fp contract(off)
     constexpr int i0 = SKIP0 ? 1 : 0;
     // Sums start from the first term (not from 0 + term, which IEEE arithmetic cannot drop).
     CT sum[kShells] = {}, jx[kShells] = {}, jy[kShells] = {}, jz[kShells] = {};
@@ -135,25 +152,27 @@ __device__ __forceinline__ void collide(const StepCoef<CT, VS::Q> &k, CT (&s)[VS
 #pragma unroll
     for (int sh = 0; sh < kShells; ++sh) {
         if (!has_shell<VS, SKIP0>(sh)) continue;
-        const CT r = mulk<SPLIT>(sum[sh], k.dec[sh]), ee = mulk<SPLIT>(sum[sh], k.edec[sh]);
-        rho = first ? r : rho + r;
-        e = first ? ee : e + ee;
+        rho = first ? mulk<SPLIT>(sum[sh], k.dec[sh]) : addk<SPLIT>(rho, sum[sh], k.dec[sh]);
+        e = first ? mulk<SPLIT>(sum[sh], k.edec[sh]) : addk<SPLIT>(e, sum[sh], k.edec[sh]);
         first = false;
         if (sh == 0) continue;  // the rest velocity carries no momentum
-        const CT ux = mulk<SPLIT>(jx[sh], k.bu[sh]);
-        const CT uy = VS::D >= 2 ? mulk<SPLIT>(jy[sh], k.bu[sh]) : (CT)0;
-        const CT uz = VS::D >= 3 ? mulk<SPLIT>(jz[sh], k.bu[sh]) : (CT)0;
-        Ux = firstu ? ux : Ux + ux;
-        Uy = firstu ? uy : Uy + uy;
-        Uz = firstu ? uz : Uz + uz;
+        if (firstu) {
+            Ux = mulk<SPLIT>(jx[sh], k.bu[sh]);
+            if (VS::D >= 2) Uy = mulk<SPLIT>(jy[sh], k.bu[sh]);
+            if (VS::D >= 3) Uz = mulk<SPLIT>(jz[sh], k.bu[sh]);
+        } else {
+            Ux = addk<SPLIT>(Ux, jx[sh], k.bu[sh]);
+            if (VS::D >= 2) Uy = addk<SPLIT>(Uy, jy[sh], k.bu[sh]);
+            if (VS::D >= 3) Uz = addk<SPLIT>(Uz, jz[sh], k.bu[sh]);
+        }
         firstu = false;
     }
-    const CT theta = mulk<SPLIT>(e, k.gm1_rho0) - mulk<SPLIT>(rho, k.theta0_rho0);
-    const CT A = mulk<SPLIT>(rho, k.a1) + mulk<SPLIT>(theta, k.a2);
-    const CT C = mulk<SPLIT>(rho, k.c1) + mulk<SPLIT>(theta, k.c2);
+    const CT theta = addk<SPLIT>(-mulk<SPLIT>(rho, k.theta0_rho0), e, k.gm1_rho0);
+    const CT A = addk<SPLIT>(mulk<SPLIT>(rho, k.a1), theta, k.a2);
+    const CT C = addk<SPLIT>(mulk<SPLIT>(rho, k.c1), theta, k.c2);
     CT As[kShells];
 #pragma unroll
-    for (int sh = 0; sh < kShells; ++sh) As[sh] = sh == 0 ? A : A + (CT)(0.5 * sh) * C;  // 1/2, 1, 3/2: exact
+    for (int sh = 0; sh < kShells; ++sh) As[sh] = sh == 0 ? A : fma((CT)(0.5 * sh), C, A);  // 1/2, 1, 3/2: exact
 #pragma unroll
     for (int i = i0; i < VS::Q; ++i) {
         const int sh = VS::c2(i);
@@ -166,8 +185,10 @@ __device__ __forceinline__ void collide(const StepCoef<CT, VS::Q> &k, CT (&s)[VS
         if (VS::cz(i) < 0) t -= Uz;
         if constexpr (HALF)
             s[i] = fmak<SPLIT>(k.w[sh], t, -s[i]);
-        else
+        else if constexpr (SPLIT)  // both products whole before the sum: the lo parts must not be lost in s
             s[i] = mulk<SPLIT>(s[i], k.keep) + mulk<SPLIT>(t, k.w[sh]);
+        else
+            s[i] = fmak<SPLIT>(k.w[sh], t, mulk<SPLIT>(s[i], k.keep));
     }
 }
 
@@ -230,7 +251,7 @@ __device__ __forceinline__ double dpp_move(double v) {
 // periodic wrap; otherwise the first lane and the last active lane load their neighbour
 // element directly.  Waves walk the chunks grid-stride (one pass when the grid covers them).
 // tune: bit 0 = non-temporal stores, bit 1 = non-temporal loads.
-enum : unsigned { kTuneNtStore = 1u, kTuneNtLoad = 2u, kTunePersistent = 4u };
+enum : unsigned { kTuneNtStore = 1u, kTuneNtLoad = 2u, kTunePersistent = 4u, kTuneInPlace = 32u };
 
 template <class ST, int VEC>
 __device__ __forceinline__ void loadv(const typename ST::elem *p, typename ST::comp (&v)[VEC], bool nt) {
@@ -432,6 +453,95 @@ __global__ __launch_bounds__(256) void step_lds(const typename ST::elem *__restr
     for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = enc_io<ST, ST::has_raw>(s[i]);
 }
 
+// ------------------------------------------------------------------ in-place streaming
+// One buffer instead of two (the "AA" pattern of in-place streaming).  The buffer holds the
+// post-collision state g*(t) in one of two layouts, alternating step by step:
+//   swapped (S): g*_i(x) in slot opposite(i) of cell x;
+//   pushed  (P): g*_i(x) in slot i of cell x + c_i (the value cell x + c_i pulls next).
+// From P a cell reads its incoming values from its own slots, collides, and writes S into the
+// same slots; from S it reads slot opposite(i) of x - c_i and writes slot i of x + c_i, which is
+// the same set of locations.  Either way every cell reads and writes only its own set, so the
+// update is race-free in place.  The rest population (c = 0) never moves.
+template <class VS>
+__host__ __device__ constexpr int opposite(int i) {
+    for (int j = 0; j < VS::Q; ++j)
+        if (VS::c[j][0] == -VS::c[i][0] && VS::c[j][1] == -VS::c[i][1] && VS::c[j][2] == -VS::c[i][2]) return j;
+    return -1;
+}
+
+template <class VS>
+constexpr bool every_velocity_has_opposite() {
+    for (int i = 0; i < VS::Q; ++i)
+        if (opposite<VS>(i) < 0) return false;
+    return true;
+}
+
+enum : int { kLayoutPlain = 0, kLayoutSwapped = 1, kLayoutPushed = 2 };
+
+// Where population i of cell (x, y, z) lives in a state buffer of the given layout.
+struct Layout {
+    int mode;
+    int nx, ny, nz;
+};
+
+template <class VS>
+__device__ __forceinline__ size_t pop_index(const Layout &L, int i, size_t N, size_t cell, int x, int y, int z) {
+    if (L.mode == kLayoutSwapped) return (size_t)opposite<VS>(i) * N + cell;
+    if (L.mode == kLayoutPushed) {
+        const int xs = wrap_add(x, VS::cx(i), L.nx);
+        const int ys = wrap_add(y, VS::cy(i), L.ny);
+        const int zs = wrap_add(z, VS::cz(i), L.nz);
+        return (size_t)i * N + ((size_t)zs * L.ny + ys) * L.nx + xs;
+    }
+    return (size_t)i * N + cell;
+}
+template <class VS>
+__device__ __forceinline__ size_t pop_index(const Layout &L, int i, size_t N, size_t cell) {
+    if (L.mode != kLayoutPushed) return pop_index<VS>(L, i, N, cell, 0, 0, 0);
+    const int x = (int)(cell % (size_t)L.nx);
+    const size_t r = cell / (size_t)L.nx;
+    return pop_index<VS>(L, i, N, cell, x, (int)(r % (size_t)L.ny), (int)(r / (size_t)L.ny));
+}
+
+// One in-place step: FROM_S = the buffer holds layout S (and leaves P), else P -> S.
+template <class VS, class ST, bool SKIP0, bool HALF, bool FROM_S>
+__global__ __launch_bounds__(256) void step_inplace(typename ST::elem *__restrict__ A, int nx, int ny, int nz, size_t N,
+                                                    StepCoef<typename ST::comp, VS::Q> k) {
+    static_assert(every_velocity_has_opposite<VS>(), "in-place streaming needs a symmetric velocity set");
+    using CT = typename ST::comp;
+    const size_t cell = (size_t)blockIdx.x * 256u + threadIdx.x;
+    if (cell >= N) return;
+    const int x = (int)(cell % (size_t)nx);
+    const size_t r = cell / (size_t)nx;
+    const int y = (int)(r % (size_t)ny);
+    const int z = (int)(r / (size_t)ny);
+    CT s[VS::Q];
+    s[0] = 0;
+#pragma unroll
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) {
+        size_t at = (size_t)i * N + cell;
+        if (FROM_S) {
+            const int xs = wrap_add(x, -VS::cx(i), nx);
+            const int ys = wrap_add(y, -VS::cy(i), ny);
+            const int zs = wrap_add(z, -VS::cz(i), nz);
+            at = (size_t)opposite<VS>(i) * N + ((size_t)zs * ny + ys) * nx + xs;
+        }
+        s[i] = dec_io<ST, ST::has_raw>(A[at]);
+    }
+    collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, s);
+#pragma unroll
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) {
+        size_t at = (size_t)opposite<VS>(i) * N + cell;
+        if (FROM_S) {
+            const int xs = wrap_add(x, VS::cx(i), nx);
+            const int ys = wrap_add(y, VS::cy(i), ny);
+            const int zs = wrap_add(z, VS::cz(i), nz);
+            at = (size_t)i * N + ((size_t)zs * ny + ys) * nx + xs;
+        }
+        A[at] = enc_io<ST, ST::has_raw>(s[i]);
+    }
+}
+
 // ------------------------------------------------------------------ initial state
 // g_i(0, x) = g_i^eq(rho'(x), u'(x), theta'(x)) in FP64, then encoded to storage.
 template <class VS, class ST>
@@ -439,7 +549,7 @@ __global__ __launch_bounds__(256) void init_equilibrium(const double *__restrict
                                                         const double *__restrict__ theta,
                                                         typename ST::elem *__restrict__ dst,
                                                         typename ST::elem *__restrict__ rest_copy, size_t N,
-                                                        FieldCoef<VS::Q> k) {
+                                                        FieldCoef<VS::Q> k, Layout lay) {
     const size_t cell = (size_t)blockIdx.x * 256u + threadIdx.x;
     if (cell >= N) return;
     const double r = rho[cell], th = theta[cell];
@@ -453,7 +563,7 @@ __global__ __launch_bounds__(256) void init_equilibrium(const double *__restrict
         const double cu = VS::cx(i) * ux + VS::cy(i) * uy + VS::cz(i) * uz;
         const double geq = k.f[i] * (A + k.b * cu + 0.5 * VS::c2(i) * C);
         const typename ST::elem v = ST::enc_d(k.enc[i] * geq);
-        dst[(size_t)i * N + cell] = v;
+        dst[pop_index<VS>(lay, i, N, cell)] = v;
         if (i == 0 && rest_copy) rest_copy[cell] = v;  // the other buffer's rest plane
     }
 }
@@ -465,7 +575,7 @@ __global__ __launch_bounds__(256) void init_region(const double *__restrict__ rh
                                                    typename ST::elem *__restrict__ dst,
                                                    typename ST::elem *__restrict__ rest_copy, int nx, int ny, size_t N,
                                                    int ox, int oy, int oz, int sx, int sy, int sz,
-                                                   FieldCoef<VS::Q> k) {
+                                                   FieldCoef<VS::Q> k, Layout lay) {
     const size_t cell = (size_t)blockIdx.x * 256u + threadIdx.x;
     if (cell >= N) return;
     const int x = (int)(cell % nx) - ox;
@@ -488,7 +598,7 @@ __global__ __launch_bounds__(256) void init_region(const double *__restrict__ rh
         const double cu = VS::cx(i) * ux + VS::cy(i) * uy + VS::cz(i) * uz;
         const double geq = k.f[i] * (A + k.b * cu + 0.5 * VS::c2(i) * C);
         const typename ST::elem v = ST::enc_d(k.enc[i] * geq);
-        dst[(size_t)i * N + cell] = v;
+        dst[pop_index<VS>(lay, i, N, cell)] = v;
         if (i == 0 && rest_copy) rest_copy[cell] = v;
     }
 }
@@ -574,11 +684,11 @@ __global__ __launch_bounds__(256) void energy_partials(const typename ST::elem *
 template <class VS, class ST>
 __device__ __forceinline__ void cell_moments(const typename ST::elem *__restrict__ src, size_t N, size_t cell,
                                              const FieldCoef<VS::Q> &k, double &rho, double (&u)[3], double &theta,
-                                             double &p) {
+                                             double &p, const Layout &lay) {
     double r = 0, jx = 0, jy = 0, jz = 0, e = 0;
 #pragma unroll
     for (int i = 0; i < VS::Q; ++i) {
-        const double g = k.dec[i] * (double)ST::dec(src[(size_t)i * N + cell]);
+        const double g = k.dec[i] * (double)ST::dec(src[pop_index<VS>(lay, i, N, cell)]);
         r += g;
         jx += VS::cx(i) * g;
         jy += VS::cy(i) * g;
@@ -596,11 +706,11 @@ __device__ __forceinline__ void cell_moments(const typename ST::elem *__restrict
 template <class VS, class ST, typename OT>
 __global__ __launch_bounds__(256) void moments_kernel(const typename ST::elem *__restrict__ src, size_t N,
                                                       FieldCoef<VS::Q> k, OT *__restrict__ p, OT *__restrict__ u,
-                                                      OT *__restrict__ rho, OT *__restrict__ theta) {
+                                                      OT *__restrict__ rho, OT *__restrict__ theta, Layout lay) {
     const size_t cell = (size_t)blockIdx.x * 256u + threadIdx.x;
     if (cell >= N) return;
     double r, uu[3], th, pp;
-    cell_moments<VS, ST>(src, N, cell, k, r, uu, th, pp);
+    cell_moments<VS, ST>(src, N, cell, k, r, uu, th, pp, lay);
     if (p) p[cell] = (OT)pp;
     if (rho) rho[cell] = (OT)r;
     if (theta) theta[cell] = (OT)th;
@@ -615,7 +725,7 @@ __global__ __launch_bounds__(256) void moments_region_kernel(const typename ST::
                                                              int nx, int ny, int ox, int oy, int oz, int sx, int sy,
                                                              int sz, FieldCoef<VS::Q> k, OT *__restrict__ p,
                                                              OT *__restrict__ u, OT *__restrict__ rho,
-                                                             OT *__restrict__ theta) {
+                                                             OT *__restrict__ theta, Layout lay) {
     const size_t Ns = (size_t)sx * sy * sz;
     const size_t sc = (size_t)blockIdx.x * 256u + threadIdx.x;
     if (sc >= Ns) return;
@@ -624,7 +734,7 @@ __global__ __launch_bounds__(256) void moments_region_kernel(const typename ST::
     const int y = (int)(r % sy), z = (int)(r / sy);
     const size_t cell = ((size_t)(z + oz) * ny + (y + oy)) * nx + (x + ox);
     double rr, uu[3], th, pp;
-    cell_moments<VS, ST>(src, N, cell, k, rr, uu, th, pp);
+    cell_moments<VS, ST>(src, N, cell, k, rr, uu, th, pp, lay);
     if (p) p[sc] = (OT)pp;
     if (rho) rho[sc] = (OT)rr;
     if (theta) theta[sc] = (OT)th;
@@ -638,12 +748,13 @@ __global__ __launch_bounds__(256) void moments_region_kernel(const typename ST::
 template <class VS, class ST>
 __global__ __launch_bounds__(256) void error_partials(const typename ST::elem *__restrict__ src, size_t N,
                                                       FieldCoef<VS::Q> k, const double *__restrict__ ref_p,
-                                                      const double *__restrict__ ref_u, double *__restrict__ part) {
+                                                      const double *__restrict__ ref_u, double *__restrict__ part,
+                                                      Layout lay) {
     double v[6] = {0, 0, 0, 0, 0, 0};
     const bool is_max[6] = {false, false, true, false, false, true};
     for (size_t cell = (size_t)blockIdx.x * 256u + threadIdx.x; cell < N; cell += (size_t)gridDim.x * 256u) {
         double r, uu[3], th, pp;
-        cell_moments<VS, ST>(src, N, cell, k, r, uu, th, pp);
+        cell_moments<VS, ST>(src, N, cell, k, r, uu, th, pp, lay);
         const double dp = pp - ref_p[cell];
         v[0] += dp * dp;
         v[1] += ref_p[cell] * ref_p[cell];
@@ -691,7 +802,7 @@ __global__ __launch_bounds__(256) void scale_partials(const double *__restrict__
 // ------------------------------------------------------------------ import / export
 template <class VS, class ST>
 __global__ __launch_bounds__(256) void export_f64(const typename ST::elem *__restrict__ src, size_t N,
-                                                  FieldCoef<VS::Q> k, double *__restrict__ g) {
+                                                  FieldCoef<VS::Q> k, double *__restrict__ g, Layout lay) {
     const size_t idx = (size_t)blockIdx.x * 256u + threadIdx.x;
     if (idx >= (size_t)VS::Q * N) return;
     const int i = (int)(idx / N);
@@ -699,13 +810,13 @@ __global__ __launch_bounds__(256) void export_f64(const typename ST::elem *__res
 #pragma unroll
     for (int j = 1; j < VS::Q; ++j)
         if (j == i) d = k.dec[j];
-    g[idx] = d * (double)ST::dec(src[idx]);
+    g[idx] = d * (double)ST::dec(src[pop_index<VS>(lay, i, N, idx - (size_t)i * N)]);
 }
 
 template <class VS, class ST>
 __global__ __launch_bounds__(256) void import_f64(const double *__restrict__ g, size_t N, FieldCoef<VS::Q> k,
                                                   typename ST::elem *__restrict__ dst,
-                                                  typename ST::elem *__restrict__ rest_copy) {
+                                                  typename ST::elem *__restrict__ rest_copy, Layout lay) {
     const size_t idx = (size_t)blockIdx.x * 256u + threadIdx.x;
     if (idx >= (size_t)VS::Q * N) return;
     const int i = (int)(idx / N);
@@ -714,7 +825,7 @@ __global__ __launch_bounds__(256) void import_f64(const double *__restrict__ g, 
     for (int j = 1; j < VS::Q; ++j)
         if (j == i) e = k.enc[j];
     const typename ST::elem v = ST::enc_d(e * g[idx]);
-    dst[idx] = v;
+    dst[pop_index<VS>(lay, i, N, idx - (size_t)i * N)] = v;
     if (i == 0 && rest_copy) rest_copy[idx] = v;
 }
 

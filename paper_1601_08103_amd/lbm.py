@@ -18,7 +18,7 @@ LATTICES = {"D1Q3": 0, "D2Q5": 1, "D2Q9": 2, "D3Q7": 3, "D3Q9": 4, "D3Q13": 5, "
             "D2Q5_DIA": 7, "D3Q7_DIA": 8}
 STORAGES = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "i16": 4, "e3m12": 5}
 ELEM_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "i16": 2, "e3m12": 2}
-TUNE = {"nt_store": 1, "nt_load": 2, "persistent": 4, "full_rest": 8, "closure_stream": 16}
+TUNE = {"nt_store": 1, "nt_load": 2, "persistent": 4, "full_rest": 8, "closure_stream": 16, "in_place": 32}
 VARIANTS = {"auto": 0, "generic": 1, "dpp": 2, "lds": 3, "dpp2": 4}
 BCS = {"periodic": 0, "zero": 1, "copy": 2, "sponge": 3, "mlp": 4}
 
@@ -313,7 +313,8 @@ class Solver:
         self.scratch_bytes = lbm_lee_scratch_bytes(self.desc)
         dev = torch.device("cuda")
         self.pop_a = torch.empty(self.state_bytes, dtype=torch.uint8, device=dev)
-        self.pop_b = torch.empty(self.state_bytes, dtype=torch.uint8, device=dev)
+        in_place = bool(int(tune) & TUNE["in_place"])
+        self.pop_b = None if in_place else torch.empty(self.state_bytes, dtype=torch.uint8, device=dev)
         self.scratch = torch.empty(self.scratch_bytes, dtype=torch.uint8, device=dev)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         if rho is None and u is None and theta is None:  # the state at rest
@@ -321,7 +322,8 @@ class Solver:
         else:
             self._keep = self._fields(rho, u, theta)  # the init kernel may still be reading them
             ptrs = tuple(a.data_ptr() for a in self._keep)
-        self.h = lbm_lee_init(self.desc, self.pop_a.data_ptr(), self.pop_b.data_ptr(), self.state_bytes, *ptrs,
+        self.h = lbm_lee_init(self.desc, self.pop_a.data_ptr(),
+                              self.pop_b.data_ptr() if self.pop_b is not None else None, self.state_bytes, *ptrs,
                               self.scratch.data_ptr(), self.scratch_bytes, self.stream.cuda_stream)
 
     def _fields(self, rho, u, theta):

@@ -73,6 +73,11 @@ def embed(torch, fields, L, E, D):
     return R, U, T
 
 
+def judge_solver(lattice, storage, E, D):
+    """The periodic judge run, streamed in place (one population buffer: half the memory)."""
+    return lbm.Solver(lattice, storage, (E,) * D, None, None, None, tune=lbm.TUNE["in_place"])
+
+
 # ---------------------------------------------------------------- training data
 def generate(lattice="D2Q9", L=512, E=1536, runs=100, steps=1024, every=8, nodes=256, seed=0, storage="f32",
              init="pulses"):
@@ -91,7 +96,7 @@ def generate(lattice="D2Q9", L=512, E=1536, runs=100, steps=1024, every=8, nodes
     st = torch.cuda.current_stream().cuda_stream
     k = 0
     t0 = time.time()
-    ext = lbm.Solver(lattice, storage, (E,) * D, None, None, None)
+    ext = judge_solver(lattice, storage, E, D)
     org = [(E - L) // 2] * D
     for r in range(runs):
         ext.reinit_region(org, (L,) * D, *initial_fields(init, rng, info, L, D))
@@ -132,7 +137,7 @@ def generate_closed_loop(lattice, params, L=512, E=1536, runs=100, steps=1024, e
     rng = np.random.default_rng(seed)
     st = torch.cuda.current_stream().cuda_stream
     P = torch.as_tensor(np.asarray(params, dtype=np.float32)).cuda()
-    ext = lbm.Solver(lattice, storage, (E,) * D, None, None, None)
+    ext = judge_solver(lattice, storage, E, D)
     box = lbm.Solver(lattice, storage, (L,) * D, None, None, None, bc="mlp")
     box.set_closure(P)
     k = 0
@@ -250,7 +255,7 @@ def reflection(lattice, closure, fields, L=512, E=1536, steps=1024, every=8, par
         box.set_closure(params)
     own_ext = ext is None
     if own_ext:
-        ext = lbm.Solver(lattice, ext_storage, (E,) * D, None, None, None)
+        ext = judge_solver(lattice, ext_storage, E, D)
     oe = (E - L) // 2
     ext.reinit_region([oe] * D, (L,) * D, *fields)
     st = torch.cuda.current_stream().cuda_stream
@@ -381,7 +386,7 @@ def main(argv=None):
     rng = np.random.default_rng(10_000 + args.seed)  # held out: training uses seeds below 10000
     closures = [c for c in args.closures.split(",") if c and (c != "mlp" or P is not None)]
     Rs = {c: [] for c in closures}
-    ext = lbm.Solver(args.lattice, args.ext_storage, (args.E,) * D, None, None, None)
+    ext = judge_solver(args.lattice, args.ext_storage, args.E, D)
     for k in range(args.seeds):
         fields = initial_fields(args.init, rng, info, args.L, D)
         for c in closures:
