@@ -57,16 +57,16 @@ def parse():
 def kernel_source_hash() -> str:
     """Hash of the sources of the step kernels (the device code the counters measured)."""
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "codec.hpp", "velsets.hpp"):
+    for f in ("kernels.hpp", "codec.hpp", "velsets.hpp", "temporal.hpp"):
         with open(os.path.join(ROOT, "paper_1601_08103_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_counters(storage: str, n: int):
+def traffic_from_counters(storage: str, n: int, variant: str):
     """HBM bytes per launch measured with rocprofv3 counters, if they were taken on the current
     kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", f"traffic_step_d3q7_{n}_{storage}.md")
+    path = os.path.join(ROOT, "profiles", f"traffic_step_{variant}_d3q7_{n}_{storage}.md")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -228,13 +228,20 @@ def main():
         return (float(torch.linalg.vector_norm(p - p_ref) / torch.linalg.vector_norm(p_ref)),
                 float(torch.linalg.vector_norm(uu - u_ref) / torch.linalg.vector_norm(u_ref)))
 
+    def steps_per_launch(variant):
+        # the two-step variant reads and writes the state once per launch of two steps
+        return 2 if variant == "tb2" else 1
+
     storage_modes = {}
     for mode, r in results.items():
         mlups = N * K / (r["ms"] / 1e3) / 1e6
-        gbs = mlups * r["bpu"] / 1e3
+        spl = steps_per_launch(r["variant"])
+        # algorithmic HBM bytes per launch (one read and one write of the moving populations)
+        # over the time per launch
+        gbs = N * r["bpu"] / (r["ms"] / K * spl / 1e3) / 1e9
         ep, eu = rel(mode)
         storage_modes[mode] = dict(MLUPS=round(mlups, 1), ms_per_step=round(r["ms"] / K, 5),
-                                   bytes_per_update=r["bpu"], GBs=round(gbs, 1),
+                                   bytes_per_update=r["bpu"], steps_per_launch=spl, GBs=round(gbs, 1),
                                    frac_peak_hbm=round(gbs / PEAK_HBM_GBS, 4),
                                    rel_l2_p_vs_f64=ep, rel_l2_u_vs_f64=eu, store_scale=r["scale"],
                                    variant=r["variant"])
@@ -261,13 +268,17 @@ def main():
     main_mode = storage_modes[args.storage]
     ms_step = results[args.storage]["ms"] / K
     bpu = results[args.storage]["bpu"]
-    achieved = N * bpu / (ms_step / 1e3) / 1e9
-    traffic = traffic_from_counters(args.storage, n)
+    variant = results[args.storage]["variant"]
+    spl = steps_per_launch(variant)
+    launch_ms = ms_step * spl
+    achieved = N * bpu / (launch_ms / 1e3) / 1e9
+    traffic = traffic_from_counters(args.storage, n, variant)
+    what = ("two fused pull-stream/collide steps per launch" if spl == 2 else "fused pull-stream/collide")
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
-                    kernel=f"step_{results[args.storage]['variant']}<D3Q7,{args.storage}> (fused pull-stream/collide)",
-                    algorithmic_bytes_per_launch=N * bpu, frac_of_copy=round(achieved / copy_gbs, 4),
-                    copy_GBs=round(copy_gbs, 1))
+                    kernel=f"step_{variant}<D3Q7,{args.storage}> ({what})", steps_per_launch=spl,
+                    launch_ms=round(launch_ms, 5), algorithmic_bytes_per_launch=N * bpu,
+                    frac_of_copy=round(achieved / copy_gbs, 4), copy_GBs=round(copy_gbs, 1))
 
     nrbc_result = None if args.no_nrbc else nrbc_leg()
 

@@ -85,6 +85,12 @@ typedef int32_t lbm_status;
                                    /* eager launches add two event calls per step)                */
 #define LBM_TUNE_IN_PLACE 32  /* one population buffer instead of two (periodic box only; pop_b */
                               /* of lbm_lee_init may be NULL); see "In-place streaming" below   */
+/* LBM_VARIANT_TB2: segment length along the march axis (z in 3D, y in 2D).  Without these bits
+ * it is chosen per launch: the length in [4, 64] that minimises (rounds of resident blocks) x
+ * (planes per block), from the kernel's occupancy on the device. */
+#define LBM_TUNE_TB_SEGMENT_8 64
+#define LBM_TUNE_TB_SEGMENT_16 128
+#define LBM_TUNE_TB_SEGMENT_32 192
 
 /* Boundary of the box.  The paper's scheme is periodic; the open closures are not in the
  * paper (it leaves boundary conditions to future work) and are defined here.  For a cell x
@@ -108,12 +114,22 @@ typedef int32_t lbm_status;
 
 /* Step kernel variant.  All variants run the same per-cell arithmetic, so their results are
  * bitwise identical; they differ only in how the streamed values are gathered. */
-#define LBM_VARIANT_AUTO 0    /* the fastest measured variant for the storage mode          */
+#define LBM_VARIANT_AUTO 0    /* the fastest measured variant: TB2 on periodic 2D/3D boxes of */
+                              /* >= 2^20 cells where it is supported; else GENERIC for 4- and  */
+                              /* 8-byte storage, DPP/DPP2/GENERIC (by nx) for 2-byte storage  */
 #define LBM_VARIANT_GENERIC 1 /* one thread per cell, per-element wrapped gathers            */
 #define LBM_VARIANT_DPP 2     /* 4 cells per lane, aligned vector loads, x shift by DPP;   */
                               /* needs nx % 4 == 0                                          */
 #define LBM_VARIANT_LDS 3     /* one thread per cell, x-shifted rows staged in LDS + halo   */
 #define LBM_VARIANT_DPP2 4    /* 2 cells per lane, as DPP; needs nx % 2 == 0                 */
+/* Two steps per launch (temporal blocking), periodic 2D and 3D boxes of any extents: a block
+ * owns a tile of 64 cells along x (and TY along y in 3D) and marches along the last axis, doing
+ * step t+1 on the tile and a one-cell ring around it (state t read from HBM) and then step t+2
+ * on the tile (state t+1 from LDS and registers), so the state crosses HBM once per two steps.
+ * An odd step count ends with one one-step launch.  LBM_E_UNSUPPORTED for open boxes, 1D sets
+ * and sets whose in-plane LDS rings do not fit 64 KB at TY = 4 (D3Q19 with FP32, and D3Q9,
+ * D3Q13 and D3Q19 with FP64). */
+#define LBM_VARIANT_TB2 5
 
 typedef struct lbm_lee_desc {
     int32_t lattice;     /* LBM_D1Q3 ...                                                    */

@@ -14,6 +14,7 @@
 #include "kernels.hpp"
 #include "nrbc.hpp"
 #include "open_bc.hpp"
+#include "temporal.hpp"
 #include "tables.hpp"
 
 using namespace lbm;
@@ -116,6 +117,14 @@ bool shell_uniform(const LatticeTable &t) {
     return true;
 }
 
+int tb2_tile_y(int lattice, int storage);  // 0: the two-step variant has no tile shape
+
+// One plane across the march axis (x by y in 3D, a row in 2D) in bytes of one population.
+bool tb2_plane_fits(const lbm_lee_desc *d, int D) {
+    const double plane = (double)d->n[0] * (D == 3 ? (double)d->n[1] : 1.0) * (double)elem_size(d->storage);
+    return plane < 4294967296.0;
+}
+
 lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
     if (!d) return fail(LBM_E_INVALID, "desc is NULL");
     if (!build_lattice(d->lattice, tab)) return fail(LBM_E_INVALID, "unknown lattice id %d", d->lattice);
@@ -129,8 +138,17 @@ lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
     if (N * tab->Q > 9.0e18 / 8.0) return fail(LBM_E_INVALID, "domain too large");
     if ((double)d->n[1] * (double)d->n[2] * 16.0 > 4.0e9) return fail(LBM_E_INVALID, "too many rows (ny * nz)");
     if (!(d->tau >= 0.5) || !std::isfinite(d->tau)) return fail(LBM_E_INVALID, "tau must be finite and >= 1/2 (got %g)", d->tau);
-    if (d->variant < LBM_VARIANT_AUTO || d->variant > LBM_VARIANT_DPP2) return fail(LBM_E_INVALID, "unknown variant %d", d->variant);
-    if (d->tune < 0 || d->tune > 63) return fail(LBM_E_INVALID, "unknown tune bits 0x%x", d->tune);
+    if (d->variant < LBM_VARIANT_AUTO || d->variant > LBM_VARIANT_TB2) return fail(LBM_E_INVALID, "unknown variant %d", d->variant);
+    if (d->tune < 0 || d->tune > 255) return fail(LBM_E_INVALID, "unknown tune bits 0x%x", d->tune);
+    if (d->variant == LBM_VARIANT_TB2) {
+        if (d->bc != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "the two-step variant needs the periodic box");
+        if (tab->D < 2) return fail(LBM_E_UNSUPPORTED, "the two-step variant needs a 2D or 3D lattice");
+        if (tb2_tile_y(d->lattice, d->storage) == 0)
+            return fail(LBM_E_UNSUPPORTED, "the two-step variant's LDS rings for lattice %d do not fit with this storage",
+                        d->lattice);
+        if (!tb2_plane_fits(d, tab->D))
+            return fail(LBM_E_UNSUPPORTED, "the two-step variant addresses a plane with 32-bit byte offsets (< 4 GiB)");
+    }
     if (d->tune & kTuneInPlace) {
         if (d->bc != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "in-place streaming needs the periodic box");
         if (d->variant != LBM_VARIANT_AUTO && d->variant != LBM_VARIANT_GENERIC)
@@ -182,6 +200,16 @@ lbm_status visit(int lattice, int storage, F &&f) {
         case LBM_D3Q19: return visit_storage<VS_D3Q19>(storage, f);
         default: return fail(LBM_E_INVALID, "unknown lattice id %d", lattice);
     }
+}
+
+int tb2_tile_y(int lattice, int storage) {
+    int ty = 0;
+    visit(lattice, storage, [&](auto vs, auto sto) -> lbm_status {
+        using VS = decltype(vs);
+        if constexpr (VS::D >= 2) ty = TbShape<VS, decltype(sto)>::TY;
+        return LBM_OK;
+    });
+    return ty;
 }
 
 template <int Q>
@@ -331,12 +359,18 @@ lbm_status launch_check() {
     return LBM_OK;
 }
 
-// AUTO: measured on MI355X (D3Q7, 256^3): for 4- and 8-byte storage the one-cell-per-thread
-// gather has the highest occupancy and beats the vectorised variants; 2-byte storage needs
-// wider per-lane accesses.
+// AUTO: measured on MI355X (D3Q7, 256^3): the two-step variant beats every one-step kernel
+// on large periodic boxes (it moves the state through HBM once per two steps); below a
+// million cells the launches are short and the one-step kernels win.  Of the one-step kernels
+// the one-cell-per-thread gather has the highest occupancy and wins for 4- and 8-byte storage;
+// 2-byte storage needs wider per-lane accesses.
 int resolve_variant(const lbm_lee *h) {
     if (h->inplace) return LBM_VARIANT_GENERIC;  // the in-place kernels are one thread per cell
     if (h->desc.variant != LBM_VARIANT_AUTO) return h->desc.variant;
+    // periodic boxes of a million cells and more: two steps per launch, for every storage mode
+    if (h->desc.bc == LBM_BC_PERIODIC && h->tab.D >= 2 && h->N >= ((size_t)1 << 20) &&
+        tb2_tile_y(h->desc.lattice, h->desc.storage) > 0 && tb2_plane_fits(&h->desc, h->tab.D))
+        return LBM_VARIANT_TB2;
     if (elem_size(h->desc.storage) >= 4) return LBM_VARIANT_GENERIC;
     if (h->nx % 4 == 0) return LBM_VARIANT_DPP;
     if (h->nx % 2 == 0) return LBM_VARIANT_DPP2;
@@ -693,6 +727,63 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
                 }
                 return LBM_OK;
             }
+            if (variant == LBM_VARIANT_TB2) {  // periodic box, two steps per launch
+                if constexpr (VS::D >= 2) {
+                    using SH = TbShape<VS, ST>;
+                    if constexpr (SH::TY > 0) {
+                        const int fx = h->nx, fy = VS::D == 3 ? h->ny : 1, fz = VS::D == 3 ? h->nz : h->ny;
+                        const long long tiles_x = (fx + kTbTx - 1) / kTbTx, tiles_y = (fy + SH::TY - 1) / SH::TY;
+                        auto fn = step_tb2<VS, ST, SK, HF, SH::TY, SH::NT, SH::WPE>;
+                        int sz = 16;
+                        const unsigned seg_bits = (tune >> 6) & 3u;
+                        if (seg_bits) {
+                            sz = 4 << seg_bits;  // 8, 16, 32
+                        } else {
+                            // a block's time is about proportional to the planes it computes
+                            // (sz + 2); the grid runs in ceil(blocks / resident slots) rounds
+                            int per_cu = 0;
+                            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, SH::NT, 0) !=
+                                    hipSuccess || per_cu <= 0)
+                                per_cu = 1;
+                            (void)hipGetLastError();
+                            const long long slots = (long long)std::max(h->cus, 1) * per_cu;
+                            long long best = -1;
+                            for (int cand = 4; cand <= 64; ++cand) {
+                                const long long g = tiles_x * tiles_y * ((fz + cand - 1) / cand);
+                                const long long cost = ((g + slots - 1) / slots) * (std::min(cand, fz) + 2);
+                                if (best < 0 || cost < best) {
+                                    best = cost;
+                                    sz = cand;
+                                }
+                            }
+                        }
+                        const long long blocks = tiles_x * tiles_y * ((fz + sz - 1) / sz);
+                        int64_t t = 0;
+                        for (; t + 2 <= nsteps; t += 2) {
+                            const E *src = static_cast<const E *>(h->buf[h->cur]);
+                            E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);
+                            fn<<<(unsigned)blocks, SH::NT, 0, st>>>(
+                                src, dst, fx, fy, fz, h->N, sz, (int)tiles_x, (int)tiles_y, k);
+                            lbm_status ls = launch_check();
+                            if (ls != LBM_OK) return ls;
+                            h->cur ^= 1;
+                            h->steps += 2;
+                        }
+                        if (t < nsteps) {  // odd count: one one-step launch
+                            const E *src = static_cast<const E *>(h->buf[h->cur]);
+                            E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);
+                            step_generic<VS, ST, SK, HF><<<blocks_for(h->N), 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz,
+                                                                                        h->N, k);
+                            lbm_status ls = launch_check();
+                            if (ls != LBM_OK) return ls;
+                            h->cur ^= 1;
+                            h->steps += 1;
+                        }
+                        return LBM_OK;
+                    }
+                }
+                return fail(LBM_E_UNSUPPORTED, "the two-step variant does not support this lattice and storage");
+            }
             for (int64_t t = 0; t < nsteps; ++t) {
                 const E *src = static_cast<const E *>(h->buf[h->cur]);
                 E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);
@@ -744,15 +835,13 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
             }
             return LBM_OK;
         };
-        // tau = 1/2 takes the one-fma relaxation; compiled for the 2-byte formats only, whose
-        // steps are bound by ALU work (the 4- and 8-byte steps are bound by memory traffic).
-        if constexpr (sizeof(E) == 2) {
-            if (h->desc.tau == 0.5) {
-                if constexpr (VS::rest_may_decouple) {
-                    if (h->skip0) return run(std::true_type{}, std::true_type{});
-                }
-                return run(std::false_type{}, std::true_type{});
+        // tau = 1/2 (keep = 1 - 1/tau = -1) takes the shorter relaxation s <- w t - s, which
+        // gives the same bits as the general form with keep = -1 in fewer operations.
+        if (h->desc.tau == 0.5) {
+            if constexpr (VS::rest_may_decouple) {
+                if (h->skip0) return run(std::true_type{}, std::true_type{});
             }
+            return run(std::false_type{}, std::true_type{});
         }
         if constexpr (VS::rest_may_decouple) {
             if (h->skip0) return run(std::true_type{}, std::false_type{});

@@ -119,7 +119,9 @@ __device__ __forceinline__ CT addk(CT acc, CT x, Kc<CT> k) {
 // SKIP0: the rest population (index 0) is left out: the host enables this only when the
 // equilibrium map leaves it invariant (E_00 = 1, E_0j = E_j0 = 0), in which case the moving
 // populations' equilibria do not depend on it either.
-// HALF: tau = 1/2 (keep = -1), the paper's second-order choice: s_i <- w t_i - s_i, one fma.
+// HALF: tau = 1/2 (keep = -1), the paper's second-order choice: s_i <- w t_i - s_i, one fma
+// (with split constants: the product w t_i formed as in the general form, then - s_i; the
+// same bits as keep s_i + w t_i with keep = -1).
 template <class VS, typename CT, bool SPLIT, bool SKIP0 = false, bool HALF = false>
 __device__ __forceinline__ void collide(const StepCoef<CT, VS::Q> &k, CT (&s)[VS::Q]) {
     // No implicit contraction: every fused multiply-add below is written out, so the result
@@ -183,7 +185,9 @@ __device__ __forceinline__ void collide(const StepCoef<CT, VS::Q> &k, CT (&s)[VS
         if (VS::cy(i) < 0) t -= Uy;
         if (VS::cz(i) > 0) t += Uz;
         if (VS::cz(i) < 0) t -= Uz;
-        if constexpr (HALF)
+        if constexpr (HALF && SPLIT)  // keep = -1 exactly: the same bits as the general form below
+            s[i] = mulk<SPLIT>(t, k.w[sh]) - s[i];
+        else if constexpr (HALF)
             s[i] = fmak<SPLIT>(k.w[sh], t, -s[i]);
         else if constexpr (SPLIT)  // both products whole before the sum: the lo parts must not be lost in s
             s[i] = mulk<SPLIT>(s[i], k.keep) + mulk<SPLIT>(t, k.w[sh]);

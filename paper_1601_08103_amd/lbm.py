@@ -18,8 +18,9 @@ LATTICES = {"D1Q3": 0, "D2Q5": 1, "D2Q9": 2, "D3Q7": 3, "D3Q9": 4, "D3Q13": 5, "
             "D2Q5_DIA": 7, "D3Q7_DIA": 8}
 STORAGES = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "i16": 4, "e3m12": 5}
 ELEM_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "i16": 2, "e3m12": 2}
-TUNE = {"nt_store": 1, "nt_load": 2, "persistent": 4, "full_rest": 8, "closure_stream": 16, "in_place": 32}
-VARIANTS = {"auto": 0, "generic": 1, "dpp": 2, "lds": 3, "dpp2": 4}
+TUNE = {"nt_store": 1, "nt_load": 2, "persistent": 4, "full_rest": 8, "closure_stream": 16, "in_place": 32,
+        "tb_segment_8": 64, "tb_segment_16": 128, "tb_segment_32": 192}
+VARIANTS = {"auto": 0, "generic": 1, "dpp": 2, "lds": 3, "dpp2": 4, "tb2": 5}
 BCS = {"periodic": 0, "zero": 1, "copy": 2, "sponge": 3, "mlp": 4}
 
 LBM_OK = 0
@@ -125,7 +126,7 @@ def make_desc(lattice: str, storage: str, shape, tau: float = 0.5, variant: str 
     for a in range(3):
         d.n[a] = dims[a]
     d.tau = float(tau)
-    d.variant = VARIANTS[variant]
+    d.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     d.tune = int(tune)
     d.store_scale = float(store_scale)
     d.bc = BCS[bc]

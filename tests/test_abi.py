@@ -75,10 +75,17 @@ def test_sizes(lattice, storage, shape, bpu):
     dict(lattice="D3Q7", storage="f16", shape=(8, 8, 8), store_scale=3.0),
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 6), variant="dpp"),
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 7), variant="dpp2"),
-    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), tune=64),
+    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), tune=256),
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), tune=32, bc="zero"),    # in place: periodic only
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), tune=32, variant="dpp"),  # in place: own kernels
     dict(lattice="D3Q7", storage="i16", shape=(8, 8, 8), store_scale=0.75),
+    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), variant="tb2", bc="zero"),  # two-step: periodic only
+    dict(lattice="D1Q3", storage="f32", shape=(64,), variant="tb2"),                 # two-step: 2D or 3D
+    dict(lattice="D3Q19", storage="f32", shape=(8, 8, 8), variant="tb2"),            # LDS rings too large
+    dict(lattice="D3Q19", storage="f64", shape=(8, 8, 8), variant="tb2"),
+    dict(lattice="D3Q9", storage="f64", shape=(8, 8, 8), variant="tb2"),
+    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), variant="tb2", tune=32),    # not with in-place
+    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), variant=6),
 ])
 def test_bad_descriptors_are_rejected(kw):
     d = lbm.make_desc(**kw)
@@ -181,3 +188,14 @@ def test_network_entry_points_reject_bad_arguments():
     with pytest.raises(lbm.LbmError):
         lbm.lbm_lee_compare_fields(256, (4, 4, 1), 512, (3, 4, 1), (0, 0, 0), 1024, 1 << 20, None)
     assert lbm.lbm_nrbc_workspace_bytes("D2Q9", 1000) >= 1024 * (lbm.lbm_nrbc_dims("D2Q9")["n_params"] + 1) * 4
+
+
+@pytest.mark.parametrize("lattice,storage", [("D3Q7", "f32"), ("D3Q7", "f64"), ("D3Q7_DIA", "e3m12"), ("D2Q9", "f32"),
+                                             ("D2Q5", "f16"), ("D3Q19", "f16"), ("D3Q9", "bf16"), ("D3Q13", "i16")])
+def test_two_step_variant_accepted(lattice, storage):
+    """The two-step variant takes any extents of a periodic 2D/3D box whose LDS rings fit."""
+    D = lbm.lbm_lee_lattice_info(lattice)["D"]
+    shape = {2: (5, 70), 3: (3, 5, 70)}[D]
+    for tune in (0, 64, 128, 192):
+        d = lbm.make_desc(lattice, storage, shape, variant="tb2", tune=tune)
+        assert lbm.lbm_lee_state_bytes(d) > 0

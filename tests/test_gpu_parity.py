@@ -24,9 +24,16 @@ ALL_LATTICES = ["D1Q3", "D2Q5", "D2Q9", "D3Q7", "D3Q9", "D3Q13", "D3Q19", "D2Q5_
 SHAPES = {
     # several chunks per row, a partial last chunk, and the one-chunk-per-row (FULLROW) paths
     1: {"dpp": [(1028,), (256,)], "dpp2": [(1030,), (128,)], "generic": [(1027,)], "lds": [(1027,), (3,)]},
-    2: {"dpp": [(9, 520), (5, 256)], "dpp2": [(7, 262), (3, 128)], "generic": [(9, 517)], "lds": [(9, 517), (4, 256)]},
-    3: {"dpp": [(5, 6, 264), (3, 4, 256)], "dpp2": [(3, 5, 130)], "generic": [(5, 6, 13)], "lds": [(5, 6, 259)]},
+    2: {"dpp": [(9, 520), (5, 256)], "dpp2": [(7, 262), (3, 128)], "generic": [(9, 517)], "lds": [(9, 517), (4, 256)],
+        "tb2": [(19, 130)]},
+    3: {"dpp": [(5, 6, 264), (3, 4, 256)], "dpp2": [(3, 5, 130)], "generic": [(5, 6, 13)], "lds": [(5, 6, 259)],
+        "tb2": [(21, 18, 66)]},
 }
+
+
+def _supported(name, storage, variant, shape):
+    from paper_1601_08103_amd import lbm
+    return lbm.lbm_lee_state_bytes(lbm.make_desc(name, storage, shape, variant=variant)) > 0
 
 
 def _solver(name, storage, shape, tau=0.5, variant="auto", store_scale=0.0, fields=None, tune=0):
@@ -44,7 +51,8 @@ def _cases():
         for variant, shapes in SHAPES[D].items():
             for shape in shapes:
                 for storage in ("f64", "f32"):
-                    out.append((name, storage, variant, shape))
+                    if _supported(name, storage, variant, shape):
+                        out.append((name, storage, variant, shape))
     return out
 
 
@@ -503,3 +511,64 @@ def test_in_place_streaming_matches_two_buffers(name, storage, shape):
     assert torch.equal(one.export_f64(), two.export_f64())
     one.close()
     two.close()
+
+
+@pytest.mark.parametrize("name,storage,shape,tau", [
+    ("D3Q7", "f32", (20, 40, 130), 0.5),      # ragged tiles in x (2 x 64 + 2) and y, segments 16 + 4
+    ("D3Q7", "f32", (12, 24, 64), 0.8),       # the general relaxation
+    ("D3Q7", "f64", (9, 17, 64), 0.5),
+    ("D3Q7", "e3m12", (16, 32, 128), 0.5),
+    ("D3Q7_DIA", "f16", (4, 9, 20), 0.5),     # every axis shorter than a tile: the ring wraps
+    ("D3Q19", "f16", (10, 12, 66), 0.5),
+    ("D3Q9", "bf16", (6, 10, 70), 0.5),
+    ("D3Q13", "i16", (7, 9, 64), 0.5),
+    ("D2Q9", "f32", (40, 200), 0.5),
+    ("D2Q9", "f64", (21, 64), 0.7),
+    ("D2Q5", "f16", (33, 64), 0.5),
+    ("D2Q9", "e3m12", (3, 5), 0.5),           # fewer cells than the ring
+])
+def test_two_step_variant_matches_one_step(name, storage, shape, tau):
+    """Two steps per launch (temporal blocking) give the same bits as one-step launches, for
+    even and odd step counts and every segment length along the march axis."""
+    import torch
+    from paper_1601_08103_amd import lbm
+    lat = lattice(name)
+    fields = inputs.random_fields(6, shape, lat.D)
+    ref = _solver(name, storage, shape, tau=tau, variant="generic", fields=fields)
+    sims = [_solver(name, storage, shape, tau=tau, variant="tb2", fields=fields, tune=tune, store_scale=ref.store_scale)
+            for tune in (0, lbm.TUNE["tb_segment_8"], lbm.TUNE["tb_segment_32"])]
+    for n in (2, 1, 4, 3):
+        say("two-step", name, storage, shape, tau, n)
+        ref.step(n)
+        want = ref.export_f64()
+        for sim in sims:
+            assert sim.variant == "tb2"
+            sim.step(n)
+            assert torch.equal(sim.export_f64(), want), (n, sim.desc.tune)
+    m_ref = ref.moments()
+    m = sims[0].moments()
+    for key in ("p", "rho", "theta", "u"):
+        assert torch.equal(m[key], m_ref[key]), key
+    for sim in sims + [ref]:
+        sim.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "e3m12", "f64"])
+def test_two_step_variant_full_size(storage):
+    """The 256^3 D3Q7 workload (8 pulses): the two-step variant after 10 steps equals ten
+    one-step launches bit for bit (whose parity with the oracle the sampled test checks)."""
+    import torch
+    lat = lattice("D3Q7")
+    shape = (256, 256, 256)
+    say("two-step full size", storage)
+    p0 = inputs.gaussian_pressure(shape, inputs.pulses_3d(seed=0))
+    rho, u, theta = inputs.fields_from_pressure(p0, lat.rho0, lat.theta0, lat.gamma)
+    ref = _solver("D3Q7", storage, shape, variant="generic", fields=(rho, u, theta))
+    ref.step(10)
+    want = ref.export_f64()
+    scale = ref.store_scale
+    ref.close()
+    sim = _solver("D3Q7", storage, shape, variant="tb2", fields=(rho, u, theta), store_scale=scale)
+    sim.step(10)
+    assert torch.equal(sim.export_f64(), want)
+    sim.close()
