@@ -278,6 +278,7 @@ def main():
                     frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
                     kernel=f"step_{variant}<D3Q7,{args.storage}> ({what})", steps_per_launch=spl,
                     launch_ms=round(launch_ms, 5), algorithmic_bytes_per_launch=N * bpu,
+                    measured_traffic_GBs=None if traffic is None else round(traffic / (launch_ms / 1e3) / 1e9, 1),
                     frac_of_copy=round(achieved / copy_gbs, 4), copy_GBs=round(copy_gbs, 1))
 
     nrbc_result = None if args.no_nrbc else nrbc_leg()
