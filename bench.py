@@ -177,25 +177,38 @@ def main():
     th_d = torch.from_numpy(theta).to(dev)
     stream = torch.cuda.current_stream()
 
+    def steps_per_launch(variant):
+        # the temporal-blocking variants read and write the state once per launch of 2 or 3 steps
+        return {"tb2": 2, "tb3": 3}.get(variant, 1)
+
     def timed_run(storage):
         sim = lbm.Solver("D3Q7", storage, shape, rho_d, u_d, th_d, variant=args.variant)
         sim.step(W)
         sim.reinit(rho_d, u_d, th_d)
         torch.cuda.synchronize()
+        # the multi-step variants run K // spl launches of spl steps and K % spl one-step
+        # launches; the first part alone gives the time per launch of the dominant kernel
+        spl = steps_per_launch(sim.variant)
+        main = K - K % spl
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
+        ev2 = torch.cuda.Event(enable_timing=True)
         t_host = time.perf_counter()
         ev0.record(stream)
-        sim.step(K)
+        sim.step(main)
         ev1.record(stream)
+        sim.step(K - main)
+        ev2.record(stream)
         torch.cuda.synchronize()
         t_host = time.perf_counter() - t_host
-        ms = ev0.elapsed_time(ev1)
-        log(f"{storage}: {K} steps in {ms:.3f} ms (host {t_host * 1e3:.3f} ms)")
-        return sim, ms
+        ms = ev0.elapsed_time(ev2)
+        launch_ms = ev0.elapsed_time(ev1) / (main // spl) if main else float("nan")
+        log(f"{storage}: {K} steps in {ms:.3f} ms (host {t_host * 1e3:.3f} ms); {main // spl} launches of "
+            f"{spl} steps, {launch_ms * 1e3:.1f} us each")
+        return sim, ms, launch_ms
 
     if args.profile_only:
-        sim, ms = timed_run(args.storage)
+        sim, ms, _ = timed_run(args.storage)
         log(f"profile-only: {N * K / (ms / 1e3) / 1e6:.1f} MLUPS, {sim.bytes_per_update} B/LU")
         if args.with_copy:
             nbytes = N * 7 * 4
@@ -215,10 +228,11 @@ def main():
     results = {}
     moments = {}
     for mode in modes:
-        sim, ms = timed_run(mode)
+        sim, ms, launch_ms = timed_run(mode)
         m = sim.moments()
         moments[mode] = (m["p"].clone(), m["u"].clone())
-        results[mode] = dict(ms=ms, bpu=sim.bytes_per_update, scale=sim.store_scale, variant=sim.variant)
+        results[mode] = dict(ms=ms, launch_ms=launch_ms, bpu=sim.bytes_per_update, scale=sim.store_scale,
+                             variant=sim.variant)
         sim.close()
         del sim
     p_ref, u_ref = moments["f64"]
@@ -228,17 +242,13 @@ def main():
         return (float(torch.linalg.vector_norm(p - p_ref) / torch.linalg.vector_norm(p_ref)),
                 float(torch.linalg.vector_norm(uu - u_ref) / torch.linalg.vector_norm(u_ref)))
 
-    def steps_per_launch(variant):
-        # the two-step variant reads and writes the state once per launch of two steps
-        return 2 if variant == "tb2" else 1
-
     storage_modes = {}
     for mode, r in results.items():
         mlups = N * K / (r["ms"] / 1e3) / 1e6
         spl = steps_per_launch(r["variant"])
         # algorithmic HBM bytes per launch (one read and one write of the moving populations)
         # over the time per launch
-        gbs = N * r["bpu"] / (r["ms"] / K * spl / 1e3) / 1e9
+        gbs = N * r["bpu"] / (r["launch_ms"] / 1e3) / 1e9
         ep, eu = rel(mode)
         storage_modes[mode] = dict(MLUPS=round(mlups, 1), ms_per_step=round(r["ms"] / K, 5),
                                    bytes_per_update=r["bpu"], steps_per_launch=spl, GBs=round(gbs, 1),
@@ -270,15 +280,18 @@ def main():
     bpu = results[args.storage]["bpu"]
     variant = results[args.storage]["variant"]
     spl = steps_per_launch(variant)
-    launch_ms = ms_step * spl
+    launch_ms = results[args.storage]["launch_ms"]
     achieved = N * bpu / (launch_ms / 1e3) / 1e9
     traffic = traffic_from_counters(args.storage, n, variant)
-    what = ("two fused pull-stream/collide steps per launch" if spl == 2 else "fused pull-stream/collide")
+    what = (f"{spl} fused pull-stream/collide steps per launch" if spl > 1 else "fused pull-stream/collide")
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
                     kernel=f"step_{variant}<D3Q7,{args.storage}> ({what})", steps_per_launch=spl,
                     launch_ms=round(launch_ms, 5), algorithmic_bytes_per_launch=N * bpu,
                     measured_traffic_GBs=None if traffic is None else round(traffic / (launch_ms / 1e3) / 1e9, 1),
+                    # the one-step scheme's bytes per lattice update at this update rate: above the
+                    # HBM peak when the launches fuse several steps
+                    one_step_equivalent_GBs=round(N * bpu * spl / (launch_ms / 1e3) / 1e9, 1),
                     frac_of_copy=round(achieved / copy_gbs, 4), copy_GBs=round(copy_gbs, 1))
 
     nrbc_result = None if args.no_nrbc else nrbc_leg()

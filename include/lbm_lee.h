@@ -114,9 +114,10 @@ typedef int32_t lbm_status;
 
 /* Step kernel variant.  All variants run the same per-cell arithmetic, so their results are
  * bitwise identical; they differ only in how the streamed values are gathered. */
-#define LBM_VARIANT_AUTO 0    /* the fastest measured variant: TB2 on periodic 2D/3D boxes of */
-                              /* >= 2^20 cells where it is supported; else GENERIC for 4- and  */
-                              /* 8-byte storage, DPP/DPP2/GENERIC (by nx) for 2-byte storage  */
+#define LBM_VARIANT_AUTO 0    /* the fastest measured variant: on periodic 2D/3D boxes of     */
+                              /* >= 2^20 cells TB3 (sets of <= 9 velocities) or TB2 where they */
+                              /* are supported; else GENERIC for 4- and 8-byte storage,        */
+                              /* DPP/DPP2/GENERIC (by nx) for 2-byte storage                   */
 #define LBM_VARIANT_GENERIC 1 /* one thread per cell, per-element wrapped gathers            */
 #define LBM_VARIANT_DPP 2     /* 4 cells per lane, aligned vector loads, x shift by DPP;   */
                               /* needs nx % 4 == 0                                          */
@@ -130,6 +131,11 @@ typedef int32_t lbm_status;
  * and sets whose in-plane LDS rings do not fit 64 KB at TY = 4 (D3Q19 with FP32, and D3Q9,
  * D3Q13 and D3Q19 with FP64). */
 #define LBM_VARIANT_TB2 5
+/* Three steps per launch, the same scheme one stage deeper (the tile dilated by two cells for
+ * step t+1, by one for t+2); LDS rings of two intermediate steps (up to 128 KB per block).
+ * LBM_E_UNSUPPORTED where they do not fit at TY = 4 (D3Q13 and D3Q19 with FP64) and in the
+ * cases TB2 refuses.  A remainder of the step count (mod 3) runs one-step launches. */
+#define LBM_VARIANT_TB3 6
 
 typedef struct lbm_lee_desc {
     int32_t lattice;     /* LBM_D1Q3 ...                                                    */

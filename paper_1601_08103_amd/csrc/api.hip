@@ -117,10 +117,10 @@ bool shell_uniform(const LatticeTable &t) {
     return true;
 }
 
-int tb2_tile_y(int lattice, int storage);  // 0: the two-step variant has no tile shape
+int tb_tile_y(int lattice, int storage, int K);  // 0: the K-step variant has no tile shape
 
 // One plane across the march axis (x by y in 3D, a row in 2D) in bytes of one population.
-bool tb2_plane_fits(const lbm_lee_desc *d, int D) {
+bool tb_plane_fits(const lbm_lee_desc *d, int D) {
     const double plane = (double)d->n[0] * (D == 3 ? (double)d->n[1] : 1.0) * (double)elem_size(d->storage);
     return plane < 4294967296.0;
 }
@@ -138,16 +138,17 @@ lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
     if (N * tab->Q > 9.0e18 / 8.0) return fail(LBM_E_INVALID, "domain too large");
     if ((double)d->n[1] * (double)d->n[2] * 16.0 > 4.0e9) return fail(LBM_E_INVALID, "too many rows (ny * nz)");
     if (!(d->tau >= 0.5) || !std::isfinite(d->tau)) return fail(LBM_E_INVALID, "tau must be finite and >= 1/2 (got %g)", d->tau);
-    if (d->variant < LBM_VARIANT_AUTO || d->variant > LBM_VARIANT_TB2) return fail(LBM_E_INVALID, "unknown variant %d", d->variant);
+    if (d->variant < LBM_VARIANT_AUTO || d->variant > LBM_VARIANT_TB3) return fail(LBM_E_INVALID, "unknown variant %d", d->variant);
     if (d->tune < 0 || d->tune > 255) return fail(LBM_E_INVALID, "unknown tune bits 0x%x", d->tune);
-    if (d->variant == LBM_VARIANT_TB2) {
-        if (d->bc != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "the two-step variant needs the periodic box");
-        if (tab->D < 2) return fail(LBM_E_UNSUPPORTED, "the two-step variant needs a 2D or 3D lattice");
-        if (tb2_tile_y(d->lattice, d->storage) == 0)
-            return fail(LBM_E_UNSUPPORTED, "the two-step variant's LDS rings for lattice %d do not fit with this storage",
-                        d->lattice);
-        if (!tb2_plane_fits(d, tab->D))
-            return fail(LBM_E_UNSUPPORTED, "the two-step variant addresses a plane with 32-bit byte offsets (< 4 GiB)");
+    if (d->variant == LBM_VARIANT_TB2 || d->variant == LBM_VARIANT_TB3) {
+        const int K = d->variant == LBM_VARIANT_TB2 ? 2 : 3;
+        if (d->bc != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "the %d-step variant needs the periodic box", K);
+        if (tab->D < 2) return fail(LBM_E_UNSUPPORTED, "the %d-step variant needs a 2D or 3D lattice", K);
+        if (tb_tile_y(d->lattice, d->storage, K) == 0)
+            return fail(LBM_E_UNSUPPORTED, "the %d-step variant's LDS rings for lattice %d do not fit with this storage",
+                        K, d->lattice);
+        if (!tb_plane_fits(d, tab->D))
+            return fail(LBM_E_UNSUPPORTED, "the %d-step variant addresses a plane with 32-bit byte offsets (< 4 GiB)", K);
     }
     if (d->tune & kTuneInPlace) {
         if (d->bc != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "in-place streaming needs the periodic box");
@@ -202,11 +203,11 @@ lbm_status visit(int lattice, int storage, F &&f) {
     }
 }
 
-int tb2_tile_y(int lattice, int storage) {
+int tb_tile_y(int lattice, int storage, int K) {
     int ty = 0;
     visit(lattice, storage, [&](auto vs, auto sto) -> lbm_status {
         using VS = decltype(vs);
-        if constexpr (VS::D >= 2) ty = TbShape<VS, decltype(sto)>::TY;
+        if constexpr (VS::D >= 2) ty = K == 2 ? TbShape<VS, decltype(sto), 2>::TY : TbShape<VS, decltype(sto), 3>::TY;
         return LBM_OK;
     });
     return ty;
@@ -359,18 +360,22 @@ lbm_status launch_check() {
     return LBM_OK;
 }
 
-// AUTO: measured on MI355X (D3Q7, 256^3): the two-step variant beats every one-step kernel
-// on large periodic boxes (it moves the state through HBM once per two steps); below a
-// million cells the launches are short and the one-step kernels win.  Of the one-step kernels
+// AUTO: measured on MI355X (D3Q7, 256^3): the temporal-blocking variants beat every one-step
+// kernel on large periodic boxes (they move the state through HBM once per two or three
+// steps), three steps beating two except for D3Q19; below a million cells the launches are
+// short and the one-step kernels win.  Of the one-step kernels
 // the one-cell-per-thread gather has the highest occupancy and wins for 4- and 8-byte storage;
 // 2-byte storage needs wider per-lane accesses.
 int resolve_variant(const lbm_lee *h) {
     if (h->inplace) return LBM_VARIANT_GENERIC;  // the in-place kernels are one thread per cell
     if (h->desc.variant != LBM_VARIANT_AUTO) return h->desc.variant;
-    // periodic boxes of a million cells and more: two steps per launch, for every storage mode
-    if (h->desc.bc == LBM_BC_PERIODIC && h->tab.D >= 2 && h->N >= ((size_t)1 << 20) &&
-        tb2_tile_y(h->desc.lattice, h->desc.storage) > 0 && tb2_plane_fits(&h->desc, h->tab.D))
-        return LBM_VARIANT_TB2;
+    // periodic boxes of a million cells and more: three steps per launch for the sets of up to 9
+    // velocities, two for the larger ones (their two collisions per column already fill the
+    // registers), for every storage mode
+    if (h->desc.bc == LBM_BC_PERIODIC && h->tab.D >= 2 && h->N >= ((size_t)1 << 20) && tb_plane_fits(&h->desc, h->tab.D)) {
+        if (h->tab.Q <= 9 && tb_tile_y(h->desc.lattice, h->desc.storage, 3) > 0) return LBM_VARIANT_TB3;
+        if (tb_tile_y(h->desc.lattice, h->desc.storage, 2) > 0) return LBM_VARIANT_TB2;
+    }
     if (elem_size(h->desc.storage) >= 4) return LBM_VARIANT_GENERIC;
     if (h->nx % 4 == 0) return LBM_VARIANT_DPP;
     if (h->nx % 2 == 0) return LBM_VARIANT_DPP2;
@@ -727,20 +732,22 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
                 }
                 return LBM_OK;
             }
-            if (variant == LBM_VARIANT_TB2) {  // periodic box, two steps per launch
+            // periodic box, K steps per launch; a remainder of the step count runs one-step launches
+            auto run_tbk = [&](auto kk) -> lbm_status {
+                constexpr int K = decltype(kk)::value;
                 if constexpr (VS::D >= 2) {
-                    using SH = TbShape<VS, ST>;
+                    using SH = TbShape<VS, ST, K>;
                     if constexpr (SH::TY > 0) {
                         const int fx = h->nx, fy = VS::D == 3 ? h->ny : 1, fz = VS::D == 3 ? h->nz : h->ny;
                         const long long tiles_x = (fx + kTbTx - 1) / kTbTx, tiles_y = (fy + SH::TY - 1) / SH::TY;
-                        auto fn = step_tb2<VS, ST, SK, HF, SH::TY, SH::NT, SH::WPE>;
+                        auto fn = step_tbk<VS, ST, SK, HF, K, SH::TY, SH::NT, SH::WPE>;
                         int sz = 16;
                         const unsigned seg_bits = (tune >> 6) & 3u;
                         if (seg_bits) {
                             sz = 4 << seg_bits;  // 8, 16, 32
                         } else {
                             // a block's time is about proportional to the planes it computes
-                            // (sz + 2); the grid runs in ceil(blocks / resident slots) rounds
+                            // (sz + 2(K - 1)); the grid runs in ceil(blocks / resident slots) rounds
                             int per_cu = 0;
                             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, SH::NT, 0) !=
                                     hipSuccess || per_cu <= 0)
@@ -750,7 +757,7 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
                             long long best = -1;
                             for (int cand = 4; cand <= 64; ++cand) {
                                 const long long g = tiles_x * tiles_y * ((fz + cand - 1) / cand);
-                                const long long cost = ((g + slots - 1) / slots) * (std::min(cand, fz) + 2);
+                                const long long cost = ((g + slots - 1) / slots) * (std::min(cand, fz) + 2 * (K - 1));
                                 if (best < 0 || cost < best) {
                                     best = cost;
                                     sz = cand;
@@ -759,17 +766,17 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
                         }
                         const long long blocks = tiles_x * tiles_y * ((fz + sz - 1) / sz);
                         int64_t t = 0;
-                        for (; t + 2 <= nsteps; t += 2) {
+                        for (; t + K <= nsteps; t += K) {
                             const E *src = static_cast<const E *>(h->buf[h->cur]);
                             E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);
-                            fn<<<(unsigned)blocks, SH::NT, 0, st>>>(
-                                src, dst, fx, fy, fz, h->N, sz, (int)tiles_x, (int)tiles_y, k);
+                            fn<<<(unsigned)blocks, SH::NT, 0, st>>>(src, dst, fx, fy, fz, h->N, sz, (int)tiles_x,
+                                                                   (int)tiles_y, k);
                             lbm_status ls = launch_check();
                             if (ls != LBM_OK) return ls;
                             h->cur ^= 1;
-                            h->steps += 2;
+                            h->steps += K;
                         }
-                        if (t < nsteps) {  // odd count: one one-step launch
+                        for (; t < nsteps; ++t) {
                             const E *src = static_cast<const E *>(h->buf[h->cur]);
                             E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);
                             step_generic<VS, ST, SK, HF><<<blocks_for(h->N), 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz,
@@ -782,8 +789,10 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
                         return LBM_OK;
                     }
                 }
-                return fail(LBM_E_UNSUPPORTED, "the two-step variant does not support this lattice and storage");
-            }
+                return fail(LBM_E_UNSUPPORTED, "the %d-step variant does not support this lattice and storage", K);
+            };
+            if (variant == LBM_VARIANT_TB2) return run_tbk(std::integral_constant<int, 2>{});
+            if (variant == LBM_VARIANT_TB3) return run_tbk(std::integral_constant<int, 3>{});
             for (int64_t t = 0; t < nsteps; ++t) {
                 const E *src = static_cast<const E *>(h->buf[h->cur]);
                 E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);

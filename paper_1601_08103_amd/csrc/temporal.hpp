@@ -1,21 +1,23 @@
-// Two time steps per launch (temporal blocking) for periodic boxes.
+// K time steps per launch (temporal blocking, K = 2 or 3) for periodic boxes.
 //
 // The pull update of Section "The lattice Boltzmann scheme" reads, for every cell, population
-// i of the neighbour x - c_i; two updates in a row therefore need the state of step t on the
-// cells within two stencil hops of a tile, and the state of step t+1 within one hop.  One
-// block owns a tile of the box and marches along the last axis ("march" axis z in 3D, y in
-// 2D), one plane at a time:
-//   phase A (plane p):   step t -> t+1 on the tile plus a one-cell ring (read from HBM),
-//   phase B (plane p-1): step t+1 -> t+2 on the tile (read from phase A's results),
-// so the state goes through HBM once per two steps: read once (plus the ring and two warm-up
-// planes per segment) and written once.  Populations that move within the plane are exchanged
-// between threads through LDS rings of 3 + c_z planes; populations with c_x = c_y = 0 stay in
-// the registers of the thread that owns the column.  The loads of the next two planes (one for
-// the sets with 13 and more velocities) are in flight while a plane is computed, and one
-// barrier per plane orders the LDS traffic.  Each step's results are rounded to the
-// storage type exactly as a store and reload would (encode, decode), and every cell goes
-// through the same collision as the one-step kernels, so two steps here give the same bits as
-// two one-step launches.
+// i of the neighbour x - c_i; K updates in a row therefore need the state of step t on the
+// cells within K stencil hops of a tile, the state of step t+1 within K-1 hops, and so on.
+// One block owns a tile of the box and marches along the last axis ("march" axis z in 3D, y
+// in 2D), one plane at a time.  Per iteration, stage s (s = 1..K) computes step t+s on one
+// plane of the tile dilated by K-s cells (in x, and in y in 3D), s-1 planes behind stage 1:
+//   stage 1 reads the state of step t from HBM,
+//   stage s > 1 reads stage s-1's results from LDS and registers,
+//   stage K writes step t+K to HBM,
+// so the state goes through HBM once per K steps: read once (plus the rings around the tile
+// and 2(K-1) warm-up planes per segment) and written once.  Populations that move within the
+// plane are exchanged between threads through LDS rings of 2 + c_z planes (3 + c_z for K = 2);
+// populations with c_x = c_y = 0 stay in the registers of the thread that owns the column in
+// every stage.  The loads of the next plane (two for K = 2 and up to 9 velocities) are in
+// flight while a plane is computed, and K-1 barriers per iteration order the LDS traffic.  Each
+// stage's results are rounded to the storage type exactly as a store and reload would
+// (encode, decode), and every cell goes through the same collision as the one-step kernels,
+// so K steps here give the same bits as K one-step launches.
 #pragma once
 
 #include "kernels.hpp"
@@ -30,21 +32,21 @@ struct TbFrame {
     static constexpr int ky(int i) { return VS::D == 3 ? VS::cy(i) : 0; }
     static constexpr int kz(int i) { return VS::D == 3 ? VS::cz(i) : VS::cy(i); }
     static constexpr bool moves_xy(int i) { return kx(i) != 0 || ky(i) != 0; }
-    // a population with march-axis component c_z is read c_z planes behind, by phase B one
-    // plane behind phase A: ring of 3 + c_z slots (one more than the planes in use, see below)
-    static constexpr int depth(int i) { return 3 + kz(i); }
+    // a population with march-axis component c_z is read c_z planes behind the plane computed
+    // from it: 2 + c_z planes in use; with K = 2 the ring holds one more (see step_tbk)
+    static constexpr int depth(int i, int K) { return (K == 2 ? 3 : 2) + kz(i); }
     static constexpr bool y_halo() {
         for (int i = 0; i < VS::Q; ++i)
             if (ky(i) != 0) return true;
         return false;
     }
-    static constexpr int plane_off(int i) {
+    static constexpr int plane_off(int i, int K) {
         int o = 0;
         for (int j = 0; j < i; ++j)
-            if (moves_xy(j)) o += depth(j);
+            if (moves_xy(j)) o += depth(j, K);
         return o;
     }
-    static constexpr int planes() { return plane_off(VS::Q); }
+    static constexpr int planes(int K) { return plane_off(VS::Q, K); }
     // the population with c_x = c_y = 0 and c_z = dz, or -1
     static constexpr int local(int dz) {
         for (int i = 0; i < VS::Q; ++i)
@@ -53,30 +55,32 @@ struct TbFrame {
     }
 };
 
-// Tile shape per (set, storage): 64 cells along x; in 3D the largest TY in {16, 8, 4} whose
-// LDS rings fit kTbLdsBudget, 32 TY threads with two interior columns each; in 2D one row of
-// 64 columns per block of 64 threads.  TY = 0: no shape fits (the variant is unsupported).
+// Tile shape per (set, storage, K): 64 cells along x; in 3D the largest TY in {16, 8, 4} whose
+// LDS rings (one set per intermediate step) fit the budget, 32 TY threads with two interior
+// columns each; in 2D one row of 64 columns per block of 64 threads.  TY = 0: no shape fits
+// (the variant is unsupported).
 constexpr int kTbTx = 64;
-constexpr int kTbLdsBudget = 64 * 1024;
 
-template <class VS, class ST>
+template <class VS, class ST, int K>
 struct TbShape {
     using F = TbFrame<VS>;
     static constexpr int hy = F::y_halo() ? 1 : 0;
+    static constexpr long budget = K == 2 ? 64 * 1024 : 128 * 1024;
     static constexpr long lds_bytes(int ty) {
-        return (long)F::planes() * (kTbTx + 2) * (ty + 2 * hy) * (long)sizeof(typename ST::elem);
+        long cells = 0;
+        for (int s = 1; s < K; ++s) cells += (long)(kTbTx + 2 * (K - s)) * (ty + 2 * hy * (K - s));
+        return (long)F::planes(K) * cells * (long)sizeof(typename ST::elem);
     }
     static constexpr int pick() {
-        if (VS::D == 2) return lds_bytes(1) <= kTbLdsBudget ? 1 : 0;
+        if (VS::D == 2) return lds_bytes(1) <= budget ? 1 : 0;
         for (int ty = 16; ty >= 4; ty /= 2)
-            if (lds_bytes(ty) <= kTbLdsBudget) return ty;
+            if (lds_bytes(ty) <= budget) return ty;
         return 0;
     }
     static constexpr int TY = pick();
-    // two interior columns per thread in 3D, one in 2D
     static constexpr int NT = VS::D == 2 ? 64 : (TY > 0 ? 32 * TY : 64);
     // waves per SIMD the register budget is set for (4: 128 VGPRs; 2 for the sets with 13 or
-    // more velocities, whose two collisions per column need more), lowered where the LDS
+    // more velocities, whose collisions per column need more), lowered where the LDS
     // (160 KB per CU) holds fewer blocks than that needs
     static constexpr int blocks_by_lds() { return TY == 0 ? 1 : (int)(160 * 1024 / lds_bytes(TY)); }
     static constexpr int wpe() {
@@ -117,11 +121,41 @@ __device__ __forceinline__ void buf_store(E v, __amdgpu_buffer_rsrc_t r, unsigne
     }
 }
 
-template <class VS, class ST, bool SKIP0, bool HALF, int TY, int NT, int WPE>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void step_tb2(const typename ST::elem *__restrict__ src,
-                                               typename ST::elem *__restrict__ dst, int fx, int fy, int fz,
-                                               size_t N, int sz, int tiles_x, int tiles_y,
-                                               StepCoef<typename ST::comp, VS::Q> k) {
+// Column bookkeeping (frame: the tile dilated by K-1 cells, origin at its corner; the tile's
+// own cells start at (K-1, HY (K-1))).  A thread owns NJ interior columns (the same in every
+// stage) and, for each ring b = 1..K-1 around the tile (b cells out), NH(b) ring columns;
+// stage s works on the interior and the rings b <= K - s.
+template <int K, int TY, int NT, int HY>
+struct TbCols {
+    static constexpr int TX = kTbTx;
+    static constexpr int NJ = TX * TY / NT;
+    static constexpr int ring_cols(int b) { return HY ? 2 * (TX + 2 * b) + 2 * (TY + 2 * b - 2) : 2; }
+    static constexpr int NH(int b) { return (ring_cols(b) + NT - 1) / NT; }
+    static constexpr int NC() {
+        int n = NJ;
+        for (int b = 1; b < K; ++b) n += NH(b);
+        return n;
+    }
+    static constexpr int ring_of(int c) {  // 0 = interior
+        if (c < NJ) return 0;
+        int o = NJ;
+        for (int b = 1; b < K; ++b) {
+            if (c < o + NH(b)) return b;
+            o += NH(b);
+        }
+        return K;
+    }
+    static constexpr int first_of_ring(int b) {
+        int o = NJ;
+        for (int r = 1; r < b; ++r) o += NH(r);
+        return o;
+    }
+};
+
+template <class VS, class ST, bool SKIP0, bool HALF, int K, int TY, int NT, int WPE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void step_tbk(
+    const typename ST::elem *__restrict__ src, typename ST::elem *__restrict__ dst, int fx, int fy, int fz, size_t N,
+    int sz, int tiles_x, int tiles_y, StepCoef<typename ST::comp, VS::Q> k) {
     using F = TbFrame<VS>;
     using E = typename ST::elem;
     using CT = typename ST::comp;
@@ -130,19 +164,26 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     constexpr int i0 = SKIP0 ? 1 : 0;
     constexpr int TX = kTbTx;
     constexpr int HY = F::y_halo() ? 1 : 0;
-    constexpr int DX = TX + 2, DY = TY + 2 * HY, PL = DX * DY;
-    constexpr int NJ = TX * TY / NT;  // interior columns per thread
+    using C = TbCols<K, TY, NT, HY>;
+    constexpr int NJ = C::NJ;
     static_assert(NJ * NT == TX * TY && NJ >= 1, "tile and block size");
-    constexpr int H = PL - TX * TY;    // columns of the ring around the tile
-    constexpr int NH = (H + NT - 1) / NT;
-    constexpr int NC = NJ + NH;
-    constexpr int IU = F::local(1);                  // c = (0, 0, +1): read two planes later
-    constexpr int ID = F::local(-1);                 // c = (0, 0, -1): read in the same iteration
-    constexpr int IR = SKIP0 ? -1 : F::local(0);     // the rest population, when it is updated
-    static_assert(F::planes() > 0, "some population moves within the plane");
-    // planes of loads in flight: two where the registers allow (up to 9 velocities)
-    constexpr int PF = Q <= 9 ? 2 : 1;
-    __shared__ E ring[F::planes() * PL];
+    static_assert(K >= 2 && K <= 3, "two or three steps per launch");
+    constexpr int NC = C::NC();
+    constexpr int IU = F::local(1);               // c = (0, 0, +1): read two iterations later
+    constexpr int ID = F::local(-1);              // c = (0, 0, -1): read in the same iteration
+    constexpr int IR = SKIP0 ? -1 : F::local(0);  // the rest population, when it is updated
+    static_assert(F::planes(K) > 0, "some population moves within the plane");
+    // planes of loads in flight: two where the registers allow (up to 9 velocities, two steps)
+    constexpr int PF = (Q <= 9 && K == 2) ? 2 : 1;
+    // LDS ring set s (s = 1..K-1) holds stage s's results on the tile dilated by K - s
+    constexpr int DX1 = TX + 2 * (K - 1), DY1 = TY + 2 * HY * (K - 1);
+    constexpr int DX2 = TX + 2 * (K - 2), DY2 = TY + 2 * HY * (K - 2);
+    constexpr int SET_ELEMS1 = F::planes(K) * DX1 * DY1;
+    constexpr int RING_ELEMS = K == 2 ? SET_ELEMS1 : SET_ELEMS1 + F::planes(K) * DX2 * DY2;
+    __shared__ E ring[RING_ELEMS];
+    auto set_dx = [](int s) { return s == 1 ? DX1 : DX2; };
+    auto set_pl = [](int s) { return s == 1 ? DX1 * DY1 : DX2 * DY2; };
+    auto set_off = [](int s) { return s == 1 ? 0 : SET_ELEMS1; };
 
     // tile of this block; consecutive tiles on one XCD (blocks go round-robin over the 8 XCDs)
     unsigned b = blockIdx.x;
@@ -155,59 +196,63 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     const int w = min(TX, fx - x0), hgt = min(TY, fy - y0), seg = min(sz, fz - z0);
     const int tid = threadIdx.x;
 
-    // columns of this thread in the dilated tile: NJ interior ones (phase B owns the same), then
-    // ring columns; (cxl, cyl) dilated coordinates.  Loads and stores address a plane through a
-    // block-uniform base pointer plus a per-column 32-bit offset within the plane (xy offsets
-    // of the source cell of each population, and of the column's own cell for the stores).
+    // Columns: (cxl, cyl) in the frame.  Loads and stores address a plane through a
+    // block-uniform base plus a per-column 32-bit byte offset within the plane (the source cell
+    // of each population; the column's own cell for the stores).
     int cxl[NC], cyl[NC];
     unsigned xyoff[NC][Q], oxy[NJ];  // byte offsets (the host keeps a plane under 4 GiB)
     bool valid[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
+        const int rb = C::ring_of(c);
         int ax, ay;
         bool ok = true;
-        if (c < NJ) {
+        if (rb == 0) {
             const int cc = tid + NT * c;
-            ax = cc % TX + 1;
-            ay = cc / TX + HY;
+            ax = cc % TX + (K - 1);
+            ay = cc / TX + HY * (K - 1);
         } else {
-            const int h = tid + NT * (c - NJ);
-            ok = h < H;
+            // odd rings from the last thread down, even ones from the first up, so that no
+            // wave holds a column of two rings
+            const int h = ((rb & 1) ? NT - 1 - tid : tid) + NT * (c - C::first_of_ring(rb));
+            ok = h < C::ring_cols(rb);
+            const int W = TX + 2 * rb, lo = K - 1 - rb;
             if (HY == 0) {
-                ax = h == 0 ? 0 : DX - 1;
+                ax = h == 0 ? lo : lo + W - 1;
                 ay = 0;
-            } else if (h < DX) {
-                ax = h;
-                ay = 0;
-            } else if (h < 2 * DX) {
-                ax = h - DX;
-                ay = DY - 1;
+            } else if (h < W) {
+                ax = lo + h;
+                ay = lo;
+            } else if (h < 2 * W) {
+                ax = lo + h - W;
+                ay = lo + TY + 2 * rb - 1;
             } else {
-                const int h2 = h - 2 * DX;
-                ax = (h2 & 1) ? DX - 1 : 0;
-                ay = 1 + (h2 >> 1);
+                const int h2 = h - 2 * W;
+                ax = (h2 & 1) ? lo + W - 1 : lo;
+                ay = lo + 1 + (h2 >> 1);
             }
-            if (!ok) ax = ay = 0;
+            if (!ok) ax = ay = K - 1;
         }
         cxl[c] = ax;
         cyl[c] = ay;
         valid[c] = ok;
-        int X = (x0 - 1 + ax) % fx;
+        int X = (x0 - (K - 1) + ax) % fx;
         if (X < 0) X += fx;
-        int Y = (y0 - HY + ay) % fy;
+        int Y = (y0 - HY * (K - 1) + ay) % fy;
         if (Y < 0) Y += fy;
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-            xyoff[c][i] = (unsigned)(wrap_add(Y, -F::ky(i), fy) * fx + wrap_add(X, -F::kx(i), fx)) * (unsigned)sizeof(E);
-        if (c < NJ) oxy[c < NJ ? c : 0] = (unsigned)(Y * fx + X) * (unsigned)sizeof(E);
+            xyoff[c][i] =
+                (unsigned)(wrap_add(Y, -F::ky(i), fy) * fx + wrap_add(X, -F::kx(i), fx)) * (unsigned)sizeof(E);
+        if (rb == 0) oxy[c < NJ ? c : 0] = (unsigned)(Y * fx + X) * (unsigned)sizeof(E);
     }
     const size_t plane = (size_t)fx * fy;
 
+    // local plane l is global plane z0 - (K - 1) + l (wrapped)
     E la[NC][Q], lb[NC][Q];
-    auto load_plane = [&](int pl, E(&ld)[NC][Q]) {
-        int Z = z0 - 1 + pl;
+    auto load_plane = [&](int l, E(&ld)[NC][Q]) {
+        int Z = (z0 - (K - 1) + l) % fz;
         if (Z < 0) Z += fz;
-        if (Z >= fz) Z -= fz;
 #pragma unroll
         for (int i = i0; i < Q; ++i) {
             const auto r = plane_rsrc(src + (size_t)i * N + (size_t)wrap_add(Z, -F::kz(i), fz) * plane);
@@ -217,93 +262,115 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         }
     };
 
-    // column-local populations of the interior columns: up ring (planes pl, pl-1, pl-2),
-    // rest (pl, pl-1), down (pl)
-    CT u0[NJ], u1[NJ], u2[NJ], r0[NJ], r1[NJ], d0[NJ];
+    // column-local results of stage s < K on the thread's columns of stage s + 1: c = (0, 0, +1)
+    // for the planes of this and the two previous iterations, the rest for this and the
+    // previous one, c = (0, 0, -1) for this one
+    CT u0[K][NC], u1[K][NC], u2[K][NC], r0[K][NC], r1[K][NC], d0[K][NC];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) u0[j] = u1[j] = u2[j] = r0[j] = r1[j] = d0[j] = 0;
+    for (int s = 0; s < K; ++s)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) u0[s][c] = u1[s][c] = u2[s][c] = r0[s][c] = r1[s][c] = d0[s][c] = 0;
 
-    // LDS ring slot of plane q for a population with march-axis component cz (3 + cz slots)
-    auto slot = [](int cz, int q, int q3) { return cz > 0 ? (q & 3) : cz == 0 ? q3 : (q & 1); };
+    // LDS ring slot of local plane q (q3 = q % 3) for a population with march-axis component cz
+    auto slot = [](int cz, int q, int q3) {
+        if (K == 2) return cz > 0 ? (q & 3) : cz == 0 ? q3 : (q & 1);
+        return cz > 0 ? q3 : cz == 0 ? (q & 1) : 0;
+    };
 
-    int m3 = 0;  // pl % 3
-    // One iteration: phase A on local plane pl from the loads in cur, then the loads of plane
-    // pl + 2 into cur, one barrier, phase B on plane pl - 1.  A wave that leaves phase B early
-    // writes plane pl + 1 in the next phase A while others still read planes pl - 2 .. pl: the
-    // rings have one slot more than the planes phase B reads, so it never overwrites them.
+    // One iteration pl: stage s computes local plane l = pl - (s - 1).  Stage 1 uses the loads
+    // in cur and then issues the loads of plane pl + PF into it; a barrier separates consecutive
+    // stages.  With K = 2 a wave that runs ahead into the next iteration's stage 1 writes ring
+    // set 1 one plane beyond those the slowest wave may still read in stage 2, so those rings
+    // have one slot more than the planes in use.  With K = 3 the next stage 1 (ring set 1) and
+    // stage 2 (ring set 2) start only after a barrier that every wave passes once it is done
+    // with the stage that reads that set, so the planes in use are enough.
+    const int last = seg + 2 * K - 3;  // stage K writes the segment's seg planes
     auto body = [&](int pl, E(&cur)[NC][Q]) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            if (!valid[c]) continue;
-            CT s[Q];
-            s[0] = 0;
+        for (int s = 1; s <= K; ++s) {
+            const int l = pl - (s - 1);
+            if (l >= s - 1) {
+                const int l3 = l % 3;
+                const int lm3 = (l + 2) % 3;  // (l - 1) % 3
+                const int lp3 = (l + 1) % 3;  // (l + 1) % 3
 #pragma unroll
-            for (int i = i0; i < Q; ++i) s[i] = dec_io<ST, RAW>(cur[c][i]);
-            collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, s);
+                for (int c = 0; c < NC; ++c) {
+                    if (C::ring_of(c) > K - s || !valid[c]) continue;
+                    CT sv[Q];
+                    sv[0] = 0;
+                    if (s == 1) {
 #pragma unroll
-            for (int i = i0; i < Q; ++i) {
-                const E e = enc_io<ST, RAW>(s[i]);
-                if (F::moves_xy(i)) {
-                    ring[(F::plane_off(i) + slot(F::kz(i), pl, m3)) * PL + cyl[c] * DX + cxl[c]] = e;
-                } else if (c < NJ) {
-                    const int cj = c < NJ ? c : 0;
-                    const CT v = dec_io<ST, RAW>(e);
-                    if (i == IU) u0[cj] = v;
-                    if (i == IR) r0[cj] = v;
-                    if (i == ID) d0[cj] = v;
-                }
-            }
-        }
-        if (pl + PF <= seg + 1) load_plane(pl + PF, cur);  // PF planes in flight across phase B
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-        __builtin_amdgcn_s_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-        if (pl >= 2) {
-            // phase B: step t+2 on plane z0 - 2 + pl (local plane pl - 1), reading local planes
-            // pl - 2 (cz = +1), pl - 1 (cz = 0) and pl (cz = -1)
-            const int Zq = z0 - 2 + pl;
-            const int m3m1 = m3 == 0 ? 2 : m3 - 1;  // (pl - 1) % 3
-#pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-                CT s[Q];
-                s[0] = 0;
-#pragma unroll
-                for (int i = i0; i < Q; ++i) {
-                    if (F::moves_xy(i)) {
-                        const int q = pl - 1 - F::kz(i);
-                        s[i] = dec_io<ST, RAW>(ring[(F::plane_off(i) + slot(F::kz(i), q, m3m1)) * PL +
-                                                    (cyl[j] - F::ky(i)) * DX + (cxl[j] - F::kx(i))]);
+                        for (int i = i0; i < Q; ++i) sv[i] = dec_io<ST, RAW>(cur[c][i]);
                     } else {
-                        s[i] = i == IU ? u2[j] : i == IR ? r1[j] : d0[j];
+                        const int set = s - 1;  // ring set read, in its own coordinates
+                        const int lxy = (cyl[c] - HY * (s - 2)) * set_dx(set) + (cxl[c] - (s - 2));
+#pragma unroll
+                        for (int i = i0; i < Q; ++i) {
+                            if (F::moves_xy(i)) {
+                                const int kz = F::kz(i);
+                                const int q = l - kz;
+                                const int q3 = kz > 0 ? lm3 : kz < 0 ? lp3 : l3;
+                                sv[i] = dec_io<ST, RAW>(ring[set_off(set) + (F::plane_off(i, K) + slot(kz, q, q3)) * set_pl(set) +
+                                                             lxy - F::ky(i) * set_dx(set) - F::kx(i)]);
+                            } else {
+                                sv[i] = i == IU ? u2[set][c] : i == IR ? r1[set][c] : d0[set][c];
+                            }
+                        }
+                    }
+                    collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, sv);
+                    if (s == K) {
+                        const int xl = cxl[c] - (K - 1), yl = cyl[c] - HY * (K - 1);
+                        if (xl < w && yl < hgt) {
+                            const int Zq = z0 - (K - 1) + l;  // in [z0, z0 + seg)
+#pragma unroll
+                            for (int i = i0; i < Q; ++i)
+                                buf_store<E>(enc_io<ST, RAW>(sv[i]), plane_rsrc(dst + (size_t)i * N + (size_t)Zq * plane),
+                                             oxy[c < NJ ? c : 0]);
+                        }
+                    } else {
+                        const int lxy = (cyl[c] - HY * (s - 1)) * set_dx(s) + (cxl[c] - (s - 1));
+                        const bool keep_local = C::ring_of(c) <= K - s - 1;
+#pragma unroll
+                        for (int i = i0; i < Q; ++i) {
+                            const E e = enc_io<ST, RAW>(sv[i]);
+                            if (F::moves_xy(i)) {
+                                ring[set_off(s) + (F::plane_off(i, K) + slot(F::kz(i), l, l3)) * set_pl(s) + lxy] = e;
+                            } else if (keep_local) {
+                                const CT v = dec_io<ST, RAW>(e);
+                                if (i == IU) u0[s][c] = v;
+                                if (i == IR) r0[s][c] = v;
+                                if (i == ID) d0[s][c] = v;
+                            }
+                        }
                     }
                 }
-                collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, s);
-                const int xl = cxl[j] - 1, yl = cyl[j] - HY;
-                if (xl < w && yl < hgt) {
-#pragma unroll
-                    for (int i = i0; i < Q; ++i)
-                        buf_store<E>(enc_io<ST, RAW>(s[i]), plane_rsrc(dst + (size_t)i * N + (size_t)Zq * plane), oxy[j]);
-                }
+            }
+            if (s == 1 && pl + PF <= last) load_plane(pl + PF, cur);  // in flight across the stages
+            if (s < K) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+                __builtin_amdgcn_s_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
             }
         }
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            u2[j] = u1[j];
-            u1[j] = u0[j];
-            r1[j] = r0[j];
-        }
-        m3 = m3 == 2 ? 0 : m3 + 1;
+        for (int s = 1; s < K; ++s)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                u2[s][c] = u1[s][c];
+                u1[s][c] = u0[s][c];
+                r1[s][c] = r0[s][c];
+            }
     };
 
     load_plane(0, la);
     if constexpr (PF == 2) {
-        load_plane(1, lb);  // seg >= 1: planes 0 .. seg + 1 are at least three
-        for (int pl = 0; pl <= seg + 1; pl += 2) {
+        load_plane(1, lb);  // seg >= 1: at least 2K - 1 >= 3 planes
+        for (int pl = 0; pl <= last; pl += 2) {
             body(pl, la);
-            if (pl + 1 <= seg + 1) body(pl + 1, lb);
+            if (pl + 1 <= last) body(pl + 1, lb);
         }
     } else {
-        for (int pl = 0; pl <= seg + 1; ++pl) body(pl, la);
+        for (int pl = 0; pl <= last; ++pl) body(pl, la);
     }
 }
 

@@ -25,9 +25,9 @@ SHAPES = {
     # several chunks per row, a partial last chunk, and the one-chunk-per-row (FULLROW) paths
     1: {"dpp": [(1028,), (256,)], "dpp2": [(1030,), (128,)], "generic": [(1027,)], "lds": [(1027,), (3,)]},
     2: {"dpp": [(9, 520), (5, 256)], "dpp2": [(7, 262), (3, 128)], "generic": [(9, 517)], "lds": [(9, 517), (4, 256)],
-        "tb2": [(19, 130)]},
+        "tb2": [(19, 130)], "tb3": [(23, 131)]},
     3: {"dpp": [(5, 6, 264), (3, 4, 256)], "dpp2": [(3, 5, 130)], "generic": [(5, 6, 13)], "lds": [(5, 6, 259)],
-        "tb2": [(21, 18, 66)]},
+        "tb2": [(21, 18, 66)], "tb3": [(22, 19, 67)]},
 }
 
 
@@ -527,22 +527,26 @@ def test_in_place_streaming_matches_two_buffers(name, storage, shape):
     ("D2Q5", "f16", (33, 64), 0.5),
     ("D2Q9", "e3m12", (3, 5), 0.5),           # fewer cells than the ring
 ])
-def test_two_step_variant_matches_one_step(name, storage, shape, tau):
-    """Two steps per launch (temporal blocking) give the same bits as one-step launches, for
-    even and odd step counts and every segment length along the march axis."""
+@pytest.mark.parametrize("variant", ["tb2", "tb3"])
+def test_temporal_blocking_matches_one_step(name, storage, shape, tau, variant):
+    """Two and three steps per launch (temporal blocking) give the same bits as one-step
+    launches, for every remainder of the step count and every segment length along the march
+    axis."""
     import torch
     from paper_1601_08103_amd import lbm
     lat = lattice(name)
+    if lbm.lbm_lee_state_bytes(lbm.make_desc(name, storage, shape, variant=variant)) == 0:
+        pytest.skip(f"{variant} does not fit {name}/{storage} (LDS)")
     fields = inputs.random_fields(6, shape, lat.D)
     ref = _solver(name, storage, shape, tau=tau, variant="generic", fields=fields)
-    sims = [_solver(name, storage, shape, tau=tau, variant="tb2", fields=fields, tune=tune, store_scale=ref.store_scale)
+    sims = [_solver(name, storage, shape, tau=tau, variant=variant, fields=fields, tune=tune, store_scale=ref.store_scale)
             for tune in (0, lbm.TUNE["tb_segment_8"], lbm.TUNE["tb_segment_32"])]
-    for n in (2, 1, 4, 3):
-        say("two-step", name, storage, shape, tau, n)
+    for n in (2, 1, 4, 3, 6, 5):
+        say("temporal blocking", variant, name, storage, shape, tau, n)
         ref.step(n)
         want = ref.export_f64()
         for sim in sims:
-            assert sim.variant == "tb2"
+            assert sim.variant == variant
             sim.step(n)
             assert torch.equal(sim.export_f64(), want), (n, sim.desc.tune)
     m_ref = ref.moments()
@@ -553,14 +557,16 @@ def test_two_step_variant_matches_one_step(name, storage, shape, tau):
         sim.close()
 
 
+@pytest.mark.parametrize("variant", ["tb2", "tb3"])
 @pytest.mark.parametrize("storage", ["f32", "f16", "e3m12", "f64"])
-def test_two_step_variant_full_size(storage):
-    """The 256^3 D3Q7 workload (8 pulses): the two-step variant after 10 steps equals ten
-    one-step launches bit for bit (whose parity with the oracle the sampled test checks)."""
+def test_temporal_blocking_full_size(storage, variant):
+    """The 256^3 D3Q7 workload (8 pulses): the two- and three-step variants after 10 steps
+    equal ten one-step launches bit for bit (whose parity with the oracle the sampled test
+    checks)."""
     import torch
     lat = lattice("D3Q7")
     shape = (256, 256, 256)
-    say("two-step full size", storage)
+    say("temporal blocking full size", variant, storage)
     p0 = inputs.gaussian_pressure(shape, inputs.pulses_3d(seed=0))
     rho, u, theta = inputs.fields_from_pressure(p0, lat.rho0, lat.theta0, lat.gamma)
     ref = _solver("D3Q7", storage, shape, variant="generic", fields=(rho, u, theta))
@@ -568,7 +574,7 @@ def test_two_step_variant_full_size(storage):
     want = ref.export_f64()
     scale = ref.store_scale
     ref.close()
-    sim = _solver("D3Q7", storage, shape, variant="tb2", fields=(rho, u, theta), store_scale=scale)
+    sim = _solver("D3Q7", storage, shape, variant=variant, fields=(rho, u, theta), store_scale=scale)
     sim.step(10)
     assert torch.equal(sim.export_f64(), want)
     sim.close()
