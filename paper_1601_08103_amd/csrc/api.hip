@@ -255,20 +255,26 @@ StepCoef<CT, Q> step_coef(const lbm_lee *h, double raw_unit = 1.0) {
     std::memset(&k, 0, sizeof k);
     const double omega = 1.0 / h->desc.tau;
     const LatticeTable &t = h->tab;
+    // per-shell constants in FP64 (the host checks that they agree within a shell)
+    double dec[kShells] = {}, edec[kShells] = {}, bu[kShells] = {}, w[kShells] = {};
     for (int i = 0; i < Q; ++i) {
         const int sh = t.c[i][0] * t.c[i][0] + t.c[i][1] * t.c[i][1] + t.c[i][2] * t.c[i][2];
-        k.dec[sh] = split<CT>(f.dec[i] / raw_unit);
-        k.edec[sh] = split<CT>(f.e[i] * f.dec[i] / raw_unit);
-        k.bu[sh] = split<CT>(f.b * f.dec[i] / f.rho0 / raw_unit);
-        k.w[sh] = split<CT>(omega * f.enc[i] * f.f[i] * raw_unit);
+        dec[sh] = f.dec[i] / raw_unit;
+        edec[sh] = f.e[i] * f.dec[i] / raw_unit;
+        bu[sh] = f.b * f.dec[i] / f.rho0 / raw_unit;
+        w[sh] = omega * f.enc[i] * f.f[i] * raw_unit;
     }
+    // A = kA rho' + kA' e and C = kC rho' + kC' e after eliminating theta'
+    const double gm1_rho0 = f.gm1 / f.rho0, theta0_rho0 = f.theta0 / f.rho0;
+    const double kA = f.a1 - f.a2 * theta0_rho0, kAe = f.a2 * gm1_rho0;
+    const double kC = f.c1 - f.c2 * theta0_rho0, kCe = f.c2 * gm1_rho0;
+    for (int to = 0; to < kShells; ++to)
+        for (int from = 0; from < kShells; ++from) {
+            const double gA = kA * dec[from] + kAe * edec[from], gC = kC * dec[from] + kCe * edec[from];
+            k.H[to][from] = split<CT>(w[to] * (gA + 0.5 * to * gC));
+            k.WB[to][from] = split<CT>(w[to] * bu[from]);
+        }
     k.keep = split<CT>(1.0 - omega);
-    k.gm1_rho0 = split<CT>(f.gm1 / f.rho0);
-    k.theta0_rho0 = split<CT>(f.theta0 / f.rho0);
-    k.a1 = split<CT>(f.a1);
-    k.a2 = split<CT>(f.a2);
-    k.c1 = split<CT>(f.c1);
-    k.c2 = split<CT>(f.c2);
     return k;
 }
 

@@ -50,22 +50,26 @@ constexpr bool split_constants() {
 // kernels, ST::dec_raw / enc_raw), for compute type CT, per shell: the populations with
 // the same |c_i|^2 (0 rest, 1 axes, 2 edges, 3 corners) share f*_i, beta_i and hence every
 // constant below (the host checks this for each table).  With stored value s_i and decoded
-// population g_i = dec_i s_i:
+// population g_i = dec_i s_i the moments are
 //   rho'  = sum_shell dec (sum s_i),      e = sum_shell edec (sum s_i),
 //   U     = b u' = sum_shell bu (sum c_i s_i),        bu = b dec / rho0,
 //   theta' = gm1_rho0 e - theta0_rho0 rho',
 //   A = a1 rho' + a2 theta',  C = c1 rho' + c2 theta',
-//   s_i <- keep s_i + w (A + |c_i|^2/2 C + c_i.U)
-// where keep = 1 - 1/tau and w = (1/tau) enc_i f*_i (the equilibrium in storage units).
+// and the update s_i <- keep s_i + w (A + |c_i|^2/2 C + c_i.U), keep = 1 - 1/tau and
+// w = (1/tau) enc_i f*_i (the equilibrium in storage units).  Every term is linear in the
+// per-shell sums, so the host folds the constants (in FP64) into
+//   H[to][from]  = w_to (kA dec_from + kA' edec_from + |c_to|^2/2 (kC dec_from + kC' edec_from)),
+//   WB[to][from] = w_to bu_from,
+// with kA = a1 - a2 theta0_rho0, kA' = a2 gm1_rho0 and kC, kC' likewise from c1, c2, and the
+// step computes s_i <- keep s_i + sum_from H[sh_i][from] S_from + c_i . sum_from WB[sh_i][from] J_from
+// from the shell sums S and J = sum c_i s_i.
 constexpr int kShells = 4;
 
 template <typename CT, int Q>
 struct StepCoef {
-    Kc<CT> dec[kShells];
-    Kc<CT> edec[kShells];
-    Kc<CT> bu[kShells];
-    Kc<CT> w[kShells];
-    Kc<CT> keep, gm1_rho0, theta0_rho0, a1, a2, c1, c2;
+    Kc<CT> H[kShells][kShells];
+    Kc<CT> WB[kShells][kShells];
+    Kc<CT> keep;
 };
 
 // FP64 constants of the non-hot kernels (init, moments, reductions, import/export).
@@ -119,9 +123,8 @@ __device__ __forceinline__ CT addk(CT acc, CT x, Kc<CT> k) {
 // SKIP0: the rest population (index 0) is left out: the host enables this only when the
 // equilibrium map leaves it invariant (E_00 = 1, E_0j = E_j0 = 0), in which case the moving
 // populations' equilibria do not depend on it either.
-// HALF: tau = 1/2 (keep = -1), the paper's second-order choice: s_i <- w t_i - s_i, one fma
-// (with split constants: the product w t_i formed as in the general form, then - s_i; the
-// same bits as keep s_i + w t_i with keep = -1).
+// HALF: tau = 1/2 (keep = -1), the paper's second-order choice: s_i <- (relaxed equilibrium)
+// - s_i, the same bits as keep s_i + (relaxed equilibrium) with keep = -1.
 template <class VS, typename CT, bool SPLIT, bool SKIP0 = false, bool HALF = false>
 __device__ __forceinline__ void collide(const StepCoef<CT, VS::Q> &k, CT (&s)[VS::Q]) {
     // No implicit contraction: every fused multiply-add below is written out, so the result
@@ -149,50 +152,49 @@ __device__ __forceinline__ void collide(const StepCoef<CT, VS::Q> &k, CT (&s)[VS
             if (first_of<VS, i0>(i, 2)) jz[sh] = sv; else jz[sh] += sv;
         }
     }
-    CT rho = 0, e = 0, Ux = 0, Uy = 0, Uz = 0;
-    bool first = true, firstu = true;
+    // relaxed equilibrium per target shell: E = H . S, V = WB . J (J only for moving shells)
+    CT E[kShells] = {}, Vx[kShells] = {}, Vy[kShells] = {}, Vz[kShells] = {};
 #pragma unroll
-    for (int sh = 0; sh < kShells; ++sh) {
-        if (!has_shell<VS, SKIP0>(sh)) continue;
-        rho = first ? mulk<SPLIT>(sum[sh], k.dec[sh]) : addk<SPLIT>(rho, sum[sh], k.dec[sh]);
-        e = first ? mulk<SPLIT>(sum[sh], k.edec[sh]) : addk<SPLIT>(e, sum[sh], k.edec[sh]);
-        first = false;
-        if (sh == 0) continue;  // the rest velocity carries no momentum
-        if (firstu) {
-            Ux = mulk<SPLIT>(jx[sh], k.bu[sh]);
-            if (VS::D >= 2) Uy = mulk<SPLIT>(jy[sh], k.bu[sh]);
-            if (VS::D >= 3) Uz = mulk<SPLIT>(jz[sh], k.bu[sh]);
-        } else {
-            Ux = addk<SPLIT>(Ux, jx[sh], k.bu[sh]);
-            if (VS::D >= 2) Uy = addk<SPLIT>(Uy, jy[sh], k.bu[sh]);
-            if (VS::D >= 3) Uz = addk<SPLIT>(Uz, jz[sh], k.bu[sh]);
+    for (int to = 0; to < kShells; ++to) {
+        if (!has_shell<VS, SKIP0>(to)) continue;
+        bool first = true;
+#pragma unroll
+        for (int from = 0; from < kShells; ++from) {
+            if (!has_shell<VS, SKIP0>(from)) continue;
+            E[to] = first ? mulk<SPLIT>(sum[from], k.H[to][from]) : addk<SPLIT>(E[to], sum[from], k.H[to][from]);
+            first = false;
         }
-        firstu = false;
-    }
-    const CT theta = addk<SPLIT>(-mulk<SPLIT>(rho, k.theta0_rho0), e, k.gm1_rho0);
-    const CT A = addk<SPLIT>(mulk<SPLIT>(rho, k.a1), theta, k.a2);
-    const CT C = addk<SPLIT>(mulk<SPLIT>(rho, k.c1), theta, k.c2);
-    CT As[kShells];
+        if (to == 0) continue;  // the rest velocity carries no momentum term
+        bool firstu = true;
 #pragma unroll
-    for (int sh = 0; sh < kShells; ++sh) As[sh] = sh == 0 ? A : fma((CT)(0.5 * sh), C, A);  // 1/2, 1, 3/2: exact
+        for (int from = 1; from < kShells; ++from) {
+            if (!has_shell<VS, SKIP0>(from)) continue;
+            if (firstu) {
+                Vx[to] = mulk<SPLIT>(jx[from], k.WB[to][from]);
+                if (VS::D >= 2) Vy[to] = mulk<SPLIT>(jy[from], k.WB[to][from]);
+                if (VS::D >= 3) Vz[to] = mulk<SPLIT>(jz[from], k.WB[to][from]);
+            } else {
+                Vx[to] = addk<SPLIT>(Vx[to], jx[from], k.WB[to][from]);
+                if (VS::D >= 2) Vy[to] = addk<SPLIT>(Vy[to], jy[from], k.WB[to][from]);
+                if (VS::D >= 3) Vz[to] = addk<SPLIT>(Vz[to], jz[from], k.WB[to][from]);
+            }
+            firstu = false;
+        }
+    }
 #pragma unroll
     for (int i = i0; i < VS::Q; ++i) {
         const int sh = VS::c2(i);
-        CT t = As[sh];
-        if (VS::cx(i) > 0) t += Ux;
-        if (VS::cx(i) < 0) t -= Ux;
-        if (VS::cy(i) > 0) t += Uy;
-        if (VS::cy(i) < 0) t -= Uy;
-        if (VS::cz(i) > 0) t += Uz;
-        if (VS::cz(i) < 0) t -= Uz;
-        if constexpr (HALF && SPLIT)  // keep = -1 exactly: the same bits as the general form below
-            s[i] = mulk<SPLIT>(t, k.w[sh]) - s[i];
-        else if constexpr (HALF)
-            s[i] = fmak<SPLIT>(k.w[sh], t, -s[i]);
-        else if constexpr (SPLIT)  // both products whole before the sum: the lo parts must not be lost in s
-            s[i] = mulk<SPLIT>(s[i], k.keep) + mulk<SPLIT>(t, k.w[sh]);
+        CT t = E[sh];
+        if (VS::cx(i) > 0) t += Vx[sh];
+        if (VS::cx(i) < 0) t -= Vx[sh];
+        if (VS::cy(i) > 0) t += Vy[sh];
+        if (VS::cy(i) < 0) t -= Vy[sh];
+        if (VS::cz(i) > 0) t += Vz[sh];
+        if (VS::cz(i) < 0) t -= Vz[sh];
+        if constexpr (HALF)  // keep = -1 exactly
+            s[i] = t - s[i];
         else
-            s[i] = fmak<SPLIT>(k.w[sh], t, mulk<SPLIT>(s[i], k.keep));
+            s[i] = mulk<SPLIT>(s[i], k.keep) + t;
     }
 }
 

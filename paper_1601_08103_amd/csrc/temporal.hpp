@@ -13,8 +13,8 @@
 // and 2(K-1) warm-up planes per segment) and written once.  Populations that move within the
 // plane are exchanged between threads through LDS rings of 2 + c_z planes (3 + c_z for K = 2);
 // populations with c_x = c_y = 0 stay in the registers of the thread that owns the column in
-// every stage.  The loads of the next plane (two for K = 2 and up to 9 velocities) are in
-// flight while a plane is computed, and K-1 barriers per iteration order the LDS traffic.  Each
+// every stage.  The loads of the next two planes (one for the sets with 13 and more velocities)
+// are in flight while a plane is computed, and K-1 barriers per iteration order the LDS traffic.  Each
 // stage's results are rounded to the storage type exactly as a store and reload would
 // (encode, decode), and every cell goes through the same collision as the one-step kernels,
 // so K steps here give the same bits as K one-step launches.
@@ -167,23 +167,24 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     using C = TbCols<K, TY, NT, HY>;
     constexpr int NJ = C::NJ;
     static_assert(NJ * NT == TX * TY && NJ >= 1, "tile and block size");
-    static_assert(K >= 2 && K <= 3, "two or three steps per launch");
+    static_assert(K >= 2 && K <= 4, "two to four steps per launch");
     constexpr int NC = C::NC();
     constexpr int IU = F::local(1);               // c = (0, 0, +1): read two iterations later
     constexpr int ID = F::local(-1);              // c = (0, 0, -1): read in the same iteration
     constexpr int IR = SKIP0 ? -1 : F::local(0);  // the rest population, when it is updated
     static_assert(F::planes(K) > 0, "some population moves within the plane");
-    // planes of loads in flight: two where the registers allow (up to 9 velocities, two steps)
-    constexpr int PF = (Q <= 9 && K == 2) ? 2 : 1;
+    // planes of loads in flight: two where the registers allow (up to 9 velocities)
+    constexpr int PF = Q <= 9 ? 2 : 1;
     // LDS ring set s (s = 1..K-1) holds stage s's results on the tile dilated by K - s
-    constexpr int DX1 = TX + 2 * (K - 1), DY1 = TY + 2 * HY * (K - 1);
-    constexpr int DX2 = TX + 2 * (K - 2), DY2 = TY + 2 * HY * (K - 2);
-    constexpr int SET_ELEMS1 = F::planes(K) * DX1 * DY1;
-    constexpr int RING_ELEMS = K == 2 ? SET_ELEMS1 : SET_ELEMS1 + F::planes(K) * DX2 * DY2;
+    auto set_dx = [](int s) { return TX + 2 * (K - s); };
+    auto set_pl = [](int s) { return (TX + 2 * (K - s)) * (TY + 2 * HY * (K - s)); };
+    auto set_off = [](int s) {
+        int o = 0;
+        for (int r = 1; r < s; ++r) o += F::planes(K) * (TX + 2 * (K - r)) * (TY + 2 * HY * (K - r));
+        return o;
+    };
+    constexpr int RING_ELEMS = set_off(K);
     __shared__ E ring[RING_ELEMS];
-    auto set_dx = [](int s) { return s == 1 ? DX1 : DX2; };
-    auto set_pl = [](int s) { return s == 1 ? DX1 * DY1 : DX2 * DY2; };
-    auto set_off = [](int s) { return s == 1 ? 0 : SET_ELEMS1; };
 
     // tile of this block; consecutive tiles on one XCD (blocks go round-robin over the 8 XCDs)
     unsigned b = blockIdx.x;
