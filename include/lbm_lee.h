@@ -132,7 +132,7 @@ typedef int32_t lbm_status;
  * D3Q13 and D3Q19 with FP64). */
 #define LBM_VARIANT_TB2 5
 /* Three steps per launch, the same scheme one stage deeper (the tile dilated by two cells for
- * step t+1, by one for t+2); LDS rings of two intermediate steps (up to 128 KB per block).
+ * step t+1, by one for t+2); LDS rings of two intermediate steps (up to 160 KB per block).
  * LBM_E_UNSUPPORTED where they do not fit at TY = 4 (D3Q13 and D3Q19 with FP64) and in the
  * cases TB2 refuses.  A remainder of the step count (mod 3) runs one-step launches. */
 #define LBM_VARIANT_TB3 6

@@ -55,17 +55,17 @@ struct TbFrame {
     }
 };
 
-// Tile shape per (set, storage, K): 64 cells along x; in 3D the largest TY in {16, 8, 4} whose
-// LDS rings (one set per intermediate step) fit the budget, 32 TY threads with two interior
-// columns each; in 2D one row of 64 columns per block of 64 threads.  TY = 0: no shape fits
-// (the variant is unsupported).
+// Tile shape per (set, storage, K): 64 cells along x; in 3D the largest TY in {32 or 16, 8, 4}
+// whose LDS rings (one set per intermediate step) fit the budget (64 KB for K = 2, the CU's
+// 160 KB otherwise), 32 TY threads with two interior columns each; in 2D one row of 64 columns
+// per block of 64 threads.  TY = 0: no shape fits (the variant is unsupported).
 constexpr int kTbTx = 64;
 
 template <class VS, class ST, int K>
 struct TbShape {
     using F = TbFrame<VS>;
     static constexpr int hy = F::y_halo() ? 1 : 0;
-    static constexpr long budget = K == 2 ? 64 * 1024 : 128 * 1024;
+    static constexpr long budget = K == 2 ? 64 * 1024 : 160 * 1024;
     static constexpr long lds_bytes(int ty) {
         long cells = 0;
         for (int s = 1; s < K; ++s) cells += (long)(kTbTx + 2 * (K - s)) * (ty + 2 * hy * (K - s));
@@ -73,7 +73,11 @@ struct TbShape {
     }
     static constexpr int pick() {
         if (VS::D == 2) return lds_bytes(1) <= budget ? 1 : 0;
-        for (int ty = 16; ty >= 4; ty /= 2)
+        // taller tiles (less ring overhead, one 1024-thread block per CU) pay off for the 4- and
+        // 8-byte formats with three or more steps; the 16-bit ones run faster with more, smaller
+        // blocks (measured, D3Q7 256^3)
+        const int top = (K >= 3 && sizeof(typename ST::elem) >= 4) ? 32 : 16;
+        for (int ty = top; ty >= 4; ty /= 2)
             if (lds_bytes(ty) <= budget) return ty;
         return 0;
     }
