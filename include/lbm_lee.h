@@ -212,8 +212,14 @@ lbm_status lbm_lee_reinit(lbm_lee_handle h, const double *rho, const double *u, 
 lbm_status lbm_lee_reinit_region(lbm_lee_handle h, const int64_t origin[3], const int64_t n_sub[3], const double *rho,
                                  const double *u, const double *theta, void *stream);
 
-/* Advance nsteps >= 0 time steps (fused pull-stream + moments + equilibrium + relaxation,
- * one kernel launch per step, periodic box). */
+/* Advance nsteps >= 0 time steps (Section "Derivation of the Lattice Boltzmann Equation", the
+ * fully discrete update: fused pull-stream + moments + equilibrium + relaxation), enqueued on
+ * `stream`.  One-step variants launch one kernel per step (plus, on open boxes, the boundary
+ * kernels of LBM_BC_*); TB2/TB3 launch one kernel per two/three steps and one-step kernels for a
+ * remainder of nsteps, so the result does not depend on how the steps are split over calls
+ * (every kernel gives the same bits).  The step counter advances by nsteps.  Errors:
+ * LBM_E_INVALID for a NULL handle or nsteps < 0, LBM_E_STATE for an LBM_BC_MLP handle without
+ * lbm_lee_set_closure, LBM_E_HIP if a launch fails. */
 lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream);
 
 /*

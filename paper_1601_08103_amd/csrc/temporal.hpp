@@ -1,8 +1,10 @@
-// K time steps per launch (temporal blocking, K = 2 or 3) for periodic boxes.
+// K time steps per launch (temporal blocking, K = 2 or 3; the ring sets allow 4) for periodic
+// boxes.
 //
-// The pull update of Section "The lattice Boltzmann scheme" reads, for every cell, population
-// i of the neighbour x - c_i; K updates in a row therefore need the state of step t on the
-// cells within K stencil hops of a tile, the state of step t+1 within K-1 hops, and so on.
+// The pull form of the update of Section "Derivation of the Lattice Boltzmann Equation" reads,
+// for every cell, population i of the neighbour x - c_i; K updates in a row therefore need the
+// state of step t on the cells within K stencil hops of a tile, the state of step t+1 within
+// K-1 hops, and so on.
 // One block owns a tile of the box and marches along the last axis ("march" axis z in 3D, y
 // in 2D), one plane at a time.  Per iteration, stage s (s = 1..K) computes step t+s on one
 // plane of the tile dilated by K-s cells (in x, and in y in 3D), s-1 planes behind stage 1:
