@@ -180,7 +180,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     constexpr int IR = SKIP0 ? -1 : F::local(0);  // the rest population, when it is updated
     static_assert(F::planes(K) > 0, "some population moves within the plane");
     // planes of loads in flight: two where the registers allow (up to 9 velocities)
-    constexpr int PF = Q <= 9 ? 2 : 1;
+    constexpr int PF = (Q <= 9 && K <= 3) ? 2 : 1;
     // LDS ring set s (s = 1..K-1) holds stage s's results on the tile dilated by K - s
     auto set_dx = [](int s) { return TX + 2 * (K - s); };
     auto set_pl = [](int s) { return (TX + 2 * (K - s)) * (TY + 2 * HY * (K - s)); };
