@@ -302,7 +302,8 @@ def reflection(lattice, closure, fields, L=512, E=1536, steps=1024, every=8, par
 def time_solver(sim, steps=200, graph=False):
     """ms per step.  graph=True replays a captured graph of six steps (no host launch cost per
     kernel; six is a whole number of launches for the one-, two- and three-step kernels); the
-    replays advance the buffers but not the handle's step counter."""
+    replays advance the buffers but not the handle's step counter (timing only: with the two-step
+    kernel the three launches do not end in the buffer they started from)."""
     import torch
     sim.step(10)
     torch.cuda.synchronize()
