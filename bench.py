@@ -202,13 +202,16 @@ def main():
         torch.cuda.synchronize()
         t_host = time.perf_counter() - t_host
         ms = ev0.elapsed_time(ev2)
-        launch_ms = ev0.elapsed_time(ev1) / (main // spl) if main else float("nan")
-        log(f"{storage}: {K} steps in {ms:.3f} ms (host {t_host * 1e3:.3f} ms); {main // spl} launches of "
-            f"{spl} steps, {launch_ms * 1e3:.1f} us each")
-        return sim, ms, launch_ms
+        if main:
+            launch_ms = ev0.elapsed_time(ev1) / (main // spl)
+        else:  # fewer steps than one multi-step launch: only one-step launches ran
+            spl, launch_ms = 1, ms / K
+        log(f"{storage}: {K} steps in {ms:.3f} ms (host {t_host * 1e3:.3f} ms); {max(main // spl, K - main)} "
+            f"launches of {spl} steps, {launch_ms * 1e3:.1f} us each")
+        return sim, ms, launch_ms, spl
 
     if args.profile_only:
-        sim, ms, _ = timed_run(args.storage)
+        sim, ms, _, _ = timed_run(args.storage)
         log(f"profile-only: {N * K / (ms / 1e3) / 1e6:.1f} MLUPS, {sim.bytes_per_update} B/LU")
         if args.with_copy:
             nbytes = N * 7 * 4
@@ -228,11 +231,11 @@ def main():
     results = {}
     moments = {}
     for mode in modes:
-        sim, ms, launch_ms = timed_run(mode)
+        sim, ms, launch_ms, spl = timed_run(mode)
         m = sim.moments()
         moments[mode] = (m["p"].clone(), m["u"].clone())
-        results[mode] = dict(ms=ms, launch_ms=launch_ms, bpu=sim.bytes_per_update, scale=sim.store_scale,
-                             variant=sim.variant)
+        results[mode] = dict(ms=ms, launch_ms=launch_ms, spl=spl, bpu=sim.bytes_per_update, scale=sim.store_scale,
+                             variant=sim.variant if spl > 1 or sim.variant not in ("tb2", "tb3") else "generic")
         sim.close()
         del sim
     p_ref, u_ref = moments["f64"]
@@ -245,7 +248,7 @@ def main():
     storage_modes = {}
     for mode, r in results.items():
         mlups = N * K / (r["ms"] / 1e3) / 1e6
-        spl = steps_per_launch(r["variant"])
+        spl = r["spl"]
         # algorithmic HBM bytes per launch (one read and one write of the moving populations)
         # over the time per launch
         gbs = N * r["bpu"] / (r["launch_ms"] / 1e3) / 1e9
@@ -279,7 +282,7 @@ def main():
     ms_step = results[args.storage]["ms"] / K
     bpu = results[args.storage]["bpu"]
     variant = results[args.storage]["variant"]
-    spl = steps_per_launch(variant)
+    spl = results[args.storage]["spl"]
     launch_ms = results[args.storage]["launch_ms"]
     achieved = N * bpu / (launch_ms / 1e3) / 1e9
     traffic = traffic_from_counters(args.storage, n, variant)
