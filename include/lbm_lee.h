@@ -172,6 +172,18 @@ size_t lbm_lee_state_bytes(const lbm_lee_desc *desc);
 /* Bytes of device scratch lbm_lee_init needs (reductions, scale search).  0 on a bad desc. */
 size_t lbm_lee_scratch_bytes(const lbm_lee_desc *desc);
 
+/* The collision constants of the step kernels, in FP64 before they are rounded to the compute
+ * type (host only, no GPU work).  The paper's update (Section "Derivation of the Lattice Boltzmann
+ * Equation": moments, equilibrium of Section "Derivation of Finite Discrete Velocity Models for
+ * Monoatomic Gases" / "Generalization of the Finite Discrete Velocity Ansatz for Polyatomic
+ * Gases", relaxation with tau) is linear in the per-shell sums S_sh = sum s_i and J_sh =
+ * sum c_i s_i of the stored values (shell sh = |c|^2 in 0..3); a population of shell `to` becomes
+ *   keep s + sum_from H[to*4 + from] S_from + c . sum_from WB[to*4 + from] J_from.
+ * Storage units: F64/F32 store g itself; the 16-bit formats store S g/f* with S =
+ * desc->store_scale (1 if 0: the automatic choice is made at lbm_lee_init).  Entries of shells the
+ * set lacks are meaningless.  Errors: LBM_E_INVALID for NULL outputs or a bad desc. */
+lbm_status lbm_lee_collision_constants(const lbm_lee_desc *desc, double H[16], double WB[16], double *keep);
+
 /* Algorithmic HBM bytes per lattice-cell update of the step kernel: Q loads and Q stores of
  * the storage element (2 Q s), or 2 (Q - 1) s when the rest population is left out of the step.
  * It is left out when the equilibrium map leaves it invariant (E_00 = 1, E_0j = E_j0 = 0:

@@ -248,33 +248,46 @@ Kc<CT> split(double v) {
 // checked that every population of a shell has the same f*_i and beta_i.
 // raw_unit: the step works on stored values times raw_unit (the storage type's raw domain, 1
 // for the plain formats): the moment constants take 1/raw_unit, the equilibrium weight raw_unit.
-template <typename CT, int Q>
-StepCoef<CT, Q> step_coef(const lbm_lee *h, double raw_unit = 1.0) {
-    const FieldCoef<Q> f = field_coef<Q>(h);
-    StepCoef<CT, Q> k;
-    std::memset(&k, 0, sizeof k);
-    const double omega = 1.0 / h->desc.tau;
-    const LatticeTable &t = h->tab;
-    // per-shell constants in FP64 (the host checks that they agree within a shell)
+// The collision folded into two FP64 matrices per shell pair (see StepCoef): per-shell constants
+// of the storage mode (scale S for the 16-bit formats, raw_unit for a raw step domain), then
+// A = kA rho' + kA' e and C = kC rho' + kC' e after eliminating theta'.
+void fold_constants(const LatticeTable &t, int storage, double S, double tau, double raw_unit,
+                    double H[kShells][kShells], double WB[kShells][kShells], double &keep) {
+    const bool scaled = is_scaled(storage);
+    const double omega = 1.0 / tau;
     double dec[kShells] = {}, edec[kShells] = {}, bu[kShells] = {}, w[kShells] = {};
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 0; i < t.Q; ++i) {  // shell_uniform() has checked that a shell's constants agree
         const int sh = t.c[i][0] * t.c[i][0] + t.c[i][1] * t.c[i][1] + t.c[i][2] * t.c[i][2];
-        dec[sh] = f.dec[i] / raw_unit;
-        edec[sh] = f.e[i] * f.dec[i] / raw_unit;
-        bu[sh] = f.b * f.dec[i] / f.rho0 / raw_unit;
-        w[sh] = omega * f.enc[i] * f.f[i] * raw_unit;
+        const double d = scaled ? t.f[i] / S : 1.0, e = scaled ? S / t.f[i] : 1.0;
+        dec[sh] = d / raw_unit;
+        edec[sh] = 0.5 * (sh + t.beta[i]) * d / raw_unit;
+        bu[sh] = t.b * d / t.rho0 / raw_unit;
+        w[sh] = omega * e * t.f[i] * raw_unit;
     }
-    // A = kA rho' + kA' e and C = kC rho' + kC' e after eliminating theta'
-    const double gm1_rho0 = f.gm1 / f.rho0, theta0_rho0 = f.theta0 / f.rho0;
-    const double kA = f.a1 - f.a2 * theta0_rho0, kAe = f.a2 * gm1_rho0;
-    const double kC = f.c1 - f.c2 * theta0_rho0, kCe = f.c2 * gm1_rho0;
+    const double gm1_rho0 = (t.gamma - 1.0) / t.rho0, theta0_rho0 = t.theta0 / t.rho0;
+    const double kA = t.a1 - t.a2 * theta0_rho0, kAe = t.a2 * gm1_rho0;
+    const double kC = t.c1 - t.c2 * theta0_rho0, kCe = t.c2 * gm1_rho0;
     for (int to = 0; to < kShells; ++to)
         for (int from = 0; from < kShells; ++from) {
             const double gA = kA * dec[from] + kAe * edec[from], gC = kC * dec[from] + kCe * edec[from];
-            k.H[to][from] = split<CT>(w[to] * (gA + 0.5 * to * gC));
-            k.WB[to][from] = split<CT>(w[to] * bu[from]);
+            H[to][from] = w[to] * (gA + 0.5 * to * gC);
+            WB[to][from] = w[to] * bu[from];
         }
-    k.keep = split<CT>(1.0 - omega);
+    keep = 1.0 - omega;
+}
+
+template <typename CT, int Q>
+StepCoef<CT, Q> step_coef(const lbm_lee *h, double raw_unit = 1.0) {
+    StepCoef<CT, Q> k;
+    std::memset(&k, 0, sizeof k);
+    double H[kShells][kShells], WB[kShells][kShells], keep;
+    fold_constants(h->tab, h->desc.storage, h->S, h->desc.tau, raw_unit, H, WB, keep);
+    for (int to = 0; to < kShells; ++to)
+        for (int from = 0; from < kShells; ++from) {
+            k.H[to][from] = split<CT>(H[to][from]);
+            k.WB[to][from] = split<CT>(WB[to][from]);
+        }
+    k.keep = split<CT>(keep);
     return k;
 }
 
@@ -507,6 +520,21 @@ size_t lbm_lee_scratch_bytes(const lbm_lee_desc *d) {
     LatticeTable t;
     if (check_desc(d, &t) != LBM_OK) return 0;
     return kScratchBytes;
+}
+
+lbm_status lbm_lee_collision_constants(const lbm_lee_desc *desc, double H[16], double WB[16], double *keep) {
+    if (!H || !WB || !keep) return fail(LBM_E_INVALID, "H, WB or keep is NULL");
+    LatticeTable t;
+    const lbm_status s = check_desc(desc, &t);
+    if (s != LBM_OK) return s;
+    double h2[kShells][kShells], w2[kShells][kShells];
+    fold_constants(t, desc->storage, desc->store_scale > 0.0 ? desc->store_scale : 1.0, desc->tau, 1.0, h2, w2, *keep);
+    for (int to = 0; to < kShells; ++to)
+        for (int from = 0; from < kShells; ++from) {
+            H[to * kShells + from] = h2[to][from];
+            WB[to * kShells + from] = w2[to][from];
+        }
+    return ok();
 }
 
 double lbm_lee_bytes_per_update(const lbm_lee_desc *d) {

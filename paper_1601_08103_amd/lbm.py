@@ -55,6 +55,7 @@ SIGNATURES = {
     "lbm_lee_state_bytes": (ctypes.c_size_t, [_DESC_P]),
     "lbm_lee_scratch_bytes": (ctypes.c_size_t, [_DESC_P]),
     "lbm_lee_bytes_per_update": (ctypes.c_double, [_DESC_P]),
+    "lbm_lee_collision_constants": (ctypes.c_int, [_DESC_P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_lee_init": (ctypes.c_int32, [_DESC_P, _VP, _VP, ctypes.c_size_t, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP,
                                       ctypes.POINTER(_VP)]),
     "lbm_lee_reinit": (ctypes.c_int32, [_VP, _VP, _VP, _VP, _VP]),
@@ -156,6 +157,16 @@ def lbm_lee_scratch_bytes(desc) -> int:
 
 def lbm_lee_bytes_per_update(desc) -> float:
     return float(load().lbm_lee_bytes_per_update(ctypes.byref(desc)))
+
+
+def lbm_lee_collision_constants(desc):
+    """(H (4, 4), WB (4, 4), keep): the step kernels' folded collision constants in FP64."""
+    H = np.zeros(16)
+    WB = np.zeros(16)
+    keep = ctypes.c_double(0.0)
+    _check("lbm_lee_collision_constants",
+           load().lbm_lee_collision_constants(ctypes.byref(desc), H.ctypes.data, WB.ctypes.data, ctypes.byref(keep)))
+    return H.reshape(4, 4), WB.reshape(4, 4), keep.value
 
 
 def lbm_lee_init(desc, pop_a, pop_b, bytes_each, rho, u, theta, scratch, scratch_bytes, stream) -> int:

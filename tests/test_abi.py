@@ -207,3 +207,28 @@ def test_temporal_blocking_variants_accepted(lattice, storage):
         d3 = lbm.make_desc(lattice, storage, shape, variant="tb3", tune=tune)
         fits3 = not (lattice in ("D3Q13", "D3Q19") and storage == "f64")
         assert (lbm.lbm_lee_state_bytes(d3) > 0) == fits3
+
+
+@pytest.mark.parametrize("lattice", ["D1Q3", "D2Q5", "D2Q9", "D3Q7", "D3Q9", "D3Q13", "D3Q19", "D2Q5_DIA", "D3Q7_DIA"])
+@pytest.mark.parametrize("storage,scale", [("f64", 0.0), ("f16", 64.0)])
+@pytest.mark.parametrize("tau", [0.5, 0.8])
+def test_folded_collision_constants_match_the_oracle_update(lattice, storage, scale, tau):
+    """The step kernels' folded constants rebuild the oracle's update matrix H(tau) = (1 - 1/tau) I
+    + E / tau entry by entry: for populations i (shell a) and j (shell b), in storage units
+    (s = S g / f* for the 16-bit formats), H_ij = keep delta_ij + (H[a][b] + (c_i . c_j) WB[a][b]) f*_i / f*_j
+    (the factor is 1 for unscaled storage)."""
+    from oracle import lbe
+    lat = L.get(lattice)
+    D = lat.D
+    shape = {1: (64,), 2: (8, 8), 3: (4, 4, 4)}[D]
+    H, WB, keep = lbm.lbm_lee_collision_constants(lbm.make_desc(lattice, storage, shape, tau=tau, store_scale=scale))
+    assert keep == 1.0 - 1.0 / tau
+    c = np.array(lat.c, dtype=np.int64).reshape(lat.Q, -1)
+    c3 = np.zeros((lat.Q, 3), dtype=np.int64)
+    c3[:, :c.shape[1]] = c
+    sh = (c3 * c3).sum(axis=1)
+    f = np.asarray(lat.fstar, dtype=np.float64)
+    ratio = np.outer(f, 1.0 / f) if storage != "f64" else np.ones((lat.Q, lat.Q))
+    rebuilt = keep * np.eye(lat.Q) + (H[sh][:, sh] + (c3 @ c3.T) * WB[sh][:, sh]) * ratio
+    want = lbe.update_matrix(lat, tau)
+    assert np.abs(rebuilt - want).max() <= 1e-14 * max(1.0, np.abs(want).max())
