@@ -114,10 +114,11 @@ typedef int32_t lbm_status;
 
 /* Step kernel variant.  All variants run the same per-cell arithmetic, so their results are
  * bitwise identical; they differ only in how the streamed values are gathered. */
-#define LBM_VARIANT_AUTO 0    /* the fastest measured variant: on periodic 2D/3D boxes of     */
-                              /* >= 2^20 cells TB3 (sets of <= 9 velocities) or TB2 where they */
-                              /* are supported; else GENERIC for 4- and 8-byte storage,        */
-                              /* DPP/DPP2/GENERIC (by nx) for 2-byte storage                   */
+#define LBM_VARIANT_AUTO 0    /* the fastest measured variant: OPEN2D on 2D open boxes; on    */
+                              /* periodic 2D/3D boxes of >= 2^20 cells TB3 (sets of <= 9       */
+                              /* velocities) or TB2 where they are supported; else GENERIC for */
+                              /* 4- and 8-byte storage, DPP/DPP2/GENERIC (by nx) for 2-byte    */
+                              /* storage                                                       */
 #define LBM_VARIANT_GENERIC 1 /* one thread per cell, per-element wrapped gathers            */
 #define LBM_VARIANT_DPP 2     /* 4 cells per lane, aligned vector loads, x shift by DPP;   */
                               /* needs nx % 4 == 0                                          */
@@ -136,6 +137,13 @@ typedef int32_t lbm_status;
  * LBM_E_UNSUPPORTED where they do not fit at TY = 4 (D3Q13 and D3Q19 with FP64) and in the
  * cases TB2 refuses.  A remainder of the step count (mod 3) runs one-step launches. */
 #define LBM_VARIANT_TB3 6
+/* 2D open boxes (every boundary but LBM_BC_PERIODIC): one launch per step.  Blocks of the ring
+ * (the cells on a face) and blocks of the interior run side by side; with LBM_BC_MLP each wave
+ * of the ring evaluates the closure network for the face nodes its ring cells pull from and
+ * keeps the predictions in LDS.  Same values, ghost buffer and history as the separate
+ * network, bulk and boundary kernels of the other variants; LBM_TUNE_CLOSURE_STREAM has no
+ * effect.  LBM_E_UNSUPPORTED for periodic boxes and for 1D and 3D lattices. */
+#define LBM_VARIANT_OPEN2D 7
 
 typedef struct lbm_lee_desc {
     int32_t lattice;     /* LBM_D1Q3 ...                                                    */

@@ -138,7 +138,7 @@ lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
     if (N * tab->Q > 9.0e18 / 8.0) return fail(LBM_E_INVALID, "domain too large");
     if ((double)d->n[1] * (double)d->n[2] * 16.0 > 4.0e9) return fail(LBM_E_INVALID, "too many rows (ny * nz)");
     if (!(d->tau >= 0.5) || !std::isfinite(d->tau)) return fail(LBM_E_INVALID, "tau must be finite and >= 1/2 (got %g)", d->tau);
-    if (d->variant < LBM_VARIANT_AUTO || d->variant > LBM_VARIANT_TB3) return fail(LBM_E_INVALID, "unknown variant %d", d->variant);
+    if (d->variant < LBM_VARIANT_AUTO || d->variant > LBM_VARIANT_OPEN2D) return fail(LBM_E_INVALID, "unknown variant %d", d->variant);
     if (d->tune < 0 || d->tune > 255) return fail(LBM_E_INVALID, "unknown tune bits 0x%x", d->tune);
     if (d->variant == LBM_VARIANT_TB2 || d->variant == LBM_VARIANT_TB3) {
         const int K = d->variant == LBM_VARIANT_TB2 ? 2 : 3;
@@ -150,6 +150,8 @@ lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
         if (!tb_plane_fits(d, tab->D))
             return fail(LBM_E_UNSUPPORTED, "the %d-step variant addresses a plane with 32-bit byte offsets (< 4 GiB)", K);
     }
+    if (d->variant == LBM_VARIANT_OPEN2D && (tab->D != 2 || d->bc == LBM_BC_PERIODIC))
+        return fail(LBM_E_UNSUPPORTED, "the one-launch open-box step needs a 2D lattice and an open boundary");
     if (d->tune & kTuneInPlace) {
         if (d->bc != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "in-place streaming needs the periodic box");
         if (d->variant != LBM_VARIANT_AUTO && d->variant != LBM_VARIANT_GENERIC)
@@ -388,6 +390,9 @@ lbm_status launch_check() {
 int resolve_variant(const lbm_lee *h) {
     if (h->inplace) return LBM_VARIANT_GENERIC;  // the in-place kernels are one thread per cell
     if (h->desc.variant != LBM_VARIANT_AUTO) return h->desc.variant;
+    // 2D open boxes: ring, interior and closure network in one launch (the separate kernels of
+    // the other variants are each latency-bound on boxes of this size)
+    if (h->desc.bc != LBM_BC_PERIODIC && h->tab.D == 2) return LBM_VARIANT_OPEN2D;
     // periodic boxes of a million cells and more: three steps per launch for the sets of up to 9
     // velocities, two for the larger ones (their two collisions per column already fill the
     // registers), for every storage mode
@@ -825,6 +830,40 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
                 }
                 return fail(LBM_E_UNSUPPORTED, "the %d-step variant does not support this lattice and storage", K);
             };
+            if (variant == LBM_VARIANT_OPEN2D) {
+                if constexpr (VS::D == 2) {
+                    const int nx = h->nx, ny = h->ny;
+                    const long long ring = 2LL * ny + 2LL * (nx - 2);
+                    const unsigned face_blocks = bc == LBM_BC_MLP ? (unsigned)((open2d_segments(nx, ny) + 3) / 4)
+                                                                  : (unsigned)((ring + 255) / 256);
+                    const long long interior = (long long)(nx - 2) * (ny - 2);
+                    const unsigned bulk_blocks = (unsigned)std::min<long long>((interior + 255) / 256, 1LL << 20);
+                    for (int64_t t = 0; t < nsteps; ++t) {
+                        const E *src = static_cast<const E *>(h->buf[h->cur]);
+                        E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);
+                        if (bc == LBM_BC_MLP) {
+                            float *hist = h->ghost + nodes * (long long)net_outputs(h->tab);
+                            const float *hin = h->hist_valid ? hist + (long long)h->cur * nodes * nstrip : nullptr;
+                            float *hout = hist + (long long)(h->cur ^ 1) * nodes * nstrip;
+                            open_step_2d<VS, ST, SK, HF, true><<<face_blocks + bulk_blocks, 256, 0, st>>>(
+                                src, dst, h->N, bc, (int)face_blocks, h->net, h->ghost, hin, hout, ft, k, ks, fk);
+                            h->hist_valid = true;
+                        } else {
+                            open_step_2d<VS, ST, SK, HF, false><<<face_blocks + bulk_blocks, 256, 0, st>>>(
+                                src, dst, h->N, bc, (int)face_blocks, nullptr, nullptr, nullptr, nullptr, ft, k, ks, fk);
+                            if (bc == LBM_BC_SPONGE)
+                                sponge_kernel<VS, ST><<<dim3(sponge_x, 2 * VS::D), 256, 0, st>>>(
+                                    dst, h->N, h->nx, h->ny, h->nz, h->desc.sponge_width, h->desc.sponge_sigma);
+                        }
+                        lbm_status ls = launch_check();
+                        if (ls != LBM_OK) return ls;
+                        h->cur ^= 1;
+                        h->steps += 1;
+                    }
+                    return LBM_OK;
+                }
+                return fail(LBM_E_UNSUPPORTED, "the one-launch open-box step needs a 2D lattice");
+            }
             if (variant == LBM_VARIANT_TB2) return run_tbk(std::integral_constant<int, 2>{});
             if (variant == LBM_VARIANT_TB3) return run_tbk(std::integral_constant<int, 3>{});
             for (int64_t t = 0; t < nsteps; ++t) {

@@ -291,31 +291,25 @@ __device__ floatx4 net_forward_tile_staged(const NetFrags<VS> &F, TT &T, int lan
     return acc;
 }
 
-// Load a tile of raw strips (rows >= nrows are zero) into T.z as bf16 of x / rms(x); returns
-// rms of row (lane & 15) in every lane that holds that row.  X(row, v) gives strip value v.
-// With EW (v -> weight, 0 for most inputs), also returns in *m_out the row's max |x| and in
-// *e_out sum_v EW(v) (x_v / max|x|)^2 (an energy in units of the row's max, no underflow).
-// ON(row, v, x) sees every loaded value (row < nrows, v < n_in).
-// A row whose max is below 2^-100 is scaled by 2^64 first (exact), so the reciprocals of its
-// max and rms cannot overflow; the returned max and rms are scaled back.
-template <class VS, class TT, class LoadFn, class EWFn, class OnFn>
-__device__ float load_normalised_tile(TT &T, int nrows, int lane, LoadFn X, EWFn EW, float *m_out, float *e_out,
-                                      OnFn ON) {
+// Values of a tile per lane: v = g + 4 t (t < tile_vals) of row lane & 15, g = lane >> 4.
+template <class VS>
+constexpr int tile_vals() {
+    return (NetGeom<VS>::NIN_PAD + 3) / 4;
+}
+
+// Normalise a tile whose values are already in registers (vals, zero for rows >= nrows and
+// v >= n_in) into T.z as bf16 of x / rms(x); returns rms of row (lane & 15) in every lane that
+// holds that row.  With EW (v -> weight, 0 for most inputs), also returns in *m_out the row's
+// max |x| and in *e_out sum_v EW(v) (x_v / max|x|)^2 (an energy in units of the row's max, no
+// underflow).  A row whose max is below 2^-100 is scaled by 2^64 first (exact), so the
+// reciprocals of its max and rms cannot overflow; the returned max and rms are scaled back.
+template <class VS, class TT, class EWFn>
+__device__ float normalise_tile(TT &T, int lane, float (&vals)[tile_vals<VS>()], EWFn EW, float *m_out, float *e_out) {
     using G = NetGeom<VS>;
     const int r = lane & 15, g = lane >> 4;
-    float vals[(G::NIN_PAD + 3) / 4];
     float m = 0.0f;
 #pragma unroll
-    for (int t = 0; t < (G::NIN_PAD + 3) / 4; ++t) {
-        const int v = g + 4 * t;
-        float x = 0.0f;
-        if (r < nrows && v < G::NIN) {
-            x = X(r, v);
-            ON(r, v, x);
-        }
-        vals[t] = x;
-        m = fmaxf(m, fabsf(x));
-    }
+    for (int t = 0; t < tile_vals<VS>(); ++t) m = fmaxf(m, fabsf(vals[t]));
     m = fmaxf(m, __shfl_xor(m, 16, 64));
     m = fmaxf(m, __shfl_xor(m, 32, 64));
     const float pre = m < 0x1p-100f ? 0x1p64f : 1.0f;
@@ -323,7 +317,7 @@ __device__ float load_normalised_tile(TT &T, int nrows, int lane, LoadFn X, EWFn
     const float im = m > 0.0f ? 1.0f / m : 0.0f;
     float ss = 0.0f, ee = 0.0f;
 #pragma unroll
-    for (int t = 0; t < (G::NIN_PAD + 3) / 4; ++t) {
+    for (int t = 0; t < tile_vals<VS>(); ++t) {
         vals[t] *= pre;
         const float q = vals[t] * im;
         ss += q * q;
@@ -337,7 +331,7 @@ __device__ float load_normalised_tile(TT &T, int nrows, int lane, LoadFn X, EWFn
     const float s = m * sqrtf(ss / (float)G::NIN);
     const float is = s > 0.0f ? 1.0f / s : 0.0f;
 #pragma unroll
-    for (int t = 0; t < (G::NIN_PAD + 3) / 4; ++t) {
+    for (int t = 0; t < tile_vals<VS>(); ++t) {
         const int v = g + 4 * t;
         if (v < G::NIN_PAD) T.z[r][v] = v < G::NIN ? bf16_bits(vals[t] * is) : (unsigned short)0;
     }
@@ -345,6 +339,27 @@ __device__ float load_normalised_tile(TT &T, int nrows, int lane, LoadFn X, EWFn
     if (m_out) *m_out = m / pre;
     if (e_out) *e_out = ee;
     return s / pre;
+}
+
+// Load a tile of raw strips (rows >= nrows are zero) and normalise it as normalise_tile does.
+// X(row, v) gives strip value v; ON(row, v, x) sees every loaded value (row < nrows, v < n_in).
+template <class VS, class TT, class LoadFn, class EWFn, class OnFn>
+__device__ float load_normalised_tile(TT &T, int nrows, int lane, LoadFn X, EWFn EW, float *m_out, float *e_out,
+                                      OnFn ON) {
+    using G = NetGeom<VS>;
+    const int r = lane & 15, g = lane >> 4;
+    float vals[tile_vals<VS>()];
+#pragma unroll
+    for (int t = 0; t < tile_vals<VS>(); ++t) {
+        const int v = g + 4 * t;
+        float x = 0.0f;
+        if (r < nrows && v < G::NIN) {
+            x = X(r, v);
+            ON(r, v, x);
+        }
+        vals[t] = x;
+    }
+    return normalise_tile<VS>(T, lane, vals, EW, m_out, e_out);
 }
 template <class VS, class TT, class LoadFn, class EWFn>
 __device__ float load_normalised_tile(TT &T, int nrows, int lane, LoadFn X, EWFn EW, float *m_out, float *e_out) {

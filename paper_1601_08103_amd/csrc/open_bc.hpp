@@ -86,6 +86,62 @@ __device__ inline int node_cell(const FaceTab<Q> &ft, long long g, int (&p)[3]) 
 }
 
 // ------------------------------------------------------------------ shell recompute
+// Streamed values of boundary cell x, in two passes: shell_inside takes every source inside the
+// box (every source with COPY, clamped) from the state and leaves 0 for the others (ZERO,
+// SPONGE); shell_outside then fills, with MLP, each outside source with the mean over the
+// faces it lies beyond of the prediction GH(face, clamp(s), entering rank).
+template <class VS, class ST, bool SKIP0>
+__device__ inline void shell_inside(const typename ST::elem *__restrict__ src, size_t N, int closure,
+                                    const int (&x)[3], const FaceTab<VS::Q> &ft, typename ST::comp (&s)[VS::Q]) {
+    using CT = typename ST::comp;
+    s[0] = 0;
+#pragma unroll
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) {
+        const int c[3] = {VS::cx(i), VS::cy(i), VS::cz(i)};
+        int cl[3];
+        bool inside = true;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const int sp = x[b] - c[b];
+            cl[b] = min(max(sp, 0), ft.n[b] - 1);
+            inside = inside && sp == cl[b];
+        }
+        const size_t scell = ((size_t)cl[2] * ft.n[1] + cl[1]) * ft.n[0] + cl[0];
+        s[i] = (inside || closure == kBcCopy) ? (CT)ST::dec(src[(size_t)i * N + scell]) : (CT)0;
+    }
+}
+
+template <class VS, class ST, bool SKIP0, class GH>
+__device__ inline void shell_outside(const int (&x)[3], const FaceTab<VS::Q> &ft, const FieldCoef<VS::Q> &fk,
+                                     typename ST::comp (&s)[VS::Q], GH ghost_at) {
+    using CT = typename ST::comp;
+#pragma unroll
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) {
+        const int c[3] = {VS::cx(i), VS::cy(i), VS::cz(i)};
+        int sp[3], cl[3];
+        bool inside = true;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            sp[b] = x[b] - c[b];
+            cl[b] = min(max(sp[b], 0), ft.n[b] - 1);
+            inside = inside && sp[b] == cl[b];
+        }
+        if (inside) continue;
+        float acc = 0.0f;
+        int cnt = 0;
+#pragma unroll
+        for (int b = 0; b < VS::D; ++b) {
+            if (sp[b] != cl[b]) {
+                const int fb = 2 * b + (sp[b] > cl[b] ? 1 : 0);
+                const int r = ft.rank[fb][i];
+                acc += ghost_at(fb, cl, r < 0 ? 0 : r);
+                ++cnt;
+            }
+        }
+        s[i] = (CT)(acc / (float)cnt) * (CT)fk.enc[i];
+    }
+}
+
 template <class VS, class ST, bool SKIP0, bool HALF = false>
 __global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__restrict__ src,
                                                     typename ST::elem *__restrict__ dst, size_t N, int closure,
@@ -114,38 +170,11 @@ __global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__r
     constexpr int K = NetGeom<VS>::NOUT;
 
     CT s[VS::Q];
-    s[0] = 0;
-#pragma unroll
-    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) {
-        const int c[3] = {VS::cx(i), VS::cy(i), VS::cz(i)};
-        int sp[3], cl[3];
-        bool inside = true;
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            sp[b] = x[b] - c[b];
-            cl[b] = min(max(sp[b], 0), ft.n[b] - 1);
-            inside = inside && sp[b] == cl[b];
-        }
-        const size_t scell = ((size_t)cl[2] * ft.n[1] + cl[1]) * ft.n[0] + cl[0];
-        CT v = 0;
-        if (inside || closure == kBcCopy) {
-            v = ST::dec(src[(size_t)i * N + scell]);
-        } else if (closure == kBcMlp) {
-            float acc = 0.0f;
-            int cnt = 0;
-#pragma unroll
-            for (int b = 0; b < VS::D; ++b) {
-                if (sp[b] != cl[b]) {
-                    const int fb = 2 * b + (sp[b] > cl[b] ? 1 : 0);
-                    const int r = ft.rank[fb][i];
-                    acc += ghost[node_index(ft, fb, cl) * K + (r < 0 ? 0 : r)];
-                    ++cnt;
-                }
-            }
-            v = (CT)(acc / (float)cnt) * (CT)fk.enc[i];
-        }
-        s[i] = v;
-    }
+    shell_inside<VS, ST, SKIP0>(src, N, closure, x, ft, s);
+    if (closure == kBcMlp)
+        shell_outside<VS, ST, SKIP0>(x, ft, fk, s, [&](int fb, const int (&cl)[3], int r) {
+            return ghost[node_index(ft, fb, cl) * K + r];
+        });
     collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, s);
 #pragma unroll
     for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
@@ -285,6 +314,295 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
             for (int k = 0; k < G::NOUT; ++k) ghost[(base + lane) * G::NOUT + k] = sc * pred[wid][lane][k];
         }
         wave_lds_sync();
+    }
+}
+
+// ------------------------------------------------------------------ 2D open box, one launch per step
+// The step of a 2D open box as a single launch: blocks [0, face_blocks) recompute the ring (the
+// cells on a face), the blocks after them step the interior cells 0 < x < nx - 1, 0 < y < ny - 1
+// as the generic step kernel does.  Ring cells are owned as by the shell kernel: the x faces
+// hold their corners, the y faces the cells 0 < x < nx - 1 between them.
+//
+// With MLP every wave owns a segment of at most kOpenSeg ring cells of one face.  It evaluates
+// the network for the face nodes those cells pull from (rows of one 16-row tile): the segment's
+// own nodes and one more on each side, and, for a segment holding a corner cell of an x face,
+// the two nodes of the y face nearest that corner.  Predictions stay in LDS; each lane then
+// recomputes one ring cell.  Each network row depends on its own node only, so the values,
+// the ghost buffer and the history strips equal those of the separate network kernel (rows of
+// nodes that two waves evaluate are written twice with equal values).
+constexpr int kOpenSeg = 10;
+static_assert(kOpenSeg + 2 + 4 <= 16, "a segment's rows must fit one 16-row tile");
+
+struct OpenSeg {
+    int f, p0, m;  // face, first owned in-face position, owned cells
+};
+struct OpenRows {
+    int f, lo, nsame, cA, cB, nrows;  // see open2d_rows
+};
+
+// Owned in-face positions of face f: y in [0, ny) on the x faces, x in [1, nx - 1) on the y faces.
+__host__ __device__ inline void open2d_owned(int f, int nx, int ny, int &p_lo, int &p_end) {
+    p_lo = f < 2 ? 0 : 1;
+    p_end = f < 2 ? ny : nx - 1;
+}
+__host__ __device__ inline int open2d_face_segments(int f, int nx, int ny) {
+    int lo, end;
+    open2d_owned(f, nx, ny, lo, end);
+    return (end - lo + kOpenSeg - 1) / kOpenSeg;
+}
+__host__ __device__ inline int open2d_segments(int nx, int ny) {
+    int n = 0;
+    for (int f = 0; f < 4; ++f) n += open2d_face_segments(f, nx, ny);
+    return n;
+}
+__host__ __device__ inline OpenSeg open2d_segment(int w, int nx, int ny) {
+    OpenSeg sg{0, 0, 0};
+    for (int f = 0; f < 4; ++f) {
+        const int nf = open2d_face_segments(f, nx, ny);
+        if (w < nf) {
+            int lo, end;
+            open2d_owned(f, nx, ny, lo, end);
+            sg.f = f;
+            sg.p0 = lo + w * kOpenSeg;
+            sg.m = min(kOpenSeg, end - sg.p0);
+            return sg;
+        }
+        w -= nf;
+    }
+    return sg;
+}
+// Rows [0, nsame): nodes lo + j of the segment's face; rows cA, cA + 1 (cA >= 0 when the
+// segment holds the corner at y = 0 of an x face): y-low nodes at the corner's x and one
+// inward; rows cB, cB + 1 likewise for the corner at y = ny - 1 (y-high nodes).
+__host__ __device__ inline OpenRows open2d_rows(const OpenSeg &sg, int nx, int ny) {
+    OpenRows r;
+    r.f = sg.f;
+    const int nface = sg.f < 2 ? ny : nx;
+    r.lo = max(sg.p0 - 1, 0);
+    r.nsame = min(sg.p0 + sg.m, nface - 1) - r.lo + 1;
+    int n = r.nsame;
+    r.cA = r.cB = -1;
+    if (sg.f < 2 && sg.p0 == 0) {
+        r.cA = n;
+        n += 2;
+    }
+    if (sg.f < 2 && sg.p0 + sg.m == ny) {
+        r.cB = n;
+        n += 2;
+    }
+    r.nrows = n;
+    return r;
+}
+__host__ __device__ inline void open2d_row_node(const OpenRows &r, int j, int nx, int &f, int &p) {
+    if (j < r.nsame) {
+        f = r.f;
+        p = r.lo + j;
+        return;
+    }
+    const int x0 = r.f == 0 ? 0 : nx - 1, dir = r.f == 0 ? 1 : -1;
+    if (r.cA >= 0 && j < r.cA + 2) {
+        f = 2;
+        p = x0 + dir * (j - r.cA);
+    } else {
+        f = 3;
+        p = x0 + dir * (j - r.cB);
+    }
+}
+// Row of face fb's node at clamp position cl, for a source of a cell of the segment.
+__host__ __device__ inline int open2d_row_of(const OpenRows &r, int fb, const int (&cl)[3], int nx) {
+    if (fb == r.f) return (fb < 2 ? cl[1] : cl[0]) - r.lo;
+    const int d = r.f == 0 ? cl[0] : nx - 1 - cl[0];
+    return (fb == 2 ? r.cA : r.cB) + d;
+}
+// Ring cell c (0 <= c < 2 ny + 2 (nx - 2)) in the ownership order.
+__host__ __device__ inline void open2d_ring_cell(long long c, int nx, int ny, int (&x)[3]) {
+    x[2] = 0;
+    if (c < ny) {
+        x[0] = 0;
+        x[1] = (int)c;
+    } else if (c < 2LL * ny) {
+        x[0] = nx - 1;
+        x[1] = (int)(c - ny);
+    } else if (c < 2LL * ny + (nx - 2)) {
+        x[0] = 1 + (int)(c - 2LL * ny);
+        x[1] = 0;
+    } else {
+        x[0] = 1 + (int)(c - 2LL * ny - (nx - 2));
+        x[1] = ny - 1;
+    }
+}
+
+// Two 16 x 64 tiles per wave: the network's input z and its second hidden layer h2 share one
+// (z is dead once the first layer has read it).
+struct Open2dTiles {
+    unsigned short (&z)[16][64];
+    unsigned short (&h1)[16][64];
+    unsigned short (&h2)[16][64];
+};
+
+template <class VS, class ST, bool SKIP0, bool HALF>
+__device__ void open2d_ring_mlp(const typename ST::elem *__restrict__ src, typename ST::elem *__restrict__ dst,
+                                size_t N, const float *__restrict__ P, float *__restrict__ ghost,
+                                const float *__restrict__ hist_in, float *__restrict__ hist_out,
+                                const FaceTab<VS::Q> &ft, const StepCoef<typename ST::comp, VS::Q> &ks,
+                                const FieldCoef<VS::Q> &fk) {
+    using G = NetGeom<VS>;
+    using CT = typename ST::comp;
+    static_assert(VS::D == 2 && G::ZW == 64, "2D sets only");
+    constexpr int NS = G::NSTRIP, K = G::NOUT;
+    __shared__ NetFrags<VS> F;
+    __shared__ unsigned short zt[4][16][64], h1t[4][16][64];
+    __shared__ float pred[4][16][K];
+    __shared__ int perm_s[4][VS::Q];
+    __shared__ float dec_s[4][VS::Q], invf_s[4][VS::Q];
+    for (int t = threadIdx.x; t < 4 * VS::Q; t += 256) {
+        const int f = t / VS::Q, j = t - f * VS::Q;
+        const int i = ft.perm[f][j];
+        perm_s[f][j] = i;
+        dec_s[f][j] = (float)fk.dec[i];
+        invf_s[f][j] = (float)(1.0 / fk.f[i]);
+    }
+    __syncthreads();  // tables visible before the loads below
+    const int nx = ft.n[0], ny = ft.n[1];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int w = blockIdx.x * 4 + wid;
+    const bool active = w < open2d_segments(nx, ny);
+    const OpenSeg sg = open2d_segment(active ? w : 0, nx, ny);
+    const OpenRows plan = open2d_rows(sg, nx, ny);
+    // the loads of this lane's ring cell, of its tile values and of the weights are all issued
+    // before the wave waits for any of them
+    const bool owner = active && lane < sg.m;
+    int xc[3] = {0, 0, 0};
+    {
+        const int a = sg.f >> 1, q = sg.p0 + (owner ? lane : 0);
+        xc[a] = (sg.f & 1) ? ft.n[a] - 1 : 0;
+        xc[1 - a] = q;
+    }
+    CT s[VS::Q];
+    if (owner) shell_inside<VS, ST, SKIP0>(src, N, kBcMlp, xc, ft, s);
+
+    const int r = lane & 15, g = lane >> 4;
+    const bool row_ok = active && r < plan.nrows;
+    int f, pos;
+    open2d_row_node(plan, row_ok ? r : 0, nx, f, pos);
+    int p[3] = {0, 0, 0};
+    const int a = f >> 1, step = (f & 1) ? -1 : 1;
+    p[a] = (f & 1) ? ft.n[a] - 1 : 0;
+    p[1 - a] = pos;
+    const long long node = ft.node_off[f] + pos;
+    const size_t cell0 = (size_t)p[1] * nx + p[0];
+    const long long stride_a = a == 0 ? 1 : (long long)nx;
+    auto strip_now = [&](int v) {  // value v of this row's current strip
+        const int m = v / VS::Q, j = v - m * VS::Q;
+        const size_t cell = (size_t)((long long)cell0 + (long long)(m * step) * stride_a);
+        return dec_s[f][j] * (float)ST::dec(src[(size_t)perm_s[f][j] * N + cell]);
+    };
+    // input [strip(t), strip(t-1)]: the previous strip from the history (the current one again on
+    // the first step after the state was set); this step's strip becomes the next step's history
+    float vals[tile_vals<VS>()];
+#pragma unroll
+    for (int t = 0; t < tile_vals<VS>(); ++t) {
+        const int v = g + 4 * t;
+        float x = 0.0f;
+        if (row_ok && v < G::NIN) {
+            x = v < NS ? strip_now(v) : (hist_in ? hist_in[node * NS + (v - NS)] : strip_now(v - NS));
+            if (v < NS) hist_out[node * NS + v] = x;
+        }
+        vals[t] = x;
+    }
+    stage_forward_weights<VS>(P, F);  // ends with a block barrier
+    if (!active) return;
+
+    Open2dTiles T{zt[wid], h1t[wid], zt[wid]};
+    float mx = 0.0f, e_out = 0.0f;
+    const float sn = normalise_tile<VS>(
+        T, lane, vals, [&](int v) { return v < VS::Q && VS::cx(v) == -1 ? invf_s[f][v] : 0.0f; }, &mx, &e_out);
+    const floatx4 y = net_forward_tile_staged<VS>(F, T, lane);
+    const int col = lane & 15;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int row = 4 * (lane >> 4) + e;
+        const float srow = __shfl(sn, row, 64);
+        if (row < plan.nrows && col < K) pred[wid][row][col] = srow * y[e];
+    }
+    wave_lds_sync();
+    if (lane < plan.nrows) {  // lane == r: energies of this row's node in units of mx^2
+        float e_in = 0.0f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float v = pred[wid][lane][k] / mx;
+            e_in += v * v * invf_s[f][entering_index<VS>(k)];
+        }
+        const int nf = (p[0] == 0) + (p[0] == nx - 1) + (p[1] == 0) + (p[1] == ny - 1);
+        const float budget = e_out / (float)((1 << nf) - 1);
+        const float sc = e_in > budget ? sqrtf(budget / e_in) : 1.0f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float gv = sc * pred[wid][lane][k];
+            pred[wid][lane][k] = gv;
+            ghost[node * K + k] = gv;
+        }
+    }
+    wave_lds_sync();
+    if (!owner) return;
+    shell_outside<VS, ST, SKIP0>(xc, ft, fk, s, [&](int fb, const int (&cl)[3], int rk) {
+        return pred[wid][open2d_row_of(plan, fb, cl, nx)][rk];
+    });
+    collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(ks, s);
+    const size_t cell = (size_t)xc[1] * nx + xc[0];
+#pragma unroll
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
+}
+
+template <class VS, class ST, bool SKIP0, bool HALF, bool MLP>
+__global__ __launch_bounds__(256) void open_step_2d(const typename ST::elem *__restrict__ src,
+                                                    typename ST::elem *__restrict__ dst, size_t N, int closure,
+                                                    int face_blocks, const float *__restrict__ P,
+                                                    float *__restrict__ ghost, const float *__restrict__ hist_in,
+                                                    float *__restrict__ hist_out, FaceTab<VS::Q> ft,
+                                                    StepCoef<typename ST::comp, VS::Q> k,
+                                                    StepCoef<typename ST::comp, VS::Q> ks, FieldCoef<VS::Q> fk) {
+    using CT = typename ST::comp;
+    static_assert(VS::D == 2, "2D sets only");
+    const int nx = ft.n[0], ny = ft.n[1];
+    if ((int)blockIdx.x < face_blocks) {
+        if constexpr (MLP) {
+            open2d_ring_mlp<VS, ST, SKIP0, HALF>(src, dst, N, P, ghost, hist_in, hist_out, ft, ks, fk);
+        } else {
+            const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+            if (c >= 2LL * ny + 2LL * (nx - 2)) return;
+            int x[3];
+            open2d_ring_cell(c, nx, ny, x);
+            CT s[VS::Q];
+            shell_inside<VS, ST, SKIP0>(src, N, closure, x, ft, s);
+            collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(ks, s);
+            const size_t cell = (size_t)x[1] * nx + x[0];
+#pragma unroll
+            for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
+        }
+        return;
+    }
+    // interior cells, grid-stride over the blocks after the ring's
+    const size_t mx = (size_t)(nx - 2), interior = mx * (size_t)(ny - 2);
+    const size_t stride = (size_t)(gridDim.x - face_blocks) * 256u;
+    for (size_t t = (size_t)(blockIdx.x - face_blocks) * 256u + threadIdx.x; t < interior; t += stride) {
+        int x, y;
+        if (interior <= 0xffffffffull) {  // 32-bit division when it fits
+            x = 1 + (int)((unsigned)t % (unsigned)mx);
+            y = 1 + (int)((unsigned)t / (unsigned)mx);
+        } else {
+            x = 1 + (int)(t % mx);
+            y = 1 + (int)(t / mx);
+        }
+        CT s[VS::Q];
+        s[0] = 0;
+#pragma unroll
+        for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i)
+            s[i] = dec_io<ST, ST::has_raw>(src[(size_t)i * N + (size_t)(y - VS::cy(i)) * nx + (x - VS::cx(i))]);
+        collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, s);
+        const size_t cell = (size_t)y * nx + x;
+#pragma unroll
+        for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = enc_io<ST, ST::has_raw>(s[i]);
     }
 }
 

@@ -85,7 +85,10 @@ def test_sizes(lattice, storage, shape, bpu):
     dict(lattice="D3Q19", storage="f64", shape=(8, 8, 8), variant="tb2"),
     dict(lattice="D3Q9", storage="f64", shape=(8, 8, 8), variant="tb2"),
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), variant="tb2", tune=32),    # not with in-place
-    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), variant=7),
+    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), variant=8),
+    dict(lattice="D2Q9", storage="f32", shape=(8, 8), variant="open2d"),              # one-launch open step:
+    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), variant="open2d", bc="zero"),  # open 2D boxes only
+    dict(lattice="D1Q3", storage="f32", shape=(64,), variant="open2d", bc="zero"),
     dict(lattice="D3Q19", storage="f64", shape=(8, 8, 8), variant="tb3"),
     dict(lattice="D3Q13", storage="f64", shape=(8, 8, 8), variant="tb3"),
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), variant="tb3", bc="sponge", sponge_width=2,
@@ -207,6 +210,16 @@ def test_temporal_blocking_variants_accepted(lattice, storage):
         d3 = lbm.make_desc(lattice, storage, shape, variant="tb3", tune=tune)
         fits3 = not (lattice in ("D3Q13", "D3Q19") and storage == "f64")
         assert (lbm.lbm_lee_state_bytes(d3) > 0) == fits3
+
+
+@pytest.mark.parametrize("lattice", ["D2Q5", "D2Q9", "D2Q5_DIA"])
+@pytest.mark.parametrize("bc", ["zero", "copy", "sponge", "mlp"])
+def test_one_launch_open_step_accepted(lattice, bc):
+    """The one-launch open-box step takes every open boundary of a 2D box from 3 x 3 cells."""
+    kw = dict(sponge_width=2, sponge_sigma=0.1) if bc == "sponge" else {}
+    for shape in ((3, 3), (5, 70), (512, 512)):
+        d = lbm.make_desc(lattice, "f32", shape, variant="open2d", bc=bc, **kw)
+        assert lbm.lbm_lee_state_bytes(d) > 0
 
 
 @pytest.mark.parametrize("lattice", ["D1Q3", "D2Q5", "D2Q9", "D3Q7", "D3Q9", "D3Q13", "D3Q19", "D2Q5_DIA", "D3Q7_DIA"])
