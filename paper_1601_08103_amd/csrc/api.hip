@@ -837,7 +837,8 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
                     const unsigned face_blocks = bc == LBM_BC_MLP ? (unsigned)((open2d_segments(nx, ny) + 3) / 4)
                                                                   : (unsigned)((ring + 255) / 256);
                     const long long interior = (long long)(nx - 2) * (ny - 2);
-                    const unsigned bulk_blocks = (unsigned)std::min<long long>((interior + 255) / 256, 1LL << 20);
+                    const unsigned bulk_blocks =
+                        (unsigned)std::min<long long>((interior + 256 * kOpenCells - 1) / (256 * kOpenCells), 1LL << 20);
                     for (int64_t t = 0; t < nsteps; ++t) {
                         const E *src = static_cast<const E *>(h->buf[h->cur]);
                         E *dst = static_cast<E *>(h->buf[h->cur ^ 1]);

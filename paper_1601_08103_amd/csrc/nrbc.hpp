@@ -352,12 +352,13 @@ __device__ float load_normalised_tile(TT &T, int nrows, int lane, LoadFn X, EWFn
 #pragma unroll
     for (int t = 0; t < tile_vals<VS>(); ++t) {
         const int v = g + 4 * t;
-        float x = 0.0f;
-        if (r < nrows && v < G::NIN) {
-            x = X(r, v);
-            ON(r, v, x);
-        }
-        vals[t] = x;
+        vals[t] = (r < nrows && v < G::NIN) ? X(r, v) : 0.0f;
+    }
+    // after every load is issued (a store of a loaded value waits for that load)
+#pragma unroll
+    for (int t = 0; t < tile_vals<VS>(); ++t) {
+        const int v = g + 4 * t;
+        if (r < nrows && v < G::NIN) ON(r, v, vals[t]);
     }
     return normalise_tile<VS>(T, lane, vals, EW, m_out, e_out);
 }

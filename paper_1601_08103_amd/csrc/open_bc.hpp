@@ -88,8 +88,9 @@ __device__ inline int node_cell(const FaceTab<Q> &ft, long long g, int (&p)[3]) 
 // ------------------------------------------------------------------ shell recompute
 // Streamed values of boundary cell x, in two passes: shell_inside takes every source inside the
 // box (every source with COPY, clamped) from the state and leaves 0 for the others (ZERO,
-// SPONGE); shell_outside then fills, with MLP, each outside source with the mean over the
-// faces it lies beyond of the prediction GH(face, clamp(s), entering rank).
+// SPONGE); shell_outside then fills, with MLP, each outside source i with the mean over the
+// faces fb it lies beyond of the prediction GH(fb, clamp(s), i) (the face node's value for the
+// rank population i enters with), times GH.enc(i) (physical to stored units).
 template <class VS, class ST, bool SKIP0>
 __device__ inline void shell_inside(const typename ST::elem *__restrict__ src, size_t N, int closure,
                                     const int (&x)[3], const FaceTab<VS::Q> &ft, typename ST::comp (&s)[VS::Q]) {
@@ -112,8 +113,7 @@ __device__ inline void shell_inside(const typename ST::elem *__restrict__ src, s
 }
 
 template <class VS, class ST, bool SKIP0, class GH>
-__device__ inline void shell_outside(const int (&x)[3], const FaceTab<VS::Q> &ft, const FieldCoef<VS::Q> &fk,
-                                     typename ST::comp (&s)[VS::Q], GH ghost_at) {
+__device__ inline void shell_outside(const int (&x)[3], const int (&n)[3], typename ST::comp (&s)[VS::Q], GH ghost_at) {
     using CT = typename ST::comp;
 #pragma unroll
     for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) {
@@ -123,7 +123,7 @@ __device__ inline void shell_outside(const int (&x)[3], const FaceTab<VS::Q> &ft
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             sp[b] = x[b] - c[b];
-            cl[b] = min(max(sp[b], 0), ft.n[b] - 1);
+            cl[b] = min(max(sp[b], 0), n[b] - 1);
             inside = inside && sp[b] == cl[b];
         }
         if (inside) continue;
@@ -133,12 +133,11 @@ __device__ inline void shell_outside(const int (&x)[3], const FaceTab<VS::Q> &ft
         for (int b = 0; b < VS::D; ++b) {
             if (sp[b] != cl[b]) {
                 const int fb = 2 * b + (sp[b] > cl[b] ? 1 : 0);
-                const int r = ft.rank[fb][i];
-                acc += ghost_at(fb, cl, r < 0 ? 0 : r);
+                acc += ghost_at(fb, cl, i);
                 ++cnt;
             }
         }
-        s[i] = (CT)(acc / (float)cnt) * (CT)fk.enc[i];
+        s[i] = (CT)(acc / (float)cnt) * ghost_at.enc(i);
     }
 }
 
@@ -171,10 +170,20 @@ __global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__r
 
     CT s[VS::Q];
     shell_inside<VS, ST, SKIP0>(src, N, closure, x, ft, s);
-    if (closure == kBcMlp)
-        shell_outside<VS, ST, SKIP0>(x, ft, fk, s, [&](int fb, const int (&cl)[3], int r) {
-            return ghost[node_index(ft, fb, cl) * K + r];
-        });
+    if (closure == kBcMlp) {
+        struct {
+            const float *ghost;
+            const FaceTab<VS::Q> &ft;
+            const FieldCoef<VS::Q> &fk;
+            __device__ float operator()(int fb, const int (&cl)[3], int i) const {
+                const int r = ft.rank[fb][i];
+                return ghost[node_index(ft, fb, cl) * K + (r < 0 ? 0 : r)];
+            }
+            __device__ CT enc(int i) const { return (CT)fk.enc[i]; }
+        } gh{ghost, ft, fk};
+        const int n[3] = {ft.n[0], ft.n[1], ft.n[2]};
+        shell_outside<VS, ST, SKIP0>(x, n, s, gh);
+    }
     collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, s);
 #pragma unroll
     for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
@@ -331,6 +340,7 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
 // the ghost buffer and the history strips equal those of the separate network kernel (rows of
 // nodes that two waves evaluate are written twice with equal values).
 constexpr int kOpenSeg = 10;
+constexpr int kOpenCells = 2;  // interior cells per thread and pass
 static_assert(kOpenSeg + 2 + 4 <= 16, "a segment's rows must fit one 16-row tile");
 
 struct OpenSeg {
@@ -440,27 +450,43 @@ struct Open2dTiles {
     unsigned short (&h2)[16][64];
 };
 
-template <class VS, class ST, bool SKIP0, bool HALF>
-__device__ void open2d_ring_mlp(const typename ST::elem *__restrict__ src, typename ST::elem *__restrict__ dst,
-                                size_t N, const float *__restrict__ P, float *__restrict__ ghost,
-                                const float *__restrict__ hist_in, float *__restrict__ hist_out,
-                                const FaceTab<VS::Q> &ft, const StepCoef<typename ST::comp, VS::Q> &ks,
-                                const FieldCoef<VS::Q> &fk) {
+// LDS of a block of the ring with MLP.
+template <class VS>
+struct Open2dShared {
+    NetFrags<VS> F;
+    unsigned short zt[4][16][64], h1t[4][16][64];
+    float pred[4][16][NetGeom<VS>::NOUT];
+    float predp[4][16][VS::Q];  // limited predictions by population: the row's value for rank[face][i]
+    int perm[4][VS::Q], rank[4][VS::Q];
+    float dec[VS::Q], invf[VS::Q];  // by population
+};
+
+// HIST: the previous strips come from hist_in (else the current strips stand in for them).
+template <class VS, class ST, bool SKIP0, bool HALF, bool HIST>
+__device__ void open2d_ring_mlp(Open2dShared<VS> &sh, const typename ST::elem *__restrict__ src,
+                                typename ST::elem *__restrict__ dst, size_t N, const float *__restrict__ P,
+                                float *__restrict__ ghost, const float *__restrict__ hist_in,
+                                float *__restrict__ hist_out, const FaceTab<VS::Q> &ft,
+                                const StepCoef<typename ST::comp, VS::Q> &ks, const FieldCoef<VS::Q> &fk) {
     using G = NetGeom<VS>;
     using CT = typename ST::comp;
     static_assert(VS::D == 2 && G::ZW == 64, "2D sets only");
     constexpr int NS = G::NSTRIP, K = G::NOUT;
-    __shared__ NetFrags<VS> F;
-    __shared__ unsigned short zt[4][16][64], h1t[4][16][64];
-    __shared__ float pred[4][16][K];
-    __shared__ int perm_s[4][VS::Q];
-    __shared__ float dec_s[4][VS::Q], invf_s[4][VS::Q];
-    for (int t = threadIdx.x; t < 4 * VS::Q; t += 256) {
+    NetFrags<VS> &F = sh.F;
+    auto &pred = sh.pred;
+    auto &perm_s = sh.perm;
+    auto &rank_s = sh.rank;
+    auto &dec_s = sh.dec;
+    auto &invf_s = sh.invf;
+    for (int t = threadIdx.x; t < 4 * VS::Q; t += 256) {  // no load here waits for another
         const int f = t / VS::Q, j = t - f * VS::Q;
-        const int i = ft.perm[f][j];
-        perm_s[f][j] = i;
-        dec_s[f][j] = (float)fk.dec[i];
-        invf_s[f][j] = (float)(1.0 / fk.f[i]);
+        perm_s[f][j] = ft.perm[f][j];
+        const int rk = ft.rank[f][j];  // rank of population j entering through face f
+        rank_s[f][j] = rk < 0 ? 0 : rk;
+        if (f == 0) {
+            dec_s[j] = (float)fk.dec[j];
+            invf_s[j] = (float)(1.0 / fk.f[j]);
+        }
     }
     __syncthreads();  // tables visible before the loads below
     const int nx = ft.n[0], ny = ft.n[1];
@@ -475,11 +501,21 @@ __device__ void open2d_ring_mlp(const typename ST::elem *__restrict__ src, typen
     int xc[3] = {0, 0, 0};
     {
         const int a = sg.f >> 1, q = sg.p0 + (owner ? lane : 0);
-        xc[a] = (sg.f & 1) ? ft.n[a] - 1 : 0;
+        xc[a] = (sg.f & 1) ? (a == 0 ? nx : ny) - 1 : 0;
         xc[1 - a] = q;
     }
     CT s[VS::Q];
     if (owner) shell_inside<VS, ST, SKIP0>(src, N, kBcMlp, xc, ft, s);
+    // the tile rows of the face nodes each source of the ring cell lies beyond (-1: not beyond
+    // that face), x face first as in shell_outside; computed before the network
+    int row_x[VS::Q], row_y[VS::Q];
+#pragma unroll
+    for (int i = 0; i < VS::Q; ++i) {
+        const int sp[2] = {xc[0] - VS::cx(i), xc[1] - VS::cy(i)};
+        const int cl[3] = {min(max(sp[0], 0), nx - 1), min(max(sp[1], 0), ny - 1), 0};
+        row_x[i] = sp[0] != cl[0] ? open2d_row_of(plan, sp[0] > cl[0] ? 1 : 0, cl, nx) : -1;
+        row_y[i] = sp[1] != cl[1] ? open2d_row_of(plan, sp[1] > cl[1] ? 3 : 2, cl, nx) : -1;
+    }
 
     const int r = lane & 15, g = lane >> 4;
     const bool row_ok = active && r < plan.nrows;
@@ -487,36 +523,59 @@ __device__ void open2d_ring_mlp(const typename ST::elem *__restrict__ src, typen
     open2d_row_node(plan, row_ok ? r : 0, nx, f, pos);
     int p[3] = {0, 0, 0};
     const int a = f >> 1, step = (f & 1) ? -1 : 1;
-    p[a] = (f & 1) ? ft.n[a] - 1 : 0;
+    p[a] = (f & 1) ? (a == 0 ? nx : ny) - 1 : 0;
     p[1 - a] = pos;
-    const long long node = ft.node_off[f] + pos;
+    // node ids run face after face: ny nodes on each x face, nx on each y face
+    const long long node = (f < 2 ? (long long)f * ny : 2LL * ny + (long long)(f - 2) * nx) + pos;
     const size_t cell0 = (size_t)p[1] * nx + p[0];
     const long long stride_a = a == 0 ? 1 : (long long)nx;
     auto strip_now = [&](int v) {  // value v of this row's current strip
         const int m = v / VS::Q, j = v - m * VS::Q;
         const size_t cell = (size_t)((long long)cell0 + (long long)(m * step) * stride_a);
-        return dec_s[f][j] * (float)ST::dec(src[(size_t)perm_s[f][j] * N + cell]);
+        const int i = perm_s[f][j];
+        return dec_s[i] * (float)ST::dec(src[(size_t)i * N + cell]);
     };
     // input [strip(t), strip(t-1)]: the previous strip from the history (the current one again on
-    // the first step after the state was set); this step's strip becomes the next step's history
+    // the first step after the state was set); this step's strip becomes the next step's history.
+    // Every lane loads (padding values and rows past the tile's read a valid value, later scaled
+    // by 0; kept values are scaled by 1, exactly), so no load sits in a branch, and all of them,
+    // the ring cell's and the weights' are issued before the first wait.
+    float now[tile_vals<VS>()], before[tile_vals<VS>()];
+#pragma unroll
+    for (int t = 0; t < tile_vals<VS>(); ++t) {
+        const int v = g + 4 * t, vv = v < G::NIN ? v : G::NIN - 1;
+        now[t] = strip_now(vv < NS ? vv : vv - NS);
+    }
+    if constexpr (HIST) {
+        const float *hrow = hist_in + node * NS;
+#pragma unroll
+        for (int t = 0; t < tile_vals<VS>(); ++t) {
+            const int v = g + 4 * t, vv = v < G::NIN ? v : G::NIN - 1;
+            before[t] = hrow[vv < NS ? 0 : vv - NS];
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < tile_vals<VS>(); ++t) before[t] = now[t];
+    }
+    CT enc[VS::Q];  // physical to stored units, for the predictions pulled into the ring cell
+#pragma unroll
+    for (int i = 0; i < VS::Q; ++i) enc[i] = (CT)fk.enc[i];
+    stage_forward_weights<VS>(P, F);  // ends with a block barrier
+    if (!active) return;
+
     float vals[tile_vals<VS>()];
 #pragma unroll
     for (int t = 0; t < tile_vals<VS>(); ++t) {
         const int v = g + 4 * t;
-        float x = 0.0f;
-        if (row_ok && v < G::NIN) {
-            x = v < NS ? strip_now(v) : (hist_in ? hist_in[node * NS + (v - NS)] : strip_now(v - NS));
-            if (v < NS) hist_out[node * NS + v] = x;
-        }
-        vals[t] = x;
+        const int vv = v < G::NIN ? v : G::NIN - 1;
+        vals[t] = (vv < NS ? now[t] : before[t]) * ((row_ok && v < G::NIN) ? 1.0f : 0.0f);
+        if (row_ok && v < NS) hist_out[node * NS + v] = vals[t];
     }
-    stage_forward_weights<VS>(P, F);  // ends with a block barrier
-    if (!active) return;
-
-    Open2dTiles T{zt[wid], h1t[wid], zt[wid]};
+    Open2dTiles T{sh.zt[wid], sh.h1t[wid], sh.zt[wid]};
     float mx = 0.0f, e_out = 0.0f;
     const float sn = normalise_tile<VS>(
-        T, lane, vals, [&](int v) { return v < VS::Q && VS::cx(v) == -1 ? invf_s[f][v] : 0.0f; }, &mx, &e_out);
+        T, lane, vals, [&](int v) { return v < VS::Q && VS::cx(v) == -1 ? invf_s[perm_s[f][v]] : 0.0f; }, &mx,
+        &e_out);
     const floatx4 y = net_forward_tile_staged<VS>(F, T, lane);
     const int col = lane & 15;
 #pragma unroll
@@ -531,23 +590,45 @@ __device__ void open2d_ring_mlp(const typename ST::elem *__restrict__ src, typen
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const float v = pred[wid][lane][k] / mx;
-            e_in += v * v * invf_s[f][entering_index<VS>(k)];
+            e_in += v * v * invf_s[perm_s[f][entering_index<VS>(k)]];
         }
         const int nf = (p[0] == 0) + (p[0] == nx - 1) + (p[1] == 0) + (p[1] == ny - 1);
         const float budget = e_out / (float)((1 << nf) - 1);
         const float sc = e_in > budget ? sqrtf(budget / e_in) : 1.0f;
+        float gv[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const float gv = sc * pred[wid][lane][k];
-            pred[wid][lane][k] = gv;
-            ghost[node * K + k] = gv;
+            gv[k] = sc * pred[wid][lane][k];
+            ghost[node * K + k] = gv[k];
+        }
+#pragma unroll
+        for (int i = 0; i < VS::Q; ++i) {
+            const int rk = rank_s[f][i];
+            float v = gv[0];
+#pragma unroll
+            for (int k = 1; k < K; ++k) v = rk == k ? gv[k] : v;
+            sh.predp[wid][lane][i] = v;
         }
     }
     wave_lds_sync();
     if (!owner) return;
-    shell_outside<VS, ST, SKIP0>(xc, ft, fk, s, [&](int fb, const int (&cl)[3], int rk) {
-        return pred[wid][open2d_row_of(plan, fb, cl, nx)][rk];
-    });
+    // the closure's values, as shell_outside forms them (mean over the faces, then to stored units;
+    // division by a count of 1 or 2 is exact as the identity or a product with 1/2)
+#pragma unroll
+    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) {
+        if (row_x[i] < 0 && row_y[i] < 0) continue;
+        float acc = 0.0f;
+        int cnt = 0;
+        if (row_x[i] >= 0) {
+            acc += sh.predp[wid][row_x[i]][i];
+            ++cnt;
+        }
+        if (row_y[i] >= 0) {
+            acc += sh.predp[wid][row_y[i]][i];
+            ++cnt;
+        }
+        s[i] = (CT)(cnt == 2 ? acc * 0.5f : acc) * enc[i];
+    }
     collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(ks, s);
     const size_t cell = (size_t)xc[1] * nx + xc[0];
 #pragma unroll
@@ -567,7 +648,11 @@ __global__ __launch_bounds__(256) void open_step_2d(const typename ST::elem *__r
     const int nx = ft.n[0], ny = ft.n[1];
     if ((int)blockIdx.x < face_blocks) {
         if constexpr (MLP) {
-            open2d_ring_mlp<VS, ST, SKIP0, HALF>(src, dst, N, P, ghost, hist_in, hist_out, ft, ks, fk);
+            __shared__ Open2dShared<VS> sh;
+            if (hist_in)
+                open2d_ring_mlp<VS, ST, SKIP0, HALF, true>(sh, src, dst, N, P, ghost, hist_in, hist_out, ft, ks, fk);
+            else
+                open2d_ring_mlp<VS, ST, SKIP0, HALF, false>(sh, src, dst, N, P, ghost, hist_in, hist_out, ft, ks, fk);
         } else {
             const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
             if (c >= 2LL * ny + 2LL * (nx - 2)) return;
@@ -582,27 +667,41 @@ __global__ __launch_bounds__(256) void open_step_2d(const typename ST::elem *__r
         }
         return;
     }
-    // interior cells, grid-stride over the blocks after the ring's
+    // interior cells, kOpenCells per thread and pass (the loads of all of them in flight together;
+    // a cell past the end loads a valid cell and stores nothing), grid-stride over the blocks
+    // after the ring's
     const size_t mx = (size_t)(nx - 2), interior = mx * (size_t)(ny - 2);
     const size_t stride = (size_t)(gridDim.x - face_blocks) * 256u;
-    for (size_t t = (size_t)(blockIdx.x - face_blocks) * 256u + threadIdx.x; t < interior; t += stride) {
-        int x, y;
-        if (interior <= 0xffffffffull) {  // 32-bit division when it fits
-            x = 1 + (int)((unsigned)t % (unsigned)mx);
-            y = 1 + (int)((unsigned)t / (unsigned)mx);
-        } else {
-            x = 1 + (int)(t % mx);
-            y = 1 + (int)(t / mx);
+    for (size_t t0 = (size_t)(blockIdx.x - face_blocks) * 256u + threadIdx.x; t0 < interior;
+         t0 += kOpenCells * stride) {
+        CT s[kOpenCells][VS::Q];
+        size_t cell[kOpenCells];
+#pragma unroll
+        for (int c = 0; c < kOpenCells; ++c) {
+            const size_t t = t0 + c * stride < interior ? t0 + c * stride : t0;
+            int x, y;
+            if (interior <= 0xffffffffull) {  // 32-bit division when it fits
+                x = 1 + (int)((unsigned)t % (unsigned)mx);
+                y = 1 + (int)((unsigned)t / (unsigned)mx);
+            } else {
+                x = 1 + (int)(t % mx);
+                y = 1 + (int)(t / mx);
+            }
+            cell[c] = (size_t)y * nx + x;
+            s[c][0] = 0;
+#pragma unroll
+            for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i)
+                s[c][i] = dec_io<ST, ST::has_raw>(src[(size_t)i * N + (size_t)(y - VS::cy(i)) * nx + (x - VS::cx(i))]);
         }
-        CT s[VS::Q];
-        s[0] = 0;
 #pragma unroll
-        for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i)
-            s[i] = dec_io<ST, ST::has_raw>(src[(size_t)i * N + (size_t)(y - VS::cy(i)) * nx + (x - VS::cx(i))]);
-        collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, s);
-        const size_t cell = (size_t)y * nx + x;
+        for (int c = 0; c < kOpenCells; ++c) {
+            collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, s[c]);
+            if (t0 + c * stride < interior) {
 #pragma unroll
-        for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = enc_io<ST, ST::has_raw>(s[i]);
+                for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i)
+                    dst[(size_t)i * N + cell[c]] = enc_io<ST, ST::has_raw>(s[c][i]);
+            }
+        }
     }
 }
 
