@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-nrbc", action="store_true", help="skip the learned-closure leg")
+    ap.add_argument("--closure-only", action="store_true",
+                    help="only the learned-closure leg (for rocprofv3); its result on stdout")
     ap.add_argument("--profile-only", action="store_true", help="only the timed steps of --storage (for rocprofv3)")
     ap.add_argument("--with-copy", action="store_true",
                     help="with --profile-only: also run the plain copy kernel on one state buffer's bytes "
@@ -162,6 +164,9 @@ def main():
         sys.exit(1)
     lbm.load()
     torch.cuda.set_device(0)
+    if args.closure_only:
+        print(json.dumps(nrbc_leg()))
+        return
     n = args.n
     shape = (n, n, n)
     N = n ** 3
