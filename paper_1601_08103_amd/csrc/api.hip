@@ -879,8 +879,12 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
                         LBM_HIP(hipEventRecord(h->fork, st));
                         LBM_HIP(hipStreamWaitEvent(h->aux, h->fork, 0));
                     }
-                    ghost_mlp_kernel<VS, ST><<<ghost_blocks, 256, 0, fork ? h->aux : st>>>(src, h->N, h->net, h->ghost,
-                                                                                           hin, hout, ft, fk);
+                    if (hin)
+                        ghost_mlp_kernel<VS, ST, true><<<ghost_blocks, 256, 0, fork ? h->aux : st>>>(
+                            src, h->N, h->net, h->ghost, hin, hout, ft, fk);
+                    else
+                        ghost_mlp_kernel<VS, ST, false><<<ghost_blocks, 256, 0, fork ? h->aux : st>>>(
+                            src, h->N, h->net, h->ghost, hin, hout, ft, fk);
                     if (fork) LBM_HIP(hipEventRecord(h->join, h->aux));
                     h->hist_valid = true;
                 }

@@ -61,27 +61,46 @@ __device__ inline long long node_index(const FaceTab<Q> &ft, int f, const int (&
     return ft.node_off[f] + nd;
 }
 
+// Face and cell of global node g.  Offsets and extents are read at fixed indices (kernel
+// arguments stay in scalar registers) and selected, so no lookup waits on a memory load.
 template <int Q>
 __device__ inline int node_cell(const FaceTab<Q> &ft, long long g, int (&p)[3]) {
+    const int n[3] = {ft.n[0], ft.n[1], ft.n[2]};
     int f = 0;
-    while (f + 1 < ft.nfaces && g >= ft.node_off[f + 1]) ++f;
-    long long nd = g - ft.node_off[f];
+    long long lo = 0;  // node_off[0] = 0
+#pragma unroll
+    for (int k = 1; k < 6; ++k) {
+        const long long o = ft.node_off[k];
+        if (k < ft.nfaces && g >= o) {  // offsets increase: the last face starting at or before g
+            f = k;
+            lo = o;
+        }
+    }
+    long long nd = g - lo;
     const int a = f >> 1;
     int t1, t2;
     infaces(a, ft.D, t1, t2);
+    auto ext = [&](int b) { return b == 0 ? n[0] : (b == 1 ? n[1] : n[2]); };
     p[0] = p[1] = p[2] = 0;
+    int q1 = 0, q2 = 0;
     if (t1 >= 0) {
+        const int m = ext(t1);
         if (nd <= 0x7fffffffLL) {  // 32-bit division when it fits (64-bit division is emulated)
-            const unsigned u = (unsigned)nd, m = (unsigned)ft.n[t1];
-            p[t1] = (int)(u % m);
-            nd = u / m;
+            const unsigned u = (unsigned)nd, um = (unsigned)m;
+            q1 = (int)(u % um);
+            nd = u / um;
         } else {
-            p[t1] = (int)(nd % ft.n[t1]);
-            nd /= ft.n[t1];
+            q1 = (int)(nd % m);
+            nd /= m;
         }
     }
-    if (t2 >= 0) p[t2] = (int)nd;
-    p[a] = (f & 1) ? ft.n[a] - 1 : 0;
+    if (t2 >= 0) q2 = (int)nd;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        if (b == t1) p[b] = q1;
+        if (b == t2) p[b] = q2;
+        if (b == a) p[b] = (f & 1) ? ext(a) - 1 : 0;
+    }
     return f;
 }
 
@@ -247,7 +266,7 @@ __global__ __launch_bounds__(256) void sponge_kernel(typename ST::elem *__restri
 // box belongs to one node, and a face prediction feeds at most (2^n - 1) / n of its energy into
 // the box (means over faces), so the energy entering at a node never exceeds the energy leaving
 // it: the open box cannot gain energy at tau = 1/2 whatever the network predicts.
-template <class VS, class ST>
+template <class VS, class ST, bool HIST>
 __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem *__restrict__ src, size_t N,
                                                         const float *__restrict__ P, float *__restrict__ ghost,
                                                         const float *__restrict__ hist_in, float *__restrict__ hist_out,
@@ -277,8 +296,9 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
         const int nrows = (int)min((long long)16, count - base);
         // the node of this lane's row
         int p[3];
-        const int r = lane & 15;
-        const long long node = base + (r < nrows ? r : 0);
+        const int r = lane & 15, g = lane >> 4;
+        const bool row_ok = r < nrows;
+        const long long node = base + (row_ok ? r : 0);
         const int f = node_cell(ft, node, p);
         const int a = f >> 1, step = (f & 1) ? -1 : 1;
         const size_t cell0 = ((size_t)p[2] * ft.n[1] + p[1]) * ft.n[0] + p[0];
@@ -288,17 +308,28 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
             const size_t cell = (size_t)((long long)cell0 + (long long)(m * step) * stride_a);
             return dec_s[f][j] * (float)ST::dec(src[(size_t)perm_s[f][j] * N + cell]);
         };
-        // input [strip(t), strip(t-1)]; the previous strip comes from the history buffer (the
-        // current one again on the first step after the state was set)
-        // this step's strip becomes the next step's history (the other buffer of the pair)
+        // input [strip(t), strip(t-1)]; the previous strip comes from the history buffer (HIST),
+        // else the current one stands in; this step's strip becomes the next step's history (the
+        // other buffer of the pair).  Every lane loads (padding values and rows past the tile's read
+        // a valid value, then scaled by 0; kept values are scaled by 1, exactly), so no load sits in
+        // a branch and none waits for another.
+        float now[tile_vals<VS>()], before[tile_vals<VS>()], vals[tile_vals<VS>()];
+#pragma unroll
+        for (int t = 0; t < tile_vals<VS>(); ++t) {
+            const int v = g + 4 * t, vv = v < G::NIN ? v : G::NIN - 1;
+            now[t] = strip_now(vv < NS ? vv : vv - NS);
+            if constexpr (HIST) before[t] = hist_in[node * NS + (vv < NS ? 0 : vv - NS)];
+        }
+#pragma unroll
+        for (int t = 0; t < tile_vals<VS>(); ++t) {
+            const int v = g + 4 * t, vv = v < G::NIN ? v : G::NIN - 1;
+            const float x = HIST && vv >= NS ? before[t] : now[t];
+            vals[t] = x * ((row_ok && v < G::NIN) ? 1.0f : 0.0f);
+            if (row_ok && v < NS) hist_out[node * NS + v] = vals[t];
+        }
         float mx = 0.0f, e_out = 0.0f;
-        const float s = load_normalised_tile<VS>(
-            T, nrows, lane,
-            [&](int, int v) { return v < NS ? strip_now(v) : (hist_in ? hist_in[node * NS + (v - NS)] : strip_now(v - NS)); },
-            [&](int v) { return v < VS::Q && VS::cx(v) == -1 ? invf_s[f][v] : 0.0f; }, &mx, &e_out,
-            [&](int, int v, float x) {
-                if (v < NS) hist_out[node * NS + v] = x;
-            });
+        const float s = normalise_tile<VS>(
+            T, lane, vals, [&](int v) { return v < VS::Q && VS::cx(v) == -1 ? invf_s[f][v] : 0.0f; }, &mx, &e_out);
         const floatx4 y = net_forward_tile_staged<VS>(F, T, lane);
         const int col = lane & 15;
 #pragma unroll

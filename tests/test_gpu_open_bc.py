@@ -342,3 +342,36 @@ def test_one_launch_open_step_matches_separate_kernels(name, bc, storage):
                 assert torch.equal(fused.ghost, separate.ghost), (shape, tau, step)
         for sim in sims:
             sim.close()
+
+
+@pytest.mark.parametrize("bc,storage", [("mlp", "f32"), ("mlp", "f16"), ("sponge", "f32"), ("zero", "e3m12")])
+def test_one_launch_open_step_full_size(bc, storage):
+    """The learned-closure workload's box (D2Q9 512^2) with the shipped weights: the one-launch step
+    equals the separate kernels bit for bit over 6 steps from a seeded pulse state."""
+    import os
+    from paper_1601_08103_amd import lbm
+    lat = L.get("D2Q9")
+    shape = (512, 512)
+    kw = dict(sponge_width=96, sponge_sigma=0.03) if bc == "sponge" else {}
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1601_08103_amd",
+                        "weights", "nrbc_D2Q9.npy")
+    params = np.load(path, allow_pickle=False).astype(np.float32)
+    info = lbm.lbm_lee_lattice_info("D2Q9")
+    p0 = inputs.gaussian_pressure(shape, inputs.pulses_2d(seed=3, n=512))
+    rho, u, theta = inputs.fields_from_pressure(p0, info["rho0"], info["theta0"], info["gamma"])
+    say("one-launch open step, full size", bc, storage)
+    sims = []
+    for variant in ("auto", "generic"):
+        sim = lbm.Solver("D2Q9", storage, shape, rho, u, theta, variant=variant, bc=bc, **kw)
+        if bc == "mlp":
+            sim.set_closure(params)
+        sims.append(sim)
+    fused, separate = sims
+    assert fused.variant == "open2d"
+    for sim in sims:
+        sim.step(6)
+    a, b = fused.export_f64().cpu().numpy(), separate.export_f64().cpu().numpy()
+    assert np.array_equal(a, b)
+    assert np.abs(a).max() > 0
+    for sim in sims:
+        sim.close()
