@@ -140,9 +140,10 @@ typedef int32_t lbm_status;
 /* 2D open boxes (every boundary but LBM_BC_PERIODIC): one launch per step.  Blocks of the ring
  * (the cells on a face) and blocks of the interior run side by side; with LBM_BC_MLP each wave
  * of the ring evaluates the closure network for the face nodes its ring cells pull from and
- * keeps the predictions in LDS.  Same values, ghost buffer and history as the separate
- * network, bulk and boundary kernels of the other variants; LBM_TUNE_CLOSURE_STREAM has no
- * effect.  LBM_E_UNSUPPORTED for periodic boxes and for 1D and 3D lattices. */
+ * keeps the predictions in LDS; with LBM_BC_SPONGE each cell of the layer is damped by the
+ * thread that stores it.  Same values, ghost buffer and history as the separate network, bulk,
+ * boundary and sponge kernels of the other variants; LBM_TUNE_CLOSURE_STREAM has no effect.
+ * LBM_E_UNSUPPORTED for periodic boxes and for 1D and 3D lattices. */
 #define LBM_VARIANT_OPEN2D 7
 
 typedef struct lbm_lee_desc {

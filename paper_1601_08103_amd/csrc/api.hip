@@ -847,14 +847,14 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
                             const float *hin = h->hist_valid ? hist + (long long)h->cur * nodes * nstrip : nullptr;
                             float *hout = hist + (long long)(h->cur ^ 1) * nodes * nstrip;
                             open_step_2d<VS, ST, SK, HF, true><<<face_blocks + bulk_blocks, 256, 0, st>>>(
-                                src, dst, h->N, bc, (int)face_blocks, h->net, h->ghost, hin, hout, ft, k, ks, fk);
+                                src, dst, h->N, bc, (int)face_blocks, h->net, h->ghost, hin, hout, ft, k, ks, fk, 0,
+                                0.0);
                             h->hist_valid = true;
                         } else {
+                            // the sponge layer is damped inside the step kernel
                             open_step_2d<VS, ST, SK, HF, false><<<face_blocks + bulk_blocks, 256, 0, st>>>(
-                                src, dst, h->N, bc, (int)face_blocks, nullptr, nullptr, nullptr, nullptr, ft, k, ks, fk);
-                            if (bc == LBM_BC_SPONGE)
-                                sponge_kernel<VS, ST><<<dim3(sponge_x, 2 * VS::D), 256, 0, st>>>(
-                                    dst, h->N, h->nx, h->ny, h->nz, h->desc.sponge_width, h->desc.sponge_sigma);
+                                src, dst, h->N, bc, (int)face_blocks, nullptr, nullptr, nullptr, nullptr, ft, k, ks, fk,
+                                bc == LBM_BC_SPONGE ? h->desc.sponge_width : 0, h->desc.sponge_sigma);
                         }
                         lbm_status ls = launch_check();
                         if (ls != LBM_OK) return ls;

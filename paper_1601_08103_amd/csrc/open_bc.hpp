@@ -209,6 +209,18 @@ __global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__r
 }
 
 // ------------------------------------------------------------------ sponge damping
+// Damping factor at distance d < width from the nearest face, and a stored value damped by it
+// (decoded, scaled, encoded again).
+template <class CT>
+__device__ inline CT sponge_factor(int d, int width, double sigma_max) {
+    const CT w = (CT)(width - d) / (CT)width;
+    return (CT)1 - (CT)sigma_max * w * w;
+}
+template <class ST>
+__device__ inline typename ST::elem sponge_damp(typename ST::elem e, typename ST::comp fac) {
+    return ST::enc(ST::dec(e) * fac);
+}
+
 // Grid (x blocks, 2D slabs): slab f = 2a + side holds the cells within W of face f that are not
 // in a slab of a lower axis, so every layer cell is visited exactly once and the interior not at all.
 template <class VS, class ST>
@@ -248,12 +260,11 @@ __global__ __launch_bounds__(256) void sponge_kernel(typename ST::elem *__restri
     if (VS::D >= 3) d = min(d, min(z, nz - 1 - z));
     if (d >= width) return;
     const size_t cell = ((size_t)z * ny + y) * nx + x;
-    const CT w = (CT)(width - d) / (CT)width;
-    const CT fac = (CT)1 - (CT)sigma_max * w * w;
+    const CT fac = sponge_factor<CT>(d, width, sigma_max);
 #pragma unroll
     for (int i = 0; i < VS::Q; ++i) {
         typename ST::elem *p = g + (size_t)i * N + cell;
-        *p = ST::enc(ST::dec(*p) * fac);
+        *p = sponge_damp<ST>(*p, fac);
     }
 }
 
@@ -673,10 +684,24 @@ __global__ __launch_bounds__(256) void open_step_2d(const typename ST::elem *__r
                                                     float *__restrict__ ghost, const float *__restrict__ hist_in,
                                                     float *__restrict__ hist_out, FaceTab<VS::Q> ft,
                                                     StepCoef<typename ST::comp, VS::Q> k,
-                                                    StepCoef<typename ST::comp, VS::Q> ks, FieldCoef<VS::Q> fk) {
+                                                    StepCoef<typename ST::comp, VS::Q> ks, FieldCoef<VS::Q> fk,
+                                                    int sponge_width, double sponge_sigma) {
     using CT = typename ST::comp;
     static_assert(VS::D == 2, "2D sets only");
     const int nx = ft.n[0], ny = ft.n[1];
+    // SPONGE: each cell within sponge_width of a face is damped as the sponge kernel damps it,
+    // right after its new state is stored (same values: decode, scale, encode)
+    auto store = [&](size_t cell, int x, int y, const CT (&s)[VS::Q], auto encode) {
+        const int d = min(min(x, nx - 1 - x), min(y, ny - 1 - y));
+        if (!MLP && closure == kBcSponge && d < sponge_width) {
+            const CT fac = sponge_factor<CT>(d, sponge_width, sponge_sigma);
+#pragma unroll
+            for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = sponge_damp<ST>(encode(s[i]), fac);
+        } else {
+#pragma unroll
+            for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = encode(s[i]);
+        }
+    };
     if ((int)blockIdx.x < face_blocks) {
         if constexpr (MLP) {
             __shared__ Open2dShared<VS> sh;
@@ -692,9 +717,7 @@ __global__ __launch_bounds__(256) void open_step_2d(const typename ST::elem *__r
             CT s[VS::Q];
             shell_inside<VS, ST, SKIP0>(src, N, closure, x, ft, s);
             collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(ks, s);
-            const size_t cell = (size_t)x[1] * nx + x[0];
-#pragma unroll
-            for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
+            store((size_t)x[1] * nx + x[0], x[0], x[1], s, [](CT v) { return ST::enc(v); });
         }
         return;
     }
@@ -707,6 +730,7 @@ __global__ __launch_bounds__(256) void open_step_2d(const typename ST::elem *__r
          t0 += kOpenCells * stride) {
         CT s[kOpenCells][VS::Q];
         size_t cell[kOpenCells];
+        int cx[kOpenCells], cy[kOpenCells];
 #pragma unroll
         for (int c = 0; c < kOpenCells; ++c) {
             const size_t t = t0 + c * stride < interior ? t0 + c * stride : t0;
@@ -719,6 +743,8 @@ __global__ __launch_bounds__(256) void open_step_2d(const typename ST::elem *__r
                 y = 1 + (int)(t / mx);
             }
             cell[c] = (size_t)y * nx + x;
+            cx[c] = x;
+            cy[c] = y;
             s[c][0] = 0;
 #pragma unroll
             for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i)
@@ -728,9 +754,7 @@ __global__ __launch_bounds__(256) void open_step_2d(const typename ST::elem *__r
         for (int c = 0; c < kOpenCells; ++c) {
             collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, s[c]);
             if (t0 + c * stride < interior) {
-#pragma unroll
-                for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i)
-                    dst[(size_t)i * N + cell[c]] = enc_io<ST, ST::has_raw>(s[c][i]);
+                store(cell[c], cx[c], cy[c], s[c], [](CT v) { return enc_io<ST, ST::has_raw>(v); });
             }
         }
     }
