@@ -82,7 +82,8 @@ typedef int32_t lbm_status;
 #define LBM_TUNE_CLOSURE_STREAM 16 /* LBM_BC_MLP: run the network on the handle's helper stream,  */
                                    /* forked from and joined to the caller's stream each step, so */
                                    /* it overlaps the bulk step (pays off in captured graphs;     */
-                                   /* eager launches add two event calls per step)                */
+                                   /* eager launches add two event calls per step); no effect     */
+                                   /* with LBM_VARIANT_OPEN2D (one launch per step)               */
 #define LBM_TUNE_IN_PLACE 32  /* one population buffer instead of two (periodic box only; pop_b */
                               /* of lbm_lee_init may be NULL); see "In-place streaming" below   */
 /* LBM_VARIANT_TB2: segment length along the march axis (z in 3D, y in 2D).  Without these bits
