@@ -114,7 +114,8 @@ typedef int32_t lbm_status;
 #define LBM_BC_MLP 4
 
 /* Step kernel variant.  All variants run the same per-cell arithmetic, so their results are
- * bitwise identical; they differ only in how the streamed values are gathered. */
+ * bitwise identical; they differ only in how the streamed values are gathered (the multi-step
+ * variants TB2/TB3 with 16-bit storage excepted: they round once per launch, see below). */
 #define LBM_VARIANT_AUTO 0    /* the fastest measured variant: OPEN2D on 2D open boxes; on    */
                               /* periodic 2D/3D boxes of >= 2^20 cells TB3 (sets of <= 9       */
                               /* velocities) or TB2 where they are supported; else GENERIC for */
@@ -129,12 +130,17 @@ typedef int32_t lbm_status;
  * owns a tile of 64 cells along x (and TY along y in 3D) and marches along the last axis, doing
  * step t+1 on the tile and a one-cell ring around it (state t read from HBM) and then step t+2
  * on the tile (state t+1 from LDS and registers), so the state crosses HBM once per two steps.
- * An odd step count ends with one one-step launch.  LBM_E_UNSUPPORTED for open boxes, 1D sets
+ * The intermediate state is never stored: with F64/F32 storage the result equals two one-step
+ * launches bit for bit; with the 16-bit formats it stays in FP32 and a launch rounds to the
+ * format once instead of twice (half the rounding error of the one-step kernels, whose error at
+ * tau = 1/2 accumulates undamped).  An odd step count ends with one one-step launch.  LBM_E_UNSUPPORTED for open boxes, 1D sets
  * and sets whose in-plane LDS rings do not fit 64 KB at TY = 4 (D3Q19 with FP32, and D3Q9,
  * D3Q13 and D3Q19 with FP64). */
 #define LBM_VARIANT_TB2 5
 /* Three steps per launch, the same scheme one stage deeper (the tile dilated by two cells for
- * step t+1, by one for t+2); LDS rings of two intermediate steps (up to 160 KB per block).
+ * step t+1, by one for t+2); LDS rings of two intermediate steps (up to 160 KB per block).  As
+ * with TB2, F64/F32 results equal one-step launches bit for bit and the 16-bit formats round
+ * once per launch of three steps.
  * LBM_E_UNSUPPORTED where they do not fit at TY = 4 (D3Q13 and D3Q19 with FP64) and in the
  * cases TB2 refuses.  A remainder of the step count (mod 3) runs one-step launches. */
 #define LBM_VARIANT_TB3 6
@@ -238,8 +244,10 @@ lbm_status lbm_lee_reinit_region(lbm_lee_handle h, const int64_t origin[3], cons
  * fully discrete update: fused pull-stream + moments + equilibrium + relaxation), enqueued on
  * `stream`.  One-step variants launch one kernel per step (plus, on open boxes, the boundary
  * kernels of LBM_BC_*); TB2/TB3 launch one kernel per two/three steps and one-step kernels for a
- * remainder of nsteps, so the result does not depend on how the steps are split over calls
- * (every kernel gives the same bits).  The step counter advances by nsteps.  Errors:
+ * remainder of nsteps.  With F64/F32 storage every kernel gives the same bits, so the result does
+ * not depend on how the steps are split over calls; with the 16-bit formats a multi-step launch
+ * rounds the state once per launch, so it does (each split is a valid run of the scheme with
+ * one rounding per stored state).  The step counter advances by nsteps.  Errors:
  * LBM_E_INVALID for a NULL handle or nsteps < 0, LBM_E_STATE for an LBM_BC_MLP handle without
  * lbm_lee_set_closure, LBM_E_HIP if a launch fails. */
 lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream);

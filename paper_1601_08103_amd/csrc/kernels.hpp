@@ -836,7 +836,7 @@ __global__ __launch_bounds__(256) void import_f64(const double *__restrict__ g, 
 }
 
 // ------------------------------------------------------------------ plain copy (calibration)
-__global__ __launch_bounds__(256) void copy16(const f32x4 *__restrict__ src, f32x4 *__restrict__ dst, size_t n16) {
+[[maybe_unused]] static __global__ __launch_bounds__(256) void copy16(const f32x4 *__restrict__ src, f32x4 *__restrict__ dst, size_t n16) {
     for (size_t i = (size_t)blockIdx.x * 256u + threadIdx.x; i < n16; i += (size_t)gridDim.x * 256u) dst[i] = src[i];
 }
 

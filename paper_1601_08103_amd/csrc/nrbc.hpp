@@ -545,7 +545,7 @@ __global__ __launch_bounds__(256) void nrbc_grad_kernel(const float *__restrict_
     if (lane == 0) out[G::NPARAM] = sq;
 }
 
-__global__ void nrbc_zero_counter(unsigned long long *c) { *c = 0ull; }
+[[maybe_unused]] static __global__ void nrbc_zero_counter(unsigned long long *c) { *c = 0ull; }
 
 // Number of strips with at least one non-zero value (the samples the loss averages over).
 template <class VS>
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(256) void nrbc_count_valid(const float *__restrict_
 }
 
 // grad[p] = sum over waves of ws[w][p] (fixed order); loss = sum of the squared errors / (count k).
-__global__ __launch_bounds__(256) void nrbc_reduce_kernel(const float *__restrict__ ws, int nwaves, int nparam,
+[[maybe_unused]] static __global__ __launch_bounds__(256) void nrbc_reduce_kernel(const float *__restrict__ ws, int nwaves, int nparam,
                                                           const unsigned long long *__restrict__ nvalid, int nout,
                                                           float *__restrict__ grad, float *__restrict__ loss) {
     const int p = blockIdx.x * 256 + threadIdx.x;
@@ -575,7 +575,7 @@ __global__ __launch_bounds__(256) void nrbc_reduce_kernel(const float *__restric
 }
 
 // Adam (Kingma & Ba) on FP32 master parameters; t counts from 1.
-__global__ __launch_bounds__(256) void nrbc_adam_kernel(long long n, float *__restrict__ P, const float *__restrict__ g,
+[[maybe_unused]] static __global__ __launch_bounds__(256) void nrbc_adam_kernel(long long n, float *__restrict__ P, const float *__restrict__ g,
                                                         float *__restrict__ m, float *__restrict__ v, float lr,
                                                         float b1, float b2, float eps, float c1, float c2) {
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;

@@ -812,7 +812,7 @@ __global__ __launch_bounds__(256) void gather_pairs_kernel(const typename ST::el
 // ------------------------------------------------------------------ field comparison
 // Partials of { sum (a - b)^2, sum b^2, max |a - b| } of a box field a against field b of a
 // larger box at offset origin.
-__global__ __launch_bounds__(256) void compare_partials(const double *__restrict__ A, int nx, int ny, int nz,
+[[maybe_unused]] static __global__ __launch_bounds__(256) void compare_partials(const double *__restrict__ A, int nx, int ny, int nz,
                                                         const double *__restrict__ B, int bnx, int bny, int ox, int oy,
                                                         int oz, double *__restrict__ part) {
     double v[3] = {0, 0, 0};

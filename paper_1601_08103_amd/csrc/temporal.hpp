@@ -16,11 +16,16 @@
 // plane are exchanged between threads through LDS rings of 2 + c_z planes (3 + c_z for K = 2);
 // populations with c_x = c_y = 0 stay in the registers of the thread that owns the column in
 // every stage.  The loads of the next two planes (one for the sets with 13 and more velocities)
-// are in flight while a plane is computed, and K-1 barriers per iteration order the LDS traffic.  Each
-// stage's results are rounded to the storage type exactly as a store and reload would
-// (encode, decode), and every cell goes through the same collision as the one-step kernels,
-// so K steps here give the same bits as K one-step launches.
+// are in flight while a plane is computed, and K-1 barriers per iteration order the LDS traffic.
+// Every cell goes through the same collision as the one-step kernels.  The intermediate steps
+// t+1 .. t+K-1 are never stored, so they stay in the compute type: for FP64 and FP32 storage
+// that is the stored value itself and K steps here give the same bits as K one-step launches;
+// for the 16-bit formats (FP32 collision) a launch rounds to the storage format once, at step
+// t+K, instead of once per step, which divides the number of roundings, the dominant error of
+// those formats at tau = 1/2 (nothing damps it), by K.
 #pragma once
+
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -63,6 +68,12 @@ struct TbFrame {
 // per block of 64 threads.  TY = 0: no shape fits (the variant is unsupported).
 constexpr int kTbTx = 64;
 
+// Element type of the LDS rings: the storage type where it holds the compute type's values
+// exactly (FP64, FP32), the compute type (FP32) for the 16-bit formats, whose intermediate steps
+// are not rounded.
+template <class ST>
+using TbRing = std::conditional_t<ST::scaled, typename ST::comp, typename ST::elem>;
+
 template <class VS, class ST, int K>
 struct TbShape {
     using F = TbFrame<VS>;
@@ -71,14 +82,13 @@ struct TbShape {
     static constexpr long lds_bytes(int ty) {
         long cells = 0;
         for (int s = 1; s < K; ++s) cells += (long)(kTbTx + 2 * (K - s)) * (ty + 2 * hy * (K - s));
-        return (long)F::planes(K) * cells * (long)sizeof(typename ST::elem);
+        return (long)F::planes(K) * cells * (long)sizeof(TbRing<ST>);
     }
     static constexpr int pick() {
         if (VS::D == 2) return lds_bytes(1) <= budget ? 1 : 0;
-        // taller tiles (less ring overhead, one 1024-thread block per CU) pay off for the 4- and
-        // 8-byte formats with three or more steps; the 16-bit ones run faster with more, smaller
-        // blocks (measured, D3Q7 256^3)
-        const int top = (K >= 3 && sizeof(typename ST::elem) >= 4) ? 32 : 16;
+        // taller tiles (less ring overhead, one 1024-thread block per CU) pay off for 4- and
+        // 8-byte ring elements with three or more steps (measured, D3Q7 256^3)
+        const int top = (K >= 3 && sizeof(TbRing<ST>) >= 4) ? 32 : 16;
         for (int ty = top; ty >= 4; ty /= 2)
             if (lds_bytes(ty) <= budget) return ty;
         return 0;
@@ -98,10 +108,36 @@ struct TbShape {
 };
 
 // Raw buffer access: a block-uniform descriptor for one plane of one population (base address,
-// no stride, 2^32 - 1 bytes, gfx9 word 3) and a 32-bit byte offset per lane, so a load or store
-// is one instruction with no per-lane 64-bit address arithmetic.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *p) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, -1, 0x00020000);
+// no stride, record count = the plane's bytes, gfx9 word 3) and a 32-bit byte offset per lane, so
+// a load or store is one instruction with no per-lane 64-bit address arithmetic.  An offset at or
+// beyond the record count is out of range: the load returns 0 and the store is dropped, without
+// a memory access.  Lanes without a cell to load or store (ring columns past the ring's end,
+// cells past a ragged box edge) and prefetches past a segment's last plane use that instead of a
+// branch, so every path through the kernel issues the same sequence of memory instructions and
+// the compiler's wait counts stay exact (a load skipped on some paths makes it wait for all of
+// them at the next use of any).  The host keeps a plane under 2 GiB, below kTbOob.
+constexpr unsigned kTbOob = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *p, unsigned records) {
+    // records is block-uniform; readfirstlane keeps it in a scalar register (a per-lane value
+    // would turn every access into a loop over distinct descriptors)
+    const int rec = __builtin_amdgcn_readfirstlane((int)records);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, rec, 0x00020000);
+}
+
+// Decode a value loaded from HBM for stage 1.  FP32 decodes to itself, so the loaded register
+// would stay live through the collision, overlap the next prefetch into the same variable, and
+// force a copy (and a wait for that prefetch) at the loop latch; an explicit move into a fresh
+// register ends the loaded register's life at the decode.
+template <class ST, bool RAW>
+__device__ __forceinline__ typename ST::comp dec_loaded(typename ST::elem v) {
+    if constexpr (sizeof(typename ST::elem) == 4 && !ST::scaled && !ST::has_raw) {
+        float r;
+        __asm__("v_mov_b32 %0, %1" : "=v"(r) : "v"(v));
+        return r;
+    } else {
+        return dec_io<ST, RAW>(v);
+    }
 }
 
 template <typename E>
@@ -190,7 +226,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         return o;
     };
     constexpr int RING_ELEMS = set_off(K);
-    __shared__ E ring[RING_ELEMS];
+    using RE = TbRing<ST>;
+    constexpr bool CARRY = !std::is_same_v<RE, E>;  // intermediate steps kept in the compute type
+    __shared__ RE ring[RING_ELEMS];
 
     // tile of this block; consecutive tiles on one XCD (blocks go round-robin over the 8 XCDs)
     unsigned b = blockIdx.x;
@@ -207,7 +245,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     // block-uniform base plus a per-column 32-bit byte offset within the plane (the source cell
     // of each population; the column's own cell for the stores).
     int cxl[NC], cyl[NC];
-    unsigned xyoff[NC][Q], oxy[NJ];  // byte offsets (the host keeps a plane under 4 GiB)
+    unsigned xyoff[NC][Q], oxy[NJ];  // byte offsets within a plane, or kTbOob
     bool valid[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -249,23 +287,30 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         if (Y < 0) Y += fy;
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-            xyoff[c][i] =
-                (unsigned)(wrap_add(Y, -F::ky(i), fy) * fx + wrap_add(X, -F::kx(i), fx)) * (unsigned)sizeof(E);
-        if (rb == 0) oxy[c < NJ ? c : 0] = (unsigned)(Y * fx + X) * (unsigned)sizeof(E);
+            xyoff[c][i] = ok ? (unsigned)(wrap_add(Y, -F::ky(i), fy) * fx + wrap_add(X, -F::kx(i), fx)) * (unsigned)sizeof(E)
+                             : kTbOob;
+        // stores of interior columns outside the box (a ragged tile) go out of range
+        if (rb == 0)
+            oxy[c < NJ ? c : 0] = (ax - (K - 1) < w && ay - HY * (K - 1) < hgt)
+                                      ? (unsigned)(Y * fx + X) * (unsigned)sizeof(E)
+                                      : kTbOob;
     }
     const size_t plane = (size_t)fx * fy;
+    const unsigned plane_bytes = (unsigned)(plane * sizeof(E));  // < 2^31 (host check)
 
     // local plane l is global plane z0 - (K - 1) + l (wrapped)
     E la[NC][Q], lb[NC][Q];
-    auto load_plane = [&](int l, E(&ld)[NC][Q]) {
+    // live = false: a prefetch past the segment's last plane, issued anyway so the load sits
+    // outside any branch; its records are empty and it reads nothing
+    auto load_plane = [&](int l, E(&ld)[NC][Q], bool live) {
         int Z = (z0 - (K - 1) + l) % fz;
         if (Z < 0) Z += fz;
 #pragma unroll
         for (int i = i0; i < Q; ++i) {
-            const auto r = plane_rsrc(src + (size_t)i * N + (size_t)wrap_add(Z, -F::kz(i), fz) * plane);
+            const auto r = plane_rsrc(src + (size_t)i * N + (size_t)wrap_add(Z, -F::kz(i), fz) * plane,
+                                      live ? plane_bytes : 0u);
 #pragma unroll
-            for (int c = 0; c < NC; ++c)
-                if (valid[c]) ld[c][i] = buf_load<E>(r, xyoff[c][i]);
+            for (int c = 0; c < NC; ++c) ld[c][i] = buf_load<E>(r, xyoff[c][i]);  // 0 where not valid
         }
     };
 
@@ -307,7 +352,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                     sv[0] = 0;
                     if (s == 1) {
 #pragma unroll
-                        for (int i = i0; i < Q; ++i) sv[i] = dec_io<ST, RAW>(cur[c][i]);
+                        for (int i = i0; i < Q; ++i) sv[i] = dec_loaded<ST, RAW>(cur[c][i]);
                     } else {
                         const int set = s - 1;  // ring set read, in its own coordinates
                         const int lxy = (cyl[c] - HY * (s - 2)) * set_dx(set) + (cxl[c] - (s - 2));
@@ -317,8 +362,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                                 const int kz = F::kz(i);
                                 const int q = l - kz;
                                 const int q3 = kz > 0 ? lm3 : kz < 0 ? lp3 : l3;
-                                sv[i] = dec_io<ST, RAW>(ring[set_off(set) + (F::plane_off(i, K) + slot(kz, q, q3)) * set_pl(set) +
-                                                             lxy - F::ky(i) * set_dx(set) - F::kx(i)]);
+                                const RE e = ring[set_off(set) + (F::plane_off(i, K) + slot(kz, q, q3)) * set_pl(set) +
+                                                  lxy - F::ky(i) * set_dx(set) - F::kx(i)];
+                                if constexpr (CARRY)
+                                    sv[i] = e;
+                                else
+                                    sv[i] = dec_io<ST, RAW>(e);
                             } else {
                                 sv[i] = i == IU ? u2[set][c] : i == IR ? r1[set][c] : d0[set][c];
                             }
@@ -326,24 +375,29 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                     }
                     collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, sv);
                     if (s == K) {
-                        const int xl = cxl[c] - (K - 1), yl = cyl[c] - HY * (K - 1);
-                        if (xl < w && yl < hgt) {
-                            const int Zq = z0 - (K - 1) + l;  // in [z0, z0 + seg)
+                        // cells outside the box have an out-of-range offset: no branch
+                        const int Zq = z0 - (K - 1) + l;  // in [z0, z0 + seg)
 #pragma unroll
-                            for (int i = i0; i < Q; ++i)
-                                buf_store<E>(enc_io<ST, RAW>(sv[i]), plane_rsrc(dst + (size_t)i * N + (size_t)Zq * plane),
-                                             oxy[c < NJ ? c : 0]);
-                        }
+                        for (int i = i0; i < Q; ++i)
+                            buf_store<E>(enc_io<ST, RAW>(sv[i]),
+                                         plane_rsrc(dst + (size_t)i * N + (size_t)Zq * plane, plane_bytes),
+                                         oxy[c < NJ ? c : 0]);
                     } else {
                         const int lxy = (cyl[c] - HY * (s - 1)) * set_dx(s) + (cxl[c] - (s - 1));
                         const bool keep_local = C::ring_of(c) <= K - s - 1;
 #pragma unroll
                         for (int i = i0; i < Q; ++i) {
-                            const E e = enc_io<ST, RAW>(sv[i]);
+                            // as stored and reloaded (FP64, FP32: the value itself), or carried
+                            // unrounded (16-bit formats)
+                            CT v = sv[i];
+                            if constexpr (!CARRY) v = dec_io<ST, RAW>(enc_io<ST, RAW>(sv[i]));
                             if (F::moves_xy(i)) {
-                                ring[set_off(s) + (F::plane_off(i, K) + slot(F::kz(i), l, l3)) * set_pl(s) + lxy] = e;
+                                if constexpr (CARRY)
+                                    ring[set_off(s) + (F::plane_off(i, K) + slot(F::kz(i), l, l3)) * set_pl(s) + lxy] = v;
+                                else
+                                    ring[set_off(s) + (F::plane_off(i, K) + slot(F::kz(i), l, l3)) * set_pl(s) + lxy] =
+                                        enc_io<ST, RAW>(sv[i]);
                             } else if (keep_local) {
-                                const CT v = dec_io<ST, RAW>(e);
                                 if (i == IU) u0[s][c] = v;
                                 if (i == IR) r0[s][c] = v;
                                 if (i == ID) d0[s][c] = v;
@@ -352,7 +406,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                     }
                 }
             }
-            if (s == 1 && pl + PF <= last) load_plane(pl + PF, cur);  // in flight across the stages
+            if (s == 1) {
+                // the next loads into `cur` may not move above the last reads of its old values:
+                // otherwise the two overlap, the loop latch copies the new values into the old
+                // registers, and that copy waits for the loads it was meant to keep in flight
+                __builtin_amdgcn_sched_barrier(0);
+                load_plane(pl + PF, cur, pl + PF <= last);  // in flight across the stages
+            }
             if (s < K) {
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
                 __builtin_amdgcn_s_barrier();
@@ -369,9 +429,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
             }
     };
 
-    load_plane(0, la);
+    load_plane(0, la, true);
     if constexpr (PF == 2) {
-        load_plane(1, lb);  // seg >= 1: at least 2K - 1 >= 3 planes
+        load_plane(1, lb, true);  // seg >= 1: at least 2K - 1 >= 3 planes
         for (int pl = 0; pl <= last; pl += 2) {
             body(pl, la);
             if (pl + 1 <= last) body(pl + 1, lb);

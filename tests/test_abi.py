@@ -200,13 +200,14 @@ def test_network_entry_points_reject_bad_arguments():
 @pytest.mark.parametrize("lattice,storage", [("D3Q7", "f32"), ("D3Q7", "f64"), ("D3Q7_DIA", "e3m12"), ("D2Q9", "f32"),
                                              ("D2Q5", "f16"), ("D3Q19", "f16"), ("D3Q9", "bf16"), ("D3Q13", "i16")])
 def test_temporal_blocking_variants_accepted(lattice, storage):
-    """The two-step variant takes any extents of a periodic 2D/3D box whose LDS rings fit; the
-    three-step one where its larger rings fit."""
+    """The two-step variant takes any extents of a periodic 2D/3D box whose LDS rings fit (64 KB;
+    the rings hold FP32 values for the 16-bit formats, so D3Q19's 16 in-plane populations no
+    longer fit); the three-step one where its larger rings fit (160 KB)."""
     D = lbm.lbm_lee_lattice_info(lattice)["D"]
     shape = {2: (5, 70), 3: (3, 5, 70)}[D]
     for tune in (0, 64, 128, 192):
         d = lbm.make_desc(lattice, storage, shape, variant="tb2", tune=tune)
-        assert lbm.lbm_lee_state_bytes(d) > 0
+        assert (lbm.lbm_lee_state_bytes(d) > 0) == (lattice != "D3Q19")
         d3 = lbm.make_desc(lattice, storage, shape, variant="tb3", tune=tune)
         fits3 = not (lattice in ("D3Q13", "D3Q19") and storage == "f64")
         assert (lbm.lbm_lee_state_bytes(d3) > 0) == fits3

@@ -299,6 +299,64 @@ def test_adam_first_step_is_signed_learning_rate():
     assert np.allclose(p["w"], [0.99, -1.99, 3.0], atol=1e-9)
 
 
+def test_adam_bias_correction_over_many_steps():
+    """With a constant gradient g the bias-corrected moments are exactly m_hat = g and
+    v_hat = g^2 at every step t (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so every step moves a
+    parameter by lr g / (|g| + eps).  A bias correction with any other exponent than t fails this
+    from t = 2 on (at t = 1 every exponent agrees)."""
+    g0 = np.array([0.5, -1e-3, 2.0, -7.0])
+    p = {"w": np.array([1.0, -2.0, 3.0, 0.25])}
+    g = {"w": g0.copy()}
+    m = {"w": np.zeros(4)}
+    v = {"w": np.zeros(4)}
+    lr, eps = 0.01, 1e-12
+    for t in range(1, 11):
+        before = p["w"].copy()
+        mlp.adam(p, g, m, v, t, lr=lr, b1=0.9, b2=0.999, eps=eps)
+        assert np.allclose(before - p["w"], lr * g0 / (np.abs(g0) + eps), rtol=1e-12, atol=0), t
+        assert np.allclose(m["w"], (1 - 0.9 ** t) * g0, rtol=1e-13, atol=0), t
+        assert np.allclose(v["w"], (1 - 0.999 ** t) * g0 ** 2, rtol=1e-12, atol=0), t
+
+
+def test_adam_planted_bias_correction_mistake_is_caught():
+    """The pin above is not vacuous: the same loop with the bias correction frozen at t = 1
+    (a wrong exponent) departs from lr g / |g| at t = 2."""
+    g0 = np.array([0.5, -2.0])
+    m, v = np.zeros(2), np.zeros(2)
+    steps = []
+    for t in range(1, 3):
+        m = 0.9 * m + 0.1 * g0
+        v = 0.999 * v + 0.001 * g0 ** 2
+        mh, vh = m / (1 - 0.9 ** 1), v / (1 - 0.999 ** 1)  # planted: exponent 1 instead of t
+        steps.append(0.01 * mh / (np.sqrt(vh) + 1e-12))
+    assert np.allclose(steps[0], 0.01 * np.sign(g0))
+    assert not np.allclose(steps[1], 0.01 * np.sign(g0), rtol=1e-6)
+
+
+def test_normalise_scale_is_the_root_mean_square():
+    """s is the root mean square of each row, from hand-computable rows: [3, 4, 0, ...] of length n
+    has s = 5 / sqrt(n) (its mean |x| is 7 / n, so a mean in place of the RMS fails); a constant
+    row c has s = |c|; a row scaled by 2^-120 (squares below FP64's normal range) has its s scaled
+    exactly by 2^-120; an all-zero row has s = 0 and z = 0; z = x / s in every other row."""
+    n = 21
+    rows = np.zeros((5, n))
+    rows[0, :2] = [3.0, 4.0]
+    rows[1, :] = -0.75
+    rows[2, :2] = [3.0 * 2.0 ** -120, 4.0 * 2.0 ** -120]
+    rows[3, :] = np.arange(1, n + 1, dtype=np.float64)
+    z, s = mlp.normalise(rows)
+    s = s.ravel()
+    want = [5.0 / np.sqrt(n), 0.75, 5.0 / np.sqrt(n) * 2.0 ** -120,
+            np.sqrt(np.sum(np.arange(1, n + 1) ** 2.0) / n), 0.0]
+    for k in range(5):
+        assert abs(s[k] - want[k]) <= 1e-15 * want[k], k
+    assert s[0] != 7.0 / n
+    assert np.all(z[4] == 0.0)
+    for k in range(4):
+        assert np.allclose(z[k] * s[k], rows[k], rtol=1e-15, atol=0)
+        assert abs(np.sqrt(np.mean(z[k] ** 2)) - 1.0) <= 1e-15
+
+
 def test_flat_layout_roundtrip():
     p = mlp.init_params(np.random.default_rng(0), 27, 3)
     v = mlp.flat(p)
