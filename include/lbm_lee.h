@@ -402,6 +402,18 @@ lbm_status lbm_lee_compare_fields(const double *a, const int64_t n_a[3], const d
                                   const int64_t origin[3], double out[3], void *scratch, size_t scratch_bytes,
                                   void *stream);
 
+/* lbm_lee_compare_fields without the scratch argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * no hipMalloc, hipFree or allocating library call.  Its reduction scratch is a file-scope device
+ * array of 96 KiB that each GPU the library runs on holds until the process ends (its address is
+ * looked up once per device, on the first call there).  The scratch need does not grow with the
+ * boxes (a fixed grid of partial sums), so every box lbm_lee_compare_fields accepts fits; other
+ * arguments and errors as there.  All calls on one GPU share the array: calls that overlap on one
+ * GPU (concurrent streams or threads) race and must be serialised by the caller.
+ * SYNCHRONISES the stream. */
+lbm_status lbm_lee_compare_fields_static(const double *a, const int64_t n_a[3], const double *b,
+                                         const int64_t n_b[3], const int64_t origin[3], double out[3], void *stream);
+
 /* Plain device-to-device copy kernel (16-byte vectors): the reference point for bandwidth
  * and counter calibration.  bytes must be a multiple of 16, both pointers 16-byte aligned. */
 lbm_status lbm_lee_device_copy(void *dst, const void *src, size_t bytes, void *stream);

@@ -2,6 +2,7 @@
 // The step launch sequences live in step_<set>.hip (one translation unit per velocity set).
 #include <cstdarg>
 #include <cstdio>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -604,6 +605,34 @@ lbm_status check_compare_args(const double *a, const int64_t n_a[3], const doubl
     return LBM_OK;
 }
 
+// Scratch of lbm_lee_compare_fields_static: a file-scope device array, so that entry point
+// needs no allocation and no workspace argument.  Every GPU the library runs on holds its own
+// copy until the process ends.  In host code the array's name is only a stand-in for the
+// symbol: its device address, different on each GPU, comes from hipGetSymbolAddress, taken once
+// per device (with that device current) on the entry point's first call there and kept below.
+constexpr size_t kStaticScratchBytes = kScratchBytes;  // 96 KiB: kReduceBlocks partial rows + results
+static_assert((size_t)(6 * kReduceBlocks + 6) * sizeof(double) <= kStaticScratchBytes, "reduction layout");
+static __device__ __align__(256) unsigned char static_scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_scratch_mu;
+void *g_static_scratch_ptr[kMaxDevices] = {};
+
+lbm_status static_scratch_on_current_device(void **out) {
+    int dev = -1;
+    LBM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LBM_E_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_static_scratch_mu);
+    if (!g_static_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(static_scratch));
+        if (e != hipSuccess || !p)
+            return fail(LBM_E_HIP, "hipGetSymbolAddress(static_scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_static_scratch_ptr[dev] = p;
+    }
+    *out = g_static_scratch_ptr[dev];
+    return LBM_OK;
+}
 }  // namespace
 
 lbm_status lbm_lee_compare_fields(const double *a, const int64_t n_a[3], const double *b, const int64_t n_b[3],
@@ -613,6 +642,16 @@ lbm_status lbm_lee_compare_fields(const double *a, const int64_t n_a[3], const d
     if (s != LBM_OK) return s;
     if (!scratch || scratch_bytes < kScratchBytes || !aligned256(scratch))
         return fail(LBM_E_INVALID, "scratch too small or misaligned");
+    s = compare_fields_on(a, n_a, b, n_b, origin, out, scratch, static_cast<hipStream_t>(stream));
+    return s == LBM_OK ? ok() : s;
+}
+
+lbm_status lbm_lee_compare_fields_static(const double *a, const int64_t n_a[3], const double *b,
+                                         const int64_t n_b[3], const int64_t origin[3], double out[3], void *stream) {
+    lbm_status s = check_compare_args(a, n_a, b, n_b, origin, out);
+    if (s != LBM_OK) return s;
+    void *scratch = nullptr;
+    if ((s = static_scratch_on_current_device(&scratch)) != LBM_OK) return s;
     s = compare_fields_on(a, n_a, b, n_b, origin, out, scratch, static_cast<hipStream_t>(stream));
     return s == LBM_OK ? ok() : s;
 }

@@ -89,6 +89,9 @@ SIGNATURES = {
     "lbm_lee_compare_fields": (ctypes.c_int32, [_VP, ctypes.POINTER(ctypes.c_int64), _VP,
                                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                                 ctypes.POINTER(ctypes.c_double), _VP, ctypes.c_size_t, _VP]),
+    "lbm_lee_compare_fields_static": (ctypes.c_int32, [_VP, ctypes.POINTER(ctypes.c_int64), _VP,
+                                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                                       ctypes.POINTER(ctypes.c_double), _VP]),
     "lbm_lee_last_error": (ctypes.c_char_p, []),
     "lbm_lee_version": (ctypes.c_char_p, []),
 }
@@ -290,6 +293,13 @@ def lbm_lee_compare_fields(a, n_a, b, n_b, origin, scratch, scratch_bytes, strea
     out = (ctypes.c_double * 3)()
     _check("lbm_lee_compare_fields", load().lbm_lee_compare_fields(a, _i64x3(n_a), b, _i64x3(n_b), _i64x3(origin),
                                                                    out, scratch, int(scratch_bytes), stream))
+    return [float(v) for v in out]
+
+
+def lbm_lee_compare_fields_static(a, n_a, b, n_b, origin, stream):
+    out = (ctypes.c_double * 3)()
+    _check("lbm_lee_compare_fields_static", load().lbm_lee_compare_fields_static(a, _i64x3(n_a), b, _i64x3(n_b),
+                                                                                 _i64x3(origin), out, stream))
     return [float(v) for v in out]
 
 
