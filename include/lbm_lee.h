@@ -57,7 +57,9 @@ typedef int32_t lbm_status;
 #define LBM_D3Q19 6    /* 3D family, theta0 = 3/10, alpha = 0                      */
 #define LBM_D2Q5_DIA 7 /* diatomic, rho0 = 20/3, theta0 = 3/10, gamma = 5/3        */
 #define LBM_D3Q7_DIA 8 /* diatomic, f1 = 5/42 (rho0 = 1), theta0 = 5/21, gamma = 7/5 */
-#define LBM_NUM_LATTICES 9
+#define LBM_D3Q27 9    /* 3D family, theta0 = 1/3, alpha = 1/216: all 27 weights positive */
+                       /* (8/27, 2/27, 1/54, 1/216); one-step variants only, no LBM_BC_MLP */
+#define LBM_NUM_LATTICES 10
 
 /* Population storage.  F64 and F32 store g itself.  F16 and BF16 store the normalised
  * deviation h_i = S g_i / f*_i (S a power of two, see lbm_lee_desc.store_scale) rounded to
@@ -181,6 +183,36 @@ typedef struct lbm_lee *lbm_lee_handle;
 
 /* Tables of a velocity set as used by the kernels (host only, no GPU work). */
 lbm_status lbm_lee_lattice_info(int32_t lattice, lbm_lattice_info *out);
+
+/* Units of a dimensional problem run on a velocity set (Section "The Linearized Euler
+ * Equations", non-dimensionalisation): dimensional quantities (underlined in the paper) are the
+ * non-dimensional ones times these scales:
+ *     rho_dim = rho_star rho (background and fluctuation), theta_dim = theta_star theta,
+ *     u_dim = u_star u with u_star^2 = theta_star, x_dim = x_star x, t_dim = t_star t,
+ *     t_star = x_star / u_star.
+ * Because the non-dimensional LEE keep the same form, a set with background (rho0, theta0) runs any
+ * dimensional background (rho0_dim, theta0_dim): rho_star = rho0_dim / rho0, theta_star =
+ * theta0_dim / theta0.  The library's lattice units are these non-dimensional units with
+ * dx = dt = 1; a grid of spacing dx (non-dimensional) maps cell j to x = j dx and step n to
+ * t = n dx. */
+typedef struct lbm_lee_scaling {
+    double rho_star, theta_star, u_star, x_star, t_star;
+} lbm_lee_scaling;
+
+/* Scales for a dimensional background rho0_dim, theta0_dim (both > 0) and length unit x_star > 0
+ * on `lattice` (host only, no GPU work).  Errors: LBM_E_INVALID for an unknown lattice, a NULL out
+ * or a non-positive or non-finite argument. */
+lbm_status lbm_lee_dimensional_scaling(int32_t lattice, double rho0_dim, double theta0_dim, double x_star,
+                                       lbm_lee_scaling *out);
+
+/* Time steps for a dimensional end time t_dim >= 0 with non-dimensional step dt = dx > 0 (host
+ * only): T = t_dim / t_star, *nsteps = round(T / dt) (half away from zero), *t_end = nsteps dt,
+ * the end time the run reaches, and *offset = T - nsteps dt, the mismatch Table 1 of Section
+ * "Numerical Results" lists for the 3D diatomic runs.  Any output may be NULL.  Errors:
+ * LBM_E_INVALID for a NULL or invalid scaling, a negative or non-finite time, dt <= 0 or a step
+ * count beyond 2^62. */
+lbm_status lbm_lee_dimensional_steps(const lbm_lee_scaling *s, double t_dim, double dt, int64_t *nsteps,
+                                     double *t_end, double *offset);
 
 /* Bytes of one population buffer: Q * N * sizeof(storage element).  0 on a bad desc. */
 size_t lbm_lee_state_bytes(const lbm_lee_desc *desc);

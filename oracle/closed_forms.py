@@ -133,6 +133,72 @@ def radial_3d_gaussian(lat: Lattice, A: float, sigma: float, centre, shape, t: f
     return join_state(lat, p, u, np.zeros_like(p))
 
 
+def radial_2d_gaussian(lat: Lattice, A: float, sigma: float, centre, shape, t: float, nodes: int = 1000,
+                       table: int = 20000):
+    """Isentropic 2D Gaussian pressure pulse p'0 = A exp(-r^2/(2 sigma^2)), u'0 = 0, at time t, on
+    the periodic box (the sum over periodic images of the free-space solution).
+
+    The 2D wave equation (c^2 = gamma theta0) in the order-0 Hankel representation:
+      p'(r,t)   = int_0^inf P(k) cos(c k t) J0(k r) k dk,  P(k) = A sigma^2 exp(-sigma^2 k^2 / 2)
+                  (at t = 0 the Hankel pair of the Gaussian),
+      u'_r(r,t) = (1 / (rho0 c)) int_0^inf P(k) sin(c k t) J1(k r) k dk
+                  (from rho0 d_t u' = -grad p' and d_r J0(k r) = -k J1(k r)).
+    Gauss-Legendre quadrature in k on [0, 12/sigma] (P is below exp(-72) A sigma^2 beyond), on a
+    table of radii up to c t + 12 sigma (nothing arrives beyond it), then a cubic spline in r.
+    """
+    from scipy.interpolate import CubicSpline
+    from scipy.special import j0, j1
+
+    ny, nx = shape
+    L = np.array([nx, ny], dtype=np.float64)
+    c = np.sqrt(lat.cs2)
+    reach = c * t + 12.0 * sigma
+    xg, wg = np.polynomial.legendre.leggauss(nodes)
+    K = 12.0 / sigma
+    k = 0.5 * K * (xg + 1.0)
+    w = 0.5 * K * wg * A * sigma * sigma * np.exp(-0.5 * sigma * sigma * k * k) * k
+    rr = np.linspace(0.0, reach, table)
+    kr = np.outer(rr, k)
+    prof_p = j0(kr) @ (w * np.cos(c * k * t))
+    prof_u = j1(kr) @ (w * np.sin(c * k * t)) / (lat.rho0 * c)
+    sp, su = CubicSpline(rr, prof_p), CubicSpline(rr, prof_u)
+    y, x = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64), indexing="ij")
+    p = np.zeros(shape)
+    u = np.zeros((2,) + tuple(shape))
+    images = int(np.ceil(reach / L.min())) + 1
+    for iy in range(-images, images + 1):
+        for ix in range(-images, images + 1):
+            dx = x - (centre[0] + ix * L[0])
+            dy = y - (centre[1] + iy * L[1])
+            r = np.sqrt(dx * dx + dy * dy)
+            near = r <= reach
+            if not near.any():
+                continue
+            rn = r[near]
+            p[near] += sp(rn)
+            ur = su(rn)
+            safe = np.where(rn > 0, rn, 1.0)
+            u[0][near] += np.where(rn > 0, ur * dx[near] / safe, 0.0)
+            u[1][near] += np.where(rn > 0, ur * dy[near] / safe, 0.0)
+    return join_state(lat, p, u, np.zeros_like(p))
+
+
+def gaussian_periodic(shape, A: float, sigma: float, centre) -> np.ndarray:
+    """A exp(-r^2/(2 sigma^2)) summed over the periodic images of the box (C-order shape, centre in
+    cells (x, y[, z])): the smooth periodic initial field the radial closed forms evolve."""
+    dims = list(reversed([int(s) for s in shape]))
+    grids = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape], indexing="ij")
+    coords = [grids[len(shape) - 1 - a] for a in range(len(shape))]
+    out = np.zeros(tuple(shape))
+    reach = 12.0 * sigma
+    rng = [range(-(int(np.ceil(reach / n)) + 1), int(np.ceil(reach / n)) + 2) for n in dims]
+    from itertools import product
+    for img in product(*rng):
+        r2 = sum((coords[a] - (centre[a] + img[a] * dims[a])) ** 2 for a in range(len(dims)))
+        out += A * np.exp(-r2 / (2.0 * sigma * sigma))
+    return out
+
+
 def nondimensional_time(t_dim: float, theta0_dim: float, theta0: float, x_star: float = 1.0) -> float:
     """Non-dimensional time for a dimensional one (conversions of the LEE section):
     theta0_dim = theta0* theta0, (u*)^2 = theta0*, u* = x*/t*, t = t_dim / t*."""

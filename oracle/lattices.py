@@ -11,7 +11,8 @@ Every table is generated from the formulas the paper prints, not typed in as dec
   beta, and the coefficients a1, a2, b, c1, c2 printed there).
 * 3D monoatomic family f*(rho0, theta0, alpha) on the 27 velocities of Section "3D",
   reduced to D3Q7 (theta0 = 1/5, alpha = 0), D3Q9 (3/5, 3/40), D3Q13 (2/5, 0) and
-  D3Q19 (3/10, 0) by dropping the velocities whose weight is zero.
+  D3Q19 (3/10, 0) by dropping the velocities whose weight is zero, and in full as D3Q27
+  (1/3, 1/216: every weight positive).
 * D3Q7 diatomic family: subsection "Diatomic Gases" of Section "3D" with f1 = 5/42.
 * D2Q9 is NOT in the paper.  Its weights are derived here from the similarity
   conditions of Section "Derivation of Finite Discrete Velocity Models for Monoatomic
@@ -175,6 +176,13 @@ def d3q19():
     return family27("D3Q19", Fr(3, 10), Fr(0))
 
 
+def d3q27():
+    """The member of the 27-velocity family with every weight positive that the build uses:
+    theta0 = 1/3, alpha = 1/216 (weights 8/27, 2/27, 1/54, 1/216).  The paper prints the family,
+    not this member."""
+    return family27("D3Q27", Fr(1, 3), Fr(1, 216))
+
+
 def d3q7_dia(f1=Fr(5, 42)):
     rho0, theta0 = Fr(42, 5) * f1, Fr(5, 21)
     vw = [((0, 0, 0), Fr(12, 5) * f1)] + [(v, f1) for v in _axis_order(3)]
@@ -185,10 +193,10 @@ def d3q7_dia(f1=Fr(5, 42)):
 
 ALL = {
     "D1Q3": d1q3, "D2Q5": d2q5, "D2Q9": d2q9, "D3Q7": d3q7, "D3Q9": d3q9, "D3Q13": d3q13,
-    "D3Q19": d3q19, "D2Q5_DIA": d2q5_dia, "D3Q7_DIA": d3q7_dia,
+    "D3Q19": d3q19, "D2Q5_DIA": d2q5_dia, "D3Q7_DIA": d3q7_dia, "D3Q27": d3q27,
 }
 
-MONOATOMIC = ("D1Q3", "D2Q5", "D2Q9", "D3Q7", "D3Q9", "D3Q13", "D3Q19")
+MONOATOMIC = ("D1Q3", "D2Q5", "D2Q9", "D3Q7", "D3Q9", "D3Q13", "D3Q19", "D3Q27")
 
 
 def get(name: str) -> Lattice:

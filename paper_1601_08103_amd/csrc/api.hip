@@ -133,6 +133,37 @@ lbm_status lbm_lee_lattice_info(int32_t lattice, lbm_lattice_info *out) {
     return ok();
 }
 
+lbm_status lbm_lee_dimensional_scaling(int32_t lattice, double rho0_dim, double theta0_dim, double x_star,
+                                       lbm_lee_scaling *out) {
+    if (!out) return fail(LBM_E_INVALID, "out is NULL");
+    LatticeTable t;
+    if (!build_lattice(lattice, &t)) return fail(LBM_E_INVALID, "unknown lattice id %d", lattice);
+    if (!(rho0_dim > 0.0) || !(theta0_dim > 0.0) || !(x_star > 0.0) || !std::isfinite(rho0_dim) ||
+        !std::isfinite(theta0_dim) || !std::isfinite(x_star))
+        return fail(LBM_E_INVALID, "rho0_dim, theta0_dim and x_star must be finite and > 0");
+    out->rho_star = rho0_dim / t.rho0;
+    out->theta_star = theta0_dim / t.theta0;
+    out->u_star = std::sqrt(out->theta_star);
+    out->x_star = x_star;
+    out->t_star = x_star / out->u_star;
+    return ok();
+}
+
+lbm_status lbm_lee_dimensional_steps(const lbm_lee_scaling *s, double t_dim, double dt, int64_t *nsteps,
+                                     double *t_end, double *offset) {
+    if (!s) return fail(LBM_E_INVALID, "scaling is NULL");
+    if (!(s->t_star > 0.0) || !std::isfinite(s->t_star)) return fail(LBM_E_INVALID, "scaling has no valid t_star");
+    if (!(t_dim >= 0.0) || !std::isfinite(t_dim)) return fail(LBM_E_INVALID, "t_dim must be finite and >= 0");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(LBM_E_INVALID, "dt must be finite and > 0");
+    const double T = t_dim / s->t_star;
+    const double n = std::round(T / dt);
+    if (!(n <= 4.6e18)) return fail(LBM_E_INVALID, "more than 2^62 steps");
+    if (nsteps) *nsteps = (int64_t)n;
+    if (t_end) *t_end = n * dt;
+    if (offset) *offset = T - n * dt;
+    return ok();
+}
+
 size_t lbm_lee_state_bytes(const lbm_lee_desc *d) {
     LatticeTable t;
     if (check_desc(d, &t) != LBM_OK) return 0;
@@ -318,6 +349,7 @@ lbm_status lbm_lee_step(lbm_lee_handle h, int64_t nsteps, void *stream) {
         case LBM_D3Q9: s = step_lattice<VS_D3Q9>(h, nsteps, st); break;
         case LBM_D3Q13: s = step_lattice<VS_D3Q13>(h, nsteps, st); break;
         case LBM_D3Q19: s = step_lattice<VS_D3Q19>(h, nsteps, st); break;
+        case LBM_D3Q27: s = step_lattice<VS_D3Q27>(h, nsteps, st); break;
         default: s = fail(LBM_E_INVALID, "unknown lattice id %d", h->desc.lattice);
     }
     return s == LBM_OK ? ok() : s;
@@ -472,6 +504,7 @@ lbm_status lbm_nrbc_dims(int32_t lattice, int32_t dims[4]) {
     LatticeTable t;
     if (!dims) return fail(LBM_E_INVALID, "dims is NULL");
     if (!build_lattice(lattice, &t)) return fail(LBM_E_INVALID, "unknown lattice id %d", lattice);
+    if (!net_fits(t)) return fail(LBM_E_UNSUPPORTED, "the closure network takes sets of up to 21 velocities");
     dims[0] = (int32_t)net_inputs(t);
     dims[1] = net_outputs(t);
     dims[2] = kHidden;
@@ -505,8 +538,11 @@ lbm_status lbm_nrbc_forward(int32_t lattice, const float *params, const float *s
     const unsigned grid = (unsigned)std::min<long long>((tiles + 3) / 4, 4096);
     lbm_status s = visit(lattice, LBM_F32, [&](auto vs, auto) -> lbm_status {
         using VS = decltype(vs);
-        nrbc_forward_kernel<VS><<<grid, 256, 0, st>>>(params, strips, count, out);
-        return launch_check();
+        if constexpr (NetGeom<VS>::fits) {
+            nrbc_forward_kernel<VS><<<grid, 256, 0, st>>>(params, strips, count, out);
+            return launch_check();
+        }
+        return fail(LBM_E_UNSUPPORTED, "the closure network takes sets of up to 21 velocities");
     });
     return s == LBM_OK ? ok() : s;
 }
@@ -520,18 +556,22 @@ lbm_status lbm_nrbc_loss_grad(int32_t lattice, const float *params, const float 
     hipStream_t st = static_cast<hipStream_t>(stream);
     lbm_status s = visit(lattice, LBM_F32, [&](auto vs, auto) -> lbm_status {
         using VS = decltype(vs);
-        using G = NetGeom<VS>;
-        // layout: [counter (256 bytes)][kNetGrid * 4 partial rows]
-        auto *nvalid = static_cast<unsigned long long *>(workspace);
-        float *ws = reinterpret_cast<float *>(static_cast<char *>(workspace) + 256);
-        nrbc_zero_counter<<<1, 1, 0, st>>>(nvalid);
-        nrbc_count_valid<VS><<<blocks_for((size_t)count), 256, 0, st>>>(strips, count, nvalid);
-        nrbc_grad_kernel<VS><<<kNetGrid, 256, 0, st>>>(params, strips, targets, count, nvalid, ws);
-        lbm_status ls = launch_check();
-        if (ls != LBM_OK) return ls;
-        nrbc_reduce_kernel<<<(G::NPARAM + 1 + 255) / 256, 256, 0, st>>>(ws, kNetGrid * 4, G::NPARAM, nvalid, G::NOUT,
-                                                                       grad, loss);
-        return launch_check();
+        if constexpr (!NetGeom<VS>::fits) {
+            return fail(LBM_E_UNSUPPORTED, "the closure network takes sets of up to 21 velocities");
+        } else {
+            using G = NetGeom<VS>;
+            // layout: [counter (256 bytes)][kNetGrid * 4 partial rows]
+            auto *nvalid = static_cast<unsigned long long *>(workspace);
+            float *ws = reinterpret_cast<float *>(static_cast<char *>(workspace) + 256);
+            nrbc_zero_counter<<<1, 1, 0, st>>>(nvalid);
+            nrbc_count_valid<VS><<<blocks_for((size_t)count), 256, 0, st>>>(strips, count, nvalid);
+            nrbc_grad_kernel<VS><<<kNetGrid, 256, 0, st>>>(params, strips, targets, count, nvalid, ws);
+            lbm_status ls = launch_check();
+            if (ls != LBM_OK) return ls;
+            nrbc_reduce_kernel<<<(G::NPARAM + 1 + 255) / 256, 256, 0, st>>>(ws, kNetGrid * 4, G::NPARAM, nvalid, G::NOUT,
+                                                                           grad, loss);
+            return launch_check();
+        }
     });
     return s == LBM_OK ? ok() : s;
 }

@@ -115,6 +115,13 @@ inline bool tb_plane_fits(const lbm_lee_desc *d, int D) {
     return plane <= 2147483648.0;
 }
 
+// The closure network's matrix-core tiles: at most 128 inputs (6 Q) and 16 outputs.
+inline bool net_fits(const LatticeTable &t) {
+    int k = 0;
+    for (int i = 0; i < t.Q; ++i) k += t.c[i][0] == 1 ? 1 : 0;
+    return (kHistory * 3 * t.Q + 15) / 16 * 16 <= 128 && k <= 16;
+}
+
 inline lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
     if (!d) return fail(LBM_E_INVALID, "desc is NULL");
     if (!build_lattice(d->lattice, tab)) return fail(LBM_E_INVALID, "unknown lattice id %d", d->lattice);
@@ -156,6 +163,9 @@ inline lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
     if (d->bc != LBM_BC_PERIODIC)
         for (int a = 0; a < tab->D; ++a)
             if (d->n[a] < 3) return fail(LBM_E_INVALID, "open boundaries need n[%d] >= 3", a);
+    if (d->bc == LBM_BC_MLP && !net_fits(*tab))
+        return fail(LBM_E_UNSUPPORTED, "the closure network takes sets of up to 21 velocities (lattice %d has %d)",
+                    d->lattice, tab->Q);
     if (d->bc == LBM_BC_SPONGE) {
         if (d->sponge_width < 1) return fail(LBM_E_INVALID, "sponge_width must be >= 1");
         if (!(d->sponge_sigma >= 0.0 && d->sponge_sigma <= 1.0)) return fail(LBM_E_INVALID, "sponge_sigma must lie in [0, 1]");
@@ -191,6 +201,7 @@ inline lbm_status visit(int lattice, int storage, F &&f) {
         case LBM_D3Q9: return visit_storage<VS_D3Q9>(storage, f);
         case LBM_D3Q13: return visit_storage<VS_D3Q13>(storage, f);
         case LBM_D3Q19: return visit_storage<VS_D3Q19>(storage, f);
+        case LBM_D3Q27: return visit_storage<VS_D3Q27>(storage, f);
         default: return fail(LBM_E_INVALID, "unknown lattice id %d", lattice);
     }
 }
@@ -310,7 +321,7 @@ FaceTab<VS::Q> face_table(const LatticeTable &t, const int64_t n[3]) {
             for (int j = 0; j < VS::Q; ++j)
                 if (t.c[j][0] == c[0] && t.c[j][1] == c[1] && t.c[j][2] == c[2]) ft.perm[f][j] = (signed char)i;
         }
-        for (int r = 0; r < NetGeom<VS>::NOUT; ++r) ft.rank[f][ft.perm[f][entering_index<VS>(r)]] = (signed char)r;
+        for (int r = 0; r < entering_count<VS>(); ++r) ft.rank[f][ft.perm[f][entering_index<VS>(r)]] = (signed char)r;
     }
     for (int f = ft.nfaces; f < 7; ++f) ft.node_off[f] = off;
     return ft;

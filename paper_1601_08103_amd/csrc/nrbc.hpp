@@ -82,8 +82,9 @@ struct NetGeom {
     static constexpr int OFF_W3 = OFF_B2 + kHidden;
     static constexpr int OFF_B3 = OFF_W3 + kHidden * NOUT;
     static constexpr int NPARAM = OFF_B3 + NOUT;
-    static_assert(NIN_PAD <= 128, "strip wider than the input tile");
-    static_assert(NOUT <= 16, "too many entering populations for one output tile");
+    // the matrix-core tiles hold an input of at most 128 values and at most 16 outputs (every set
+    // but D3Q27); kernels that run the network assert it
+    static constexpr bool fits = NIN_PAD <= 128 && NOUT <= 16;
 };
 
 // Per-wave LDS tiles (bfloat16 bits); ZW = width of the input tile.
@@ -376,6 +377,7 @@ template <class VS>
 __global__ __launch_bounds__(256) void nrbc_forward_kernel(const float *__restrict__ P, const float *__restrict__ strips,
                                                            long long count, float *__restrict__ out) {
     using G = NetGeom<VS>;
+    static_assert(G::fits, "network tiles");
     __shared__ FwdTiles<G::ZW> tiles[4];
     __shared__ NetFrags<VS> F;
     stage_forward_weights<VS>(P, F);
@@ -416,6 +418,7 @@ __global__ __launch_bounds__(256) void nrbc_grad_kernel(const float *__restrict_
                                                         const float *__restrict__ targets, long long count,
                                                         const unsigned long long *__restrict__ nvalid,
                                                         float *__restrict__ ws) {
+    static_assert(NetGeom<VS>::fits, "network tiles");
     using G = NetGeom<VS>;
     constexpr int MT1 = G::NIN_PAD / 16;
     __shared__ WaveTiles<G::ZW> tiles[4];

@@ -185,7 +185,7 @@ __global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__r
     }
     x[a] = side ? ft.n[a] - 1 : 0;
     const size_t cell = ((size_t)x[2] * ft.n[1] + x[1]) * ft.n[0] + x[0];
-    constexpr int K = NetGeom<VS>::NOUT;
+    constexpr int K = entering_count<VS>();
 
     CT s[VS::Q];
     shell_inside<VS, ST, SKIP0>(src, N, closure, x, ft, s);
@@ -282,6 +282,7 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
                                                         const float *__restrict__ P, float *__restrict__ ghost,
                                                         const float *__restrict__ hist_in, float *__restrict__ hist_out,
                                                         FaceTab<VS::Q> ft, FieldCoef<VS::Q> fk) {
+    static_assert(NetGeom<VS>::fits, "network tiles");
     using G = NetGeom<VS>;
     constexpr int NS = G::NSTRIP;
     __shared__ FwdTiles<G::ZW> tiles[4];
@@ -510,6 +511,7 @@ __device__ void open2d_ring_mlp(Open2dShared<VS> &sh, const typename ST::elem *_
                                 float *__restrict__ ghost, const float *__restrict__ hist_in,
                                 float *__restrict__ hist_out, const FaceTab<VS::Q> &ft,
                                 const StepCoef<typename ST::comp, VS::Q> &ks, const FieldCoef<VS::Q> &fk) {
+    static_assert(NetGeom<VS>::fits, "network tiles");
     using G = NetGeom<VS>;
     using CT = typename ST::comp;
     static_assert(VS::D == 2 && G::ZW == 64, "2D sets only");

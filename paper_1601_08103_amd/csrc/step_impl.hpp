@@ -200,12 +200,14 @@ lbm_status step_lattice(lbm_lee *h, int64_t nsteps, hipStream_t st) {
                         LBM_HIP(hipEventRecord(h->fork, st));
                         LBM_HIP(hipStreamWaitEvent(h->aux, h->fork, 0));
                     }
-                    if (hin)
-                        ghost_mlp_kernel<VS, ST, true><<<ghost_blocks, 256, 0, fork ? h->aux : st>>>(
-                            src, h->N, h->net, h->ghost, hin, hout, ft, fk);
-                    else
-                        ghost_mlp_kernel<VS, ST, false><<<ghost_blocks, 256, 0, fork ? h->aux : st>>>(
-                            src, h->N, h->net, h->ghost, hin, hout, ft, fk);
+                    if constexpr (NetGeom<VS>::fits) {
+                        if (hin)
+                            ghost_mlp_kernel<VS, ST, true><<<ghost_blocks, 256, 0, fork ? h->aux : st>>>(
+                                src, h->N, h->net, h->ghost, hin, hout, ft, fk);
+                        else
+                            ghost_mlp_kernel<VS, ST, false><<<ghost_blocks, 256, 0, fork ? h->aux : st>>>(
+                                src, h->N, h->net, h->ghost, hin, hout, ft, fk);
+                    }
                     if (fork) LBM_HIP(hipEventRecord(h->join, h->aux));
                     h->hist_valid = true;
                 }

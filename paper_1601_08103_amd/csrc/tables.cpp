@@ -8,7 +8,8 @@
 //    adiabatic exponent gamma = (M+2)/M with M = D degrees of freedom;
 //  * D1Q3 and D2Q5 weights: subsections "D1Q3" and "D2Q5 for Monoatomic Gases";
 //  * the 3D family f*(rho0, theta0, alpha) of Section "3D" (rest, axis, edge, corner weights),
-//    with the (theta0, alpha) choices that reduce it to D3Q7, D3Q9, D3Q13 and D3Q19;
+//    with the (theta0, alpha) choices that reduce it to D3Q7, D3Q9, D3Q13 and D3Q19, and the
+//    member theta0 = 1/3, alpha = 1/216 with all 27 weights positive (D3Q27);
 //  * diatomic D2Q5 and D3Q7 (subsection "D2Q5 for Diatomic Gases" and the "Diatomic Gases"
 //    subsection of Section "3D"): printed weights, beta and coefficients, gamma = (M+2)/M with
 //    M = 2D - 1.
@@ -112,6 +113,13 @@ bool build_lattice(int id, LatticeTable *t) {
             copy_velocities<VS_D3Q19>(t);
             family3d(t, 1.0, 0.3, 0.0);
             t->name = "D3Q19";
+            return true;
+        case LBM_D3Q27:
+            // a member of the family with every weight positive: theta0 = 1/3, alpha = 1/216 gives
+            // 8/27, 2/27, 1/54, 1/216 (the products of the D1Q3 weights 2/3, 1/6, 1/6)
+            copy_velocities<VS_D3Q27>(t);
+            family3d(t, 1.0, 1.0 / 3.0, 1.0 / 216.0);
+            t->name = "D3Q27";
             return true;
         case LBM_D2Q5_DIA: {
             copy_velocities<VS_D2Q5>(t);

@@ -1,8 +1,8 @@
 // Compile-time velocity sets of the LEE lattice Boltzmann schemes.
 //
 // Velocities of Section "Examples of Velocity Sets": D1Q3, D2Q5, the 27-velocity 3D family
-// reduced to D3Q7 / D3Q9 / D3Q13 / D3Q19 by its zero weights, and D2Q9 (rest, axes and
-// diagonals; not in the paper).  The diatomic D2Q5/D3Q7 sets use the same velocities as
+// (in full as D3Q27, and reduced to D3Q7 / D3Q9 / D3Q13 / D3Q19 by its zero weights), and D2Q9
+// (rest, axes and diagonals; not in the paper).  The diatomic D2Q5/D3Q7 sets use the same velocities as
 // their monoatomic twins and differ only in the runtime coefficient table.
 //
 // Canonical order: rest, -x, +x, -y, +y, -z, +z, then edges grouped by the plane they lie in
@@ -51,6 +51,14 @@ LBM_VELSET(VS_D3Q19, 3, 19, false, {0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0},
            {-1, -1, 0}, {-1, 1, 0}, {1, -1, 0}, {1, 1, 0},
            {-1, 0, -1}, {-1, 0, 1}, {1, 0, -1}, {1, 0, 1},
            {0, -1, -1}, {0, -1, 1}, {0, 1, -1}, {0, 1, 1})
+
+// The full 27-velocity member of the 3D family (every weight positive for alpha > 0).
+LBM_VELSET(VS_D3Q27, 3, 27, false, {0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1},
+           {-1, -1, 0}, {-1, 1, 0}, {1, -1, 0}, {1, 1, 0},
+           {-1, 0, -1}, {-1, 0, 1}, {1, 0, -1}, {1, 0, 1},
+           {0, -1, -1}, {0, -1, 1}, {0, 1, -1}, {0, 1, 1},
+           {-1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}, {-1, 1, 1},
+           {1, -1, -1}, {1, -1, 1}, {1, 1, -1}, {1, 1, 1})
 
 #undef LBM_VELSET
 

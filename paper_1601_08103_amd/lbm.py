@@ -15,7 +15,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "liblbm_lee.so")
 
 LATTICES = {"D1Q3": 0, "D2Q5": 1, "D2Q9": 2, "D3Q7": 3, "D3Q9": 4, "D3Q13": 5, "D3Q19": 6,
-            "D2Q5_DIA": 7, "D3Q7_DIA": 8}
+            "D2Q5_DIA": 7, "D3Q7_DIA": 8, "D3Q27": 9}
 STORAGES = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "i16": 4, "e3m12": 5}
 ELEM_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "i16": 2, "e3m12": 2}
 TUNE = {"nt_store": 1, "nt_load": 2, "persistent": 4, "full_rest": 8, "closure_stream": 16, "in_place": 32,
@@ -39,6 +39,11 @@ class lbm_lee_desc(ctypes.Structure):
                 ("sponge_sigma", ctypes.c_double)]
 
 
+class lbm_lee_scaling(ctypes.Structure):
+    _fields_ = [("rho_star", ctypes.c_double), ("theta_star", ctypes.c_double), ("u_star", ctypes.c_double),
+                ("x_star", ctypes.c_double), ("t_star", ctypes.c_double)]
+
+
 class lbm_lattice_info(ctypes.Structure):
     _fields_ = [("D", ctypes.c_int32), ("Q", ctypes.c_int32), ("c", (ctypes.c_int32 * 3) * 27),
                 ("fstar", ctypes.c_double * 27), ("beta", ctypes.c_double * 27),
@@ -52,6 +57,11 @@ _VP = ctypes.c_void_p
 _DESC_P = ctypes.POINTER(lbm_lee_desc)
 SIGNATURES = {
     "lbm_lee_lattice_info": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(lbm_lattice_info)]),
+    "lbm_lee_dimensional_scaling": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                                     ctypes.c_double, ctypes.POINTER(lbm_lee_scaling)]),
+    "lbm_lee_dimensional_steps": (ctypes.c_int32, [ctypes.POINTER(lbm_lee_scaling), ctypes.c_double, ctypes.c_double,
+                                                   ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                                   ctypes.POINTER(ctypes.c_double)]),
     "lbm_lee_state_bytes": (ctypes.c_size_t, [_DESC_P]),
     "lbm_lee_scratch_bytes": (ctypes.c_size_t, [_DESC_P]),
     "lbm_lee_bytes_per_update": (ctypes.c_double, [_DESC_P]),
@@ -148,6 +158,25 @@ def lbm_lee_lattice_info(lattice: str) -> dict:
                 fstar=np.array(info.fstar[:Q]), beta=np.array(info.beta[:Q]), rho0=info.rho0,
                 theta0=info.theta0, gamma=info.gamma, a1=info.a1, a2=info.a2, b=info.b, c1=info.c1, c2=info.c2,
                 name=info.name.decode())
+
+
+def lbm_lee_dimensional_scaling(lattice: str, rho0_dim: float, theta0_dim: float, x_star: float = 1.0):
+    s = lbm_lee_scaling()
+    _check("lbm_lee_dimensional_scaling", load().lbm_lee_dimensional_scaling(LATTICES[lattice], float(rho0_dim),
+                                                                             float(theta0_dim), float(x_star),
+                                                                             ctypes.byref(s)))
+    return s
+
+
+def lbm_lee_dimensional_steps(scaling, t_dim: float, dt: float):
+    """(nsteps, t_end, offset) for a dimensional end time with non-dimensional step dt."""
+    n = ctypes.c_int64()
+    te = ctypes.c_double()
+    off = ctypes.c_double()
+    _check("lbm_lee_dimensional_steps", load().lbm_lee_dimensional_steps(ctypes.byref(scaling), float(t_dim), float(dt),
+                                                                         ctypes.byref(n), ctypes.byref(te),
+                                                                         ctypes.byref(off)))
+    return int(n.value), float(te.value), float(off.value)
 
 
 def lbm_lee_state_bytes(desc) -> int:

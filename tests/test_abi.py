@@ -141,8 +141,16 @@ def test_null_handle_calls_fail_cleanly():
 
 @pytest.mark.parametrize("name", list(L.ALL))
 def test_network_dims_match_the_oracle_definition(name):
+    """Network sizes as the oracle defines them; sets whose strips exceed the matrix-core input
+    tile (6 Q > 128: D3Q27) are refused, for the network entry points and for LBM_BC_MLP boxes."""
     from oracle import mlp, open_bc
     lat = L.get(name)
+    if 6 * lat.Q > 128:
+        with pytest.raises(lbm.LbmError):
+            lbm.lbm_nrbc_dims(name)
+        assert lbm.lbm_lee_state_bytes(lbm.make_desc(name, "f32", (4, 4, 4), bc="mlp")) == 0
+        assert lbm.lbm_lee_state_bytes(lbm.make_desc(name, "f32", (4, 4, 4), bc="zero")) > 0
+        return
     d = lbm.lbm_nrbc_dims(name)
     k = len(open_bc.incoming_canonical(lat))
     assert d["n_in"] == 6 * lat.Q and d["n_out"] == k and d["hidden"] == 64  # two time levels of 3Q
@@ -223,7 +231,8 @@ def test_one_launch_open_step_accepted(lattice, bc):
         assert lbm.lbm_lee_state_bytes(d) > 0
 
 
-@pytest.mark.parametrize("lattice", ["D1Q3", "D2Q5", "D2Q9", "D3Q7", "D3Q9", "D3Q13", "D3Q19", "D2Q5_DIA", "D3Q7_DIA"])
+@pytest.mark.parametrize("lattice", ["D1Q3", "D2Q5", "D2Q9", "D3Q7", "D3Q9", "D3Q13", "D3Q19", "D2Q5_DIA", "D3Q7_DIA",
+                                     "D3Q27"])
 @pytest.mark.parametrize("storage,scale", [("f64", 0.0), ("f16", 64.0)])
 @pytest.mark.parametrize("tau", [0.5, 0.8])
 def test_folded_collision_constants_match_the_oracle_update(lattice, storage, scale, tau):
@@ -246,3 +255,32 @@ def test_folded_collision_constants_match_the_oracle_update(lattice, storage, sc
     rebuilt = keep * np.eye(lat.Q) + (H[sh][:, sh] + (c3 @ c3.T) * WB[sh][:, sh]) * ratio
     want = lbe.update_matrix(lat, tau)
     assert np.abs(rebuilt - want).max() <= 1e-14 * max(1.0, np.abs(want).max())
+
+
+def test_dimensional_mapping_reproduces_table1(golden_dir):
+    """The product's dimensional mapping (Section "The Linearized Euler Equations") on the 3D
+    diatomic experiment of Section "Numerical Results": dimensional background rho0 = theta0 = 1,
+    length unit 1, on D3Q7 diatomic (theta0 = 5/21) gives the non-dimensional end time
+    sqrt(21/5) for t_dim = 1, and on [0, 2)^3 with N cells (dt = 2/N) the step counts and end-time
+    offsets of Table 1, to its printed digits."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(golden_dir, "paper_tables.json")))["table1"]
+    s = lbm.lbm_lee_dimensional_scaling("D3Q7_DIA", 1.0, 1.0, 1.0)
+    assert abs(s.theta_star - 21.0 / 5.0) < 1e-15 and abs(s.u_star ** 2 - 21.0 / 5.0) < 1e-14
+    assert s.rho_star == 1.0 and s.x_star == 1.0
+    assert abs(1.0 / s.t_star - np.sqrt(21.0 / 5.0)) < 1e-15
+    for N, want in zip(gold["N"], gold["offset"]):
+        n, t_end, off = lbm.lbm_lee_dimensional_steps(s, 1.0, 2.0 / N)
+        assert n == int(round(np.sqrt(21.0 / 5.0) * N / 2.0)), N
+        assert abs(t_end - n * 2.0 / N) < 1e-15
+        assert float(f"{off:.2e}") == want, (N, off)
+    # a background given in other units maps onto any set: rho_star and theta_star absorb it
+    s2 = lbm.lbm_lee_dimensional_scaling("D2Q5", 1.2, 287.0 * 300.0, 0.5)
+    assert abs(s2.rho_star - 1.2) < 1e-15 and abs(s2.theta_star - 4.0 * 287.0 * 300.0) < 1e-9
+    assert abs(s2.t_star - 0.5 / np.sqrt(4.0 * 287.0 * 300.0)) < 1e-18
+    for bad in ((0.0, 1.0, 1.0), (1.0, -1.0, 1.0), (1.0, 1.0, float("nan"))):
+        with pytest.raises(lbm.LbmError):
+            lbm.lbm_lee_dimensional_scaling("D3Q7_DIA", *bad)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_lee_dimensional_steps(s, 1.0, 0.0)

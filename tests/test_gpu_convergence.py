@@ -40,7 +40,8 @@ def test_plane_wave_second_order_to_1024(name, kdir):
     assert min(slopes) > 1.95 and max(slopes) < 2.05, slopes
 
 
-@pytest.mark.parametrize("name,kdir", [("D3Q7", (1, 1, 0)), ("D3Q19", (1, 1, 1)), ("D3Q13", (1, 0, 0))])
+@pytest.mark.parametrize("name,kdir", [("D3Q7", (1, 1, 0)), ("D3Q19", (1, 1, 1)), ("D3Q13", (1, 0, 0)),
+                                       ("D3Q27", (1, 1, 1))])
 def test_plane_wave_second_order_3d(name, kdir):
     lat = lattice(name)
     errs = []

@@ -52,6 +52,48 @@ def test_open_step_matches_oracle(name, bc, storage):
     sim.close()
 
 
+# storage scale for a random state g = 1e-3 f* N(0, 1): h = S g / f* well inside each format.  A
+# collision can double |h| of such a non-equilibrium state, so E3M12 (saturating at 2) starts
+# below 1/2: with S = 256 the D2Q9 sponge case reaches |h| = 2.05 after one step and saturates.
+_S16 = {"f16": 512.0, "bf16": 512.0, "e3m12": 128.0, "i16": 2.0 ** 21}
+
+
+@pytest.mark.parametrize("name,shape", [("D2Q9", (14, 17)), ("D2Q5", (14, 17)), ("D3Q7", (20, 20, 20)),
+                                        ("D3Q19", (8, 9, 12))])
+@pytest.mark.parametrize("bc", ["zero", "copy", "sponge", "mlp"])
+@pytest.mark.parametrize("storage", ["e3m12", "f16"])
+def test_open_step_16bit_matches_oracle(name, shape, bc, storage):
+    """Open boxes with 16-bit storage in the launch configuration AUTO picks (2D: the one-launch
+    step; 3D with nx % 4 == 0: the DPP bulk kernel, the boundary recompute and the closure-network
+    kernel) against the FP64 oracle from the same (exactly stored) initial state, 4 steps: relative
+    L2 of all populations within 2e-3.  The network closure is compared with the oracle's network
+    with the same bfloat16 rounding points."""
+    lat = L.get(name)
+    kw = dict(sponge_width=3, sponge_sigma=0.4) if bc == "sponge" else {}
+    say("open 16-bit", name, shape, bc, storage)
+    sim = _solver(name, storage, shape, bc, store_scale=_S16[storage], **kw)
+    want_variant = "open2d" if lat.D == 2 else ("dpp" if shape[-1] % 4 == 0 else "dpp2")
+    assert sim.variant == want_variant
+    params = None
+    if bc == "mlp":
+        params = _small_params(lat, 5)
+        sim.set_closure(mlp.flat(params).astype(np.float32))
+    sim.import_f64(_random_state(lat, shape, stable_seed(name, bc, storage, "16")))
+    g = sim.export_f64().cpu().numpy()
+    sim.step(4)
+    got = sim.export_f64().cpu().numpy()
+    if bc == "mlp":
+        k = len(ob.incoming_canonical(lat))
+        p32 = mlp.unflat(mlp.flat(params).astype(np.float32).astype(np.float64), 6 * lat.Q, k)
+        want = ob.run_open(lat, g, 4, "mlp", params=p32, quantize=True)
+    else:
+        want = ob.run_open(lat, g, 4, bc, **kw)
+    err = rel_l2(got, want)
+    say("open 16-bit", name, shape, bc, storage, "rel L2", err)
+    assert err < 2e-3
+    sim.close()
+
+
 def _small_params(lat, seed):
     k = len(ob.incoming_canonical(lat))
     p = mlp.init_params(np.random.default_rng(seed), 6 * lat.Q, k)
@@ -309,7 +351,7 @@ def test_captured_graph_replays_match_eager_steps(case):
 
 @pytest.mark.parametrize("name", ["D2Q9", "D2Q5", "D2Q5_DIA"])
 @pytest.mark.parametrize("bc", ["zero", "copy", "sponge", "mlp"])
-@pytest.mark.parametrize("storage", ["f32", "f16", "f64", "e3m12"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "f64", "e3m12", "bf16", "i16"])
 def test_one_launch_open_step_matches_separate_kernels(name, bc, storage):
     """The one-launch 2D open step (ring, interior and closure network in one kernel) gives the
     same state, bit for bit, as the separate network, bulk and boundary kernels, after each of

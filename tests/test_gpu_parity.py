@@ -19,7 +19,7 @@ pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ok(), reason="needs a 
 BAR = {"f64": 1e-12, "f32": 1e-5}
 UNIT_ROUNDOFF = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "f16": 2.0 ** -11, "bf16": 2.0 ** -8, "e3m12": 2.0 ** -13}
 # I16 rounds h to an integer: absolute error <= 1/2 in h units
-ALL_LATTICES = ["D1Q3", "D2Q5", "D2Q9", "D3Q7", "D3Q9", "D3Q13", "D3Q19", "D2Q5_DIA", "D3Q7_DIA"]
+ALL_LATTICES = ["D1Q3", "D2Q5", "D2Q9", "D3Q7", "D3Q9", "D3Q13", "D3Q19", "D2Q5_DIA", "D3Q7_DIA", "D3Q27"]
 
 SHAPES = {
     # several chunks per row, a partial last chunk, and the one-chunk-per-row (FULLROW) paths
@@ -86,8 +86,9 @@ def test_16bit_storage_single_step_rounding(name, storage):
     say(name, storage, shape)
     rng = np.random.default_rng(5)
     t0 = 1e-3 * lat.fstar.reshape((-1,) + (1,) * lat.D) * rng.standard_normal((lat.Q,) + shape)
-    # h ~ N(0, 1/2) for the floating formats (E3M12 saturates at 2), N(0, 2^11) for fixed point
-    S = {"i16": 2.0 ** 21, "e3m12": 256.0}.get(storage, 512.0)
+    # h ~ N(0, 1/2) for the floating formats, N(0, 2^11) for fixed point; E3M12 saturates at 2
+    # and a collision of a non-equilibrium state can double |h| (D3Q27 reaches 2.2 from N(0, 1/4))
+    S = {"i16": 2.0 ** 21, "e3m12": 128.0}.get(storage, 512.0)
     sim = _solver(name, storage, shape, store_scale=S)
     assert sim.store_scale == S
     sim.import_f64(t0)
@@ -588,7 +589,7 @@ def test_temporal_blocking_16bit_rounds_once_per_launch(name, storage, shape, va
     if lbm.lbm_lee_state_bytes(lbm.make_desc(name, storage, shape, variant=variant)) == 0:
         pytest.skip(f"{variant} does not fit {name}/{storage} (LDS)")
     K = {"tb2": 2, "tb3": 3}[variant]
-    S = {"i16": 2.0 ** 21, "e3m12": 256.0}.get(storage, 512.0)
+    S = {"i16": 2.0 ** 21, "e3m12": 128.0}.get(storage, 512.0)
     rng = np.random.default_rng(stable_seed(name, storage, variant))
     g0 = 1e-3 * lat.fstar.reshape((-1,) + (1,) * lat.D) * rng.standard_normal((lat.Q,) + tuple(shape))
     sims = [_solver(name, storage, shape, variant=variant, store_scale=S, tune=tune)

@@ -444,3 +444,51 @@ def test_planted_mistakes_are_caught(mistake):
         co["fstar"] = f
     assert _pins_detect(lat, co)
     assert not _pins_detect(lat, {})
+
+
+# --------------------------------------------------------------------------- 2D radial closed form
+def test_radial_2d_closed_form_starts_from_the_gaussian():
+    """At t = 0 the Hankel representation is the Gaussian's own Hankel pair: p' equals the
+    periodic image sum of A exp(-r^2 / (2 sigma^2)) and u' vanishes."""
+    lat = L.get("D2Q5")
+    N = 48
+    sig = N / (2.0 * np.sqrt(14.0))
+    f = cf.radial_2d_gaussian(lat, 0.25, sig, (N / 2, N / 2), (N, N), 0.0)
+    g = cf.gaussian_periodic((N, N), 0.25, sig, (N / 2, N / 2))
+    assert np.abs(f["p"] - g).max() < 1e-13 * 0.25
+    assert np.abs(f["u"]).max() == 0.0
+
+
+@pytest.mark.parametrize("name", ["D2Q5", "D2Q5_DIA"])
+def test_radial_2d_closed_form_conserves_acoustic_energy(name):
+    """The acoustic energy sum(p'^2 / (rho0 c^2) + rho0 |u'|^2) of the periodic solution stays
+    constant in time (the LEE's energy identity); the grid sum of a smooth periodic field is
+    exact to rounding.  A J1/J0 mix-up, a wrong sound speed or a missing 1/(rho0 c) in u' breaks
+    it (the sign of u' is pinned by the stepper test below)."""
+    lat = L.get(name)
+    N = 40
+    sig = N / (2.0 * np.sqrt(14.0))
+    E = []
+    for t in (0.0, 7.0, 19.0, 33.0):
+        f = cf.radial_2d_gaussian(lat, 1.0, sig, (N / 2 + 0.3, N / 2 - 1.1), (N, N), t)
+        E.append(float(np.sum(f["p"] ** 2) / (lat.rho0 * lat.cs2) + lat.rho0 * np.sum(f["u"] ** 2)))
+    assert max(abs(e - E[0]) for e in E) < 1e-9 * E[0], E
+
+
+def test_radial_2d_closed_form_is_the_limit_of_the_stepper():
+    """The oracle's LBE stepper converges to the closed form at second order (D2Q5, the paper's
+    2D Gauss pulse exp(-7 |x - (1,1)|^2) on [0,2)^2 in the isentropic form, t = 1), in p' and in
+    u'."""
+    lat = L.get("D2Q5")
+    errs = {"p": [], "u": []}
+    for N in (32, 64, 128):
+        sig = N / (2.0 * np.sqrt(14.0))
+        p0 = cf.gaussian_periodic((N, N), 1.0, sig, (N / 2, N / 2))
+        rho, u, theta = inputs.fields_from_pressure(p0, lat.rho0, lat.theta0, lat.gamma)
+        m = lbe.moments(lat, lbe.run(lat, rho, u, theta, N // 2))
+        ex = cf.radial_2d_gaussian(lat, 1.0, sig, (N / 2, N / 2), (N, N), N / 2)
+        for key in errs:
+            errs[key].append(lbe.l2_space(m[key] - ex[key], 2.0 / N, 2))
+    for key, e in errs.items():
+        slopes = [np.log2(e[i] / e[i + 1]) for i in range(2)]
+        assert 1.9 < min(slopes) and max(slopes) < 2.1, (key, e, slopes)
