@@ -44,7 +44,9 @@ def parse():
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--variant", default="auto")
     ap.add_argument("--modes", default="f32,f16,bf16,i16,e3m12,f64", help="storage modes to time and compare")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline")
+    ap.add_argument("--reps", type=int, default=5, help="timed repetitions of the K steps (median reported)")
+    ap.add_argument("--cpu-seconds", type=float, default=24.0,
+                    help="budget of the oracle CPU baseline (half on one thread, half on all cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-nrbc", action="store_true", help="skip the learned-closure leg")
     ap.add_argument("--closure-only", action="store_true",
@@ -94,23 +96,30 @@ def nrbc_leg():
     if not os.path.exists(path):
         return None
     P = np.load(path, allow_pickle=False)
-    L, E, steps, seeds = 512, 1536, 1024, 2
+    L, E, steps, seeds = 512, 1536, 1024, 8
     sponge = dict(sponge_width=96, sponge_sigma=0.03)
     info = lbm.lbm_lee_lattice_info("D2Q9")
     rng = np.random.default_rng(10_000)  # held-out states: training draws seeds below 10000
     ext = nrbc.judge_solver("D2Q9", "f32", E, 2)
     closures = ("zero", "sponge", "mlp")
     R = {c: [] for c in closures}
+    first = None
     for _ in range(seeds):
         fields = nrbc.initial_fields("pulses", rng, info, L, 2)
+        first = fields if first is None else first
+        ref = nrbc.judge_reference("D2Q9", fields, L, E, steps, 8, ext=ext)  # one judge run per state
         for c in closures:
-            R[c].append(nrbc.reflection("D2Q9", c, fields, L, E, steps, 8, params=P, ext=ext, **sponge))
+            R[c].append(nrbc.reflection_vs("D2Q9", c, fields, ref, L, steps, 8, params=P, **sponge))
+        del ref
+    # step times on live states: the judge holds the last run's state; each box starts from the
+    # first held-out state (the sponge box from it on its inner box)
     times = {"extended_periodic": round(nrbc.time_solver(ext, 200), 5)}
     ext.close()
     for c in closures:
-        nb = L + 2 * sponge["sponge_width"] if c == "sponge" else L
+        W = sponge["sponge_width"] if c == "sponge" else 0
         kw = sponge if c == "sponge" else {}
-        times[c] = round(nrbc.time_per_step("D2Q9", (nb, nb), bc=c, params=P, **kw), 5)
+        times[c] = round(nrbc.time_per_step("D2Q9", (L + 2 * W,) * 2, bc=c, params=P, fields=first,
+                                            origin=(W, W) if W else None, **kw), 5)
     out = dict(workload=f"2D open box D2Q9 {L}^2 FP32, judge {E}^2 periodic, {steps} steps, {seeds} held-out "
                         "pulse states", weights="paper_1601_08103_amd/weights/nrbc_D2Q9.npy",
                sponge=dict(width=sponge["sponge_width"], sigma=sponge["sponge_sigma"]),
@@ -120,31 +129,70 @@ def nrbc_leg():
     return out
 
 
+def host_cpu():
+    """(nproc, CPUs this process may run on, CPU model name) of the host."""
+    import platform
+    import subprocess
+    nproc = os.cpu_count() or 1
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = nproc
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.strip().startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if not model:
+        try:
+            with open("/proc/cpuinfo") as fh:
+                for line in fh:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            model = platform.processor()
+    return nproc, avail, model
+
+
 def cpu_baseline(shape, rho, u, theta, budget_s):
     """The FP64 oracle (C stepper, OpenMP over rows) on the same workload, for a bounded number
-    of steps, on this host's cores."""
+    of steps: once on one thread and once on every CPU this process may use (capped at the 16 a
+    one-GPU share of the host provides), each for about budget_s / 2 seconds."""
     from oracle import lattices as L
     from oracle import lbe
 
     lat = L.get("D3Q7")
-    try:
-        threads = len(os.sched_getaffinity(0))
-    except AttributeError:
-        threads = os.cpu_count() or 1
-    threads = int(os.environ.get("LBM_ORACLE_THREADS", min(threads, 16)))
-    g = lbe.equilibrium(lat, rho, u, theta)
+    nproc, avail, model = host_cpu()
+    all_threads = int(os.environ.get("LBM_ORACLE_THREADS", min(avail, 16)))
+    g0 = lbe.equilibrium(lat, rho, u, theta)
     N = int(np.prod(shape))
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        g = lbe.steps(lat, g, 1, nthreads=threads)
-        steps += 1
-        el = time.perf_counter() - t0
-        log(f"cpu baseline: {steps} oracle steps, {el:.1f} s")
-        if el >= budget_s:
-            break
-    return dict(value=round(N * steps / el / 1e6, 3), unit="MLUPS", cores=threads, kind="oracle",
-                sample=f"first {steps} steps of the same {shape[0]}^3 D3Q7 workload, FP64, push-form C stepper")
+
+    def leg(threads):
+        g = g0
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            g = lbe.steps(lat, g, 1, nthreads=threads)
+            steps += 1
+            el = time.perf_counter() - t0
+            log(f"cpu baseline, {threads} thread(s): {steps} oracle steps, {el:.1f} s")
+            if el >= budget_s / 2:
+                break
+        return steps, el
+
+    s1, t1 = leg(1)
+    sa, ta = leg(all_threads)
+    return dict(value=round(N * sa / ta / 1e6, 3), unit="MLUPS", cores=all_threads, kind="oracle",
+                sample=f"first {sa} steps of the same {shape[0]}^3 D3Q7 workload, FP64, push-form C stepper, "
+                       f"{all_threads} OpenMP threads",
+                single_thread=dict(value=round(N * s1 / t1 / 1e6, 3), unit="MLUPS", cores=1,
+                                   sample=f"first {s1} steps, 1 thread"),
+                nproc=nproc, cpus_available=avail, cpu_model=model)
 
 
 def main():
@@ -186,37 +234,56 @@ def main():
         # the temporal-blocking variants read and write the state once per launch of 2 or 3 steps
         return {"tb2": 2, "tb3": 3}.get(variant, 1)
 
+    reps = args.reps
+
     def timed_run(storage):
+        """The workload's K steps, `reps` times from the initial state (HIP events on the library's
+        stream around each K-step region): median time and median time per multi-step launch."""
         sim = lbm.Solver("D3Q7", storage, shape, rho_d, u_d, th_d, variant=args.variant)
         sim.step(W)
-        sim.reinit(rho_d, u_d, th_d)
-        torch.cuda.synchronize()
         # the multi-step variants run K // spl launches of spl steps and K % spl one-step
         # launches; the first part alone gives the time per launch of the dominant kernel
         spl = steps_per_launch(sim.variant)
         main = K - K % spl
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev2 = torch.cuda.Event(enable_timing=True)
-        t_host = time.perf_counter()
-        ev0.record(stream)
-        sim.step(main)
-        ev1.record(stream)
-        sim.step(K - main)
-        ev2.record(stream)
-        torch.cuda.synchronize()
-        t_host = time.perf_counter() - t_host
-        ms = ev0.elapsed_time(ev2)
-        if main:
-            launch_ms = ev0.elapsed_time(ev1) / (main // spl)
-        else:  # fewer steps than one multi-step launch: only one-step launches ran
-            spl, launch_ms = 1, ms / K
-        log(f"{storage}: {K} steps in {ms:.3f} ms (host {t_host * 1e3:.3f} ms); {max(main // spl, K - main)} "
-            f"launches of {spl} steps, {launch_ms * 1e3:.1f} us each")
-        return sim, ms, launch_ms, spl
+        rep_ms, rep_launch = [], []
+        for _ in range(reps):
+            sim.reinit(rho_d, u_d, th_d)
+            torch.cuda.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev2 = torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            sim.step(main)
+            ev1.record(stream)
+            sim.step(K - main)
+            ev2.record(stream)
+            torch.cuda.synchronize()
+            rep_ms.append(ev0.elapsed_time(ev2))
+            rep_launch.append(ev0.elapsed_time(ev1) / (main // spl) if main else ev0.elapsed_time(ev2) / K)
+        if not main:  # fewer steps than one multi-step launch: only one-step launches ran
+            spl = 1
+        ms, launch_ms = float(np.median(rep_ms)), float(np.median(rep_launch))
+        log(f"{storage}: {K} steps, median of {reps}: {ms:.3f} ms ({', '.join('%.3f' % v for v in rep_ms)}); "
+            f"{max(main // spl, K - main)} launches of {spl} steps, {launch_ms * 1e3:.1f} us each")
+        return sim, ms, launch_ms, spl, rep_ms
+
+    def sustained(sim, spl, launch_ms):
+        """reps timed regions of at least 100 ms of whole multi-step launches each, continuing from
+        the current state: median ms per step."""
+        n = max(1, int(np.ceil(100.0 / launch_ms))) * spl
+        out = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            sim.step(n)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return n, out
 
     if args.profile_only:
-        sim, ms, _, _ = timed_run(args.storage)
+        sim, ms, _, _, _ = timed_run(args.storage)
         log(f"profile-only: {N * K / (ms / 1e3) / 1e6:.1f} MLUPS, {sim.bytes_per_update} B/LU")
         if args.with_copy:
             nbytes = N * 7 * 4
@@ -236,11 +303,14 @@ def main():
     results = {}
     moments = {}
     for mode in modes:
-        sim, ms, launch_ms, spl = timed_run(mode)
+        sim, ms, launch_ms, spl, rep_ms = timed_run(mode)
         m = sim.moments()
         moments[mode] = (m["p"].clone(), m["u"].clone())
+        n_s, s_ms = sustained(sim, spl, launch_ms)
+        log(f"{mode}: sustained, {reps} regions of {n_s} steps: {', '.join('%.2f' % v for v in s_ms)} ms")
         results[mode] = dict(ms=ms, launch_ms=launch_ms, spl=spl, bpu=sim.bytes_per_update, scale=sim.store_scale,
-                             variant=sim.variant if spl > 1 or sim.variant not in ("tb2", "tb3") else "generic")
+                             variant=sim.variant if spl > 1 or sim.variant not in ("tb2", "tb3") else "generic",
+                             rep_ms=rep_ms, sustained_steps=n_s, sustained_ms=s_ms)
         sim.close()
         del sim
     p_ref, u_ref = moments["f64"]
@@ -258,11 +328,15 @@ def main():
         # over the time per launch
         gbs = N * r["bpu"] / (r["launch_ms"] / 1e3) / 1e9
         ep, eu = rel(mode)
+        s_med = float(np.median(r["sustained_ms"]))
         storage_modes[mode] = dict(MLUPS=round(mlups, 1), ms_per_step=round(r["ms"] / K, 5),
                                    bytes_per_update=r["bpu"], steps_per_launch=spl, GBs=round(gbs, 1),
                                    frac_peak_hbm=round(gbs / PEAK_HBM_GBS, 4),
                                    rel_l2_p_vs_f64=ep, rel_l2_u_vs_f64=eu, store_scale=r["scale"],
-                                   variant=r["variant"])
+                                   variant=r["variant"], rep_ms=[round(v, 4) for v in r["rep_ms"]],
+                                   sustained=dict(steps_per_region=r["sustained_steps"],
+                                                  region_ms=[round(v, 3) for v in r["sustained_ms"]],
+                                                  MLUPS_median=round(N * r["sustained_steps"] / (s_med / 1e3) / 1e6, 1)))
         log(mode, storage_modes[mode])
 
     # plain copy kernel of the same size as one population buffer pair (read + write)
@@ -273,13 +347,13 @@ def main():
         lbm.lbm_lee_device_copy(b.data_ptr(), a.data_ptr(), nbytes, stream.cuda_stream)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 20
+    copy_reps = 20
     ev0.record(stream)
-    for _ in range(reps):
+    for _ in range(copy_reps):
         lbm.lbm_lee_device_copy(b.data_ptr(), a.data_ptr(), nbytes, stream.cuda_stream)
     ev1.record(stream)
     torch.cuda.synchronize()
-    copy_gbs = 2 * nbytes * reps / (ev0.elapsed_time(ev1) / 1e3) / 1e9
+    copy_gbs = 2 * nbytes * copy_reps / (ev0.elapsed_time(ev1) / 1e3) / 1e9
     del a, b
     log(f"copy kernel: {copy_gbs:.1f} GB/s")
 
@@ -326,6 +400,9 @@ def main():
                                f"(amplitude 1e-3, sigma 12 cells), tau=1/2, {K} steps",
                    "lattice": "D3Q7", "cells": N, "storage": args.storage, "variant": args.variant,
                    "global_batch": 1, "parallelism": "none (1 GPU)"},
+        "timing": {"protocol": f"HIP events on the library's stream; value = median of {reps} timed regions of "
+                               f"exactly {K} steps from the initial state; each storage mode also reports {reps} "
+                               "sustained regions of >= 100 ms of whole launches (median MLUPS)"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "storage_modes": storage_modes,

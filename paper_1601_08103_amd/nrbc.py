@@ -200,7 +200,8 @@ def train(lattice, S, T, epochs=4, batch=4096, lr=1e-3, lr_end=1e-5, seed=0, par
     nb = (n - nval) // batch
     total = epochs * nb
     it = 0
-    hist = []
+    # epoch 0: the validation loss of the starting parameters
+    hist = [dict(epoch=0, train_loss=float("nan"), val_loss=evaluate_loss(lattice, P, Sv, Tv, ws, wsb))]
     t0 = time.time()
     for ep in range(epochs):
         order = tr[torch.randperm(tr.numel(), generator=torch.Generator().manual_seed(seed + 1 + ep)).cuda()]
@@ -239,10 +240,44 @@ def _compare(a, b, n3, scratch, scratch_bytes, st):
     return lbm.lbm_lee_compare_fields(a.data_ptr(), n3, b.data_ptr(), n3, [0, 0, 0], scratch, scratch_bytes, st)
 
 
-def reflection(lattice, closure, fields, L=512, E=1536, steps=1024, every=8, params=None, storage="f32",
-               ext_storage="f32", sponge_width=32, sponge_sigma=0.2, ext=None, slices=False):
-    """R of one closure on one initial state (see the module docstring).  slices: compare on the
-    box's mid-planes (one per axis) instead of the whole box."""
+def _regions(L, D, slices):
+    """Regions compared, (origin in box coordinates, extent), x first: the whole box, or its
+    mid-planes (one per axis)."""
+    if slices and D > 1:
+        out = []
+        for a in range(D):
+            o = [0] * D
+            n = [L] * D
+            o[a], n[a] = L // 2, 1
+            out.append((o, n))
+        return out
+    return [([0] * D, [L] * D)]
+
+
+def judge_reference(lattice, fields, L=512, E=1536, steps=1024, every=8, ext_storage="f32", ext=None, slices=False):
+    """The judge's p' on the compared regions of the inner box every `every` steps (device FP64
+    tensors, [sample][region]): run once per initial state and shared by every closure."""
+    info = lbm.lbm_lee_lattice_info(lattice)
+    D = info["D"]
+    own_ext = ext is None
+    if own_ext:
+        ext = judge_solver(lattice, ext_storage, E, D)
+    oe = (E - L) // 2
+    ext.reinit_region([oe] * D, (L,) * D, *fields)
+    ref = []
+    for t in range(0, steps + 1, every):
+        if t:
+            ext.step(every)
+        ref.append([ext.moments_region([v + oe for v in o], tuple(reversed(n)))["p"].clone()
+                    for o, n in _regions(L, D, slices)])
+    if own_ext:
+        ext.close()
+    return ref
+
+
+def reflection_vs(lattice, closure, fields, ref, L=512, steps=1024, every=8, params=None, storage="f32",
+                  sponge_width=32, sponge_sigma=0.2, slices=False):
+    """R of one closure on one initial state against a judge reference from judge_reference."""
     import torch
     info = lbm.lbm_lee_lattice_info(lattice)
     D = info["D"]
@@ -259,32 +294,15 @@ def reflection(lattice, closure, fields, L=512, E=1536, steps=1024, every=8, par
         box.reinit_region([W] * D, (L,) * D, *fields)
     if closure == "mlp":
         box.set_closure(params)
-    own_ext = ext is None
-    if own_ext:
-        ext = judge_solver(lattice, ext_storage, E, D)
-    oe = (E - L) // 2
-    ext.reinit_region([oe] * D, (L,) * D, *fields)
     st = torch.cuda.current_stream().cuda_stream
-    # regions compared: (origin in box coordinates, extent), x-first
-    if slices and D > 1:
-        regions = []
-        for a in range(D):
-            o = [0] * D
-            n = [L] * D
-            o[a], n[a] = L // 2, 1
-            regions.append((o, n))
-    else:
-        regions = [([0] * D, [L] * D)]
+    regions = _regions(L, D, slices)
     err_max = ref_max = 0.0
-    for t in range(0, steps + 1, every):
+    for k, t in enumerate(range(0, steps + 1, every)):
         if t:
             box.step(every)
-            ext.step(every)
         e2 = r2 = 0.0
-        for o, n in regions:
-            shape = tuple(reversed(n))
-            pb = box.moments_region([v + W for v in o], shape)["p"]
-            pe = ext.moments_region([v + oe for v in o], shape)["p"]
+        for (o, n), pe in zip(regions, ref[k]):
+            pb = box.moments_region([v + W for v in o], tuple(reversed(n)))["p"]
             out = _compare(pb, pe, list(n) + [1] * (3 - D), box.scratch.data_ptr(), box.scratch_bytes, st)
             e2 += out[0]
             r2 += out[1]
@@ -294,9 +312,16 @@ def reflection(lattice, closure, fields, L=512, E=1536, steps=1024, every=8, par
         err_max = max(err_max, math.sqrt(e2))
         ref_max = max(ref_max, math.sqrt(r2))
     box.close()
-    if own_ext:
-        ext.close()
     return err_max / ref_max if ref_max > 0 else float("nan")
+
+
+def reflection(lattice, closure, fields, L=512, E=1536, steps=1024, every=8, params=None, storage="f32",
+               ext_storage="f32", sponge_width=32, sponge_sigma=0.2, ext=None, slices=False):
+    """R of one closure on one initial state (see the module docstring).  slices: compare on the
+    box's mid-planes (one per axis) instead of the whole box."""
+    ref = judge_reference(lattice, fields, L, E, steps, every, ext_storage, ext, slices)
+    return reflection_vs(lattice, closure, fields, ref, L, steps, every, params, storage, sponge_width, sponge_sigma,
+                         slices)
 
 
 def time_solver(sim, steps=200, graph=False):
@@ -328,8 +353,17 @@ def time_solver(sim, steps=200, graph=False):
     return e0.elapsed_time(e1) / (6 * reps)
 
 
-def time_per_step(lattice, shape, bc="periodic", params=None, storage="f32", steps=200, graph=False, tune=0, **kw):
-    sim = lbm.Solver(lattice, storage, shape, None, None, None, bc=bc, tune=tune, **kw)
+def time_per_step(lattice, shape, bc="periodic", params=None, storage="f32", steps=200, graph=False, tune=0,
+                  fields=None, origin=None, **kw):
+    """ms per step of a box of `shape`, started from `fields` (a seeded state, so the timed steps
+    work on live data) on the whole box, or on a sub-box at cell offset `origin` (x, y, z) with the
+    rest at rest; None: the state at rest."""
+    if fields is not None and origin is None:
+        sim = lbm.Solver(lattice, storage, shape, *fields, bc=bc, tune=tune, **kw)
+    else:
+        sim = lbm.Solver(lattice, storage, shape, None, None, None, bc=bc, tune=tune, **kw)
+        if fields is not None:
+            sim.reinit_region(origin, fields[0].shape, *fields)
     if bc == "mlp":
         sim.set_closure(params)
     ms = time_solver(sim, steps, graph)
@@ -395,29 +429,36 @@ def main(argv=None):
     closures = [c for c in args.closures.split(",") if c and (c != "mlp" or P is not None)]
     Rs = {c: [] for c in closures}
     ext = judge_solver(args.lattice, args.ext_storage, args.E, D)
+    first = None
     for k in range(args.seeds):
         fields = initial_fields(args.init, rng, info, args.L, D)
+        first = fields if first is None else first
+        ref = judge_reference(args.lattice, fields, args.L, args.E, args.steps, args.every, args.ext_storage, ext,
+                              args.slices)
         for c in closures:
-            Rs[c].append(reflection(args.lattice, c, fields, args.L, args.E, args.steps, args.every, params=P,
-                                    storage=args.storage, ext_storage=args.ext_storage,
-                                    sponge_width=args.sponge_width, sponge_sigma=args.sponge_sigma, ext=ext,
-                                    slices=args.slices))
+            Rs[c].append(reflection_vs(args.lattice, c, fields, ref, args.L, args.steps, args.every, params=P,
+                                       storage=args.storage, sponge_width=args.sponge_width,
+                                       sponge_sigma=args.sponge_sigma, slices=args.slices))
+        del ref
         log(f"evaluate: seed {k + 1}/{args.seeds}: " + ", ".join(f"{c} {Rs[c][-1]:.4f}" for c in closures))
     nrep = 50 if D == 3 else 200
     times = {"extended_periodic": time_solver(ext, nrep)}
     times_graph = {"extended_periodic": time_solver(ext, nrep, graph=True)}
     ext.close()
     del ext
+    # step times on live data: every box starts from the first held-out state
     for c in closures:
+        W = args.sponge_width if c == "sponge" else 0
         kw = dict(sponge_width=args.sponge_width, sponge_sigma=args.sponge_sigma) if c == "sponge" else {}
-        nb = args.L + (2 * args.sponge_width if c == "sponge" else 0)
-        times[c] = time_per_step(args.lattice, (nb,) * D, bc=c, params=P, storage=args.storage, **kw)
+        live = dict(fields=first, origin=[W] * D if W else None)
+        nb = args.L + 2 * W
+        times[c] = time_per_step(args.lattice, (nb,) * D, bc=c, params=P, storage=args.storage, **live, **kw)
         times_graph[c] = time_per_step(args.lattice, (nb,) * D, bc=c, params=P, storage=args.storage, graph=True,
-                                       **kw)
+                                       **live, **kw)
         if c == "mlp":
             times_graph["mlp_closure_stream"] = time_per_step(args.lattice, (nb,) * D, bc=c, params=P,
                                                               storage=args.storage, graph=True,
-                                                              tune=lbm.TUNE["closure_stream"])
+                                                              tune=lbm.TUNE["closure_stream"], **live)
     print(json.dumps(dict(mode="evaluate", lattice=args.lattice, init=args.init, L=args.L, E=args.E,
                           steps=args.steps, storage=args.storage, ext_storage=args.ext_storage, seeds=args.seeds,
                           slices=args.slices, R_mean={c: float(np.mean(v)) for c, v in Rs.items()},
