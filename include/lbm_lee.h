@@ -128,16 +128,17 @@ typedef int32_t lbm_status;
                               /* needs nx % 4 == 0                                          */
 #define LBM_VARIANT_LDS 3     /* one thread per cell, x-shifted rows staged in LDS + halo   */
 #define LBM_VARIANT_DPP2 4    /* 2 cells per lane, as DPP; needs nx % 2 == 0                 */
-/* Two steps per launch (temporal blocking), periodic 2D and 3D boxes of any extents: a block
- * owns a tile of 64 cells along x (and TY along y in 3D) and marches along the last axis, doing
- * step t+1 on the tile and a one-cell ring around it (state t read from HBM) and then step t+2
- * on the tile (state t+1 from LDS and registers), so the state crosses HBM once per two steps.
+/* Two steps per launch (temporal blocking), periodic 2D boxes of any extents and 3D boxes with
+ * even nx: a block owns a tile of 64 cells along x (and TY along y in 3D) and marches along the
+ * last axis, doing step t+1 on the tile and a one-cell ring around it (state t read from HBM) and
+ * then step t+2 on the tile (state t+1 from LDS and registers), so the state crosses HBM once per
+ * two steps.  In 3D each thread reads and writes two x-adjacent cells per access (hence even nx).
  * The intermediate state is never stored: with F64/F32 storage the result equals two one-step
  * launches bit for bit; with the 16-bit formats it stays in FP32 and a launch rounds to the
  * format once instead of twice (half the rounding error of the one-step kernels, whose error at
- * tau = 1/2 accumulates undamped).  An odd step count ends with one one-step launch.  LBM_E_UNSUPPORTED for open boxes, 1D sets
- * and sets whose in-plane LDS rings do not fit 64 KB at TY = 4 (D3Q19 with FP32, and D3Q9,
- * D3Q13 and D3Q19 with FP64). */
+ * tau = 1/2 accumulates undamped).  An odd step count ends with one one-step launch.
+ * LBM_E_UNSUPPORTED for open boxes, 1D sets, 3D boxes with odd nx, and sets whose in-plane LDS
+ * rings do not fit 64 KB at TY = 4 (D3Q19 and D3Q27, and D3Q9 and D3Q13 with FP64). */
 #define LBM_VARIANT_TB2 5
 /* Three steps per launch, the same scheme one stage deeper (the tile dilated by two cells for
  * step t+1, by one for t+2); LDS rings of two intermediate steps (up to 160 KB per block).  As

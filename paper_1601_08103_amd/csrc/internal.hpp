@@ -144,6 +144,8 @@ inline lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
         if (tb_tile_y(d->lattice, d->storage, K) == 0)
             return fail(LBM_E_UNSUPPORTED, "the %d-step variant's LDS rings for lattice %d do not fit with this storage",
                         K, d->lattice);
+        if (tab->D == 3 && d->n[0] % 2 != 0)
+            return fail(LBM_E_UNSUPPORTED, "the %d-step variant reads and writes x-pairs in 3D: nx must be even", K);
         if (!tb_plane_fits(d, tab->D))
             return fail(LBM_E_UNSUPPORTED, "the %d-step variant addresses a plane with 31-bit byte offsets (<= 2 GiB)", K);
     }
@@ -397,7 +399,8 @@ inline int resolve_variant(const lbm_lee *h) {
     // periodic boxes of a million cells and more: three steps per launch for the sets of up to 9
     // velocities, two for the larger ones (their two collisions per column already fill the
     // registers), for every storage mode
-    if (h->desc.bc == LBM_BC_PERIODIC && h->tab.D >= 2 && h->N >= ((size_t)1 << 20) && tb_plane_fits(&h->desc, h->tab.D)) {
+    if (h->desc.bc == LBM_BC_PERIODIC && h->tab.D >= 2 && h->N >= ((size_t)1 << 20) && tb_plane_fits(&h->desc, h->tab.D) &&
+        (h->tab.D == 2 || h->nx % 2 == 0)) {
         if (h->tab.Q <= 9 && tb_tile_y(h->desc.lattice, h->desc.storage, 3) > 0) return LBM_VARIANT_TB3;
         if (tb_tile_y(h->desc.lattice, h->desc.storage, 2) > 0) return LBM_VARIANT_TB2;
     }

@@ -17,6 +17,9 @@
 // populations with c_x = c_y = 0 stay in the registers of the thread that owns the column in
 // every stage.  The loads of the next two planes (one for the sets with 13 and more velocities)
 // are in flight while a plane is computed, and K-1 barriers per iteration order the LDS traffic.
+// In 3D each thread's interior cells are an x-adjacent pair read and written with one access of
+// two elements per population (so nx must be even); the x-neighbour beyond the pair comes from
+// the neighbouring lane by DPP.
 // Every cell goes through the same collision as the one-step kernels.  The intermediate steps
 // t+1 .. t+K-1 are never stored, so they stay in the compute type: for FP64 and FP32 storage
 // that is the stored value itself and K steps here give the same bits as K one-step launches;
@@ -163,33 +166,77 @@ __device__ __forceinline__ void buf_store(E v, __amdgpu_buffer_rsrc_t r, unsigne
     }
 }
 
+// Two consecutive elements at a 2-element-aligned byte offset: one access of 4, 8 or 16 bytes.
+template <typename E>
+using Vec2 = E __attribute__((ext_vector_type(2)));
+
+template <typename E>
+__device__ __forceinline__ Vec2<E> buf_load2(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    if constexpr (sizeof(E) == 2) {
+        return __builtin_bit_cast(Vec2<E>, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+    } else if constexpr (sizeof(E) == 4) {
+        return __builtin_bit_cast(Vec2<E>, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+    } else {
+        return __builtin_bit_cast(Vec2<E>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+    }
+}
+
+template <typename E>
+__device__ __forceinline__ void buf_store2(Vec2<E> v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    if constexpr (sizeof(E) == 2) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+    } else if constexpr (sizeof(E) == 4) {
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)off, 0, 0);
+    } else {
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, (int)off, 0, 0);
+    }
+}
+
 // Column bookkeeping (frame: the tile dilated by K-1 cells, origin at its corner; the tile's
-// own cells start at (K-1, HY (K-1))).  A thread owns NJ interior columns (the same in every
-// stage) and, for each ring b = 1..K-1 around the tile (b cells out), NH(b) ring columns;
-// stage s works on the interior and the rings b <= K - s.
-template <int K, int TY, int NT, int HY>
+// own cells start at (K-1, HY (K-1))).  In 3D a thread owns two interior cells: for 2- and 8-byte
+// elements two x-adjacent ones (a "pair": 32 pairs per 64-cell row, a wave holds two rows), read
+// and written with one access of two elements per population; for FP32, two cells TY/2 rows
+// apart, each with its own accesses (measured faster there: the pair's extra registers push the
+// FP32 kernel, whose constants are split in two, past 128 VGPRs); in 2D one interior cell.  The rings b = 1..K-1 around the tile
+// (b cells out) are spread over NR ring slots per thread, one column each (threads past the
+// last ring column have none); stage s works on the interior and the rings b <= K - s.
+template <int K, int TY, int NT, int HY, bool PAIR_>
 struct TbCols {
     static constexpr int TX = kTbTx;
-    static constexpr int NJ = TX * TY / NT;
+    static constexpr bool PAIR = PAIR_;
+    static constexpr int NJ = TX * TY / NT;  // interior cells per thread: 2 in 3D (a pair or two rows), 1 in 2D
     static constexpr int ring_cols(int b) { return HY ? 2 * (TX + 2 * b) + 2 * (TY + 2 * b - 2) : 2; }
-    static constexpr int NH(int b) { return (ring_cols(b) + NT - 1) / NT; }
-    static constexpr int NC() {
-        int n = NJ;
-        for (int b = 1; b < K; ++b) n += NH(b);
+    static constexpr int ring_total() {
+        int n = 0;
+        for (int b = 1; b < K; ++b) n += ring_cols(b);
         return n;
     }
-    static constexpr int ring_of(int c) {  // 0 = interior
-        if (c < NJ) return 0;
-        int o = NJ;
+    // Ring slots: with pairs every ring column of every ring shares one pool (ring 1 first), so a
+    // thread holds at most ceil(total / NT) of them and a slot's ring is known at run time; else
+    // each ring has its own slots (odd rings from the last thread down, even ones from the first
+    // up), so a slot's ring is a compile-time constant and the stages it works in cost nothing
+    // (the FP32 kernel needs that to stay within 128 registers).
+    static constexpr int NH(int b) { return (ring_cols(b) + NT - 1) / NT; }
+    static constexpr int NR = [] {
+        if (PAIR) return (ring_total() + NT - 1) / NT;
+        int n = 0;
+        for (int b = 1; b < K; ++b) n += NH(b);
+        return n;
+    }();
+    static constexpr int NC = NJ + NR;
+    static constexpr int ring_of(int r) {  // !PAIR: ring of slot r
+        int o = 0;
         for (int b = 1; b < K; ++b) {
-            if (c < o + NH(b)) return b;
+            if (r < o + NH(b)) return b;
             o += NH(b);
         }
         return K;
     }
     static constexpr int first_of_ring(int b) {
-        int o = NJ;
-        for (int r = 1; r < b; ++r) o += NH(r);
+        int o = 0;
+        for (int q = 1; q < b; ++q) o += NH(q);
         return o;
     }
 };
@@ -201,16 +248,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     using F = TbFrame<VS>;
     using E = typename ST::elem;
     using CT = typename ST::comp;
+    using E2 = Vec2<E>;
     constexpr bool RAW = ST::has_raw;
     constexpr int Q = VS::Q;
     constexpr int i0 = SKIP0 ? 1 : 0;
     constexpr int TX = kTbTx;
     constexpr int HY = F::y_halo() ? 1 : 0;
-    using C = TbCols<K, TY, NT, HY>;
+    using C = TbCols<K, TY, NT, HY, HY == 1 && sizeof(E) != 4>;
+    constexpr bool PAIR = C::PAIR;
     constexpr int NJ = C::NJ;
-    static_assert(NJ * NT == TX * TY && NJ >= 1, "tile and block size");
+    constexpr int NR = C::NR;
+    constexpr int NC = C::NC;
+    static_assert(NJ * NT == TX * TY && NJ == (HY ? 2 : 1), "tile and block size");
     static_assert(K >= 2 && K <= 4, "two to four steps per launch");
-    constexpr int NC = C::NC();
     constexpr int IU = F::local(1);               // c = (0, 0, +1): read two iterations later
     constexpr int ID = F::local(-1);              // c = (0, 0, -1): read in the same iteration
     constexpr int IR = SKIP0 ? -1 : F::local(0);  // the rest population, when it is updated
@@ -226,6 +276,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         return o;
     };
     constexpr int RING_ELEMS = set_off(K);
+    // Index of cell (xs, ys) of ring set s within one plane.  In 3D a row keeps its even x first
+    // and its odd x after them, so the two cells of every lane's pair, and their x-neighbours, are
+    // consecutive across the lanes (no bank conflicts from the pair's stride of two); in 2D rows
+    // are plain.
+    auto lidx = [](int s, int xs, int ys) {
+        const int dx = TX + 2 * (K - s);  // even
+        return PAIR ? ys * dx + (xs & 1) * (dx >> 1) + (xs >> 1) : ys * dx + xs;
+    };
     using RE = TbRing<ST>;
     constexpr bool CARRY = !std::is_same_v<RE, E>;  // intermediate steps kept in the compute type
     __shared__ RE ring[RING_ELEMS];
@@ -240,27 +298,73 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * sz;
     const int w = min(TX, fx - x0), hgt = min(TY, fy - y0), seg = min(sz, fz - z0);
     const int tid = threadIdx.x;
+    // 3D: the first and the last pair of a row, whose x-neighbour outside the pair is not in
+    // the neighbouring lane
+    const bool row_first = PAIR && (tid & 31) == 0, row_last = PAIR && (tid & 31) == 31;
 
-    // Columns: (cxl, cyl) in the frame.  Loads and stores address a plane through a
-    // block-uniform base plus a per-column 32-bit byte offset within the plane (the source cell
-    // of each population; the column's own cell for the stores).
-    int cxl[NC], cyl[NC];
-    unsigned xyoff[NC][Q], oxy[NJ];  // byte offsets within a plane, or kTbOob
-    bool valid[NC];
+    // Columns: (cxl, cyl) in the frame; rbx = 0 for the interior, the ring for a ring slot, K for
+    // a slot without a column.  Loads and stores address a plane through a block-uniform base
+    // plus a per-lane 32-bit byte offset within the plane: io[i] the interior's source row at the
+    // cell (3D: the pair's first cell; the x-shift of a pair comes from the neighbouring lane),
+    // fo[i] the element a first or last pair needs from beyond the neighbouring lane, ro[r][i]
+    // the source cell of a ring column, so the store offset of the interior (kTbOob where no
+    // access is wanted: out of range, no memory touched).
+    int cxl[NC], cyl[NC], rbx[NC];
+    // io[j][i]: interior cell j (pairs: one offset for the pair, j = 0)
+    constexpr int NIO = PAIR ? 1 : NJ;
+    unsigned io[NIO][Q], fo[Q], ro[NR > 0 ? NR : 1][Q], so[NIO];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        const int rb = C::ring_of(c);
+    for (int j = 0; j < NIO; ++j) {
         int ax, ay;
-        bool ok = true;
-        if (rb == 0) {
-            const int cc = tid + NT * c;
-            ax = cc % TX + (K - 1);
-            ay = cc / TX + HY * (K - 1);
+        if constexpr (PAIR) {
+            ax = 2 * (tid & 31) + (K - 1);
+            ay = (tid >> 5) + (K - 1);
         } else {
-            // odd rings from the last thread down, even ones from the first up, so that no
-            // wave holds a column of two rings
-            const int h = ((rb & 1) ? NT - 1 - tid : tid) + NT * (c - C::first_of_ring(rb));
-            ok = h < C::ring_cols(rb);
+            const int cc = tid + NT * j;
+            ax = cc % TX + (K - 1);
+            ay = HY * (cc / TX + (K - 1));
+        }
+        for (int c = 0; c < (PAIR ? 2 : 1); ++c) {
+            cxl[j + c] = ax + c;
+            cyl[j + c] = ay;
+            rbx[j + c] = 0;
+        }
+        int X = (x0 + ax - (K - 1)) % fx;
+        if (X < 0) X += fx;
+        int Y = (y0 + ay - HY * (K - 1)) % fy;
+        if (Y < 0) Y += fy;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int Ys = wrap_add(Y, -F::ky(i), fy);
+            // pairs read their own two cells (the x-shift comes from the neighbouring lane)
+            io[j][i] = (unsigned)(Ys * fx + wrap_add(X, PAIR ? 0 : -F::kx(i), fx)) * (unsigned)sizeof(E);
+            if (PAIR) {
+                unsigned f = kTbOob;
+                if (F::kx(i) > 0 && row_first) f = (unsigned)(Ys * fx + wrap_add(X, -1, fx)) * (unsigned)sizeof(E);
+                if (F::kx(i) < 0 && row_last) f = (unsigned)(Ys * fx + wrap_add(X, 2, fx)) * (unsigned)sizeof(E);
+                fo[i] = f;
+            }
+        }
+        // a pair lies wholly inside or wholly outside the box (even fx, even tile origin)
+        so[j] = (ax - (K - 1) < w && ay - HY * (K - 1) < hgt) ? (unsigned)(Y * fx + X) * (unsigned)sizeof(E) : kTbOob;
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        int h, rb;
+        if constexpr (PAIR) {  // one pool, ring 1 first
+            h = tid + NT * r;
+            rb = 1;
+            while (rb < K && h >= C::ring_cols(rb)) {
+                h -= C::ring_cols(rb);
+                ++rb;
+            }
+        } else {  // the slot's own ring
+            rb = C::ring_of(r);
+            h = ((rb & 1) ? NT - 1 - tid : tid) + NT * (r - C::first_of_ring(rb));
+            if (h >= C::ring_cols(rb)) rb = K;
+        }
+        int ax = K - 1, ay = HY * (K - 1);
+        if (rb < K) {
             const int W = TX + 2 * rb, lo = K - 1 - rb;
             if (HY == 0) {
                 ax = h == 0 ? lo : lo + W - 1;
@@ -276,41 +380,50 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                 ax = (h2 & 1) ? lo + W - 1 : lo;
                 ay = lo + 1 + (h2 >> 1);
             }
-            if (!ok) ax = ay = K - 1;
         }
-        cxl[c] = ax;
-        cyl[c] = ay;
-        valid[c] = ok;
+        cxl[NJ + r] = ax;
+        cyl[NJ + r] = ay;
+        rbx[NJ + r] = rb;
         int X = (x0 - (K - 1) + ax) % fx;
         if (X < 0) X += fx;
         int Y = (y0 - HY * (K - 1) + ay) % fy;
         if (Y < 0) Y += fy;
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-            xyoff[c][i] = ok ? (unsigned)(wrap_add(Y, -F::ky(i), fy) * fx + wrap_add(X, -F::kx(i), fx)) * (unsigned)sizeof(E)
-                             : kTbOob;
-        // stores of interior columns outside the box (a ragged tile) go out of range
-        if (rb == 0)
-            oxy[c < NJ ? c : 0] = (ax - (K - 1) < w && ay - HY * (K - 1) < hgt)
-                                      ? (unsigned)(Y * fx + X) * (unsigned)sizeof(E)
-                                      : kTbOob;
+            ro[r][i] = rb < K ? (unsigned)(wrap_add(Y, -F::ky(i), fy) * fx + wrap_add(X, -F::kx(i), fx)) * (unsigned)sizeof(E)
+                              : kTbOob;
     }
     const size_t plane = (size_t)fx * fy;
-    const unsigned plane_bytes = (unsigned)(plane * sizeof(E));  // < 2^31 (host check)
+    const unsigned plane_bytes = (unsigned)(plane * sizeof(E));  // <= 2^31 (host check)
 
-    // local plane l is global plane z0 - (K - 1) + l (wrapped)
-    E la[NC][Q], lb[NC][Q];
-    // live = false: a prefetch past the segment's last plane, issued anyway so the load sits
-    // outside any branch; its records are empty and it reads nothing
-    auto load_plane = [&](int l, E(&ld)[NC][Q], bool live) {
+    // The loads of one plane: the interior's (a pair, or one element in 2D), the elements beyond
+    // the neighbouring lane, the ring columns'.
+    struct Loaded {
+        E2 pr[PAIR ? Q : 1];     // the pair's two elements
+        E in[PAIR ? 1 : NJ][Q];  // single interior cells
+        E fx1[PAIR ? Q : 1];     // a first or last pair's element beyond the neighbouring lane
+        E rg[NR > 0 ? NR : 1][Q];
+    };
+    // local plane l is global plane z0 - (K - 1) + l (wrapped).  live = false: a prefetch past
+    // the segment's last plane, issued anyway so the load sits outside any branch; its records are
+    // empty and it reads nothing.
+    Loaded la, lb;
+    auto load_plane = [&](int l, Loaded &ld, bool live) {
         int Z = (z0 - (K - 1) + l) % fz;
         if (Z < 0) Z += fz;
 #pragma unroll
         for (int i = i0; i < Q; ++i) {
             const auto r = plane_rsrc(src + (size_t)i * N + (size_t)wrap_add(Z, -F::kz(i), fz) * plane,
                                       live ? plane_bytes : 0u);
+            if constexpr (PAIR) {
+                ld.pr[i] = buf_load2<E>(r, io[0][i]);
+                if (F::kx(i) != 0) ld.fx1[i] = buf_load<E>(r, fo[i]);
+            } else {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) ld[c][i] = buf_load<E>(r, xyoff[c][i]);  // 0 where not valid
+                for (int j = 0; j < NIO; ++j) ld.in[j][i] = buf_load<E>(r, io[j][i]);
+            }
+#pragma unroll
+            for (int q = 0; q < NR; ++q) ld.rg[q][i] = buf_load<E>(r, ro[q][i]);  // 0 where no column
         }
     };
 
@@ -337,7 +450,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     // stage 2 (ring set 2) start only after a barrier that every wave passes once it is done
     // with the stage that reads that set, so the planes in use are enough.
     const int last = seg + 2 * K - 3;  // stage K writes the segment's seg planes
-    auto body = [&](int pl, E(&cur)[NC][Q]) {
+    // on = false: a pass past the segment's last plane (see the loop below): its stores go out of
+    // range, its other work is never used
+    auto body = [&](int pl, Loaded &cur, bool on) {
+        const unsigned out_bytes = on ? plane_bytes : 0u;
 #pragma unroll
         for (int s = 1; s <= K; ++s) {
             const int l = pl - (s - 1);
@@ -345,17 +461,53 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                 const int l3 = l % 3;
                 const int lm3 = (l + 2) % 3;  // (l - 1) % 3
                 const int lp3 = (l + 1) % 3;  // (l + 1) % 3
+                // stage 1's interior inputs: in 3D the pair's own two elements, the x-neighbour
+                // beyond it from the neighbouring lane (DPP, all lanes active here) or, for the
+                // first and last pair of a row, from its own extra element
+                CT in1[PAIR ? NJ : 1][Q];
+                if (PAIR && s == 1) {
+#pragma unroll
+                    for (int i = i0; i < Q; ++i) {
+                        if constexpr (PAIR) {
+                            const CT a = dec_loaded<ST, RAW>(cur.pr[i].x), bb = dec_loaded<ST, RAW>(cur.pr[i].y);
+                            if (F::kx(i) == 0) {
+                                in1[0][i] = a;
+                                in1[1][i] = bb;
+                            } else if (F::kx(i) > 0) {  // pulls from x - 1
+                                const CT left = dpp_move<kDppWaveShr1>(bb);
+                                const CT edge = dec_loaded<ST, RAW>(cur.fx1[i]);  // decoded on every lane: a select,
+                                in1[0][i] = row_first ? edge : left;             // not a branch
+                                in1[1][i] = a;
+                            } else {  // pulls from x + 1
+                                const CT right = dpp_move<kDppWaveShl1>(a);
+                                const CT edge = dec_loaded<ST, RAW>(cur.fx1[i]);
+                                in1[0][i] = bb;
+                                in1[1][i] = row_last ? edge : right;
+                            }
+                        }
+                    }
+                }
+                CT outK[PAIR ? NJ : 1][Q];  // stage K's results of a pair, stored together after the loop
+                const int Zq = z0 - (K - 1) + l;  // stage K: in [z0, z0 + seg)
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
-                    if (C::ring_of(c) > K - s || !valid[c]) continue;
+                    // ring columns work in stages 1 .. K - ring (a slot without a column has ring K)
+                    if (c >= NJ && (PAIR ? rbx[c] > K - s : (C::ring_of(c - NJ) > K - s || rbx[c] == K))) continue;
                     CT sv[Q];
                     sv[0] = 0;
                     if (s == 1) {
 #pragma unroll
-                        for (int i = i0; i < Q; ++i) sv[i] = dec_loaded<ST, RAW>(cur[c][i]);
+                        for (int i = i0; i < Q; ++i) {
+                            if (c >= NJ)
+                                sv[i] = dec_loaded<ST, RAW>(cur.rg[c < NJ ? 0 : c - NJ][i]);
+                            else if constexpr (PAIR)
+                                sv[i] = in1[c < NJ ? c : 0][i];
+                            else
+                                sv[i] = dec_loaded<ST, RAW>(cur.in[c < NJ ? c : 0][i]);
+                        }
                     } else {
                         const int set = s - 1;  // ring set read, in its own coordinates
-                        const int lxy = (cyl[c] - HY * (s - 2)) * set_dx(set) + (cxl[c] - (s - 2));
+                        const int xs = cxl[c] - (s - 2), ys = cyl[c] - HY * (s - 2);
 #pragma unroll
                         for (int i = i0; i < Q; ++i) {
                             if (F::moves_xy(i)) {
@@ -363,7 +515,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                                 const int q = l - kz;
                                 const int q3 = kz > 0 ? lm3 : kz < 0 ? lp3 : l3;
                                 const RE e = ring[set_off(set) + (F::plane_off(i, K) + slot(kz, q, q3)) * set_pl(set) +
-                                                  lxy - F::ky(i) * set_dx(set) - F::kx(i)];
+                                                  lidx(set, xs - F::kx(i), ys - F::ky(i))];
                                 if constexpr (CARRY)
                                     sv[i] = e;
                                 else
@@ -375,16 +527,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                     }
                     collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, sv);
                     if (s == K) {
-                        // cells outside the box have an out-of-range offset: no branch
-                        const int Zq = z0 - (K - 1) + l;  // in [z0, z0 + seg)
+                        if constexpr (PAIR) {
+                            if (c < NJ)
 #pragma unroll
-                        for (int i = i0; i < Q; ++i)
-                            buf_store<E>(enc_io<ST, RAW>(sv[i]),
-                                         plane_rsrc(dst + (size_t)i * N + (size_t)Zq * plane, plane_bytes),
-                                         oxy[c < NJ ? c : 0]);
+                                for (int i = i0; i < Q; ++i) outK[c < NJ ? c : 0][i] = sv[i];
+                        } else if (c < NJ) {
+                            // cells outside the box have an out-of-range offset: no branch
+#pragma unroll
+                            for (int i = i0; i < Q; ++i)
+                                buf_store<E>(enc_io<ST, RAW>(sv[i]),
+                                             plane_rsrc(dst + (size_t)i * N + (size_t)Zq * plane, out_bytes),
+                                             so[c < NJ ? c : 0]);
+                        }
                     } else {
-                        const int lxy = (cyl[c] - HY * (s - 1)) * set_dx(s) + (cxl[c] - (s - 1));
-                        const bool keep_local = C::ring_of(c) <= K - s - 1;
+                        const int lxy = lidx(s, cxl[c] - (s - 1), cyl[c] - HY * (s - 1));
+                        const bool keep_local = c < NJ ? true
+                                                : PAIR ? rbx[c] <= K - s - 1 : C::ring_of(c - NJ) <= K - s - 1;
 #pragma unroll
                         for (int i = i0; i < Q; ++i) {
                             // as stored and reloaded (FP64, FP32: the value itself), or carried
@@ -403,6 +561,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                                 if (i == ID) d0[s][c] = v;
                             }
                         }
+                    }
+                }
+                if (PAIR && s == K) {
+                    // a pair's step t+K: one access per population; a pair outside the box has an
+                    // out-of-range offset, so there is no branch
+#pragma unroll
+                    for (int i = i0; i < Q; ++i) {
+                        E2 v;
+                        v.x = enc_io<ST, RAW>(outK[0][i]);
+                        v.y = enc_io<ST, RAW>(outK[PAIR ? 1 : 0][i]);
+                        buf_store2<E>(v, plane_rsrc(dst + (size_t)i * N + (size_t)Zq * plane, out_bytes), so[0]);
                     }
                 }
             }
@@ -432,12 +601,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     load_plane(0, la, true);
     if constexpr (PF == 2) {
         load_plane(1, lb, true);  // seg >= 1: at least 2K - 1 >= 3 planes
+        // every pass through the loop runs both bodies, so there is one path to the loop head
+        // and the compiler's wait counts there stay exact (with the second body under a branch it
+        // waits for every load in flight); past the last plane the second body stores nothing
         for (int pl = 0; pl <= last; pl += 2) {
-            body(pl, la);
-            if (pl + 1 <= last) body(pl + 1, lb);
+            body(pl, la, true);
+            body(pl + 1, lb, pl + 1 <= last);
         }
     } else {
-        for (int pl = 0; pl <= last; ++pl) body(pl, la);
+        for (int pl = 0; pl <= last; ++pl) body(pl, la, true);
     }
 }
 

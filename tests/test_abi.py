@@ -90,6 +90,8 @@ def test_sizes(lattice, storage, shape, bpu):
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), variant="open2d", bc="zero"),  # open 2D boxes only
     dict(lattice="D1Q3", storage="f32", shape=(64,), variant="open2d", bc="zero"),
     dict(lattice="D3Q19", storage="f64", shape=(8, 8, 8), variant="tb3"),
+    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 9), variant="tb3"),             # 3D x-pairs: nx even
+    dict(lattice="D3Q7", storage="f16", shape=(8, 8, 9), variant="tb2"),
     dict(lattice="D3Q13", storage="f64", shape=(8, 8, 8), variant="tb3"),
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), variant="tb3", bc="sponge", sponge_width=2,
          sponge_sigma=0.1),

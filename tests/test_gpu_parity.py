@@ -27,7 +27,7 @@ SHAPES = {
     2: {"dpp": [(9, 520), (5, 256)], "dpp2": [(7, 262), (3, 128)], "generic": [(9, 517)], "lds": [(9, 517), (4, 256)],
         "tb2": [(19, 130)], "tb3": [(23, 131)]},
     3: {"dpp": [(5, 6, 264), (3, 4, 256)], "dpp2": [(3, 5, 130)], "generic": [(5, 6, 13)], "lds": [(5, 6, 259)],
-        "tb2": [(21, 18, 66)], "tb3": [(22, 19, 67)]},
+        "tb2": [(21, 18, 66)], "tb3": [(22, 19, 66)]},
 }
 
 
