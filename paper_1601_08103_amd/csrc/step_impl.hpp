@@ -99,8 +99,8 @@ lbm_status step_lattice(lbm_lee *h, int64_t nsteps, hipStream_t st) {
                     using SH = TbShape<VS, ST, K>;
                     if constexpr (SH::TY > 0) {
                         const int fx = h->nx, fy = VS::D == 3 ? h->ny : 1, fz = VS::D == 3 ? h->nz : h->ny;
-                        const long long tiles_x = (fx + kTbTx - 1) / kTbTx, tiles_y = (fy + SH::TY - 1) / SH::TY;
-                        auto fn = step_tbk<VS, ST, SK, HF, K, SH::TY, SH::NT, SH::WPE>;
+                        const long long tiles_x = (fx + SH::TX - 1) / SH::TX, tiles_y = (fy + SH::TY - 1) / SH::TY;
+                        auto fn = step_tbk<VS, ST, SK, HF, K, SH::TX, SH::TY, SH::NT, SH::WPE>;
                         int sz = 16;
                         const unsigned seg_bits = (tune >> 6) & 3u;
                         if (seg_bits) {

@@ -65,11 +65,17 @@ struct TbFrame {
     }
 };
 
-// Tile shape per (set, storage, K): 64 cells along x; in 3D the largest TY in {32 or 16, 8, 4}
-// whose LDS rings (one set per intermediate step) fit the budget (64 KB for K = 2, the CU's
-// 160 KB otherwise), 32 TY threads with two interior columns each; in 2D one row of 64 columns
-// per block of 64 threads.  TY = 0: no shape fits (the variant is unsupported).
-constexpr int kTbTx = 64;
+// Tile shape per (set, storage, K): TX cells along x and TY along y.  In 3D with three or more
+// steps and 4-byte ring elements TX = 128 where the rings fit at TY = 16, else TX = 64; TY is the
+// largest in {32 or 16, 8, 4} whose LDS rings (one set per intermediate step) fit the budget (64 KB
+// for K = 2, the CU's 160 KB otherwise); TX TY / 2 threads with two interior columns each.  In 2D
+// one row of 64 columns per block of 64 threads.  TY = 0: no shape fits (the variant is
+// unsupported).
+// The loads of a tile's side columns (the rings' cells left and right of the tile) fetch a cache
+// line per row for a few bytes; every wave-wide load of a row's interior fetches its row segment
+// whole.  The L1-to-L2 request rate per CU is what bounds these kernels (the same rate as a plain
+// copy kernel's, measured), so a wider tile, with half the side columns per interior cell, runs
+// faster although its rings hold more rows (128 x 16 against 64 x 32).
 
 // Element type of the LDS rings: the storage type where it holds the compute type's values
 // exactly (FP64, FP32), the compute type (FP32) for the 16-bit formats, whose intermediate steps
@@ -82,13 +88,17 @@ struct TbShape {
     using F = TbFrame<VS>;
     static constexpr int hy = F::y_halo() ? 1 : 0;
     static constexpr long budget = K == 2 ? 64 * 1024 : 160 * 1024;
-    static constexpr long lds_bytes(int ty) {
+    static constexpr long lds_for(int tx, int ty) {
         long cells = 0;
-        for (int s = 1; s < K; ++s) cells += (long)(kTbTx + 2 * (K - s)) * (ty + 2 * hy * (K - s));
+        for (int s = 1; s < K; ++s) cells += (long)(tx + 2 * (K - s)) * (ty + 2 * hy * (K - s));
         return (long)F::planes(K) * cells * (long)sizeof(TbRing<ST>);
     }
+    static constexpr int TX =
+        (VS::D == 3 && K >= 3 && sizeof(TbRing<ST>) == 4 && lds_for(128, 16) <= budget) ? 128 : 64;
+    static constexpr long lds_bytes(int ty) { return lds_for(TX, ty); }
     static constexpr int pick() {
         if (VS::D == 2) return lds_bytes(1) <= budget ? 1 : 0;
+        if (TX == 128) return 16;
         // taller tiles (less ring overhead, one 1024-thread block per CU) pay off for 4- and
         // 8-byte ring elements with three or more steps (measured, D3Q7 256^3)
         const int top = (K >= 3 && sizeof(TbRing<ST>) >= 4) ? 32 : 16;
@@ -97,7 +107,7 @@ struct TbShape {
         return 0;
     }
     static constexpr int TY = pick();
-    static constexpr int NT = VS::D == 2 ? 64 : (TY > 0 ? 32 * TY : 64);
+    static constexpr int NT = VS::D == 2 ? 64 : (TY > 0 ? TX / 2 * TY : 64);
     // waves per SIMD the register budget is set for (4: 128 VGPRs; 2 for the sets with 13 or
     // more velocities, whose collisions per column need more), lowered where the LDS
     // (160 KB per CU) holds fewer blocks than that needs
@@ -154,15 +164,25 @@ __device__ __forceinline__ E buf_load(__amdgpu_buffer_rsrc_t r, unsigned off) {
     }
 }
 
+// Cache policy of the stores: non-temporal for 2- and 4-byte elements.  The state written at
+// step t+K is read again only by the next launch, and stores that allocate in L2 evict the planes
+// in flight and the halo cells that neighbouring tiles on the same XCD read shortly after
+// (measured at 256^3: 2 % faster for FP32, 8 % for the 16-bit formats; FP64, with half as many
+// cells per tile, ran 8 % slower with it).  The loads keep the default policy: the halo rows and
+// columns are read by two tiles, and with the non-temporal policy on the loads too the kernel
+// runs 1.5 times slower.
+template <typename E>
+constexpr int kTbStream = sizeof(E) == 8 ? 0 : 2;  // 2: the nt bit of the cache-policy operand
+
 template <typename E>
 __device__ __forceinline__ void buf_store(E v, __amdgpu_buffer_rsrc_t r, unsigned off) {
     if constexpr (sizeof(E) == 2) {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)off, 0, kTbStream<E>);
     } else if constexpr (sizeof(E) == 4) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, kTbStream<E>);
     } else {
         typedef unsigned u2 __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)off, 0, kTbStream<E>);
     }
 }
 
@@ -184,27 +204,28 @@ __device__ __forceinline__ Vec2<E> buf_load2(__amdgpu_buffer_rsrc_t r, unsigned 
 template <typename E>
 __device__ __forceinline__ void buf_store2(Vec2<E> v, __amdgpu_buffer_rsrc_t r, unsigned off) {
     if constexpr (sizeof(E) == 2) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, kTbStream<E>);
     } else if constexpr (sizeof(E) == 4) {
         typedef unsigned u2 __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)off, 0, kTbStream<E>);
     } else {
         typedef unsigned u4 __attribute__((ext_vector_type(4)));
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, (int)off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, (int)off, 0, kTbStream<E>);
     }
 }
 
 // Column bookkeeping (frame: the tile dilated by K-1 cells, origin at its corner; the tile's
-// own cells start at (K-1, HY (K-1))).  In 3D a thread owns two interior cells: for 2- and 8-byte
-// elements two x-adjacent ones (a "pair": 32 pairs per 64-cell row, a wave holds two rows), read
-// and written with one access of two elements per population; for FP32, two cells TY/2 rows
-// apart, each with its own accesses (measured faster there: the pair's extra registers push the
-// FP32 kernel, whose constants are split in two, past 128 VGPRs); in 2D one interior cell.  The rings b = 1..K-1 around the tile
-// (b cells out) are spread over NR ring slots per thread, one column each (threads past the
-// last ring column have none); stage s works on the interior and the rings b <= K - s.
-template <int K, int TY, int NT, int HY, bool PAIR_>
+// own cells start at (K-1, HY (K-1))).  In 3D a thread owns two interior cells: two x-adjacent
+// ones (a "pair": TX/2 pairs per row, a wave holds one or two rows), read and written with one
+// access of two elements per population, except for FP32 with 13 or more velocities, where the
+// pair's registers would spill (the FP32 collision's constants are split in two): there two
+// cells TY/2 rows apart, each with its own accesses; in 2D one interior cell.  The rings
+// b = 1..K-1 around the tile (b cells out) are spread over NR ring slots per thread, one column
+// each (threads past the last ring column have none); stage s works on the interior and the
+// rings b <= K - s.
+template <int K, int TX_, int TY, int NT, int HY, bool PAIR_>
 struct TbCols {
-    static constexpr int TX = kTbTx;
+    static constexpr int TX = TX_;
     static constexpr bool PAIR = PAIR_;
     static constexpr int NJ = TX * TY / NT;  // interior cells per thread: 2 in 3D (a pair or two rows), 1 in 2D
     static constexpr int ring_cols(int b) { return HY ? 2 * (TX + 2 * b) + 2 * (TY + 2 * b - 2) : 2; }
@@ -217,7 +238,7 @@ struct TbCols {
     // thread holds at most ceil(total / NT) of them and a slot's ring is known at run time; else
     // each ring has its own slots (odd rings from the last thread down, even ones from the first
     // up), so a slot's ring is a compile-time constant and the stages it works in cost nothing
-    // (the FP32 kernel needs that to stay within 128 registers).
+    // (fewer registers).
     static constexpr int NH(int b) { return (ring_cols(b) + NT - 1) / NT; }
     static constexpr int NR = [] {
         if (PAIR) return (ring_total() + NT - 1) / NT;
@@ -241,7 +262,7 @@ struct TbCols {
     }
 };
 
-template <class VS, class ST, bool SKIP0, bool HALF, int K, int TY, int NT, int WPE>
+template <class VS, class ST, bool SKIP0, bool HALF, int K, int TX, int TY, int NT, int WPE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void step_tbk(
     const typename ST::elem *__restrict__ src, typename ST::elem *__restrict__ dst, int fx, int fy, int fz, size_t N,
     int sz, int tiles_x, int tiles_y, StepCoef<typename ST::comp, VS::Q> k) {
@@ -252,9 +273,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     constexpr bool RAW = ST::has_raw;
     constexpr int Q = VS::Q;
     constexpr int i0 = SKIP0 ? 1 : 0;
-    constexpr int TX = kTbTx;
     constexpr int HY = F::y_halo() ? 1 : 0;
-    using C = TbCols<K, TY, NT, HY, HY == 1 && sizeof(E) != 4>;
+    using C = TbCols<K, TX, TY, NT, HY, HY == 1 && (sizeof(E) != 4 || Q <= 9)>;
     constexpr bool PAIR = C::PAIR;
     constexpr int NJ = C::NJ;
     constexpr int NR = C::NR;
@@ -300,7 +320,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     const int tid = threadIdx.x;
     // 3D: the first and the last pair of a row, whose x-neighbour outside the pair is not in
     // the neighbouring lane
-    const bool row_first = PAIR && (tid & 31) == 0, row_last = PAIR && (tid & 31) == 31;
+    constexpr int PX = TX / 2;  // pairs per row
+    const bool row_first = PAIR && tid % PX == 0, row_last = PAIR && tid % PX == PX - 1;
 
     // Columns: (cxl, cyl) in the frame; rbx = 0 for the interior, the ring for a ring slot, K for
     // a slot without a column.  Loads and stores address a plane through a block-uniform base
@@ -317,8 +338,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     for (int j = 0; j < NIO; ++j) {
         int ax, ay;
         if constexpr (PAIR) {
-            ax = 2 * (tid & 31) + (K - 1);
-            ay = (tid >> 5) + (K - 1);
+            ax = 2 * (tid % PX) + (K - 1);
+            ay = tid / PX + (K - 1);
         } else {
             const int cc = tid + NT * j;
             ax = cc % TX + (K - 1);
@@ -408,11 +429,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     // the segment's last plane, issued anyway so the load sits outside any branch; its records are
     // empty and it reads nothing.
     Loaded la, lb;
-    auto load_plane = [&](int l, Loaded &ld, bool live) {
+    // Populations [ia, ib) only: a prefetch is spread over the K stages of an iteration (chunk s in
+    // stage s), so every stage keeps the memory pipeline busy; issued in one burst, the loads of a
+    // whole plane fill the queues, stall the issuing waves and leave the pipeline idle for the
+    // rest of the iteration.
+    auto load_plane = [&](int l, Loaded &ld, bool live, int ia, int ib) {
         int Z = (z0 - (K - 1) + l) % fz;
         if (Z < 0) Z += fz;
 #pragma unroll
         for (int i = i0; i < Q; ++i) {
+            if (i < ia || i >= ib) continue;
             const auto r = plane_rsrc(src + (size_t)i * N + (size_t)wrap_add(Z, -F::kz(i), fz) * plane,
                                       live ? plane_bytes : 0u);
             if constexpr (PAIR) {
@@ -450,12 +476,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     // stage 2 (ring set 2) start only after a barrier that every wave passes once it is done
     // with the stage that reads that set, so the planes in use are enough.
     const int last = seg + 2 * K - 3;  // stage K writes the segment's seg planes
+    // first population of the prefetch chunk issued in stage s (chunk(K + 1) = Q)
+    auto chunk = [](int s) { return i0 + (Q - i0) * (s - 1) / K; };
     // on = false: a pass past the segment's last plane (see the loop below): its stores go out of
     // range, its other work is never used
     auto body = [&](int pl, Loaded &cur, bool on) {
         const unsigned out_bytes = on ? plane_bytes : 0u;
 #pragma unroll
         for (int s = 1; s <= K; ++s) {
+            if (s > 1) load_plane(pl + PF, cur, pl + PF <= last, chunk(s), chunk(s + 1));
             const int l = pl - (s - 1);
             if (l >= s - 1) {
                 const int l3 = l % 3;
@@ -580,7 +609,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                 // otherwise the two overlap, the loop latch copies the new values into the old
                 // registers, and that copy waits for the loads it was meant to keep in flight
                 __builtin_amdgcn_sched_barrier(0);
-                load_plane(pl + PF, cur, pl + PF <= last);  // in flight across the stages
+                load_plane(pl + PF, cur, pl + PF <= last, chunk(1), chunk(2));  // in flight across the stages
             }
             if (s < K) {
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
@@ -598,9 +627,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
             }
     };
 
-    load_plane(0, la, true);
+    load_plane(0, la, true, 0, Q);
     if constexpr (PF == 2) {
-        load_plane(1, lb, true);  // seg >= 1: at least 2K - 1 >= 3 planes
+        // plane 0's loads must be issued before plane 1's: the loop's first use of plane 0 then
+        // waits only for those (issued in the other order, the wait at the loop head, shared by
+        // every pass, is for all loads in flight)
+        __builtin_amdgcn_sched_barrier(0);
+        load_plane(1, lb, true, 0, Q);  // seg >= 1: at least 2K - 1 >= 3 planes
         // every pass through the loop runs both bodies, so there is one path to the loop head
         // and the compiler's wait counts there stay exact (with the second body under a branch it
         // waits for every load in flight); past the last plane the second body stores nothing
