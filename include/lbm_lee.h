@@ -118,7 +118,8 @@ typedef int32_t lbm_status;
 /* Step kernel variant.  All variants run the same per-cell arithmetic, so their results are
  * bitwise identical; they differ only in how the streamed values are gathered (the multi-step
  * variants TB2/TB3 with 16-bit storage excepted: they round once per launch, see below). */
-#define LBM_VARIANT_AUTO 0    /* the fastest measured variant: OPEN2D on 2D open boxes; on    */
+#define LBM_VARIANT_AUTO 0    /* the fastest measured variant: OPEN2D on 2D open boxes of     */
+                              /* <= 2^23 cells (GENERIC on larger ones); on                    */
                               /* periodic 2D/3D boxes of >= 2^20 cells TB3 (sets of <= 9       */
                               /* velocities) or TB2 where they are supported; else GENERIC for */
                               /* 4- and 8-byte storage, DPP/DPP2/GENERIC (by nx) for 2-byte    */
@@ -141,7 +142,9 @@ typedef int32_t lbm_status;
  * rings do not fit 64 KB at TY = 4 (D3Q19 and D3Q27, and D3Q9 and D3Q13 with FP64). */
 #define LBM_VARIANT_TB2 5
 /* Three steps per launch, the same scheme one stage deeper (the tile dilated by two cells for
- * step t+1, by one for t+2); LDS rings of two intermediate steps (up to 160 KB per block).  As
+ * step t+1, by one for t+2); LDS rings of two intermediate steps (up to 160 KB per block).  In 3D
+ * the tile is 128 x 16 cells where those rings fit with 4-byte ring elements (FP32 storage and
+ * the 16-bit formats, whose intermediate steps are kept in FP32; D3Q7), else 64 x TY.  As
  * with TB2, F64/F32 results equal one-step launches bit for bit and the 16-bit formats round
  * once per launch of three steps.
  * LBM_E_UNSUPPORTED where they do not fit at TY = 4 (D3Q13 and D3Q19 with FP64) and in the

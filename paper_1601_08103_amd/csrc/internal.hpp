@@ -393,9 +393,14 @@ inline lbm_status launch_check() {
 inline int resolve_variant(const lbm_lee *h) {
     if (h->inplace) return LBM_VARIANT_GENERIC;  // the in-place kernels are one thread per cell
     if (h->desc.variant != LBM_VARIANT_AUTO) return h->desc.variant;
-    // 2D open boxes: ring, interior and closure network in one launch (the separate kernels of
-    // the other variants are each latency-bound on boxes of this size)
-    if (h->desc.bc != LBM_BC_PERIODIC && h->tab.D == 2) return LBM_VARIANT_OPEN2D;
+    // 2D open boxes: ring, interior and closure network in one launch up to 8 M cells (the
+    // separate kernels of the other variants are each latency-bound there); on larger boxes the
+    // one-launch kernel's interior blocks, which reserve the network's LDS, lose to the
+    // one-cell-per-thread step plus the boundary kernels (D2Q9, us per step, one launch against
+    // separate kernels: 2048^2 FP32 network 62 vs 81, E3M12 31 vs 51; 4096^2 FP32 zero 259 vs
+    // 222, network 252 vs 237, E3M12 about equal)
+    if (h->desc.bc != LBM_BC_PERIODIC && h->tab.D == 2)
+        return h->N <= ((size_t)8 << 20) ? LBM_VARIANT_OPEN2D : LBM_VARIANT_GENERIC;
     // periodic boxes of a million cells and more: three steps per launch for the sets of up to 9
     // velocities, two for the larger ones (their two collisions per column already fill the
     // registers), for every storage mode

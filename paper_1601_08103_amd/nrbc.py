@@ -397,12 +397,20 @@ def main(argv=None):
     ap.add_argument("--closures", default="zero,copy,sponge,mlp")
     ap.add_argument("--weights", default=None, help="weights file (.npy) to write (train) or read (evaluate)")
     ap.add_argument("--seeds", type=int, default=32, help="held-out initial states for evaluate")
-    ap.add_argument("--sponge-width", type=int, default=32)
-    ap.add_argument("--sponge-sigma", type=float, default=0.2)
+    ap.add_argument("--sponge-width", default="32",
+                    help="layer width; a comma-separated list evaluates one sponge per width (evaluate)")
+    ap.add_argument("--sponge-sigma", default="0.2", help="damping rate, or one per width")
     ap.add_argument("--dagger", type=int, default=0, help="rounds of closed-loop data + further training")
     ap.add_argument("--dagger-runs", type=int, default=100)
     ap.add_argument("--dagger-epochs", type=int, default=2)
     args = ap.parse_args(argv)
+    widths = [int(w) for w in str(args.sponge_width).split(",")]
+    sigmas = [float(x) for x in str(args.sponge_sigma).split(",")]
+    if len(sigmas) == 1:
+        sigmas = sigmas * len(widths)
+    if len(sigmas) != len(widths):
+        ap.error("--sponge-sigma: one value, or one per width")
+    args.sponge_width, args.sponge_sigma = widths[0], sigmas[0]
     torch.cuda.set_device(0)
     lbm.load()
     info = lbm.lbm_lee_lattice_info(args.lattice)
@@ -427,6 +435,10 @@ def main(argv=None):
     P = np.load(args.weights, allow_pickle=False) if args.weights else None
     rng = np.random.default_rng(10_000 + args.seed)  # held out: training uses seeds below 10000
     closures = [c for c in args.closures.split(",") if c and (c != "mlp" or P is not None)]
+    # every sponge is (name, width, sigma); a single one keeps the name "sponge"
+    sponges = {"sponge": (widths[0], sigmas[0])} if len(widths) == 1 else {
+        f"sponge_W{w}_s{g:g}": (w, g) for w, g in zip(widths, sigmas)}
+    closures = [n for c in closures for n in (sponges if c == "sponge" else [c])]
     Rs = {c: [] for c in closures}
     ext = judge_solver(args.lattice, args.ext_storage, args.E, D)
     first = None
@@ -436,9 +448,10 @@ def main(argv=None):
         ref = judge_reference(args.lattice, fields, args.L, args.E, args.steps, args.every, args.ext_storage, ext,
                               args.slices)
         for c in closures:
-            Rs[c].append(reflection_vs(args.lattice, c, fields, ref, args.L, args.steps, args.every, params=P,
-                                       storage=args.storage, sponge_width=args.sponge_width,
-                                       sponge_sigma=args.sponge_sigma, slices=args.slices))
+            kind = "sponge" if c in sponges else c
+            w, g = sponges.get(c, (0, 0.0))
+            Rs[c].append(reflection_vs(args.lattice, kind, fields, ref, args.L, args.steps, args.every, params=P,
+                                       storage=args.storage, sponge_width=w, sponge_sigma=g, slices=args.slices))
         del ref
         log(f"evaluate: seed {k + 1}/{args.seeds}: " + ", ".join(f"{c} {Rs[c][-1]:.4f}" for c in closures))
     nrep = 50 if D == 3 else 200
@@ -448,12 +461,13 @@ def main(argv=None):
     del ext
     # step times on live data: every box starts from the first held-out state
     for c in closures:
-        W = args.sponge_width if c == "sponge" else 0
-        kw = dict(sponge_width=args.sponge_width, sponge_sigma=args.sponge_sigma) if c == "sponge" else {}
+        kind = "sponge" if c in sponges else c
+        W, g = sponges.get(c, (0, 0.0))
+        kw = dict(sponge_width=W, sponge_sigma=g) if kind == "sponge" else {}
         live = dict(fields=first, origin=[W] * D if W else None)
         nb = args.L + 2 * W
-        times[c] = time_per_step(args.lattice, (nb,) * D, bc=c, params=P, storage=args.storage, **live, **kw)
-        times_graph[c] = time_per_step(args.lattice, (nb,) * D, bc=c, params=P, storage=args.storage, graph=True,
+        times[c] = time_per_step(args.lattice, (nb,) * D, bc=kind, params=P, storage=args.storage, **live, **kw)
+        times_graph[c] = time_per_step(args.lattice, (nb,) * D, bc=kind, params=P, storage=args.storage, graph=True,
                                        **live, **kw)
         if c == "mlp":
             times_graph["mlp_closure_stream"] = time_per_step(args.lattice, (nb,) * D, bc=c, params=P,
@@ -461,7 +475,8 @@ def main(argv=None):
                                                               tune=lbm.TUNE["closure_stream"], **live)
     print(json.dumps(dict(mode="evaluate", lattice=args.lattice, init=args.init, L=args.L, E=args.E,
                           steps=args.steps, storage=args.storage, ext_storage=args.ext_storage, seeds=args.seeds,
-                          slices=args.slices, R_mean={c: float(np.mean(v)) for c, v in Rs.items()},
+                          slices=args.slices, sponges={k: dict(width=w, sigma=g) for k, (w, g) in sponges.items()},
+                          R_mean={c: float(np.mean(v)) for c, v in Rs.items()},
                           R_max={c: float(np.max(v)) for c, v in Rs.items()}, ms_per_step=times,
                           ms_per_step_graph=times_graph)))
 
