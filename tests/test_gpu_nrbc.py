@@ -101,3 +101,19 @@ def test_shipped_weights_beat_the_zero_closure(lattice, L, E, steps, init, seeds
     say("shipped weights vs zero closure", lattice, {c: float(np.mean(v)) for c, v in R.items()})
     assert np.all(np.isfinite(R["mlp"]))
     assert np.mean(R["mlp"]) < np.mean(R["zero"])
+
+
+def test_evaluate_compares_several_sponges_per_judge_run(capsys):
+    """nrbc evaluate with a list of sponge widths reports one sponge per width (each on its own
+    widened box), next to the other closures, from the same judge runs."""
+    import json
+    from paper_1601_08103_amd import nrbc
+    say("evaluate with two sponges")
+    nrbc.main(["evaluate", "--lattice", "D2Q9", "--L", "24", "--E", "72", "--steps", "32", "--every", "8",
+               "--seeds", "2", "--closures", "zero,sponge", "--sponge-width", "2,4", "--sponge-sigma", "0.3"])
+    out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert set(out["R_mean"]) == {"zero", "sponge_W2_s0.3", "sponge_W4_s0.3"}
+    assert out["sponges"]["sponge_W4_s0.3"] == {"width": 4, "sigma": 0.3}
+    for c, r in out["R_mean"].items():
+        assert np.isfinite(r) and r > 0, (c, r)
+    assert out["ms_per_step"]["sponge_W4_s0.3"] > 0

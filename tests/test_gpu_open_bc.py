@@ -417,3 +417,15 @@ def test_one_launch_open_step_full_size(bc, storage):
     assert np.abs(a).max() > 0
     for sim in sims:
         sim.close()
+
+
+@pytest.mark.parametrize("shape,want", [((2048, 2048), "open2d"), ((2048, 4096), "open2d"), ((2050, 4096), "generic"),
+                                        ((4096, 4096), "generic")])
+def test_auto_takes_the_one_launch_open_step_up_to_8m_cells(shape, want):
+    """AUTO on 2D open boxes: the one-launch step up to 2^23 cells (inclusive), the one-cell-per-thread
+    step with the boundary kernels above (measured faster there)."""
+    from paper_1601_08103_amd import lbm
+    say("auto open 2D", shape)
+    sim = lbm.Solver("D2Q9", "f32", shape, None, None, None, bc="zero")
+    assert sim.variant == want
+    sim.close()

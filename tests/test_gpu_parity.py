@@ -515,7 +515,7 @@ def test_in_place_streaming_matches_two_buffers(name, storage, shape):
 
 
 @pytest.mark.parametrize("name,storage,shape,tau", [
-    ("D3Q7", "f32", (20, 40, 130), 0.5),      # ragged tiles in x (2 x 64 + 2) and y, segments 16 + 4
+    ("D3Q7", "f32", (20, 40, 130), 0.5),      # ragged tiles in x (TB3: 128 + 2, TB2: 2 x 64 + 2) and y, segments 16 + 4
     ("D3Q7", "f32", (12, 24, 64), 0.8),       # the general relaxation
     ("D3Q7", "f64", (9, 17, 64), 0.5),
     ("D2Q9", "f32", (40, 200), 0.5),
@@ -568,7 +568,7 @@ def _h_bound_ok(storage, lat, S, got, want, nsteps):
 
 @pytest.mark.parametrize("name,storage,shape", [
     ("D3Q7", "e3m12", (16, 32, 128)),
-    ("D3Q7", "f16", (20, 40, 130)),           # ragged tiles in x and y
+    ("D3Q7", "f16", (20, 40, 130)),           # ragged tiles in x (TB3: 128 + 2) and y
     ("D3Q7_DIA", "f16", (4, 9, 20)),          # every axis shorter than a tile: the ring wraps
     ("D3Q19", "f16", (10, 12, 66)),
     ("D3Q9", "bf16", (6, 10, 70)),
