@@ -87,8 +87,9 @@ def traffic_from_counters(storage: str, n: int, variant: str):
 def nrbc_leg():
     """The learned non-reflecting closure on its 2D workload (D2Q9 512^2 open box, 1536^2 periodic
     judge, 1024 steps) with the shipped weights (trained by the library's own kernels): reflection
-    coefficient of the zero, sponge and network closures on two held-out initial states, and the
-    time per step of each box next to the judge's."""
+    coefficient of the zero closure, two sponges (the wide one of the earlier comparisons and one
+    that costs less per step than the network box) and the network closure on 32 held-out initial
+    states, and the time per step of each box next to the judge's."""
 
     from paper_1601_08103_amd import lbm, nrbc
 
@@ -96,12 +97,20 @@ def nrbc_leg():
     if not os.path.exists(path):
         return None
     P = np.load(path, allow_pickle=False)
-    L, E, steps, seeds = 512, 1536, 1024, 8
-    sponge = dict(sponge_width=96, sponge_sigma=0.03)
+    L, E, steps, seeds = 512, 1536, 1024, 32
+    sponges = {"sponge": (96, 0.03), "sponge_W160": (160, 0.015)}
     info = lbm.lbm_lee_lattice_info("D2Q9")
     rng = np.random.default_rng(10_000)  # held-out states: training draws seeds below 10000
     ext = nrbc.judge_solver("D2Q9", "f32", E, 2)
-    closures = ("zero", "sponge", "mlp")
+    closures = ("zero", "sponge", "sponge_W160", "mlp")
+
+    def kind(c):
+        return "sponge" if c in sponges else c
+
+    def layer(c):
+        w, g = sponges.get(c, (0, 0.0))
+        return w, (dict(sponge_width=w, sponge_sigma=g) if w else {})
+
     R = {c: [] for c in closures}
     first = None
     for _ in range(seeds):
@@ -109,20 +118,19 @@ def nrbc_leg():
         first = fields if first is None else first
         ref = nrbc.judge_reference("D2Q9", fields, L, E, steps, 8, ext=ext)  # one judge run per state
         for c in closures:
-            R[c].append(nrbc.reflection_vs("D2Q9", c, fields, ref, L, steps, 8, params=P, **sponge))
+            R[c].append(nrbc.reflection_vs("D2Q9", kind(c), fields, ref, L, steps, 8, params=P, **layer(c)[1]))
         del ref
     # step times on live states: the judge holds the last run's state; each box starts from the
-    # first held-out state (the sponge box from it on its inner box)
+    # first held-out state (a sponge box from it on its inner box)
     times = {"extended_periodic": round(nrbc.time_solver(ext, 200), 5)}
     ext.close()
     for c in closures:
-        W = sponge["sponge_width"] if c == "sponge" else 0
-        kw = sponge if c == "sponge" else {}
-        times[c] = round(nrbc.time_per_step("D2Q9", (L + 2 * W,) * 2, bc=c, params=P, fields=first,
+        W, kw = layer(c)
+        times[c] = round(nrbc.time_per_step("D2Q9", (L + 2 * W,) * 2, bc=kind(c), params=P, fields=first,
                                             origin=(W, W) if W else None, **kw), 5)
     out = dict(workload=f"2D open box D2Q9 {L}^2 FP32, judge {E}^2 periodic, {steps} steps, {seeds} held-out "
                         "pulse states", weights="paper_1601_08103_amd/weights/nrbc_D2Q9.npy",
-               sponge=dict(width=sponge["sponge_width"], sigma=sponge["sponge_sigma"]),
+               sponges={c: dict(width=w, sigma=g) for c, (w, g) in sponges.items()},
                R_mean={c: round(float(np.mean(v)), 5) for c, v in R.items()},
                R_max={c: round(float(np.max(v)), 5) for c, v in R.items()}, ms_per_step=times)
     log("nrbc", out)
