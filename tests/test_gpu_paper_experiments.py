@@ -17,6 +17,7 @@ from oracle import closed_forms as cf
 from oracle import lbe
 from paper_1601_08103_amd import inputs
 from tests._gpu import gpu_ok, lattice, say
+from tests.test_paper_points import paper_e5_points
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ok(), reason="needs a GPU")]
 
@@ -137,7 +138,7 @@ def test_e4_e6_3d_gauss_second_order(name):
         assert min(s) > 1.9, (k, s)
 
 
-def test_e5_3d_diatomic_dimensional():
+def test_e5_3d_diatomic_dimensional(golden_dir):
     """3D diatomic, dimensional background rho0 = theta0 = 1 on [0, 2)^3 to dimensional time 1:
     the product's dimensional mapping gives the non-dimensional end time sqrt(21/5) and, for
     N = 25, 40, 80, 120 cells per axis, N_TS = round(T / dt) steps (Table 1).  The density error
@@ -161,3 +162,9 @@ def test_e5_3d_diatomic_dimensional():
     say("E5 density error at T", ["%.3e" % v for v in e_T], ["%.3f" % v for v in _slopes(e_T, Ns)])
     assert min(_slopes(e_run, Ns)) > 1.9, e_run
     assert all(b < a for a, b in zip(e_T, e_T[1:]))
+    # the paper's points (against a finite-volume reference, at the same comparison time T) agree in
+    # size: within a factor 1.5 on every grid (measured: 1.04 to 1.30)
+    _, _, paper = paper_e5_points(golden_dir)
+    say("E5 paper points", ["%.3e" % v for v in paper], "ratio", ["%.2f" % (a / b) for a, b in zip(e_T, paper)])
+    for a, b in zip(e_T, paper):
+        assert b / 1.5 < a < 1.5 * b, (e_T, paper)
