@@ -18,8 +18,8 @@
 // every stage.  The loads of the next two planes (one for the sets with 13 and more velocities)
 // are in flight while a plane is computed, and K-1 barriers per iteration order the LDS traffic.
 // In 3D each thread's interior cells are an x-adjacent pair read and written with one access of
-// two elements per population (so nx must be even); the x-neighbour beyond the pair comes from
-// the neighbouring lane by DPP.
+// two elements per population (so nx must be even; FP32 sets of 13 and more velocities excepted);
+// the x-neighbour beyond the pair comes from the neighbouring lane by DPP.
 // Every cell goes through the same collision as the one-step kernels.  The intermediate steps
 // t+1 .. t+K-1 are never stored, so they stay in the compute type: for FP64 and FP32 storage
 // that is the stored value itself and K steps here give the same bits as K one-step launches;
@@ -73,9 +73,9 @@ struct TbFrame {
 // unsupported).
 // The loads of a tile's side columns (the rings' cells left and right of the tile) fetch a cache
 // line per row for a few bytes; every wave-wide load of a row's interior fetches its row segment
-// whole.  The L1-to-L2 request rate per CU is what bounds these kernels (the same rate as a plain
-// copy kernel's, measured), so a wider tile, with half the side columns per interior cell, runs
-// faster although its rings hold more rows (128 x 16 against 64 x 32).
+// whole.  The L1-to-L2 request rate per CU is what bounds these kernels (about 80 % of a plain
+// copy kernel's rate, measured), so a wider tile, with half the side columns per interior cell,
+// runs faster although its rings hold more rows (128 x 16 against 64 x 32).
 
 // Element type of the LDS rings: the storage type where it holds the compute type's values
 // exactly (FP64, FP32), the compute type (FP32) for the 16-bit formats, whose intermediate steps
