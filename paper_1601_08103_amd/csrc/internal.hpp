@@ -119,7 +119,7 @@ inline bool tb_plane_fits(const lbm_lee_desc *d, int D) {
 inline bool net_fits(const LatticeTable &t) {
     int k = 0;
     for (int i = 0; i < t.Q; ++i) k += t.c[i][0] == 1 ? 1 : 0;
-    return (kHistory * 3 * t.Q + 15) / 16 * 16 <= 128 && k <= 16;
+    return (kHistory * 3 * t.Q + 31) / 32 * 32 <= 128 && k <= 16;  // as NetGeom::fits
 }
 
 inline lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {

@@ -8,12 +8,19 @@
 //   not underflow; an all-zero strip has s = 0, z = 0 and predicts 0.
 // Parameters are FP32 (master copy, layout W1[n_in][64], b1[64], W2[64][64], b2[64],
 // W3[64][k], b3[k], row-major).  Every matrix product takes bfloat16 inputs (round to
-// nearest even) and accumulates in FP32 on v_mfma_f32_16x16x16_bf16; biases are added in FP32.
+// nearest even) and accumulates in FP32 on the matrix cores; biases are added in FP32.  The
+// forward pass reduces over 32 values per instruction (v_mfma_f32_16x16x32_bf16, gfx950), the
+// input padded with zeros to a multiple of 32 (a 16-wide product accumulated onto a 32-wide one's
+// result gave wrong rows in this compiler's code, measured on D3Q7 and D3Q13, so every product of
+// the forward pass has the one shape); the backward pass reduces over the 16 samples of a tile or
+// over the hidden width with v_mfma_f32_16x16x16_bf16.
 //
-// One wave owns a tile of 16 samples.  MFMA 16x16x16 operand layouts (lane l, element e):
-//   A (16 x 16, rows i, reduction k): A[l % 16][4 (l / 16) + e]
-//   B (16 x 16, reduction k, cols j): B[4 (l / 16) + e][l % 16]
-//   C (16 x 16):                      C[4 (l / 16) + e][l % 16]
+// One wave owns a tile of 16 samples.  MFMA operand layouts (lane l, element e; measured for
+// 16x16x32 with an exact integer product on one wave):
+//   16x16x16: A (16 x 16, rows i, reduction k): A[l % 16][4 (l / 16) + e]     (e < 4)
+//             B (16 x 16, reduction k, cols j): B[4 (l / 16) + e][l % 16]
+//   16x16x32: A (16 x 32): A[l % 16][8 (l / 16) + e], B (32 x 16): B[8 (l / 16) + e][l % 16]  (e < 8)
+//   both:     C (16 x 16): C[4 (l / 16) + e][l % 16]
 // Activations pass between layers through LDS (a per-wave [16][64] bfloat16 tile).
 #pragma once
 
@@ -24,6 +31,8 @@
 namespace lbm {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kHidden = 64;
@@ -37,6 +46,10 @@ __device__ __forceinline__ float bf16_val(unsigned short b) { return __uint_as_f
 
 __device__ __forceinline__ floatx4 mfma16(bf16x4 a, bf16x4 b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ floatx4 mfma32(bf16x8 a, bf16x8 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8v, a), __builtin_bit_cast(bf16x8v, b), c,
+                                                   0, 0, 0);
 }
 
 // Wave-local LDS ordering: the wave's LDS accesses complete in program order; the fences
@@ -72,8 +85,13 @@ template <class VS>
 struct NetGeom {
     static constexpr int NSTRIP = 3 * VS::Q;         // one time level: 3 cells x Q populations
     static constexpr int NIN = kHistory * NSTRIP;    // input: [strip(t), strip(t-1)]
-    static constexpr int NIN_PAD = (NIN + 15) / 16 * 16;
+    // the input tile: NIN values and zeros up to NIN_PAD, a multiple of 32 (the first layer's
+    // reduction, K32 products of 32 inputs); NIN_FILL, a multiple of 16, of them come from the
+    // strips' normalisation, the rest are zeroed separately
+    static constexpr int NIN_PAD = (NIN + 31) / 32 * 32;
+    static constexpr int NIN_FILL = (NIN + 15) / 16 * 16;
     static constexpr int ZW = NIN_PAD > kHidden ? NIN_PAD : kHidden;  // width of the input tile
+    static constexpr int K32 = NIN_PAD / 32;
     static constexpr int NOUT = entering_count<VS>();
     static constexpr int OFF_W1 = 0;
     static constexpr int OFF_B1 = OFF_W1 + NIN * kHidden;
@@ -87,9 +105,10 @@ struct NetGeom {
     static constexpr bool fits = NIN_PAD <= 128 && NOUT <= 16;
 };
 
-// Per-wave LDS tiles (bfloat16 bits); ZW = width of the input tile.
+// Per-wave LDS tiles (bfloat16 bits); ZW = width of the input tile, a multiple of 16.  16-byte
+// aligned (every member's size is a multiple of 16 bytes): the 32-wide A operands are 16-byte reads.
 template <int ZW>
-struct WaveTiles {
+struct alignas(16) WaveTiles {
     unsigned short z[16][ZW];
     unsigned short h1[16][64];
     unsigned short h2[16][64];
@@ -98,9 +117,9 @@ struct WaveTiles {
     unsigned short da1[16][64];
 };
 
-// Per-wave LDS tiles of the forward pass alone (inference).
+// Per-wave LDS tiles of the forward pass alone (inference), aligned as WaveTiles.
 template <int ZW>
-struct FwdTiles {
+struct alignas(16) FwdTiles {
     unsigned short z[16][ZW];
     unsigned short h1[16][64];
     unsigned short h2[16][64];
@@ -112,6 +131,16 @@ __device__ __forceinline__ bf16x4 a_rows(const unsigned short (*X)[LD], int kk, 
     const int i = lane & 15, k0 = kk * 16 + 4 * (lane >> 4);
     bf16x4 a;
     a.x = (short)X[i][k0]; a.y = (short)X[i][k0 + 1]; a.z = (short)X[i][k0 + 2]; a.w = (short)X[i][k0 + 3];
+    return a;
+}
+// 32-wide A operand from an LDS tile X[16][LD] (rows = samples): columns kk*32 + 8 (l/16) + e, one
+// 16-byte read (LD is a multiple of 16, so every row and every 8-column group is 16-byte aligned).
+template <int LD>
+__device__ __forceinline__ bf16x8 a_rows32(const unsigned short (*X)[LD], int kk, int lane) {
+    static_assert(LD % 16 == 0, "16-byte aligned rows");
+    const int i = lane & 15, k0 = kk * 32 + 8 * (lane >> 4);
+    bf16x8 a;
+    __builtin_memcpy(&a, __builtin_assume_aligned(&X[i][k0], 16), sizeof(a));
     return a;
 }
 // A operand = transpose of an LDS tile: A[i][k] = X[k][mt*16 + i] (rows of A = tile columns).
@@ -143,6 +172,17 @@ __device__ __forceinline__ bf16x4 b_weight(const float *__restrict__ W, int rows
     bf16x4 b = {v[0], v[1], v[2], v[3]};
     return b;
 }
+// 32-wide B operand from a row-major FP32 matrix: B[k][j] = W[kk*32 + k][nt*16 + j], zero outside.
+__device__ __forceinline__ bf16x8 b_weight32(const float *__restrict__ W, int rows, int cols, int kk, int nt, int lane) {
+    const int j = nt * 16 + (lane & 15), k0 = kk * 32 + 8 * (lane >> 4);
+    bf16x8 b;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int k = k0 + e;
+        b[e] = (k < rows && j < cols) ? (short)bf16_bits(W[k * cols + j]) : (short)0;
+    }
+    return b;
+}
 // B operand from the transpose of W[rows][cols]: B[k][j] = W[nt*16 + j][kk*16 + k].
 __device__ __forceinline__ bf16x4 b_weight_t(const float *__restrict__ W, int rows, int cols, int kk, int nt, int lane) {
     const int j = nt * 16 + (lane & 15), k0 = kk * 16 + 4 * (lane >> 4);
@@ -165,8 +205,8 @@ __device__ floatx4 net_forward_tile(const float *__restrict__ P, TT &T, int lane
     for (int nt = 0; nt < 4; ++nt) {
         floatx4 acc = {0, 0, 0, 0};
 #pragma unroll
-        for (int kk = 0; kk < G::NIN_PAD / 16; ++kk)
-            acc = mfma16(a_rows(T.z, kk, lane), b_weight(P + G::OFF_W1, G::NIN, kHidden, kk, nt, lane), acc);
+        for (int kk = 0; kk < G::K32; ++kk)
+            acc = mfma32(a_rows32(T.z, kk, lane), b_weight32(P + G::OFF_W1, G::NIN, kHidden, kk, nt, lane), acc);
         const float bias = P[G::OFF_B1 + nt * 16 + col];
 #pragma unroll
         for (int e = 0; e < 4; ++e) T.h1[row0 + e][nt * 16 + col] = bf16_bits(fmaxf(acc[e] + bias, 0.0f));
@@ -176,8 +216,8 @@ __device__ floatx4 net_forward_tile(const float *__restrict__ P, TT &T, int lane
     for (int nt = 0; nt < 4; ++nt) {
         floatx4 acc = {0, 0, 0, 0};
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
-            acc = mfma16(a_rows(T.h1, kk, lane), b_weight(P + G::OFF_W2, kHidden, kHidden, kk, nt, lane), acc);
+        for (int kk = 0; kk < 2; ++kk)
+            acc = mfma32(a_rows32(T.h1, kk, lane), b_weight32(P + G::OFF_W2, kHidden, kHidden, kk, nt, lane), acc);
         const float bias = P[G::OFF_B2 + nt * 16 + col];
 #pragma unroll
         for (int e = 0; e < 4; ++e) T.h2[row0 + e][nt * 16 + col] = bf16_bits(fmaxf(acc[e] + bias, 0.0f));
@@ -185,21 +225,21 @@ __device__ floatx4 net_forward_tile(const float *__restrict__ P, TT &T, int lane
     wave_lds_sync();
     floatx4 acc = {0, 0, 0, 0};
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
-        acc = mfma16(a_rows(T.h2, kk, lane), b_weight(P + G::OFF_W3, kHidden, G::NOUT, kk, 0, lane), acc);
+    for (int kk = 0; kk < 2; ++kk)
+        acc = mfma32(a_rows32(T.h2, kk, lane), b_weight32(P + G::OFF_W3, kHidden, G::NOUT, kk, 0, lane), acc);
     const float bias = col < G::NOUT ? P[G::OFF_B3 + col] : 0.0f;
 #pragma unroll
     for (int e = 0; e < 4; ++e) acc[e] += bias;
     return acc;
 }
 
-// The forward pass's weights as bfloat16 B-operand fragments (one 8-byte LDS read per lane and
+// The forward pass's weights as bfloat16 B-operand fragments (one 16-byte LDS read per lane and
 // product) and its FP32 biases, staged once per block.
 template <class VS>
 struct NetFrags {
-    bf16x4 w1[NetGeom<VS>::NIN_PAD / 16][4][64];
-    bf16x4 w2[4][4][64];
-    bf16x4 w3[4][64];
+    bf16x8 w1[NetGeom<VS>::K32][4][64];
+    bf16x8 w2[2][4][64];
+    bf16x8 w3[2][64];
     float b1[kHidden], b2[kHidden], b3[16];
 };
 
@@ -210,27 +250,28 @@ struct NetFrags {
 template <class VS>
 __device__ void stage_forward_weights(const float *__restrict__ P, NetFrags<VS> &F) {
     using G = NetGeom<VS>;
-    constexpr int K1 = G::NIN_PAD / 16;
+    constexpr int K32 = G::K32;
     const int tid = threadIdx.x, l = tid & 63, nt = (tid >> 6) & 3;
-    const int j = nt * 16 + (l & 15), r0 = 4 * (l >> 4);
-    float v1[K1][4], v2[4][4], v3[4][4];
+    const int j = nt * 16 + (l & 15), r8 = 8 * (l >> 4);
+    float v1[K32][8], v2[2][8], v3[8];
 #pragma unroll
-    for (int kk = 0; kk < K1; ++kk)
+    for (int kk = 0; kk < K32; ++kk)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int k = kk * 16 + r0 + e;
+        for (int e = 0; e < 8; ++e) {
+            const int k = kk * 32 + r8 + e;
             v1[kk][e] = k < G::NIN ? P[G::OFF_W1 + k * kHidden + j] : 0.0f;
         }
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
+    for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v2[kk][e] = P[G::OFF_W2 + (kk * 16 + r0 + e) * kHidden + j];
-    // W3 has one column tile: thread 64 nt + l takes k-block kk = nt
+        for (int e = 0; e < 8; ++e) v2[kk][e] = P[G::OFF_W2 + (kk * 32 + r8 + e) * kHidden + j];
+    // W3 has one column tile and two k-blocks: thread 64 nt + l takes k-block nt & 1 (stored by
+    // the threads with nt < 2)
     const int j3 = l & 15;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int k = nt * 16 + r0 + e;
-        v3[0][e] = j3 < G::NOUT ? P[G::OFF_W3 + k * G::NOUT + j3] : 0.0f;
+    for (int e = 0; e < 8; ++e) {
+        const int k = (nt & 1) * 32 + r8 + e;
+        v3[e] = j3 < G::NOUT ? P[G::OFF_W3 + k * G::NOUT + j3] : 0.0f;
     }
     float bias = 0.0f;
     if (tid < kHidden)
@@ -239,16 +280,17 @@ __device__ void stage_forward_weights(const float *__restrict__ P, NetFrags<VS> 
         bias = P[G::OFF_B2 + tid - kHidden];
     else if (tid < 2 * kHidden + 16)
         bias = tid - 2 * kHidden < G::NOUT ? P[G::OFF_B3 + tid - 2 * kHidden] : 0.0f;
-    auto pack = [](const float (&v)[4]) {
-        const bf16x4 b = {(short)bf16_bits(v[0]), (short)bf16_bits(v[1]), (short)bf16_bits(v[2]),
-                          (short)bf16_bits(v[3])};
+    auto pack8 = [](const float (&v)[8]) {
+        bf16x8 b;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) b[e] = (short)bf16_bits(v[e]);
         return b;
     };
 #pragma unroll
-    for (int kk = 0; kk < K1; ++kk) F.w1[kk][nt][l] = pack(v1[kk]);
+    for (int kk = 0; kk < K32; ++kk) F.w1[kk][nt][l] = pack8(v1[kk]);
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) F.w2[kk][nt][l] = pack(v2[kk]);
-    F.w3[nt][l] = pack(v3[0]);
+    for (int kk = 0; kk < 2; ++kk) F.w2[kk][nt][l] = pack8(v2[kk]);
+    if (nt < 2) F.w3[nt][l] = pack8(v3);
     if (tid < kHidden)
         F.b1[tid] = bias;
     else if (tid < 2 * kHidden)
@@ -267,7 +309,7 @@ __device__ floatx4 net_forward_tile_staged(const NetFrags<VS> &F, TT &T, int lan
     for (int nt = 0; nt < 4; ++nt) {
         floatx4 acc = {0, 0, 0, 0};
 #pragma unroll
-        for (int kk = 0; kk < G::NIN_PAD / 16; ++kk) acc = mfma16(a_rows(T.z, kk, lane), F.w1[kk][nt][lane], acc);
+        for (int kk = 0; kk < G::K32; ++kk) acc = mfma32(a_rows32(T.z, kk, lane), F.w1[kk][nt][lane], acc);
         const float bias = F.b1[nt * 16 + col];
 #pragma unroll
         for (int e = 0; e < 4; ++e) T.h1[row0 + e][nt * 16 + col] = bf16_bits(fmaxf(acc[e] + bias, 0.0f));
@@ -277,7 +319,7 @@ __device__ floatx4 net_forward_tile_staged(const NetFrags<VS> &F, TT &T, int lan
     for (int nt = 0; nt < 4; ++nt) {
         floatx4 acc = {0, 0, 0, 0};
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) acc = mfma16(a_rows(T.h1, kk, lane), F.w2[kk][nt][lane], acc);
+        for (int kk = 0; kk < 2; ++kk) acc = mfma32(a_rows32(T.h1, kk, lane), F.w2[kk][nt][lane], acc);
         const float bias = F.b2[nt * 16 + col];
 #pragma unroll
         for (int e = 0; e < 4; ++e) T.h2[row0 + e][nt * 16 + col] = bf16_bits(fmaxf(acc[e] + bias, 0.0f));
@@ -285,7 +327,7 @@ __device__ floatx4 net_forward_tile_staged(const NetFrags<VS> &F, TT &T, int lan
     wave_lds_sync();
     floatx4 acc = {0, 0, 0, 0};
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) acc = mfma16(a_rows(T.h2, kk, lane), F.w3[kk][lane], acc);
+    for (int kk = 0; kk < 2; ++kk) acc = mfma32(a_rows32(T.h2, kk, lane), F.w3[kk][lane], acc);
     const float bias = F.b3[col];
 #pragma unroll
     for (int e = 0; e < 4; ++e) acc[e] += bias;
@@ -295,7 +337,7 @@ __device__ floatx4 net_forward_tile_staged(const NetFrags<VS> &F, TT &T, int lan
 // Values of a tile per lane: v = g + 4 t (t < tile_vals) of row lane & 15, g = lane >> 4.
 template <class VS>
 constexpr int tile_vals() {
-    return (NetGeom<VS>::NIN_PAD + 3) / 4;
+    return (NetGeom<VS>::NIN_FILL + 3) / 4;
 }
 
 // Normalise a tile whose values are already in registers (vals, zero for rows >= nrows and
@@ -334,8 +376,11 @@ __device__ float normalise_tile(TT &T, int lane, float (&vals)[tile_vals<VS>()],
 #pragma unroll
     for (int t = 0; t < tile_vals<VS>(); ++t) {
         const int v = g + 4 * t;
-        if (v < G::NIN_PAD) T.z[r][v] = v < G::NIN ? bf16_bits(vals[t] * is) : (unsigned short)0;
+        if (v < G::NIN_FILL) T.z[r][v] = v < G::NIN ? bf16_bits(vals[t] * is) : (unsigned short)0;
     }
+    // the columns between NIN_FILL and NIN_PAD (another 16 where NIN_FILL is an odd multiple of 16)
+#pragma unroll
+    for (int t = 0; t < (G::NIN_PAD - G::NIN_FILL) / 4; ++t) T.z[r][G::NIN_FILL + g + 4 * t] = 0;
     wave_lds_sync();
     if (m_out) *m_out = m / pre;
     if (e_out) *e_out = ee;

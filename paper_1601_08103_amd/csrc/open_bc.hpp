@@ -497,7 +497,8 @@ struct Open2dTiles {
 template <class VS>
 struct Open2dShared {
     NetFrags<VS> F;
-    unsigned short zt[4][16][64], h1t[4][16][64];
+    alignas(16) unsigned short zt[4][16][64];  // 16-byte aligned rows: the network's 16-byte operand reads
+    alignas(16) unsigned short h1t[4][16][64];
     float pred[4][16][NetGeom<VS>::NOUT];
     float predp[4][16][VS::Q];  // limited predictions by population: the row's value for rank[face][i]
     int perm[4][VS::Q], rank[4][VS::Q];
