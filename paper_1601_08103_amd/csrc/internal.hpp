@@ -136,7 +136,7 @@ inline lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
     if ((double)d->n[1] * (double)d->n[2] * 16.0 > 4.0e9) return fail(LBM_E_INVALID, "too many rows (ny * nz)");
     if (!(d->tau >= 0.5) || !std::isfinite(d->tau)) return fail(LBM_E_INVALID, "tau must be finite and >= 1/2 (got %g)", d->tau);
     if (d->variant < LBM_VARIANT_AUTO || d->variant > LBM_VARIANT_OPEN2D) return fail(LBM_E_INVALID, "unknown variant %d", d->variant);
-    if (d->tune < 0 || d->tune > 255) return fail(LBM_E_INVALID, "unknown tune bits 0x%x", d->tune);
+    if (d->tune < 0 || d->tune > 511) return fail(LBM_E_INVALID, "unknown tune bits 0x%x", d->tune);
     if (d->variant == LBM_VARIANT_TB2 || d->variant == LBM_VARIANT_TB3) {
         const int K = d->variant == LBM_VARIANT_TB2 ? 2 : 3;
         if (d->bc != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "the %d-step variant needs the periodic box", K);

@@ -66,7 +66,7 @@ lbm_status step_lattice(lbm_lee *h, int64_t nsteps, hipStream_t st) {
             }
             nodes = ft.node_off[ft.nfaces];
             const long long tiles = (nodes + 15) / 16;
-            ghost_blocks = (unsigned)std::min<long long>((tiles + 3) / 4, 4096);
+            ghost_blocks = (tune & LBM_TUNE_NET_ONE_BLOCK) ? 1u : (unsigned)std::min<long long>((tiles + 3) / 4, 4096);
         }
         auto run = [&](auto skip, auto half) -> lbm_status {
             constexpr bool SK = decltype(skip)::value;

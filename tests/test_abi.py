@@ -75,7 +75,7 @@ def test_sizes(lattice, storage, shape, bpu):
     dict(lattice="D3Q7", storage="f16", shape=(8, 8, 8), store_scale=3.0),
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 6), variant="dpp"),
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 7), variant="dpp2"),
-    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), tune=256),
+    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), tune=512),
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), tune=32, bc="zero"),    # in place: periodic only
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), tune=32, variant="dpp"),  # in place: own kernels
     dict(lattice="D3Q7", storage="i16", shape=(8, 8, 8), store_scale=0.75),

@@ -429,3 +429,29 @@ def test_auto_takes_the_one_launch_open_step_up_to_8m_cells(shape, want):
     sim = lbm.Solver("D2Q9", "f32", shape, None, None, None, bc="zero")
     assert sim.variant == want
     sim.close()
+
+
+@pytest.mark.parametrize("name,shape,storage", [("D3Q7", (20, 20, 20), "f32"), ("D3Q7", (20, 20, 20), "f16"),
+                                                ("D3Q19", (8, 9, 12), "f32"), ("D1Q3", (40,), "f64")])
+def test_network_kernel_grid_stride_loop(name, shape, storage):
+    """The closure network's kernel on one block (LBM_TUNE_NET_ONE_BLOCK: its four waves walk every
+    tile of face nodes, the loop it takes on boxes of more than 262144 face nodes) gives the same
+    state and ghost values, bit for bit, as the kernel on its full grid."""
+    import torch
+    from paper_1601_08103_amd import lbm
+    lat = L.get(name)
+    say("network grid-stride loop", name, shape, storage)
+    params = mlp.flat(_small_params(lat, 7)).astype(np.float32)
+    g0 = _random_state(lat, shape, stable_seed(name, storage, "grid"))
+    sims = []
+    for tune in (0, lbm.TUNE["net_one_block"]):
+        sim = _solver(name, storage, shape, "mlp", tune=tune, **(dict(store_scale=_S16[storage]) if storage in _S16 else {}))
+        sim.set_closure(params)
+        sim.import_f64(g0)
+        sim.step(3)
+        sims.append(sim)
+    a, b = sims
+    assert torch.equal(a.export_f64(), b.export_f64())
+    assert torch.equal(a.ghost, b.ghost)
+    for sim in sims:
+        sim.close()
