@@ -257,7 +257,10 @@ def test_3d_workload_full_size_sampled(storage):
         errs.append(np.abs(u_gpu[(slice(None),) + cell] - u_or).max() / np.abs(u_gpu).max())
     worst = max(errs)
     say("3D sampled", storage, "worst rel err", worst)
-    bar = {"f64": 1e-12, "f32": 1e-5, "f16": 2e-3, "bf16": 2e-2, "i16": 2e-3, "e3m12": 1e-3}[storage]
+    # BF16 (8 significant bits) cannot meet 2e-3 even here: its bound is two unit roundoffs (2^-9)
+    # times the square root of the n roundings a stored value can have gone through
+    bar = {"f64": 1e-12, "f32": 1e-5, "f16": 2e-3, "bf16": 2 * 2.0 ** -9 * np.sqrt(n), "i16": 2e-3,
+           "e3m12": 1e-3}[storage]
     assert worst < bar
 
 
