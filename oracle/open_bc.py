@@ -17,7 +17,8 @@ Closures for a source s = x - c_i outside the box:
   "copy"    g*_i(clamp(s)) (zero normal gradient; clamp = nearest cell of the box),
   "sponge"  0, and after the collision g* <- (1 - sigma(d)) g* for cells at distance
             d = min_a min(x_a, n_a - 1 - x_a) < W from the faces, sigma(d) = sigma_max ((W-d)/W)^2,
-  "mlp"     a network prediction (below),
+  "mlp"     a network prediction (below); with a width W >= 1 given, the new post-collision
+            values are then damped as the sponge damps them (a network behind a sponge layer),
   "external" the value of a given outer state at s (a test device: with the state of a
             larger periodic run the open step must reproduce that run inside the box).
 
@@ -204,7 +205,8 @@ def step_open(lat: Lattice, g, closure: str, tau: float = 0.5, params: dict | No
               sponge_width: int = 0, sponge_sigma: float = 0.0, quantize: bool = False,
               limit: bool = True, g_prev=None) -> np.ndarray:
     """One step of the open-box scheme on the post-collision state g (Q, *shape); g_prev is the
-    state one step earlier (the network closure's second time level)."""
+    state one step earlier (the network closure's second time level).  sponge_width: the damped
+    layer of the "sponge" closure, and of the "mlp" closure when >= 1 (0: none)."""
     shape = g.shape[1:]
     D = lat.D
     pad = ghost_values(lat, g, closure, params, quantize, limit, g_prev)
@@ -218,7 +220,7 @@ def step_open(lat: Lattice, g, closure: str, tau: float = 0.5, params: dict | No
         pulled[i] = pad[(i,) + tuple(sl)]
     H = update_matrix(lat, tau)
     out = np.tensordot(H, pulled, axes=(1, 0))
-    if closure == "sponge":
+    if closure == "sponge" or (closure == "mlp" and sponge_width >= 1):
         out *= sponge_factor(shape, D, sponge_width, sponge_sigma)[None]
     return out
 

@@ -155,6 +155,36 @@ def test_network_closure_never_adds_energy(name):
     assert grew_without
 
 
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q7"])
+def test_network_behind_a_sponge_layer(name):
+    """The network closure with a sponge layer (width W >= 1).  A network that predicts nothing
+    (every weight zero) behind the layer is the sponge closure, bit for bit, over several steps;
+    with sigma 0 the layer changes nothing; with damping, a step of any network ends with no more
+    weighted energy than the same step without the layer, and with less whenever the layer holds
+    a wave."""
+    lat = L.get(name)
+    shape = {2: (11, 12), 3: (7, 8, 9)}[lat.D]
+    k = len(ob.incoming_canonical(lat))
+    rng = np.random.default_rng(41)
+    g = rng.standard_normal((lat.Q,) + shape) * lat.fstar.reshape((-1,) + (1,) * lat.D)
+    nothing = {n: np.zeros_like(v) for n, v in mlp.init_params(rng, 6 * lat.Q, k).items()}
+    a = ob.run_open(lat, g, 3, "mlp", params=nothing, sponge_width=3, sponge_sigma=0.4)
+    b = ob.run_open(lat, g, 3, "sponge", sponge_width=3, sponge_sigma=0.4)
+    assert np.array_equal(a, b)
+    p = mlp.init_params(rng, 6 * lat.Q, k)
+    p["b3"] = 0.1 * rng.standard_normal(k)
+    a = ob.run_open(lat, g, 3, "mlp", params=p, sponge_width=3, sponge_sigma=0.0)
+    b = ob.run_open(lat, g, 3, "mlp", params=p)
+    assert np.array_equal(a, b)
+    h = g
+    for _ in range(4):
+        damped = ob.step_open(lat, h, "mlp", params=p, sponge_width=3, sponge_sigma=0.4)
+        free = ob.step_open(lat, h, "mlp", params=p)
+        assert lbe.weighted_energy(lat, damped) < lbe.weighted_energy(lat, free)
+        assert not np.array_equal(damped, free)
+        h = damped
+
+
 def test_energy_limit_budget_by_face_count():
     """The limit scales a prediction to E_out / (2^n - 1) only when it exceeds that budget."""
     lat = L.get("D2Q9")
