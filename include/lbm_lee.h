@@ -112,7 +112,9 @@ typedef int32_t lbm_status;
  *           E_out / (2^n - 1), E_out the energy of p's populations leaving through that face and
  *           n the number of faces p lies on (scaled down, direction kept), so the energy that
  *           enters at p never exceeds the energy that leaves it: at tau = 1/2 the open box's
- *           weighted energy cannot grow, whatever the network predicts. */
+ *           weighted energy cannot grow, whatever the network predicts.  With sponge_width
+ *           W >= 1 the network closes a box whose outer W cells form a sponge layer: after the
+ *           collision the state is damped there as SPONGE damps it (W = 0: no layer). */
 #define LBM_BC_PERIODIC 0
 #define LBM_BC_ZERO 1
 #define LBM_BC_COPY 2
@@ -174,8 +176,9 @@ typedef struct lbm_lee_desc {
                          /* max |S g / f*| lies in [1/2, 1) (F16/BF16/E3M12) or [2^13, 2^14)*/
                          /* (I16); otherwise a power of two > 0.  Ignored for F64/F32.     */
     int32_t bc;          /* LBM_BC_*; open boxes need n[a] >= 3 on every axis a < D         */
-    int32_t sponge_width;/* LBM_BC_SPONGE: layer width W >= 1 in cells                      */
-    double sponge_sigma; /* LBM_BC_SPONGE: sigma_max in [0, 1]                              */
+    int32_t sponge_width;/* LBM_BC_SPONGE: layer width W >= 1 in cells; LBM_BC_MLP: W >= 0  */
+                         /* (a sponge layer behind the network, 0 = none); else ignored     */
+    double sponge_sigma; /* sigma_max in [0, 1] when there is a sponge layer                */
 } lbm_lee_desc;
 
 typedef struct lbm_lattice_info {

@@ -122,6 +122,12 @@ inline bool net_fits(const LatticeTable &t) {
     return (kHistory * 3 * t.Q + 31) / 32 * 32 <= 128 && k <= 16;  // as NetGeom::fits
 }
 
+// A damped layer along the faces: the sponge closure's, and the network closure's when it is
+// given a width (a network behind a sponge layer).
+inline bool sponge_layer(const lbm_lee_desc *d) {
+    return d->bc == LBM_BC_SPONGE || (d->bc == LBM_BC_MLP && d->sponge_width > 0);
+}
+
 inline lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
     if (!d) return fail(LBM_E_INVALID, "desc is NULL");
     if (!build_lattice(d->lattice, tab)) return fail(LBM_E_INVALID, "unknown lattice id %d", d->lattice);
@@ -168,10 +174,11 @@ inline lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
     if (d->bc == LBM_BC_MLP && !net_fits(*tab))
         return fail(LBM_E_UNSUPPORTED, "the closure network takes sets of up to 21 velocities (lattice %d has %d)",
                     d->lattice, tab->Q);
-    if (d->bc == LBM_BC_SPONGE) {
-        if (d->sponge_width < 1) return fail(LBM_E_INVALID, "sponge_width must be >= 1");
-        if (!(d->sponge_sigma >= 0.0 && d->sponge_sigma <= 1.0)) return fail(LBM_E_INVALID, "sponge_sigma must lie in [0, 1]");
-    }
+    if (d->bc == LBM_BC_SPONGE && d->sponge_width < 1) return fail(LBM_E_INVALID, "sponge_width must be >= 1");
+    if (d->bc == LBM_BC_MLP && d->sponge_width < 0)
+        return fail(LBM_E_INVALID, "sponge_width must be >= 0 with the network closure");
+    if (sponge_layer(d) && !(d->sponge_sigma >= 0.0 && d->sponge_sigma <= 1.0))
+        return fail(LBM_E_INVALID, "sponge_sigma must lie in [0, 1]");
     if (d->variant == LBM_VARIANT_DPP && d->n[0] % 4 != 0) return fail(LBM_E_UNSUPPORTED, "DPP variant needs nx %% 4 == 0");
     if (d->variant == LBM_VARIANT_DPP2 && d->n[0] % 2 != 0) return fail(LBM_E_UNSUPPORTED, "DPP2 variant needs nx %% 2 == 0");
     return LBM_OK;
@@ -331,8 +338,8 @@ FaceTab<VS::Q> face_table(const LatticeTable &t, const int64_t n[3]) {
 
 // The rest population (index 0, velocity 0) is invariant under the update for every tau when
 // the equilibrium map E = d g^eq / d g has E_00 = 1 and E_0j = E_j0 = 0: then
-// g_0* = (1 - 1/tau) g_0 + (1/tau) g_0 = g_0 and no moving population depends on g_0.  The
-// sponge damps every population, so it keeps the rest population in the update.
+// g_0* = (1 - 1/tau) g_0 + (1/tau) g_0 = g_0 and no moving population depends on g_0.  A
+// sponge layer damps every population, so it keeps the rest population in the update.
 inline bool rest_decoupled(const LatticeTable &t) {
     if (t.c[0][0] || t.c[0][1] || t.c[0][2]) return false;
     auto E = [&](int i, int j) {
@@ -349,7 +356,7 @@ inline bool rest_decoupled(const LatticeTable &t) {
 }
 
 inline bool skip_rest(const LatticeTable &t, const lbm_lee_desc *d) {
-    return rest_decoupled(t) && d->bc != LBM_BC_SPONGE && !(d->tune & LBM_TUNE_FULL_REST);
+    return rest_decoupled(t) && !sponge_layer(d) && !(d->tune & LBM_TUNE_FULL_REST);
 }
 
 inline int64_t face_node_count(const LatticeTable &t, const int64_t n[3]) {

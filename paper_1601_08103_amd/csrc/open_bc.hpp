@@ -511,7 +511,8 @@ __device__ void open2d_ring_mlp(Open2dShared<VS> &sh, const typename ST::elem *_
                                 typename ST::elem *__restrict__ dst, size_t N, const float *__restrict__ P,
                                 float *__restrict__ ghost, const float *__restrict__ hist_in,
                                 float *__restrict__ hist_out, const FaceTab<VS::Q> &ft,
-                                const StepCoef<typename ST::comp, VS::Q> &ks, const FieldCoef<VS::Q> &fk) {
+                                const StepCoef<typename ST::comp, VS::Q> &ks, const FieldCoef<VS::Q> &fk,
+                                int sponge_width, double sponge_sigma) {
     static_assert(NetGeom<VS>::fits, "network tiles");
     using G = NetGeom<VS>;
     using CT = typename ST::comp;
@@ -676,8 +677,14 @@ __device__ void open2d_ring_mlp(Open2dShared<VS> &sh, const typename ST::elem *_
     }
     collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(ks, s);
     const size_t cell = (size_t)xc[1] * nx + xc[0];
+    if (sponge_width > 0) {  // a sponge layer behind the network: ring cells lie at distance 0
+        const CT fac = sponge_factor<CT>(0, sponge_width, sponge_sigma);
 #pragma unroll
-    for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
+        for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = sponge_damp<ST>(ST::enc(s[i]), fac);
+    } else {
+#pragma unroll
+        for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
+    }
 }
 
 template <class VS, class ST, bool SKIP0, bool HALF, bool MLP>
@@ -692,11 +699,12 @@ __global__ __launch_bounds__(256) void open_step_2d(const typename ST::elem *__r
     using CT = typename ST::comp;
     static_assert(VS::D == 2, "2D sets only");
     const int nx = ft.n[0], ny = ft.n[1];
-    // SPONGE: each cell within sponge_width of a face is damped as the sponge kernel damps it,
-    // right after its new state is stored (same values: decode, scale, encode)
+    // A sponge layer (sponge_width > 0: the sponge closure, or a layer behind the network): each
+    // cell within sponge_width of a face is damped as the sponge kernel damps it, right after its
+    // new state is stored (same values: decode, scale, encode)
     auto store = [&](size_t cell, int x, int y, const CT (&s)[VS::Q], auto encode) {
         const int d = min(min(x, nx - 1 - x), min(y, ny - 1 - y));
-        if (!MLP && closure == kBcSponge && d < sponge_width) {
+        if (d < sponge_width) {
             const CT fac = sponge_factor<CT>(d, sponge_width, sponge_sigma);
 #pragma unroll
             for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = sponge_damp<ST>(encode(s[i]), fac);
@@ -709,9 +717,11 @@ __global__ __launch_bounds__(256) void open_step_2d(const typename ST::elem *__r
         if constexpr (MLP) {
             __shared__ Open2dShared<VS> sh;
             if (hist_in)
-                open2d_ring_mlp<VS, ST, SKIP0, HALF, true>(sh, src, dst, N, P, ghost, hist_in, hist_out, ft, ks, fk);
+                open2d_ring_mlp<VS, ST, SKIP0, HALF, true>(sh, src, dst, N, P, ghost, hist_in, hist_out, ft, ks, fk,
+                                                           sponge_width, sponge_sigma);
             else
-                open2d_ring_mlp<VS, ST, SKIP0, HALF, false>(sh, src, dst, N, P, ghost, hist_in, hist_out, ft, ks, fk);
+                open2d_ring_mlp<VS, ST, SKIP0, HALF, false>(sh, src, dst, N, P, ghost, hist_in, hist_out, ft, ks, fk,
+                                                            sponge_width, sponge_sigma);
         } else {
             const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
             if (c >= 2LL * ny + 2LL * (nx - 2)) return;

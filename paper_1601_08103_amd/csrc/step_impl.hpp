@@ -54,7 +54,7 @@ lbm_status step_lattice(lbm_lee *h, int64_t nsteps, hipStream_t st) {
                 if (cnt > mx) mx = cnt;
             }
             shell_x = (unsigned)((mx + 255) / 256);
-            if (bc == LBM_BC_SPONGE) {  // the largest slab: depth W times a full face
+            if (sponge_layer(&h->desc)) {  // the largest slab: depth W times a full face
                 long long big = 1;
                 for (int a = 0; a < VS::D; ++a) {
                     long long cnt = std::min<long long>(h->desc.sponge_width, h->desc.n[a]);
@@ -167,9 +167,10 @@ lbm_status step_lattice(lbm_lee *h, int64_t nsteps, hipStream_t st) {
                             float *hist = h->ghost + nodes * (long long)net_outputs(h->tab);
                             const float *hin = h->hist_valid ? hist + (long long)h->cur * nodes * nstrip : nullptr;
                             float *hout = hist + (long long)(h->cur ^ 1) * nodes * nstrip;
+                            // a sponge layer behind the network (width 0: none) is damped inside the step kernel
                             open_step_2d<VS, ST, SK, HF, true><<<face_blocks + bulk_blocks, 256, 0, st>>>(
-                                src, dst, h->N, bc, (int)face_blocks, h->net, h->ghost, hin, hout, ft, k, ks, fk, 0,
-                                0.0);
+                                src, dst, h->N, bc, (int)face_blocks, h->net, h->ghost, hin, hout, ft, k, ks, fk,
+                                h->desc.sponge_width, h->desc.sponge_sigma);
                             h->hist_valid = true;
                         } else {
                             // the sponge layer is damped inside the step kernel
@@ -234,7 +235,7 @@ lbm_status step_lattice(lbm_lee *h, int64_t nsteps, hipStream_t st) {
                 if (bc != LBM_BC_PERIODIC) {
                     shell_kernel<VS, ST, SK, HF><<<dim3(shell_x, 2 * VS::D), 256, 0, st>>>(src, dst, h->N, bc, h->ghost,
                                                                                       ft, ks, fk);
-                    if (bc == LBM_BC_SPONGE)
+                    if (sponge_layer(&h->desc))
                         sponge_kernel<VS, ST><<<dim3(sponge_x, 2 * VS::D), 256, 0, st>>>(
                             dst, h->N, h->nx, h->ny, h->nz, h->desc.sponge_width, h->desc.sponge_sigma);
                 }

@@ -9,7 +9,8 @@ state in its centre and zero elsewhere; inside the box it is exact for n <= E - 
 signal travels faster than one cell per step).  The reflection coefficient of a closure is
     R = max_t ||p'_bc(t) - p'_ext(t)||_2,box / max_t ||p'_ext(t)||_2,box,   t every 8 steps.
 The sponge baseline runs on a box widened by its layer (L + 2W per axis, the layer outside the
-compared L^D region), so its damping is not counted as error inside the box.
+compared L^D region), so its damping is not counted as error inside the box; so does the network
+behind a sponge layer ("mlp_sponge": the network closes the widened box, the layer damps).
 Training pairs come from the same judge runs: the strips at each face node now and one step
 earlier, and the true entering populations at its outside neighbour.
 """
@@ -277,22 +278,25 @@ def judge_reference(lattice, fields, L=512, E=1536, steps=1024, every=8, ext_sto
 
 def reflection_vs(lattice, closure, fields, ref, L=512, steps=1024, every=8, params=None, storage="f32",
                   sponge_width=32, sponge_sigma=0.2, slices=False):
-    """R of one closure on one initial state against a judge reference from judge_reference."""
+    """R of one closure on one initial state against a judge reference from judge_reference.
+    closure: zero, copy, sponge, mlp, or mlp_sponge (the network behind a sponge layer)."""
     import torch
     info = lbm.lbm_lee_lattice_info(lattice)
     D = info["D"]
-    W = sponge_width if closure == "sponge" else 0
-    kw = dict(sponge_width=sponge_width, sponge_sigma=sponge_sigma) if closure == "sponge" else {}
+    layered = closure in ("sponge", "mlp_sponge")
+    bc = "mlp" if closure == "mlp_sponge" else closure
+    W = sponge_width if layered else 0
+    kw = dict(sponge_width=sponge_width, sponge_sigma=sponge_sigma) if layered else {}
     nb = L + 2 * W
     if W == 0:  # the library picks the 16-bit storage scale from the fields
-        box = lbm.Solver(lattice, storage, (L,) * D, *fields, bc=closure, **kw)
+        box = lbm.Solver(lattice, storage, (L,) * D, *fields, bc=bc, **kw)
     else:  # the sponge layer lies outside the fields: take the scale the box alone would get
         probe = lbm.Solver(lattice, storage, (L,) * D, *fields)
         scale = probe.store_scale if lbm.ELEM_BYTES[storage] == 2 else 0.0
         probe.close()
-        box = lbm.Solver(lattice, storage, (nb,) * D, None, None, None, bc=closure, store_scale=scale, **kw)
+        box = lbm.Solver(lattice, storage, (nb,) * D, None, None, None, bc=bc, store_scale=scale, **kw)
         box.reinit_region([W] * D, (L,) * D, *fields)
-    if closure == "mlp":
+    if bc == "mlp":
         box.set_closure(params)
     st = torch.cuda.current_stream().cuda_stream
     regions = _regions(L, D, slices)
@@ -394,22 +398,30 @@ def main(argv=None):
     ap.add_argument("--storage", default="f32", help="storage of the open box (evaluate)")
     ap.add_argument("--ext-storage", default="f32", help="storage of the judge run")
     ap.add_argument("--slices", action="store_true", help="compare on the mid-planes only (evaluate)")
-    ap.add_argument("--closures", default="zero,copy,sponge,mlp")
+    ap.add_argument("--closures", default="zero,copy,sponge,mlp",
+                    help="zero, copy, sponge, mlp, mlp_sponge (the network behind a sponge layer)")
     ap.add_argument("--weights", default=None, help="weights file (.npy) to write (train) or read (evaluate)")
     ap.add_argument("--seeds", type=int, default=32, help="held-out initial states for evaluate")
     ap.add_argument("--sponge-width", default="32",
                     help="layer width; a comma-separated list evaluates one sponge per width (evaluate)")
     ap.add_argument("--sponge-sigma", default="0.2", help="damping rate, or one per width")
+    ap.add_argument("--mlp-sponge-width", default="8", help="layer width(s) behind the network (mlp_sponge)")
+    ap.add_argument("--mlp-sponge-sigma", default="0.1", help="damping rate, or one per width (mlp_sponge)")
     ap.add_argument("--dagger", type=int, default=0, help="rounds of closed-loop data + further training")
     ap.add_argument("--dagger-runs", type=int, default=100)
     ap.add_argument("--dagger-epochs", type=int, default=2)
     args = ap.parse_args(argv)
-    widths = [int(w) for w in str(args.sponge_width).split(",")]
-    sigmas = [float(x) for x in str(args.sponge_sigma).split(",")]
-    if len(sigmas) == 1:
-        sigmas = sigmas * len(widths)
-    if len(sigmas) != len(widths):
-        ap.error("--sponge-sigma: one value, or one per width")
+    def layers(wtext, stext, flag):
+        ws = [int(w) for w in str(wtext).split(",")]
+        gs = [float(x) for x in str(stext).split(",")]
+        if len(gs) == 1:
+            gs = gs * len(ws)
+        if len(gs) != len(ws):
+            ap.error(f"{flag}: one value, or one per width")
+        return ws, gs
+
+    widths, sigmas = layers(args.sponge_width, args.sponge_sigma, "--sponge-sigma")
+    mwidths, msigmas = layers(args.mlp_sponge_width, args.mlp_sponge_sigma, "--mlp-sponge-sigma")
     args.sponge_width, args.sponge_sigma = widths[0], sigmas[0]
     torch.cuda.set_device(0)
     lbm.load()
@@ -434,11 +446,16 @@ def main(argv=None):
         return
     P = np.load(args.weights, allow_pickle=False) if args.weights else None
     rng = np.random.default_rng(10_000 + args.seed)  # held out: training uses seeds below 10000
-    closures = [c for c in args.closures.split(",") if c and (c != "mlp" or P is not None)]
-    # every sponge is (name, width, sigma); a single one keeps the name "sponge"
-    sponges = {"sponge": (widths[0], sigmas[0])} if len(widths) == 1 else {
-        f"sponge_W{w}_s{g:g}": (w, g) for w, g in zip(widths, sigmas)}
-    closures = [n for c in closures for n in (sponges if c == "sponge" else [c])]
+    closures = [c for c in args.closures.split(",") if c and (c not in ("mlp", "mlp_sponge") or P is not None)]
+
+    # every layered closure is name -> (width, sigma); a single one keeps the closure's name
+    def named(base, ws, gs):
+        return {base: (ws[0], gs[0])} if len(ws) == 1 else {f"{base}_W{w}_s{g:g}": (w, g) for w, g in zip(ws, gs)}
+
+    layered = {"sponge": named("sponge", widths, sigmas), "mlp_sponge": named("mlp_sponge", mwidths, msigmas)}
+    kinds = {n: c for c in closures for n in layered.get(c, [c])}  # name -> closure
+    sponges = {n: wg for c in closures for n, wg in layered.get(c, {}).items()}
+    closures = list(kinds)
     Rs = {c: [] for c in closures}
     ext = judge_solver(args.lattice, args.ext_storage, args.E, D)
     first = None
@@ -448,9 +465,8 @@ def main(argv=None):
         ref = judge_reference(args.lattice, fields, args.L, args.E, args.steps, args.every, args.ext_storage, ext,
                               args.slices)
         for c in closures:
-            kind = "sponge" if c in sponges else c
             w, g = sponges.get(c, (0, 0.0))
-            Rs[c].append(reflection_vs(args.lattice, kind, fields, ref, args.L, args.steps, args.every, params=P,
+            Rs[c].append(reflection_vs(args.lattice, kinds[c], fields, ref, args.L, args.steps, args.every, params=P,
                                        storage=args.storage, sponge_width=w, sponge_sigma=g, slices=args.slices))
         del ref
         log(f"evaluate: seed {k + 1}/{args.seeds}: " + ", ".join(f"{c} {Rs[c][-1]:.4f}" for c in closures))
@@ -461,9 +477,9 @@ def main(argv=None):
     del ext
     # step times on live data: every box starts from the first held-out state
     for c in closures:
-        kind = "sponge" if c in sponges else c
+        kind = "mlp" if kinds[c] == "mlp_sponge" else kinds[c]
         W, g = sponges.get(c, (0, 0.0))
-        kw = dict(sponge_width=W, sponge_sigma=g) if kind == "sponge" else {}
+        kw = dict(sponge_width=W, sponge_sigma=g) if c in sponges else {}
         live = dict(fields=first, origin=[W] * D if W else None)
         nb = args.L + 2 * W
         times[c] = time_per_step(args.lattice, (nb,) * D, bc=kind, params=P, storage=args.storage, **live, **kw)

@@ -176,7 +176,10 @@ def test_face_node_count_and_ghost_bytes(name, shape):
     dict(lattice="D2Q9", storage="f32", shape=(8, 8), bc="periodic"),
 ])
 def test_good_boundary_descriptors(kw):
-    for bc, extra in (("zero", {}), ("copy", {}), ("sponge", dict(sponge_width=3, sponge_sigma=0.5)), ("mlp", {})):
+    for bc, extra in (("zero", {}), ("copy", {}), ("sponge", dict(sponge_width=3, sponge_sigma=0.5)), ("mlp", {}),
+                      ("mlp", dict(sponge_width=3, sponge_sigma=0.5)),  # a network behind a sponge layer
+                      ("mlp", dict(sponge_width=0, sponge_sigma=7.0)),  # no layer: sigma is not read
+                      ("zero", dict(sponge_width=-4, sponge_sigma=7.0))):  # only the sponge and network read them
         k = dict(kw, bc=bc, **extra)
         assert lbm.lbm_lee_state_bytes(lbm.make_desc(**k)) > 0
 
@@ -185,6 +188,8 @@ def test_good_boundary_descriptors(kw):
     dict(lattice="D2Q9", storage="f32", shape=(8, 2), bc="zero"),
     dict(lattice="D2Q9", storage="f32", shape=(8, 8), bc="sponge", sponge_width=0, sponge_sigma=0.5),
     dict(lattice="D2Q9", storage="f32", shape=(8, 8), bc="sponge", sponge_width=3, sponge_sigma=1.5),
+    dict(lattice="D2Q9", storage="f32", shape=(8, 8), bc="mlp", sponge_width=-1, sponge_sigma=0.5),
+    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), bc="mlp", sponge_width=3, sponge_sigma=-0.5),
 ])
 def test_bad_boundary_descriptors(kw):
     assert lbm.lbm_lee_state_bytes(lbm.make_desc(**kw)) == 0

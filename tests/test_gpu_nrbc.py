@@ -117,3 +117,59 @@ def test_evaluate_compares_several_sponges_per_judge_run(capsys):
     for c, r in out["R_mean"].items():
         assert np.isfinite(r) and r > 0, (c, r)
     assert out["ms_per_step"]["sponge_W4_s0.3"] > 0
+
+
+def test_3d_open_box_full_size():
+    """The 3D open-box workload at its full size and in its launch configuration: a 384^3 D3Q7 box
+    with FP16 storage and the shipped network on all six faces (AUTO: the DPP bulk step, the
+    boundary recompute and the network kernel), one held-out state (pulses or a packet), 1000
+    steps, judged on the mid-planes against the 1384^3 FP32 periodic run (the first held-out state
+    of the evaluate command): the network reflects less than half what the zero closure does, and
+    the box steps faster than the judge."""
+    import os
+    import torch
+    from paper_1601_08103_amd import lbm, nrbc
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1601_08103_amd",
+                        "weights", "nrbc_D3Q7.npy")
+    P = np.load(path, allow_pickle=False)
+    info = lbm.lbm_lee_lattice_info("D3Q7")
+    L, E, steps, every = 384, 1384, 1000, 50
+    rng = np.random.default_rng(10_000)
+    fields = nrbc.initial_fields("mixed", rng, info, L, 3)
+    say("3D open box, full size: judge")
+    ext = nrbc.judge_solver("D3Q7", "f32", E, 3)
+    ref = nrbc.judge_reference("D3Q7", fields, L, E, steps, every, "f32", ext, True)
+    t_judge = nrbc.time_solver(ext, 12)
+    ext.close()
+    del ext
+    R = {}
+    for c in ("zero", "mlp"):
+        say("3D open box, full size:", c)
+        R[c] = nrbc.reflection_vs("D3Q7", c, fields, ref, L, steps, every, params=P, storage="f16", slices=True)
+    t_mlp = nrbc.time_per_step("D3Q7", (L,) * 3, bc="mlp", params=P, storage="f16", steps=24, fields=fields)
+    say("3D open box, full size:", R, "ms/step network", t_mlp, "judge", t_judge)
+    del ref
+    torch.cuda.empty_cache()
+    assert np.isfinite(R["mlp"]) and R["mlp"] < 0.5 * R["zero"]
+    assert t_mlp < t_judge
+
+
+def test_evaluate_network_behind_sponge_layers(capsys):
+    """nrbc evaluate with mlp_sponge: one network-behind-a-layer closure per layer width, each on
+    its own widened box, from the same judge runs as the plain network; with sigma 0 the layer
+    only widens the box, and the compared region sees the plain network's closure farther out."""
+    import json
+    import os
+    from paper_1601_08103_amd import nrbc
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1601_08103_amd",
+                        "weights", "nrbc_D2Q9.npy")
+    say("evaluate the network behind sponge layers")
+    nrbc.main(["evaluate", "--lattice", "D2Q9", "--L", "24", "--E", "72", "--steps", "32", "--every", "8",
+               "--seeds", "2", "--closures", "mlp,mlp_sponge", "--weights", path,
+               "--mlp-sponge-width", "2,4", "--mlp-sponge-sigma", "0.2,0.0"])
+    out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert set(out["R_mean"]) == {"mlp", "mlp_sponge_W2_s0.2", "mlp_sponge_W4_s0"}
+    assert out["sponges"]["mlp_sponge_W2_s0.2"] == {"width": 2, "sigma": 0.2}
+    for c, r in out["R_mean"].items():
+        assert np.isfinite(r) and r > 0, (c, r)
+        assert out["ms_per_step"][c] > 0

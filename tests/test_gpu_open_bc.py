@@ -124,6 +124,30 @@ def test_network_closure_step_matches_oracle(name, storage):
     sim.close()
 
 
+@pytest.mark.parametrize("name", ["D2Q9", "D2Q5", "D3Q7", "D3Q19", "D1Q3"])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_network_behind_a_sponge_layer_matches_oracle(name, storage):
+    """The network closure with a sponge layer (W = 3, sigma 0.4) against the oracle, 3 steps, on
+    boxes where the layer covers most cells (so a missing or misplaced damping shows)."""
+    lat = L.get(name)
+    shape = {1: (23,), 2: (14, 17), 3: (8, 9, 11)}[lat.D]
+    say("mlp closure behind a sponge", name, storage)
+    params = _small_params(lat, 3)
+    sim = _solver(name, storage, shape, "mlp", sponge_width=3, sponge_sigma=0.4)
+    sim.set_closure(mlp.flat(params).astype(np.float32))
+    sim.import_f64(_random_state(lat, shape, 19))
+    g = sim.export_f64().cpu().numpy()
+    sim.step(3)
+    got = sim.export_f64().cpu().numpy()
+    sim.close()
+    p32 = mlp.unflat(mlp.flat(params).astype(np.float32).astype(np.float64), 6 * lat.Q, len(ob.incoming_canonical(lat)))
+    want = ob.run_open(lat, g, 3, "mlp", params=p32, quantize=True, sponge_width=3, sponge_sigma=0.4)
+    free = ob.run_open(lat, g, 3, "mlp", params=p32, quantize=True)
+    err = rel_l2(got, want)
+    say("mlp closure behind a sponge", name, storage, "rel L2", err, "against the undamped closure", rel_l2(free, want))
+    assert err < 2e-3 and rel_l2(free, want) > 0.1
+
+
 def test_network_closure_never_adds_energy_on_gpu():
     """The energy limit on the GPU: a network with large biases, random state, tau = 1/2: the
     weighted energy of the open box never grows (FP64 storage, per step)."""
@@ -350,18 +374,19 @@ def test_captured_graph_replays_match_eager_steps(case):
 
 
 @pytest.mark.parametrize("name", ["D2Q9", "D2Q5", "D2Q5_DIA"])
-@pytest.mark.parametrize("bc", ["zero", "copy", "sponge", "mlp"])
+@pytest.mark.parametrize("bc", ["zero", "copy", "sponge", "mlp", "mlp_sponge"])
 @pytest.mark.parametrize("storage", ["f32", "f16", "f64", "e3m12", "bf16", "i16"])
 def test_one_launch_open_step_matches_separate_kernels(name, bc, storage):
     """The one-launch 2D open step (ring, interior and closure network in one kernel) gives the
     same state, bit for bit, as the separate network, bulk and boundary kernels, after each of
     several steps, on the smallest box, boxes whose faces span several network segments with
     ragged ends, and at two relaxation times; with the network also the same ghost values and
-    history strips."""
+    history strips.  mlp_sponge: the network behind a sponge layer."""
     import torch
     from paper_1601_08103_amd import lbm
     lat = L.get(name)
-    kw = dict(sponge_width=3, sponge_sigma=0.4) if bc == "sponge" else {}
+    kw = dict(sponge_width=3, sponge_sigma=0.4) if bc in ("sponge", "mlp_sponge") else {}
+    bc = "mlp" if bc == "mlp_sponge" else bc
     params = mlp.flat(_small_params(lat, 4)).astype(np.float32)
     for shape, tau in (((3, 3), 0.5), ((14, 17), 0.5), ((37, 23), 0.8), ((130, 67), 0.5)):
         say("one-launch open step", name, bc, storage, shape, tau)
@@ -386,7 +411,8 @@ def test_one_launch_open_step_matches_separate_kernels(name, bc, storage):
             sim.close()
 
 
-@pytest.mark.parametrize("bc,storage", [("mlp", "f32"), ("mlp", "f16"), ("sponge", "f32"), ("zero", "e3m12")])
+@pytest.mark.parametrize("bc,storage", [("mlp", "f32"), ("mlp", "f16"), ("sponge", "f32"), ("zero", "e3m12"),
+                                        ("mlp_sponge", "f32")])
 def test_one_launch_open_step_full_size(bc, storage):
     """The learned-closure workload's box (D2Q9 512^2) with the shipped weights: the one-launch step
     equals the separate kernels bit for bit over 6 steps from a seeded pulse state."""
@@ -394,7 +420,9 @@ def test_one_launch_open_step_full_size(bc, storage):
     from paper_1601_08103_amd import lbm
     lat = L.get("D2Q9")
     shape = (512, 512)
-    kw = dict(sponge_width=96, sponge_sigma=0.03) if bc == "sponge" else {}
+    kw = {"sponge": dict(sponge_width=96, sponge_sigma=0.03),
+          "mlp_sponge": dict(sponge_width=16, sponge_sigma=0.1)}.get(bc, {})
+    bc = "mlp" if bc == "mlp_sponge" else bc
     path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1601_08103_amd",
                         "weights", "nrbc_D2Q9.npy")
     params = np.load(path, allow_pickle=False).astype(np.float32)
