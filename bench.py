@@ -8,7 +8,8 @@ relaxation pass over all cells.  The initial state is resident in HBM before tim
 Besides the FP32 headline the line reports every storage mode with its error against the FP64
 path, the roofline of the step kernel, the FP64 CPU oracle as a baseline, and the learned
 non-reflecting closure on its 2D open-box workload (reflection coefficient and step time
-against the zero and sponge closures and the wider periodic run).
+against the zero and sponge closures and the wider periodic run) and the step times of its 3D
+open-box workload.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -48,9 +49,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=24.0,
                     help="budget of the oracle CPU baseline (half on one thread, half on all cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-nrbc", action="store_true", help="skip the learned-closure leg")
+    ap.add_argument("--no-nrbc", action="store_true", help="skip the learned-closure legs (2D and 3D)")
     ap.add_argument("--closure-only", action="store_true",
                     help="only the learned-closure leg (for rocprofv3); its result on stdout")
+    ap.add_argument("--closure3d-only", action="store_true",
+                    help="only the 3D learned-closure step times (for rocprofv3); its result on stdout")
     ap.add_argument("--profile-only", action="store_true", help="only the timed steps of --storage (for rocprofv3)")
     ap.add_argument("--with-copy", action="store_true",
                     help="with --profile-only: also run the plain copy kernel on one state buffer's bytes "
@@ -135,6 +138,42 @@ def nrbc_leg():
                R_max={c: round(float(np.max(v)), 5) for c, v in R.items()}, ms_per_step=times)
     log("nrbc", out)
     return out
+
+
+def nrbc3d_leg():
+    """Step times of the 3D learned-closure workload: D3Q7 384^3 open boxes with FP16 storage, the
+    zero closure and the network on all six faces (shipped weights), each started from the first
+    held-out state (Gaussian pulses or a wave packet), next to the 1384^3 FP32 periodic judge that
+    holds the same state in its centre.  Eager launches and graph replays.  (The reflection
+    coefficients take ten seconds of judge per state and are left to `nrbc evaluate`.)"""
+
+    import torch
+
+    from paper_1601_08103_amd import lbm, nrbc
+
+    path = os.path.join(ROOT, "paper_1601_08103_amd", "weights", "nrbc_D3Q7.npy")
+    if not os.path.exists(path):
+        return None
+    P = np.load(path, allow_pickle=False)
+    L, E = 384, 1384
+    info = lbm.lbm_lee_lattice_info("D3Q7")
+    fields = nrbc.initial_fields("mixed", np.random.default_rng(10_000), info, L, 3)
+    ext = nrbc.judge_solver("D3Q7", "f32", E, 3)
+    ext.reinit_region([(E - L) // 2] * 3, (L,) * 3, *fields)
+    times = {"extended_periodic": round(nrbc.time_solver(ext, 24), 4)}
+    graph = {"extended_periodic": round(nrbc.time_solver(ext, 24, graph=True), 4)}
+    ext.close()
+    del ext
+    torch.cuda.empty_cache()
+    for c in ("zero", "mlp"):
+        for out, g in ((times, False), (graph, True)):
+            out[c] = round(nrbc.time_per_step("D3Q7", (L,) * 3, bc=c, params=P, storage="f16", steps=120, graph=g,
+                                              fields=fields), 4)
+    res = dict(workload=f"3D open box D3Q7 {L}^3 FP16 storage, network on all six faces; judge {E}^3 FP32 "
+                        "periodic; first held-out state", weights="paper_1601_08103_amd/weights/nrbc_D3Q7.npy",
+               ms_per_step=times, ms_per_step_graph=graph)
+    log("nrbc3d", res)
+    return res
 
 
 def host_cpu():
@@ -222,6 +261,9 @@ def main():
     torch.cuda.set_device(0)
     if args.closure_only:
         print(json.dumps(nrbc_leg()))
+        return
+    if args.closure3d_only:
+        print(json.dumps(nrbc3d_leg()))
         return
     n = args.n
     shape = (n, n, n)
@@ -385,6 +427,7 @@ def main():
                     frac_of_copy=round(achieved / copy_gbs, 4), copy_GBs=round(copy_gbs, 1))
 
     nrbc_result = None if args.no_nrbc else nrbc_leg()
+    nrbc3d_result = None if args.no_nrbc else nrbc3d_leg()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -416,6 +459,7 @@ def main():
         "storage_modes": storage_modes,
         "error_reference": "GPU FP64 path (parity with the FP64 oracle <= 1e-12 in the test suite)",
         "learned_closure": nrbc_result,
+        "learned_closure_3d": nrbc3d_result,
     }
     print(json.dumps(line), flush=True)
 

@@ -302,13 +302,20 @@ __device__ __forceinline__ void load_chunk(const typename ST::elem *__restrict__
     }
 }
 
+// Row ends of a periodic box: the x-neighbour beyond one end of a row is the cell at the other.
+// An open box's bulk step passes its own EDGE whose value() gives what is pulled from beyond an
+// x face instead.
+struct WrapEdge {
+    static constexpr bool open = false;
+};
+
 // Decode a loaded chunk, move the x-neighbours across lanes, collide and store.
-template <class VS, class ST, int VEC, bool FULLROW, bool SKIP0, bool HALF>
+template <class VS, class ST, int VEC, bool FULLROW, bool SKIP0, bool HALF, class EDGE = WrapEdge>
 __device__ __forceinline__ void finish_chunk(const typename ST::elem *__restrict__ src,
                                              typename ST::elem *__restrict__ dst, int nx, int ny, int nz, size_t N,
                                              unsigned row, int chunk, int lane, bool nts,
                                              const StepCoef<typename ST::comp, VS::Q> &k,
-                                             const ChunkRaw<VS, ST, VEC> &r) {
+                                             const ChunkRaw<VS, ST, VEC> &r, const EDGE &edge = EDGE{}) {
     using CT = typename ST::comp;
     using E = typename ST::elem;
     constexpr bool RAW = ST::has_raw;
@@ -335,13 +342,21 @@ __device__ __forceinline__ void finish_chunk(const typename ST::elem *__restrict
             const E *rowp = src + (size_t)i * N + ((size_t)zs * ny + ys) * (size_t)nx;
             if (VS::cx(i) > 0) {
                 CT prev = FULLROW ? dpp_move<kDppWaveRor1>(v[VEC - 1]) : dpp_move<kDppWaveShr1>(v[VEC - 1]);
-                if (!FULLROW && lane == 0) prev = dec_io<ST, RAW>(rowp[x0 == 0 ? nx - 1 : x0 - 1]);
+                if (!FULLROW && lane == 0 && !(EDGE::open && x0 == 0))
+                    prev = dec_io<ST, RAW>(rowp[x0 == 0 ? nx - 1 : x0 - 1]);
+                if constexpr (EDGE::open) {
+                    if (x0 == 0) prev = edge.template value<VS, ST, RAW>(0, i, ys, zs, v[0]);
+                }
                 s[i][0] = prev;
 #pragma unroll
                 for (int q = 1; q < VEC; ++q) s[i][q] = v[q - 1];
             } else {
                 CT next = FULLROW ? dpp_move<kDppWaveRol1>(v[0]) : dpp_move<kDppWaveShl1>(v[0]);
-                if (!FULLROW && last && active) next = dec_io<ST, RAW>(rowp[x0 + VEC >= nx ? 0 : x0 + VEC]);
+                if (!FULLROW && last && active && !(EDGE::open && x0 + VEC >= nx))
+                    next = dec_io<ST, RAW>(rowp[x0 + VEC >= nx ? 0 : x0 + VEC]);
+                if constexpr (EDGE::open) {
+                    if (active && x0 + VEC >= nx) next = edge.template value<VS, ST, RAW>(1, i, ys, zs, v[VEC - 1]);
+                }
 #pragma unroll
                 for (int q = 0; q < VEC - 1; ++q) s[i][q] = v[q + 1];
                 s[i][VEC - 1] = next;

@@ -160,18 +160,24 @@ __device__ inline void shell_outside(const int (&x)[3], const int (&n)[3], typen
     }
 }
 
+// Grid (x blocks, one y block per face).  bulk_x: the bulk step (step_dpp_open) has already
+// computed the x faces' cells of every row that lies on no y or z face; the grid then covers the
+// y and z faces only (blockIdx.y + 2), which own their cells on the x faces.
 template <class VS, class ST, bool SKIP0, bool HALF = false>
 __global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__restrict__ src,
                                                     typename ST::elem *__restrict__ dst, size_t N, int closure,
                                                     const float *__restrict__ ghost, FaceTab<VS::Q> ft,
-                                                    StepCoef<typename ST::comp, VS::Q> k, FieldCoef<VS::Q> fk) {
+                                                    StepCoef<typename ST::comp, VS::Q> k, FieldCoef<VS::Q> fk,
+                                                    int bulk_x) {
     using CT = typename ST::comp;
-    const int f = blockIdx.y;
+    const int f = (int)blockIdx.y + (bulk_x ? 2 : 0);
     const int a = f >> 1, side = f & 1;
     int t1, t2;
     infaces(a, VS::D, t1, t2);
-    // cells of this face not already owned by a face of a lower axis
-    const int lo1 = (t1 >= 0 && t1 < a) ? 1 : 0, lo2 = (t2 >= 0 && t2 < a) ? 1 : 0;
+    // cells of this face not already owned by a face of a lower axis (with bulk_x the x faces own
+    // none: their rows off the other faces are the bulk step's)
+    const int lo1 = (t1 >= 0 && t1 < a && !(bulk_x && t1 == 0)) ? 1 : 0;
+    const int lo2 = (t2 >= 0 && t2 < a && !(bulk_x && t2 == 0)) ? 1 : 0;
     const int n1 = t1 >= 0 ? ft.n[t1] - 2 * lo1 : 1, n2 = t2 >= 0 ? ft.n[t2] - 2 * lo2 : 1;
     const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
     if (t >= (long long)n1 * n2) return;
@@ -206,6 +212,68 @@ __global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__r
     collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, s);
 #pragma unroll
     for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
+}
+
+// ------------------------------------------------------------------ bulk step of an open box
+// The one-step DPP bulk kernel with the x faces closed in the bulk step itself: where a row's
+// end cell pulls from beyond an x face (population i with c_x = +1 at x = 0, c_x = -1 at
+// x = nx - 1), it takes the closure's value there instead of the other end of the row: 0 for
+// ZERO and SPONGE, the row's end cell itself for COPY (the clamped source), and for MLP the face
+// node's prediction in stored units, the value shell_outside forms for a source beyond one face.
+// Rows on a y or z face pull from beyond those faces too; the shell kernel recomputes them.  So
+// the x faces, whose cells are strided in memory, cost no second pass.
+template <int Q>
+struct OpenEdge {
+    static constexpr bool open = true;
+    int closure;
+    const float *ghost;
+    const FaceTab<Q> &ft;
+    const FieldCoef<Q> &fk;
+    // side 0: the low x face (sources at x = -1), 1: the high one; (ys, zs) the source row
+    template <class VS, class ST, bool RAW>
+    __device__ typename ST::comp value(int side, int i, int ys, int zs, typename ST::comp own) const {
+        using CT = typename ST::comp;
+        if (closure == kBcCopy) return own;
+        if (closure != kBcMlp) return (CT)0;
+        const int p[3] = {side ? ft.n[0] - 1 : 0, ys, zs};
+        const int r = ft.rank[side][i];
+        CT v = (CT)ghost[node_index(ft, side, p) * entering_count<VS>() + (r < 0 ? 0 : r)] * (CT)fk.enc[i];
+        if constexpr (RAW) v *= (CT)ST::raw_unit;
+        return v;
+    }
+};
+
+// Same chunk walk as step_dpp (including the persistent tuning).
+template <class VS, class ST, int VEC, bool FULLROW, bool SKIP0, bool HALF = false>
+__global__ __launch_bounds__(256) void step_dpp_open(const typename ST::elem *__restrict__ src,
+                                                     typename ST::elem *__restrict__ dst, int nx, int ny, int nz,
+                                                     size_t N, int chunks_per_row, unsigned total_waves, unsigned tune,
+                                                     StepCoef<typename ST::comp, VS::Q> k, int closure,
+                                                     const float *__restrict__ ghost, FaceTab<VS::Q> ft,
+                                                     FieldCoef<VS::Q> fk) {
+    const int lane = threadIdx.x & 63;
+    const unsigned wid = (unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool ntl = (tune & kTuneNtLoad) != 0, nts = (tune & kTuneNtStore) != 0;
+    const unsigned G = gridDim.x * 4u;
+    unsigned wave = blockIdx.x * 4u + wid;
+    if (wave >= total_waves) return;
+    const OpenEdge<VS::Q> edge{closure, ghost, ft, fk};
+    ChunkRaw<VS, ST, VEC> cur, nxt;
+    load_chunk<VS, ST, VEC, SKIP0>(src, nx, ny, nz, N, wave / (unsigned)chunks_per_row,
+                                   (int)(wave % (unsigned)chunks_per_row), lane, ntl, cur);
+    for (;;) {
+        const unsigned wn = wave + G;
+        const bool more = wn < total_waves;  // uniform across the wave
+        if (more)
+            load_chunk<VS, ST, VEC, SKIP0>(src, nx, ny, nz, N, wn / (unsigned)chunks_per_row,
+                                           (int)(wn % (unsigned)chunks_per_row), lane, ntl, nxt);
+        finish_chunk<VS, ST, VEC, FULLROW, SKIP0, HALF>(src, dst, nx, ny, nz, N, wave / (unsigned)chunks_per_row,
+                                                        (int)(wave % (unsigned)chunks_per_row), lane, nts, k, cur,
+                                                        edge);
+        if (!more) break;
+        cur = nxt;
+        wave = wn;
+    }
 }
 
 // ------------------------------------------------------------------ sponge damping

@@ -76,6 +76,21 @@ lbm_status step_lattice(lbm_lee *h, int64_t nsteps, hipStream_t st) {
             const unsigned g_dpp4f = dpp && vec == 4 && !fullrow ? dpp_grid((const void *)&step_dpp<VS, ST, 4, false, SK, HF>) : 1;
             const unsigned g_dpp2t = dpp && vec == 2 && fullrow ? dpp_grid((const void *)&step_dpp<VS, ST, 2, true, SK, HF>) : 1;
             const unsigned g_dpp2f = dpp && vec == 2 && !fullrow ? dpp_grid((const void *)&step_dpp<VS, ST, 2, false, SK, HF>) : 1;
+            // 3D open boxes with the DPP bulk step close their x faces in the bulk kernel (not
+            // with the network on the helper stream: the bulk kernel reads this step's ghosts)
+            const bool bulk_x = VS::D == 3 && dpp && bc != LBM_BC_PERIODIC && !(bc == LBM_BC_MLP && fork);
+            auto open_bulk = [&](const E *src, E *dst) {
+                if constexpr (VS::D == 3) {
+                    auto go = [&](auto kern) {
+                        kern<<<dpp_grid((const void *)kern), 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
+                                                                           waves, tune, k, bc, h->ghost, ft, fk);
+                    };
+                    if (vec == 4)
+                        fullrow ? go(&step_dpp_open<VS, ST, 4, true, SK, HF>) : go(&step_dpp_open<VS, ST, 4, false, SK, HF>);
+                    else
+                        fullrow ? go(&step_dpp_open<VS, ST, 2, true, SK, HF>) : go(&step_dpp_open<VS, ST, 2, false, SK, HF>);
+                }
+            };
             if (h->inplace) {  // periodic box, one buffer: layouts S and P alternate
                 E *A = static_cast<E *>(h->buf[0]);
                 for (int64_t t = 0; t < nsteps; ++t) {
@@ -212,7 +227,9 @@ lbm_status step_lattice(lbm_lee *h, int64_t nsteps, hipStream_t st) {
                     if (fork) LBM_HIP(hipEventRecord(h->join, h->aux));
                     h->hist_valid = true;
                 }
-                if (variant == LBM_VARIANT_GENERIC) {
+                if (bulk_x) {
+                    open_bulk(src, dst);
+                } else if (variant == LBM_VARIANT_GENERIC) {
                     step_generic<VS, ST, SK, HF><<<blocks_for(h->N), 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, k);
                 } else if (variant == LBM_VARIANT_LDS) {
                     step_lds<VS, ST, SK, HF><<<lds_blocks, 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, lds_cpr, k);
@@ -233,8 +250,8 @@ lbm_status step_lattice(lbm_lee *h, int64_t nsteps, hipStream_t st) {
                 }
                 if (bc == LBM_BC_MLP && fork) LBM_HIP(hipStreamWaitEvent(st, h->join, 0));  // join
                 if (bc != LBM_BC_PERIODIC) {
-                    shell_kernel<VS, ST, SK, HF><<<dim3(shell_x, 2 * VS::D), 256, 0, st>>>(src, dst, h->N, bc, h->ghost,
-                                                                                      ft, ks, fk);
+                    shell_kernel<VS, ST, SK, HF><<<dim3(shell_x, 2 * VS::D - (bulk_x ? 2 : 0)), 256, 0, st>>>(
+                        src, dst, h->N, bc, h->ghost, ft, ks, fk, bulk_x ? 1 : 0);
                     if (sponge_layer(&h->desc))
                         sponge_kernel<VS, ST><<<dim3(sponge_x, 2 * VS::D), 256, 0, st>>>(
                             dst, h->N, h->nx, h->ny, h->nz, h->desc.sponge_width, h->desc.sponge_sigma);
