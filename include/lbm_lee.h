@@ -95,8 +95,9 @@ typedef int32_t lbm_status;
 #define LBM_TUNE_TB_SEGMENT_16 128
 #define LBM_TUNE_TB_SEGMENT_32 192
 /* LBM_BC_MLP in 1D and 3D: the closure network's kernel runs as one block of four waves that walk
- * every tile of face nodes (the grid-stride loop the kernel takes on boxes of more than 262144
- * face nodes, exercised on small boxes; slow, for tests).  Same results as without it. */
+ * every tile of face nodes (the grid-stride loop the kernel takes once the face nodes outnumber
+ * 64 per resident block slot of the GPU, exercised on small boxes; slow, for tests).  Same results
+ * as without it. */
 #define LBM_TUNE_NET_ONE_BLOCK 256
 
 /* Boundary of the box.  The paper's scheme is periodic; the open closures are not in the

@@ -117,12 +117,17 @@ struct alignas(16) WaveTiles {
     unsigned short da1[16][64];
 };
 
-// Per-wave LDS tiles of the forward pass alone (inference), aligned as WaveTiles.
+// Per-wave LDS tiles of the forward pass alone (inference), aligned as WaveTiles.  Each row is
+// padded by kTilePad values (16 bytes): with rows of 64 or 128 values every row would start in
+// LDS bank 0, and the 16 rows that a wave writes or reads at one column would all hit the same
+// banks; with the pad, row r starts 4 r banks further, so 8 consecutive rows cover all 32 banks
+// (the operand reads, 16 bytes per lane, are conflict-free; the column writes conflict 2-way).
+constexpr int kTilePad = 8;
 template <int ZW>
 struct alignas(16) FwdTiles {
-    unsigned short z[16][ZW];
-    unsigned short h1[16][64];
-    unsigned short h2[16][64];
+    unsigned short z[16][ZW + kTilePad];
+    unsigned short h1[16][64 + kTilePad];
+    unsigned short h2[16][64 + kTilePad];
 };
 
 // A operand from an LDS tile X[16][LD] (rows = samples): columns kk*16 + 4 (l/16) + e.
@@ -134,10 +139,10 @@ __device__ __forceinline__ bf16x4 a_rows(const unsigned short (*X)[LD], int kk, 
     return a;
 }
 // 32-wide A operand from an LDS tile X[16][LD] (rows = samples): columns kk*32 + 8 (l/16) + e, one
-// 16-byte read (LD is a multiple of 16, so every row and every 8-column group is 16-byte aligned).
+// 16-byte read (LD is a multiple of 8, so every row and every 8-column group is 16-byte aligned).
 template <int LD>
 __device__ __forceinline__ bf16x8 a_rows32(const unsigned short (*X)[LD], int kk, int lane) {
-    static_assert(LD % 16 == 0, "16-byte aligned rows");
+    static_assert(LD % 8 == 0, "16-byte aligned rows");
     const int i = lane & 15, k0 = kk * 32 + 8 * (lane >> 4);
     bf16x8 a;
     __builtin_memcpy(&a, __builtin_assume_aligned(&X[i][k0], 16), sizeof(a));

@@ -390,7 +390,8 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
         };
         // input [strip(t), strip(t-1)]; the previous strip comes from the history buffer (HIST),
         // else the current one stands in; this step's strip becomes the next step's history (the
-        // other buffer of the pair).  Every lane loads (padding values and rows past the tile's read
+        // other buffer of the pair).  History layout: value v of node n at v * count + n, so the
+        // 16 consecutive nodes of a tile read and write 64 contiguous bytes per value.  Every lane loads (padding values and rows past the tile's read
         // a valid value, then scaled by 0; kept values are scaled by 1, exactly), so no load sits in
         // a branch and none waits for another.
         float now[tile_vals<VS>()], before[tile_vals<VS>()], vals[tile_vals<VS>()];
@@ -398,14 +399,14 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
         for (int t = 0; t < tile_vals<VS>(); ++t) {
             const int v = g + 4 * t, vv = v < G::NIN ? v : G::NIN - 1;
             now[t] = strip_now(vv < NS ? vv : vv - NS);
-            if constexpr (HIST) before[t] = hist_in[node * NS + (vv < NS ? 0 : vv - NS)];
+            if constexpr (HIST) before[t] = hist_in[(long long)(vv < NS ? 0 : vv - NS) * count + node];
         }
 #pragma unroll
         for (int t = 0; t < tile_vals<VS>(); ++t) {
             const int v = g + 4 * t, vv = v < G::NIN ? v : G::NIN - 1;
             const float x = HIST && vv >= NS ? before[t] : now[t];
             vals[t] = x * ((row_ok && v < G::NIN) ? 1.0f : 0.0f);
-            if (row_ok && v < NS) hist_out[node * NS + v] = vals[t];
+            if (row_ok && v < NS) hist_out[(long long)v * count + node] = vals[t];
         }
         float mx = 0.0f, e_out = 0.0f;
         const float s = normalise_tile<VS>(
@@ -553,20 +554,20 @@ __host__ __device__ inline void open2d_ring_cell(long long c, int nx, int ny, in
     }
 }
 
-// Two 16 x 64 tiles per wave: the network's input z and its second hidden layer h2 share one
-// (z is dead once the first layer has read it).
+// Two 16 x 64 tiles per wave (rows padded as FwdTiles'): the network's input z and its second
+// hidden layer h2 share one (z is dead once the first layer has read it).
 struct Open2dTiles {
-    unsigned short (&z)[16][64];
-    unsigned short (&h1)[16][64];
-    unsigned short (&h2)[16][64];
+    unsigned short (&z)[16][64 + kTilePad];
+    unsigned short (&h1)[16][64 + kTilePad];
+    unsigned short (&h2)[16][64 + kTilePad];
 };
 
 // LDS of a block of the ring with MLP.
 template <class VS>
 struct Open2dShared {
     NetFrags<VS> F;
-    alignas(16) unsigned short zt[4][16][64];  // 16-byte aligned rows: the network's 16-byte operand reads
-    alignas(16) unsigned short h1t[4][16][64];
+    alignas(16) unsigned short zt[4][16][64 + kTilePad];  // 16-byte aligned rows: the network's 16-byte operand reads
+    alignas(16) unsigned short h1t[4][16][64 + kTilePad];
     float pred[4][16][NetGeom<VS>::NOUT];
     float predp[4][16][VS::Q];  // limited predictions by population: the row's value for rank[face][i]
     int perm[4][VS::Q], rank[4][VS::Q];
@@ -660,12 +661,12 @@ __device__ void open2d_ring_mlp(Open2dShared<VS> &sh, const typename ST::elem *_
         const int v = g + 4 * t, vv = v < G::NIN ? v : G::NIN - 1;
         now[t] = strip_now(vv < NS ? vv : vv - NS);
     }
+    const long long count = ft.node_off[ft.nfaces];  // history: value v of node n at v * count + n
     if constexpr (HIST) {
-        const float *hrow = hist_in + node * NS;
 #pragma unroll
         for (int t = 0; t < tile_vals<VS>(); ++t) {
             const int v = g + 4 * t, vv = v < G::NIN ? v : G::NIN - 1;
-            before[t] = hrow[vv < NS ? 0 : vv - NS];
+            before[t] = hist_in[(long long)(vv < NS ? 0 : vv - NS) * count + node];
         }
     } else {
 #pragma unroll
@@ -683,7 +684,7 @@ __device__ void open2d_ring_mlp(Open2dShared<VS> &sh, const typename ST::elem *_
         const int v = g + 4 * t;
         const int vv = v < G::NIN ? v : G::NIN - 1;
         vals[t] = (vv < NS ? now[t] : before[t]) * ((row_ok && v < G::NIN) ? 1.0f : 0.0f);
-        if (row_ok && v < NS) hist_out[node * NS + v] = vals[t];
+        if (row_ok && v < NS) hist_out[(long long)v * count + node] = vals[t];
     }
     Open2dTiles T{sh.zt[wid], sh.h1t[wid], sh.zt[wid]};
     float mx = 0.0f, e_out = 0.0f;

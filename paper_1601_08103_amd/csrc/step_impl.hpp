@@ -66,7 +66,19 @@ lbm_status step_lattice(lbm_lee *h, int64_t nsteps, hipStream_t st) {
             }
             nodes = ft.node_off[ft.nfaces];
             const long long tiles = (nodes + 15) / 16;
-            ghost_blocks = (tune & LBM_TUNE_NET_ONE_BLOCK) ? 1u : (unsigned)std::min<long long>((tiles + 3) / 4, 4096);
+            // one block per resident slot (each block stages the weights once, then its waves walk
+            // the tiles), at most one per four tiles
+            long long slots = 4096;
+            if constexpr (NetGeom<VS>::fits) {
+                int per_cu = 0;
+                if (h->cus > 0 &&
+                    hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &per_cu, (const void *)&ghost_mlp_kernel<VS, ST, true>, 256, 0) == hipSuccess &&
+                    per_cu > 0)
+                    slots = (long long)per_cu * h->cus;
+                (void)hipGetLastError();
+            }
+            ghost_blocks = (tune & LBM_TUNE_NET_ONE_BLOCK) ? 1u : (unsigned)std::min<long long>((tiles + 3) / 4, slots);
         }
         auto run = [&](auto skip, auto half) -> lbm_status {
             constexpr bool SK = decltype(skip)::value;

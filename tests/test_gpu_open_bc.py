@@ -463,7 +463,7 @@ def test_auto_takes_the_one_launch_open_step_up_to_8m_cells(shape, want):
                                                 ("D3Q19", (8, 9, 12), "f32"), ("D1Q3", (40,), "f64")])
 def test_network_kernel_grid_stride_loop(name, shape, storage):
     """The closure network's kernel on one block (LBM_TUNE_NET_ONE_BLOCK: its four waves walk every
-    tile of face nodes, the loop it takes on boxes of more than 262144 face nodes) gives the same
+    tile of face nodes, the loop it takes once the face nodes outnumber 64 per resident block) gives the same
     state and ghost values, bit for bit, as the kernel on its full grid."""
     import torch
     from paper_1601_08103_amd import lbm
