@@ -391,15 +391,19 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
         // input [strip(t), strip(t-1)]; the previous strip comes from the history buffer (HIST),
         // else the current one stands in; this step's strip becomes the next step's history (the
         // other buffer of the pair).  History layout: value v of node n at v * count + n, so the
-        // 16 consecutive nodes of a tile read and write 64 contiguous bytes per value.  Every lane loads (padding values and rows past the tile's read
-        // a valid value, then scaled by 0; kept values are scaled by 1, exactly), so no load sits in
-        // a branch and none waits for another.
+        // 16 consecutive nodes of a tile read and write 64 contiguous bytes per value.  Every lane
+        // of a load loads (padding values and rows past the tile's read a valid value, then scaled
+        // by 0; kept values are scaled by 1, exactly), so no load sits in a lane-dependent branch
+        // and none waits for another; with the history, the loads of columns 4t .. 4t + 3 skip the
+        // strip when all four are history columns, and the history when none is.
         float now[tile_vals<VS>()], before[tile_vals<VS>()], vals[tile_vals<VS>()];
 #pragma unroll
         for (int t = 0; t < tile_vals<VS>(); ++t) {
             const int v = g + 4 * t, vv = v < G::NIN ? v : G::NIN - 1;
-            now[t] = strip_now(vv < NS ? vv : vv - NS);
-            if constexpr (HIST) before[t] = hist_in[(long long)(vv < NS ? 0 : vv - NS) * count + node];
+            if (!HIST || 4 * t < NS) now[t] = strip_now(vv < NS ? vv : vv - NS);
+            if constexpr (HIST) {
+                if (4 * t + 3 >= NS) before[t] = hist_in[(long long)(vv < NS ? 0 : vv - NS) * count + node];
+            }
         }
 #pragma unroll
         for (int t = 0; t < tile_vals<VS>(); ++t) {
@@ -655,18 +659,20 @@ __device__ void open2d_ring_mlp(Open2dShared<VS> &sh, const typename ST::elem *_
     // Every lane loads (padding values and rows past the tile's read a valid value, later scaled
     // by 0; kept values are scaled by 1, exactly), so no load sits in a branch, and all of them,
     // the ring cell's and the weights' are issued before the first wait.
+    // (with the history, as in the network kernel: no strip loads for the columns 4t .. 4t + 3 that
+    // are all history columns, no history loads where none is)
     float now[tile_vals<VS>()], before[tile_vals<VS>()];
 #pragma unroll
     for (int t = 0; t < tile_vals<VS>(); ++t) {
         const int v = g + 4 * t, vv = v < G::NIN ? v : G::NIN - 1;
-        now[t] = strip_now(vv < NS ? vv : vv - NS);
+        if (!HIST || 4 * t < NS) now[t] = strip_now(vv < NS ? vv : vv - NS);
     }
     const long long count = ft.node_off[ft.nfaces];  // history: value v of node n at v * count + n
     if constexpr (HIST) {
 #pragma unroll
         for (int t = 0; t < tile_vals<VS>(); ++t) {
             const int v = g + 4 * t, vv = v < G::NIN ? v : G::NIN - 1;
-            before[t] = hist_in[(long long)(vv < NS ? 0 : vv - NS) * count + node];
+            if (4 * t + 3 >= NS) before[t] = hist_in[(long long)(vv < NS ? 0 : vv - NS) * count + node];
         }
     } else {
 #pragma unroll
