@@ -304,7 +304,7 @@ __device__ __forceinline__ void load_chunk(const typename ST::elem *__restrict__
 
 // Row ends of a periodic box: the x-neighbour beyond one end of a row is the cell at the other.
 // An open box's bulk step passes its own EDGE whose value() gives what is pulled from beyond an
-// x face instead.
+// x face instead, and whose damp() damps the stored cells of a sponge layer (sponge_width > 0).
 struct WrapEdge {
     static constexpr bool open = false;
 };
@@ -374,6 +374,24 @@ __device__ __forceinline__ void finish_chunk(const typename ST::elem *__restrict
         for (int i = 0; i < VS::Q; ++i) s[i][q] = c[i];
     }
     const size_t out = ((size_t)z * ny + y) * (size_t)nx + x0;
+    if constexpr (EDGE::open) {
+        if (edge.sponge_width > 0) {  // a sponge layer: cells within its width of a face are damped
+            using V = typename ChunkRaw<VS, ST, VEC>::ev;
+            const int dyz = min(min(y, ny - 1 - y), min(z, nz - 1 - z));
+#pragma unroll
+            for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) {
+                V c;
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) {
+                    const E e = enc_io<ST, RAW>(s[i][q]);
+                    const int d = min(dyz, min(x0 + q, nx - 1 - x0 - q));
+                    c[q] = d < edge.sponge_width ? edge.template damp<ST>(e, d) : e;
+                }
+                vstore(reinterpret_cast<V *>(dst + (size_t)i * N + out), c, nts);
+            }
+            return;
+        }
+    }
 #pragma unroll
     for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) storev<ST, VEC>(dst + (size_t)i * N + out, s[i], nts);
 }

@@ -104,6 +104,19 @@ __device__ inline int node_cell(const FaceTab<Q> &ft, long long g, int (&p)[3]) 
     return f;
 }
 
+// ------------------------------------------------------------------ sponge damping
+// Damping factor at distance d < width from the nearest face, and a stored value damped by it
+// (decoded, scaled, encoded again).
+template <class CT>
+__device__ inline CT sponge_factor(int d, int width, double sigma_max) {
+    const CT w = (CT)(width - d) / (CT)width;
+    return (CT)1 - (CT)sigma_max * w * w;
+}
+template <class ST>
+__device__ inline typename ST::elem sponge_damp(typename ST::elem e, typename ST::comp fac) {
+    return ST::enc(ST::dec(e) * fac);
+}
+
 // ------------------------------------------------------------------ shell recompute
 // Streamed values of boundary cell x, in two passes: shell_inside takes every source inside the
 // box (every source with COPY, clamped) from the state and leaves 0 for the others (ZERO,
@@ -162,13 +175,14 @@ __device__ inline void shell_outside(const int (&x)[3], const int (&n)[3], typen
 
 // Grid (x blocks, one y block per face).  bulk_x: the bulk step (step_dpp_open) has already
 // computed the x faces' cells of every row that lies on no y or z face; the grid then covers the
-// y and z faces only (blockIdx.y + 2), which own their cells on the x faces.
+// y and z faces only (blockIdx.y + 2), which own their cells on the x faces.  sponge_width > 0
+// (only with bulk_x): the cells stored are damped as the sponge kernel would damp them.
 template <class VS, class ST, bool SKIP0, bool HALF = false>
 __global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__restrict__ src,
                                                     typename ST::elem *__restrict__ dst, size_t N, int closure,
                                                     const float *__restrict__ ghost, FaceTab<VS::Q> ft,
                                                     StepCoef<typename ST::comp, VS::Q> k, FieldCoef<VS::Q> fk,
-                                                    int bulk_x) {
+                                                    int bulk_x, int sponge_width, double sponge_sigma) {
     using CT = typename ST::comp;
     const int f = (int)blockIdx.y + (bulk_x ? 2 : 0);
     const int a = f >> 1, side = f & 1;
@@ -210,6 +224,12 @@ __global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__r
         shell_outside<VS, ST, SKIP0>(x, n, s, gh);
     }
     collide<VS, CT, split_constants<ST>(), SKIP0, HALF>(k, s);
+    if (sponge_width > 0) {  // with bulk_x, a sponge layer: face cells lie at distance 0
+        const CT fac = sponge_factor<CT>(0, sponge_width, sponge_sigma);
+#pragma unroll
+        for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = sponge_damp<ST>(ST::enc(s[i]), fac);
+        return;
+    }
 #pragma unroll
     for (int i = SKIP0 ? 1 : 0; i < VS::Q; ++i) dst[(size_t)i * N + cell] = ST::enc(s[i]);
 }
@@ -221,7 +241,9 @@ __global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__r
 // ZERO and SPONGE, the row's end cell itself for COPY (the clamped source), and for MLP the face
 // node's prediction in stored units, the value shell_outside forms for a source beyond one face.
 // Rows on a y or z face pull from beyond those faces too; the shell kernel recomputes them.  So
-// the x faces, whose cells are strided in memory, cost no second pass.
+// the x faces, whose cells are strided in memory, cost no second pass.  A sponge layer
+// (sponge_width > 0) is damped as each cell is stored, as the sponge kernel damps a stored value;
+// the shell kernel damps the face cells it recomputes, so no sponge pass is needed either.
 template <int Q>
 struct OpenEdge {
     static constexpr bool open = true;
@@ -229,6 +251,12 @@ struct OpenEdge {
     const float *ghost;
     const FaceTab<Q> &ft;
     const FieldCoef<Q> &fk;
+    int sponge_width;
+    double sponge_sigma;
+    template <class ST>
+    __device__ typename ST::elem damp(typename ST::elem e, int d) const {
+        return sponge_damp<ST>(e, sponge_factor<typename ST::comp>(d, sponge_width, sponge_sigma));
+    }
     // side 0: the low x face (sources at x = -1), 1: the high one; (ys, zs) the source row
     template <class VS, class ST, bool RAW>
     __device__ typename ST::comp value(int side, int i, int ys, int zs, typename ST::comp own) const {
@@ -250,14 +278,14 @@ __global__ __launch_bounds__(256) void step_dpp_open(const typename ST::elem *__
                                                      size_t N, int chunks_per_row, unsigned total_waves, unsigned tune,
                                                      StepCoef<typename ST::comp, VS::Q> k, int closure,
                                                      const float *__restrict__ ghost, FaceTab<VS::Q> ft,
-                                                     FieldCoef<VS::Q> fk) {
+                                                     FieldCoef<VS::Q> fk, int sponge_width, double sponge_sigma) {
     const int lane = threadIdx.x & 63;
     const unsigned wid = (unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool ntl = (tune & kTuneNtLoad) != 0, nts = (tune & kTuneNtStore) != 0;
     const unsigned G = gridDim.x * 4u;
     unsigned wave = blockIdx.x * 4u + wid;
     if (wave >= total_waves) return;
-    const OpenEdge<VS::Q> edge{closure, ghost, ft, fk};
+    const OpenEdge<VS::Q> edge{closure, ghost, ft, fk, sponge_width, sponge_sigma};
     ChunkRaw<VS, ST, VEC> cur, nxt;
     load_chunk<VS, ST, VEC, SKIP0>(src, nx, ny, nz, N, wave / (unsigned)chunks_per_row,
                                    (int)(wave % (unsigned)chunks_per_row), lane, ntl, cur);
@@ -276,18 +304,7 @@ __global__ __launch_bounds__(256) void step_dpp_open(const typename ST::elem *__
     }
 }
 
-// ------------------------------------------------------------------ sponge damping
-// Damping factor at distance d < width from the nearest face, and a stored value damped by it
-// (decoded, scaled, encoded again).
-template <class CT>
-__device__ inline CT sponge_factor(int d, int width, double sigma_max) {
-    const CT w = (CT)(width - d) / (CT)width;
-    return (CT)1 - (CT)sigma_max * w * w;
-}
-template <class ST>
-__device__ inline typename ST::elem sponge_damp(typename ST::elem e, typename ST::comp fac) {
-    return ST::enc(ST::dec(e) * fac);
-}
+// ------------------------------------------------------------------ sponge layer
 
 // Grid (x blocks, 2D slabs): slab f = 2a + side holds the cells within W of face f that are not
 // in a slab of a lower axis, so every layer cell is visited exactly once and the interior not at all.

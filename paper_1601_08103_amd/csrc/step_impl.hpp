@@ -91,11 +91,14 @@ lbm_status step_lattice(lbm_lee *h, int64_t nsteps, hipStream_t st) {
             // 3D open boxes with the DPP bulk step close their x faces in the bulk kernel (not
             // with the network on the helper stream: the bulk kernel reads this step's ghosts)
             const bool bulk_x = VS::D == 3 && dpp && bc != LBM_BC_PERIODIC && !(bc == LBM_BC_MLP && fork);
+            // with bulk_x a sponge layer is damped by the bulk and shell kernels as they store
+            const int layer_w = bulk_x && sponge_layer(&h->desc) ? h->desc.sponge_width : 0;
             auto open_bulk = [&](const E *src, E *dst) {
                 if constexpr (VS::D == 3) {
                     auto go = [&](auto kern) {
                         kern<<<dpp_grid((const void *)kern), 256, 0, st>>>(src, dst, h->nx, h->ny, h->nz, h->N, cpr,
-                                                                           waves, tune, k, bc, h->ghost, ft, fk);
+                                                                           waves, tune, k, bc, h->ghost, ft, fk,
+                                                                           layer_w, h->desc.sponge_sigma);
                     };
                     if (vec == 4)
                         fullrow ? go(&step_dpp_open<VS, ST, 4, true, SK, HF>) : go(&step_dpp_open<VS, ST, 4, false, SK, HF>);
@@ -263,8 +266,8 @@ lbm_status step_lattice(lbm_lee *h, int64_t nsteps, hipStream_t st) {
                 if (bc == LBM_BC_MLP && fork) LBM_HIP(hipStreamWaitEvent(st, h->join, 0));  // join
                 if (bc != LBM_BC_PERIODIC) {
                     shell_kernel<VS, ST, SK, HF><<<dim3(shell_x, 2 * VS::D - (bulk_x ? 2 : 0)), 256, 0, st>>>(
-                        src, dst, h->N, bc, h->ghost, ft, ks, fk, bulk_x ? 1 : 0);
-                    if (sponge_layer(&h->desc))
+                        src, dst, h->N, bc, h->ghost, ft, ks, fk, bulk_x ? 1 : 0, layer_w, h->desc.sponge_sigma);
+                    if (sponge_layer(&h->desc) && layer_w == 0)
                         sponge_kernel<VS, ST><<<dim3(sponge_x, 2 * VS::D), 256, 0, st>>>(
                             dst, h->N, h->nx, h->ny, h->nz, h->desc.sponge_width, h->desc.sponge_sigma);
                 }

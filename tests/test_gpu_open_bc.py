@@ -486,18 +486,20 @@ def test_network_kernel_grid_stride_loop(name, shape, storage):
 
 
 @pytest.mark.parametrize("name", ["D3Q7", "D3Q19", "D3Q13"])
-@pytest.mark.parametrize("bc", ["zero", "copy", "sponge", "mlp"])
+@pytest.mark.parametrize("bc", ["zero", "copy", "sponge", "mlp", "mlp_sponge"])
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16", "e3m12"])
 def test_open_dpp_bulk_closes_the_x_faces(name, bc, storage):
     """3D open boxes with the DPP bulk step close their x faces in the bulk kernel (the shell
-    kernel then recomputes the y and z faces only).  Against the GENERIC variant (bulk step, then
-    every face in the shell kernel) after each of 4 steps: bit for bit where both work in the
+    kernel then recomputes the y and z faces only), and damp a sponge layer as they store (no
+    sponge pass).  Against the GENERIC variant (bulk step, every face in the shell kernel, then
+    the sponge kernel) after each of 4 steps: bit for bit where both work in the
     same domain (every storage but E3M12, whose bulk step works in its raw domain and the shell in
     the real one), and on the small boxes against the oracle.  Boxes: rows of one chunk and of
     several (ragged last chunk), four and two cells per lane."""
     import torch
     lat = L.get(name)
-    kw = dict(sponge_width=2, sponge_sigma=0.4) if bc == "sponge" else {}
+    kw = dict(sponge_width=2, sponge_sigma=0.4) if bc in ("sponge", "mlp_sponge") else {}
+    bc = "mlp" if bc == "mlp_sponge" else bc
     params = _small_params(lat, 6)
     p32 = mlp.unflat(mlp.flat(params).astype(np.float32).astype(np.float64), 6 * lat.Q, len(ob.incoming_canonical(lat)))
     bar = {"f64": 1e-12, "f32": 1e-5}.get(storage, 2e-3)
