@@ -304,9 +304,11 @@ __device__ __forceinline__ void load_chunk(const typename ST::elem *__restrict__
 
 // Row ends of a periodic box: the x-neighbour beyond one end of a row is the cell at the other.
 // An open box's bulk step passes its own EDGE whose value() gives what is pulled from beyond an
-// x face instead, and whose damp() damps the stored cells of a sponge layer (sponge_width > 0).
+// x face instead, and whose damp() damps the stored cells of a sponge layer (EDGE::layer, and
+// sponge_width > 0).
 struct WrapEdge {
     static constexpr bool open = false;
+    static constexpr bool layer = false;
 };
 
 // Decode a loaded chunk, move the x-neighbours across lanes, collide and store.
@@ -374,7 +376,7 @@ __device__ __forceinline__ void finish_chunk(const typename ST::elem *__restrict
         for (int i = 0; i < VS::Q; ++i) s[i][q] = c[i];
     }
     const size_t out = ((size_t)z * ny + y) * (size_t)nx + x0;
-    if constexpr (EDGE::open) {
+    if constexpr (EDGE::open && EDGE::layer) {
         if (edge.sponge_width > 0) {  // a sponge layer: cells within its width of a face are damped
             using V = typename ChunkRaw<VS, ST, VEC>::ev;
             const int dyz = min(min(y, ny - 1 - y), min(z, nz - 1 - z));

@@ -244,9 +244,10 @@ __global__ __launch_bounds__(256) void shell_kernel(const typename ST::elem *__r
 // the x faces, whose cells are strided in memory, cost no second pass.  A sponge layer
 // (sponge_width > 0) is damped as each cell is stored, as the sponge kernel damps a stored value;
 // the shell kernel damps the face cells it recomputes, so no sponge pass is needed either.
-template <int Q>
+template <int Q, bool LAYER>
 struct OpenEdge {
     static constexpr bool open = true;
+    static constexpr bool layer = LAYER;  // compiled with the damping path (kept out of other boxes' code)
     int closure;
     const float *ghost;
     const FaceTab<Q> &ft;
@@ -271,8 +272,8 @@ struct OpenEdge {
     }
 };
 
-// Same chunk walk as step_dpp (including the persistent tuning).
-template <class VS, class ST, int VEC, bool FULLROW, bool SKIP0, bool HALF = false>
+// Same chunk walk as step_dpp (including the persistent tuning).  LAYER: with a sponge layer.
+template <class VS, class ST, int VEC, bool FULLROW, bool SKIP0, bool HALF, bool LAYER>
 __global__ __launch_bounds__(256) void step_dpp_open(const typename ST::elem *__restrict__ src,
                                                      typename ST::elem *__restrict__ dst, int nx, int ny, int nz,
                                                      size_t N, int chunks_per_row, unsigned total_waves, unsigned tune,
@@ -285,7 +286,7 @@ __global__ __launch_bounds__(256) void step_dpp_open(const typename ST::elem *__
     const unsigned G = gridDim.x * 4u;
     unsigned wave = blockIdx.x * 4u + wid;
     if (wave >= total_waves) return;
-    const OpenEdge<VS::Q> edge{closure, ghost, ft, fk, sponge_width, sponge_sigma};
+    const OpenEdge<VS::Q, LAYER> edge{closure, ghost, ft, fk, sponge_width, sponge_sigma};
     ChunkRaw<VS, ST, VEC> cur, nxt;
     load_chunk<VS, ST, VEC, SKIP0>(src, nx, ny, nz, N, wave / (unsigned)chunks_per_row,
                                    (int)(wave % (unsigned)chunks_per_row), lane, ntl, cur);

@@ -91,8 +91,10 @@ lbm_status step_lattice(lbm_lee *h, int64_t nsteps, hipStream_t st) {
             // 3D open boxes with the DPP bulk step close their x faces in the bulk kernel (not
             // with the network on the helper stream: the bulk kernel reads this step's ghosts)
             const bool bulk_x = VS::D == 3 && dpp && bc != LBM_BC_PERIODIC && !(bc == LBM_BC_MLP && fork);
-            // with bulk_x a sponge layer is damped by the bulk and shell kernels as they store
-            const int layer_w = bulk_x && sponge_layer(&h->desc) ? h->desc.sponge_width : 0;
+            // with bulk_x a sponge layer is damped by the bulk and shell kernels as they store; not
+            // for storage with a raw step domain (E3M12), whose damping (a real-domain decode and
+            // encode per value) takes the bulk kernel to 132 registers: slower than a sponge pass
+            const int layer_w = bulk_x && sponge_layer(&h->desc) && !ST::has_raw ? h->desc.sponge_width : 0;
             auto open_bulk = [&](const E *src, E *dst) {
                 if constexpr (VS::D == 3) {
                     auto go = [&](auto kern) {
@@ -100,10 +102,22 @@ lbm_status step_lattice(lbm_lee *h, int64_t nsteps, hipStream_t st) {
                                                                            waves, tune, k, bc, h->ghost, ft, fk,
                                                                            layer_w, h->desc.sponge_sigma);
                     };
-                    if (vec == 4)
-                        fullrow ? go(&step_dpp_open<VS, ST, 4, true, SK, HF>) : go(&step_dpp_open<VS, ST, 4, false, SK, HF>);
-                    else
-                        fullrow ? go(&step_dpp_open<VS, ST, 2, true, SK, HF>) : go(&step_dpp_open<VS, ST, 2, false, SK, HF>);
+                    auto pick = [&](auto layer) {
+                        constexpr bool LY = decltype(layer)::value;
+                        if (vec == 4)
+                            fullrow ? go(&step_dpp_open<VS, ST, 4, true, SK, HF, LY>)
+                                    : go(&step_dpp_open<VS, ST, 4, false, SK, HF, LY>);
+                        else
+                            fullrow ? go(&step_dpp_open<VS, ST, 2, true, SK, HF, LY>)
+                                    : go(&step_dpp_open<VS, ST, 2, false, SK, HF, LY>);
+                    };
+                    if constexpr (!ST::has_raw) {
+                        if (layer_w > 0) {
+                            pick(std::true_type{});
+                            return;
+                        }
+                    }
+                    pick(std::false_type{});
                 }
             };
             if (h->inplace) {  // periodic box, one buffer: layouts S and P alternate
