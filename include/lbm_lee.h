@@ -83,9 +83,12 @@ typedef int32_t lbm_status;
                               /* provably invariant (see lbm_lee_bytes_per_update)            */
 #define LBM_TUNE_CLOSURE_STREAM 16 /* LBM_BC_MLP: run the network on the handle's helper stream,  */
                                    /* forked from and joined to the caller's stream each step, so */
-                                   /* it overlaps the bulk step (pays off in captured graphs;     */
-                                   /* eager launches add two event calls per step); no effect     */
-                                   /* with LBM_VARIANT_OPEN2D (one launch per step)               */
+                                   /* it overlaps the bulk step (eager launches add two event     */
+                                   /* calls per step); no effect with LBM_VARIANT_OPEN2D (one     */
+                                   /* launch per step).  In 3D the DPP bulk step then leaves the  */
+                                   /* x faces to the boundary pass (it would read this step's     */
+                                   /* predictions), which costs more than the overlap gains       */
+                                   /* (D3Q7 384^3 FP16: 0.49 against 0.39 ms per step)            */
 #define LBM_TUNE_IN_PLACE 32  /* one population buffer instead of two (periodic box only; pop_b */
                               /* of lbm_lee_init may be NULL); see "In-place streaming" below   */
 /* LBM_VARIANT_TB2: segment length along the march axis (z in 3D, y in 2D).  Without these bits
