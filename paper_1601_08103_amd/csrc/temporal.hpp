@@ -288,7 +288,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     // planes of loads in flight: two where the registers allow (up to 9 velocities)
     constexpr int PF = (Q <= 9 && K <= 3) ? 2 : 1;
     // LDS ring set s (s = 1..K-1) holds stage s's results on the tile dilated by K - s
-    auto set_dx = [](int s) { return TX + 2 * (K - s); };
     auto set_pl = [](int s) { return (TX + 2 * (K - s)) * (TY + 2 * HY * (K - s)); };
     auto set_off = [](int s) {
         int o = 0;
