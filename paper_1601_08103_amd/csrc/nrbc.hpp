@@ -122,13 +122,25 @@ struct alignas(16) WaveTiles {
 // LDS bank 0, and the 16 rows that a wave writes or reads at one column would all hit the same
 // banks; with the pad, row r starts 4 r banks further, so 8 consecutive rows cover all 32 banks
 // (the operand reads, 16 bytes per lane, are conflict-free; the column writes conflict 2-way).
+// The second hidden layer h2 reuses z's storage (z is dead once the first layer has read it;
+// ZW >= 64), which leaves room for one more block per CU in the network kernels.
 constexpr int kTilePad = 8;
 template <int ZW>
 struct alignas(16) FwdTiles {
     unsigned short z[16][ZW + kTilePad];
     unsigned short h1[16][64 + kTilePad];
-    unsigned short h2[16][64 + kTilePad];
 };
+template <int ZW>
+struct FwdView {
+    unsigned short (&z)[16][ZW + kTilePad];
+    unsigned short (&h1)[16][64 + kTilePad];
+    unsigned short (&h2)[16][64 + kTilePad];
+};
+template <int ZW>
+__device__ inline FwdView<ZW> fwd_view(FwdTiles<ZW> &t) {
+    static_assert(ZW >= 64, "h2 fits in z's storage");
+    return {t.z, t.h1, *reinterpret_cast<unsigned short (*)[16][64 + kTilePad]>(&t.z[0][0])};
+}
 
 // A operand from an LDS tile X[16][LD] (rows = samples): columns kk*16 + 4 (l/16) + e.
 template <int LD>
@@ -432,7 +444,7 @@ __global__ __launch_bounds__(256) void nrbc_forward_kernel(const float *__restri
     __shared__ NetFrags<VS> F;
     stage_forward_weights<VS>(P, F);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    FwdTiles<G::ZW> &T = tiles[wid];
+    FwdView<G::ZW> T = fwd_view(tiles[wid]);
     const long long ntiles = (count + 15) / 16;
     for (long long tile = (long long)blockIdx.x * 4 + wid; tile < ntiles; tile += (long long)gridDim.x * 4) {
         const long long base = tile * 16;

@@ -386,7 +386,7 @@ __global__ __launch_bounds__(256) void ghost_mlp_kernel(const typename ST::elem 
     }
     stage_forward_weights<VS>(P, F);  // ends with a block barrier
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    FwdTiles<G::ZW> &T = tiles[wid];
+    FwdView<G::ZW> T = fwd_view(tiles[wid]);
     const long long count = ft.node_off[ft.nfaces];
     const long long ntiles = (count + 15) / 16;
     for (long long tile = (long long)blockIdx.x * 4 + wid; tile < ntiles; tile += (long long)gridDim.x * 4) {
