@@ -156,6 +156,10 @@ def nrbc3d_leg():
         return None
     P = np.load(path, allow_pickle=False)
     L, E = 384, 1384
+    need = lbm.lbm_lee_state_bytes(lbm.make_desc("D3Q7", "f32", (E,) * 3))  # the judge in place, at least
+    free, _ = torch.cuda.mem_get_info()
+    if need > 0.9 * free:
+        return dict(skipped=f"the {E}^3 FP32 judge needs {need / 2**30:.0f} GiB, {free / 2**30:.0f} GiB free")
     info = lbm.lbm_lee_lattice_info("D3Q7")
     fields = nrbc.initial_fields("mixed", np.random.default_rng(10_000), info, L, 3)
     ext = nrbc.judge_solver("D3Q7", "f32", E, 3)
