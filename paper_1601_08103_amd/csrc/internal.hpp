@@ -416,13 +416,15 @@ inline int resolve_variant(const lbm_lee *h) {
         if (h->tab.Q <= 9 && tb_tile_y(h->desc.lattice, h->desc.storage, 3) > 0) return LBM_VARIANT_TB3;
         if (tb_tile_y(h->desc.lattice, h->desc.storage, 2) > 0) return LBM_VARIANT_TB2;
     }
-    // 3D open boxes of the 7-velocity sets: the DPP bulk step closes the x faces (and damps a sponge
-    // layer) itself, which beats the one-cell-per-thread step plus the full boundary pass for every
-    // storage (D3Q7 384^3, ms per step, GENERIC against DPP: FP32 zero 0.611 / 0.508, network
-    // 0.749 / 0.671, sponge W 16 0.907 / 0.599; FP64 zero 1.120 / 1.023, network 1.265 / 1.179,
-    // sponge 1.652 / 1.169); the larger sets keep the rule below (their DPP kernels hold 180 to 256
-    // registers, unmeasured here)
-    const bool open3d = h->desc.bc != LBM_BC_PERIODIC && h->tab.D == 3 && h->tab.Q <= 7;
+    // 3D open boxes: the DPP bulk step closes the x faces (and damps a sponge layer) itself, which
+    // beats the one-cell-per-thread step plus the full boundary pass for every set and storage but
+    // D3Q27 with 8-byte storage, whose DPP kernel spills (ms per step, GENERIC against DPP; D3Q7
+    // 384^3: FP32 zero 0.611 / 0.508, network 0.749 / 0.671, sponge W 16 0.907 / 0.599; FP64 zero
+    // 1.120 / 1.023; 256^3 zero closure, FP32 / FP64: D3Q9 0.258 / 0.212, 0.466 / 0.410; D3Q13
+    // 0.399 / 0.313, 0.717 / 0.627; D3Q19 0.643 / 0.548, 1.146 / 0.981; D3Q27 0.920 / 0.710,
+    // 1.647 / 3.591)
+    const bool open3d = h->desc.bc != LBM_BC_PERIODIC && h->tab.D == 3 &&
+                        !(h->tab.Q > 19 && elem_size(h->desc.storage) == 8);
     if (elem_size(h->desc.storage) >= 4 && !open3d) return LBM_VARIANT_GENERIC;
     if (h->nx % 4 == 0) return LBM_VARIANT_DPP;
     if (h->nx % 2 == 0) return LBM_VARIANT_DPP2;
