@@ -131,7 +131,8 @@ typedef int32_t lbm_status;
 #define LBM_VARIANT_AUTO 0    /* the fastest measured variant: OPEN2D on 2D open boxes of     */
                               /* <= 2^23 cells (GENERIC on larger ones); on                    */
                               /* periodic 2D/3D boxes of >= 2^20 cells TB3 (sets of <= 9       */
-                              /* velocities) or TB2 where they are supported; on 3D open boxes */
+                              /* velocities) or TB2 where they are supported; TB2 on periodic  */
+                              /* 2D boxes of 2^18 to 2^20 cells; on 3D open boxes               */
                               /* DPP/DPP2/GENERIC (by nx: nx % 4, nx % 2, odd), but GENERIC for */
                               /* D3Q27 with 8-byte storage; else GENERIC for 4- and 8-byte      */
                               /* storage, DPP/DPP2/GENERIC (by nx) for 2-byte storage           */

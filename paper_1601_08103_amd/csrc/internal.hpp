@@ -416,6 +416,12 @@ inline int resolve_variant(const lbm_lee *h) {
         if (h->tab.Q <= 9 && tb_tile_y(h->desc.lattice, h->desc.storage, 3) > 0) return LBM_VARIANT_TB3;
         if (tb_tile_y(h->desc.lattice, h->desc.storage, 2) > 0) return LBM_VARIANT_TB2;
     }
+    // periodic 2D boxes of 2^18 to 2^20 cells: two steps per launch (the launches, not HBM, bound a
+    // step there; D2Q9 512^2, us per step, GENERIC / DPP / TB2 / TB3: FP32 7.7 / 6.0 / 4.2 / 4.8,
+    // FP16 4.9 / 4.6 / 4.0 / 4.2; D2Q5 FP32 4.3 / 3.4 / 2.9 / 2.7; at 256^2 all within 1 us)
+    if (h->desc.bc == LBM_BC_PERIODIC && h->tab.D == 2 && h->N >= ((size_t)1 << 18) && tb_plane_fits(&h->desc, 2) &&
+        tb_tile_y(h->desc.lattice, h->desc.storage, 2) > 0)
+        return LBM_VARIANT_TB2;
     // 3D open boxes: the DPP bulk step closes the x faces (and damps a sponge layer) itself, which
     // beats the one-cell-per-thread step plus the full boundary pass for every set and storage but
     // D3Q27 with 8-byte storage, whose DPP kernel spills (ms per step, GENERIC against DPP; D3Q7

@@ -197,13 +197,15 @@ def test_1d_workload_exact(mode, variant):
 @pytest.mark.parametrize("name", ["D2Q9", "D2Q5"])
 @pytest.mark.parametrize("storage", ["f32", "f64"])
 def test_2d_workload_full_size(name, storage):
-    """512^2, 16 seeded pulses (amplitude U(-1e-3, 1e-3), sigma U(8, 24)), 2000 steps, every cell."""
+    """512^2, 16 seeded pulses (amplitude U(-1e-3, 1e-3), sigma U(8, 24)), 2000 steps, every cell, in
+    AUTO's launch configuration (two steps per launch at this size)."""
     lat = lattice(name)
     shape = (512, 512)
     say("2D workload", name, storage)
     p0 = inputs.gaussian_pressure(shape, inputs.pulses_2d(seed=0))
     rho, u, theta = inputs.fields_from_pressure(p0, lat.rho0, lat.theta0, lat.gamma)
     sim = _solver(name, storage, shape, fields=(rho, u, theta))
+    assert sim.variant == "tb2"
     sim.step(2000)
     m = {k: v.cpu().numpy() for k, v in sim.moments().items()}
     g_or = lbe.run(lat, rho, u, theta, 2000, nthreads=16)
