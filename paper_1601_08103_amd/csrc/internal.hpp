@@ -391,12 +391,11 @@ inline lbm_status launch_check() {
     return LBM_OK;
 }
 
-// AUTO: measured on MI355X (D3Q7, 256^3): the temporal-blocking variants beat every one-step
-// kernel on large periodic boxes (they move the state through HBM once per two or three
-// steps), three steps beating two except for D3Q19; below a million cells the launches are
-// short and the one-step kernels win.  Of the one-step kernels
-// the one-cell-per-thread gather has the highest occupancy and wins for 4- and 8-byte storage;
-// 2-byte storage needs wider per-lane accesses.
+// AUTO: measured on MI355X.  The temporal-blocking variants beat every one-step kernel on large
+// periodic boxes (they move the state through HBM once per two or three steps), three steps
+// beating two except for D3Q19, and on mid-size ones (fewer launches); on small boxes the
+// one-cell-per-thread step, which has the highest occupancy, wins in every storage.  Open boxes
+// have their own kernels (one launch per step in 2D, the bulk step closing the x faces in 3D).
 inline int resolve_variant(const lbm_lee *h) {
     if (h->inplace) return LBM_VARIANT_GENERIC;  // the in-place kernels are one thread per cell
     if (h->desc.variant != LBM_VARIANT_AUTO) return h->desc.variant;
@@ -422,6 +421,12 @@ inline int resolve_variant(const lbm_lee *h) {
     if (h->desc.bc == LBM_BC_PERIODIC && h->tab.D == 2 && h->N >= ((size_t)1 << 18) && tb_plane_fits(&h->desc, 2) &&
         tb_tile_y(h->desc.lattice, h->desc.storage, 2) > 0)
         return LBM_VARIANT_TB2;
+    // periodic 3D boxes of 3 x 2^18 cells and more, sets of up to 9 velocities: three steps per launch
+    // (D3Q7 96^3, us per step, GENERIC / TB3: FP32 8.4 / 7.6, FP16 8.3 / 6.0, FP64 14.0 / 8.6; at
+    // 64^3 GENERIC is ahead)
+    if (h->desc.bc == LBM_BC_PERIODIC && h->tab.D == 3 && h->N >= ((size_t)3 << 18) && h->tab.Q <= 9 &&
+        h->nx % 2 == 0 && tb_plane_fits(&h->desc, 3) && tb_tile_y(h->desc.lattice, h->desc.storage, 3) > 0)
+        return LBM_VARIANT_TB3;
     // 3D open boxes: the DPP bulk step closes the x faces (and damps a sponge layer) itself, which
     // beats the one-cell-per-thread step plus the full boundary pass for every set and storage but
     // D3Q27 with 8-byte storage, whose DPP kernel spills (ms per step, GENERIC against DPP; D3Q7
@@ -431,9 +436,15 @@ inline int resolve_variant(const lbm_lee *h) {
     // 1.647 / 3.591)
     const bool open3d = h->desc.bc != LBM_BC_PERIODIC && h->tab.D == 3 &&
                         !(h->tab.Q > 19 && elem_size(h->desc.storage) == 8);
-    if (elem_size(h->desc.storage) >= 4 && !open3d) return LBM_VARIANT_GENERIC;
-    if (h->nx % 4 == 0) return LBM_VARIANT_DPP;
-    if (h->nx % 2 == 0) return LBM_VARIANT_DPP2;
+    if (open3d) {
+        if (h->nx % 4 == 0) return LBM_VARIANT_DPP;
+        if (h->nx % 2 == 0) return LBM_VARIANT_DPP2;
+    }
+    // everything else (periodic boxes below those sizes or without a multi-step kernel, 1D, large
+    // 2D open boxes): one thread per cell, in every storage.  The four-cells-per-lane step loses
+    // there for 2-byte storage too (us per step, GENERIC / DPP, FP16: D3Q7 64^3 3.5 / 5.2, 96^3
+    // 8.3 / 8.8; D3Q19 64^3 5.8 / 14.7, 96^3 13.5 / 28.6, its registers allow two waves per SIMD;
+    // D2Q9 256^2 3.0 / 3.4)
     return LBM_VARIANT_GENERIC;
 }
 
