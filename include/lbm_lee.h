@@ -131,11 +131,12 @@ typedef int32_t lbm_status;
 #define LBM_VARIANT_AUTO 0    /* the fastest measured variant: OPEN2D on 2D open boxes of     */
                               /* <= 2^23 cells (GENERIC on larger ones); on                    */
                               /* periodic 2D/3D boxes of >= 2^20 cells TB3 (sets of <= 9       */
-                              /* velocities) or TB2 where they are supported; TB2 on periodic  */
-                              /* 2D boxes of 2^18 to 2^20 cells, TB3 on periodic 3D boxes of   */
-                              /* 3 x 2^18 to 2^20 cells (sets of <= 9 velocities, nx even); on  */
-                              /* 3D open boxes DPP/DPP2/GENERIC (by nx: nx % 4, nx % 2, odd),   */
-                              /* but GENERIC for D3Q27 with 8-byte storage; else GENERIC        */
+                              /* velocities) or TB2 (4- and 8-byte storage) where supported;  */
+                              /* TB2 on periodic 2D boxes of 2^18 to 2^20 cells, TB3 on         */
+                              /* periodic 3D boxes of 3 x 2^18 to 2^20 cells (sets of <= 9      */
+                              /* velocities, nx even); DPP/DPP2/GENERIC (by nx: nx % 4, nx % 2, */
+                              /* odd) on 3D open boxes (but not D3Q27 with 8-byte storage) and  */
+                              /* for 2-byte storage on boxes of >= 2^20 cells; else GENERIC     */
 #define LBM_VARIANT_GENERIC 1 /* one thread per cell, per-element wrapped gathers            */
 #define LBM_VARIANT_DPP 2     /* 4 cells per lane, aligned vector loads, x shift by DPP;   */
                               /* needs nx % 4 == 0                                          */

@@ -413,7 +413,9 @@ inline int resolve_variant(const lbm_lee *h) {
     if (h->desc.bc == LBM_BC_PERIODIC && h->tab.D >= 2 && h->N >= ((size_t)1 << 20) && tb_plane_fits(&h->desc, h->tab.D) &&
         (h->tab.D == 2 || h->nx % 2 == 0)) {
         if (h->tab.Q <= 9 && tb_tile_y(h->desc.lattice, h->desc.storage, 3) > 0) return LBM_VARIANT_TB3;
-        if (tb_tile_y(h->desc.lattice, h->desc.storage, 2) > 0) return LBM_VARIANT_TB2;
+        // (not for 2-byte storage: D3Q13 256^3, us per step, TB2 / DPP, FP16 172 / 147, BF16 173 / 140)
+        if (elem_size(h->desc.storage) != 2 && tb_tile_y(h->desc.lattice, h->desc.storage, 2) > 0)
+            return LBM_VARIANT_TB2;
     }
     // periodic 2D boxes of 2^18 to 2^20 cells: two steps per launch (the launches, not HBM, bound a
     // step there; D2Q9 512^2, us per step, GENERIC / DPP / TB2 / TB3: FP32 7.7 / 6.0 / 4.2 / 4.8,
@@ -436,15 +438,18 @@ inline int resolve_variant(const lbm_lee *h) {
     // 1.647 / 3.591)
     const bool open3d = h->desc.bc != LBM_BC_PERIODIC && h->tab.D == 3 &&
                         !(h->tab.Q > 19 && elem_size(h->desc.storage) == 8);
-    if (open3d) {
+    // 2-byte storage on boxes of a million cells and more (bound by HBM): the four-cells-per-lane
+    // step and its wider accesses (256^3, us per step, GENERIC / DPP, FP16: D3Q13 162 / 147, D3Q19
+    // 244 / 231, D3Q27 363 / 332)
+    const bool wide = elem_size(h->desc.storage) == 2 && h->N >= ((size_t)1 << 20);
+    if (open3d || wide) {
         if (h->nx % 4 == 0) return LBM_VARIANT_DPP;
         if (h->nx % 2 == 0) return LBM_VARIANT_DPP2;
     }
-    // everything else (periodic boxes below those sizes or without a multi-step kernel, 1D, large
-    // 2D open boxes): one thread per cell, in every storage.  The four-cells-per-lane step loses
-    // there for 2-byte storage too (us per step, GENERIC / DPP, FP16: D3Q7 64^3 3.5 / 5.2, 96^3
-    // 8.3 / 8.8; D3Q19 64^3 5.8 / 14.7, 96^3 13.5 / 28.6, its registers allow two waves per SIMD;
-    // D2Q9 256^2 3.0 / 3.4)
+    // everything else (smaller periodic boxes, 4- and 8-byte storage without a multi-step kernel,
+    // 1D, large 2D open boxes): one thread per cell.  On small boxes it beats the four-cells-per-lane
+    // step for 2-byte storage too (us per step, GENERIC / DPP, FP16: D3Q7 64^3 3.5 / 5.2, 96^3
+    // 8.3 / 8.8; D3Q19 64^3 5.8 / 14.7, 96^3 13.5 / 28.6; D2Q9 256^2 3.0 / 3.4)
     return LBM_VARIANT_GENERIC;
 }
 
