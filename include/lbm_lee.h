@@ -128,7 +128,8 @@ typedef int32_t lbm_status;
 /* Step kernel variant.  All variants run the same per-cell arithmetic, so their results are
  * bitwise identical; they differ only in how the streamed values are gathered (the multi-step
  * variants TB2/TB3 with 16-bit storage excepted: they round once per launch, see below). */
-#define LBM_VARIANT_AUTO 0    /* the fastest measured variant: OPEN2D on 2D open boxes of     */
+#define LBM_VARIANT_AUTO 0    /* the fastest measured variant: RESIDENT on periodic boxes     */
+                              /* whose state fits it; OPEN2D on 2D open boxes of              */
                               /* <= 2^23 cells (GENERIC on larger ones); on                    */
                               /* periodic 2D/3D boxes of >= 2^20 cells TB3 (sets of <= 9       */
                               /* velocities) or TB2 (4- and 8-byte storage) where supported;  */
@@ -171,6 +172,11 @@ typedef int32_t lbm_status;
  * boundary and sponge kernels of the other variants; LBM_TUNE_CLOSURE_STREAM has no effect.
  * LBM_E_UNSUPPORTED for periodic boxes and for 1D and 3D lattices. */
 #define LBM_VARIANT_OPEN2D 7
+/* Every step of one call in a single launch, the whole state held in LDS: periodic boxes whose
+ * two copies of the state fit 64 KiB (2 Q N bytes-per-value <= 65536; the paper's 1D runs, small
+ * 2D/3D grids), where one launch per step is what bounds the one-step variants.  Same values as
+ * GENERIC.  LBM_E_UNSUPPORTED for open boxes and larger states. */
+#define LBM_VARIANT_RESIDENT 8
 
 typedef struct lbm_lee_desc {
     int32_t lattice;     /* LBM_D1Q3 ...                                                    */

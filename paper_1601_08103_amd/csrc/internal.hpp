@@ -16,6 +16,7 @@
 #include "nrbc.hpp"
 #include "open_bc.hpp"
 #include "tables.hpp"
+#include "resident.hpp"
 #include "temporal.hpp"
 
 using namespace lbm;
@@ -128,6 +129,12 @@ inline bool sponge_layer(const lbm_lee_desc *d) {
     return d->bc == LBM_BC_SPONGE || (d->bc == LBM_BC_MLP && d->sponge_width > 0);
 }
 
+// Two copies of the whole state fit the LDS-resident step's 64 KiB.
+inline bool resident_fits(const lbm_lee_desc *d, const LatticeTable &t) {
+    const double cells = (double)d->n[0] * (double)d->n[1] * (double)d->n[2];
+    return 2.0 * t.Q * cells * (double)elem_size(d->storage) <= (double)kResidentLds;
+}
+
 inline lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
     if (!d) return fail(LBM_E_INVALID, "desc is NULL");
     if (!build_lattice(d->lattice, tab)) return fail(LBM_E_INVALID, "unknown lattice id %d", d->lattice);
@@ -141,7 +148,12 @@ inline lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
     if (N * tab->Q > 9.0e18 / 8.0) return fail(LBM_E_INVALID, "domain too large");
     if ((double)d->n[1] * (double)d->n[2] * 16.0 > 4.0e9) return fail(LBM_E_INVALID, "too many rows (ny * nz)");
     if (!(d->tau >= 0.5) || !std::isfinite(d->tau)) return fail(LBM_E_INVALID, "tau must be finite and >= 1/2 (got %g)", d->tau);
-    if (d->variant < LBM_VARIANT_AUTO || d->variant > LBM_VARIANT_OPEN2D) return fail(LBM_E_INVALID, "unknown variant %d", d->variant);
+    if (d->variant < LBM_VARIANT_AUTO || d->variant > LBM_VARIANT_RESIDENT) return fail(LBM_E_INVALID, "unknown variant %d", d->variant);
+    if (d->variant == LBM_VARIANT_RESIDENT) {
+        if (d->bc != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "the LDS-resident variant needs the periodic box");
+        if (!resident_fits(d, *tab))
+            return fail(LBM_E_UNSUPPORTED, "the LDS-resident variant holds two copies of the state in 64 KiB");
+    }
     if (d->tune < 0 || d->tune > 511) return fail(LBM_E_INVALID, "unknown tune bits 0x%x", d->tune);
     if (d->variant == LBM_VARIANT_TB2 || d->variant == LBM_VARIANT_TB3) {
         const int K = d->variant == LBM_VARIANT_TB2 ? 2 : 3;
@@ -399,6 +411,8 @@ inline lbm_status launch_check() {
 inline int resolve_variant(const lbm_lee *h) {
     if (h->inplace) return LBM_VARIANT_GENERIC;  // the in-place kernels are one thread per cell
     if (h->desc.variant != LBM_VARIANT_AUTO) return h->desc.variant;
+    // tiny periodic boxes: every step of a call in one launch, the state in LDS
+    if (h->desc.bc == LBM_BC_PERIODIC && resident_fits(&h->desc, h->tab)) return LBM_VARIANT_RESIDENT;
     // 2D open boxes: ring, interior and closure network in one launch up to 8 M cells (the
     // separate kernels of the other variants are each latency-bound there); on larger boxes the
     // one-launch kernel's interior blocks, which reserve the network's LDS, lose to the

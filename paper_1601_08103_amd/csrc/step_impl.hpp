@@ -195,6 +195,18 @@ lbm_status step_lattice(lbm_lee *h, int64_t nsteps, hipStream_t st) {
                 }
                 return fail(LBM_E_UNSUPPORTED, "the %d-step variant does not support this lattice and storage", K);
             };
+            if (variant == LBM_VARIANT_RESIDENT) {
+                if (nsteps <= 0) return LBM_OK;
+                const E *src = static_cast<const E *>(h->buf[h->cur]);
+                E *dst = static_cast<E *>(h->buf[h->cur ^ (int)(nsteps & 1)]);
+                const size_t lds = 2 * (size_t)VS::Q * h->N * sizeof(E);
+                step_resident<VS, ST, SK, HF><<<1, 1024, lds, st>>>(src, dst, h->nx, h->ny, h->nz, (int)h->N, nsteps, k);
+                lbm_status ls = launch_check();
+                if (ls != LBM_OK) return ls;
+                h->cur ^= (int)(nsteps & 1);
+                h->steps += nsteps;
+                return LBM_OK;
+            }
             if (variant == LBM_VARIANT_OPEN2D) {
                 if constexpr (VS::D == 2) {
                     const int nx = h->nx, ny = h->ny;

@@ -20,7 +20,7 @@ STORAGES = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "i16": 4, "e3m12": 5}
 ELEM_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "i16": 2, "e3m12": 2}
 TUNE = {"nt_store": 1, "nt_load": 2, "persistent": 4, "full_rest": 8, "closure_stream": 16, "in_place": 32,
         "tb_segment_8": 64, "tb_segment_16": 128, "tb_segment_32": 192, "net_one_block": 256}
-VARIANTS = {"auto": 0, "generic": 1, "dpp": 2, "lds": 3, "dpp2": 4, "tb2": 5, "tb3": 6, "open2d": 7}
+VARIANTS = {"auto": 0, "generic": 1, "dpp": 2, "lds": 3, "dpp2": 4, "tb2": 5, "tb3": 6, "open2d": 7, "resident": 8}
 BCS = {"periodic": 0, "zero": 1, "copy": 2, "sponge": 3, "mlp": 4}
 
 LBM_OK = 0

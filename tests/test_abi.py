@@ -85,7 +85,9 @@ def test_sizes(lattice, storage, shape, bpu):
     dict(lattice="D3Q19", storage="f64", shape=(8, 8, 8), variant="tb2"),
     dict(lattice="D3Q9", storage="f64", shape=(8, 8, 8), variant="tb2"),
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), variant="tb2", tune=32),    # not with in-place
-    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), variant=8),
+    dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), variant=9),
+    dict(lattice="D3Q7", storage="f32", shape=(16, 16, 16), variant="resident"),  # 229 KiB: too large
+    dict(lattice="D2Q9", storage="f32", shape=(8, 8), variant="resident", bc="zero"),  # periodic only
     dict(lattice="D2Q9", storage="f32", shape=(8, 8), variant="open2d"),              # one-launch open step:
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), variant="open2d", bc="zero"),  # open 2D boxes only
     dict(lattice="D1Q3", storage="f32", shape=(64,), variant="open2d", bc="zero"),
@@ -291,3 +293,18 @@ def test_dimensional_mapping_reproduces_table1(golden_dir):
             lbm.lbm_lee_dimensional_scaling("D3Q7_DIA", *bad)
     with pytest.raises(lbm.LbmError):
         lbm.lbm_lee_dimensional_steps(s, 1.0, 0.0)
+
+
+@pytest.mark.parametrize("lattice,storage,shape,fits", [
+    ("D1Q3", "f64", (1024,), True),      # 2 x 3 x 1024 x 8 B = 48 KiB
+    ("D1Q3", "f64", (1366,), False),     # 64.03 KiB
+    ("D2Q9", "f32", (30, 30), True),
+    ("D3Q7", "f16", (8, 16, 16), True),     # 56 KiB
+    ("D3Q19", "f32", (6, 8, 8), True),      # 57 KiB
+    ("D3Q27", "f64", (8, 8, 8), False),
+])
+def test_resident_variant_takes_states_that_fit_its_lds(lattice, storage, shape, fits):
+    """The LDS-resident variant holds two copies of the state in 64 KiB; larger states and open
+    boxes are rejected at descriptor check."""
+    d = lbm.make_desc(lattice, storage, shape, variant="resident")
+    assert (lbm.lbm_lee_state_bytes(d) > 0) == fits

@@ -724,3 +724,65 @@ def test_temporal_blocking_graph_replays(variant):
         torch.cuda.synchronize()
     sim.close()
     ref.close()
+
+
+@pytest.mark.parametrize("name,shape", [("D1Q3", (1024,)), ("D1Q3", (37,)), ("D2Q9", (17, 23)), ("D2Q5", (25, 30)),
+                                        ("D3Q7", (5, 6, 7)), ("D3Q19", (4, 5, 6)), ("D3Q13", (3, 4, 5)),
+                                        ("D2Q5_DIA", (9, 11)), ("D3Q7_DIA", (4, 4, 6))])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "e3m12"])
+def test_resident_variant_matches_generic(name, shape, storage):
+    """The LDS-resident variant (every step of a call in one launch) against GENERIC on random
+    states, bit for bit, after calls of 1, 2, 7 and 30 steps (odd and even, so both buffers end
+    the calls), at tau = 1/2 and 0.8; AUTO takes it for these boxes."""
+    import torch
+    lat = lattice(name)
+    from paper_1601_08103_amd import lbm
+    for tau in (0.5, 0.8):
+        say("resident", name, shape, storage, tau)
+        g0 = 1e-3 * lat.fstar.reshape((-1,) + (1,) * lat.D) * np.random.default_rng(
+            stable_seed(name, shape, storage, tau)).standard_normal((lat.Q,) + tuple(shape))
+        sims = []
+        for variant in ("auto", "generic"):
+            sim = _solver(name, storage, shape, tau=tau, variant=variant,
+                          store_scale=128.0 if storage in ("f16", "e3m12") else 0.0)
+            sim.import_f64(g0)
+            sims.append(sim)
+        assert sims[0].variant == "resident" and sims[1].variant == "generic"
+        for n in (1, 2, 7, 30):
+            for sim in sims:
+                sim.step(n)
+            a, b = sims[0].export_f64(), sims[1].export_f64()
+            assert torch.equal(a, b), (tau, n, float((a - b).abs().max()))
+        ca, cb = lbm.lbm_lee_current(sims[0].h), lbm.lbm_lee_current(sims[1].h)
+        # the same step count, and the state in the same buffer of each pair
+        assert ca[1] == cb[1] == 40
+        assert (ca[0] == sims[0].pop_a.data_ptr()) == (cb[0] == sims[1].pop_a.data_ptr())
+        for sim in sims:
+            sim.close()
+
+
+def test_resident_variant_speed_on_the_1d_workload():
+    """The paper's 1D run (D1Q3, 1024 cells, FP64, 1000 steps) in one launch against one launch per
+    step: the same state, and faster."""
+    import torch
+    from paper_1601_08103_amd import lbm
+    lat = lattice("D1Q3")
+    x = np.arange(1024)
+    p0 = 1e-3 * np.exp(-0.5 * ((x - 512) / 20.0) ** 2)
+    rho, u, theta = inputs.fields_from_pressure(p0, lat.rho0, lat.theta0, lat.gamma)
+    ms, out = {}, {}
+    for variant in ("auto", "generic"):
+        sim = _solver("D1Q3", "f64", (1024,), variant=variant, fields=(rho, u, theta))
+        sim.step(10)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sim.step(1000)
+        e1.record()
+        torch.cuda.synchronize()
+        ms[sim.variant] = e0.elapsed_time(e1)
+        out[sim.variant] = sim.export_f64()
+        sim.close()
+    say("1D workload, 1000 steps, ms:", ms)
+    assert torch.equal(out["resident"], out["generic"])
+    assert ms["resident"] < ms["generic"]
