@@ -173,9 +173,9 @@ typedef int32_t lbm_status;
  * LBM_E_UNSUPPORTED for periodic boxes and for 1D and 3D lattices. */
 #define LBM_VARIANT_OPEN2D 7
 /* Every step of one call in a single launch, the whole state held in LDS: periodic boxes whose
- * two copies of the state fit 64 KiB (2 Q N bytes-per-value <= 65536; the paper's 1D runs, small
- * 2D/3D grids), where one launch per step is what bounds the one-step variants.  Same values as
- * GENERIC.  LBM_E_UNSUPPORTED for open boxes and larger states. */
+ * two copies of the state fit 160 KiB (2 Q N bytes-per-value <= 163840; the paper's 1D runs,
+ * small 2D/3D grids), where one launch per step is what bounds the one-step variants.  Same
+ * values as GENERIC.  LBM_E_UNSUPPORTED for open boxes and larger states. */
 #define LBM_VARIANT_RESIDENT 8
 
 typedef struct lbm_lee_desc {

@@ -129,7 +129,7 @@ inline bool sponge_layer(const lbm_lee_desc *d) {
     return d->bc == LBM_BC_SPONGE || (d->bc == LBM_BC_MLP && d->sponge_width > 0);
 }
 
-// Two copies of the whole state fit the LDS-resident step's 64 KiB.
+// Two copies of the whole state fit the LDS-resident step's 160 KiB.
 inline bool resident_fits(const lbm_lee_desc *d, const LatticeTable &t) {
     const double cells = (double)d->n[0] * (double)d->n[1] * (double)d->n[2];
     return 2.0 * t.Q * cells * (double)elem_size(d->storage) <= (double)kResidentLds;
@@ -152,7 +152,7 @@ inline lbm_status check_desc(const lbm_lee_desc *d, LatticeTable *tab) {
     if (d->variant == LBM_VARIANT_RESIDENT) {
         if (d->bc != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "the LDS-resident variant needs the periodic box");
         if (!resident_fits(d, *tab))
-            return fail(LBM_E_UNSUPPORTED, "the LDS-resident variant holds two copies of the state in 64 KiB");
+            return fail(LBM_E_UNSUPPORTED, "the LDS-resident variant holds two copies of the state in 160 KiB");
     }
     if (d->tune < 0 || d->tune > 511) return fail(LBM_E_INVALID, "unknown tune bits 0x%x", d->tune);
     if (d->variant == LBM_VARIANT_TB2 || d->variant == LBM_VARIANT_TB3) {

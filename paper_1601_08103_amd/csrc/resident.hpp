@@ -1,5 +1,5 @@
 // Whole-box steps in one launch for periodic boxes small enough to live in LDS (two copies of
-// the state within 64 KiB): one block of 1024 threads loads the state, runs every step out of
+// the state within 160 KiB, a CU's LDS): one block of 1024 threads loads the state, runs every step out of
 // LDS with a block barrier between steps, and stores the result.  A tiny box (the paper's 1D
 // runs, small convergence-study grids) is otherwise bound by one kernel launch per step.  The
 // arithmetic is step_generic's, value for value: the same gathers, collision, and rounding to
@@ -12,7 +12,7 @@
 
 namespace lbm {
 
-constexpr size_t kResidentLds = 65536;  // bytes: both copies of the state
+constexpr size_t kResidentLds = 160 * 1024;  // bytes: both copies of the state (dynamic LDS)
 
 template <class VS, class ST, bool SKIP0, bool HALF>
 __global__ __launch_bounds__(1024) void step_resident(const typename ST::elem *__restrict__ src,

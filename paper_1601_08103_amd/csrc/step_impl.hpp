@@ -200,6 +200,9 @@ lbm_status step_lattice(lbm_lee *h, int64_t nsteps, hipStream_t st) {
                 const E *src = static_cast<const E *>(h->buf[h->cur]);
                 E *dst = static_cast<E *>(h->buf[h->cur ^ (int)(nsteps & 1)]);
                 const size_t lds = 2 * (size_t)VS::Q * h->N * sizeof(E);
+                // more than 64 KiB of dynamic LDS has to be allowed per kernel
+                LBM_HIP(hipFuncSetAttribute((const void *)&step_resident<VS, ST, SK, HF>,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kResidentLds));
                 step_resident<VS, ST, SK, HF><<<1, 1024, lds, st>>>(src, dst, h->nx, h->ny, h->nz, (int)h->N, nsteps, k);
                 lbm_status ls = launch_check();
                 if (ls != LBM_OK) return ls;

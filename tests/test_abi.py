@@ -86,7 +86,7 @@ def test_sizes(lattice, storage, shape, bpu):
     dict(lattice="D3Q9", storage="f64", shape=(8, 8, 8), variant="tb2"),
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), variant="tb2", tune=32),    # not with in-place
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), variant=9),
-    dict(lattice="D3Q7", storage="f32", shape=(16, 16, 16), variant="resident"),  # 229 KiB: too large
+    dict(lattice="D3Q7", storage="f32", shape=(16, 16, 16), variant="resident"),  # 224 KiB: too large
     dict(lattice="D2Q9", storage="f32", shape=(8, 8), variant="resident", bc="zero"),  # periodic only
     dict(lattice="D2Q9", storage="f32", shape=(8, 8), variant="open2d"),              # one-launch open step:
     dict(lattice="D3Q7", storage="f32", shape=(8, 8, 8), variant="open2d", bc="zero"),  # open 2D boxes only
@@ -297,14 +297,15 @@ def test_dimensional_mapping_reproduces_table1(golden_dir):
 
 @pytest.mark.parametrize("lattice,storage,shape,fits", [
     ("D1Q3", "f64", (1024,), True),      # 2 x 3 x 1024 x 8 B = 48 KiB
-    ("D1Q3", "f64", (1366,), False),     # 64.03 KiB
+    ("D1Q3", "f64", (3413,), True),      # 159.98 KiB
+    ("D1Q3", "f64", (3414,), False),     # 160.03 KiB
     ("D2Q9", "f32", (30, 30), True),
     ("D3Q7", "f16", (8, 16, 16), True),     # 56 KiB
     ("D3Q19", "f32", (6, 8, 8), True),      # 57 KiB
     ("D3Q27", "f64", (8, 8, 8), False),
 ])
 def test_resident_variant_takes_states_that_fit_its_lds(lattice, storage, shape, fits):
-    """The LDS-resident variant holds two copies of the state in 64 KiB; larger states and open
+    """The LDS-resident variant holds two copies of the state in 160 KiB; larger states and open
     boxes are rejected at descriptor check."""
     d = lbm.make_desc(lattice, storage, shape, variant="resident")
     assert (lbm.lbm_lee_state_bytes(d) > 0) == fits

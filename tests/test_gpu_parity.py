@@ -728,7 +728,8 @@ def test_temporal_blocking_graph_replays(variant):
 
 @pytest.mark.parametrize("name,shape", [("D1Q3", (1024,)), ("D1Q3", (37,)), ("D2Q9", (17, 23)), ("D2Q5", (25, 30)),
                                         ("D3Q7", (5, 6, 7)), ("D3Q19", (4, 5, 6)), ("D3Q13", (3, 4, 5)),
-                                        ("D2Q5_DIA", (9, 11)), ("D3Q7_DIA", (4, 4, 6))])
+                                        ("D2Q5_DIA", (9, 11)), ("D3Q7_DIA", (4, 4, 6)),
+                                        ("D2Q5", (40, 40)), ("D1Q3", (3413,))])  # 125 and 160 KiB in FP64
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16", "e3m12"])
 def test_resident_variant_matches_generic(name, shape, storage):
     """The LDS-resident variant (every step of a call in one launch) against GENERIC on random
